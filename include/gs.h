@@ -1,0 +1,210 @@
+/*
+ * gs.h -- C ABI of the MI355X differentiable Gaussian tile rasterizer.
+ *
+ * The operation is the renderer R(G, C) of VastGaussian (arXiv 2402.17427),
+ * section 3: a set G of 3D Gaussians (position, anisotropic covariance from
+ * scale and rotation, opacity, spherical-harmonic colour) is projected to 2D
+ * image-space Gaussians by EWA splatting, the 2D Gaussians are assigned to
+ * screen tiles, sorted by depth within each tile and alpha-blended front to
+ * back into the image I = R(G, C).  R is differentiable: given dLoss/dImage
+ * the backward call returns dLoss/d(every Gaussian parameter), which is how
+ * each partition cell's Gaussians are optimised (sections 3 and 4.2).
+ *
+ * The image-formation constants the paper leaves to 3DGS (section 5.1) are:
+ *   2D dilation 0.3 px^2; affine clamp |x/z| <= 1.3 (W/2)/fx, same for y;
+ *   alpha = min(0.99, o exp(power)), Gaussians with alpha < 1/255 skipped;
+ *   a pixel stops before the Gaussian that would take T below 1e-4;
+ *   colour = max(0, SH(view direction) + 0.5); quaternions (w, x, y, z);
+ *   pixel centres at (x + 0.5, y + 0.5); depth = camera-space z of the
+ *   centre, ties broken by Gaussian index.
+ * A Gaussian's tile rectangle is the bounding box of the pixels where its
+ * alpha can reach 1/255 (the ellipse of radius^2 = 2 ln(255 o) in its conic
+ * metric), so binning never changes the image: the result is the plain
+ * every-Gaussian-at-every-pixel blend in depth order, for any tile size.
+ *
+ * Conventions for every call:
+ *  - Pointers named "device" are device memory on the current HIP device;
+ *    the caller allocates and owns them (the library never frees caller
+ *    memory).  Descriptor structs themselves live in host memory and are
+ *    read during the call only.
+ *  - Calls enqueue work on `stream` (a hipStream_t, NULL = default stream)
+ *    and return without synchronising, except where stated.
+ *  - Return GS_OK (0) or a negative gs_status; gs_last_error() gives a
+ *    thread-local message.  Host-detectable errors (NULL pointers, negative
+ *    sizes, unsupported tile sizes, SH degree > 3, ld < n, W or H <= 0) are
+ *    rejected before anything is enqueued.
+ *  - Device-detected pair overflow (more (Gaussian, tile) pairs than the
+ *    caller's capacity) sets *status = GS_ERR_CAPACITY in device memory; the
+ *    render calls then write NaN images and zero gradients instead of
+ *    partial results.  Read `status` after the stream completes.
+ *  - All float data is IEEE FP32 (centres of projected Gaussians are FP64).
+ *    Gradients are w.r.t. the inputs as given: linear scale, opacity in
+ *    (0, 1), un-normalised quaternion, raw SH coefficients.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_ABI_VERSION 1
+
+typedef enum {
+    GS_OK = 0,
+    GS_ERR_INVALID = -1,     /* bad argument, detected on the host */
+    GS_ERR_OOM = -2,         /* allocation failed (handles only) */
+    GS_ERR_HIP = -3,         /* a HIP runtime call failed */
+    GS_ERR_CAPACITY = -4,    /* pair buffer too small (device status flag) */
+    GS_ERR_BUSY = -5,        /* server queue full */
+    GS_ERR_UNSUPPORTED = -6, /* valid but not implemented (e.g. tile size) */
+    GS_ERR_TIMEOUT = -7,     /* wait timed out */
+    GS_ERR_NOT_FOUND = -8    /* unknown ticket */
+} gs_status;
+
+typedef void *gs_stream; /* a hipStream_t */
+
+int gs_abi_version(void);
+const char *gs_last_error(void);
+
+/* Gaussian set, structure of arrays, device FP32 planes with stride ld >= n
+ * (element k of Gaussian i of a [P][ld] array is at [k*ld + i]):
+ *   mean[3][ld]  world position          scale[3][ld] linear scale (> 0)
+ *   quat[4][ld]  rotation (w, x, y, z)   opacity[ld]  in (0, 1)
+ *   sh[3K][ld]   SH coefficients, plane c*K + j for colour channel c and
+ *                basis j = l*l + l + m, K = (sh_degree + 1)^2, degree <= 3.
+ * Non-finite parameters, centres at or behind near_z, opacity < 1/255 and
+ * Gaussians whose support misses the image are culled (no pairs, zero
+ * gradient). */
+typedef struct {
+    int64_t n, ld;
+    int32_t sh_degree;
+    const float *mean, *scale, *quat, *opacity, *sh;
+} gs_gaussians;
+
+/* Pinhole camera (host struct).  R: world->camera rotation, row-major;
+ * t: translation (x_cam = R x_world + t).  Camera +z looks forward, +x right,
+ * +y down the image.  Pixel (x, y) has centre (x + 0.5, y + 0.5).
+ * bg: background colour blended with the final transmittance. */
+typedef struct {
+    float R[9], t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float near_z;
+    float bg[3];
+} gs_camera;
+
+/* Tuning options (host struct); pass NULL for the defaults.  Zero fields
+ * take defaults.  Supported tiles: 16x16 (default), 8x8, 16x8, 32x8, 32x16,
+ * 32x32.
+ * The image does not depend on the tile size. */
+typedef struct {
+    int32_t tile_w, tile_h;
+    int32_t reserved[6];
+} gs_opts;
+
+/* Projection output (caller-owned device buffers, n entries each):
+ *   rec   n x 48-byte records, 16-byte aligned: { double u, v (pixel-space
+ *         centre); float A, B, C (conic = inverse 2D covariance, with
+ *         power = -0.5 (A dx^2 + C dy^2) - B dx dy); float opacity;
+ *         float r, g, b (colour); uint32 ext = two binary16 half-extents
+ *         (ex, ey) of the alpha >= 1/255 support, rounded up }.
+ *   depth n floats: camera-space z (the sort key).
+ *   rect  n x 4 uint16, 8-byte aligned: tile rectangle x0, y0, x1, y1
+ *         (x1, y1 exclusive).
+ *   tiles_touched n uint32: (x1 - x0) (y1 - y0), 0 for culled Gaussians.
+ * Records of culled Gaussians are unspecified. */
+typedef struct {
+    void *rec;
+    float *depth;
+    uint16_t *rect;
+    uint32_t *tiles_touched;
+} gs_proj;
+
+/* Binning output (caller-owned device buffers):
+ *   keys[pair_capacity]  sorted (tile << 32 | float32 bits of depth)
+ *   vals[pair_capacity]  Gaussian index of each sorted pair
+ *   ranges[n_tiles][2]   [start, end) of each tile's pairs; empty = [0, 0)
+ *   pair_count[2]        written by gs_bin_sort: [0] = number of sorted
+ *                        pairs P (0 on overflow), [1] = pairs the view
+ *                        needs (saturated at 2^32-1), to size a retry
+ *   status[1]            0, or GS_ERR_CAPACITY if the pairs needed exceed
+ *                        pair_capacity (nothing is sorted then)
+ * Tiles are numbered row-major: tile_y * ceil(W / tile_w) + tile_x. */
+typedef struct {
+    uint64_t *keys;
+    uint32_t *vals;
+    uint32_t *ranges;
+    uint32_t *pair_count;
+    int32_t *status;
+    int64_t pair_capacity;
+} gs_bins;
+
+/* Gradient output (caller-owned device buffers, same shapes as gs_gaussians
+ * with plane stride ld; overwritten):  mean[3][ld], scale[3][ld],
+ * quat[4][ld], opacity[ld], sh[3K][ld].
+ * grad2d[9][n]: per-Gaussian image-space gradients (du, dv, dA, dB, dC,
+ * d opacity, dr, dg, db), used as the accumulator and left holding them. */
+typedef struct {
+    int64_t ld;
+    float *mean, *scale, *quat, *opacity, *sh;
+    float *grad2d;
+} gs_grads;
+
+/* Section 3: project every Gaussian (EWA 2D covariance + dilation, conic,
+ * SH colour, depth, conservative tile rectangle).  One lane per Gaussian. */
+gs_status gs_project(const gs_gaussians *g, const gs_camera *cam, const gs_opts *opts,
+                     gs_proj *out, gs_stream stream);
+
+/* Workspace bytes gs_bin_sort needs for n Gaussians, a pair capacity and
+ * a tile count (host query, no device work). */
+gs_status gs_bin_sort_workspace(int64_t n, int64_t pair_capacity, int64_t n_tiles, size_t *bytes);
+
+/* Section 3 (2D Gaussians binned to tiles and depth-sorted): exclusive scan of
+ * tiles_touched, emission of one (tile|depth, index) pair per covered tile
+ * (tiles in row-major order within each Gaussian), stable LSD radix sort
+ * (onesweep, 8-bit digits) and per-tile ranges.  `ws` is device scratch of
+ * gs_bin_sort_workspace() bytes.  No host synchronisation: the pair count
+ * stays on the device.  pair_capacity <= 2^30 - 1. */
+gs_status gs_bin_sort(const gs_proj *proj, int64_t n, const gs_camera *cam, const gs_opts *opts,
+                      gs_bins *out, void *ws, size_t ws_bytes, gs_stream stream);
+
+/* Section 3 (tiles blended front to back): one workgroup per tile.
+ * image[3][H][W] (planar RGB), final_T[H][W], n_contrib[H][W] = 1-based
+ * position, within the tile's list, of the last blended Gaussian (0 if
+ * none).  All three are outputs (device). */
+gs_status gs_render_fwd(const gs_proj *proj, const gs_bins *bins, const gs_camera *cam,
+                        const gs_opts *opts, float *image, float *final_T, uint32_t *n_contrib,
+                        gs_stream stream);
+
+/* Section 3 (differentiable rasterizer, Gaussians optimised by gradient
+ * descent): gradient of L w.r.t. every Gaussian parameter given dL/dImage
+ * [3][H][W] (device) and the forward's final_T and n_contrib (device).
+ * `g`, `proj` and `bins` must be the ones the forward used.  Each pixel
+ * walks its list back to front from its last contributor, recovering the
+ * transmittance by division from final_T; no per-contributor state is
+ * stored.  Per-Gaussian sums use FP32 atomics, so the last bits depend on
+ * the order the hardware applies them.  out->grad2d is zeroed here, then
+ * accumulated; the parameter gradients are overwritten (zero for culled
+ * Gaussians, and for all Gaussians when *bins->status is non-zero). */
+gs_status gs_render_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_opts *opts,
+                        const gs_proj *proj, const gs_bins *bins, const float *final_T,
+                        const uint32_t *n_contrib, const float *dL_dimage, gs_grads *out,
+                        gs_stream stream);
+
+/* Stable LSD radix sort of (uint64 key, uint32 value) pairs on the low
+ * `key_bits` bits (<= 64), the sort gs_bin_sort runs, exposed for testing
+ * on arbitrary keys.  count: device pointer to the number of pairs
+ * (<= capacity); keys/vals: device [capacity], sorted in place; ws: device
+ * scratch of gs_sort_workspace() bytes. */
+gs_status gs_sort_workspace(int64_t capacity, int32_t key_bits, size_t *bytes);
+gs_status gs_sort_pairs(uint64_t *keys, uint32_t *vals, const uint32_t *count, int64_t capacity,
+                        int32_t key_bits, void *ws, size_t ws_bytes, gs_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS_H */

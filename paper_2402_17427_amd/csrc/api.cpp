@@ -1,0 +1,248 @@
+// C ABI of the rasterizer: argument validation, workspace carving and
+// kernel dispatch.  The declarations and their contracts are in gs.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/gs.h"
+#include "api_internal.h"
+#include "kernels.h"
+
+namespace gs {
+
+namespace {
+thread_local std::string g_err;
+}
+
+const char* g_err_cstr() { return g_err.c_str(); }
+
+gs_status fail(gs_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+gs_status check_hip(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(GS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return GS_OK;
+}
+
+gs_status to_cam(const gs_camera* c, Cam* out) {
+    if (!c) return fail(GS_ERR_INVALID, "camera is NULL");
+    if (c->width <= 0 || c->height <= 0) return fail(GS_ERR_INVALID, "image size %dx%d", c->width, c->height);
+    if (c->width > 65535 * 8 || c->height > 65535 * 8) return fail(GS_ERR_INVALID, "image too large");
+    if (!(c->fx > 0.f) || !(c->fy > 0.f) || !std::isfinite(c->fx) || !std::isfinite(c->fy))
+        return fail(GS_ERR_INVALID, "focal lengths must be finite and > 0");
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(c->R[i])) return fail(GS_ERR_INVALID, "camera rotation not finite");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(c->t[i]) || !std::isfinite(c->bg[i])) return fail(GS_ERR_INVALID, "camera not finite");
+    if (!std::isfinite(c->cx) || !std::isfinite(c->cy) || !std::isfinite(c->near_z))
+        return fail(GS_ERR_INVALID, "camera not finite");
+    std::memcpy(out->R, c->R, sizeof out->R);
+    std::memcpy(out->t, c->t, sizeof out->t);
+    out->fx = c->fx;
+    out->fy = c->fy;
+    out->cx = c->cx;
+    out->cy = c->cy;
+    out->W = c->width;
+    out->H = c->height;
+    out->near_z = c->near_z;
+    std::memcpy(out->bg, c->bg, sizeof out->bg);
+    return GS_OK;
+}
+
+gs_status to_gauss(const gs_gaussians* g, Gauss* out) {
+    if (!g) return fail(GS_ERR_INVALID, "gaussians is NULL");
+    if (g->n < 0 || g->ld < g->n) return fail(GS_ERR_INVALID, "bad n=%lld ld=%lld", (long long)g->n, (long long)g->ld);
+    if (g->n > (int64_t)0xFFFFFFFF) return fail(GS_ERR_INVALID, "more than 2^32-1 Gaussians");
+    if (g->sh_degree < 0 || g->sh_degree > 3) return fail(GS_ERR_INVALID, "sh_degree %d not in [0, 3]", g->sh_degree);
+    if (g->n > 0 && (!g->mean || !g->scale || !g->quat || !g->opacity || !g->sh))
+        return fail(GS_ERR_INVALID, "Gaussian plane pointer is NULL");
+    out->n = g->n;
+    out->ld = g->ld;
+    out->deg = g->sh_degree;
+    out->K = (g->sh_degree + 1) * (g->sh_degree + 1);
+    out->mean = g->mean;
+    out->scale = g->scale;
+    out->quat = g->quat;
+    out->opacity = g->opacity;
+    out->sh = g->sh;
+    return GS_OK;
+}
+
+gs_status tiles_of(const gs_opts* o, int* tw, int* th) {
+    *tw = (o && o->tile_w) ? o->tile_w : 16;
+    *th = (o && o->tile_h) ? o->tile_h : 16;
+    if (!render_tile_supported(*tw, *th)) return fail(GS_ERR_UNSUPPORTED, "tile %dx%d not supported", *tw, *th);
+    return GS_OK;
+}
+
+int tile_bits(int64_t n_tiles) {
+    int b = 0;
+    while (((int64_t)1 << b) < n_tiles) ++b;
+    return b;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t bin_sort_ws_bytes(int64_t n, int64_t cap, int64_t n_tiles) {
+    const int kb = 32 + tile_bits(n_tiles);
+    return align256(scan_workspace_bytes(n)) + align256((size_t)cap * 8) + align256((size_t)cap * 4) +
+           align256(sort_workspace_bytes(cap, kb));
+}
+
+gs_status check_proj(const gs_proj* p, int64_t n) {
+    if (!p) return fail(GS_ERR_INVALID, "proj is NULL");
+    if (n > 0 && (!p->rec || !p->depth || !p->rect || !p->tiles_touched))
+        return fail(GS_ERR_INVALID, "proj buffer is NULL");
+    if (reinterpret_cast<uintptr_t>(p->rec) % 16) return fail(GS_ERR_INVALID, "proj rec not 16-byte aligned");
+    if (reinterpret_cast<uintptr_t>(p->rect) % 8) return fail(GS_ERR_INVALID, "proj rect not 8-byte aligned");
+    return GS_OK;
+}
+
+gs_status check_bins(const gs_bins* b) {
+    if (!b) return fail(GS_ERR_INVALID, "bins is NULL");
+    if (b->pair_capacity < 0 || b->pair_capacity > kMaxPairs)
+        return fail(GS_ERR_INVALID, "pair_capacity %lld not in [0, 2^30-1]", (long long)b->pair_capacity);
+    if (!b->ranges || !b->pair_count || !b->status) return fail(GS_ERR_INVALID, "bins buffer is NULL");
+    if (b->pair_capacity > 0 && (!b->keys || !b->vals)) return fail(GS_ERR_INVALID, "bins keys/vals NULL");
+    if (reinterpret_cast<uintptr_t>(b->ranges) % 8) return fail(GS_ERR_INVALID, "ranges not 8-byte aligned");
+    return GS_OK;
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+int gs_abi_version(void) { return GS_ABI_VERSION; }
+
+const char* gs_last_error(void) { return g_err_cstr(); }
+
+gs_status gs_project(const gs_gaussians* g, const gs_camera* cam, const gs_opts* opts, gs_proj* out,
+                     gs_stream stream) {
+    Gauss G;
+    Cam C;
+    int tw, th;
+    gs_status s;
+    if ((s = to_gauss(g, &G)) || (s = to_cam(cam, &C)) || (s = tiles_of(opts, &tw, &th))) return s;
+    if ((s = check_proj(out, G.n))) return s;
+    const int ntx = (C.W + tw - 1) / tw, nty = (C.H + th - 1) / th;
+    if (ntx > 65535 || nty > 65535) return fail(GS_ERR_INVALID, "too many tiles");
+    launch_project(G, C, tw, th, static_cast<Rec*>(out->rec), out->depth, reinterpret_cast<ushort4*>(out->rect),
+                   out->tiles_touched, static_cast<hipStream_t>(stream));
+    return check_hip("gs_project");
+}
+
+gs_status gs_bin_sort_workspace(int64_t n, int64_t pair_capacity, int64_t n_tiles, size_t* bytes) {
+    if (!bytes) return fail(GS_ERR_INVALID, "bytes is NULL");
+    if (n < 0 || pair_capacity < 0 || pair_capacity > kMaxPairs || n_tiles <= 0)
+        return fail(GS_ERR_INVALID, "bad sizes");
+    *bytes = bin_sort_ws_bytes(n, pair_capacity, n_tiles);
+    return GS_OK;
+}
+
+gs_status gs_bin_sort(const gs_proj* proj, int64_t n, const gs_camera* cam, const gs_opts* opts, gs_bins* out,
+                      void* ws, size_t ws_bytes, gs_stream stream) {
+    Cam C;
+    int tw, th;
+    gs_status s;
+    if (n < 0 || n > (int64_t)0xFFFFFFFF) return fail(GS_ERR_INVALID, "bad n");
+    if ((s = to_cam(cam, &C)) || (s = tiles_of(opts, &tw, &th)) || (s = check_proj(proj, n)) ||
+        (s = check_bins(out)))
+        return s;
+    const int ntx = (C.W + tw - 1) / tw, nty = (C.H + th - 1) / th;
+    const int64_t n_tiles = (int64_t)ntx * nty;
+    const int64_t cap = out->pair_capacity;
+    const size_t need = bin_sort_ws_bytes(n, cap, n_tiles);
+    if (!ws || ws_bytes < need) return fail(GS_ERR_INVALID, "workspace too small: %zu < %zu", ws_bytes, need);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* p = static_cast<char*>(ws);
+    void* scan_ws = p;
+    p += align256(scan_workspace_bytes(n));
+    uint64_t* alt_k = reinterpret_cast<uint64_t*>(p);
+    p += align256((size_t)cap * 8);
+    uint32_t* alt_v = reinterpret_cast<uint32_t*>(p);
+    p += align256((size_t)cap * 4);
+    void* sort_ws = p;
+    const int kb = 32 + tile_bits(n_tiles);
+    const bool odd = sort_passes(kb) % 2 == 1;
+    launch_emit_pairs(n, proj->tiles_touched, reinterpret_cast<const ushort4*>(proj->rect), proj->depth, ntx, cap,
+                      odd ? alt_k : out->keys, odd ? alt_v : out->vals, out->pair_count, out->status, scan_ws, st);
+    launch_sort_pairs(out->keys, out->vals, alt_k, alt_v, out->pair_count, cap, kb, odd, sort_ws, st);
+    launch_tile_ranges(out->keys, out->pair_count, cap, n_tiles, out->ranges, st);
+    return check_hip("gs_bin_sort");
+}
+
+gs_status gs_render_fwd(const gs_proj* proj, const gs_bins* bins, const gs_camera* cam, const gs_opts* opts,
+                        float* image, float* final_T, uint32_t* n_contrib, gs_stream stream) {
+    Cam C;
+    int tw, th;
+    gs_status s;
+    if ((s = to_cam(cam, &C)) || (s = tiles_of(opts, &tw, &th)) || (s = check_bins(bins))) return s;
+    if (!proj || !proj->rec) return fail(GS_ERR_INVALID, "proj is NULL");
+    if (!image || !final_T || !n_contrib) return fail(GS_ERR_INVALID, "output buffer is NULL");
+    launch_render_fwd(static_cast<const Rec*>(proj->rec), bins->vals, bins->ranges, bins->status, C, tw, th, image,
+                      final_T, n_contrib, static_cast<hipStream_t>(stream));
+    return check_hip("gs_render_fwd");
+}
+
+gs_status gs_render_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_opts* opts, const gs_proj* proj,
+                        const gs_bins* bins, const float* final_T, const uint32_t* n_contrib,
+                        const float* dL_dimage, gs_grads* out, gs_stream stream) {
+    Gauss G;
+    Cam C;
+    int tw, th;
+    gs_status s;
+    if ((s = to_gauss(g, &G)) || (s = to_cam(cam, &C)) || (s = tiles_of(opts, &tw, &th)) ||
+        (s = check_proj(proj, G.n)) || (s = check_bins(bins)))
+        return s;
+    if (!final_T || !n_contrib || !dL_dimage || !out) return fail(GS_ERR_INVALID, "buffer is NULL");
+    if (out->ld < G.n) return fail(GS_ERR_INVALID, "gradient ld < n");
+    if (G.n > 0 && (!out->mean || !out->scale || !out->quat || !out->opacity || !out->sh || !out->grad2d))
+        return fail(GS_ERR_INVALID, "gradient buffer is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(out->grad2d), 0u, (size_t)G.n * 9, st);
+    launch_render_bwd(static_cast<const Rec*>(proj->rec), bins->vals, bins->ranges, bins->status, C, tw, th, final_T,
+                      n_contrib, dL_dimage, G.n, out->grad2d, st);
+    launch_project_bwd(G, C, proj->tiles_touched, out->grad2d, bins->status, out->ld, out->mean, out->scale,
+                       out->quat, out->opacity, out->sh, st);
+    return check_hip("gs_render_bwd");
+}
+
+gs_status gs_sort_workspace(int64_t capacity, int32_t key_bits, size_t* bytes) {
+    if (!bytes || capacity < 0 || capacity > kMaxPairs || key_bits < 0 || key_bits > 64)
+        return fail(GS_ERR_INVALID, "bad arguments");
+    *bytes = align256((size_t)capacity * 8) + align256((size_t)capacity * 4) +
+             align256(sort_workspace_bytes(capacity, key_bits));
+    return GS_OK;
+}
+
+gs_status gs_sort_pairs(uint64_t* keys, uint32_t* vals, const uint32_t* count, int64_t capacity, int32_t key_bits,
+                        void* ws, size_t ws_bytes, gs_stream stream) {
+    size_t need = 0;
+    gs_status s;
+    if ((s = gs_sort_workspace(capacity, key_bits, &need))) return s;
+    if (!count || (capacity > 0 && (!keys || !vals))) return fail(GS_ERR_INVALID, "NULL buffer");
+    if (!ws || ws_bytes < need) return fail(GS_ERR_INVALID, "workspace too small: %zu < %zu", ws_bytes, need);
+    char* p = static_cast<char*>(ws);
+    uint64_t* alt_k = reinterpret_cast<uint64_t*>(p);
+    p += align256((size_t)capacity * 8);
+    uint32_t* alt_v = reinterpret_cast<uint32_t*>(p);
+    p += align256((size_t)capacity * 4);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    launch_sort_pairs(keys, vals, alt_k, alt_v, count, capacity, key_bits, false, p, st);
+    return check_hip("gs_sort_pairs");
+}
+
+}  // extern "C"

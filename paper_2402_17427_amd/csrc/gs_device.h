@@ -1,0 +1,128 @@
+// Device-side definitions shared by the rasterizer kernels (gfx950).
+//
+// The image-formation model is the one VastGaussian (arXiv 2402.17427)
+// inherits from 3D Gaussian Splatting (section 3; section 5.1 keeps the 3DGS
+// settings): 2D Gaussians blended front to back with alpha = min(0.99,
+// o exp(power)), contributions below 1/255 skipped and a pixel finished
+// before the Gaussian that would take its transmittance below 1e-4.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace gs {
+
+// Image-formation constants.
+constexpr float kDilation = 0.3f;     // px^2 added to the projected covariance
+constexpr float kFovClamp = 1.3f;     // affine-approximation clamp of x/z, y/z
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTMin = 1e-4f;
+constexpr float kLog2e = 1.4426950408889634f;
+
+constexpr int kWave = 64;
+
+// Projected Gaussian, 48 bytes, read as three 16-byte vectors.  The centre
+// is kept in FP64 so that pixel offsets can be formed to a few ulp of the
+// offset itself, whatever the image size.
+struct alignas(16) Rec {
+    double u, v;        // pixel-space centre
+    float A, B, C, o;   // conic (inverse 2D covariance) and opacity
+    float r, g, b;      // colour
+    uint32_t ext;       // half-extents (ex, ey) of the alpha >= 1/255
+                        // support as two binary16 values rounded up
+};
+static_assert(sizeof(Rec) == 48, "record layout");
+
+// Camera as the kernels see it (mirrors gs_camera).
+struct Cam {
+    float R[9], t[3];
+    float fx, fy, cx, cy;
+    int W, H;
+    float near_z;
+    float bg[3];
+};
+
+// Gaussian SoA planes (mirrors gs_gaussians).
+struct Gauss {
+    int64_t n, ld;
+    int deg, K;
+    const float *mean, *scale, *quat, *opacity, *sh;
+};
+
+// One projected Gaussian staged in LDS for a tile.  The centre is held as
+// an unevaluated float sum hi + lo of the FP64 centre, and a pixel offset is
+// formed as (pixel centre - hi) - lo: a function of the pixel and the
+// Gaussian only, so the result does not depend on the tile size or origin,
+// and its error is a few ulp of the offset itself.  The conic is pre-scaled
+// so that exp2(ca dx^2 + cb dx dy + cc dy^2) = exp(power).  Forward and
+// backward stage the same values through stage_rec(), so both take
+// identical decisions.
+struct Staged {
+    float4 geo;   // hi_u, lo_u, hi_v, lo_v
+    float4 coef;  // ca, cb, cc, o
+    float4 col;   // r, g, b, half-extents (ex, ey) as binary16 bits
+};
+
+__device__ __forceinline__ Staged stage_rec(const Rec& r) {
+    Staged s;
+    const float hu = (float)r.u, hv = (float)r.v;
+    s.geo = make_float4(hu, (float)(r.u - (double)hu), hv, (float)(r.v - (double)hv));
+    s.coef = make_float4(r.A * (-0.5f * kLog2e), r.B * (-kLog2e), r.C * (-0.5f * kLog2e), r.o);
+    s.col = make_float4(r.r, r.g, r.b, __uint_as_float(r.ext));
+    return s;
+}
+
+// Evaluate one staged Gaussian at pixel centre (x, y) (image coordinates).
+// Returns alpha (0 when the pair is skipped) and G = exp(power).
+struct Eval {
+    float dx, dy, G, alpha;
+    bool capped;
+};
+
+__device__ __forceinline__ Eval eval_pair(const Staged& s, float x, float y) {
+    Eval e;
+    e.dx = (x - s.geo.x) - s.geo.y;
+    e.dy = (y - s.geo.z) - s.geo.w;
+    const float p = __builtin_fmaf(s.coef.x, e.dx * e.dx, __builtin_fmaf(s.coef.z, e.dy * e.dy, s.coef.y * (e.dx * e.dy)));
+    e.G = __builtin_amdgcn_exp2f(p);
+    const float araw = s.coef.w * e.G;
+    e.capped = araw > kAlphaMax;
+    const float a = e.capped ? kAlphaMax : araw;
+    e.alpha = (p > 0.0f || a < kAlphaMin) ? 0.0f : a;
+    return e;
+}
+
+// Can the staged Gaussian reach alpha >= 1/255 at any pixel centre in the
+// box [x0, x1] x [y0, y1] (image coordinates)?  Conservative: the
+// half-extents are rounded up and get a margin.
+__device__ __forceinline__ bool box_overlaps(const Staged& s, float x0, float x1, float y0, float y1) {
+    const __half2 e = *reinterpret_cast<const __half2*>(&s.col.w);
+    const float ex = __half2float(__low2half(e)) + 0.01f, ey = __half2float(__high2half(e)) + 0.01f;
+    return s.geo.x + ex >= x0 && s.geo.x - ex <= x1 && s.geo.z + ey >= y0 && s.geo.z - ey <= y1;
+}
+
+__device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_relaxed(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum of v over the 64 lanes of the wave, returned to every lane
+// (DPP row reductions, then the two cross-row broadcasts of GFX9).
+__device__ __forceinline__ float wave_sum(float v) {
+    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true));  // quad_perm [1,0,3,2]
+    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, true));  // quad_perm [2,3,0,1]
+    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x141, 0xF, 0xF, true)); // row_half_mirror
+    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x140, 0xF, 0xF, true)); // row_mirror
+    // every lane of a 16-lane row now holds the row sum
+    const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
+    const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
+    const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+    const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
+}  // namespace gs

@@ -1,0 +1,186 @@
+// Backward of the tile blend: per-Gaussian image-space gradients.
+//
+// VastGaussian (arXiv 2402.17427), section 3: the renderer is differentiable
+// and the Gaussians are optimised by gradient descent.  For a pixel with
+// blended Gaussians i = 1..n (weights w_i = alpha_i T_i), colour
+// C = sum_i rgb_i w_i + T_final bg, the gradients are
+//   dL/drgb_i   = g w_i
+//   dL/dalpha_i = g . (rgb_i T_i - S_i / (1 - alpha_i)),
+//                 S_i = sum_{j > i} rgb_j w_j + T_final bg
+// and, unless alpha_i was capped at 0.99, dL/do = dalpha G and
+// dL/dpower = dalpha alpha, from which the conic (A, B, C) and centre (u, v)
+// gradients follow.  g is dL/dpixel.
+//
+// No per-contributor state is stored by the forward: each pixel walks its
+// tile list back to front from its last contributor, recomputes alpha with
+// the same staged values and code as the forward (so it takes the same
+// skip decisions), recovers T_i = T_{i+1} / (1 - alpha_i) from the stored
+// final transmittance, and accumulates S_i as it goes.
+//
+// Reduction: per staged Gaussian, a wave first checks (ballot) whether any
+// of its 64 pixels contributed; only then are the nine gradient terms
+// summed across the wave with DPP row reductions, added into a per-tile LDS
+// accumulator by one lane, and flushed with one global FP32 atomic per
+// (Gaussian, term, tile) after the batch.
+#include "kernels.h"
+
+namespace gs {
+
+namespace {
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_render_bwd(const Rec* __restrict__ rec, const uint32_t* __restrict__ vals,
+                                                        const uint2* __restrict__ ranges,
+                                                        const int32_t* __restrict__ status, int W, int H, int ntx,
+                                                        float bg0, float bg1, float bg2,
+                                                        const float* __restrict__ final_T,
+                                                        const uint32_t* __restrict__ n_contrib,
+                                                        const float* __restrict__ dimg, int64_t n,
+                                                        float* __restrict__ g2d) {
+    constexpr int NT = TW * TH;
+    constexpr int B = NT < 256 ? NT : 256;   // staged Gaussians per batch
+    constexpr int WX = TW / 8;
+    __shared__ Staged s[B];
+    __shared__ uint32_t s_gid[B];
+    __shared__ float s_acc[B * 9];
+    __shared__ uint32_t s_max;
+
+    if (*status != 0) return;
+
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int tile = blockIdx.x;
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int bx = (wv % WX) * 8, by = (wv / WX) * 8;
+    const int lx = bx + (lane & 7), ly = by + (lane >> 3);
+    const int px = tx * TW + lx, py = ty * TH + ly;
+    const bool inside = px < W && py < H;
+    const int64_t npix = (int64_t)W * H;
+    const int64_t off = (int64_t)py * W + px;
+
+    const uint2 rg = ranges[tile];
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const float bx0 = (float)(tx * TW + bx) + 0.5f, bx1 = bx0 + 7.0f;
+    const float by0 = (float)(ty * TH + by) + 0.5f, by1 = by0 + 7.0f;
+
+    uint32_t my_last = 0;
+    float T = 1.0f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    if (inside) {
+        my_last = n_contrib[off];
+        T = final_T[off];
+        g0 = dimg[off];
+        g1 = dimg[npix + off];
+        g2 = dimg[2 * npix + off];
+    }
+    const float tb0 = T * bg0, tb1 = T * bg1, tb2 = T * bg2;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;   // sum of rgb_j w_j over j behind the current entry
+
+    if (tid == 0) s_max = 0u;
+    __syncthreads();
+    if (my_last) atomicMax(&s_max, my_last);
+    __syncthreads();
+    // never walk past the tile's list, whatever n_contrib holds
+    const uint32_t max_last = min(s_max, rg.y - rg.x);
+
+    for (int64_t hi = (int64_t)max_last; hi > 0; hi -= B) {
+        const int64_t lo = hi - B > 0 ? hi - B : 0;
+        const int nb = (int)(hi - lo);
+        __syncthreads();
+        if (tid < nb) {
+            const uint32_t gid = vals[rg.x + lo + tid];
+            s_gid[tid] = gid;
+            s[tid] = stage_rec(rec[gid]);
+        }
+        for (int q = tid; q < B * 9; q += NT) s_acc[q] = 0.f;
+        __syncthreads();
+
+        for (int k = nb - 1; k >= 0; --k) {
+            const Staged g = s[k];
+            if (!__builtin_amdgcn_readfirstlane((int)box_overlaps(g, bx0, bx1, by0, by1))) continue;
+            const uint32_t pos = (uint32_t)(lo + k);
+            float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f, v7 = 0.f, v8 = 0.f;
+            bool contrib = false;
+            if (pos < my_last) {
+                const Eval e = eval_pair(g, fx, fy);
+                if (e.alpha > 0.0f) {
+                    contrib = true;
+                    const float om = 1.0f - e.alpha;
+                    const float Ti = T / om;
+                    const float w = e.alpha * Ti;
+                    const float r = g.col.x, gg = g.col.y, b = g.col.z;
+                    v6 = g0 * w;
+                    v7 = g1 * w;
+                    v8 = g2 * w;
+                    const float iom = 1.0f / om;
+                    const float da = g0 * (r * Ti - (a0 + tb0) * iom) + g1 * (gg * Ti - (a1 + tb1) * iom) +
+                                     g2 * (b * Ti - (a2 + tb2) * iom);
+                    a0 = __builtin_fmaf(r, w, a0);
+                    a1 = __builtin_fmaf(gg, w, a1);
+                    a2 = __builtin_fmaf(b, w, a2);
+                    T = Ti;
+                    if (!e.capped) {
+                        v5 = da * e.G;
+                        const float dpow = da * e.alpha;
+                        v2 = -0.5f * e.dx * e.dx * dpow;
+                        v3 = -e.dx * e.dy * dpow;
+                        v4 = -0.5f * e.dy * e.dy * dpow;
+                        // A = -2 ca / log2e, B = -cb / log2e, C = -2 cc / log2e
+                        const float q = -dpow * (1.0f / kLog2e);
+                        v0 = (2.0f * g.coef.x * e.dx + g.coef.y * e.dy) * q;
+                        v1 = (g.coef.y * e.dx + 2.0f * g.coef.z * e.dy) * q;
+                    }
+                }
+            }
+            if (__ballot(contrib) == 0ull) continue;
+            const float r0 = wave_sum(v0), r1 = wave_sum(v1), r2 = wave_sum(v2), r3 = wave_sum(v3),
+                        r4 = wave_sum(v4), r5 = wave_sum(v5), r6 = wave_sum(v6), r7 = wave_sum(v7),
+                        r8 = wave_sum(v8);
+            if (lane == 0) {
+                float* acc = &s_acc[k * 9];
+                atomicAdd(acc + 0, r0);
+                atomicAdd(acc + 1, r1);
+                atomicAdd(acc + 2, r2);
+                atomicAdd(acc + 3, r3);
+                atomicAdd(acc + 4, r4);
+                atomicAdd(acc + 5, r5);
+                atomicAdd(acc + 6, r6);
+                atomicAdd(acc + 7, r7);
+                atomicAdd(acc + 8, r8);
+            }
+        }
+        __syncthreads();
+        for (int q = tid; q < nb * 9; q += NT) {
+            const float v = s_acc[q];
+            if (v != 0.0f) {
+                const int k = q / 9, c = q - 9 * (q / 9);
+                atomicAdd(&g2d[(int64_t)c * n + s_gid[k]], v);
+            }
+        }
+    }
+}
+
+template <int TW, int TH>
+void launch_t(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status, const Cam& cam,
+              const float* final_T, const uint32_t* n_contrib, const float* dimg, int64_t n, float* g2d,
+              hipStream_t st) {
+    const int ntx = (cam.W + TW - 1) / TW, nty = (cam.H + TH - 1) / TH;
+    hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3((unsigned)(ntx * nty)), dim3(TW * TH), 0, st, rec, vals,
+                       reinterpret_cast<const uint2*>(ranges), status, cam.W, cam.H, ntx, cam.bg[0], cam.bg[1],
+                       cam.bg[2], final_T, n_contrib, dimg, n, g2d);
+}
+
+}  // namespace
+
+void launch_render_bwd(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status,
+                       const Cam& cam, int tw, int th, const float* final_T, const uint32_t* n_contrib,
+                       const float* dimg, int64_t n, float* g2d, hipStream_t st) {
+#define GS_BWD(a, b) launch_t<a, b>(rec, vals, ranges, status, cam, final_T, n_contrib, dimg, n, g2d, st)
+    if (tw == 16 && th == 16) GS_BWD(16, 16);
+    else if (tw == 8 && th == 8) GS_BWD(8, 8);
+    else if (tw == 16 && th == 8) GS_BWD(16, 8);
+    else if (tw == 32 && th == 8) GS_BWD(32, 8);
+    else if (tw == 32 && th == 16) GS_BWD(32, 16);
+    else if (tw == 32 && th == 32) GS_BWD(32, 32);
+#undef GS_BWD
+}
+
+}  // namespace gs

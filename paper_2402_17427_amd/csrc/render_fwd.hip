@@ -1,0 +1,131 @@
+// Front-to-back alpha blend of each screen tile (forward).
+//
+// VastGaussian (arXiv 2402.17427), section 3: the sorted 2D Gaussians of
+// each tile are alpha-blended into the image in a point-based volume
+// rendering manner.  Per pixel, walking the tile's list in depth order:
+//   alpha = min(0.99, o exp(power)); skipped when power > 0 or
+//   alpha < 1/255; the pixel stops before the Gaussian that would take T
+//   below 1e-4; otherwise C += colour alpha T and T *= (1 - alpha).
+// Output pixel = C + T bg.
+//
+// Launch: one workgroup per tile, one lane per pixel.  Every wave covers an
+// 8x8 block of the tile, so that a small Gaussian touches few waves; a wave
+// skips (uniformly) every Gaussian whose support box misses its block,
+// which never changes a result because such a Gaussian has alpha < 1/255 at
+// all of the block's pixels.  Batches of records are staged in LDS and
+// read as broadcasts; a wave leaves the batch once all its pixels have
+// stopped, and the workgroup leaves the tile once all of its waves have.
+#include "kernels.h"
+
+namespace gs {
+
+namespace {
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ rec, const uint32_t* __restrict__ vals,
+                                                        const uint2* __restrict__ ranges,
+                                                        const int32_t* __restrict__ status, int W, int H, int ntx,
+                                                        float bg0, float bg1, float bg2, float* __restrict__ image,
+                                                        float* __restrict__ final_T, uint32_t* __restrict__ n_contrib) {
+    constexpr int NT = TW * TH;
+    constexpr int WX = TW / 8;
+    __shared__ Staged s[NT];
+
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int tile = blockIdx.x;
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int bx = (wv % WX) * 8, by = (wv / WX) * 8;
+    const int lx = bx + (lane & 7), ly = by + (lane >> 3);
+    const int px = tx * TW + lx, py = ty * TH + ly;
+    const bool inside = px < W && py < H;
+    const int64_t npix = (int64_t)W * H;
+    const int64_t off = (int64_t)py * W + px;
+
+    if (*status != 0) {
+        if (inside) {
+            const float nan = __builtin_nanf("");
+            image[off] = nan;
+            image[npix + off] = nan;
+            image[2 * npix + off] = nan;
+            final_T[off] = nan;
+            n_contrib[off] = 0u;
+        }
+        return;
+    }
+
+    const uint2 rg = ranges[tile];
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const float bx0 = (float)(tx * TW + bx) + 0.5f, bx1 = bx0 + 7.0f;
+    const float by0 = (float)(ty * TH + by) + 0.5f, by1 = by0 + 7.0f;
+
+    float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+    uint32_t last = 0;
+    bool done = !inside;
+
+    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += NT) {
+        if (__syncthreads_count(done) == NT) break;
+        const uint32_t j = b0 + tid;
+        if (j < rg.y) s[tid] = stage_rec(rec[vals[j]]);
+        __syncthreads();
+        const int nb = (int)min((uint32_t)NT, rg.y - b0);
+        if (__ballot(!done) != 0ull) {
+            for (int k = 0; k < nb; ++k) {
+                const Staged g = s[k];
+                if (!__builtin_amdgcn_readfirstlane((int)box_overlaps(g, bx0, bx1, by0, by1))) continue;
+                if (!done) {
+                    const Eval e = eval_pair(g, fx, fy);
+                    if (e.alpha > 0.0f) {
+                        const float Tn = T * (1.0f - e.alpha);
+                        if (Tn < kTMin) {
+                            done = true;
+                        } else {
+                            const float w = e.alpha * T;
+                            c0 = __builtin_fmaf(g.col.x, w, c0);
+                            c1 = __builtin_fmaf(g.col.y, w, c1);
+                            c2 = __builtin_fmaf(g.col.z, w, c2);
+                            T = Tn;
+                            last = b0 - rg.x + (uint32_t)k + 1u;
+                        }
+                    }
+                }
+                if (__ballot(!done) == 0ull) break;
+            }
+        }
+    }
+    if (inside) {
+        image[off] = __builtin_fmaf(T, bg0, c0);
+        image[npix + off] = __builtin_fmaf(T, bg1, c1);
+        image[2 * npix + off] = __builtin_fmaf(T, bg2, c2);
+        final_T[off] = T;
+        n_contrib[off] = last;
+    }
+}
+
+template <int TW, int TH>
+void launch_t(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status, const Cam& cam,
+              float* image, float* final_T, uint32_t* n_contrib, hipStream_t st) {
+    const int ntx = (cam.W + TW - 1) / TW, nty = (cam.H + TH - 1) / TH;
+    hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3((unsigned)(ntx * nty)), dim3(TW * TH), 0, st, rec, vals,
+                       reinterpret_cast<const uint2*>(ranges), status, cam.W, cam.H, ntx, cam.bg[0], cam.bg[1],
+                       cam.bg[2], image, final_T, n_contrib);
+}
+
+}  // namespace
+
+bool render_tile_supported(int tw, int th) {
+    return (tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 16 && th == 8) || (tw == 32 && th == 8) ||
+           (tw == 32 && th == 16) || (tw == 32 && th == 32);
+}
+
+void launch_render_fwd(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status,
+                       const Cam& cam, int tw, int th, float* image, float* final_T, uint32_t* n_contrib,
+                       hipStream_t st) {
+    if (tw == 16 && th == 16) launch_t<16, 16>(rec, vals, ranges, status, cam, image, final_T, n_contrib, st);
+    else if (tw == 8 && th == 8) launch_t<8, 8>(rec, vals, ranges, status, cam, image, final_T, n_contrib, st);
+    else if (tw == 16 && th == 8) launch_t<16, 8>(rec, vals, ranges, status, cam, image, final_T, n_contrib, st);
+    else if (tw == 32 && th == 8) launch_t<32, 8>(rec, vals, ranges, status, cam, image, final_T, n_contrib, st);
+    else if (tw == 32 && th == 16) launch_t<32, 16>(rec, vals, ranges, status, cam, image, final_T, n_contrib, st);
+    else if (tw == 32 && th == 32) launch_t<32, 32>(rec, vals, ranges, status, cam, image, final_T, n_contrib, st);
+}
+
+}  // namespace gs

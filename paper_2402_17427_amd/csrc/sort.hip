@@ -1,0 +1,310 @@
+// Stable LSD radix sort of (uint64 key, uint32 value) pairs, onesweep form.
+//
+// VastGaussian (arXiv 2402.17427), section 3: the (Gaussian, tile) pairs are
+// sorted by tile and, within a tile, by depth.  The key is
+// (tile << 32) | float32 bits of the (positive) depth, so an unsigned
+// integer sort gives both orders at once; the sort must be stable so that
+// equal keys keep the Gaussian-index order in which they were emitted.
+//
+// Structure (8-bit digits, one kernel per digit pass):
+//   k_sort_clear  zero the digit histograms, partition counters and
+//                 look-back words for the pair count on the device
+//   k_hist        one read of every key builds the histograms of all
+//                 passes at once (LDS atomics, then one global atomic per
+//                 non-empty bin and workgroup)
+//   k_hist_scan   exclusive scan of each pass's 256 bins
+//   k_onesweep    per pass: each workgroup takes the next partition of
+//                 4096 keys from an atomic counter, ranks its keys stably
+//                 with wave64 ballots (match-by-digit), publishes its digit
+//                 counts and resolves its global offsets by decoupled
+//                 look-back over the earlier partitions, sorts the
+//                 partition locally in LDS and writes it out digit run by
+//                 digit run (coalesced).
+// The pair count stays on the device; grids are sized for the capacity
+// and surplus workgroups find no partition and exit.
+#include "kernels.h"
+
+namespace gs {
+
+namespace {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortWaves = kSortThreads / kWave;
+constexpr int kIPT = 16;                        // keys per lane per partition
+constexpr int kWavePart = kWave * kIPT;         // 1024
+constexpr int kPart = kSortThreads * kIPT;      // 4096 keys per partition
+constexpr int kRadix = 256;
+constexpr int kMaxPasses = 8;
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagInc = 2u << 30;
+constexpr uint32_t kValMask = (1u << 30) - 1u;
+constexpr int kMaxGrid = 2048;
+
+struct SortWs {
+    int64_t capacity;    // pairs the buffers hold; the device count is clamped to it
+    uint32_t* hist;      // [passes][256]: counts, then exclusive offsets
+    uint32_t* counter;   // [passes]: next partition id
+    uint32_t* look;      // [passes][max_parts][256]: look-back words
+    int64_t max_parts;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+SortWs carve(void* ws, int64_t capacity, int passes) {
+    SortWs s;
+    char* p = static_cast<char*>(ws);
+    s.capacity = capacity;
+    s.max_parts = (capacity + kPart - 1) / kPart;
+    s.hist = reinterpret_cast<uint32_t*>(p);
+    p += align256((size_t)kMaxPasses * kRadix * 4);
+    s.counter = reinterpret_cast<uint32_t*>(p);
+    p += align256((size_t)kMaxPasses * 4);
+    s.look = reinterpret_cast<uint32_t*>(p);
+    (void)passes;
+    return s;
+}
+
+__device__ __forceinline__ int64_t clamp_count(const uint32_t* count, int64_t capacity) {
+    const int64_t c = *count;
+    return c < capacity ? c : capacity;
+}
+
+__global__ __launch_bounds__(256) void k_sort_clear(SortWs w, const uint32_t* __restrict__ count, int passes) {
+    const int64_t P = clamp_count(count, w.capacity);
+    const int64_t parts = ((int64_t)P + kPart - 1) / kPart;
+    const int64_t tid = (int64_t)blockIdx.x * 256 + threadIdx.x, stride = (int64_t)gridDim.x * 256;
+    for (int64_t j = tid; j < (int64_t)passes * kRadix; j += stride) w.hist[j] = 0u;
+    for (int64_t j = tid; j < passes; j += stride) w.counter[j] = 0u;
+    for (int p = 0; p < passes; ++p)
+        for (int64_t j = tid; j < parts * kRadix; j += stride) w.look[(int64_t)p * w.max_parts * kRadix + j] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_hist(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ count,
+                                              int passes, SortWs w) {
+    __shared__ uint32_t h[kMaxPasses * kRadix];
+    for (int j = threadIdx.x; j < passes * kRadix; j += 256) h[j] = 0u;
+    __syncthreads();
+    const int64_t P = clamp_count(count, w.capacity);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256) {
+        const uint64_t k = keys[i];
+        for (int p = 0; p < passes; ++p) atomicAdd(&h[p * kRadix + (uint32_t)((k >> (8 * p)) & 0xFF)], 1u);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < passes * kRadix; j += 256)
+        if (h[j]) atomicAdd(&w.hist[j], h[j]);
+}
+
+__global__ __launch_bounds__(kRadix) void k_hist_scan(SortWs w, int passes) {
+    __shared__ uint32_t s[kRadix];
+    const int t = threadIdx.x;
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t v = w.hist[p * kRadix + t];
+        s[t] = v;
+        __syncthreads();
+        // Hillis-Steele inclusive scan over 256 entries
+        for (int d = 1; d < kRadix; d <<= 1) {
+            const uint32_t y = t >= d ? s[t - d] : 0u;
+            __syncthreads();
+            s[t] += y;
+            __syncthreads();
+        }
+        w.hist[p * kRadix + t] = s[t] - v;
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ uint64_t ballot64(bool b) { return __ballot(b); }
+
+__global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __restrict__ kin,
+                                                           const uint32_t* __restrict__ vin,
+                                                           uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                           const uint32_t* __restrict__ count, int pass, SortWs w) {
+    __shared__ uint64_t s_keys[kPart];
+    __shared__ uint32_t s_vals[kPart];
+    __shared__ uint32_t s_whist[kSortWaves][kRadix];  // per-wave counts, then per-wave offsets
+    __shared__ uint32_t s_lofs[kRadix];               // digit start within the partition
+    __shared__ uint32_t s_dbase[kRadix];              // digit start in the output
+    __shared__ uint32_t s_scan[kSortWaves];
+    __shared__ int64_t s_part;
+
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int shift = 8 * pass;
+    const int64_t P = clamp_count(count, w.capacity);
+    const int64_t nparts = (P + kPart - 1) / kPart;
+    uint32_t* look = w.look + (int64_t)pass * w.max_parts * kRadix;
+    const uint32_t* goff = w.hist + pass * kRadix;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+    for (;;) {
+        if (tid == 0) s_part = (int64_t)atomicAdd(&w.counter[pass], 1u);
+        __syncthreads();
+        const int64_t part = s_part;
+        if (part >= nparts) break;
+        const int64_t base = part * kPart;
+        const int nvalid = (int)((P - base) < kPart ? (P - base) : kPart);
+
+        for (int j = lane; j < kRadix; j += kWave) s_whist[wv][j] = 0u;
+
+        uint64_t key[kIPT];
+        uint32_t val[kIPT];
+        uint32_t rank[kIPT];
+        const int64_t wbase = base + (int64_t)wv * kWavePart;
+#pragma unroll
+        for (int k = 0; k < kIPT; ++k) {
+            const int64_t idx = wbase + k * kWave + lane;
+            const bool ok = idx < P;
+            key[k] = ok ? kin[idx] : ~0ull;
+            val[k] = ok ? vin[idx] : 0u;
+        }
+        __builtin_amdgcn_wave_barrier();
+
+#pragma unroll
+        for (int k = 0; k < kIPT; ++k) {
+            const int64_t idx = wbase + k * kWave + lane;
+            const bool ok = idx < P;
+            const uint32_t d = (uint32_t)(key[k] >> shift) & 0xFFu;
+            uint64_t m = ballot64(ok);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t vote = ballot64(bit);
+                m &= bit ? vote : ~vote;
+            }
+            const uint32_t below = (uint32_t)__popcll(m & lt_mask);
+            const uint32_t old = ok ? s_whist[wv][d] : 0u;
+            rank[k] = old + below;
+            __builtin_amdgcn_wave_barrier();
+            if (ok && below == 0) s_whist[wv][d] = old + (uint32_t)__popcll(m);
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+
+        // thread t owns digit t: wave offsets, partition count, look-back
+        {
+            const int t = tid;
+            uint32_t run = 0;
+#pragma unroll
+            for (int q = 0; q < kSortWaves; ++q) {
+                const uint32_t c = s_whist[q][t];
+                s_whist[q][t] = run;
+                run += c;
+            }
+            const uint32_t total = run;
+            if (part == 0) {
+                store_relaxed(&look[t], kFlagInc | total);
+                s_dbase[t] = goff[t];
+            } else {
+                store_relaxed(&look[part * kRadix + t], kFlagAgg | total);
+                uint32_t prefix = 0;
+                int64_t j = part - 1;
+                while (j >= 0) {
+                    const uint32_t v = load_relaxed(&look[j * kRadix + t]);
+                    const uint32_t flag = v & ~kValMask;
+                    if (flag == 0u) {
+                        __builtin_amdgcn_s_sleep(1);
+                        continue;
+                    }
+                    prefix += v & kValMask;
+                    if (flag == kFlagInc) break;
+                    --j;
+                }
+                store_relaxed(&look[part * kRadix + t], kFlagInc | (prefix + total));
+                s_dbase[t] = goff[t] + prefix;
+            }
+            // exclusive scan of the partition's digit counts
+            uint32_t x = total;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t y = __shfl_up(x, d, kWave);
+                if (lane >= d) x += y;
+            }
+            if (lane == kWave - 1) s_scan[wv] = x;
+            __syncthreads();
+            uint32_t wb = 0;
+#pragma unroll
+            for (int q = 0; q < kSortWaves; ++q)
+                if (q < wv) wb += s_scan[q];
+            s_lofs[t] = wb + x - total;
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int k = 0; k < kIPT; ++k) {
+            const int64_t idx = wbase + k * kWave + lane;
+            if (idx < P) {
+                const uint32_t d = (uint32_t)(key[k] >> shift) & 0xFFu;
+                const uint32_t lp = s_lofs[d] + s_whist[wv][d] + rank[k];
+                s_keys[lp] = key[k];
+                s_vals[lp] = val[k];
+            }
+        }
+        __syncthreads();
+
+        for (int i = tid; i < nvalid; i += kSortThreads) {
+            const uint64_t kk = s_keys[i];
+            const uint32_t d = (uint32_t)(kk >> shift) & 0xFFu;
+            const uint32_t gp = s_dbase[d] + (uint32_t)i - s_lofs[d];
+            kout[gp] = kk;
+            vout[gp] = s_vals[i];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_copy_pairs(const uint64_t* __restrict__ ks, const uint32_t* __restrict__ vs,
+                                                    uint64_t* __restrict__ kd, uint32_t* __restrict__ vd,
+                                                    const uint32_t* __restrict__ count, int64_t capacity) {
+    const int64_t P = clamp_count(count, capacity);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256) {
+        kd[i] = ks[i];
+        vd[i] = vs[i];
+    }
+}
+
+}  // namespace
+
+int sort_passes(int key_bits) { return (key_bits + 7) / 8; }
+
+size_t sort_workspace_bytes(int64_t capacity, int key_bits) {
+    const int passes = sort_passes(key_bits);
+    const int64_t parts = (capacity + kPart - 1) / kPart;
+    return align256((size_t)kMaxPasses * kRadix * 4) + align256((size_t)kMaxPasses * 4) +
+           align256((size_t)passes * (size_t)(parts > 0 ? parts : 1) * kRadix * 4);
+}
+
+void launch_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals, const uint32_t* count,
+                       int64_t capacity, int key_bits, bool start_in_alt, void* ws, hipStream_t st) {
+    const int passes = sort_passes(key_bits);
+    if (passes == 0 || capacity == 0) {
+        if (start_in_alt && capacity > 0)
+            hipLaunchKernelGGL(k_copy_pairs, dim3(1024), dim3(256), 0, st, alt_keys, alt_vals, keys, vals, count,
+                               capacity);
+        return;
+    }
+    SortWs w = carve(ws, capacity, passes);
+    const int64_t parts = (capacity + kPart - 1) / kPart;
+    int64_t clear_blocks = (parts * kRadix + 255) / 256;
+    if (clear_blocks > 1024) clear_blocks = 1024;
+    if (clear_blocks < 1) clear_blocks = 1;
+    hipLaunchKernelGGL(k_sort_clear, dim3((unsigned)clear_blocks), dim3(256), 0, st, w, count, passes);
+    const uint64_t* src = start_in_alt ? alt_keys : keys;
+    int64_t hb = (capacity + 256 * 16 - 1) / (256 * 16);
+    if (hb > kMaxGrid) hb = kMaxGrid;
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)hb), dim3(256), 0, st, src, count, passes, w);
+    hipLaunchKernelGGL(k_hist_scan, dim3(1), dim3(kRadix), 0, st, w, passes);
+    int64_t grid = parts < kMaxGrid ? parts : kMaxGrid;
+    bool in_alt = start_in_alt;
+    for (int p = 0; p < passes; ++p) {
+        const uint64_t* ki = in_alt ? alt_keys : keys;
+        const uint32_t* vi = in_alt ? alt_vals : vals;
+        uint64_t* ko = in_alt ? keys : alt_keys;
+        uint32_t* vo = in_alt ? vals : alt_vals;
+        hipLaunchKernelGGL(k_onesweep, dim3((unsigned)grid), dim3(kSortThreads), 0, st, ki, vi, ko, vo, count, p, w);
+        in_alt = !in_alt;
+    }
+    if (in_alt)  // result sits in the alternate buffers
+        hipLaunchKernelGGL(k_copy_pairs, dim3(1024), dim3(256), 0, st, alt_keys, alt_vals, keys, vals, count,
+                               capacity);
+}
+
+}  // namespace gs

@@ -1,0 +1,60 @@
+"""Helpers for the GPU parity tests: unpacking the device projection record
+and the gradient tolerance used across tests.
+
+Tolerances (written out here once, used by every GPU test):
+  image        |I_gpu - I_ref| <= 1e-4 at every pixel the oracle does not
+               flag as ambiguous (a discontinuous decision within its
+               window of the threshold); flagged pixels are counted.
+  gradients    per parameter group, elementwise
+               |g - g_ref| <= 1e-3 (|g_ref| + 1e-2 max|g_ref|_group)
+               and ||g - g_ref|| / ||g_ref|| <= 1e-3, over the Gaussians that
+               touch no flagged pixel.
+  integers     keys, values, ranges, tile rectangles: bit-exact.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+IMAGE_ATOL = 1e-4
+GRAD_RTOL = 1e-3
+GRAD_FLOOR = 1e-2
+
+
+def unpack_rec(rec_f32: np.ndarray, n: int) -> dict:
+    """Split the 48-byte device records (as a float32 array) into fields."""
+    raw = np.ascontiguousarray(rec_f32[: n * 12]).view(np.uint8).reshape(n, 48)
+    uv = raw[:, 0:16].copy().view(np.float64).reshape(n, 2)
+    f = raw[:, 16:48].copy().view(np.float32).reshape(n, 8)
+    ext = raw[:, 44:48].copy().view(np.float16).reshape(n, 2).astype(np.float64)
+    return dict(uv=uv, conic=f[:, 0:3].astype(np.float64), opacity=f[:, 3].astype(np.float64),
+                rgb=f[:, 4:7].astype(np.float64), ext=ext)
+
+
+def grad_close(name, g, ref, rtol=GRAD_RTOL, floor=GRAD_FLOOR):
+    g = np.asarray(g, np.float64)
+    ref = np.asarray(ref, np.float64)
+    assert g.shape == ref.shape, (name, g.shape, ref.shape)
+    if ref.size == 0:
+        return 0.0
+    scale = np.abs(ref).max()
+    err = np.abs(g - ref)
+    lim = rtol * (np.abs(ref) + floor * scale)
+    bad = err > lim
+    nrm = np.linalg.norm(ref)
+    rel = np.linalg.norm(g - ref) / nrm if nrm > 0 else np.linalg.norm(g)
+    if bad.any() or rel > rtol:
+        i = np.unravel_index(np.argmax(err - lim), err.shape)
+        raise AssertionError(f"{name}: {bad.sum()} of {bad.size} elements outside tolerance, norm rel {rel:.3e}; "
+                             f"worst at {i}: got {g[i]:.6e} want {ref[i]:.6e} (scale {scale:.3e})")
+    return rel
+
+
+def image_close(name, img, ref, flags, atol=IMAGE_ATOL, max_flagged_frac=0.01):
+    img = np.asarray(img, np.float64)
+    ok = flags == 0
+    err = np.abs(img - ref)[:, ok] if img.ndim == 3 else np.abs(img - ref)[ok]
+    worst = float(err.max()) if err.size else 0.0
+    assert worst <= atol, f"{name}: max error {worst:.3e} at unflagged pixels (atol {atol})"
+    frac = float((~ok).mean())
+    assert frac <= max_flagged_frac, f"{name}: {frac:.4f} of pixels flagged"
+    return worst, int((~ok).sum())

@@ -1,0 +1,70 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports
+every function include/gs.h declares, and rejects bad arguments on the host
+before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2402_17427_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"^[A-Za-z_][\w \*]*?\b(gs_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary_calls():
+    names = declared_functions()
+    for required in ("gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = N.lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_abi_version_and_error_strings():
+    lib = N.lib()
+    assert lib.gs_abi_version() == 1
+    nbytes = C.c_size_t(0)
+    assert lib.gs_bin_sort_workspace(-1, 10, 4, C.byref(nbytes)) == N.GS_ERR_INVALID
+    assert b"bad sizes" in lib.gs_last_error()
+    assert lib.gs_bin_sort_workspace(1000, 4000, 64, C.byref(nbytes)) == N.GS_OK
+    assert nbytes.value >= 4000 * 12
+
+
+def test_host_validation_rejects_bad_descriptors_without_a_device():
+    lib = N.lib()
+    cam = N.gs_camera()
+    cam.width, cam.height, cam.fx, cam.fy = 64, 64, 100.0, 100.0
+    g = N.gs_gaussians()
+    g.n, g.ld, g.sh_degree = 10, 5, 0          # ld < n
+    proj = N.gs_proj()
+    assert lib.gs_project(C.byref(g), C.byref(cam), None, C.byref(proj), None) == N.GS_ERR_INVALID
+    g.ld = 10
+    g.sh_degree = 7
+    assert lib.gs_project(C.byref(g), C.byref(cam), None, C.byref(proj), None) == N.GS_ERR_INVALID
+    g.sh_degree = 0
+    cam.width = 0
+    assert lib.gs_project(C.byref(g), C.byref(cam), None, C.byref(proj), None) == N.GS_ERR_INVALID
+    cam.width = 64
+    # NULL planes
+    assert lib.gs_project(C.byref(g), C.byref(cam), None, C.byref(proj), None) == N.GS_ERR_INVALID
+    opts = N.make_opts(24, 16)
+    g.n = 0
+    assert lib.gs_project(C.byref(g), C.byref(cam), C.byref(opts), C.byref(proj), None) == N.GS_ERR_UNSUPPORTED
+    bins = N.gs_bins()
+    bins.pair_capacity = 1 << 31
+    assert lib.gs_render_fwd(C.byref(proj), C.byref(bins), C.byref(cam), None, None, None, None,
+                             None) == N.GS_ERR_INVALID

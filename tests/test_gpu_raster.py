@@ -1,0 +1,288 @@
+"""GPU parity of the HIP rasterizer against the FP64 oracle.
+
+Every test calls the HIP kernels through the C ABI (libgsmi.so via the
+ctypes binding) and compares with the oracle on the same seeded inputs.
+Tolerances are those stated in gpu_util.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from gen import scenes
+from paper_2402_17427_amd import _native as N
+from paper_2402_17427_amd import raster
+
+from gpu_util import grad_close, image_close, unpack_rec
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    print(f"\n[case] {name}", flush=True)
+
+
+# ------------------------------------------------------------------ sort --
+
+@pytest.mark.parametrize("count,key_bits,seed", [(0, 40, 0), (1, 40, 1), (4095, 45, 2), (4096, 45, 3),
+                                                 (4097, 38, 4), (100_003, 45, 5), (250_000, 64, 6),
+                                                 (70_000, 8, 7), (33_333, 13, 8)])
+def test_sort_pairs_equals_stable_argsort(count, key_bits, seed):
+    _case(f"sort count={count} bits={key_bits}")
+    rng = np.random.default_rng(seed)
+    cap = max(count, 1) + 17
+    # few distinct keys so that stability is exercised
+    distinct = rng.integers(0, 2 ** 63, size=max(count // 7, 1), dtype=np.int64).view(np.uint64)
+    keys = distinct[rng.integers(0, distinct.size, size=cap)]
+    if key_bits < 64:
+        keys = keys & np.uint64((1 << key_bits) - 1)
+    vals = np.arange(cap, dtype=np.uint32)
+    kd = torch.as_tensor(keys.view(np.int64)).cuda()
+    vd = torch.as_tensor(vals.view(np.int32)).cuda()
+    raster.sort_pairs(kd, vd, key_bits, count=count)
+    torch.cuda.synchronize()
+    order = np.argsort(keys[:count], kind="stable")
+    got_k = kd.cpu().numpy().view(np.uint64)
+    got_v = vd.cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(got_k[:count], keys[:count][order])
+    np.testing.assert_array_equal(got_v[:count], vals[:count][order])
+
+
+# ------------------------------------------------------------ projection --
+
+def _scene(name):
+    if name == "config1":
+        g, cam, _ = scenes.config1()
+        return g, cam
+    if name == "city_ragged":
+        return scenes.small_city(n=20_000, seed=11, width=200, height=150)
+    if name == "city_white":
+        return scenes.small_city(n=8_000, seed=12, width=97, height=61, bg=(1.0, 1.0, 1.0))
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["config1", "city_ragged"])
+def test_projection_matches_oracle(name):
+    _case(f"projection {name}")
+    g, cam = _scene(name)
+    dg = raster.DeviceGaussians.from_host(g)
+    f = raster.Frame(g.n, g.sh_degree, cam)
+    f.project(dg)
+    torch.cuda.synchronize()
+    ref = oracle.project(g, cam)
+    b = oracle.bin(g, cam)
+    amb = b["amb"] != 0
+    tt = f.tiles_touched.cpu().numpy().view(np.uint32)[: g.n]
+    rect = f.rect.cpu().numpy().view(np.uint16).reshape(-1, 4)[: g.n].astype(np.int64)
+    depth = f.depth.cpu().numpy()[: g.n]
+    rec = unpack_rec(f.rec.cpu().numpy(), g.n)
+    ok = ~amb
+    np.testing.assert_array_equal(tt[ok], b["tiles_touched"][ok])
+    v = (ref["valid"] != 0) & ok
+    assert v.sum() > 0.5 * g.n * (0.1 if name == "config1" else 0.3)
+    np.testing.assert_array_equal(rect[v], b["trect"][v])
+    np.testing.assert_array_equal(depth[v].view(np.uint32), b["zbits"][v])
+    np.testing.assert_allclose(rec["uv"][v], ref["uv"][v], rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(rec["conic"][v], ref["conic"][v], rtol=2e-6,
+                               atol=2e-6 * np.abs(ref["conic"][v]).max())
+    np.testing.assert_allclose(rec["rgb"][v], ref["rgb"][v], rtol=0, atol=2e-6)
+    # support half-extents are rounded up (never below the exact value)
+    assert (rec["ext"][v] >= ref["ext"][v] * (1 - 1e-7)).all()
+
+
+@pytest.mark.parametrize("name,tile", [("config1", (16, 16)), ("city_ragged", (16, 16)), ("city_ragged", (8, 8)),
+                                       ("city_ragged", (32, 8))])
+def test_bins_match_oracle_bit_exact(name, tile):
+    _case(f"bins {name} tile={tile}")
+    g, cam = _scene(name)
+    dg = raster.DeviceGaussians.from_host(g)
+    f = raster.Frame(g.n, g.sh_degree, cam, tile=tile)
+    P = f.ensure_capacity(dg)
+    b = oracle.bin(g, cam, *tile)
+    assert not b["amb"].any(), "scene has Gaussians on a rounding boundary; pick another seed"
+    assert P == b["keys"].size
+    keys = f.keys.cpu().numpy().view(np.uint64)[:P]
+    vals = f.vals.cpu().numpy().view(np.uint32)[:P]
+    ranges = f.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    np.testing.assert_array_equal(keys, b["keys"])
+    np.testing.assert_array_equal(vals, b["vals"])
+    np.testing.assert_array_equal(ranges, b["ranges"])
+
+
+# --------------------------------------------------------------- forward --
+
+@pytest.mark.parametrize("name", ["config1", "city_ragged", "city_white"])
+def test_forward_image_matches_oracle(name):
+    _case(f"forward {name}")
+    g, cam = _scene(name)
+    dg = raster.DeviceGaussians.from_host(g)
+    f = raster.render(dg, cam)
+    torch.cuda.synchronize()
+    ref = oracle.render(g, cam)
+    img = f.image.cpu().numpy()
+    fT = f.final_T.cpu().numpy()
+    worst, nflag = image_close(name, img, ref["image"], ref["flags"])
+    ok = ref["flags"] == 0
+    assert np.abs(fT - ref["final_T"])[ok].max() <= 1e-4
+    # n_contrib points at the oracle's last blended Gaussian
+    nc = f.n_contrib.cpu().numpy().astype(np.int64)
+    vals = f.vals.cpu().numpy().view(np.uint32)
+    ranges = f.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    ys, xs = np.nonzero(ok)
+    tiles = (ys // 16) * f.ntx + xs // 16
+    last = np.where(nc[ys, xs] > 0, vals[np.minimum(ranges[tiles, 0] + nc[ys, xs] - 1, vals.size - 1)], -1)
+    np.testing.assert_array_equal(last, ref["last_id"][ys, xs])
+    print(f"max err {worst:.2e}, flagged {nflag}")
+
+
+def test_tile_size_invariance_of_the_image():
+    _case("tile invariance")
+    g, cam = _scene("city_ragged")
+    dg = raster.DeviceGaussians.from_host(g)
+    ref = oracle.render(g, cam)
+    ok = ref["flags"] == 0
+    base = None
+    for tile in [(16, 16), (8, 8), (16, 8), (32, 8), (32, 16), (32, 32)]:
+        f = raster.render(dg, cam, tile=tile)
+        img = f.image.cpu().numpy()
+        if base is None:
+            base = img
+        else:
+            np.testing.assert_array_equal(img[:, ok], base[:, ok], err_msg=f"tile {tile}")
+
+
+def test_forward_is_repeatable_bitwise():
+    _case("repeatable")
+    g, cam = _scene("city_ragged")
+    dg = raster.DeviceGaussians.from_host(g)
+    a = raster.render(dg, cam).image.cpu().numpy()
+    b = raster.render(dg, cam).image.cpu().numpy()
+    np.testing.assert_array_equal(a, b)
+
+
+def test_forward_compositing_invariants_on_gpu():
+    _case("invariants")
+    g, cam = _scene("city_white")
+    dg = raster.DeviceGaussians.from_host(g)
+    f = raster.render(dg, cam)
+    fT = f.final_T.cpu().numpy()
+    img = f.image.cpu().numpy()
+    assert (fT >= 1e-4).all() and (fT <= 1.0).all()
+    # pixel is a convex combination of colours (>= 0) and the white background
+    assert (img >= fT[None] * 1.0 - 1e-6).all()
+
+
+# -------------------------------------------------------------- backward --
+
+def _backward_case(g, cam, dimg_seed=5):
+    dg = raster.DeviceGaussians.from_host(g)
+    f = raster.render(dg, cam)
+    dimg = scenes.grad_image(cam, dimg_seed, "normal")
+    gr = raster.render_backward(f, dg, torch.as_tensor(dimg).cuda())
+    torch.cuda.synchronize()
+    rb = oracle.backward(g, cam, dimg)
+    keep = rb["touch"] == 0
+    out = {k: v.cpu().numpy() for k, v in gr.items()}
+    return out, rb, keep
+
+
+@pytest.mark.parametrize("name", ["config1", "city_ragged"])
+def test_backward_matches_oracle_gradient(name):
+    _case(f"backward {name}")
+    g, cam = _scene(name)
+    out, rb, keep = _backward_case(g, cam)
+    assert keep.mean() > 0.9
+    g2 = out["grad2d"]
+    names = ["du", "dv", "dA", "dB", "dC", "dopacity", "dr", "dg", "db"]
+    for c in range(9):
+        grad_close(names[c], g2[c][keep], rb["g2d"][keep, c])
+    for k in ("mean", "scale", "quat", "opacity", "sh"):
+        grad_close(k, out[k][..., keep], rb[k][..., keep])
+
+
+def test_capacity_overflow_sets_status_and_poisons_outputs():
+    _case("capacity overflow")
+    g, cam = _scene("config1")
+    dg = raster.DeviceGaussians.from_host(g)
+    f = raster.Frame(g.n, g.sh_degree, cam, capacity=64)
+    f.forward(dg)
+    torch.cuda.synchronize()
+    assert int(f.status.item()) == N.GS_ERR_CAPACITY
+    assert f.pairs()[0] == 0 and f.pairs()[1] > 64
+    assert np.isnan(f.image.cpu().numpy()).all()
+    f.render_bwd(dg, torch.ones((3, cam.height, cam.width), device="cuda"))
+    torch.cuda.synchronize()
+    assert (f.g_mean.cpu().numpy() == 0).all()
+    with pytest.raises(N.GsError):
+        f.check_status()
+    # growing the capacity recovers
+    P = f.ensure_capacity(dg)
+    assert P == f.pairs()[1] and int(f.status.item()) == 0
+
+
+def test_empty_and_fully_culled_scenes_render_background():
+    _case("empty")
+    _, cam = _scene("config1")
+    for n in (0, 5):
+        g = scenes.Gaussians(np.zeros((3, n), np.float32), np.ones((3, n), np.float32) * 0.1,
+                             np.tile(np.array([[1], [0], [0], [0]], np.float32), (1, n)),
+                             np.full(n, 0.9, np.float32), np.zeros((3, n), np.float32), 0)
+        g.mean[2] = -5.0          # behind the camera
+        dg = raster.DeviceGaussians.from_host(g)
+        f = raster.render(dg, cam)
+        img = f.image.cpu().numpy()
+        assert f.pairs()[0] == 0
+        np.testing.assert_array_equal(img, np.ones_like(img))
+        gr = raster.render_backward(f, dg, torch.ones((3, cam.height, cam.width), device="cuda"))
+        assert all((v.cpu().numpy() == 0).all() for v in gr.values())
+
+
+def test_invalid_arguments_are_rejected_before_launch():
+    _case("invalid args")
+    g, cam = _scene("config1")
+    dg = raster.DeviceGaussians.from_host(g)
+    f = raster.Frame(g.n, g.sh_degree, cam)
+    bad = N.make_opts(12, 12)
+    import ctypes as C
+    rc = N.lib().gs_project(C.byref(dg.c_struct()), C.byref(f.c_cam), C.byref(bad), C.byref(f.c_proj()), None)
+    assert rc == N.GS_ERR_UNSUPPORTED
+    s = dg.c_struct()
+    s.sh_degree = 4
+    rc = N.lib().gs_project(C.byref(s), C.byref(f.c_cam), C.byref(f.c_opts), C.byref(f.c_proj()), None)
+    assert rc == N.GS_ERR_INVALID
+    b = f.c_bins()
+    rc = N.lib().gs_bin_sort(C.byref(f.c_proj()), g.n, C.byref(f.c_cam), C.byref(f.c_opts), C.byref(b),
+                             C.c_void_p(f.ws.data_ptr()), 16, None)
+    assert rc == N.GS_ERR_INVALID and b"workspace" in N.lib().gs_last_error()
+
+
+# ----------------------------------------------------- full-size, sampled --
+
+def test_full_size_cell_sampled_pixels_match_oracle():
+    """1M Gaussians at 1920x1080 (one partition cell): the oracle evaluates a
+    stratified sample of pixels one by one; forward and the gradient of the
+    sampled pixels are compared there."""
+    _case("full size 1M 1080p sampled")
+    g, cam = scenes.config2()
+    dg = raster.DeviceGaussians.from_host(g)
+    f = raster.render(dg, cam)
+    px, py = scenes.pixel_sample(cam.width, cam.height, stride=120)
+    ref = oracle.render(g, cam, px, py)
+    img = f.image.cpu().numpy()[:, py, px]
+    ok = ref["flags"] == 0
+    assert ok.mean() > 0.9
+    assert np.abs(img.T - ref["image"])[ok].max() <= 1e-4
+    # gradient of L = sum over the sampled pixels of w . I
+    rng = np.random.default_rng(9)
+    dimg = np.zeros((3, cam.height, cam.width), np.float32)
+    dimg[:, py, px] = rng.standard_normal((3, px.size)).astype(np.float32)
+    gr = raster.render_backward(f, dg, torch.as_tensor(dimg).cuda())
+    rb = oracle.backward(g, cam, dimg, px, py)
+    keep = rb["touch"] == 0
+    live = keep & (np.abs(rb["g2d"]).sum(1) > 0)
+    assert live.sum() > 50
+    for k in ("mean", "opacity", "sh"):
+        grad_close(k, gr[k].cpu().numpy()[..., live], rb[k][..., live])
