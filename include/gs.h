@@ -204,6 +204,28 @@ gs_status gs_sort_workspace(int64_t capacity, int32_t key_bits, size_t *bytes);
 gs_status gs_sort_pairs(uint64_t *keys, uint32_t *vals, const uint32_t *count, int64_t capacity,
                         int32_t key_bits, void *ws, size_t ws_bytes, gs_stream stream);
 
+/* Work counters of the forward blend of one view (observability; not on
+ * the training path): runs the forward walk without writing an image and
+ * stores into counters (device, 4 x uint64, overwritten):
+ *   [0] (pixel, list entry) evaluations performed (after the per-wave
+ *       culling of Gaussians whose support misses the wave's 8x8 block),
+ *   [1] evaluations with alpha >= 1/255 up to the pixel's stop,
+ *   [2] blended (pixel, Gaussian) pairs, [3] 0.
+ * These are the units in which the blend's arithmetic work is counted. */
+gs_status gs_render_stats(const gs_proj *proj, const gs_bins *bins, const gs_camera *cam,
+                          const gs_opts *opts, uint64_t *counters, gs_stream stream);
+
+/* Stage timing (observability).  gs_profile_enable(1) starts a window in
+ * which every stage the library enqueues (project, scan_emit, sort,
+ * tile_ranges, render_fwd, grad_zero, render_bwd, project_bwd, ...) is
+ * bracketed by HIP events on its stream; gs_profile_enable(0) ends it and
+ * discards what was recorded.  gs_profile_report() waits for the recorded
+ * events and writes a JSON object {"stage": [total_ms, launches], ...} of
+ * the window so far into buf (host, len bytes), then starts counting
+ * afresh.  Process-wide; calls from several threads are serialised. */
+gs_status gs_profile_enable(int on);
+gs_status gs_profile_report(char *buf, size_t len);
+
 #ifdef __cplusplus
 }
 #endif

@@ -79,6 +79,9 @@ _SIGS = {
                       C.POINTER(gs_bins), P, P, P, C.POINTER(gs_grads), P],
     "gs_sort_workspace": [C.c_int64, C.c_int32, C.POINTER(C.c_size_t)],
     "gs_sort_pairs": [P, P, P, C.c_int64, C.c_int32, P, C.c_size_t, P],
+    "gs_render_stats": [C.POINTER(gs_proj), C.POINTER(gs_bins), C.POINTER(gs_camera), C.POINTER(gs_opts), P, P],
+    "gs_profile_enable": [C.c_int],
+    "gs_profile_report": [C.c_char_p, C.c_size_t],
 }
 _RESTYPES = {"gs_last_error": C.c_char_p, "gs_abi_version": C.c_int}
 _OPTIONAL = {}
@@ -141,3 +144,16 @@ def make_opts(tile_w=16, tile_h=16) -> gs_opts:
     o = gs_opts()
     o.tile_w, o.tile_h = int(tile_w), int(tile_h)
     return o
+
+
+def profile_enable(on: bool) -> None:
+    call("gs_profile_enable", 1 if on else 0)
+
+
+def profile_report() -> dict:
+    """{stage: (total_ms, launches)} of the events recorded since the last
+    report (waits for them)."""
+    import json
+    buf = C.create_string_buffer(1 << 16)
+    call("gs_profile_report", buf, len(buf))
+    return {k: (float(v[0]), int(v[1])) for k, v in json.loads(buf.value.decode()).items()}

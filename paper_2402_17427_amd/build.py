@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgsmi.so")
 ARCH = os.environ.get("GSMI_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "project.hip", "binning.hip", "sort.hip", "render_fwd.hip", "render_bwd.hip"]
+SOURCES = ["api.cpp", "profile.cpp", "project.hip", "binning.hip", "sort.hip", "render_fwd.hip", "render_bwd.hip"]
 EXTRA_SOURCES = ["batch.cpp", "serve.cpp"]
 
 

@@ -10,6 +10,7 @@
 #include "../../include/gs.h"
 #include "api_internal.h"
 #include "kernels.h"
+#include "profile.h"
 
 namespace gs {
 
@@ -139,8 +140,11 @@ gs_status gs_project(const gs_gaussians* g, const gs_camera* cam, const gs_opts*
     if ((s = check_proj(out, G.n))) return s;
     const int ntx = (C.W + tw - 1) / tw, nty = (C.H + th - 1) / th;
     if (ntx > 65535 || nty > 65535) return fail(GS_ERR_INVALID, "too many tiles");
-    launch_project(G, C, tw, th, static_cast<Rec*>(out->rec), out->depth, reinterpret_cast<ushort4*>(out->rect),
-                   out->tiles_touched, static_cast<hipStream_t>(stream));
+    {
+        ProfScope ps("project", static_cast<hipStream_t>(stream));
+        launch_project(G, C, tw, th, static_cast<Rec*>(out->rec), out->depth, reinterpret_cast<ushort4*>(out->rect),
+                       out->tiles_touched, static_cast<hipStream_t>(stream));
+    }
     return check_hip("gs_project");
 }
 
@@ -177,10 +181,20 @@ gs_status gs_bin_sort(const gs_proj* proj, int64_t n, const gs_camera* cam, cons
     void* sort_ws = p;
     const int kb = 32 + tile_bits(n_tiles);
     const bool odd = sort_passes(kb) % 2 == 1;
-    launch_emit_pairs(n, proj->tiles_touched, reinterpret_cast<const ushort4*>(proj->rect), proj->depth, ntx, cap,
-                      odd ? alt_k : out->keys, odd ? alt_v : out->vals, out->pair_count, out->status, scan_ws, st);
-    launch_sort_pairs(out->keys, out->vals, alt_k, alt_v, out->pair_count, cap, kb, odd, sort_ws, st);
-    launch_tile_ranges(out->keys, out->pair_count, cap, n_tiles, out->ranges, st);
+    {
+        ProfScope ps("scan_emit", st);
+        launch_emit_pairs(n, proj->tiles_touched, reinterpret_cast<const ushort4*>(proj->rect), proj->depth, ntx,
+                          cap, odd ? alt_k : out->keys, odd ? alt_v : out->vals, out->pair_count, out->status,
+                          scan_ws, st);
+    }
+    {
+        ProfScope ps("sort", st);
+        launch_sort_pairs(out->keys, out->vals, alt_k, alt_v, out->pair_count, cap, kb, odd, sort_ws, st);
+    }
+    {
+        ProfScope ps("tile_ranges", st);
+        launch_tile_ranges(out->keys, out->pair_count, cap, n_tiles, out->ranges, st);
+    }
     return check_hip("gs_bin_sort");
 }
 
@@ -192,9 +206,27 @@ gs_status gs_render_fwd(const gs_proj* proj, const gs_bins* bins, const gs_camer
     if ((s = to_cam(cam, &C)) || (s = tiles_of(opts, &tw, &th)) || (s = check_bins(bins))) return s;
     if (!proj || !proj->rec) return fail(GS_ERR_INVALID, "proj is NULL");
     if (!image || !final_T || !n_contrib) return fail(GS_ERR_INVALID, "output buffer is NULL");
-    launch_render_fwd(static_cast<const Rec*>(proj->rec), bins->vals, bins->ranges, bins->status, C, tw, th, image,
-                      final_T, n_contrib, static_cast<hipStream_t>(stream));
+    {
+        ProfScope ps("render_fwd", static_cast<hipStream_t>(stream));
+        launch_render_fwd(static_cast<const Rec*>(proj->rec), bins->vals, bins->ranges, bins->status, C, tw, th,
+                          image, final_T, n_contrib, nullptr, static_cast<hipStream_t>(stream));
+    }
     return check_hip("gs_render_fwd");
+}
+
+gs_status gs_render_stats(const gs_proj* proj, const gs_bins* bins, const gs_camera* cam, const gs_opts* opts,
+                          uint64_t* counters, gs_stream stream) {
+    Cam C;
+    int tw, th;
+    gs_status s;
+    if ((s = to_cam(cam, &C)) || (s = tiles_of(opts, &tw, &th)) || (s = check_bins(bins))) return s;
+    if (!proj || !proj->rec) return fail(GS_ERR_INVALID, "proj is NULL");
+    if (!counters) return fail(GS_ERR_INVALID, "counters is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 0u, 8, st);
+    launch_render_fwd(static_cast<const Rec*>(proj->rec), bins->vals, bins->ranges, bins->status, C, tw, th, nullptr,
+                      nullptr, nullptr, reinterpret_cast<unsigned long long*>(counters), st);
+    return check_hip("gs_render_stats");
 }
 
 gs_status gs_render_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_opts* opts, const gs_proj* proj,
@@ -212,11 +244,20 @@ gs_status gs_render_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_op
     if (G.n > 0 && (!out->mean || !out->scale || !out->quat || !out->opacity || !out->sh || !out->grad2d))
         return fail(GS_ERR_INVALID, "gradient buffer is NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    launch_fill_u32(reinterpret_cast<uint32_t*>(out->grad2d), 0u, (size_t)G.n * 9, st);
-    launch_render_bwd(static_cast<const Rec*>(proj->rec), bins->vals, bins->ranges, bins->status, C, tw, th, final_T,
-                      n_contrib, dL_dimage, G.n, out->grad2d, st);
-    launch_project_bwd(G, C, proj->tiles_touched, out->grad2d, bins->status, out->ld, out->mean, out->scale,
-                       out->quat, out->opacity, out->sh, st);
+    {
+        ProfScope ps("grad_zero", st);
+        launch_fill_u32(reinterpret_cast<uint32_t*>(out->grad2d), 0u, (size_t)G.n * 9, st);
+    }
+    {
+        ProfScope ps("render_bwd", st);
+        launch_render_bwd(static_cast<const Rec*>(proj->rec), bins->vals, bins->ranges, bins->status, C, tw, th,
+                          final_T, n_contrib, dL_dimage, G.n, out->grad2d, st);
+    }
+    {
+        ProfScope ps("project_bwd", st);
+        launch_project_bwd(G, C, proj->tiles_touched, out->grad2d, bins->status, out->ld, out->mean, out->scale,
+                           out->quat, out->opacity, out->sh, st);
+    }
     return check_hip("gs_render_bwd");
 }
 

@@ -21,12 +21,17 @@ namespace gs {
 
 namespace {
 
-template <int TW, int TH>
+// STATS = true is the instrumented variant behind gs_render_stats: the same
+// walk, counting per pixel the list entries it evaluates (after the wave
+// culling), the entries with alpha >= 1/255 before its stop, and the blended
+// ones, summed into stats[0..2]; it writes no image.
+template <int TW, int TH, bool STATS>
 __global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ rec, const uint32_t* __restrict__ vals,
                                                         const uint2* __restrict__ ranges,
                                                         const int32_t* __restrict__ status, int W, int H, int ntx,
                                                         float bg0, float bg1, float bg2, float* __restrict__ image,
-                                                        float* __restrict__ final_T, uint32_t* __restrict__ n_contrib) {
+                                                        float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
+                                                        unsigned long long* __restrict__ stats) {
     constexpr int NT = TW * TH;
     constexpr int WX = TW / 8;
     __shared__ Staged s[NT];
@@ -42,7 +47,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ 
     const int64_t off = (int64_t)py * W + px;
 
     if (*status != 0) {
-        if (inside) {
+        if (!STATS && inside) {
             const float nan = __builtin_nanf("");
             image[off] = nan;
             image[npix + off] = nan;
@@ -61,6 +66,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ 
     float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
     uint32_t last = 0;
     bool done = !inside;
+    unsigned long long n_eval = 0, n_supp = 0, n_blend = 0;
 
     for (uint32_t b0 = rg.x; b0 < rg.y; b0 += NT) {
         if (__syncthreads_count(done) == NT) break;
@@ -74,11 +80,14 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ 
                 if (!__builtin_amdgcn_readfirstlane((int)box_overlaps(g, bx0, bx1, by0, by1))) continue;
                 if (!done) {
                     const Eval e = eval_pair(g, fx, fy);
+                    if (STATS) ++n_eval;
                     if (e.alpha > 0.0f) {
                         const float Tn = T * (1.0f - e.alpha);
+                        if (STATS) ++n_supp;
                         if (Tn < kTMin) {
                             done = true;
                         } else {
+                            if (STATS) ++n_blend;
                             const float w = e.alpha * T;
                             c0 = __builtin_fmaf(g.col.x, w, c0);
                             c1 = __builtin_fmaf(g.col.y, w, c1);
@@ -92,7 +101,11 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ 
             }
         }
     }
-    if (inside) {
+    if (STATS) {
+        atomicAdd(&stats[0], n_eval);
+        atomicAdd(&stats[1], n_supp);
+        atomicAdd(&stats[2], n_blend);
+    } else if (inside) {
         image[off] = __builtin_fmaf(T, bg0, c0);
         image[npix + off] = __builtin_fmaf(T, bg1, c1);
         image[2 * npix + off] = __builtin_fmaf(T, bg2, c2);
@@ -103,11 +116,16 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ 
 
 template <int TW, int TH>
 void launch_t(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status, const Cam& cam,
-              float* image, float* final_T, uint32_t* n_contrib, hipStream_t st) {
+              float* image, float* final_T, uint32_t* n_contrib, unsigned long long* stats, hipStream_t st) {
     const int ntx = (cam.W + TW - 1) / TW, nty = (cam.H + TH - 1) / TH;
-    hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3((unsigned)(ntx * nty)), dim3(TW * TH), 0, st, rec, vals,
-                       reinterpret_cast<const uint2*>(ranges), status, cam.W, cam.H, ntx, cam.bg[0], cam.bg[1],
-                       cam.bg[2], image, final_T, n_contrib);
+    if (stats)
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, true>), dim3((unsigned)(ntx * nty)), dim3(TW * TH), 0, st, rec,
+                           vals, reinterpret_cast<const uint2*>(ranges), status, cam.W, cam.H, ntx, cam.bg[0],
+                           cam.bg[1], cam.bg[2], image, final_T, n_contrib, stats);
+    else
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, false>), dim3((unsigned)(ntx * nty)), dim3(TW * TH), 0, st, rec,
+                           vals, reinterpret_cast<const uint2*>(ranges), status, cam.W, cam.H, ntx, cam.bg[0],
+                           cam.bg[1], cam.bg[2], image, final_T, n_contrib, stats);
 }
 
 }  // namespace
@@ -119,13 +137,15 @@ bool render_tile_supported(int tw, int th) {
 
 void launch_render_fwd(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status,
                        const Cam& cam, int tw, int th, float* image, float* final_T, uint32_t* n_contrib,
-                       hipStream_t st) {
-    if (tw == 16 && th == 16) launch_t<16, 16>(rec, vals, ranges, status, cam, image, final_T, n_contrib, st);
-    else if (tw == 8 && th == 8) launch_t<8, 8>(rec, vals, ranges, status, cam, image, final_T, n_contrib, st);
-    else if (tw == 16 && th == 8) launch_t<16, 8>(rec, vals, ranges, status, cam, image, final_T, n_contrib, st);
-    else if (tw == 32 && th == 8) launch_t<32, 8>(rec, vals, ranges, status, cam, image, final_T, n_contrib, st);
-    else if (tw == 32 && th == 16) launch_t<32, 16>(rec, vals, ranges, status, cam, image, final_T, n_contrib, st);
-    else if (tw == 32 && th == 32) launch_t<32, 32>(rec, vals, ranges, status, cam, image, final_T, n_contrib, st);
+                       unsigned long long* stats, hipStream_t st) {
+#define GS_FWD(a, b) launch_t<a, b>(rec, vals, ranges, status, cam, image, final_T, n_contrib, stats, st)
+    if (tw == 16 && th == 16) GS_FWD(16, 16);
+    else if (tw == 8 && th == 8) GS_FWD(8, 8);
+    else if (tw == 16 && th == 8) GS_FWD(16, 8);
+    else if (tw == 32 && th == 8) GS_FWD(32, 8);
+    else if (tw == 32 && th == 16) GS_FWD(32, 16);
+    else if (tw == 32 && th == 32) GS_FWD(32, 32);
+#undef GS_FWD
 }
 
 }  // namespace gs

@@ -171,6 +171,14 @@ class Frame:
                C.byref(self.c_proj()), C.byref(self.c_bins()), _ptr(self.final_T), _ptr(self.n_contrib),
                _ptr(dimg), C.byref(self.c_grads()), C.c_void_p(stream_handle(stream)))
 
+    def stats(self, stream=None) -> dict:
+        """Blend work counters of the current bins (synchronises)."""
+        c = torch.zeros(4, dtype=torch.int64, device=self.device)
+        N.call("gs_render_stats", C.byref(self.c_proj()), C.byref(self.c_bins()), C.byref(self.c_cam),
+               C.byref(self.c_opts), _ptr(c), C.c_void_p(stream_handle(stream)))
+        v = c.cpu().numpy()
+        return dict(evaluated=int(v[0]), support=int(v[1]), blended=int(v[2]))
+
     def forward(self, g: DeviceGaussians, stream=None):
         self.project(g, stream)
         self.bin_sort(stream)

@@ -129,8 +129,8 @@ def test_forward_image_matches_oracle(name):
     assert np.abs(fT - ref["final_T"])[ok].max() <= 1e-4
     # n_contrib points at the oracle's last blended Gaussian
     nc = f.n_contrib.cpu().numpy().astype(np.int64)
-    vals = f.vals.cpu().numpy().view(np.uint32)
-    ranges = f.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    vals = f.vals.cpu().numpy().view(np.uint32).astype(np.int64)
+    ranges = f.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2).astype(np.int64)
     ys, xs = np.nonzero(ok)
     tiles = (ys // 16) * f.ntx + xs // 16
     last = np.where(nc[ys, xs] > 0, vals[np.minimum(ranges[tiles, 0] + nc[ys, xs] - 1, vals.size - 1)], -1)
@@ -178,15 +178,21 @@ def test_forward_compositing_invariants_on_gpu():
 # -------------------------------------------------------------- backward --
 
 def _backward_case(g, cam, dimg_seed=5):
+    """Gradient of L = sum w . I with seeded w ~ N(0, 1), except w = 0 at the
+    pixels the oracle flags as ambiguous (there FP32 and FP64 may take a
+    different discontinuous decision; with w = 0 the pixel contributes
+    nothing to either gradient)."""
     dg = raster.DeviceGaussians.from_host(g)
     f = raster.render(dg, cam)
+    flags = oracle.render(g, cam)["flags"]
     dimg = scenes.grad_image(cam, dimg_seed, "normal")
+    dimg[:, flags != 0] = 0.0
     gr = raster.render_backward(f, dg, torch.as_tensor(dimg).cuda())
     torch.cuda.synchronize()
     rb = oracle.backward(g, cam, dimg)
-    keep = rb["touch"] == 0
+    assert not rb["flags"].any()
     out = {k: v.cpu().numpy() for k, v in gr.items()}
-    return out, rb, keep
+    return out, rb, np.ones(g.n, bool)
 
 
 @pytest.mark.parametrize("name", ["config1", "city_ragged"])
@@ -194,7 +200,6 @@ def test_backward_matches_oracle_gradient(name):
     _case(f"backward {name}")
     g, cam = _scene(name)
     out, rb, keep = _backward_case(g, cam)
-    assert keep.mean() > 0.9
     g2 = out["grad2d"]
     names = ["du", "dv", "dA", "dB", "dC", "dopacity", "dr", "dg", "db"]
     for c in range(9):
@@ -278,11 +283,10 @@ def test_full_size_cell_sampled_pixels_match_oracle():
     # gradient of L = sum over the sampled pixels of w . I
     rng = np.random.default_rng(9)
     dimg = np.zeros((3, cam.height, cam.width), np.float32)
-    dimg[:, py, px] = rng.standard_normal((3, px.size)).astype(np.float32)
+    dimg[:, py[ok], px[ok]] = rng.standard_normal((3, int(ok.sum()))).astype(np.float32)
     gr = raster.render_backward(f, dg, torch.as_tensor(dimg).cuda())
-    rb = oracle.backward(g, cam, dimg, px, py)
-    keep = rb["touch"] == 0
-    live = keep & (np.abs(rb["g2d"]).sum(1) > 0)
+    rb = oracle.backward(g, cam, dimg, px[ok], py[ok])
+    live = np.abs(rb["g2d"]).sum(1) > 0
     assert live.sum() > 50
     for k in ("mean", "opacity", "sh"):
         grad_close(k, gr[k].cpu().numpy()[..., live], rb[k][..., live])
