@@ -38,6 +38,10 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-ffp-contract=off", "-munsafe-fp-atomics",
+           # atomics are issued from one lane where it matters; the
+           # compiler's lane-loop rewrite of uniform-address atomics only
+           # adds instructions there
+           "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
            "-I", os.path.join(HERE, "..", "include"), "-o", tmp] + sources() + ["-lpthread"]

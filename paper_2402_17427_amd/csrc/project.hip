@@ -169,6 +169,7 @@ __device__ __forceinline__ bool geometry(const Cam& cam, const double mu[3], con
     return true;
 }
 
+template <int K>
 __global__ __launch_bounds__(kProjThreads) void k_project(Gauss G, Cam cam, int tw, int th,
                                                           Rec* __restrict__ rec, float* __restrict__ depth,
                                                           ushort4* __restrict__ rect, uint32_t* __restrict__ tt) {
@@ -190,8 +191,8 @@ __global__ __launch_bounds__(kProjThreads) void k_project(Gauss G, Cam cam, int 
     }
     const float o = G.opacity[i];
     fin = fin && isfinite(o);
-    float coef[48];
-    const int K = G.K;
+    float coef[3 * K];
+#pragma unroll
     for (int j = 0; j < 3 * K; ++j) {
         coef[j] = G.sh[(int64_t)j * ld + i];
         fin = fin && isfinite(coef[j]);
@@ -229,6 +230,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project(Gauss G, Cam cam, int 
             float col[3];
             for (int ch = 0; ch < 3; ++ch) {
                 float acc = 0.f;
+#pragma unroll
                 for (int j = 0; j < K; ++j) acc += coef[ch * K + j] * Y[j];
                 col[ch] = fmaxf(acc + 0.5f, 0.0f);
             }
@@ -263,6 +265,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project(Gauss G, Cam cam, int 
 
 // Backward of the projection for one Gaussian.  g2d planes: du, dv, dA, dB,
 // dC, d opacity, dr, dg, db (accumulated by the blend backward).
+template <int K>
 __global__ __launch_bounds__(kProjThreads) void k_project_bwd(Gauss G, Cam cam, const uint32_t* __restrict__ tt,
                                                               const float* __restrict__ g2d,
                                                               const int32_t* __restrict__ status, int64_t gld,
@@ -272,7 +275,6 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(Gauss G, Cam cam, 
     const int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
     if (i >= G.n) return;
     const int64_t ld = G.ld, n = G.n;
-    const int K = G.K;
     const bool live = tt[i] != 0 && *status == 0;
     if (!live) {
         for (int r = 0; r < 3; ++r) { gmean[r * gld + i] = 0.f; gscale[r * gld + i] = 0.f; }
@@ -302,15 +304,18 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(Gauss G, Cam cam, 
     float Y[16];
     sh_basis(dx, dy, dz, Y);
     float wsum[16];
+#pragma unroll
     for (int j = 0; j < 16; ++j) wsum[j] = 0.f;
     for (int ch = 0; ch < 3; ++ch) {
         float raw = 0.5f;
-        float kc[16];
+        float kc[K];
+#pragma unroll
         for (int j = 0; j < K; ++j) {
             kc[j] = G.sh[(int64_t)(ch * K + j) * ld + i];
             raw += kc[j] * Y[j];
         }
         const float gch = raw > 0.0f ? drgb[ch] : 0.0f;
+#pragma unroll
         for (int j = 0; j < K; ++j) {
             gsh[(int64_t)(ch * K + j) * gld + i] = gch * Y[j];
             wsum[j] += gch * kc[j];
@@ -402,7 +407,14 @@ void launch_project(const Gauss& g, const Cam& cam, int tw, int th, Rec* rec, fl
                     uint32_t* tt, hipStream_t st) {
     if (g.n == 0) return;
     const unsigned blocks = (unsigned)((g.n + kProjThreads - 1) / kProjThreads);
-    hipLaunchKernelGGL(k_project, dim3(blocks), dim3(kProjThreads), 0, st, g, cam, tw, th, rec, depth, rect, tt);
+#define GS_PROJ(k) hipLaunchKernelGGL(k_project<k>, dim3(blocks), dim3(kProjThreads), 0, st, g, cam, tw, th, rec, depth, rect, tt)
+    switch (g.K) {
+        case 1: GS_PROJ(1); break;
+        case 4: GS_PROJ(4); break;
+        case 9: GS_PROJ(9); break;
+        default: GS_PROJ(16); break;
+    }
+#undef GS_PROJ
 }
 
 void launch_project_bwd(const Gauss& g, const Cam& cam, const uint32_t* tt, const float* g2d, const int32_t* status,
@@ -410,8 +422,15 @@ void launch_project_bwd(const Gauss& g, const Cam& cam, const uint32_t* tt, cons
                         hipStream_t st) {
     if (g.n == 0) return;
     const unsigned blocks = (unsigned)((g.n + kProjThreads - 1) / kProjThreads);
-    hipLaunchKernelGGL(k_project_bwd, dim3(blocks), dim3(kProjThreads), 0, st, g, cam, tt, g2d, status, gld, gmean,
-                       gscale, gquat, gopac, gsh);
+#define GS_PROJ_BWD(k) hipLaunchKernelGGL(k_project_bwd<k>, dim3(blocks), dim3(kProjThreads), 0, st, g, cam, tt, g2d, status, gld, gmean, \
+                       gscale, gquat, gopac, gsh)
+    switch (g.K) {
+        case 1: GS_PROJ_BWD(1); break;
+        case 4: GS_PROJ_BWD(4); break;
+        case 9: GS_PROJ_BWD(9); break;
+        default: GS_PROJ_BWD(16); break;
+    }
+#undef GS_PROJ_BWD
 }
 
 }  // namespace gs

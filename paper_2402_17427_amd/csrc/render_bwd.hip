@@ -17,11 +17,14 @@
 // skip decisions), recovers T_i = T_{i+1} / (1 - alpha_i) from the stored
 // final transmittance, and accumulates S_i as it goes.
 //
-// Reduction: per staged Gaussian, a wave first checks (ballot) whether any
-// of its 64 pixels contributed; only then are the nine gradient terms
-// summed across the wave with DPP row reductions, added into a per-tile LDS
-// accumulator by one lane, and flushed with one global FP32 atomic per
-// (Gaussian, term, tile) after the batch.
+// Walk: as in the forward, each wave covers an 8x8 block and walks only the
+// staged entries whose support box meets its block (ballot mask, scanned
+// from the back) and that lie before its pixels' last contributor.
+// Reduction: per walked entry, a wave first checks (ballot) whether any of
+// its 64 pixels contributed; only then are the nine gradient terms summed
+// over the wave with DPP (row sums, then the row broadcasts), added by one
+// lane into a per-tile LDS accumulator, and flushed with one global FP32
+// atomic per (Gaussian, term, tile) after the batch.
 #include "kernels.h"
 
 namespace gs {
@@ -71,8 +74,9 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(const Rec* __restrict__ 
         g1 = dimg[npix + off];
         g2 = dimg[2 * npix + off];
     }
-    const float tb0 = T * bg0, tb1 = T * bg1, tb2 = T * bg2;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f;   // sum of rgb_j w_j over j behind the current entry
+    // g . (T_final bg): the background's share of every suffix colour
+    const float gbg = g0 * (T * bg0) + g1 * (T * bg1) + g2 * (T * bg2);
+    float ga = 0.f;   // g . sum of rgb_j w_j over the blended j behind the current entry
 
     if (tid == 0) s_max = 0u;
     __syncthreads();
@@ -80,6 +84,10 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(const Rec* __restrict__ 
     __syncthreads();
     // never walk past the tile's list, whatever n_contrib holds
     const uint32_t max_last = min(s_max, rg.y - rg.x);
+
+    // the wave never needs entries at or beyond its pixels' last contributor
+    uint32_t wave_last = my_last;
+    for (int d = 1; d < kWave; d <<= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, d, kWave));
 
     for (int64_t hi = (int64_t)max_last; hi > 0; hi -= B) {
         const int64_t lo = hi - B > 0 ? hi - B : 0;
@@ -93,58 +101,67 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(const Rec* __restrict__ 
         for (int q = tid; q < B * 9; q += NT) s_acc[q] = 0.f;
         __syncthreads();
 
-        for (int k = nb - 1; k >= 0; --k) {
-            const Staged g = s[k];
-            if (!__builtin_amdgcn_readfirstlane((int)box_overlaps(g, bx0, bx1, by0, by1))) continue;
-            const uint32_t pos = (uint32_t)(lo + k);
-            float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f, v7 = 0.f, v8 = 0.f;
-            bool contrib = false;
-            if (pos < my_last) {
-                const Eval e = eval_pair(g, fx, fy);
-                if (e.alpha > 0.0f) {
-                    contrib = true;
-                    const float om = 1.0f - e.alpha;
-                    const float Ti = T / om;
-                    const float w = e.alpha * Ti;
-                    const float r = g.col.x, gg = g.col.y, b = g.col.z;
-                    v6 = g0 * w;
-                    v7 = g1 * w;
-                    v8 = g2 * w;
-                    const float iom = 1.0f / om;
-                    const float da = g0 * (r * Ti - (a0 + tb0) * iom) + g1 * (gg * Ti - (a1 + tb1) * iom) +
-                                     g2 * (b * Ti - (a2 + tb2) * iom);
-                    a0 = __builtin_fmaf(r, w, a0);
-                    a1 = __builtin_fmaf(gg, w, a1);
-                    a2 = __builtin_fmaf(b, w, a2);
-                    T = Ti;
-                    if (!e.capped) {
-                        v5 = da * e.G;
-                        const float dpow = da * e.alpha;
-                        v2 = -0.5f * e.dx * e.dx * dpow;
-                        v3 = -e.dx * e.dy * dpow;
-                        v4 = -0.5f * e.dy * e.dy * dpow;
-                        // A = -2 ca / log2e, B = -cb / log2e, C = -2 cc / log2e
-                        const float q = -dpow * (1.0f / kLog2e);
-                        v0 = (2.0f * g.coef.x * e.dx + g.coef.y * e.dy) * q;
-                        v1 = (g.coef.y * e.dx + 2.0f * g.coef.z * e.dy) * q;
+        // 64 staged entries at a time, back to front: each lane tests one
+        // against the wave's block; the ballot lists the ones to walk.
+        for (int c0k = ((nb - 1) / kWave) * kWave; c0k >= 0; c0k -= kWave) {
+            const int k = c0k + lane;
+            const bool ov = k < nb && (uint32_t)(lo + k) < wave_last && box_overlaps(s[k], bx0, bx1, by0, by1);
+            uint64_t mask = __ballot(ov);
+            while (mask) {
+                const int bit = 63 - __builtin_clzll(mask);
+                mask &= ~(1ull << bit);
+                const int kk = c0k + bit;
+                const Staged g = s[kk];
+                const uint32_t pos = (uint32_t)(lo + kk);
+                float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f, v7 = 0.f, v8 = 0.f;
+                bool contrib = false;
+                if (pos < my_last) {
+                    const Eval e = eval_pair(g, fx, fy);
+                    if (e.alpha > 0.0f) {
+                        contrib = true;
+                        const float iom = __builtin_amdgcn_rcpf(1.0f - e.alpha);
+                        const float Ti = T * iom;
+                        const float w = e.alpha * Ti;
+                        const float grgb = g0 * g.col.x + g1 * g.col.y + g2 * g.col.z;
+                        v6 = g0 * w;
+                        v7 = g1 * w;
+                        v8 = g2 * w;
+                        // dL/dalpha = g . (rgb T_i - S_i / (1 - alpha)), S_i = suffix colour + T_final bg
+                        const float da = grgb * Ti - (ga + gbg) * iom;
+                        ga = __builtin_fmaf(grgb, w, ga);
+                        T = Ti;
+                        if (!e.capped) {
+                            v5 = da * e.G;
+                            const float dpow = da * e.alpha;
+                            const float hx = -0.5f * dpow * e.dx, hy = -0.5f * dpow * e.dy;
+                            v2 = hx * e.dx;
+                            v3 = 2.0f * hx * e.dy;
+                            v4 = hy * e.dy;
+                            // A = -2 ca / log2e, B = -cb / log2e, C = -2 cc / log2e
+                            const float q = -dpow * (1.0f / kLog2e);
+                            v0 = (2.0f * g.coef.x * e.dx + g.coef.y * e.dy) * q;
+                            v1 = (g.coef.y * e.dx + 2.0f * g.coef.z * e.dy) * q;
+                        }
                     }
                 }
-            }
-            if (__ballot(contrib) == 0ull) continue;
-            const float r0 = wave_sum(v0), r1 = wave_sum(v1), r2 = wave_sum(v2), r3 = wave_sum(v3),
-                        r4 = wave_sum(v4), r5 = wave_sum(v5), r6 = wave_sum(v6), r7 = wave_sum(v7),
-                        r8 = wave_sum(v8);
-            if (lane == 0) {
-                float* acc = &s_acc[k * 9];
-                atomicAdd(acc + 0, r0);
-                atomicAdd(acc + 1, r1);
-                atomicAdd(acc + 2, r2);
-                atomicAdd(acc + 3, r3);
-                atomicAdd(acc + 4, r4);
-                atomicAdd(acc + 5, r5);
-                atomicAdd(acc + 6, r6);
-                atomicAdd(acc + 7, r7);
-                atomicAdd(acc + 8, r8);
+                if (__ballot(contrib) == 0ull) continue;
+                // sum over the wave (complete in lane 63), one LDS atomic per
+                // term into the tile's accumulator
+                v0 = wave_sum_to_lane63(v0); v1 = wave_sum_to_lane63(v1); v2 = wave_sum_to_lane63(v2);
+                v3 = wave_sum_to_lane63(v3); v4 = wave_sum_to_lane63(v4); v5 = wave_sum_to_lane63(v5);
+                v6 = wave_sum_to_lane63(v6); v7 = wave_sum_to_lane63(v7); v8 = wave_sum_to_lane63(v8);
+                if (lane == kWave - 1) {
+                    float* acc = &s_acc[kk * 9];
+                    atomicAdd(acc + 0, v0);
+                    atomicAdd(acc + 1, v1);
+                    atomicAdd(acc + 2, v2);
+                    atomicAdd(acc + 3, v3);
+                    atomicAdd(acc + 4, v4);
+                    atomicAdd(acc + 5, v5);
+                    atomicAdd(acc + 6, v6);
+                    atomicAdd(acc + 7, v7);
+                    atomicAdd(acc + 8, v8);
+                }
             }
         }
         __syncthreads();

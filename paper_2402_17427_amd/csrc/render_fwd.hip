@@ -9,12 +9,14 @@
 // Output pixel = C + T bg.
 //
 // Launch: one workgroup per tile, one lane per pixel.  Every wave covers an
-// 8x8 block of the tile, so that a small Gaussian touches few waves; a wave
-// skips (uniformly) every Gaussian whose support box misses its block,
-// which never changes a result because such a Gaussian has alpha < 1/255 at
-// all of the block's pixels.  Batches of records are staged in LDS and
-// read as broadcasts; a wave leaves the batch once all its pixels have
-// stopped, and the workgroup leaves the tile once all of its waves have.
+// 8x8 block of the tile, so that a small Gaussian touches few waves.
+// Batches of records are staged in LDS; for each 64 of them the wave tests
+// one per lane against its block's pixel centres and walks, in list order,
+// only those whose support box meets the block (a ballot mask scanned with
+// scalar bit operations).  Skipping the others never changes a result: such
+// a Gaussian has alpha < 1/255 at every pixel of the block.  A wave leaves
+// the tile once all its pixels have stopped, the workgroup once all waves
+// have.
 #include "kernels.h"
 
 namespace gs {
@@ -74,10 +76,17 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ 
         if (j < rg.y) s[tid] = stage_rec(rec[vals[j]]);
         __syncthreads();
         const int nb = (int)min((uint32_t)NT, rg.y - b0);
-        if (__ballot(!done) != 0ull) {
-            for (int k = 0; k < nb; ++k) {
-                const Staged g = s[k];
-                if (!__builtin_amdgcn_readfirstlane((int)box_overlaps(g, bx0, bx1, by0, by1))) continue;
+        bool live = __ballot(!done) != 0ull;
+        // 64 staged Gaussians at a time: each lane tests one against the
+        // wave's block, the ballot lists the ones to walk, in order.
+        for (int c0k = 0; live && c0k < nb; c0k += kWave) {
+            const int k = c0k + lane;
+            const bool ov = k < nb && box_overlaps(s[k], bx0, bx1, by0, by1);
+            uint64_t mask = __ballot(ov);
+            while (mask) {
+                const int kk = c0k + __builtin_ctzll(mask);
+                mask &= mask - 1;
+                const Staged g = s[kk];
                 if (!done) {
                     const Eval e = eval_pair(g, fx, fy);
                     if (STATS) ++n_eval;
@@ -93,11 +102,14 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ 
                             c1 = __builtin_fmaf(g.col.y, w, c1);
                             c2 = __builtin_fmaf(g.col.z, w, c2);
                             T = Tn;
-                            last = b0 - rg.x + (uint32_t)k + 1u;
+                            last = b0 - rg.x + (uint32_t)kk + 1u;
                         }
                     }
                 }
-                if (__ballot(!done) == 0ull) break;
+                if (__ballot(!done) == 0ull) {
+                    live = false;
+                    break;
+                }
             }
         }
     }
