@@ -195,6 +195,25 @@ gs_status gs_render_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_op
                         const uint32_t *n_contrib, const float *dL_dimage, gs_grads *out,
                         gs_stream stream);
 
+/* Stored-state variant of the blend (for comparison with the recomputing
+ * backward above; same results within the gradient tolerance).
+ * gs_render_state_bytes: bytes of the state buffer for these bins and
+ * tiles = pair_capacity * tile_w * tile_h * 8 (host query).
+ * gs_render_fwd_stored: gs_render_fwd that also writes, for every (list
+ * entry, pixel) it evaluates, the entry's alpha (negated when capped at
+ * 0.99, 0 when skipped) and the transmittance in front of it into `state`
+ * (device, state_bytes, caller-owned).
+ * gs_render_bwd_stored: gs_render_bwd reading alpha and T from `state`
+ * instead of recomputing them; arguments otherwise as gs_render_bwd. */
+gs_status gs_render_state_bytes(const gs_bins *bins, const gs_opts *opts, size_t *bytes);
+gs_status gs_render_fwd_stored(const gs_proj *proj, const gs_bins *bins, const gs_camera *cam,
+                               const gs_opts *opts, float *image, float *final_T,
+                               uint32_t *n_contrib, void *state, size_t state_bytes, gs_stream stream);
+gs_status gs_render_bwd_stored(const gs_gaussians *g, const gs_camera *cam, const gs_opts *opts,
+                               const gs_proj *proj, const gs_bins *bins, const float *final_T,
+                               const uint32_t *n_contrib, const void *state, size_t state_bytes,
+                               const float *dL_dimage, gs_grads *out, gs_stream stream);
+
 /* Stable LSD radix sort of (uint64 key, uint32 value) pairs on the low
  * `key_bits` bits (<= 64), the sort gs_bin_sort runs, exposed for testing
  * on arbitrary keys.  count: device pointer to the number of pairs

@@ -209,9 +209,40 @@ gs_status gs_render_fwd(const gs_proj* proj, const gs_bins* bins, const gs_camer
     {
         ProfScope ps("render_fwd", static_cast<hipStream_t>(stream));
         launch_render_fwd(static_cast<const Rec*>(proj->rec), bins->vals, bins->ranges, bins->status, C, tw, th,
-                          image, final_T, n_contrib, nullptr, static_cast<hipStream_t>(stream));
+                          image, final_T, n_contrib, nullptr, nullptr, static_cast<hipStream_t>(stream));
     }
     return check_hip("gs_render_fwd");
+}
+
+gs_status gs_render_state_bytes(const gs_bins* bins, const gs_opts* opts, size_t* bytes) {
+    int tw, th;
+    gs_status s;
+    if ((s = tiles_of(opts, &tw, &th)) || (s = check_bins(bins))) return s;
+    if (!bytes) return fail(GS_ERR_INVALID, "bytes is NULL");
+    *bytes = (size_t)bins->pair_capacity * (size_t)(tw * th) * sizeof(float) * 2;
+    return GS_OK;
+}
+
+gs_status gs_render_fwd_stored(const gs_proj* proj, const gs_bins* bins, const gs_camera* cam, const gs_opts* opts,
+                               float* image, float* final_T, uint32_t* n_contrib, void* state,
+                               size_t state_bytes, gs_stream stream) {
+    Cam C;
+    int tw, th;
+    gs_status s;
+    size_t need = 0;
+    if ((s = to_cam(cam, &C)) || (s = tiles_of(opts, &tw, &th)) || (s = check_bins(bins)) ||
+        (s = gs_render_state_bytes(bins, opts, &need)))
+        return s;
+    if (!proj || !proj->rec) return fail(GS_ERR_INVALID, "proj is NULL");
+    if (!image || !final_T || !n_contrib) return fail(GS_ERR_INVALID, "output buffer is NULL");
+    if (!state || state_bytes < need) return fail(GS_ERR_INVALID, "state buffer too small: %zu < %zu", state_bytes, need);
+    {
+        ProfScope ps("render_fwd_stored", static_cast<hipStream_t>(stream));
+        launch_render_fwd(static_cast<const Rec*>(proj->rec), bins->vals, bins->ranges, bins->status, C, tw, th,
+                          image, final_T, n_contrib, nullptr, static_cast<float2*>(state),
+                          static_cast<hipStream_t>(stream));
+    }
+    return check_hip("gs_render_fwd_stored");
 }
 
 gs_status gs_render_stats(const gs_proj* proj, const gs_bins* bins, const gs_camera* cam, const gs_opts* opts,
@@ -225,13 +256,16 @@ gs_status gs_render_stats(const gs_proj* proj, const gs_bins* bins, const gs_cam
     hipStream_t st = static_cast<hipStream_t>(stream);
     launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 0u, 8, st);
     launch_render_fwd(static_cast<const Rec*>(proj->rec), bins->vals, bins->ranges, bins->status, C, tw, th, nullptr,
-                      nullptr, nullptr, reinterpret_cast<unsigned long long*>(counters), st);
+                      nullptr, nullptr, reinterpret_cast<unsigned long long*>(counters), nullptr, st);
     return check_hip("gs_render_stats");
 }
 
-gs_status gs_render_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_opts* opts, const gs_proj* proj,
-                        const gs_bins* bins, const float* final_T, const uint32_t* n_contrib,
-                        const float* dL_dimage, gs_grads* out, gs_stream stream) {
+namespace {
+
+gs_status render_bwd_impl(const gs_gaussians* g, const gs_camera* cam, const gs_opts* opts, const gs_proj* proj,
+                          const gs_bins* bins, const float* final_T, const uint32_t* n_contrib,
+                          const float* dL_dimage, gs_grads* out, const void* state, size_t state_bytes,
+                          gs_stream stream) {
     Gauss G;
     Cam C;
     int tw, th;
@@ -243,15 +277,20 @@ gs_status gs_render_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_op
     if (out->ld < G.n) return fail(GS_ERR_INVALID, "gradient ld < n");
     if (G.n > 0 && (!out->mean || !out->scale || !out->quat || !out->opacity || !out->sh || !out->grad2d))
         return fail(GS_ERR_INVALID, "gradient buffer is NULL");
+    if (state) {
+        size_t need = 0;
+        if ((s = gs_render_state_bytes(bins, opts, &need))) return s;
+        if (state_bytes < need) return fail(GS_ERR_INVALID, "state buffer too small: %zu < %zu", state_bytes, need);
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     {
         ProfScope ps("grad_zero", st);
         launch_fill_u32(reinterpret_cast<uint32_t*>(out->grad2d), 0u, (size_t)G.n * 9, st);
     }
     {
-        ProfScope ps("render_bwd", st);
+        ProfScope ps(state ? "render_bwd_stored" : "render_bwd", st);
         launch_render_bwd(static_cast<const Rec*>(proj->rec), bins->vals, bins->ranges, bins->status, C, tw, th,
-                          final_T, n_contrib, dL_dimage, G.n, out->grad2d, st);
+                          final_T, n_contrib, dL_dimage, G.n, out->grad2d, static_cast<const float2*>(state), st);
     }
     {
         ProfScope ps("project_bwd", st);
@@ -259,6 +298,23 @@ gs_status gs_render_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_op
                            out->quat, out->opacity, out->sh, st);
     }
     return check_hip("gs_render_bwd");
+}
+
+}  // namespace
+
+gs_status gs_render_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_opts* opts, const gs_proj* proj,
+                        const gs_bins* bins, const float* final_T, const uint32_t* n_contrib,
+                        const float* dL_dimage, gs_grads* out, gs_stream stream) {
+    return render_bwd_impl(g, cam, opts, proj, bins, final_T, n_contrib, dL_dimage, out, nullptr, 0, stream);
+}
+
+gs_status gs_render_bwd_stored(const gs_gaussians* g, const gs_camera* cam, const gs_opts* opts,
+                               const gs_proj* proj, const gs_bins* bins, const float* final_T,
+                               const uint32_t* n_contrib, const void* state, size_t state_bytes,
+                               const float* dL_dimage, gs_grads* out, gs_stream stream) {
+    if (!state) return fail(GS_ERR_INVALID, "state is NULL");
+    return render_bwd_impl(g, cam, opts, proj, bins, final_T, n_contrib, dL_dimage, out, state, state_bytes,
+                           stream);
 }
 
 gs_status gs_sort_workspace(int64_t capacity, int32_t key_bits, size_t* bytes) {

@@ -46,12 +46,14 @@ void launch_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint3
 
 // ---- blend (render_fwd.hip / render_bwd.hip)
 bool render_tile_supported(int tw, int th);
-// stats != NULL runs the counting variant instead (no image written).
+// stats != NULL runs the counting variant instead (no image written);
+// state != NULL also stores the per-entry blend state (P * tile pixels).
 void launch_render_fwd(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status,
                        const Cam& cam, int tw, int th, float* image, float* final_T, uint32_t* n_contrib,
-                       unsigned long long* stats, hipStream_t st);
+                       unsigned long long* stats, float2* state, hipStream_t st);
+// state != NULL reads the stored blend state instead of recomputing it.
 void launch_render_bwd(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status,
                        const Cam& cam, int tw, int th, const float* final_T, const uint32_t* n_contrib,
-                       const float* dimg, int64_t n, float* g2d, hipStream_t st);
+                       const float* dimg, int64_t n, float* g2d, const float2* state, hipStream_t st);
 
 }  // namespace gs

@@ -31,7 +31,9 @@ namespace gs {
 
 namespace {
 
-template <int TW, int TH>
+// STORED = true reads each entry's (alpha, T) from the state the storing
+// forward wrote (alpha negated when capped) instead of recomputing them.
+template <int TW, int TH, bool STORED>
 __global__ __launch_bounds__(TW * TH) void k_render_bwd(const Rec* __restrict__ rec, const uint32_t* __restrict__ vals,
                                                         const uint2* __restrict__ ranges,
                                                         const int32_t* __restrict__ status, int W, int H, int ntx,
@@ -39,7 +41,8 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(const Rec* __restrict__ 
                                                         const float* __restrict__ final_T,
                                                         const uint32_t* __restrict__ n_contrib,
                                                         const float* __restrict__ dimg, int64_t n,
-                                                        float* __restrict__ g2d) {
+                                                        float* __restrict__ g2d,
+                                                        const float2* __restrict__ state) {
     constexpr int NT = TW * TH;
     constexpr int B = NT < 256 ? NT : 256;   // staged Gaussians per batch
     constexpr int WX = TW / 8;
@@ -116,11 +119,23 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(const Rec* __restrict__ 
                 float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f, v7 = 0.f, v8 = 0.f;
                 bool contrib = false;
                 if (pos < my_last) {
-                    const Eval e = eval_pair(g, fx, fy);
+                    Eval e;
+                    float Ti = 0.f;
+                    if (STORED) {
+                        const float2 st = state[(int64_t)(rg.x + pos) * NT + tid];
+                        e.alpha = fabsf(st.x);
+                        e.capped = st.x < 0.0f;
+                        e.dx = (fx - g.geo.x) - g.geo.y;
+                        e.dy = (fy - g.geo.z) - g.geo.w;
+                        e.G = e.alpha * __builtin_amdgcn_rcpf(g.coef.w);
+                        Ti = st.y;
+                    } else {
+                        e = eval_pair(g, fx, fy);
+                    }
                     if (e.alpha > 0.0f) {
                         contrib = true;
                         const float iom = __builtin_amdgcn_rcpf(1.0f - e.alpha);
-                        const float Ti = T * iom;
+                        if (!STORED) Ti = T * iom;
                         const float w = e.alpha * Ti;
                         const float grgb = g0 * g.col.x + g1 * g.col.y + g2 * g.col.z;
                         v6 = g0 * w;
@@ -178,19 +193,24 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(const Rec* __restrict__ 
 template <int TW, int TH>
 void launch_t(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status, const Cam& cam,
               const float* final_T, const uint32_t* n_contrib, const float* dimg, int64_t n, float* g2d,
-              hipStream_t st) {
+              const float2* state, hipStream_t st) {
     const int ntx = (cam.W + TW - 1) / TW, nty = (cam.H + TH - 1) / TH;
-    hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3((unsigned)(ntx * nty)), dim3(TW * TH), 0, st, rec, vals,
-                       reinterpret_cast<const uint2*>(ranges), status, cam.W, cam.H, ntx, cam.bg[0], cam.bg[1],
-                       cam.bg[2], final_T, n_contrib, dimg, n, g2d);
+    const dim3 grid((unsigned)(ntx * nty)), block(TW * TH);
+    const uint2* rg = reinterpret_cast<const uint2*>(ranges);
+    if (state)
+        hipLaunchKernelGGL((k_render_bwd<TW, TH, true>), grid, block, 0, st, rec, vals, rg, status, cam.W, cam.H,
+                           ntx, cam.bg[0], cam.bg[1], cam.bg[2], final_T, n_contrib, dimg, n, g2d, state);
+    else
+        hipLaunchKernelGGL((k_render_bwd<TW, TH, false>), grid, block, 0, st, rec, vals, rg, status, cam.W, cam.H,
+                           ntx, cam.bg[0], cam.bg[1], cam.bg[2], final_T, n_contrib, dimg, n, g2d, state);
 }
 
 }  // namespace
 
 void launch_render_bwd(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status,
                        const Cam& cam, int tw, int th, const float* final_T, const uint32_t* n_contrib,
-                       const float* dimg, int64_t n, float* g2d, hipStream_t st) {
-#define GS_BWD(a, b) launch_t<a, b>(rec, vals, ranges, status, cam, final_T, n_contrib, dimg, n, g2d, st)
+                       const float* dimg, int64_t n, float* g2d, const float2* state, hipStream_t st) {
+#define GS_BWD(a, b) launch_t<a, b>(rec, vals, ranges, status, cam, final_T, n_contrib, dimg, n, g2d, state, st)
     if (tw == 16 && th == 16) GS_BWD(16, 16);
     else if (tw == 8 && th == 8) GS_BWD(8, 8);
     else if (tw == 16 && th == 8) GS_BWD(16, 8);

@@ -23,18 +23,26 @@ namespace gs {
 
 namespace {
 
-// STATS = true is the instrumented variant behind gs_render_stats: the same
-// walk, counting per pixel the list entries it evaluates (after the wave
-// culling), the entries with alpha >= 1/255 before its stop, and the blended
-// ones, summed into stats[0..2]; it writes no image.
-template <int TW, int TH, bool STATS>
+// MODE kPlain is the forward.  kStats is the instrumented variant behind
+// gs_render_stats: the same walk, counting per pixel the list entries it
+// evaluates (after the wave culling), the entries with alpha >= 1/255
+// before its stop, and the blended ones, summed into stats[0..2]; it
+// writes no image.  kStore is the forward that also keeps the blend state:
+// for every entry a pixel evaluates, state[(list position) * NT + lane in
+// tile] = (alpha, T before it), alpha negated when capped at 0.99 and 0 when
+// skipped; the stored-state backward reads it instead of recomputing.
+constexpr int kPlain = 0, kStats = 1, kStore = 2;
+
+template <int TW, int TH, int MODE>
 __global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ rec, const uint32_t* __restrict__ vals,
                                                         const uint2* __restrict__ ranges,
                                                         const int32_t* __restrict__ status, int W, int H, int ntx,
                                                         float bg0, float bg1, float bg2, float* __restrict__ image,
                                                         float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
-                                                        unsigned long long* __restrict__ stats) {
+                                                        unsigned long long* __restrict__ stats,
+                                                        float2* __restrict__ state) {
     constexpr int NT = TW * TH;
+    constexpr bool STATS = MODE == kStats;
     constexpr int WX = TW / 8;
     __shared__ Staged s[NT];
 
@@ -89,6 +97,9 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ 
                 const Staged g = s[kk];
                 if (!done) {
                     const Eval e = eval_pair(g, fx, fy);
+                    if (MODE == kStore)
+                        state[(int64_t)(b0 + (uint32_t)kk) * NT + tid] =
+                            make_float2(e.capped && e.alpha > 0.0f ? -e.alpha : e.alpha, T);
                     if (STATS) ++n_eval;
                     if (e.alpha > 0.0f) {
                         const float Tn = T * (1.0f - e.alpha);
@@ -128,16 +139,20 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ 
 
 template <int TW, int TH>
 void launch_t(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status, const Cam& cam,
-              float* image, float* final_T, uint32_t* n_contrib, unsigned long long* stats, hipStream_t st) {
+              float* image, float* final_T, uint32_t* n_contrib, unsigned long long* stats, float2* state,
+              hipStream_t st) {
     const int ntx = (cam.W + TW - 1) / TW, nty = (cam.H + TH - 1) / TH;
+    const dim3 grid((unsigned)(ntx * nty)), block(TW * TH);
+    const uint2* rg = reinterpret_cast<const uint2*>(ranges);
     if (stats)
-        hipLaunchKernelGGL((k_render_fwd<TW, TH, true>), dim3((unsigned)(ntx * nty)), dim3(TW * TH), 0, st, rec,
-                           vals, reinterpret_cast<const uint2*>(ranges), status, cam.W, cam.H, ntx, cam.bg[0],
-                           cam.bg[1], cam.bg[2], image, final_T, n_contrib, stats);
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, kStats>), grid, block, 0, st, rec, vals, rg, status, cam.W, cam.H,
+                           ntx, cam.bg[0], cam.bg[1], cam.bg[2], image, final_T, n_contrib, stats, state);
+    else if (state)
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, kStore>), grid, block, 0, st, rec, vals, rg, status, cam.W, cam.H,
+                           ntx, cam.bg[0], cam.bg[1], cam.bg[2], image, final_T, n_contrib, stats, state);
     else
-        hipLaunchKernelGGL((k_render_fwd<TW, TH, false>), dim3((unsigned)(ntx * nty)), dim3(TW * TH), 0, st, rec,
-                           vals, reinterpret_cast<const uint2*>(ranges), status, cam.W, cam.H, ntx, cam.bg[0],
-                           cam.bg[1], cam.bg[2], image, final_T, n_contrib, stats);
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, kPlain>), grid, block, 0, st, rec, vals, rg, status, cam.W, cam.H,
+                           ntx, cam.bg[0], cam.bg[1], cam.bg[2], image, final_T, n_contrib, stats, state);
 }
 
 }  // namespace
@@ -149,8 +164,8 @@ bool render_tile_supported(int tw, int th) {
 
 void launch_render_fwd(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status,
                        const Cam& cam, int tw, int th, float* image, float* final_T, uint32_t* n_contrib,
-                       unsigned long long* stats, hipStream_t st) {
-#define GS_FWD(a, b) launch_t<a, b>(rec, vals, ranges, status, cam, image, final_T, n_contrib, stats, st)
+                       unsigned long long* stats, float2* state, hipStream_t st) {
+#define GS_FWD(a, b) launch_t<a, b>(rec, vals, ranges, status, cam, image, final_T, n_contrib, stats, state, st)
     if (tw == 16 && th == 16) GS_FWD(16, 16);
     else if (tw == 8 && th == 8) GS_FWD(8, 8);
     else if (tw == 16 && th == 8) GS_FWD(16, 8);

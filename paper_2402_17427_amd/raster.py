@@ -179,6 +179,24 @@ class Frame:
         v = c.cpu().numpy()
         return dict(evaluated=int(v[0]), support=int(v[1]), blended=int(v[2]))
 
+    # -- stored blend state (for comparison with the recomputing backward) --
+    def state_bytes(self) -> int:
+        nbytes = C.c_size_t(0)
+        N.call("gs_render_state_bytes", C.byref(self.c_bins()), C.byref(self.c_opts), C.byref(nbytes))
+        return int(nbytes.value)
+
+    def render_fwd_stored(self, state: torch.Tensor, stream=None):
+        N.call("gs_render_fwd_stored", C.byref(self.c_proj()), C.byref(self.c_bins()), C.byref(self.c_cam),
+               C.byref(self.c_opts), _ptr(self.image), _ptr(self.final_T), _ptr(self.n_contrib), _ptr(state),
+               state.numel() * state.element_size(), C.c_void_p(stream_handle(stream)))
+
+    def render_bwd_stored(self, g: DeviceGaussians, dimg: torch.Tensor, state: torch.Tensor, stream=None):
+        assert dimg.shape == (3, self.H, self.W) and dimg.dtype == torch.float32 and dimg.is_contiguous()
+        N.call("gs_render_bwd_stored", C.byref(g.c_struct()), C.byref(self.c_cam), C.byref(self.c_opts),
+               C.byref(self.c_proj()), C.byref(self.c_bins()), _ptr(self.final_T), _ptr(self.n_contrib),
+               _ptr(state), state.numel() * state.element_size(), _ptr(dimg), C.byref(self.c_grads()),
+               C.c_void_p(stream_handle(stream)))
+
     def forward(self, g: DeviceGaussians, stream=None):
         self.project(g, stream)
         self.bin_sort(stream)
