@@ -223,6 +223,55 @@ gs_status gs_sort_workspace(int64_t capacity, int32_t key_bits, size_t *bytes);
 gs_status gs_sort_pairs(uint64_t *keys, uint32_t *vals, const uint32_t *count, int64_t capacity,
                         int32_t key_bits, void *ws, size_t ws_bytes, gs_stream stream);
 
+/* ---- Batched cells (training) --------------------------------------------
+ * Section 4.1: a scene is split into cells optimised independently.  A
+ * gs_batch runs one training step (render, L1 image loss, backward) of
+ * several cells of uneven Gaussian counts together: each stage is one
+ * launch over all cells, the blends are persistent grids pulling tiles
+ * longest list first, and the step is captured once as a hipGraph and
+ * replayed by gs_batch_step.  With `autotune` the tile shape and the launch
+ * form are chosen at creation by timing each candidate on the batch.
+ *
+ * gs_batch_create: cells[n_cells] (device SoA planes, one SH degree for all)
+ * and cams[n_cells] (host) define the cells and their training views;
+ * targets[n_cells] are device [3][H][W] target images; outputs: images
+ * (device, stacked: cell c's [3][H][W] image starts at the sum of 3 W H of
+ * the cells before it), grads[n_cells] (device planes per cell, overwritten
+ * each step) and loss (device, n_cells floats: mean |I - I*| of each cell).
+ * Every pointer must stay valid until gs_batch_destroy (the graph holds
+ * them).  The pair capacity is sized at creation from the cells' current
+ * parameters with the configured headroom; a later step that needs more
+ * sets the device status to GS_ERR_CAPACITY (images NaN, gradients zero),
+ * read by gs_batch_status.  Creation synchronises `stream`; it allocates
+ * the batch's workspace (freed by gs_batch_destroy).
+ * gs_batch_step: enqueue one step on `stream` (graph replay), no sync. */
+typedef struct gs_batch gs_batch;
+typedef struct {
+    int32_t tile_w, tile_h;     /* tile shape (0 = 16x16) */
+    int32_t persistent;         /* 1 = persistent blend grids with a longest-first tile queue */
+    int32_t use_graph;          /* 1 = capture the step as a hipGraph */
+    int32_t autotune;           /* 1 = time the candidate shapes/forms at creation, keep the fastest */
+    double capacity_headroom;   /* pair capacity = headroom x pairs needed at creation (<= 1: 1.25) */
+} gs_batch_config;              /* NULL = {16, 16, 1, 1, 0, 1.25} */
+typedef struct {
+    int32_t tile_w, tile_h, persistent, use_graph, grid_fwd, grid_bwd;
+    uint32_t n_tiles;
+    int64_t slots, pair_capacity;
+    int32_t n_candidates;       /* autotune: candidates timed, in order */
+    int32_t cand_tile_w[16], cand_tile_h[16], cand_persistent[16];
+    double cand_ms[16];         /* mean step time of each candidate */
+} gs_batch_stats;
+
+gs_status gs_batch_create(const gs_gaussians *cells, const gs_camera *cams, const float *const *targets,
+                          int32_t n_cells, float *images, gs_grads *grads, float *loss,
+                          const gs_batch_config *cfg, gs_stream stream, gs_batch **out);
+gs_status gs_batch_step(gs_batch *b, gs_stream stream);
+/* Chosen configuration and autotune timings (host). */
+gs_status gs_batch_info(const gs_batch *b, gs_batch_stats *info);
+/* Device status of the last step and its pairs [P, needed]; synchronises `stream`. */
+gs_status gs_batch_status(gs_batch *b, gs_stream stream, int32_t *status, uint32_t *pairs);
+void gs_batch_destroy(gs_batch *b);
+
 /* Work counters of the forward blend of one view (observability; not on
  * the training path): runs the forward walk without writing an image and
  * stores into counters (device, 4 x uint64, overwritten):

@@ -17,8 +17,9 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgsmi.so")
 ARCH = os.environ.get("GSMI_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "profile.cpp", "project.hip", "binning.hip", "sort.hip", "render_fwd.hip", "render_bwd.hip"]
-EXTRA_SOURCES = ["batch.cpp", "serve.cpp"]
+SOURCES = ["api.cpp", "profile.cpp", "project.hip", "binning.hip", "sort.hip", "render_fwd.hip", "render_bwd.hip",
+           "batch_kernels.hip", "batch.cpp"]
+EXTRA_SOURCES = ["serve.cpp"]
 
 
 def hipcc() -> str:

@@ -101,6 +101,55 @@ size_t bin_sort_ws_bytes(int64_t n, int64_t cap, int64_t n_tiles) {
            align256(sort_workspace_bytes(cap, kb));
 }
 
+ViewTab single_view(const Cam& C, int tw, int th) {
+    ViewTab t;
+    t.dev = nullptr;
+    t.n = 1;
+    std::memset(&t.one, 0, sizeof t.one);
+    t.one.cam = C;
+    t.one.ntx = (C.W + tw - 1) / tw;
+    t.one.nty = (C.H + th - 1) / th;
+    t.one.tile_base = 0;
+    t.one.img_base = 0;
+    t.one.pix_base = 0;
+    return t;
+}
+
+JobTab single_job(const Gauss& G, const gs_grads* out) {
+    JobTab t;
+    t.dev = nullptr;
+    t.n = 1;
+    std::memset(&t.one, 0, sizeof t.one);
+    t.one.g = G;
+    t.one.src0 = 0;
+    t.one.count = G.n;
+    t.one.out0 = 0;
+    t.one.view = 0;
+    if (out) {
+        t.one.gmean = out->mean;
+        t.one.gscale = out->scale;
+        t.one.gquat = out->quat;
+        t.one.gopac = out->opacity;
+        t.one.gsh = out->sh;
+        t.one.gld = out->ld;
+    }
+    return t;
+}
+
+RenderArgs single_render(const gs_proj* proj, const gs_bins* bins, const Cam& C, int tw, int th) {
+    RenderArgs r;
+    std::memset(&r, 0, sizeof r);
+    r.rec = static_cast<const Rec*>(proj->rec);
+    r.vals = bins->vals;
+    r.ranges = bins->ranges;
+    r.status = bins->status;
+    r.views = single_view(C, tw, th);
+    r.n_tiles = (uint32_t)(r.views.one.ntx * r.views.one.nty);
+    r.tw = tw;
+    r.th = th;
+    return r;
+}
+
 gs_status check_proj(const gs_proj* p, int64_t n) {
     if (!p) return fail(GS_ERR_INVALID, "proj is NULL");
     if (n > 0 && (!p->rec || !p->depth || !p->rect || !p->tiles_touched))
@@ -142,8 +191,9 @@ gs_status gs_project(const gs_gaussians* g, const gs_camera* cam, const gs_opts*
     if (ntx > 65535 || nty > 65535) return fail(GS_ERR_INVALID, "too many tiles");
     {
         ProfScope ps("project", static_cast<hipStream_t>(stream));
-        launch_project(G, C, tw, th, static_cast<Rec*>(out->rec), out->depth, reinterpret_cast<ushort4*>(out->rect),
-                       out->tiles_touched, static_cast<hipStream_t>(stream));
+        launch_project(single_job(G, nullptr), single_view(C, tw, th), G.K, G.n, tw, th, static_cast<Rec*>(out->rec),
+                       out->depth, reinterpret_cast<ushort4*>(out->rect), out->tiles_touched,
+                       static_cast<hipStream_t>(stream));
     }
     return check_hip("gs_project");
 }
@@ -183,9 +233,12 @@ gs_status gs_bin_sort(const gs_proj* proj, int64_t n, const gs_camera* cam, cons
     const bool odd = sort_passes(kb) % 2 == 1;
     {
         ProfScope ps("scan_emit", st);
-        launch_emit_pairs(n, proj->tiles_touched, reinterpret_cast<const ushort4*>(proj->rect), proj->depth, ntx,
-                          cap, odd ? alt_k : out->keys, odd ? alt_v : out->vals, out->pair_count, out->status,
-                          scan_ws, st);
+        Gauss G0;
+        std::memset(&G0, 0, sizeof G0);
+        G0.n = n;
+        launch_emit_pairs(n, proj->tiles_touched, reinterpret_cast<const ushort4*>(proj->rect), proj->depth,
+                          single_job(G0, nullptr), single_view(C, tw, th), cap, odd ? alt_k : out->keys,
+                          odd ? alt_v : out->vals, out->pair_count, out->status, scan_ws, st);
     }
     {
         ProfScope ps("sort", st);
@@ -208,8 +261,8 @@ gs_status gs_render_fwd(const gs_proj* proj, const gs_bins* bins, const gs_camer
     if (!image || !final_T || !n_contrib) return fail(GS_ERR_INVALID, "output buffer is NULL");
     {
         ProfScope ps("render_fwd", static_cast<hipStream_t>(stream));
-        launch_render_fwd(static_cast<const Rec*>(proj->rec), bins->vals, bins->ranges, bins->status, C, tw, th,
-                          image, final_T, n_contrib, nullptr, nullptr, static_cast<hipStream_t>(stream));
+        launch_render_fwd(single_render(proj, bins, C, tw, th), image, final_T, n_contrib, nullptr, nullptr,
+                          static_cast<hipStream_t>(stream));
     }
     return check_hip("gs_render_fwd");
 }
@@ -238,9 +291,8 @@ gs_status gs_render_fwd_stored(const gs_proj* proj, const gs_bins* bins, const g
     if (!state || state_bytes < need) return fail(GS_ERR_INVALID, "state buffer too small: %zu < %zu", state_bytes, need);
     {
         ProfScope ps("render_fwd_stored", static_cast<hipStream_t>(stream));
-        launch_render_fwd(static_cast<const Rec*>(proj->rec), bins->vals, bins->ranges, bins->status, C, tw, th,
-                          image, final_T, n_contrib, nullptr, static_cast<float2*>(state),
-                          static_cast<hipStream_t>(stream));
+        launch_render_fwd(single_render(proj, bins, C, tw, th), image, final_T, n_contrib, nullptr,
+                          static_cast<float2*>(state), static_cast<hipStream_t>(stream));
     }
     return check_hip("gs_render_fwd_stored");
 }
@@ -255,8 +307,8 @@ gs_status gs_render_stats(const gs_proj* proj, const gs_bins* bins, const gs_cam
     if (!counters) return fail(GS_ERR_INVALID, "counters is NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
     launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 0u, 8, st);
-    launch_render_fwd(static_cast<const Rec*>(proj->rec), bins->vals, bins->ranges, bins->status, C, tw, th, nullptr,
-                      nullptr, nullptr, reinterpret_cast<unsigned long long*>(counters), nullptr, st);
+    launch_render_fwd(single_render(proj, bins, C, tw, th), nullptr, nullptr, nullptr,
+                      reinterpret_cast<unsigned long long*>(counters), nullptr, st);
     return check_hip("gs_render_stats");
 }
 
@@ -289,13 +341,13 @@ gs_status render_bwd_impl(const gs_gaussians* g, const gs_camera* cam, const gs_
     }
     {
         ProfScope ps(state ? "render_bwd_stored" : "render_bwd", st);
-        launch_render_bwd(static_cast<const Rec*>(proj->rec), bins->vals, bins->ranges, bins->status, C, tw, th,
-                          final_T, n_contrib, dL_dimage, G.n, out->grad2d, static_cast<const float2*>(state), st);
+        launch_render_bwd(single_render(proj, bins, C, tw, th), final_T, n_contrib, dL_dimage, G.n, out->grad2d,
+                          static_cast<const float2*>(state), st);
     }
     {
         ProfScope ps("project_bwd", st);
-        launch_project_bwd(G, C, proj->tiles_touched, out->grad2d, bins->status, out->ld, out->mean, out->scale,
-                           out->quat, out->opacity, out->sh, st);
+        launch_project_bwd(single_job(G, out), single_view(C, tw, th), G.K, G.n, proj->tiles_touched, out->grad2d,
+                           bins->status, st);
     }
     return check_hip("gs_render_bwd");
 }

@@ -8,6 +8,7 @@
 
 #include "../../include/gs.h"
 #include "gs_device.h"
+#include "kernels.h"
 
 namespace gs {
 
@@ -25,5 +26,12 @@ gs_status tiles_of(const gs_opts* o, int* tw, int* th);
 int tile_bits(int64_t n_tiles);
 size_t align256(size_t x);
 size_t bin_sort_ws_bytes(int64_t n, int64_t cap, int64_t n_tiles);
+gs_status check_proj(const gs_proj* p, int64_t n);
+gs_status check_bins(const gs_bins* b);
+
+// One-entry view / job tables and blend arguments of the single-view calls.
+ViewTab single_view(const Cam& C, int tw, int th);
+JobTab single_job(const Gauss& G, const gs_grads* out);
+RenderArgs single_render(const gs_proj* proj, const gs_bins* bins, const Cam& C, int tw, int th);
 
 }  // namespace gs

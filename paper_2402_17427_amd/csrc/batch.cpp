@@ -1,0 +1,483 @@
+// Batched training step over several partition cells (gs_batch_*).
+//
+// VastGaussian (arXiv 2402.17427), section 4.1: the scene is split into
+// cells that are optimised independently.  Here several cells of uneven
+// Gaussian counts take one training step each together: every stage runs as
+// one launch over all cells (one projection over the concatenated Gaussian
+// slots, one joint sort whose keys carry each view's tile range, one blend
+// forward and one backward over all views' tiles, pulled from a
+// longest-list-first queue by a persistent grid), the whole step is captured
+// once as a hipGraph and replayed, and the tile shape and launch form are
+// chosen by timing the candidates on the batch itself.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gs.h"
+#include "api_internal.h"
+#include "kernels.h"
+
+namespace gs {
+
+namespace {
+
+struct Cand {
+    int tw, th, persistent;
+};
+
+const Cand kCands[] = {{16, 16, 1}, {16, 16, 0}, {32, 16, 1}, {32, 16, 0}, {16, 8, 1}, {32, 8, 1}};
+
+template <typename T>
+gs_status dmalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GS_ERR_OOM, "device allocation of %zu bytes failed", count * sizeof(T));
+    }
+    return GS_OK;
+}
+
+}  // namespace
+
+}  // namespace gs
+
+using namespace gs;
+
+struct gs_batch {
+    int n = 0;
+    int K = 1;
+    std::vector<Gauss> cells;
+    std::vector<Cam> cams;
+    std::vector<int64_t> out0;
+    int64_t nslots = 0;
+    int64_t img_floats = 0, pix_count = 0, max_pix = 0;
+    double headroom = 1.25;
+
+    // chosen configuration
+    int tw = 16, th = 16, persistent = 1, use_graph = 1;
+    int grid_fwd = 0, grid_bwd = 0;
+    uint32_t n_tiles = 0;
+    int64_t capacity = 0;
+    std::vector<double> tune_ms;   // per candidate (autotune), -1 when skipped
+
+    // tables
+    View* d_views = nullptr;
+    Job* d_jobs = nullptr;
+    const float** d_targets = nullptr;
+    std::vector<View> h_views;
+    std::vector<Job> h_jobs;
+
+    // per-slot buffers
+    Rec* rec = nullptr;
+    float* depth = nullptr;
+    ushort4* rect = nullptr;
+    uint32_t* tt = nullptr;
+    float* g2d = nullptr;
+    void* scan_ws = nullptr;
+    // pair buffers (capacity) and per-tile buffers (max over candidates)
+    uint64_t *keys = nullptr, *alt_k = nullptr;
+    uint32_t *vals = nullptr, *alt_v = nullptr;
+    void* sort_ws = nullptr;
+    size_t sort_ws_bytes = 0;
+    uint32_t* ranges = nullptr;
+    uint32_t* pair_count = nullptr;
+    int32_t* status = nullptr;
+    uint32_t* queue = nullptr;
+    uint32_t* tiles_dev = nullptr;   // device copy of n_tiles (count for the tile-order sort)
+    uint64_t *tkeys = nullptr, *tkeys_alt = nullptr;
+    uint32_t *tvals = nullptr, *tvals_alt = nullptr;
+    void* tsort_ws = nullptr;
+    uint32_t max_tiles = 0;
+    // per-pixel buffers
+    float* final_T = nullptr;
+    uint32_t* n_contrib = nullptr;
+    float* dimg = nullptr;
+    // caller outputs
+    float* images = nullptr;
+    float* loss = nullptr;
+
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    ~gs_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        void* ptrs[] = {d_views, d_jobs, d_targets, rec, depth, rect, tt, g2d, scan_ws, keys, alt_k, vals, alt_v,
+                        sort_ws, ranges, pair_count, status, queue, tiles_dev, tkeys, tkeys_alt, tvals, tvals_alt,
+                        tsort_ws, final_T, n_contrib, dimg};
+        for (void* p : ptrs)
+            if (p) (void)hipFree(p);
+    }
+
+    uint32_t tiles_for(int w, int h) const {
+        uint32_t t = 0;
+        for (const Cam& c : cams) t += (uint32_t)(((c.W + w - 1) / w) * ((c.H + h - 1) / h));
+        return t;
+    }
+
+    // View table for a tile shape (host copy + upload).
+    gs_status set_tiles(int w, int h, hipStream_t st) {
+        tw = w;
+        th = h;
+        uint32_t base = 0;
+        for (int c = 0; c < n; ++c) {
+            View& v = h_views[c];
+            v.ntx = (cams[c].W + w - 1) / w;
+            v.nty = (cams[c].H + h - 1) / h;
+            v.tile_base = base;
+            base += (uint32_t)(v.ntx * v.nty);
+        }
+        n_tiles = base;
+        if (hipMemcpyAsync(d_views, h_views.data(), sizeof(View) * n, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(tiles_dev, &n_tiles, sizeof(uint32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return check_hip("gs_batch: view table upload");
+        grid_fwd = render_persistent_grid(w, h, false);
+        grid_bwd = render_persistent_grid(w, h, true);
+        return GS_OK;
+    }
+
+    ViewTab vt() const {
+        ViewTab t;
+        std::memset(&t, 0, sizeof t);
+        t.dev = d_views;
+        t.n = n;
+        return t;
+    }
+    JobTab jt() const {
+        JobTab t;
+        std::memset(&t, 0, sizeof t);
+        t.dev = d_jobs;
+        t.n = n;
+        return t;
+    }
+
+    int key_bits() const { return 32 + tile_bits(n_tiles); }
+
+    void enqueue_project_bin(hipStream_t st) {
+        launch_project(jt(), vt(), K, nslots, tw, th, rec, depth, rect, tt, st);
+        const bool odd = sort_passes(key_bits()) % 2 == 1;
+        launch_emit_pairs(nslots, tt, rect, depth, jt(), vt(), capacity, odd ? alt_k : keys, odd ? alt_v : vals,
+                          pair_count, status, scan_ws, st);
+    }
+
+    // One training step of every cell: project, bin, sort, ranges, blend,
+    // L1 loss gradient, blend backward, projection backward.
+    void enqueue_step(hipStream_t st) {
+        enqueue_project_bin(st);
+        const int kb = key_bits();
+        launch_sort_pairs(keys, vals, alt_k, alt_v, pair_count, capacity, kb, sort_passes(kb) % 2 == 1, sort_ws, st);
+        launch_tile_ranges(keys, pair_count, capacity, n_tiles, ranges, st);
+        RenderArgs r;
+        std::memset(&r, 0, sizeof r);
+        r.rec = rec;
+        r.vals = vals;
+        r.ranges = ranges;
+        r.status = status;
+        r.views = vt();
+        r.n_tiles = n_tiles;
+        r.tw = tw;
+        r.th = th;
+        if (persistent) {
+            launch_tile_len_keys(ranges, n_tiles, tkeys, tvals, st);
+            launch_sort_pairs(tkeys, tvals, tkeys_alt, tvals_alt, tiles_dev, max_tiles, 20, false, tsort_ws, st);
+            r.queue = queue;
+            r.order = tvals;
+            r.persistent_grid = grid_fwd;
+        }
+        launch_render_fwd(r, images, final_T, n_contrib, nullptr, nullptr, st);
+        launch_l1(vt(), n, max_pix, d_targets, images, dimg, loss, status, st);
+        launch_fill_u32(reinterpret_cast<uint32_t*>(g2d), 0u, (size_t)nslots * 9, st);
+        if (persistent) r.persistent_grid = grid_bwd;
+        launch_render_bwd(r, final_T, n_contrib, dimg, nslots, g2d, nullptr, st);
+        launch_project_bwd(jt(), vt(), K, nslots, tt, g2d, status, st);
+    }
+
+    // Pairs the current tile shape needs (one projection + emission, synchronous).
+    gs_status pairs_needed(hipStream_t st, uint32_t* need) {
+        const int64_t cap = capacity;
+        capacity = 0;   // count only
+        enqueue_project_bin(st);
+        capacity = cap;
+        uint32_t pc[2] = {0, 0};
+        if (hipMemcpyAsync(pc, pair_count, sizeof pc, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return check_hip("gs_batch: sizing pass");
+        *need = pc[1];
+        return GS_OK;
+    }
+
+    gs_status alloc_pairs(int64_t cap) {
+        if (cap > kMaxPairs) return fail(GS_ERR_CAPACITY, "batch needs %lld pairs (> 2^30-1)", (long long)cap);
+        for (void* p : {(void*)keys, (void*)alt_k, (void*)vals, (void*)alt_v, sort_ws})
+            if (p) (void)hipFree(p);
+        keys = alt_k = nullptr;
+        vals = alt_v = nullptr;
+        sort_ws = nullptr;
+        gs_status s;
+        sort_ws_bytes = sort_workspace_bytes(cap, 64);
+        if ((s = dmalloc(&keys, cap)) || (s = dmalloc(&alt_k, cap)) || (s = dmalloc(&vals, cap)) ||
+            (s = dmalloc(&alt_v, cap)) || (s = dmalloc(reinterpret_cast<char**>(&sort_ws), sort_ws_bytes)))
+            return s;
+        capacity = cap;
+        return GS_OK;
+    }
+
+    gs_status capture(hipStream_t st) {
+        if (exec) {
+            (void)hipGraphExecDestroy(exec);
+            exec = nullptr;
+        }
+        if (graph) {
+            (void)hipGraphDestroy(graph);
+            graph = nullptr;
+        }
+        if (!use_graph) return GS_OK;
+        if (hipStreamSynchronize(st) != hipSuccess) return check_hip("gs_batch: capture");
+        if (hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return check_hip("gs_batch: begin capture");
+        enqueue_step(cap_stream);
+        if (hipStreamEndCapture(cap_stream, &graph) != hipSuccess) return check_hip("gs_batch: end capture");
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+            return check_hip("gs_batch: instantiate");
+        return GS_OK;
+    }
+
+    gs_status run(hipStream_t st) {
+        if (use_graph && exec) {
+            if (hipGraphLaunch(exec, st) != hipSuccess) return check_hip("gs_batch_step: graph launch");
+            return GS_OK;
+        }
+        enqueue_step(st);
+        return check_hip("gs_batch_step");
+    }
+
+    // Mean step time of the current configuration over `iters` launches.
+    gs_status time_steps(hipStream_t st, int warm, int iters, double* ms) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return check_hip("gs_batch: events");
+        gs_status s = GS_OK;
+        for (int i = 0; i < warm && !s; ++i) s = run(st);
+        if (!s && hipEventRecord(a, st) != hipSuccess) s = check_hip("gs_batch: event");
+        for (int i = 0; i < iters && !s; ++i) s = run(st);
+        float f = 0.f;
+        if (!s && (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                   hipEventElapsedTime(&f, a, b) != hipSuccess))
+            s = check_hip("gs_batch: timing");
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        *ms = f / (iters > 0 ? iters : 1);
+        return s;
+    }
+
+    gs_status device_status(hipStream_t st, int32_t* out) {
+        if (hipMemcpyAsync(out, status, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return check_hip("gs_batch: status");
+        return GS_OK;
+    }
+};
+
+extern "C" {
+
+gs_status gs_batch_create(const gs_gaussians* cells, const gs_camera* cams, const float* const* targets,
+                          int32_t n_cells, float* images, gs_grads* grads, float* loss,
+                          const gs_batch_config* cfg, gs_stream stream, gs_batch** out) {
+    if (!out) return fail(GS_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n_cells <= 0 || !cells || !cams || !targets || !images || !grads || !loss)
+        return fail(GS_ERR_INVALID, "NULL argument or n_cells <= 0");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    gs_batch* b = new gs_batch();
+    b->n = n_cells;
+    gs_status s = GS_OK;
+    for (int c = 0; c < n_cells && !s; ++c) {
+        Gauss G;
+        Cam C;
+        if ((s = to_gauss(&cells[c], &G)) || (s = to_cam(&cams[c], &C))) break;
+        if (c == 0) b->K = G.K;
+        else if (G.K != b->K) s = fail(GS_ERR_INVALID, "cells must share one SH degree");
+        if (!targets[c]) s = fail(GS_ERR_INVALID, "target %d is NULL", c);
+        if (grads[c].ld < G.n || (G.n > 0 && (!grads[c].mean || !grads[c].scale || !grads[c].quat ||
+                                              !grads[c].opacity || !grads[c].sh)))
+            s = fail(GS_ERR_INVALID, "gradient buffers of cell %d", c);
+        b->cells.push_back(G);
+        b->cams.push_back(C);
+    }
+    int tw0 = cfg && cfg->tile_w ? cfg->tile_w : 16, th0 = cfg && cfg->tile_h ? cfg->tile_h : 16;
+    const int autotune = cfg ? cfg->autotune : 0;
+    b->persistent = cfg ? (cfg->persistent != 0) : 1;
+    b->use_graph = cfg ? (cfg->use_graph != 0) : 1;
+    b->headroom = cfg && cfg->capacity_headroom > 1.0 ? cfg->capacity_headroom : 1.25;
+    if (!s && !render_tile_supported(tw0, th0)) s = fail(GS_ERR_UNSUPPORTED, "tile %dx%d not supported", tw0, th0);
+    if (s) {
+        delete b;
+        return s;
+    }
+    // slots, images, tables
+    int64_t slot = 0, img = 0, pix = 0;
+    b->h_views.resize(n_cells);
+    b->h_jobs.resize(n_cells);
+    for (int c = 0; c < n_cells; ++c) {
+        const Gauss& G = b->cells[c];
+        const Cam& C = b->cams[c];
+        b->out0.push_back(slot);
+        Job& j = b->h_jobs[c];
+        std::memset(&j, 0, sizeof j);
+        j.g = G;
+        j.src0 = 0;
+        j.count = G.n;
+        j.out0 = slot;
+        j.view = c;
+        j.gmean = grads[c].mean;
+        j.gscale = grads[c].scale;
+        j.gquat = grads[c].quat;
+        j.gopac = grads[c].opacity;
+        j.gsh = grads[c].sh;
+        j.gld = grads[c].ld;
+        slot += (G.n + kSlotAlign - 1) / kSlotAlign * kSlotAlign;
+        View& v = b->h_views[c];
+        std::memset(&v, 0, sizeof v);
+        v.cam = C;
+        v.img_base = img;
+        v.pix_base = pix;
+        img += 3 * (int64_t)C.W * C.H;
+        pix += (int64_t)C.W * C.H;
+        b->max_pix = std::max<int64_t>(b->max_pix, (int64_t)C.W * C.H);
+    }
+    if (slot > (int64_t)0xFFFFFFFF) s = fail(GS_ERR_INVALID, "more than 2^32-1 Gaussian slots");
+    b->nslots = slot;
+    b->img_floats = img;
+    b->pix_count = pix;
+    b->images = images;
+    b->loss = loss;
+    // tile buffers sized for the candidate with the most tiles
+    uint32_t max_tiles = b->tiles_for(tw0, th0);
+    if (autotune)
+        for (const Cand& c : kCands) max_tiles = std::max(max_tiles, b->tiles_for(c.tw, c.th));
+    b->max_tiles = max_tiles;
+    size_t tsort = sort_workspace_bytes(max_tiles, 20);
+    if (!s) {
+        if ((s = dmalloc(&b->d_views, n_cells)) || (s = dmalloc(&b->d_jobs, n_cells)) ||
+            (s = dmalloc(&b->d_targets, n_cells)) || (s = dmalloc(&b->rec, slot)) || (s = dmalloc(&b->depth, slot)) ||
+            (s = dmalloc(&b->rect, slot)) || (s = dmalloc(&b->tt, slot)) || (s = dmalloc(&b->g2d, slot * 9)) ||
+            (s = dmalloc(reinterpret_cast<char**>(&b->scan_ws), scan_workspace_bytes(slot))) ||
+            (s = dmalloc(&b->ranges, (size_t)max_tiles * 2)) || (s = dmalloc(&b->pair_count, 2)) ||
+            (s = dmalloc(&b->status, 1)) || (s = dmalloc(&b->queue, 1)) || (s = dmalloc(&b->tiles_dev, 1)) ||
+            (s = dmalloc(&b->tkeys, max_tiles)) || (s = dmalloc(&b->tkeys_alt, max_tiles)) ||
+            (s = dmalloc(&b->tvals, max_tiles)) || (s = dmalloc(&b->tvals_alt, max_tiles)) ||
+            (s = dmalloc(reinterpret_cast<char**>(&b->tsort_ws), tsort)) || (s = dmalloc(&b->final_T, pix)) ||
+            (s = dmalloc(&b->n_contrib, pix)) || (s = dmalloc(&b->dimg, img)))
+            ;
+    }
+    if (!s && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        s = check_hip("gs_batch: stream");
+    if (!s) {
+        std::vector<const float*> tg(targets, targets + n_cells);
+        if (hipMemcpyAsync(b->d_jobs, b->h_jobs.data(), sizeof(Job) * n_cells, hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(b->d_targets, tg.data(), sizeof(float*) * n_cells, hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(b->status, "\0\0\0\0", 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            s = check_hip("gs_batch: table upload");
+    }
+    // capacity: the most pairs any candidate tile shape needs, with headroom
+    std::vector<Cand> cands;
+    if (autotune) cands.assign(std::begin(kCands), std::end(kCands));
+    else cands.push_back({tw0, th0, b->persistent});
+    uint32_t need = 0;
+    for (const Cand& c : cands) {
+        if (s) break;
+        uint32_t p = 0;
+        if ((s = b->set_tiles(c.tw, c.th, st)) || (s = b->pairs_needed(st, &p))) break;
+        need = std::max(need, p);
+    }
+    if (!s) s = b->alloc_pairs((int64_t)std::ceil(need * b->headroom) + 4096);
+    // autotune: time every candidate (eager launches), keep the fastest
+    if (!s && autotune) {
+        double best = 1e30;
+        Cand pick = cands[0];
+        const int saved_graph = b->use_graph;
+        b->use_graph = 0;
+        for (const Cand& c : cands) {
+            double ms = -1;
+            b->persistent = c.persistent;
+            if ((s = b->set_tiles(c.tw, c.th, st)) || (s = b->time_steps(st, 2, 5, &ms))) break;
+            int32_t dst = 0;
+            if ((s = b->device_status(st, &dst))) break;
+            if (dst != 0) ms = -1;   // did not fit (cannot happen with the sized capacity)
+            b->tune_ms.push_back(ms);
+            if (ms > 0 && ms < best) {
+                best = ms;
+                pick = c;
+            }
+        }
+        b->use_graph = saved_graph;
+        b->persistent = pick.persistent;
+        if (!s) s = b->set_tiles(pick.tw, pick.th, st);
+    } else if (!s) {
+        s = b->set_tiles(tw0, th0, st);
+    }
+    if (!s) s = b->capture(st);
+    if (s) {
+        delete b;
+        return s;
+    }
+    *out = b;
+    return GS_OK;
+}
+
+gs_status gs_batch_step(gs_batch* b, gs_stream stream) {
+    if (!b) return fail(GS_ERR_INVALID, "batch is NULL");
+    return b->run(static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_batch_info(const gs_batch* b, gs_batch_stats* info) {
+    if (!b || !info) return fail(GS_ERR_INVALID, "NULL argument");
+    std::memset(info, 0, sizeof *info);
+    info->tile_w = b->tw;
+    info->tile_h = b->th;
+    info->persistent = b->persistent;
+    info->use_graph = b->use_graph && b->exec != nullptr;
+    info->grid_fwd = b->grid_fwd;
+    info->grid_bwd = b->grid_bwd;
+    info->n_tiles = b->n_tiles;
+    info->slots = b->nslots;
+    info->pair_capacity = b->capacity;
+    info->n_candidates = (int32_t)b->tune_ms.size();
+    for (size_t i = 0; i < b->tune_ms.size() && i < 16; ++i) {
+        info->cand_tile_w[i] = kCands[i].tw;
+        info->cand_tile_h[i] = kCands[i].th;
+        info->cand_persistent[i] = kCands[i].persistent;
+        info->cand_ms[i] = b->tune_ms[i];
+    }
+    return GS_OK;
+}
+
+gs_status gs_batch_status(gs_batch* b, gs_stream stream, int32_t* status, uint32_t* pairs) {
+    if (!b || !status) return fail(GS_ERR_INVALID, "NULL argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint32_t pc[2] = {0, 0};
+    if (hipMemcpyAsync(status, b->status, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(pc, b->pair_count, sizeof pc, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return check_hip("gs_batch_status");
+    if (pairs) {
+        pairs[0] = pc[0];
+        pairs[1] = pc[1];
+    }
+    return GS_OK;
+}
+
+void gs_batch_destroy(gs_batch* b) { delete b; }
+
+}  // extern "C"

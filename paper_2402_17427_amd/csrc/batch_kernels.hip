@@ -1,0 +1,77 @@
+// Small kernels of the batched training step: the L1 image loss and its
+// gradient for every view of the batch, and the longest-list-first tile
+// order the persistent blend launches pull from.
+//
+// VastGaussian (arXiv 2402.17427), section 3: each cell is optimised
+// against its training images with an image loss; the per-pixel L1 term is
+// the part of that loss this step evaluates (mean absolute error over the
+// three colour planes, gradient sign(I - I*) / (3 W H), sign(0) = 0).
+#include "kernels.h"
+
+namespace gs {
+
+namespace {
+
+constexpr int kL1Threads = 256;
+
+// One workgroup per (view, chunk of pixels): grid.y = view.
+__global__ __launch_bounds__(kL1Threads) void k_l1(ViewTab views, const float* const* __restrict__ targets,
+                                                   const float* __restrict__ image, float* __restrict__ dimg,
+                                                   float* __restrict__ loss, const int32_t* __restrict__ status) {
+    __shared__ float red[kL1Threads / kWave];
+    const int v = blockIdx.y;
+    const View V = view_at(views, v);
+    const int64_t npix = (int64_t)V.cam.W * V.cam.H;
+    const int64_t total = 3 * npix;
+    const float* __restrict__ tgt = targets[v];
+    const float inv = 1.0f / (float)total;
+    const bool ok = *status == 0;
+    float acc = 0.f;
+    for (int64_t q = (int64_t)blockIdx.x * kL1Threads + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * kL1Threads) {
+        const float d = image[V.img_base + q] - tgt[q];
+        acc += fabsf(d);
+        dimg[V.img_base + q] = ok ? (d > 0.f ? inv : (d < 0.f ? -inv : 0.f)) : 0.f;
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float s = 0.f;
+        for (int k = 0; k < kL1Threads / kWave; ++k) s += red[k];
+        atomicAdd(&loss[v], s * inv);
+    }
+}
+
+// keys[t] = (2^20 - 1 - min(list length, 2^20 - 1)), vals[t] = t: a stable
+// ascending sort on 20 key bits gives the tiles longest list first.
+__global__ __launch_bounds__(256) void k_tile_len_keys(const uint2* __restrict__ ranges, uint32_t n_tiles,
+                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint2 r = ranges[t];
+    const uint32_t len = min(r.y - r.x, (1u << 20) - 1u);
+    keys[t] = (uint64_t)((1u << 20) - 1u - len);
+    vals[t] = t;
+}
+
+}  // namespace
+
+void launch_l1(const ViewTab& views, int n_views, int64_t max_pix, const float* const* targets, const float* image,
+               float* dimg, float* loss, const int32_t* status, hipStream_t st) {
+    if (n_views == 0) return;
+    launch_fill_u32(reinterpret_cast<uint32_t*>(loss), 0u, (size_t)n_views, st);
+    int64_t bx = (3 * max_pix + kL1Threads * 8 - 1) / (kL1Threads * 8);
+    if (bx > 1024) bx = 1024;
+    if (bx < 1) bx = 1;
+    hipLaunchKernelGGL(k_l1, dim3((unsigned)bx, (unsigned)n_views), dim3(kL1Threads), 0, st, views, targets, image,
+                       dimg, loss, status);
+}
+
+void launch_tile_len_keys(const uint32_t* ranges, uint32_t n_tiles, uint64_t* keys, uint32_t* vals, hipStream_t st) {
+    if (n_tiles == 0) return;
+    hipLaunchKernelGGL(k_tile_len_keys, dim3((n_tiles + 255) / 256), dim3(256), 0, st,
+                       reinterpret_cast<const uint2*>(ranges), n_tiles, keys, vals);
+}
+
+}  // namespace gs

@@ -74,20 +74,23 @@ __global__ __launch_bounds__(kScanTopThreads) void k_scan_top(uint64_t* __restri
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_emit(const uint32_t* __restrict__ tt, const ushort4* __restrict__ rect,
-                                                       const float* __restrict__ depth, int64_t n, int ntx,
-                                                       const uint64_t* __restrict__ block_prefix, int64_t capacity,
-                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                                       const float* __restrict__ depth, int64_t n, JobTab jobs,
+                                                       ViewTab views, const uint64_t* __restrict__ block_prefix,
+                                                       int64_t capacity, uint64_t* __restrict__ keys,
+                                                       uint32_t* __restrict__ vals) {
     const int64_t i = (int64_t)blockIdx.x * kScanThreads + threadIdx.x;
     const uint32_t cnt = i < n ? tt[i] : 0u;
     uint64_t tot;
     uint64_t off = block_prefix[blockIdx.x] + block_exclusive_scan<kScanThreads>(cnt, &tot);
     if (cnt == 0) return;
+    // record slots are aligned so that a workgroup lies within one job
+    const View V = view_at(views, job_at(jobs, find_job(jobs, (int64_t)blockIdx.x * kScanThreads)).view);
     const ushort4 r = rect[i];
     const uint64_t zb = (uint64_t)__float_as_uint(depth[i]);
     for (int ty = r.y; ty < r.w; ++ty)
         for (int tx = r.x; tx < r.z; ++tx) {
             if (off < (uint64_t)capacity) {
-                keys[off] = ((uint64_t)(ty * ntx + tx) << 32) | zb;
+                keys[off] = ((uint64_t)(V.tile_base + (uint32_t)(ty * V.ntx + tx)) << 32) | zb;
                 vals[off] = (uint32_t)i;
             }
             ++off;
@@ -123,16 +126,16 @@ void launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, v, count);
 }
 
-void launch_emit_pairs(int64_t n, const uint32_t* tt, const ushort4* rect, const float* depth, int ntx,
-                       int64_t capacity, uint64_t* keys, uint32_t* vals, uint32_t* pair_count, int32_t* status,
-                       void* scan_ws, hipStream_t st) {
+void launch_emit_pairs(int64_t n, const uint32_t* tt, const ushort4* rect, const float* depth, const JobTab& jobs,
+                       const ViewTab& views, int64_t capacity, uint64_t* keys, uint32_t* vals, uint32_t* pair_count,
+                       int32_t* status, void* scan_ws, hipStream_t st) {
     uint64_t* bs = static_cast<uint64_t*>(scan_ws);
     const int64_t nb = (n + kScanThreads - 1) / kScanThreads;
     if (nb > 0) hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nb), dim3(kScanThreads), 0, st, tt, n, bs);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTopThreads), 0, st, bs, nb, capacity, pair_count, status);
     if (nb > 0)
-        hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kScanThreads), 0, st, tt, rect, depth, n, ntx, bs,
-                           capacity, keys, vals);
+        hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kScanThreads), 0, st, tt, rect, depth, n, jobs, views,
+                           bs, capacity, keys, vals);
 }
 
 void launch_tile_ranges(const uint64_t* keys, const uint32_t* pair_count, int64_t capacity, int64_t n_tiles,

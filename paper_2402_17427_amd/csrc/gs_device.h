@@ -51,6 +51,71 @@ struct Gauss {
     const float *mean, *scale, *quat, *opacity, *sh;
 };
 
+// ---- batches of views ------------------------------------------------
+// The kernels render a set of views at once.  Tiles of all views are
+// numbered consecutively (view v owns global tiles tile_base ..
+// tile_base + ntx * nty - 1) and the images are stacked; a "job" projects
+// a range of a Gaussian set into one view, into consecutive record slots
+// starting at out0 (a multiple of kSlotAlign, so that a workgroup of the
+// per-slot kernels never spans two jobs).  One view with one job is the
+// plain single-view render.
+constexpr int kSlotAlign = 256;
+
+struct View {
+    Cam cam;
+    int ntx, nty;          // tiles of this view
+    uint32_t tile_base;    // first global tile id of the view
+    int64_t img_base;      // offset (floats) of the view's [3][H][W] image
+    int64_t pix_base;      // offset of the view's [H][W] planes (final_T, n_contrib, dL/dimage is at img_base)
+};
+
+struct Job {
+    Gauss g;                        // SoA planes of the Gaussian set
+    int64_t src0, count, out0;      // Gaussians src0 .. src0+count-1 -> slots out0 ..
+    int view;
+    float *gmean, *gscale, *gquat, *gopac, *gsh;   // gradient planes (stride gld, index src0 + k)
+    int64_t gld;
+};
+
+// A table lives in device memory (dev != nullptr, n entries) or is the
+// single entry carried in the kernel arguments.
+struct ViewTab {
+    const View* dev;
+    int n;
+    View one;
+};
+struct JobTab {
+    const Job* dev;
+    int n;
+    Job one;
+};
+
+// Job owning record slot `slot` (jobs sorted by out0); uniform per workgroup.
+__device__ __forceinline__ int find_job(const JobTab& t, int64_t slot) {
+    if (!t.dev) return 0;
+    int lo = 0, hi = t.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t.dev[mid].out0 <= slot) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+__device__ __forceinline__ Job job_at(const JobTab& t, int j) { return t.dev ? t.dev[j] : t.one; }
+
+// View owning global tile `tile` (views sorted by tile_base).
+__device__ __forceinline__ int find_view(const ViewTab& t, uint32_t tile) {
+    if (!t.dev) return 0;
+    int lo = 0, hi = t.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t.dev[mid].tile_base <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+__device__ __forceinline__ View view_at(const ViewTab& t, int v) { return t.dev ? t.dev[v] : t.one; }
+
 // One projected Gaussian staged in LDS for a tile.  The centre is held as
 // an unevaluated float sum hi + lo of the FP64 centre, and a pixel offset is
 // formed as (pixel centre - hi) - lo: a function of the pixel and the

@@ -12,11 +12,13 @@
 namespace gs {
 
 // ---- projection (project.hip)
-void launch_project(const Gauss& g, const Cam& cam, int tw, int th, Rec* rec, float* depth, ushort4* rect,
-                    uint32_t* tiles_touched, hipStream_t st);
-void launch_project_bwd(const Gauss& g, const Cam& cam, const uint32_t* tiles_touched, const float* g2d,
-                        const int32_t* status, int64_t gld, float* gmean, float* gscale, float* gquat, float* gopac,
-                        float* gsh, hipStream_t st);
+// nslots record slots (jobs' out0 aligned to kSlotAlign; K = SH size, the
+// same for every job).  Padding slots get tiles_touched = 0.
+void launch_project(const JobTab& jobs, const ViewTab& views, int K, int64_t nslots, int tw, int th, Rec* rec,
+                    float* depth, ushort4* rect, uint32_t* tiles_touched, hipStream_t st);
+// Chain rule per slot from g2d [9][nslots] into each job's gradient planes.
+void launch_project_bwd(const JobTab& jobs, const ViewTab& views, int K, int64_t nslots,
+                        const uint32_t* tiles_touched, const float* g2d, const int32_t* status, hipStream_t st);
 
 // ---- binning (binning.hip)
 // Workspace for the tiles_touched scan over n Gaussians.
@@ -26,8 +28,8 @@ size_t scan_workspace_bytes(int64_t n);
 // GS_ERR_CAPACITY (-4) when the pairs exceed `capacity` (pairs beyond it
 // are dropped).
 void launch_emit_pairs(int64_t n, const uint32_t* tiles_touched, const ushort4* rect, const float* depth,
-                       int ntx, int64_t capacity, uint64_t* keys, uint32_t* vals, uint32_t* pair_count,
-                       int32_t* status, void* scan_ws, hipStream_t st);
+                       const JobTab& jobs, const ViewTab& views, int64_t capacity, uint64_t* keys, uint32_t* vals,
+                       uint32_t* pair_count, int32_t* status, void* scan_ws, hipStream_t st);
 void launch_tile_ranges(const uint64_t* keys, const uint32_t* pair_count, int64_t capacity, int64_t n_tiles,
                         uint32_t* ranges, hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t st);
@@ -45,15 +47,45 @@ void launch_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint3
                        hipStream_t st);
 
 // ---- blend (render_fwd.hip / render_bwd.hip)
+// What both blend passes read: records, sorted values, per-tile ranges of
+// all views' tiles (global tile ids), status, the view table and the tile
+// shape.  With `queue` set (one device uint32, zeroed by the launcher) and
+// persistent_grid > 0 the launch is a persistent grid pulling tiles from
+// `order` (a permutation of the tiles, or NULL for 0, 1, ...).
+struct RenderArgs {
+    const Rec* rec;
+    const uint32_t* vals;
+    const uint32_t* ranges;
+    const int32_t* status;
+    ViewTab views;
+    uint32_t n_tiles;
+    int tw, th;
+    uint32_t* queue;
+    const uint32_t* order;
+    int persistent_grid;
+};
+
 bool render_tile_supported(int tw, int th);
-// stats != NULL runs the counting variant instead (no image written);
-// state != NULL also stores the per-entry blend state (P * tile pixels).
-void launch_render_fwd(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status,
-                       const Cam& cam, int tw, int th, float* image, float* final_T, uint32_t* n_contrib,
+// image/final_T/n_contrib are the stacked planes of all views.  stats !=
+// NULL runs the counting variant instead (no image written); state !=
+// NULL also stores the per-entry blend state (pairs * tile pixels).
+void launch_render_fwd(const RenderArgs& r, float* image, float* final_T, uint32_t* n_contrib,
                        unsigned long long* stats, float2* state, hipStream_t st);
-// state != NULL reads the stored blend state instead of recomputing it.
-void launch_render_bwd(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status,
-                       const Cam& cam, int tw, int th, const float* final_T, const uint32_t* n_contrib,
-                       const float* dimg, int64_t n, float* g2d, const float2* state, hipStream_t st);
+// g2d [9][nslots] is accumulated (not zeroed here).  state != NULL reads
+// the stored blend state instead of recomputing it.
+void launch_render_bwd(const RenderArgs& r, const float* final_T, const uint32_t* n_contrib, const float* dimg,
+                       int64_t nslots, float* g2d, const float2* state, hipStream_t st);
+
+// Workgroups of a persistent blend launch that fit on the device at once.
+int render_persistent_grid(int tw, int th, bool backward);
+
+// ---- batched step (batch_kernels.hip)
+// L1 loss of every view against its target ([3][H][W] each; targets is a
+// device array of device pointers): loss[v] = mean |I - I*|, dimg =
+// sign(I - I*) / (3 W H), zero when *status != 0.  loss is zeroed here.
+void launch_l1(const ViewTab& views, int n_views, int64_t max_pix, const float* const* targets, const float* image,
+               float* dimg, float* loss, const int32_t* status, hipStream_t st);
+// Sort keys putting the tiles with the longest lists first.
+void launch_tile_len_keys(const uint32_t* ranges, uint32_t n_tiles, uint64_t* keys, uint32_t* vals, hipStream_t st);
 
 }  // namespace gs

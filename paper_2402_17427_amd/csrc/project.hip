@@ -170,11 +170,21 @@ __device__ __forceinline__ bool geometry(const Cam& cam, const double mu[3], con
 }
 
 template <int K>
-__global__ __launch_bounds__(kProjThreads) void k_project(Gauss G, Cam cam, int tw, int th,
+__global__ __launch_bounds__(kProjThreads) void k_project(JobTab jobs, ViewTab views, int tw, int th, int64_t nslots,
                                                           Rec* __restrict__ rec, float* __restrict__ depth,
                                                           ushort4* __restrict__ rect, uint32_t* __restrict__ tt) {
-    const int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
-    if (i >= G.n) return;
+    const int64_t slot = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
+    if (slot >= nslots) return;
+    const Job J = job_at(jobs, find_job(jobs, (int64_t)blockIdx.x * kProjThreads));
+    const int64_t k = slot - J.out0;
+    if (k >= J.count) {   // alignment padding between jobs
+        tt[slot] = 0u;
+        rect[slot] = make_ushort4(0, 0, 0, 0);
+        return;
+    }
+    const Cam cam = view_at(views, J.view).cam;
+    const Gauss& G = J.g;
+    const int64_t i = J.src0 + k;
     const int64_t ld = G.ld;
     double mu[3], s[3], q[4];
     bool fin = true;
@@ -257,25 +267,33 @@ __global__ __launch_bounds__(kProjThreads) void k_project(Gauss G, Cam cam, int 
             }
         }
     }
-    rec[i] = out;
-    depth[i] = z;
-    rect[i] = rc;
-    tt[i] = count;
+    rec[slot] = out;
+    depth[slot] = z;
+    rect[slot] = rc;
+    tt[slot] = count;
 }
 
 // Backward of the projection for one Gaussian.  g2d planes: du, dv, dA, dB,
 // dC, d opacity, dr, dg, db (accumulated by the blend backward).
 template <int K>
-__global__ __launch_bounds__(kProjThreads) void k_project_bwd(Gauss G, Cam cam, const uint32_t* __restrict__ tt,
+__global__ __launch_bounds__(kProjThreads) void k_project_bwd(JobTab jobs, ViewTab views, int64_t nslots,
+                                                              const uint32_t* __restrict__ tt,
                                                               const float* __restrict__ g2d,
-                                                              const int32_t* __restrict__ status, int64_t gld,
-                                                              float* __restrict__ gmean, float* __restrict__ gscale,
-                                                              float* __restrict__ gquat, float* __restrict__ gopac,
-                                                              float* __restrict__ gsh) {
-    const int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
-    if (i >= G.n) return;
-    const int64_t ld = G.ld, n = G.n;
-    const bool live = tt[i] != 0 && *status == 0;
+                                                              const int32_t* __restrict__ status) {
+    const int64_t slot = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
+    if (slot >= nslots) return;
+    const Job J = job_at(jobs, find_job(jobs, (int64_t)blockIdx.x * kProjThreads));
+    const int64_t k = slot - J.out0;
+    if (k >= J.count) return;   // alignment padding between jobs
+    const Cam cam = view_at(views, J.view).cam;
+    const Gauss& G = J.g;
+    const int64_t i = J.src0 + k, ld = G.ld, gld = J.gld, n = nslots;
+    float* __restrict__ gmean = J.gmean;
+    float* __restrict__ gscale = J.gscale;
+    float* __restrict__ gquat = J.gquat;
+    float* __restrict__ gopac = J.gopac;
+    float* __restrict__ gsh = J.gsh;
+    const bool live = tt[slot] != 0 && *status == 0;
     if (!live) {
         for (int r = 0; r < 3; ++r) { gmean[r * gld + i] = 0.f; gscale[r * gld + i] = 0.f; }
         for (int r = 0; r < 4; ++r) gquat[r * gld + i] = 0.f;
@@ -286,10 +304,10 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(Gauss G, Cam cam, 
     double mu[3], s[3], q[4];
     for (int r = 0; r < 3; ++r) { mu[r] = G.mean[r * ld + i]; s[r] = G.scale[r * ld + i]; }
     for (int r = 0; r < 4; ++r) q[r] = G.quat[r * ld + i];
-    const double du = g2d[i], dv = g2d[n + i];
-    const double dA = g2d[2 * n + i], dB = g2d[3 * n + i], dC = g2d[4 * n + i];
-    gopac[i] = g2d[5 * n + i];
-    const float drgb[3] = {g2d[6 * n + i], g2d[7 * n + i], g2d[8 * n + i]};
+    const double du = g2d[slot], dv = g2d[n + slot];
+    const double dA = g2d[2 * n + slot], dB = g2d[3 * n + slot], dC = g2d[4 * n + slot];
+    gopac[i] = g2d[5 * n + slot];
+    const float drgb[3] = {g2d[6 * n + slot], g2d[7 * n + slot], g2d[8 * n + slot]};
 
     Geo g;
     geometry(cam, mu, s, q, g);   // live implies it succeeded in the forward
@@ -403,12 +421,13 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(Gauss G, Cam cam, 
 
 }  // namespace
 
-void launch_project(const Gauss& g, const Cam& cam, int tw, int th, Rec* rec, float* depth, ushort4* rect,
-                    uint32_t* tt, hipStream_t st) {
-    if (g.n == 0) return;
-    const unsigned blocks = (unsigned)((g.n + kProjThreads - 1) / kProjThreads);
-#define GS_PROJ(k) hipLaunchKernelGGL(k_project<k>, dim3(blocks), dim3(kProjThreads), 0, st, g, cam, tw, th, rec, depth, rect, tt)
-    switch (g.K) {
+void launch_project(const JobTab& jobs, const ViewTab& views, int K, int64_t nslots, int tw, int th, Rec* rec,
+                    float* depth, ushort4* rect, uint32_t* tt, hipStream_t st) {
+    if (nslots == 0) return;
+    const unsigned blocks = (unsigned)((nslots + kProjThreads - 1) / kProjThreads);
+#define GS_PROJ(k) \
+    hipLaunchKernelGGL(k_project<k>, dim3(blocks), dim3(kProjThreads), 0, st, jobs, views, tw, th, nslots, rec, depth, rect, tt)
+    switch (K) {
         case 1: GS_PROJ(1); break;
         case 4: GS_PROJ(4); break;
         case 9: GS_PROJ(9); break;
@@ -417,14 +436,13 @@ void launch_project(const Gauss& g, const Cam& cam, int tw, int th, Rec* rec, fl
 #undef GS_PROJ
 }
 
-void launch_project_bwd(const Gauss& g, const Cam& cam, const uint32_t* tt, const float* g2d, const int32_t* status,
-                        int64_t gld, float* gmean, float* gscale, float* gquat, float* gopac, float* gsh,
-                        hipStream_t st) {
-    if (g.n == 0) return;
-    const unsigned blocks = (unsigned)((g.n + kProjThreads - 1) / kProjThreads);
-#define GS_PROJ_BWD(k) hipLaunchKernelGGL(k_project_bwd<k>, dim3(blocks), dim3(kProjThreads), 0, st, g, cam, tt, g2d, status, gld, gmean, \
-                       gscale, gquat, gopac, gsh)
-    switch (g.K) {
+void launch_project_bwd(const JobTab& jobs, const ViewTab& views, int K, int64_t nslots, const uint32_t* tt,
+                        const float* g2d, const int32_t* status, hipStream_t st) {
+    if (nslots == 0) return;
+    const unsigned blocks = (unsigned)((nslots + kProjThreads - 1) / kProjThreads);
+#define GS_PROJ_BWD(k) \
+    hipLaunchKernelGGL(k_project_bwd<k>, dim3(blocks), dim3(kProjThreads), 0, st, jobs, views, nslots, tt, g2d, status)
+    switch (K) {
         case 1: GS_PROJ_BWD(1); break;
         case 4: GS_PROJ_BWD(4); break;
         case 9: GS_PROJ_BWD(9); break;

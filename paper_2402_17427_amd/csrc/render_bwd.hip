@@ -31,39 +31,67 @@ namespace gs {
 
 namespace {
 
+struct BwdArgs {
+    const Rec* rec;
+    const uint32_t* vals;
+    const uint2* ranges;
+    const int32_t* status;
+    ViewTab views;
+    const float* final_T;
+    const uint32_t* n_contrib;
+    const float* dimg;
+    int64_t n;              // slots: plane stride of g2d
+    float* g2d;
+    const float2* state;
+    uint32_t* queue;        // persistent launch: next queue position (zeroed before launch)
+    const uint32_t* order;  // persistent launch: tiles in processing order (NULL = 0, 1, ...)
+    uint32_t n_tiles;
+};
+
+template <int NT>
+struct BwdShared {
+    static constexpr int B = NT < 256 ? NT : 256;   // staged Gaussians per batch
+    Staged s[B];
+    uint32_t gid[B];
+    float acc[B * 9];
+    uint32_t max_last;
+};
+
 // STORED = true reads each entry's (alpha, T) from the state the storing
 // forward wrote (alpha negated when capped) instead of recomputing them.
 template <int TW, int TH, bool STORED>
-__global__ __launch_bounds__(TW * TH) void k_render_bwd(const Rec* __restrict__ rec, const uint32_t* __restrict__ vals,
-                                                        const uint2* __restrict__ ranges,
-                                                        const int32_t* __restrict__ status, int W, int H, int ntx,
-                                                        float bg0, float bg1, float bg2,
-                                                        const float* __restrict__ final_T,
-                                                        const uint32_t* __restrict__ n_contrib,
-                                                        const float* __restrict__ dimg, int64_t n,
-                                                        float* __restrict__ g2d,
-                                                        const float2* __restrict__ state) {
+__device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdShared<TW * TH>& sh) {
     constexpr int NT = TW * TH;
-    constexpr int B = NT < 256 ? NT : 256;   // staged Gaussians per batch
+    constexpr int B = BwdShared<NT>::B;
     constexpr int WX = TW / 8;
-    __shared__ Staged s[B];
-    __shared__ uint32_t s_gid[B];
-    __shared__ float s_acc[B * 9];
-    __shared__ uint32_t s_max;
+    Staged* s = sh.s;
+    uint32_t* s_gid = sh.gid;
+    float* s_acc = sh.acc;
 
-    if (*status != 0) return;
+    if (*a.status != 0) return;
 
+    const View V = view_at(a.views, find_view(a.views, tile));
+    const int W = V.cam.W, H = V.cam.H;
+    const int local = (int)(tile - V.tile_base);
+    const int tx = local % V.ntx, ty = local / V.ntx;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    const int tile = blockIdx.x;
-    const int tx = tile % ntx, ty = tile / ntx;
     const int bx = (wv % WX) * 8, by = (wv / WX) * 8;
     const int lx = bx + (lane & 7), ly = by + (lane >> 3);
     const int px = tx * TW + lx, py = ty * TH + ly;
     const bool inside = px < W && py < H;
     const int64_t npix = (int64_t)W * H;
     const int64_t off = (int64_t)py * W + px;
+    const float* final_T = a.final_T + V.pix_base;
+    const uint32_t* n_contrib = a.n_contrib + V.pix_base;
+    const float* dimg = a.dimg + V.img_base;
+    const Rec* __restrict__ rec = a.rec;
+    const uint32_t* __restrict__ vals = a.vals;
+    const float2* __restrict__ state = a.state;
+    float* __restrict__ g2d = a.g2d;
+    const int64_t n = a.n;
+    const float bg0 = V.cam.bg[0], bg1 = V.cam.bg[1], bg2 = V.cam.bg[2];
 
-    const uint2 rg = ranges[tile];
+    const uint2 rg = a.ranges[tile];
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
     const float bx0 = (float)(tx * TW + bx) + 0.5f, bx1 = bx0 + 7.0f;
     const float by0 = (float)(ty * TH + by) + 0.5f, by1 = by0 + 7.0f;
@@ -81,12 +109,13 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(const Rec* __restrict__ 
     const float gbg = g0 * (T * bg0) + g1 * (T * bg1) + g2 * (T * bg2);
     float ga = 0.f;   // g . sum of rgb_j w_j over the blended j behind the current entry
 
-    if (tid == 0) s_max = 0u;
+    __syncthreads();   // the previous tile of a persistent workgroup is done with the shared state
+    if (tid == 0) sh.max_last = 0u;
     __syncthreads();
-    if (my_last) atomicMax(&s_max, my_last);
+    if (my_last) atomicMax(&sh.max_last, my_last);
     __syncthreads();
     // never walk past the tile's list, whatever n_contrib holds
-    const uint32_t max_last = min(s_max, rg.y - rg.x);
+    const uint32_t max_last = min(sh.max_last, rg.y - rg.x);
 
     // the wave never needs entries at or beyond its pixels' last contributor
     uint32_t wave_last = my_last;
@@ -190,34 +219,85 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(const Rec* __restrict__ 
     }
 }
 
+template <int TW, int TH, bool STORED>
+__global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
+    __shared__ BwdShared<TW * TH> sh;
+    bwd_tile<TW, TH, STORED>(a, blockIdx.x, sh);
+}
+
 template <int TW, int TH>
-void launch_t(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status, const Cam& cam,
-              const float* final_T, const uint32_t* n_contrib, const float* dimg, int64_t n, float* g2d,
-              const float2* state, hipStream_t st) {
-    const int ntx = (cam.W + TW - 1) / TW, nty = (cam.H + TH - 1) / TH;
-    const dim3 grid((unsigned)(ntx * nty)), block(TW * TH);
-    const uint2* rg = reinterpret_cast<const uint2*>(ranges);
-    if (state)
-        hipLaunchKernelGGL((k_render_bwd<TW, TH, true>), grid, block, 0, st, rec, vals, rg, status, cam.W, cam.H,
-                           ntx, cam.bg[0], cam.bg[1], cam.bg[2], final_T, n_contrib, dimg, n, g2d, state);
+__global__ __launch_bounds__(TW * TH) void k_render_bwd_persistent(BwdArgs a) {
+    __shared__ BwdShared<TW * TH> sh;
+    __shared__ uint32_t s_next;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_next = atomicAdd(a.queue, 1u);
+        __syncthreads();
+        const uint32_t q = s_next;
+        if (q >= a.n_tiles) break;
+        bwd_tile<TW, TH, false>(a, a.order ? a.order[q] : q, sh);
+    }
+}
+
+template <int TW, int TH>
+void launch_t(const BwdArgs& a, int persistent_grid, hipStream_t st) {
+    const dim3 block(TW * TH);
+    if (a.state)
+        hipLaunchKernelGGL((k_render_bwd<TW, TH, true>), dim3(a.n_tiles), block, 0, st, a);
+    else if (persistent_grid > 0)
+        hipLaunchKernelGGL((k_render_bwd_persistent<TW, TH>), dim3(persistent_grid), block, 0, st, a);
     else
-        hipLaunchKernelGGL((k_render_bwd<TW, TH, false>), grid, block, 0, st, rec, vals, rg, status, cam.W, cam.H,
-                           ntx, cam.bg[0], cam.bg[1], cam.bg[2], final_T, n_contrib, dimg, n, g2d, state);
+        hipLaunchKernelGGL((k_render_bwd<TW, TH, false>), dim3(a.n_tiles), block, 0, st, a);
 }
 
 }  // namespace
 
-void launch_render_bwd(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status,
-                       const Cam& cam, int tw, int th, const float* final_T, const uint32_t* n_contrib,
-                       const float* dimg, int64_t n, float* g2d, const float2* state, hipStream_t st) {
-#define GS_BWD(a, b) launch_t<a, b>(rec, vals, ranges, status, cam, final_T, n_contrib, dimg, n, g2d, state, st)
-    if (tw == 16 && th == 16) GS_BWD(16, 16);
-    else if (tw == 8 && th == 8) GS_BWD(8, 8);
-    else if (tw == 16 && th == 8) GS_BWD(16, 8);
-    else if (tw == 32 && th == 8) GS_BWD(32, 8);
-    else if (tw == 32 && th == 16) GS_BWD(32, 16);
-    else if (tw == 32 && th == 32) GS_BWD(32, 32);
+void launch_render_bwd(const RenderArgs& r, const float* final_T, const uint32_t* n_contrib, const float* dimg,
+                       int64_t nslots, float* g2d, const float2* state, hipStream_t st) {
+    if (r.n_tiles == 0) return;
+    BwdArgs a;
+    a.rec = r.rec;
+    a.vals = r.vals;
+    a.ranges = reinterpret_cast<const uint2*>(r.ranges);
+    a.status = r.status;
+    a.views = r.views;
+    a.final_T = final_T;
+    a.n_contrib = n_contrib;
+    a.dimg = dimg;
+    a.n = nslots;
+    a.g2d = g2d;
+    a.state = state;
+    a.queue = r.queue;
+    a.order = r.order;
+    a.n_tiles = r.n_tiles;
+    const int pg = (r.queue && !state) ? r.persistent_grid : 0;
+    if (pg > 0) launch_fill_u32(r.queue, 0u, 1, st);
+#define GS_BWD(x, y) launch_t<x, y>(a, pg, st)
+    if (r.tw == 16 && r.th == 16) GS_BWD(16, 16);
+    else if (r.tw == 8 && r.th == 8) GS_BWD(8, 8);
+    else if (r.tw == 16 && r.th == 8) GS_BWD(16, 8);
+    else if (r.tw == 32 && r.th == 8) GS_BWD(32, 8);
+    else if (r.tw == 32 && r.th == 16) GS_BWD(32, 16);
+    else if (r.tw == 32 && r.th == 32) GS_BWD(32, 32);
 #undef GS_BWD
+}
+
+int render_persistent_grid_bwd(int tw, int th) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    hipError_t e = hipErrorInvalidValue;
+#define GS_OCC(x, y) \
+    if (tw == x && th == y) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_render_bwd_persistent<x, y>, x * y, 0)
+    GS_OCC(16, 16);
+    GS_OCC(8, 8);
+    GS_OCC(16, 8);
+    GS_OCC(32, 8);
+    GS_OCC(32, 16);
+    GS_OCC(32, 32);
+#undef GS_OCC
+    if (e != hipSuccess || per < 1) per = 1;
+    return cus * per;
 }
 
 }  // namespace gs

@@ -8,7 +8,8 @@
 //   below 1e-4; otherwise C += colour alpha T and T *= (1 - alpha).
 // Output pixel = C + T bg.
 //
-// Launch: one workgroup per tile, one lane per pixel.  Every wave covers an
+// Launch: one workgroup per tile (or a persistent grid pulling tiles from
+// a queue, longest list first), one lane per pixel.  Every wave covers an
 // 8x8 block of the tile, so that a small Gaussian touches few waves.
 // Batches of records are staged in LDS; for each 64 of them the wave tests
 // one per lane against its block's pixel centres and walks, in list order,
@@ -16,7 +17,8 @@
 // scalar bit operations).  Skipping the others never changes a result: such
 // a Gaussian has alpha < 1/255 at every pixel of the block.  A wave leaves
 // the tile once all its pixels have stopped, the workgroup once all waves
-// have.
+// have.  Tiles of several views are numbered consecutively; a tile finds
+// its view (camera, image planes) in the view table.
 #include "kernels.h"
 
 namespace gs {
@@ -33,30 +35,44 @@ namespace {
 // skipped; the stored-state backward reads it instead of recomputing.
 constexpr int kPlain = 0, kStats = 1, kStore = 2;
 
+struct FwdArgs {
+    const Rec* rec;
+    const uint32_t* vals;
+    const uint2* ranges;
+    const int32_t* status;
+    ViewTab views;
+    float* image;
+    float* final_T;
+    uint32_t* n_contrib;
+    unsigned long long* stats;
+    float2* state;
+    uint32_t* queue;        // persistent launch: next queue position (zeroed before launch)
+    const uint32_t* order;  // persistent launch: tiles in processing order (NULL = 0, 1, ...)
+    uint32_t n_tiles;
+};
+
 template <int TW, int TH, int MODE>
-__global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ rec, const uint32_t* __restrict__ vals,
-                                                        const uint2* __restrict__ ranges,
-                                                        const int32_t* __restrict__ status, int W, int H, int ntx,
-                                                        float bg0, float bg1, float bg2, float* __restrict__ image,
-                                                        float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
-                                                        unsigned long long* __restrict__ stats,
-                                                        float2* __restrict__ state) {
+__device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, Staged* s) {
     constexpr int NT = TW * TH;
     constexpr bool STATS = MODE == kStats;
     constexpr int WX = TW / 8;
-    __shared__ Staged s[NT];
 
+    const View V = view_at(a.views, find_view(a.views, tile));
+    const int W = V.cam.W, H = V.cam.H;
+    const int local = (int)(tile - V.tile_base);
+    const int tx = local % V.ntx, ty = local / V.ntx;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    const int tile = blockIdx.x;
-    const int tx = tile % ntx, ty = tile / ntx;
     const int bx = (wv % WX) * 8, by = (wv / WX) * 8;
     const int lx = bx + (lane & 7), ly = by + (lane >> 3);
     const int px = tx * TW + lx, py = ty * TH + ly;
     const bool inside = px < W && py < H;
     const int64_t npix = (int64_t)W * H;
     const int64_t off = (int64_t)py * W + px;
+    float* image = a.image + V.img_base;
+    float* final_T = a.final_T + V.pix_base;
+    uint32_t* n_contrib = a.n_contrib + V.pix_base;
 
-    if (*status != 0) {
+    if (*a.status != 0) {
         if (!STATS && inside) {
             const float nan = __builtin_nanf("");
             image[off] = nan;
@@ -68,7 +84,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ 
         return;
     }
 
-    const uint2 rg = ranges[tile];
+    const uint2 rg = a.ranges[tile];
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
     const float bx0 = (float)(tx * TW + bx) + 0.5f, bx1 = bx0 + 7.0f;
     const float by0 = (float)(ty * TH + by) + 0.5f, by1 = by0 + 7.0f;
@@ -81,7 +97,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ 
     for (uint32_t b0 = rg.x; b0 < rg.y; b0 += NT) {
         if (__syncthreads_count(done) == NT) break;
         const uint32_t j = b0 + tid;
-        if (j < rg.y) s[tid] = stage_rec(rec[vals[j]]);
+        if (j < rg.y) s[tid] = stage_rec(a.rec[a.vals[j]]);
         __syncthreads();
         const int nb = (int)min((uint32_t)NT, rg.y - b0);
         bool live = __ballot(!done) != 0ull;
@@ -98,7 +114,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ 
                 if (!done) {
                     const Eval e = eval_pair(g, fx, fy);
                     if (MODE == kStore)
-                        state[(int64_t)(b0 + (uint32_t)kk) * NT + tid] =
+                        a.state[(int64_t)(b0 + (uint32_t)kk) * NT + tid] =
                             make_float2(e.capped && e.alpha > 0.0f ? -e.alpha : e.alpha, T);
                     if (STATS) ++n_eval;
                     if (e.alpha > 0.0f) {
@@ -125,34 +141,49 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const Rec* __restrict__ 
         }
     }
     if (STATS) {
-        atomicAdd(&stats[0], n_eval);
-        atomicAdd(&stats[1], n_supp);
-        atomicAdd(&stats[2], n_blend);
+        atomicAdd(&a.stats[0], n_eval);
+        atomicAdd(&a.stats[1], n_supp);
+        atomicAdd(&a.stats[2], n_blend);
     } else if (inside) {
-        image[off] = __builtin_fmaf(T, bg0, c0);
-        image[npix + off] = __builtin_fmaf(T, bg1, c1);
-        image[2 * npix + off] = __builtin_fmaf(T, bg2, c2);
+        image[off] = __builtin_fmaf(T, V.cam.bg[0], c0);
+        image[npix + off] = __builtin_fmaf(T, V.cam.bg[1], c1);
+        image[2 * npix + off] = __builtin_fmaf(T, V.cam.bg[2], c2);
         final_T[off] = T;
         n_contrib[off] = last;
     }
 }
 
+template <int TW, int TH, int MODE>
+__global__ __launch_bounds__(TW * TH) void k_render_fwd(FwdArgs a) {
+    __shared__ Staged s[TW * TH];
+    fwd_tile<TW, TH, MODE>(a, blockIdx.x, s);
+}
+
 template <int TW, int TH>
-void launch_t(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status, const Cam& cam,
-              float* image, float* final_T, uint32_t* n_contrib, unsigned long long* stats, float2* state,
-              hipStream_t st) {
-    const int ntx = (cam.W + TW - 1) / TW, nty = (cam.H + TH - 1) / TH;
-    const dim3 grid((unsigned)(ntx * nty)), block(TW * TH);
-    const uint2* rg = reinterpret_cast<const uint2*>(ranges);
-    if (stats)
-        hipLaunchKernelGGL((k_render_fwd<TW, TH, kStats>), grid, block, 0, st, rec, vals, rg, status, cam.W, cam.H,
-                           ntx, cam.bg[0], cam.bg[1], cam.bg[2], image, final_T, n_contrib, stats, state);
-    else if (state)
-        hipLaunchKernelGGL((k_render_fwd<TW, TH, kStore>), grid, block, 0, st, rec, vals, rg, status, cam.W, cam.H,
-                           ntx, cam.bg[0], cam.bg[1], cam.bg[2], image, final_T, n_contrib, stats, state);
+__global__ __launch_bounds__(TW * TH) void k_render_fwd_persistent(FwdArgs a) {
+    __shared__ Staged s[TW * TH];
+    __shared__ uint32_t s_next;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_next = atomicAdd(a.queue, 1u);
+        __syncthreads();
+        const uint32_t q = s_next;
+        if (q >= a.n_tiles) break;
+        fwd_tile<TW, TH, kPlain>(a, a.order ? a.order[q] : q, s);
+    }
+}
+
+template <int TW, int TH>
+void launch_t(const FwdArgs& a, int persistent_grid, hipStream_t st) {
+    const dim3 block(TW * TH);
+    if (a.stats)
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, kStats>), dim3(a.n_tiles), block, 0, st, a);
+    else if (a.state)
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, kStore>), dim3(a.n_tiles), block, 0, st, a);
+    else if (persistent_grid > 0)
+        hipLaunchKernelGGL((k_render_fwd_persistent<TW, TH>), dim3(persistent_grid), block, 0, st, a);
     else
-        hipLaunchKernelGGL((k_render_fwd<TW, TH, kPlain>), grid, block, 0, st, rec, vals, rg, status, cam.W, cam.H,
-                           ntx, cam.bg[0], cam.bg[1], cam.bg[2], image, final_T, n_contrib, stats, state);
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, kPlain>), dim3(a.n_tiles), block, 0, st, a);
 }
 
 }  // namespace
@@ -162,17 +193,58 @@ bool render_tile_supported(int tw, int th) {
            (tw == 32 && th == 16) || (tw == 32 && th == 32);
 }
 
-void launch_render_fwd(const Rec* rec, const uint32_t* vals, const uint32_t* ranges, const int32_t* status,
-                       const Cam& cam, int tw, int th, float* image, float* final_T, uint32_t* n_contrib,
+void launch_render_fwd(const RenderArgs& r, float* image, float* final_T, uint32_t* n_contrib,
                        unsigned long long* stats, float2* state, hipStream_t st) {
-#define GS_FWD(a, b) launch_t<a, b>(rec, vals, ranges, status, cam, image, final_T, n_contrib, stats, state, st)
-    if (tw == 16 && th == 16) GS_FWD(16, 16);
-    else if (tw == 8 && th == 8) GS_FWD(8, 8);
-    else if (tw == 16 && th == 8) GS_FWD(16, 8);
-    else if (tw == 32 && th == 8) GS_FWD(32, 8);
-    else if (tw == 32 && th == 16) GS_FWD(32, 16);
-    else if (tw == 32 && th == 32) GS_FWD(32, 32);
+    if (r.n_tiles == 0) return;
+    FwdArgs a;
+    a.rec = r.rec;
+    a.vals = r.vals;
+    a.ranges = reinterpret_cast<const uint2*>(r.ranges);
+    a.status = r.status;
+    a.views = r.views;
+    a.image = image;
+    a.final_T = final_T;
+    a.n_contrib = n_contrib;
+    a.stats = stats;
+    a.state = state;
+    a.queue = r.queue;
+    a.order = r.order;
+    a.n_tiles = r.n_tiles;
+    const int pg = (r.queue && !stats && !state) ? r.persistent_grid : 0;
+    if (pg > 0) launch_fill_u32(r.queue, 0u, 1, st);
+#define GS_FWD(x, y) launch_t<x, y>(a, pg, st)
+    if (r.tw == 16 && r.th == 16) GS_FWD(16, 16);
+    else if (r.tw == 8 && r.th == 8) GS_FWD(8, 8);
+    else if (r.tw == 16 && r.th == 8) GS_FWD(16, 8);
+    else if (r.tw == 32 && r.th == 8) GS_FWD(32, 8);
+    else if (r.tw == 32 && r.th == 16) GS_FWD(32, 16);
+    else if (r.tw == 32 && r.th == 32) GS_FWD(32, 32);
 #undef GS_FWD
+}
+
+int render_persistent_grid_bwd(int tw, int th);
+int render_persistent_grid_fwd(int tw, int th);
+
+int render_persistent_grid(int tw, int th, bool backward) {
+    return backward ? render_persistent_grid_bwd(tw, th) : render_persistent_grid_fwd(tw, th);
+}
+
+int render_persistent_grid_fwd(int tw, int th) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    hipError_t e = hipErrorInvalidValue;
+#define GS_OCC(x, y) \
+    if (tw == x && th == y) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_render_fwd_persistent<x, y>, x * y, 0)
+    GS_OCC(16, 16);
+    GS_OCC(8, 8);
+    GS_OCC(16, 8);
+    GS_OCC(32, 8);
+    GS_OCC(32, 16);
+    GS_OCC(32, 32);
+#undef GS_OCC
+    if (e != hipSuccess || per < 1) per = 1;
+    return cus * per;
 }
 
 }  // namespace gs
