@@ -244,7 +244,8 @@ def merged_city(grid=10, cell_m=100.0, per_cell=200_000, seed=5, sh_degree=3):
     """A grid of city cells, each generated on its own, merged by keeping
     every cell's Gaussians that fall inside its un-expanded footprint and
     concatenating the cells.  Returns the merged set and per-cell AABBs
-    [n_cells][6] = (xmin, ymin, zmin, xmax, ymax, zmax) plus cell offsets."""
+    [n_cells][6] = (xmin, ymin, zmin, xmax, ymax, zmax), each bounding the
+    supports of its cell's Gaussians, plus cell offsets."""
     parts = []
     aabbs = []
     offsets = [0]
@@ -259,8 +260,10 @@ def merged_city(grid=10, cell_m=100.0, per_cell=200_000, seed=5, sh_degree=3):
                       (g.mean[2] >= cz - cell_m / 2) & (g.mean[2] < cz + cell_m / 2))
             g = g.subset(np.nonzero(inside)[0])
             parts.append(g)
-            lo = g.mean.min(axis=1) - 3.0 * g.scale.max()
-            hi = g.mean.max(axis=1) + 3.0 * g.scale.max()
+            # bound every Gaussian's alpha >= 1/255 support (at most
+            # sqrt(2 ln 255) = 3.33 standard deviations from its mean)
+            lo = g.mean.min(axis=1) - 3.5 * g.scale.max()
+            hi = g.mean.max(axis=1) + 3.5 * g.scale.max()
             aabbs.append(np.concatenate([lo, hi]))
             offsets.append(offsets[-1] + g.n)
     merged = Gaussians(np.concatenate([p.mean for p in parts], axis=1),

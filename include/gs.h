@@ -272,6 +272,71 @@ gs_status gs_batch_info(const gs_batch *b, gs_batch_stats *info);
 gs_status gs_batch_status(gs_batch *b, gs_stream stream, int32_t *status, uint32_t *pairs);
 void gs_batch_destroy(gs_batch *b);
 
+/* ---- Serving the merged scene ---------------------------------------------
+ * Sections 4.3 and 5: the merged scene is rendered in real time from novel
+ * views.  A gs_server keeps the scene resident (the caller's device planes,
+ * not copied: they must outlive the server) and renders requests with
+ * continuous batching: a worker thread forms a batch from the head of the
+ * request queue whenever one of its pipelines (stream + workspace) is free,
+ * admitting requests in arrival order while the batch's Gaussian slots,
+ * pixels, tiles and estimated (Gaussian, tile) pairs fit the pipeline's share
+ * of the memory budget; each batch is one projection, one joint sort and one
+ * blend over all its views (mixed resolutions), and batches on different
+ * pipelines overlap on the device.  Cells are culled per request on the host
+ * against the view frustum.  A request's image does not depend on what it
+ * was batched with.
+ *
+ * gs_serve_create: scene (device SoA planes), cell_aabbs (host, n_cells x 6
+ * floats xmin, ymin, zmin, xmax, ymax, zmax, each bounding the alpha >= 1/255
+ * support of every Gaussian of the cell, e.g. means +- 3.5 x the largest
+ * scale), cell_offsets (host, n_cells + 1 ascending Gaussian indices, cell c
+ * owning [cell_offsets[c], cell_offsets[c+1]), first 0 and last n).  Starts
+ * the worker and completion threads and allocates the pipelines' workspace
+ * (the budget split between them).  cfg NULL = defaults below.
+ * gs_serve_submit: queue a render of `cam` into out_image (device [3][H][W],
+ * caller-owned, untouched until the request completes); returns at once
+ * with a ticket.  GS_ERR_BUSY when the queue is full, GS_ERR_INVALID when
+ * the request alone can never fit a pipeline.  Thread-safe.
+ * gs_serve_wait: block until the ticket's request completes (timeout_ms < 0
+ * waits forever; GS_ERR_TIMEOUT otherwise) and fill its statistics (host
+ * monotonic clock, ns).  Each ticket is waited for once.  The request's
+ * status is returned (GS_ERR_CAPACITY if even alone its pairs overflowed).
+ * gs_serve_destroy: finish queued and running requests, stop the threads,
+ * free the workspace. */
+typedef struct gs_server gs_server;
+typedef struct {
+    int64_t memory_budget;      /* device bytes for all pipelines' workspace (8 GiB) */
+    int32_t pipelines;          /* batches in flight at once (2) */
+    int32_t max_views;          /* requests per batch (8) */
+    int32_t max_queue;          /* queued requests before GS_ERR_BUSY (1024) */
+    int32_t tile_w, tile_h;     /* (16, 16) */
+    int64_t max_pixels;         /* pixels of one batch, cap (4 x 3840 x 2160) */
+    float widen_px;             /* frustum margin of the cell culling, pixels (64) */
+    double initial_pairs_per_slot; /* admission estimate of pairs per Gaussian before any batch (3.0) */
+    int32_t start_paused;       /* 1 = form no batch until gs_serve_resume (0) */
+    int64_t max_pairs;          /* pair capacity per pipeline (0 = from the budget) */
+} gs_serve_config;
+typedef struct {
+    int64_t t_arrive_ns, t_start_ns, t_done_ns;   /* submit, batch launch, completion */
+    int32_t status, batch_views, attempts, cells;
+    int64_t gaussians;          /* Gaussians of the cells that survived culling */
+} gs_request_stats;
+typedef struct {
+    int64_t batches, requeues, max_batch_views, queued;
+    int32_t pipelines;
+    int64_t slots_cap, pairs_cap, pixels_cap;
+    double pairs_per_slot;      /* current admission estimate */
+} gs_serve_stats;
+
+gs_status gs_serve_create(const gs_gaussians *scene, const float *cell_aabbs, const int64_t *cell_offsets,
+                          int32_t n_cells, const gs_serve_config *cfg, gs_server **out);
+gs_status gs_serve_submit(gs_server *sv, const gs_camera *cam, float *out_image, uint64_t *ticket);
+gs_status gs_serve_wait(gs_server *sv, uint64_t ticket, int32_t timeout_ms, gs_request_stats *st);
+gs_status gs_serve_info(gs_server *sv, gs_serve_stats *info);
+/* Let a server created with start_paused form batches. */
+gs_status gs_serve_resume(gs_server *sv);
+void gs_serve_destroy(gs_server *sv);
+
 /* Work counters of the forward blend of one view (observability; not on
  * the training path): runs the forward walk without writing an image and
  * stores into counters (device, 4 x uint64, overwritten):

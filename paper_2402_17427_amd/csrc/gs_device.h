@@ -67,6 +67,7 @@ struct View {
     uint32_t tile_base;    // first global tile id of the view
     int64_t img_base;      // offset (floats) of the view's [3][H][W] image
     int64_t pix_base;      // offset of the view's [H][W] planes (final_T, n_contrib, dL/dimage is at img_base)
+    float* out_image;      // when set, the forward writes this view's image here instead
 };
 
 struct Job {

@@ -68,7 +68,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, Staged
     const bool inside = px < W && py < H;
     const int64_t npix = (int64_t)W * H;
     const int64_t off = (int64_t)py * W + px;
-    float* image = a.image + V.img_base;
+    float* image = V.out_image ? V.out_image : a.image + V.img_base;
     float* final_T = a.final_T + V.pix_base;
     uint32_t* n_contrib = a.n_contrib + V.pix_base;
 
