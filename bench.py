@@ -57,6 +57,11 @@ def parse():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched-cells and serving measurements")
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=(100.0, 400.0))
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-grid", type=int, default=10, help="merged scene: grid x grid cells of 200k Gaussians")
+    ap.add_argument("--batch-steps", type=int, default=10)
     return ap.parse_args()
 
 
@@ -79,6 +84,195 @@ def cpu_baseline(g, cam, stride):
             "kind": "oracle",
             "sample": f"fwd+bwd of {px.size} pixels (every {stride}th row and column of the {cam.width}x"
                       f"{cam.height} view, 1M Gaussians) in {dt:.1f} s, per-view projection and sort included"}
+
+
+def bench_batched(args, torch, scenes, raster):
+    """Eight cells of uneven sizes (0.3M .. 2.5M Gaussians, SH degree 3),
+    one 1600x1066 aerial view each: one training step (render, L1 loss,
+    backward) of all cells as the autotuned, graph-captured batched step,
+    against the sum of the eight plain single-view steps."""
+    import numpy as np
+    from paper_2402_17427_amd.batch import BatchStep
+    cells = scenes.config4()
+    dgs, cams, tgts = [], [], []
+    for i, (g, cam) in enumerate(cells):
+        dgs.append(raster.DeviceGaussians.from_host(g))
+        cams.append(cam)
+        rng = np.random.default_rng(4000 + i)
+        tgts.append(torch.as_tensor(rng.uniform(0, 1, (3, cam.height, cam.width)).astype(np.float32)).cuda())
+    del cells
+    print("[bench] batched: cells on the device", file=sys.stderr, flush=True)
+    b = BatchStep(dgs, cams, tgts, autotune=True)
+    info = b.info()
+    for _ in range(3):
+        b.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        b.step()
+    torch.cuda.synchronize()
+    ms_batch = (time.perf_counter() - t0) / args.batch_steps * 1e3
+    st, pairs = b.status()
+    b.close()
+    # plain path: one view at a time through the single-view calls
+    frames = []
+    for dg, cam in zip(dgs, cams):
+        f = raster.Frame(dg.n, dg.sh_degree, cam)
+        f.ensure_capacity(dg)
+        frames.append(f)
+    dimgs = [torch.full((3, c.height, c.width), 1e-7, device="cuda") for c in cams]
+
+    def plain_step():
+        for f, dg, d in zip(frames, dgs, dimgs):
+            f.project(dg)
+            f.bin_sort()
+            f.render_fwd()
+            f.render_bwd(dg, d)
+
+    for _ in range(2):
+        plain_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        plain_step()
+    torch.cuda.synchronize()
+    ms_plain = (time.perf_counter() - t0) / args.batch_steps * 1e3
+    npix = sum(c.width * c.height for c in cams)
+    return {"workload": "8 cells (0.3M-2.5M Gaussians, 9.9M total, SH3), one 1600x1066 view each, "
+                        "training step = render + L1 + backward",
+            "ms_per_step": round(ms_batch, 3), "mpix_per_s": round(npix / (ms_batch * 1e-3) / 1e6, 1),
+            "plain_ms_per_step": round(ms_plain, 3),
+            "plain_mpix_per_s": round(npix / (ms_plain * 1e-3) / 1e6, 1),
+            "speedup_vs_plain": round(ms_plain / ms_batch, 3), "status": st, "pairs": pairs[0],
+            "autotune": {"tile": info["tile"], "persistent": info["persistent"], "graph": info["use_graph"],
+                         "candidates_ms": [(c["tile"], c["persistent"], round(c["ms"], 3))
+                                           for c in info["candidates"]]}}
+
+
+def _percentiles(lat):
+    import numpy as np
+    a = np.asarray(lat)
+    return round(float(np.percentile(a, 50)), 3), round(float(np.percentile(a, 99)), 3)
+
+
+def bench_serving(args, torch, scenes, raster):
+    """The merged scene (grid x grid city cells of 200k Gaussians, SH degree
+    3) resident in HBM; Poisson arrivals of requests with resolutions drawn
+    from {640x480, 1280x720, 1920x1080, 3840x2160} over the scene at 80-200 m.
+    Latency = completion - arrival on the host clock.  Compared on the same
+    trace: the continuous-batching server, the same server without batching
+    (one view per batch, one pipeline), and the plain single-view calls on
+    the whole scene in arrival order."""
+    import threading
+    from paper_2402_17427_amd import _native as N
+    from paper_2402_17427_amd.serve import Server
+    g, boxes, offs = scenes.merged_city(grid=args.serve_grid, cell_m=100.0, per_cell=200_000, seed=5)
+    ext = args.serve_grid * 100.0
+    dg = raster.DeviceGaussians.from_host(g)
+    n_total = g.n
+    del g
+    print(f"[bench] serving: {n_total} Gaussians resident", file=sys.stderr, flush=True)
+    pools = {}
+
+    def get_buf(cam):
+        key = (cam.height, cam.width)
+        lst = pools.setdefault(key, [])
+        return lst.pop() if lst else torch.empty((3, cam.height, cam.width), device="cuda")
+
+    def run_server(trace, **kw):
+        sv = Server(dg, boxes, offs, **kw)
+        torch.cuda.synchronize()
+        res = [None] * len(trace)
+        lock = threading.Lock()
+        pending = []
+        done_flag = threading.Event()
+
+        def waiter():
+            k = 0
+            while True:
+                with lock:
+                    item = pending[k] if k < len(pending) else None
+                if item is None:
+                    if done_flag.is_set() and k >= len(pending):
+                        return
+                    time.sleep(0.0002)
+                    continue
+                i, t, buf = item
+                res[i] = sv.wait(t)
+                with lock:
+                    pools[(buf.shape[1], buf.shape[2])].append(buf)
+                k += 1
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        for i, (ta, cam) in enumerate(trace):
+            dt = t0 + ta - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            with lock:
+                buf = get_buf(cam)
+            t = sv.submit(cam, buf)
+            with lock:
+                pending.append((i, t, buf))
+        done_flag.set()
+        th.join()
+        wall = time.perf_counter() - t0
+        info = sv.info()
+        sv.close()
+        return res, wall, info
+
+    def run_plain(trace):
+        frames = {}
+        res = []
+        t0 = time.perf_counter()
+        for ta, cam in trace:
+            now = time.perf_counter() - t0
+            if now < ta:
+                time.sleep(ta - now)
+            arrive = t0 + ta
+            key = (cam.width, cam.height)
+            f = frames.get(key)
+            if f is None:
+                f = raster.Frame(n_total, dg.sh_degree, cam, capacity=4 * n_total // 10, grads=False)
+                frames[key] = f
+            f.cam = cam
+            f.c_cam = N.make_camera(cam)
+            f.project(dg)
+            f.bin_sort()
+            f.render_fwd()
+            torch.cuda.synchronize()
+            if int(f.status.item()) != 0:
+                f.ensure_capacity(dg)
+                f.render_fwd()
+                torch.cuda.synchronize()
+            res.append(time.perf_counter() - arrive)
+        return res, time.perf_counter() - t0
+
+    out = {"workload": f"merged scene {n_total} Gaussians ({args.serve_grid}x{args.serve_grid} cells, SH3), "
+                       "requests uniform over {640x480, 1280x720, 1920x1080, 3840x2160}, 80-200 m, pitch -90..-30 deg",
+           "rates": []}
+    for k, rate in enumerate(args.serve_rates):
+        n = args.serve_requests
+        trace = scenes.serve_trace(n + 30, rate, seed=500 + k, extent_m=ext)
+        mpix = sum(c.width * c.height for _, c in trace[30:]) / 1e6
+        row = {"rate_hz": rate, "requests": n}
+        for name, kw in (("batched", dict(max_views=8, pipelines=2)), ("unbatched", dict(max_views=1, pipelines=1))):
+            res, wall, info = run_server(trace, **kw)
+            lat = [r["latency_ms"] for r in res[30:]]
+            p50, p99 = _percentiles(lat)
+            span = (max(r["t_done_ns"] for r in res[30:]) - min(r["t_arrive_ns"] for r in res[30:])) * 1e-9
+            row[name] = {"p50_ms": p50, "p99_ms": p99, "frames_per_s": round(n / span, 1),
+                         "mpix_per_s": round(mpix / span, 1), "batches": info["batches"],
+                         "max_batch_views": info["max_batch_views"], "requeues": info["requeues"]}
+            print(f"[bench] serving {rate} req/s {name}: p50 {p50} ms p99 {p99} ms", file=sys.stderr, flush=True)
+        lat, wall = run_plain(trace)
+        lat = [x * 1e3 for x in lat[30:]]
+        p50, p99 = _percentiles(lat)
+        row["plain_fifo"] = {"p50_ms": p50, "p99_ms": p99}
+        print(f"[bench] serving {rate} req/s plain: p50 {p50} ms p99 {p99} ms", file=sys.stderr, flush=True)
+        out["rates"].append(row)
+    return out
 
 
 def main():
@@ -147,7 +341,7 @@ def main():
                 "work_lane_ops": int(work), "avg_ms": round(dom_ms, 4)}
 
     out = {
-        "metric": "fwd+bwd Mpix/s at 1M Gaussians 1080p",
+        "metric": "fwd+bwd Mpix/s at 1M Gaussians 1080p; serve p50/p99 ms vs plain path",
         "value": round(value, 2),
         "unit": "Mpix/s",
         "n_gpus": 1,
@@ -168,6 +362,16 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(g, cam, args.cpu_stride)
+    if not args.no_forms:
+        del frame, dg
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batched(args, torch, scenes, raster)
+        torch.cuda.empty_cache()
+        serving = bench_serving(args, torch, scenes, raster)
+        out["serving"] = serving
+        r0 = serving["rates"][0]
+        out["serve_p50_p99_ms"] = {"rate_hz": r0["rate_hz"], "batched": [r0["batched"]["p50_ms"], r0["batched"]["p99_ms"]],
+                                   "plain_fifo": [r0["plain_fifo"]["p50_ms"], r0["plain_fifo"]["p99_ms"]]}
     print(json.dumps(out))
 
 

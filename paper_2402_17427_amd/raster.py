@@ -84,7 +84,7 @@ class Frame:
     `ensure_capacity`/`check_status`, which read the device status)."""
 
     def __init__(self, n: int, sh_degree: int, cam, tile=(16, 16), capacity: int | None = None,
-                 device="cuda"):
+                 device="cuda", grads: bool = True):
         self.n, self.sh_degree, self.device = int(n), int(sh_degree), device
         self.cam = cam
         self.c_cam = N.make_camera(cam)
@@ -107,12 +107,14 @@ class Frame:
         self.final_T = torch.empty((self.H, self.W), dtype=torch.float32, device=device)
         self.n_contrib = torch.empty((self.H, self.W), dtype=torch.int32, device=device)
         K = SH_DIM[self.sh_degree]
-        self.g_mean = torch.empty((3, n1), dtype=torch.float32, device=device)
-        self.g_scale = torch.empty((3, n1), dtype=torch.float32, device=device)
-        self.g_quat = torch.empty((4, n1), dtype=torch.float32, device=device)
-        self.g_opacity = torch.empty(n1, dtype=torch.float32, device=device)
-        self.g_sh = torch.empty((3 * K, n1), dtype=torch.float32, device=device)
-        self.grad2d = torch.empty((9, n1), dtype=torch.float32, device=device)
+        ng = n1 if grads else 1      # forward-only frames keep no gradient planes
+        self.g_mean = torch.empty((3, ng), dtype=torch.float32, device=device)
+        self.g_scale = torch.empty((3, ng), dtype=torch.float32, device=device)
+        self.g_quat = torch.empty((4, ng), dtype=torch.float32, device=device)
+        self.g_opacity = torch.empty(ng, dtype=torch.float32, device=device)
+        self.g_sh = torch.empty((3 * K, ng), dtype=torch.float32, device=device)
+        self.grad2d = torch.empty((9, ng), dtype=torch.float32, device=device)
+        self.has_grads = grads
         self.capacity = 0
         self.keys = self.vals = self.ws = None
         self.set_capacity(capacity if capacity is not None else max(2 * self.n, 1 << 16))
@@ -166,6 +168,7 @@ class Frame:
                C.c_void_p(stream_handle(stream)))
 
     def render_bwd(self, g: DeviceGaussians, dimg: torch.Tensor, stream=None):
+        assert self.has_grads, "frame was created without gradient buffers"
         assert dimg.shape == (3, self.H, self.W) and dimg.dtype == torch.float32 and dimg.is_contiguous()
         N.call("gs_render_bwd", C.byref(g.c_struct()), C.byref(self.c_cam), C.byref(self.c_opts),
                C.byref(self.c_proj()), C.byref(self.c_bins()), _ptr(self.final_T), _ptr(self.n_contrib),
