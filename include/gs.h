@@ -110,8 +110,8 @@ typedef struct {
  *   rec   n x 48-byte records, 16-byte aligned: { double u, v (pixel-space
  *         centre); float A, B, C (conic = inverse 2D covariance, with
  *         power = -0.5 (A dx^2 + C dy^2) - B dx dy); float opacity;
- *         float r, g, b (colour); uint32 ext = two binary16 half-extents
- *         (ex, ey) of the alpha >= 1/255 support, rounded up }.
+ *         float r, g, b (colour); float thr = -log2(255 opacity), the
+ *         base-2 exponent above which alpha >= 1/255 }.
  *   depth n floats: camera-space z (the sort key).
  *   rect  n x 4 uint16, 8-byte aligned: tile rectangle x0, y0, x1, y1
  *         (x1, y1 exclusive).

@@ -30,8 +30,8 @@ struct alignas(16) Rec {
     double u, v;        // pixel-space centre
     float A, B, C, o;   // conic (inverse 2D covariance) and opacity
     float r, g, b;      // colour
-    uint32_t ext;       // half-extents (ex, ey) of the alpha >= 1/255
-                        // support as two binary16 values rounded up
+    float thr;          // -log2(255 o): alpha >= 1/255 exactly where the
+                        // base-2 exponent of the Gaussian is >= thr
 };
 static_assert(sizeof(Rec) == 48, "record layout");
 
@@ -128,7 +128,7 @@ __device__ __forceinline__ View view_at(const ViewTab& t, int v) { return t.dev 
 struct Staged {
     float4 geo;   // hi_u, lo_u, hi_v, lo_v
     float4 coef;  // ca, cb, cc, o
-    float4 col;   // r, g, b, half-extents (ex, ey) as binary16 bits
+    float4 col;   // r, g, b, thr
 };
 
 __device__ __forceinline__ Staged stage_rec(const Rec& r) {
@@ -136,7 +136,7 @@ __device__ __forceinline__ Staged stage_rec(const Rec& r) {
     const float hu = (float)r.u, hv = (float)r.v;
     s.geo = make_float4(hu, (float)(r.u - (double)hu), hv, (float)(r.v - (double)hv));
     s.coef = make_float4(r.A * (-0.5f * kLog2e), r.B * (-kLog2e), r.C * (-0.5f * kLog2e), r.o);
-    s.col = make_float4(r.r, r.g, r.b, __uint_as_float(r.ext));
+    s.col = make_float4(r.r, r.g, r.b, r.thr);
     return s;
 }
 
@@ -160,13 +160,39 @@ __device__ __forceinline__ Eval eval_pair(const Staged& s, float x, float y) {
     return e;
 }
 
-// Can the staged Gaussian reach alpha >= 1/255 at any pixel centre in the
-// box [x0, x1] x [y0, y1] (image coordinates)?  Conservative: the
-// half-extents are rounded up and get a margin.
+// Can the staged Gaussian reach alpha >= 1/255 at some point of the
+// rectangle [x0, x1] x [y0, y1] (image coordinates; the rectangle spanned by
+// a block's pixel centres)?  The base-2 exponent q(d) = ca dx^2 + cb dx dy +
+// cc dy^2 is a concave quadratic of the offset d; its maximum over the
+// rectangle is at the centre when the centre lies inside, else on an edge,
+// where it is the clamped vertex of a 1D parabola.  The answer is
+// conservative: the comparison with thr carries a margin far above the FP32
+// error of q, and the continuous rectangle contains every pixel centre.
 __device__ __forceinline__ bool box_overlaps(const Staged& s, float x0, float x1, float y0, float y1) {
-    const __half2 e = *reinterpret_cast<const __half2*>(&s.col.w);
-    const float ex = __half2float(__low2half(e)) + 0.01f, ey = __half2float(__high2half(e)) + 0.01f;
-    return s.geo.x + ex >= x0 && s.geo.x - ex <= x1 && s.geo.z + ey >= y0 && s.geo.z - ey <= y1;
+    const float u = s.geo.x + s.geo.y, v = s.geo.z + s.geo.w;
+    const float ax = x0 - u, bx = x1 - u, ay = y0 - v, by = y1 - v;
+    if (ax <= 0.f && bx >= 0.f && ay <= 0.f && by >= 0.f) return true;
+    const float ca = s.coef.x, cb = s.coef.y, cc = s.coef.z;
+    const float kx = -0.5f * cb * __builtin_amdgcn_rcpf(cc);   // vertex of q along x = X: y* = kx X
+    const float ky = -0.5f * cb * __builtin_amdgcn_rcpf(ca);   // vertex of q along y = Y: x* = ky Y
+    float m = -3.0e38f;
+#define GS_EDGE_X(X)                                               \
+    {                                                             \
+        const float y = fminf(fmaxf(kx * (X), ay), by);           \
+        m = fmaxf(m, ca * (X) * (X) + cb * (X) * y + cc * y * y); \
+    }
+#define GS_EDGE_Y(Y)                                               \
+    {                                                             \
+        const float x = fminf(fmaxf(ky * (Y), ax), bx);           \
+        m = fmaxf(m, ca * x * x + cb * x * (Y) + cc * (Y) * (Y)); \
+    }
+    GS_EDGE_X(ax)
+    GS_EDGE_X(bx)
+    GS_EDGE_Y(ay)
+    GS_EDGE_Y(by)
+#undef GS_EDGE_X
+#undef GS_EDGE_Y
+    return m >= s.col.w - (1e-3f + 1e-4f * fabsf(m));
 }
 
 // Sum of v over each 16-lane row of the wave (DPP), left in every lane of

@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project(JobTab jobs, ViewTab v
     out.A = out.B = out.C = 0.f;
     out.o = o;
     out.r = out.g = out.b = 0.f;
-    out.ext = 0u;
+    out.thr = 0.f;
     float z = 0.f;
     ushort4 rc = make_ushort4(0, 0, 0, 0);
     uint32_t count = 0;
@@ -248,11 +248,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project(JobTab jobs, ViewTab v
             // support: centres of pixels where alpha can reach 1/255
             const double r2 = 2.0 * log(255.0 * (double)o);
             const double ex = sqrt(r2 * g.a), ey = sqrt(r2 * g.c);
-            {
-                const float hx = fminf((float)ex * 1.0001f, 65504.f), hy = fminf((float)ey * 1.0001f, 65504.f);
-                const __half2 e2 = __halves2half2(__float2half_ru(hx), __float2half_ru(hy));
-                out.ext = *reinterpret_cast<const uint32_t*>(&e2);
-            }
+            out.thr = (float)(-log2(255.0 * (double)o));
             double x0 = ceil(out.u - ex - 0.5), x1 = floor(out.u + ex - 0.5);
             double y0 = ceil(out.v - ey - 0.5), y1 = floor(out.v + ey - 0.5);
             x0 = fmax(x0, 0.0);

@@ -25,9 +25,8 @@ def unpack_rec(rec_f32: np.ndarray, n: int) -> dict:
     raw = np.ascontiguousarray(rec_f32[: n * 12]).view(np.uint8).reshape(n, 48)
     uv = raw[:, 0:16].copy().view(np.float64).reshape(n, 2)
     f = raw[:, 16:48].copy().view(np.float32).reshape(n, 8)
-    ext = raw[:, 44:48].copy().view(np.float16).reshape(n, 2).astype(np.float64)
     return dict(uv=uv, conic=f[:, 0:3].astype(np.float64), opacity=f[:, 3].astype(np.float64),
-                rgb=f[:, 4:7].astype(np.float64), ext=ext)
+                rgb=f[:, 4:7].astype(np.float64), thr=f[:, 7].astype(np.float64))
 
 
 def grad_close(name, g, ref, rtol=GRAD_RTOL, floor=GRAD_FLOOR):

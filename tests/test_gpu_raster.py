@@ -89,8 +89,9 @@ def test_projection_matches_oracle(name):
     np.testing.assert_allclose(rec["conic"][v], ref["conic"][v], rtol=2e-6,
                                atol=2e-6 * np.abs(ref["conic"][v]).max())
     np.testing.assert_allclose(rec["rgb"][v], ref["rgb"][v], rtol=0, atol=2e-6)
-    # support half-extents are rounded up (never below the exact value)
-    assert (rec["ext"][v] >= ref["ext"][v] * (1 - 1e-7)).all()
+    # base-2 exponent threshold of the alpha >= 1/255 support: -log2(255 o)
+    np.testing.assert_allclose(rec["thr"][v], -np.log2(255.0 * g.opacity[v].astype(np.float64)), rtol=1e-6,
+                               atol=1e-6)
 
 
 @pytest.mark.parametrize("name,tile", [("config1", (16, 16)), ("city_ragged", (16, 16)), ("city_ragged", (8, 8)),
