@@ -22,9 +22,9 @@
 // from the back) and that lie before its pixels' last contributor.
 // Reduction: per walked entry, a wave first checks (ballot) whether any of
 // its 64 pixels contributed; only then are the nine gradient terms summed
-// over the wave with DPP (row sums, then the row broadcasts), added by one
-// lane into a per-tile LDS accumulator, and flushed with one global FP32
-// atomic per (Gaussian, term, tile) after the batch.
+// over each 16-lane row with DPP, added by the first lane of each row that
+// has a contributing pixel into a per-tile LDS accumulator, and flushed with
+// one global FP32 atomic per (Gaussian, term, tile) after the batch.
 #include "kernels.h"
 
 namespace gs {
@@ -139,68 +139,74 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
             const int k = c0k + lane;
             const bool ov = k < nb && (uint32_t)(lo + k) < wave_last && box_overlaps(s[k], bx0, bx1, by0, by1);
             uint64_t mask = __ballot(ov);
+            // the next walked record is loaded while the current one is processed
+            int nk = mask ? c0k + 63 - __builtin_clzll(mask) : 0;
+            Staged gn = s[nk];
             while (mask) {
-                const int bit = 63 - __builtin_clzll(mask);
-                mask &= ~(1ull << bit);
-                const int kk = c0k + bit;
-                const Staged g = s[kk];
-                const uint32_t pos = (uint32_t)(lo + kk);
-                float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f, v7 = 0.f, v8 = 0.f;
-                bool contrib = false;
-                if (pos < my_last) {
-                    Eval e;
-                    float Ti = 0.f;
-                    if (STORED) {
-                        const float2 st = state[(int64_t)(rg.x + pos) * NT + tid];
-                        e.alpha = fabsf(st.x);
-                        e.capped = st.x < 0.0f;
-                        e.dx = (fx - g.geo.x) - g.geo.y;
-                        e.dy = (fy - g.geo.z) - g.geo.w;
-                        e.G = e.alpha * __builtin_amdgcn_rcpf(g.coef.w);
-                        Ti = st.y;
-                    } else {
-                        e = eval_pair(g, fx, fy);
-                    }
-                    if (e.alpha > 0.0f) {
-                        contrib = true;
-                        const float iom = __builtin_amdgcn_rcpf(1.0f - e.alpha);
-                        if (!STORED) Ti = T * iom;
-                        const float w = e.alpha * Ti;
-                        const float grgb = g0 * g.col.x + g1 * g.col.y + g2 * g.col.z;
-                        v6 = g0 * w;
-                        v7 = g1 * w;
-                        v8 = g2 * w;
-                        // dL/dalpha = g . (rgb T_i - S_i / (1 - alpha)), S_i = suffix colour + T_final bg
-                        const float da = grgb * Ti - (ga + gbg) * iom;
-                        ga = __builtin_fmaf(grgb, w, ga);
-                        T = Ti;
-                        if (!e.capped) {
-                            v5 = da * e.G;
-                            const float dpow = da * e.alpha;
-                            const float hx = -0.5f * dpow * e.dx, hy = -0.5f * dpow * e.dy;
-                            v2 = hx * e.dx;
-                            v3 = 2.0f * hx * e.dy;
-                            v4 = hy * e.dy;
-                            // A = -2 ca / log2e, B = -cb / log2e, C = -2 cc / log2e
-                            const float q = -dpow * (1.0f / kLog2e);
-                            v0 = (2.0f * g.coef.x * e.dx + g.coef.y * e.dy) * q;
-                            v1 = (g.coef.y * e.dx + 2.0f * g.coef.z * e.dy) * q;
-                        }
-                    }
+                const int kk = nk;
+                const Staged g = gn;
+                mask &= ~(1ull << (kk - c0k));
+                if (mask) {
+                    nk = c0k + 63 - __builtin_clzll(mask);
+                    gn = s[nk];
                 }
-                if (__ballot(contrib) == 0ull) continue;
-                // sum over the wave (complete in lane 63), one LDS atomic per
-                // term into the tile's accumulator
-                v0 = wave_sum_to_lane63(v0); v1 = wave_sum_to_lane63(v1); v2 = wave_sum_to_lane63(v2);
-                v3 = wave_sum_to_lane63(v3); v4 = wave_sum_to_lane63(v4); v5 = wave_sum_to_lane63(v5);
-                v6 = wave_sum_to_lane63(v6); v7 = wave_sum_to_lane63(v7); v8 = wave_sum_to_lane63(v8);
-                if (lane == kWave - 1) {
+                const uint32_t pos = (uint32_t)(lo + kk);
+                const bool live = pos < my_last;
+                // Branch-free: a pair that does not contribute gets alpha 0,
+                // which leaves T and the suffix colour unchanged and makes
+                // every gradient term 0.
+                Eval e;
+                float Ts = T;
+                if (STORED) {
+                    const float2 st = live ? state[(int64_t)(rg.x + pos) * NT + tid] : make_float2(0.f, 0.f);
+                    e.alpha = fabsf(st.x);
+                    e.capped = st.x < 0.0f;
+                    e.dx = (fx - g.geo.x) - g.geo.y;
+                    e.dy = (fy - g.geo.z) - g.geo.w;
+                    e.G = e.alpha * __builtin_amdgcn_rcpf(g.coef.w);
+                    Ts = st.y;
+                } else {
+                    e = eval_pair(g, fx, fy);
+                }
+                const bool contrib = live && e.alpha > 0.0f;
+                const float a = contrib ? e.alpha : 0.0f;
+                const float iom = __builtin_amdgcn_rcpf(1.0f - a);
+                const float Ti = STORED ? (contrib ? Ts : T) : T * iom;
+                const float w = a * Ti;
+                const float grgb = g0 * g.col.x + g1 * g.col.y + g2 * g.col.z;
+                // dL/dalpha = g . (rgb T_i - S_i / (1 - alpha)), S_i = suffix colour + T_final bg;
+                // no gradient through a capped alpha
+                const float da0 = grgb * Ti - (ga + gbg) * iom;
+                const float da = (contrib && !e.capped) ? da0 : 0.0f;
+                ga = __builtin_fmaf(grgb, w, ga);
+                T = Ti;
+                float v6 = g0 * w, v7 = g1 * w, v8 = g2 * w;
+                float v5 = da * e.G;
+                // moments of dL/dpower over the pixel offsets; the centre and
+                // conic gradients are linear in them (formed per row below)
+                const float dpow = da * a;
+                const float mx = dpow * e.dx, my = dpow * e.dy;
+                float v0 = mx, v1 = my, v2 = mx * e.dx, v3 = mx * e.dy, v4 = my * e.dy;
+                const uint64_t cm = __ballot(contrib);
+                if (cm == 0ull) continue;
+                // sum each 16-lane row (DPP), then the first lane of every row
+                // with a contributing pixel adds its row's sums into the
+                // tile's LDS accumulator
+                v0 = row_sum(v0); v1 = row_sum(v1); v2 = row_sum(v2);
+                v3 = row_sum(v3); v4 = row_sum(v4); v5 = row_sum(v5);
+                v6 = row_sum(v6); v7 = row_sum(v7); v8 = row_sum(v8);
+                if ((lane & 15) == 0 && ((cm >> lane) & 0xFFFFull) != 0ull) {
+                    // power = -(A dx^2 + C dy^2)/2 - B dx dy with dx = x - u:
+                    // du = sum dpow (A dx + B dy), dA = -sum dpow dx^2 / 2, ...
+                    // and A = -2 ca / log2e, B = -cb / log2e, C = -2 cc / log2e
+                    const float A = -2.0f * g.coef.x * (1.0f / kLog2e), Bc = -g.coef.y * (1.0f / kLog2e),
+                                C = -2.0f * g.coef.z * (1.0f / kLog2e);
                     float* acc = &s_acc[kk * 9];
-                    atomicAdd(acc + 0, v0);
-                    atomicAdd(acc + 1, v1);
-                    atomicAdd(acc + 2, v2);
-                    atomicAdd(acc + 3, v3);
-                    atomicAdd(acc + 4, v4);
+                    atomicAdd(acc + 0, A * v0 + Bc * v1);
+                    atomicAdd(acc + 1, Bc * v0 + C * v1);
+                    atomicAdd(acc + 2, -0.5f * v2);
+                    atomicAdd(acc + 3, -v3);
+                    atomicAdd(acc + 4, -0.5f * v4);
                     atomicAdd(acc + 5, v5);
                     atomicAdd(acc + 6, v6);
                     atomicAdd(acc + 7, v7);
