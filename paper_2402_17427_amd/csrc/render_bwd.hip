@@ -75,8 +75,10 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
     const int local = (int)(tile - V.tile_base);
     const int tx = local % V.ntx, ty = local / V.ntx;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    // wave = 8x8 block; its 16-lane row r = the 4x4 quadrant (r & 1, r >> 1)
+    const int row = lane >> 4, l16 = lane & 15;
     const int bx = (wv % WX) * 8, by = (wv / WX) * 8;
-    const int lx = bx + (lane & 7), ly = by + (lane >> 3);
+    const int lx = bx + (row & 1) * 4 + (l16 & 3), ly = by + (row >> 1) * 4 + (l16 >> 2);
     const int px = tx * TW + lx, py = ty * TH + ly;
     const bool inside = px < W && py < H;
     const int64_t npix = (int64_t)W * H;
@@ -93,8 +95,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
 
     const uint2 rg = a.ranges[tile];
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-    const float bx0 = (float)(tx * TW + bx) + 0.5f, bx1 = bx0 + 7.0f;
-    const float by0 = (float)(ty * TH + by) + 0.5f, by1 = by0 + 7.0f;
+    const float bx0 = (float)(tx * TW + bx) + 0.5f, by0 = (float)(ty * TH + by) + 0.5f;
 
     uint32_t my_last = 0;
     float T = 1.0f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
@@ -117,9 +118,9 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
     // never walk past the tile's list, whatever n_contrib holds
     const uint32_t max_last = min(sh.max_last, rg.y - rg.x);
 
-    // the wave never needs entries at or beyond its pixels' last contributor
-    uint32_t wave_last = my_last;
-    for (int d = 1; d < kWave; d <<= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, d, kWave));
+    // a row never needs entries at or beyond its pixels' last contributor
+    uint32_t row_last = my_last;
+    for (int d = 1; d < 16; d <<= 1) row_last = max(row_last, (uint32_t)__shfl_xor((int)row_last, d, kWave));
 
     for (int64_t hi = (int64_t)max_last; hi > 0; hi -= B) {
         const int64_t lo = hi - B > 0 ? hi - B : 0;
@@ -134,24 +135,35 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
         __syncthreads();
 
         // 64 staged entries at a time, back to front: each lane tests one
-        // against the wave's block; the ballot lists the ones to walk.
+        // against the four quadrants of the wave's block; every row then
+        // walks, back to front, the entries whose support meets its quadrant
+        // and that lie before its pixels' last contributor (the four rows
+        // of a wave walk different Gaussians in step).
         for (int c0k = ((nb - 1) / kWave) * kWave; c0k >= 0; c0k -= kWave) {
             const int k = c0k + lane;
-            const bool ov = k < nb && (uint32_t)(lo + k) < wave_last && box_overlaps(s[k], bx0, bx1, by0, by1);
-            uint64_t mask = __ballot(ov);
-            // the next walked record is loaded while the current one is processed
-            int nk = mask ? c0k + 63 - __builtin_clzll(mask) : 0;
-            Staged gn = s[nk];
-            while (mask) {
-                const int kk = nk;
-                const Staged g = gn;
-                mask &= ~(1ull << (kk - c0k));
-                if (mask) {
-                    nk = c0k + 63 - __builtin_clzll(mask);
-                    gn = s[nk];
+            bool o0 = false, o1 = false, o2 = false, o3 = false;
+            if (k < nb) {
+                const Staged gk = s[k];
+                o0 = box_overlaps(gk, bx0, bx0 + 3.0f, by0, by0 + 3.0f);
+                o1 = box_overlaps(gk, bx0 + 4.0f, bx0 + 7.0f, by0, by0 + 3.0f);
+                o2 = box_overlaps(gk, bx0, bx0 + 3.0f, by0 + 4.0f, by0 + 7.0f);
+                o3 = box_overlaps(gk, bx0 + 4.0f, bx0 + 7.0f, by0 + 4.0f, by0 + 7.0f);
+            }
+            const uint64_t m0 = __ballot(o0), m1 = __ballot(o1), m2 = __ballot(o2), m3 = __ballot(o3);
+            uint64_t mm = row == 0 ? m0 : (row == 1 ? m1 : (row == 2 ? m2 : m3));
+            const int lim = (int)row_last - (int)(lo + c0k);
+            mm = lim <= 0 ? 0ull : (lim >= kWave ? mm : (mm & ((1ull << lim) - 1ull)));
+            while (__ballot(mm != 0ull) != 0ull) {
+                const bool has = mm != 0ull;
+                int kk = 0;
+                if (has) {
+                    const int j = 63 - (int)__builtin_clzll(mm);
+                    mm &= ~(1ull << j);
+                    kk = c0k + j;
                 }
+                const Staged g = s[kk];
                 const uint32_t pos = (uint32_t)(lo + kk);
-                const bool live = pos < my_last;
+                const bool live = has && pos < my_last;
                 // Branch-free: a pair that does not contribute gets alpha 0,
                 // which leaves T and the suffix colour unchanged and makes
                 // every gradient term 0.

@@ -10,12 +10,13 @@
 //
 // Launch: one workgroup per tile (or a persistent grid pulling tiles from
 // a queue, longest list first), one lane per pixel.  Every wave covers an
-// 8x8 block of the tile, so that a small Gaussian touches few waves.
-// Batches of records are staged in LDS; for each 64 of them the wave tests
-// one per lane against its block's pixel centres and walks, in list order,
-// only those whose support box meets the block (a ballot mask scanned with
-// scalar bit operations).  Skipping the others never changes a result: such
-// a Gaussian has alpha < 1/255 at every pixel of the block.  A wave leaves
+// 8x8 block of the tile and each of its four 16-lane rows a 4x4 quadrant.
+// Batches of records are staged in LDS; for each 64 of them every lane
+// tests one against the four quadrants (an exact ellipse-rectangle test),
+// and each row then walks, in list order, only the Gaussians whose support
+// meets its quadrant; the rows of a wave walk different Gaussians in the
+// same instructions.  Skipping the others never changes a result: such a
+// Gaussian has alpha < 1/255 at every pixel of the quadrant.  A wave leaves
 // the tile once all its pixels have stopped, the workgroup once all waves
 // have.  Tiles of several views are numbered consecutively; a tile finds
 // its view (camera, image planes) in the view table.
@@ -62,8 +63,10 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, Staged
     const int local = (int)(tile - V.tile_base);
     const int tx = local % V.ntx, ty = local / V.ntx;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    // wave = 8x8 block; its 16-lane row r = the 4x4 quadrant (r & 1, r >> 1)
+    const int row = lane >> 4, l16 = lane & 15;
     const int bx = (wv % WX) * 8, by = (wv / WX) * 8;
-    const int lx = bx + (lane & 7), ly = by + (lane >> 3);
+    const int lx = bx + (row & 1) * 4 + (l16 & 3), ly = by + (row >> 1) * 4 + (l16 >> 2);
     const int px = tx * TW + lx, py = ty * TH + ly;
     const bool inside = px < W && py < H;
     const int64_t npix = (int64_t)W * H;
@@ -86,8 +89,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, Staged
 
     const uint2 rg = a.ranges[tile];
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-    const float bx0 = (float)(tx * TW + bx) + 0.5f, bx1 = bx0 + 7.0f;
-    const float by0 = (float)(ty * TH + by) + 0.5f, by1 = by0 + 7.0f;
+    const float bx0 = (float)(tx * TW + bx) + 0.5f, by0 = (float)(ty * TH + by) + 0.5f;
 
     float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
     uint32_t last = 0;
@@ -100,43 +102,55 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, Staged
         if (j < rg.y) s[tid] = stage_rec(a.rec[a.vals[j]]);
         __syncthreads();
         const int nb = (int)min((uint32_t)NT, rg.y - b0);
-        bool live = __ballot(!done) != 0ull;
         // 64 staged Gaussians at a time: each lane tests one against the
-        // wave's block, the ballot lists the ones to walk, in order.
-        for (int c0k = 0; live && c0k < nb; c0k += kWave) {
+        // four quadrants of the wave's block; every row then walks, in list
+        // order, the Gaussians whose support meets its own quadrant (the
+        // four rows of a wave walk different Gaussians in step).
+        for (int c0k = 0; c0k < nb; c0k += kWave) {
+            const uint64_t lv = __ballot(!done);
+            if (lv == 0ull) break;
             const int k = c0k + lane;
-            const bool ov = k < nb && box_overlaps(s[k], bx0, bx1, by0, by1);
-            uint64_t mask = __ballot(ov);
-            while (mask) {
-                const int kk = c0k + __builtin_ctzll(mask);
-                mask &= mask - 1;
-                const Staged g = s[kk];
-                if (!done) {
-                    const Eval e = eval_pair(g, fx, fy);
-                    if (MODE == kStore)
-                        a.state[(int64_t)(b0 + (uint32_t)kk) * NT + tid] =
-                            make_float2(e.capped && e.alpha > 0.0f ? -e.alpha : e.alpha, T);
-                    if (STATS) ++n_eval;
-                    if (e.alpha > 0.0f) {
-                        const float Tn = T * (1.0f - e.alpha);
-                        if (STATS) ++n_supp;
-                        if (Tn < kTMin) {
-                            done = true;
-                        } else {
-                            if (STATS) ++n_blend;
-                            const float w = e.alpha * T;
-                            c0 = __builtin_fmaf(g.col.x, w, c0);
-                            c1 = __builtin_fmaf(g.col.y, w, c1);
-                            c2 = __builtin_fmaf(g.col.z, w, c2);
-                            T = Tn;
-                            last = b0 - rg.x + (uint32_t)kk + 1u;
+            bool o0 = false, o1 = false, o2 = false, o3 = false;
+            if (k < nb) {
+                const Staged gk = s[k];
+                o0 = box_overlaps(gk, bx0, bx0 + 3.0f, by0, by0 + 3.0f);
+                o1 = box_overlaps(gk, bx0 + 4.0f, bx0 + 7.0f, by0, by0 + 3.0f);
+                o2 = box_overlaps(gk, bx0, bx0 + 3.0f, by0 + 4.0f, by0 + 7.0f);
+                o3 = box_overlaps(gk, bx0 + 4.0f, bx0 + 7.0f, by0 + 4.0f, by0 + 7.0f);
+            }
+            const uint64_t m0 = __ballot(o0), m1 = __ballot(o1), m2 = __ballot(o2), m3 = __ballot(o3);
+            uint64_t mm = row == 0 ? m0 : (row == 1 ? m1 : (row == 2 ? m2 : m3));
+            if (((lv >> (16 * row)) & 0xFFFFull) == 0ull) mm = 0ull;   // this row's pixels have all stopped
+            while (__ballot(mm != 0ull) != 0ull) {
+                if (mm != 0ull) {
+                    const int kk = c0k + (int)__builtin_ctzll(mm);
+                    mm &= mm - 1;
+                    const Staged g = s[kk];
+                    if (!done) {
+                        const Eval e = eval_pair(g, fx, fy);
+                        if (MODE == kStore)
+                            a.state[(int64_t)(b0 + (uint32_t)kk) * NT + tid] =
+                                make_float2(e.capped && e.alpha > 0.0f ? -e.alpha : e.alpha, T);
+                        if (STATS) ++n_eval;
+                        if (e.alpha > 0.0f) {
+                            const float Tn = T * (1.0f - e.alpha);
+                            if (STATS) ++n_supp;
+                            if (Tn < kTMin) {
+                                done = true;
+                            } else {
+                                if (STATS) ++n_blend;
+                                const float w = e.alpha * T;
+                                c0 = __builtin_fmaf(g.col.x, w, c0);
+                                c1 = __builtin_fmaf(g.col.y, w, c1);
+                                c2 = __builtin_fmaf(g.col.z, w, c2);
+                                T = Tn;
+                                last = b0 - rg.x + (uint32_t)kk + 1u;
+                            }
                         }
                     }
                 }
-                if (__ballot(!done) == 0ull) {
-                    live = false;
-                    break;
-                }
+                const uint64_t lv2 = __ballot(!done);
+                if (((lv2 >> (16 * row)) & 0xFFFFull) == 0ull) mm = 0ull;
             }
         }
     }
