@@ -127,6 +127,13 @@ typedef struct {
 /* Binning output (caller-owned device buffers):
  *   keys[pair_capacity]  sorted (tile << 32 | float32 bits of depth)
  *   vals[pair_capacity]  Gaussian index of each sorted pair
+ *   first[n]             emission position of each Gaussian's first pair:
+ *                        Gaussian i's pairs were emitted at positions
+ *                        first[i] .. first[i] + tiles_touched[i] - 1, one
+ *                        per tile of its rectangle in row-major order (the
+ *                        backward keys its per-tile sums by it).  n is the
+ *                        Gaussian count given to gs_bin_sort.  May be NULL
+ *                        when no backward follows.
  *   ranges[n_tiles][2]   [start, end) of each tile's pairs; empty = [0, 0)
  *   pair_count[2]        written by gs_bin_sort: [0] = number of sorted
  *                        pairs P (0 on overflow), [1] = pairs the view
@@ -137,6 +144,7 @@ typedef struct {
 typedef struct {
     uint64_t *keys;
     uint32_t *vals;
+    uint32_t *first;
     uint32_t *ranges;
     uint32_t *pair_count;
     int32_t *status;
@@ -147,7 +155,7 @@ typedef struct {
  * with plane stride ld; overwritten):  mean[3][ld], scale[3][ld],
  * quat[4][ld], opacity[ld], sh[3K][ld].
  * grad2d[9][n]: per-Gaussian image-space gradients (du, dv, dA, dB, dC,
- * d opacity, dr, dg, db), used as the accumulator and left holding them. */
+ * d opacity, dr, dg, db), left holding them. */
 typedef struct {
     int64_t ld;
     float *mean, *scale, *quat, *opacity, *sh;
@@ -180,20 +188,29 @@ gs_status gs_render_fwd(const gs_proj *proj, const gs_bins *bins, const gs_camer
                         const gs_opts *opts, float *image, float *final_T, uint32_t *n_contrib,
                         gs_stream stream);
 
+/* Bytes of the device workspace gs_render_bwd needs for these bins:
+ * 36 bytes per pair of capacity (host query). */
+gs_status gs_render_bwd_workspace(const gs_bins *bins, size_t *bytes);
+
 /* Section 3 (differentiable rasterizer, Gaussians optimised by gradient
  * descent): gradient of L w.r.t. every Gaussian parameter given dL/dImage
  * [3][H][W] (device) and the forward's final_T and n_contrib (device).
- * `g`, `proj` and `bins` must be the ones the forward used.  Each pixel
- * walks its list back to front from its last contributor, recovering the
- * transmittance by division from final_T; no per-contributor state is
- * stored.  Per-Gaussian sums use FP32 atomics, so the last bits depend on
- * the order the hardware applies them.  out->grad2d is zeroed here, then
- * accumulated; the parameter gradients are overwritten (zero for culled
- * Gaussians, and for all Gaussians when *bins->status is non-zero). */
+ * `g`, `proj` and `bins` must be the ones the forward used, and
+ * bins->first must be set.  Each pixel walks its list back to front from
+ * its last contributor, recovering the transmittance by division from
+ * final_T; no per-contributor state is stored.  Each tile sums its pixels'
+ * terms per Gaussian (FP32 LDS atomics, so the last bits depend on their
+ * order) and stores the sums, without global atomics, in `ws` (device
+ * scratch of gs_render_bwd_workspace() bytes, 16-byte aligned,
+ * caller-owned, contents on return unspecified) at the (Gaussian, tile)
+ * pair's emission position; each Gaussian's entries are then added in
+ * emission order into out->grad2d, which is overwritten.  The parameter
+ * gradients are overwritten (zero for culled Gaussians, and for all
+ * Gaussians when *bins->status is non-zero). */
 gs_status gs_render_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_opts *opts,
                         const gs_proj *proj, const gs_bins *bins, const float *final_T,
                         const uint32_t *n_contrib, const float *dL_dimage, gs_grads *out,
-                        gs_stream stream);
+                        void *ws, size_t ws_bytes, gs_stream stream);
 
 /* Stored-state variant of the blend (for comparison with the recomputing
  * backward above; same results within the gradient tolerance).
@@ -212,7 +229,8 @@ gs_status gs_render_fwd_stored(const gs_proj *proj, const gs_bins *bins, const g
 gs_status gs_render_bwd_stored(const gs_gaussians *g, const gs_camera *cam, const gs_opts *opts,
                                const gs_proj *proj, const gs_bins *bins, const float *final_T,
                                const uint32_t *n_contrib, const void *state, size_t state_bytes,
-                               const float *dL_dimage, gs_grads *out, gs_stream stream);
+                               const float *dL_dimage, gs_grads *out, void *ws, size_t ws_bytes,
+                               gs_stream stream);
 
 /* Stable LSD radix sort of (uint64 key, uint32 value) pairs on the low
  * `key_bits` bits (<= 64), the sort gs_bin_sort runs, exposed for testing

@@ -55,7 +55,7 @@ class gs_proj(C.Structure):
 
 
 class gs_bins(C.Structure):
-    _fields_ = [("keys", P), ("vals", P), ("ranges", P), ("pair_count", P), ("status", P),
+    _fields_ = [("keys", P), ("vals", P), ("first", P), ("ranges", P), ("pair_count", P), ("status", P),
                 ("pair_capacity", C.c_int64)]
 
 
@@ -75,15 +75,17 @@ _SIGS = {
     "gs_bin_sort": [C.POINTER(gs_proj), C.c_int64, C.POINTER(gs_camera), C.POINTER(gs_opts), C.POINTER(gs_bins),
                     P, C.c_size_t, P],
     "gs_render_fwd": [C.POINTER(gs_proj), C.POINTER(gs_bins), C.POINTER(gs_camera), C.POINTER(gs_opts), P, P, P, P],
+    "gs_render_bwd_workspace": [C.POINTER(gs_bins), C.POINTER(C.c_size_t)],
     "gs_render_bwd": [C.POINTER(gs_gaussians), C.POINTER(gs_camera), C.POINTER(gs_opts), C.POINTER(gs_proj),
-                      C.POINTER(gs_bins), P, P, P, C.POINTER(gs_grads), P],
+                      C.POINTER(gs_bins), P, P, P, C.POINTER(gs_grads), P, C.c_size_t, P],
     "gs_sort_workspace": [C.c_int64, C.c_int32, C.POINTER(C.c_size_t)],
     "gs_sort_pairs": [P, P, P, C.c_int64, C.c_int32, P, C.c_size_t, P],
     "gs_render_state_bytes": [C.POINTER(gs_bins), C.POINTER(gs_opts), C.POINTER(C.c_size_t)],
     "gs_render_fwd_stored": [C.POINTER(gs_proj), C.POINTER(gs_bins), C.POINTER(gs_camera), C.POINTER(gs_opts),
                              P, P, P, P, C.c_size_t, P],
     "gs_render_bwd_stored": [C.POINTER(gs_gaussians), C.POINTER(gs_camera), C.POINTER(gs_opts), C.POINTER(gs_proj),
-                             C.POINTER(gs_bins), P, P, P, C.c_size_t, P, C.POINTER(gs_grads), P],
+                             C.POINTER(gs_bins), P, P, P, C.c_size_t, P, C.POINTER(gs_grads), P, C.c_size_t,
+                             P],
     "gs_render_stats": [C.POINTER(gs_proj), C.POINTER(gs_bins), C.POINTER(gs_camera), C.POINTER(gs_opts), P, P],
     "gs_profile_enable": [C.c_int],
     "gs_profile_report": [C.c_char_p, C.c_size_t],

@@ -238,7 +238,7 @@ gs_status gs_bin_sort(const gs_proj* proj, int64_t n, const gs_camera* cam, cons
         G0.n = n;
         launch_emit_pairs(n, proj->tiles_touched, reinterpret_cast<const ushort4*>(proj->rect), proj->depth,
                           single_job(G0, nullptr), single_view(C, tw, th), cap, odd ? alt_k : out->keys,
-                          odd ? alt_v : out->vals, out->pair_count, out->status, scan_ws, st);
+                          odd ? alt_v : out->vals, out->first, out->pair_count, out->status, scan_ws, st);
     }
     {
         ProfScope ps("sort", st);
@@ -316,8 +316,8 @@ namespace {
 
 gs_status render_bwd_impl(const gs_gaussians* g, const gs_camera* cam, const gs_opts* opts, const gs_proj* proj,
                           const gs_bins* bins, const float* final_T, const uint32_t* n_contrib,
-                          const float* dL_dimage, gs_grads* out, const void* state, size_t state_bytes,
-                          gs_stream stream) {
+                          const float* dL_dimage, gs_grads* out, const void* state, size_t state_bytes, void* ws,
+                          size_t ws_bytes, gs_stream stream) {
     Gauss G;
     Cam C;
     int tw, th;
@@ -334,15 +334,26 @@ gs_status render_bwd_impl(const gs_gaussians* g, const gs_camera* cam, const gs_
         if ((s = gs_render_state_bytes(bins, opts, &need))) return s;
         if (state_bytes < need) return fail(GS_ERR_INVALID, "state buffer too small: %zu < %zu", state_bytes, need);
     }
+    if (G.n > 0 && !bins->first) return fail(GS_ERR_INVALID, "bins first is NULL");
+    const size_t need_ws = pair_grad_bytes(bins->pair_capacity);
+    if (need_ws > 0 && (!ws || ws_bytes < need_ws))
+        return fail(GS_ERR_INVALID, "workspace too small: %zu < %zu", ws_bytes, need_ws);
+    if (reinterpret_cast<uintptr_t>(ws) % 16) return fail(GS_ERR_INVALID, "workspace not 16-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t cap = bins->pair_capacity;
     {
-        ProfScope ps("grad_zero", st);
-        launch_fill_u32(reinterpret_cast<uint32_t*>(out->grad2d), 0u, (size_t)G.n * 9, st);
+        ProfScope ps("pair_zero", st);
+        launch_pair_zero(ws, bins->pair_count, cap, st);
     }
     {
         ProfScope ps(state ? "render_bwd_stored" : "render_bwd", st);
-        launch_render_bwd(single_render(proj, bins, C, tw, th), final_T, n_contrib, dL_dimage, G.n, out->grad2d,
+        launch_render_bwd(single_render(proj, bins, C, tw, th), final_T, n_contrib, dL_dimage,
+                          reinterpret_cast<const ushort4*>(proj->rect), bins->first, ws, cap,
                           static_cast<const float2*>(state), st);
+    }
+    {
+        ProfScope ps("pair_gather", st);
+        launch_pair_gather(G.n, bins->first, proj->tiles_touched, ws, cap, bins->status, out->grad2d, st);
     }
     {
         ProfScope ps("project_bwd", st);
@@ -354,19 +365,29 @@ gs_status render_bwd_impl(const gs_gaussians* g, const gs_camera* cam, const gs_
 
 }  // namespace
 
+gs_status gs_render_bwd_workspace(const gs_bins* bins, size_t* bytes) {
+    gs_status s;
+    if ((s = check_bins(bins))) return s;
+    if (!bytes) return fail(GS_ERR_INVALID, "bytes is NULL");
+    *bytes = pair_grad_bytes(bins->pair_capacity);
+    return GS_OK;
+}
+
 gs_status gs_render_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_opts* opts, const gs_proj* proj,
                         const gs_bins* bins, const float* final_T, const uint32_t* n_contrib,
-                        const float* dL_dimage, gs_grads* out, gs_stream stream) {
-    return render_bwd_impl(g, cam, opts, proj, bins, final_T, n_contrib, dL_dimage, out, nullptr, 0, stream);
+                        const float* dL_dimage, gs_grads* out, void* ws, size_t ws_bytes, gs_stream stream) {
+    return render_bwd_impl(g, cam, opts, proj, bins, final_T, n_contrib, dL_dimage, out, nullptr, 0, ws, ws_bytes,
+                           stream);
 }
 
 gs_status gs_render_bwd_stored(const gs_gaussians* g, const gs_camera* cam, const gs_opts* opts,
                                const gs_proj* proj, const gs_bins* bins, const float* final_T,
                                const uint32_t* n_contrib, const void* state, size_t state_bytes,
-                               const float* dL_dimage, gs_grads* out, gs_stream stream) {
+                               const float* dL_dimage, gs_grads* out, void* ws, size_t ws_bytes,
+                               gs_stream stream) {
     if (!state) return fail(GS_ERR_INVALID, "state is NULL");
-    return render_bwd_impl(g, cam, opts, proj, bins, final_T, n_contrib, dL_dimage, out, state, state_bytes,
-                           stream);
+    return render_bwd_impl(g, cam, opts, proj, bins, final_T, n_contrib, dL_dimage, out, state, state_bytes, ws,
+                           ws_bytes, stream);
 }
 
 gs_status gs_sort_workspace(int64_t capacity, int32_t key_bits, size_t* bytes) {

@@ -79,10 +79,12 @@ struct gs_batch {
     ushort4* rect = nullptr;
     uint32_t* tt = nullptr;
     float* g2d = nullptr;
+    uint32_t* first = nullptr;   // emission position of each slot's first pair
     void* scan_ws = nullptr;
     // pair buffers (capacity) and per-tile buffers (max over candidates)
     uint64_t *keys = nullptr, *alt_k = nullptr;
     uint32_t *vals = nullptr, *alt_v = nullptr;
+    void* pair_grad = nullptr;   // per-pair image-space gradients of the backward
     void* sort_ws = nullptr;
     size_t sort_ws_bytes = 0;
     uint32_t* ranges = nullptr;
@@ -110,8 +112,8 @@ struct gs_batch {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
-        void* ptrs[] = {d_views, d_jobs, d_targets, rec, depth, rect, tt, g2d, scan_ws, keys, alt_k, vals, alt_v,
-                        sort_ws, ranges, pair_count, status, queue, tiles_dev, tkeys, tkeys_alt, tvals, tvals_alt,
+        void* ptrs[] = {d_views, d_jobs, d_targets, rec, depth, rect, tt, g2d, first, scan_ws, keys, alt_k, vals,
+                        alt_v, pair_grad, sort_ws, ranges, pair_count, status, queue, tiles_dev, tkeys, tkeys_alt, tvals, tvals_alt,
                         tsort_ws, final_T, n_contrib, dimg};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
@@ -166,7 +168,7 @@ struct gs_batch {
         launch_project(jt(), vt(), K, nslots, tw, th, rec, depth, rect, tt, st);
         const bool odd = sort_passes(key_bits()) % 2 == 1;
         launch_emit_pairs(nslots, tt, rect, depth, jt(), vt(), capacity, odd ? alt_k : keys, odd ? alt_v : vals,
-                          pair_count, status, scan_ws, st);
+                          first, pair_count, status, scan_ws, st);
     }
 
     // One training step of every cell: project, bin, sort, ranges, blend,
@@ -195,9 +197,10 @@ struct gs_batch {
         }
         launch_render_fwd(r, images, final_T, n_contrib, nullptr, nullptr, st);
         launch_l1(vt(), n, max_pix, d_targets, images, dimg, loss, status, st);
-        launch_fill_u32(reinterpret_cast<uint32_t*>(g2d), 0u, (size_t)nslots * 9, st);
+        launch_pair_zero(pair_grad, pair_count, capacity, st);
         if (persistent) r.persistent_grid = grid_bwd;
-        launch_render_bwd(r, final_T, n_contrib, dimg, nslots, g2d, nullptr, st);
+        launch_render_bwd(r, final_T, n_contrib, dimg, rect, first, pair_grad, capacity, nullptr, st);
+        launch_pair_gather(nslots, first, tt, pair_grad, capacity, status, g2d, st);
         launch_project_bwd(jt(), vt(), K, nslots, tt, g2d, status, st);
     }
 
@@ -217,15 +220,16 @@ struct gs_batch {
 
     gs_status alloc_pairs(int64_t cap) {
         if (cap > kMaxPairs) return fail(GS_ERR_CAPACITY, "batch needs %lld pairs (> 2^30-1)", (long long)cap);
-        for (void* p : {(void*)keys, (void*)alt_k, (void*)vals, (void*)alt_v, sort_ws})
+        for (void* p : {(void*)keys, (void*)alt_k, (void*)vals, (void*)alt_v, pair_grad, sort_ws})
             if (p) (void)hipFree(p);
         keys = alt_k = nullptr;
         vals = alt_v = nullptr;
-        sort_ws = nullptr;
+        pair_grad = sort_ws = nullptr;
         gs_status s;
         sort_ws_bytes = sort_workspace_bytes(cap, 64);
         if ((s = dmalloc(&keys, cap)) || (s = dmalloc(&alt_k, cap)) || (s = dmalloc(&vals, cap)) ||
-            (s = dmalloc(&alt_v, cap)) || (s = dmalloc(reinterpret_cast<char**>(&sort_ws), sort_ws_bytes)))
+            (s = dmalloc(&alt_v, cap)) || (s = dmalloc(reinterpret_cast<char**>(&sort_ws), sort_ws_bytes)) ||
+            (s = dmalloc(reinterpret_cast<char**>(&pair_grad), pair_grad_bytes(cap))))
             return s;
         capacity = cap;
         return GS_OK;
@@ -368,7 +372,7 @@ gs_status gs_batch_create(const gs_gaussians* cells, const gs_camera* cams, cons
     if (!s) {
         if ((s = dmalloc(&b->d_views, n_cells)) || (s = dmalloc(&b->d_jobs, n_cells)) ||
             (s = dmalloc(&b->d_targets, n_cells)) || (s = dmalloc(&b->rec, slot)) || (s = dmalloc(&b->depth, slot)) ||
-            (s = dmalloc(&b->rect, slot)) || (s = dmalloc(&b->tt, slot)) || (s = dmalloc(&b->g2d, slot * 9)) ||
+            (s = dmalloc(&b->rect, slot)) || (s = dmalloc(&b->tt, slot)) || (s = dmalloc(&b->g2d, slot * 9)) || (s = dmalloc(&b->first, slot)) ||
             (s = dmalloc(reinterpret_cast<char**>(&b->scan_ws), scan_workspace_bytes(slot))) ||
             (s = dmalloc(&b->ranges, (size_t)max_tiles * 2)) || (s = dmalloc(&b->pair_count, 2)) ||
             (s = dmalloc(&b->status, 1)) || (s = dmalloc(&b->queue, 1)) || (s = dmalloc(&b->tiles_dev, 1)) ||

@@ -77,11 +77,14 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(const uint32_t* __restric
                                                        const float* __restrict__ depth, int64_t n, JobTab jobs,
                                                        ViewTab views, const uint64_t* __restrict__ block_prefix,
                                                        int64_t capacity, uint64_t* __restrict__ keys,
-                                                       uint32_t* __restrict__ vals) {
+                                                       uint32_t* __restrict__ vals, uint32_t* __restrict__ first) {
     const int64_t i = (int64_t)blockIdx.x * kScanThreads + threadIdx.x;
     const uint32_t cnt = i < n ? tt[i] : 0u;
     uint64_t tot;
     uint64_t off = block_prefix[blockIdx.x] + block_exclusive_scan<kScanThreads>(cnt, &tot);
+    // where this Gaussian's pairs start in emission order (the backward
+    // writes its per-tile sums there); meaningful only when all pairs fit
+    if (first && i < n) first[i] = (uint32_t)off;
     if (cnt == 0) return;
     // record slots are aligned so that a workgroup lies within one job
     const View V = view_at(views, job_at(jobs, find_job(jobs, (int64_t)blockIdx.x * kScanThreads)).view);
@@ -127,15 +130,15 @@ void launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t st) {
 }
 
 void launch_emit_pairs(int64_t n, const uint32_t* tt, const ushort4* rect, const float* depth, const JobTab& jobs,
-                       const ViewTab& views, int64_t capacity, uint64_t* keys, uint32_t* vals, uint32_t* pair_count,
-                       int32_t* status, void* scan_ws, hipStream_t st) {
+                       const ViewTab& views, int64_t capacity, uint64_t* keys, uint32_t* vals, uint32_t* first,
+                       uint32_t* pair_count, int32_t* status, void* scan_ws, hipStream_t st) {
     uint64_t* bs = static_cast<uint64_t*>(scan_ws);
     const int64_t nb = (n + kScanThreads - 1) / kScanThreads;
     if (nb > 0) hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nb), dim3(kScanThreads), 0, st, tt, n, bs);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTopThreads), 0, st, bs, nb, capacity, pair_count, status);
     if (nb > 0)
         hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kScanThreads), 0, st, tt, rect, depth, n, jobs, views,
-                           bs, capacity, keys, vals);
+                           bs, capacity, keys, vals, first);
 }
 
 void launch_tile_ranges(const uint64_t* keys, const uint32_t* pair_count, int64_t capacity, int64_t n_tiles,

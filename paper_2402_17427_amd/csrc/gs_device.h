@@ -195,6 +195,12 @@ __device__ __forceinline__ bool box_overlaps(const Staged& s, float x0, float x1
     return m >= s.col.w - (1e-3f + 1e-4f * fabsf(m));
 }
 
+// The staged record `k` of an LDS array, addressed with a 24-bit multiply
+// (full rate) instead of a 32-bit one.
+__device__ __forceinline__ const Staged& staged_at(const Staged* s, int k) {
+    return *reinterpret_cast<const Staged*>(reinterpret_cast<const char*>(s) + __umul24((unsigned)k, (unsigned)sizeof(Staged)));
+}
+
 // Sum of v over each 16-lane row of the wave (DPP), left in every lane of
 // the row.
 __device__ __forceinline__ float row_sum(float v) {

@@ -26,10 +26,11 @@ size_t scan_workspace_bytes(int64_t n);
 // Exclusive scan of tiles_touched, then one (tile << 32 | depth bits, index)
 // pair per covered tile.  Writes *pair_count and sets *status to
 // GS_ERR_CAPACITY (-4) when the pairs exceed `capacity` (pairs beyond it
-// are dropped).
+// are dropped).  `first` (optional, n entries) receives each Gaussian's
+// first emission position.
 void launch_emit_pairs(int64_t n, const uint32_t* tiles_touched, const ushort4* rect, const float* depth,
                        const JobTab& jobs, const ViewTab& views, int64_t capacity, uint64_t* keys, uint32_t* vals,
-                       uint32_t* pair_count, int32_t* status, void* scan_ws, hipStream_t st);
+                       uint32_t* first, uint32_t* pair_count, int32_t* status, void* scan_ws, hipStream_t st);
 void launch_tile_ranges(const uint64_t* keys, const uint32_t* pair_count, int64_t capacity, int64_t n_tiles,
                         uint32_t* ranges, hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t st);
@@ -71,10 +72,23 @@ bool render_tile_supported(int tw, int th);
 // NULL also stores the per-entry blend state (pairs * tile pixels).
 void launch_render_fwd(const RenderArgs& r, float* image, float* final_T, uint32_t* n_contrib,
                        unsigned long long* stats, float2* state, hipStream_t st);
-// g2d [9][nslots] is accumulated (not zeroed here).  state != NULL reads
-// the stored blend state instead of recomputing it.
+// Per-pair image-space gradients of the blend.  `pairs` is the pair
+// gradient buffer (pair_grad_bytes(capacity) bytes): the backward writes,
+// for every (Gaussian, tile) pair with a contribution, the nine sums of
+// the tile's pixels at the pair's emission position (first[slot] + the
+// tile's row-major index in the Gaussian's rectangle); launch_pair_zero
+// must have cleared it.  state != NULL reads the stored blend state
+// instead of recomputing it.
 void launch_render_bwd(const RenderArgs& r, const float* final_T, const uint32_t* n_contrib, const float* dimg,
-                       int64_t nslots, float* g2d, const float2* state, hipStream_t st);
+                       const ushort4* rect, const uint32_t* first, void* pairs, int64_t capacity,
+                       const float2* state, hipStream_t st);
+size_t pair_grad_bytes(int64_t capacity);
+// Zero the first min(*pair_count, capacity) entries of the pair buffer.
+void launch_pair_zero(void* pairs, const uint32_t* pair_count, int64_t capacity, hipStream_t st);
+// g2d[9][nslots] = the sum of each slot's pair entries (emission order);
+// zeros for culled slots and when *status != 0.
+void launch_pair_gather(int64_t nslots, const uint32_t* first, const uint32_t* tiles_touched, const void* pairs,
+                        int64_t capacity, const int32_t* status, float* g2d, hipStream_t st);
 
 // Workgroups of a persistent blend launch that fit on the device at once.
 int render_persistent_grid(int tw, int th, bool backward);

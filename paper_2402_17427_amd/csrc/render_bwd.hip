@@ -22,9 +22,12 @@
 // from the back) and that lie before its pixels' last contributor.
 // Reduction: per walked entry, a wave first checks (ballot) whether any of
 // its 64 pixels contributed; only then are the nine gradient terms summed
-// over each 16-lane row with DPP, added by the first lane of each row that
-// has a contributing pixel into a per-tile LDS accumulator, and flushed with
-// one global FP32 atomic per (Gaussian, term, tile) after the batch.
+// over each 16-lane row with a transposing DPP butterfly that leaves the
+// nine sums in lanes 0..8 of the row, which add them with one LDS atomic
+// instruction into a per-tile accumulator.  After the batch each entry's
+// sums are written, without global atomics, to its (Gaussian, tile) pair
+// slot in emission order; a gather then adds each Gaussian's slots, so the
+// per-Gaussian sum over tiles has a fixed order.
 #include "kernels.h"
 
 namespace gs {
@@ -40,13 +43,51 @@ struct BwdArgs {
     const float* final_T;
     const uint32_t* n_contrib;
     const float* dimg;
-    int64_t n;              // slots: plane stride of g2d
-    float* g2d;
+    const ushort4* rect;    // per slot: tile rectangle
+    const uint32_t* first;  // per slot: emission position of its first pair
+    float4* pg8;            // per pair: du, dv, dA, dB | dC, do, dr, dg
+    float* pg1;             // per pair: db
+    int64_t cap;            // pair capacity
     const float2* state;
     uint32_t* queue;        // persistent launch: next queue position (zeroed before launch)
     const uint32_t* order;  // persistent launch: tiles in processing order (NULL = 0, 1, ...)
     uint32_t n_tiles;
 };
+
+// One DPP exchange inside each 16-lane row: quad_perm [1,0,3,2] (partner
+// lane ^ 1), quad_perm [2,3,0,1] (lane ^ 2), row_ror:4 and row_ror:8 (lane
+// - 4 and lane - 8 within the row).
+template <int CTRL>
+__device__ __forceinline__ float xch(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kRor4 = 0x124, kRor8 = 0x128;
+
+// Sums nine values over each 16-lane row with a transposing butterfly: in
+// each of the first three exchanges a lane keeps one value of every pair and
+// sends its partner the other, so the values per lane halve as the span of
+// the sums doubles (27 VALU operations instead of 36 for nine plain
+// butterflies, and the sums end up spread over the lanes).  On return lane
+// l (0..15) of a row holds the row sum of v[l & 7] in .x and of v8 in .y.
+// b0, b1, b2 are bits 0, 1, 2 of the lane index.
+__device__ __forceinline__ float2 row_sum9(float v0, float v1, float v2, float v3, float v4, float v5, float v6,
+                                           float v7, float v8, bool b0, bool b1, bool b2) {
+    // lane ^ 1: keep v[2j + b0]
+    const float r0 = (b0 ? v1 : v0) + xch<kXor1>(b0 ? v0 : v1);
+    const float r1 = (b0 ? v3 : v2) + xch<kXor1>(b0 ? v2 : v3);
+    const float r2 = (b0 ? v5 : v4) + xch<kXor1>(b0 ? v4 : v5);
+    const float r3 = (b0 ? v7 : v6) + xch<kXor1>(b0 ? v6 : v7);
+    const float r4 = v8 + xch<kXor1>(v8);
+    // lane ^ 2: keep v[4k + 2 b1 + b0]
+    const float s0 = (b1 ? r1 : r0) + xch<kXor2>(b1 ? r0 : r1);
+    const float s1 = (b1 ? r3 : r2) + xch<kXor2>(b1 ? r2 : r3);
+    const float s2 = r4 + xch<kXor2>(r4);
+    // lane - 4 (opposite bit 2, same low bits): keep v[4 b2 + 2 b1 + b0]
+    const float t0 = (b2 ? s1 : s0) + xch<kRor4>(b2 ? s0 : s1);
+    const float t1 = s2 + xch<kRor4>(s2);
+    // lane - 8: the other two quads of the row
+    return make_float2(t0 + xch<kRor8>(t0), t1 + xch<kRor8>(t1));
+}
 
 template <int NT>
 struct BwdShared {
@@ -89,8 +130,6 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
     const Rec* __restrict__ rec = a.rec;
     const uint32_t* __restrict__ vals = a.vals;
     const float2* __restrict__ state = a.state;
-    float* __restrict__ g2d = a.g2d;
-    const int64_t n = a.n;
     const float bg0 = V.cam.bg[0], bg1 = V.cam.bg[1], bg2 = V.cam.bg[2];
 
     const uint2 rg = a.ranges[tile];
@@ -118,6 +157,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
     // never walk past the tile's list, whatever n_contrib holds
     const uint32_t max_last = min(sh.max_last, rg.y - rg.x);
 
+    const bool b0 = (lane & 1) != 0, b1 = (lane & 2) != 0, b2 = (lane & 4) != 0;
     // a row never needs entries at or beyond its pixels' last contributor
     uint32_t row_last = my_last;
     for (int d = 1; d < 16; d <<= 1) row_last = max(row_last, (uint32_t)__shfl_xor((int)row_last, d, kWave));
@@ -161,7 +201,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
                     mm &= ~(1ull << j);
                     kk = c0k + j;
                 }
-                const Staged g = s[kk];
+                const Staged g = staged_at(s, kk);
                 const uint32_t pos = (uint32_t)(lo + kk);
                 const bool live = has && pos < my_last;
                 // Branch-free: a pair that does not contribute gets alpha 0,
@@ -192,46 +232,52 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
                 const float da = (contrib && !e.capped) ? da0 : 0.0f;
                 ga = __builtin_fmaf(grgb, w, ga);
                 T = Ti;
-                float v6 = g0 * w, v7 = g1 * w, v8 = g2 * w;
-                float v5 = da * e.G;
+                // per-lane terms; a lane without a contribution holds zeros
+                const float v6 = g0 * w, v7 = g1 * w, v8 = g2 * w;
+                const float v5 = (contrib && !e.capped) ? da0 * e.G : 0.0f;
                 // moments of dL/dpower over the pixel offsets; the centre and
-                // conic gradients are linear in them (formed per row below)
+                // conic gradients are linear in them (formed at the flush)
                 const float dpow = da * a;
                 const float mx = dpow * e.dx, my = dpow * e.dy;
-                float v0 = mx, v1 = my, v2 = mx * e.dx, v3 = mx * e.dy, v4 = my * e.dy;
                 const uint64_t cm = __ballot(contrib);
                 if (cm == 0ull) continue;
-                // sum each 16-lane row (DPP), then the first lane of every row
-                // with a contributing pixel adds its row's sums into the
-                // tile's LDS accumulator
-                v0 = row_sum(v0); v1 = row_sum(v1); v2 = row_sum(v2);
-                v3 = row_sum(v3); v4 = row_sum(v4); v5 = row_sum(v5);
-                v6 = row_sum(v6); v7 = row_sum(v7); v8 = row_sum(v8);
-                if ((lane & 15) == 0 && ((cm >> lane) & 0xFFFFull) != 0ull) {
-                    // power = -(A dx^2 + C dy^2)/2 - B dx dy with dx = x - u:
-                    // du = sum dpow (A dx + B dy), dA = -sum dpow dx^2 / 2, ...
-                    // and A = -2 ca / log2e, B = -cb / log2e, C = -2 cc / log2e
-                    const float A = -2.0f * g.coef.x * (1.0f / kLog2e), Bc = -g.coef.y * (1.0f / kLog2e),
-                                C = -2.0f * g.coef.z * (1.0f / kLog2e);
-                    float* acc = &s_acc[kk * 9];
-                    atomicAdd(acc + 0, A * v0 + Bc * v1);
-                    atomicAdd(acc + 1, Bc * v0 + C * v1);
-                    atomicAdd(acc + 2, -0.5f * v2);
-                    atomicAdd(acc + 3, -v3);
-                    atomicAdd(acc + 4, -0.5f * v4);
-                    atomicAdd(acc + 5, v5);
-                    atomicAdd(acc + 6, v6);
-                    atomicAdd(acc + 7, v7);
-                    atomicAdd(acc + 8, v8);
-                }
+                // row sums, spread over the row's lanes 0..8, added into the
+                // tile's LDS accumulator of the row's entry (a row that
+                // walked nothing adds zeros)
+                const float2 r = row_sum9(mx, my, mx * e.dx, mx * e.dy, my * e.dy, v5, v6, v7, v8, b0, b1, b2);
+                if (l16 <= 8) atomicAdd(s_acc + (__umul24((uint32_t)kk, 9u) + (uint32_t)l16), l16 == 8 ? r.y : r.x);
             }
         }
         __syncthreads();
-        for (int q = tid; q < nb * 9; q += NT) {
-            const float v = s_acc[q];
-            if (v != 0.0f) {
-                const int k = q / 9, c = q - 9 * (q / 9);
-                atomicAdd(&g2d[(int64_t)c * n + s_gid[k]], v);
+        // the accumulator holds, per entry, the sums of dpow dx, dpow dy,
+        // dpow dx^2, dpow dx dy, dpow dy^2, dL/do, dL/drgb; with
+        // power = -(A dx^2 + C dy^2)/2 - B dx dy and dx = x - u:
+        // du = sum dpow (A dx + B dy), dv = sum dpow (B dx + C dy),
+        // dA = -sum dpow dx^2 / 2, dB = -sum dpow dx dy, dC = -sum dpow dy^2 / 2,
+        // where A = -2 ca / log2e, B = -cb / log2e, C = -2 cc / log2e.
+        // Each entry's nine sums go, without atomics, to the entry's own
+        // pair slot: one thread per entry.
+        if (tid < nb) {
+            const float* acc = s_acc + tid * 9;
+            float m[9];
+            bool any = false;
+            for (int c = 0; c < 9; ++c) {
+                m[c] = acc[c];
+                any |= m[c] != 0.0f;
+            }
+            if (any) {
+                const uint32_t gid = s_gid[tid];
+                const ushort4 r = a.rect[gid];
+                const int64_t p = (int64_t)a.first[gid] + (int64_t)(ty - (int)r.y) * ((int)r.z - (int)r.x) +
+                                  (tx - (int)r.x);
+                if (p >= 0 && p < a.cap) {
+                    const float4 cf = s[tid].coef;
+                    const float A = -2.0f * cf.x * (1.0f / kLog2e), Bc = -cf.y * (1.0f / kLog2e),
+                                C = -2.0f * cf.z * (1.0f / kLog2e);
+                    a.pg8[2 * p] = make_float4(A * m[0] + Bc * m[1], Bc * m[0] + C * m[1], -0.5f * m[2], -m[3]);
+                    a.pg8[2 * p + 1] = make_float4(-0.5f * m[4], m[5], m[6], m[7]);
+                    a.pg1[p] = m[8];
+                }
             }
         }
     }
@@ -257,6 +303,49 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd_persistent(BwdArgs a) {
     }
 }
 
+// Clear the pair gradient buffer over the pairs of this frame.
+__global__ __launch_bounds__(256) void k_pair_zero(float4* __restrict__ pg8, float* __restrict__ pg1,
+                                                   const uint32_t* __restrict__ pair_count, int64_t cap) {
+    const int64_t P = (int64_t)*pair_count < cap ? (int64_t)*pair_count : cap;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < P; p += (int64_t)gridDim.x * 256) {
+        pg8[2 * p] = make_float4(0.f, 0.f, 0.f, 0.f);
+        pg8[2 * p + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        pg1[p] = 0.f;
+    }
+}
+
+// Per slot: the sum over its pairs (emission order, so a fixed order) of
+// the per-tile image-space gradients, into g2d[9][nslots].
+__global__ __launch_bounds__(256) void k_pair_gather(int64_t nslots, const uint32_t* __restrict__ first,
+                                                     const uint32_t* __restrict__ tt, const float4* __restrict__ pg8,
+                                                     const float* __restrict__ pg1, int64_t cap,
+                                                     const int32_t* __restrict__ status, float* __restrict__ g2d) {
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (slot >= nslots) return;
+    float4 s0 = make_float4(0.f, 0.f, 0.f, 0.f), s1 = s0;
+    float s2 = 0.f;
+    if (*status == 0) {
+        const int64_t b = first[slot];
+        int64_t e = b + (int64_t)tt[slot];
+        if (e > cap) e = cap;
+        for (int64_t p = b; p < e; ++p) {
+            const float4 x = pg8[2 * p], y = pg8[2 * p + 1];
+            s0.x += x.x; s0.y += x.y; s0.z += x.z; s0.w += x.w;
+            s1.x += y.x; s1.y += y.y; s1.z += y.z; s1.w += y.w;
+            s2 += pg1[p];
+        }
+    }
+    g2d[slot] = s0.x;
+    g2d[nslots + slot] = s0.y;
+    g2d[2 * nslots + slot] = s0.z;
+    g2d[3 * nslots + slot] = s0.w;
+    g2d[4 * nslots + slot] = s1.x;
+    g2d[5 * nslots + slot] = s1.y;
+    g2d[6 * nslots + slot] = s1.z;
+    g2d[7 * nslots + slot] = s1.w;
+    g2d[8 * nslots + slot] = s2;
+}
+
 template <int TW, int TH>
 void launch_t(const BwdArgs& a, int persistent_grid, hipStream_t st) {
     const dim3 block(TW * TH);
@@ -270,8 +359,30 @@ void launch_t(const BwdArgs& a, int persistent_grid, hipStream_t st) {
 
 }  // namespace
 
+size_t pair_grad_bytes(int64_t capacity) { return (size_t)(capacity > 0 ? capacity : 0) * 36; }
+
+void launch_pair_zero(void* pairs, const uint32_t* pair_count, int64_t capacity, hipStream_t st) {
+    if (capacity <= 0) return;
+    int64_t blocks = (capacity + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_pair_zero, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<float4*>(pairs),
+                       reinterpret_cast<float*>(static_cast<char*>(pairs) + (size_t)capacity * 32), pair_count,
+                       capacity);
+}
+
+void launch_pair_gather(int64_t nslots, const uint32_t* first, const uint32_t* tiles_touched, const void* pairs,
+                        int64_t capacity, const int32_t* status, float* g2d, hipStream_t st) {
+    if (nslots <= 0) return;
+    const int64_t blocks = (nslots + 255) / 256;
+    hipLaunchKernelGGL(k_pair_gather, dim3((unsigned)blocks), dim3(256), 0, st, nslots, first, tiles_touched,
+                       static_cast<const float4*>(pairs),
+                       reinterpret_cast<const float*>(static_cast<const char*>(pairs) + (size_t)capacity * 32),
+                       capacity, status, g2d);
+}
+
 void launch_render_bwd(const RenderArgs& r, const float* final_T, const uint32_t* n_contrib, const float* dimg,
-                       int64_t nslots, float* g2d, const float2* state, hipStream_t st) {
+                       const ushort4* rect, const uint32_t* first, void* pairs, int64_t capacity,
+                       const float2* state, hipStream_t st) {
     if (r.n_tiles == 0) return;
     BwdArgs a;
     a.rec = r.rec;
@@ -282,8 +393,11 @@ void launch_render_bwd(const RenderArgs& r, const float* final_T, const uint32_t
     a.final_T = final_T;
     a.n_contrib = n_contrib;
     a.dimg = dimg;
-    a.n = nslots;
-    a.g2d = g2d;
+    a.rect = rect;
+    a.first = first;
+    a.pg8 = static_cast<float4*>(pairs);
+    a.pg1 = reinterpret_cast<float*>(static_cast<char*>(pairs) + (size_t)capacity * 32);
+    a.cap = capacity;
     a.state = state;
     a.queue = r.queue;
     a.order = r.order;

@@ -278,7 +278,7 @@ struct gs_server {
         const bool odd = sort_passes(kb) % 2 == 1;
         launch_project(jt, vt, scene.K, slot, tw, th, p.rec, p.depth, p.rect, p.tt, st);
         launch_emit_pairs(slot, p.tt, p.rect, p.depth, jt, vt, cap, odd ? p.alt_k : p.keys, odd ? p.alt_v : p.vals,
-                          p.pair_count, p.status, p.scan_ws, st);
+                          nullptr, p.pair_count, p.status, p.scan_ws, st);
         launch_sort_pairs(p.keys, p.vals, p.alt_k, p.alt_v, p.pair_count, cap, kb, odd, p.sort_ws, st);
         launch_tile_ranges(p.keys, p.pair_count, cap, tile, p.ranges, st);
         RenderArgs r;

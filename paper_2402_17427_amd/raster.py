@@ -99,6 +99,7 @@ class Frame:
         self.depth = torch.empty(n1, dtype=torch.float32, device=device)
         self.rect = torch.empty(n1 * 4, dtype=torch.int16, device=device)
         self.tiles_touched = torch.empty(n1, dtype=torch.int32, device=device)
+        self.first = torch.empty(n1, dtype=torch.int32, device=device)
         self.ranges = torch.empty(self.n_tiles * 2, dtype=torch.int32, device=device)
         self.pair_count = torch.zeros(2, dtype=torch.int32, device=device)
         self.status = torch.zeros(1, dtype=torch.int32, device=device)
@@ -116,7 +117,7 @@ class Frame:
         self.grad2d = torch.empty((9, ng), dtype=torch.float32, device=device)
         self.has_grads = grads
         self.capacity = 0
-        self.keys = self.vals = self.ws = None
+        self.keys = self.vals = self.ws = self.bwd_ws = None
         self.set_capacity(capacity if capacity is not None else max(2 * self.n, 1 << 16))
         del npix
 
@@ -131,6 +132,11 @@ class Frame:
         nbytes = C.c_size_t(0)
         N.call("gs_bin_sort_workspace", self.n, cap, self.n_tiles, C.byref(nbytes))
         self.ws = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=self.device)
+        if self.has_grads:
+            N.call("gs_render_bwd_workspace", C.byref(self.c_bins()), C.byref(nbytes))
+            # float32 storage keeps the 16-byte alignment the ABI asks for
+            self.bwd_ws = torch.empty(max((int(nbytes.value) + 15) // 16 * 4, 4), dtype=torch.float32,
+                                      device=self.device)
 
     def c_proj(self) -> N.gs_proj:
         p = N.gs_proj()
@@ -141,6 +147,7 @@ class Frame:
     def c_bins(self) -> N.gs_bins:
         b = N.gs_bins()
         b.keys, b.vals, b.ranges = _ptr(self.keys), _ptr(self.vals), _ptr(self.ranges)
+        b.first = _ptr(self.first)
         b.pair_count, b.status = _ptr(self.pair_count), _ptr(self.status)
         b.pair_capacity = self.capacity
         return b
@@ -172,7 +179,8 @@ class Frame:
         assert dimg.shape == (3, self.H, self.W) and dimg.dtype == torch.float32 and dimg.is_contiguous()
         N.call("gs_render_bwd", C.byref(g.c_struct()), C.byref(self.c_cam), C.byref(self.c_opts),
                C.byref(self.c_proj()), C.byref(self.c_bins()), _ptr(self.final_T), _ptr(self.n_contrib),
-               _ptr(dimg), C.byref(self.c_grads()), C.c_void_p(stream_handle(stream)))
+               _ptr(dimg), C.byref(self.c_grads()), _ptr(self.bwd_ws), self.bwd_ws.numel() * 4,
+               C.c_void_p(stream_handle(stream)))
 
     def stats(self, stream=None) -> dict:
         """Blend work counters of the current bins (synchronises)."""
@@ -198,7 +206,7 @@ class Frame:
         N.call("gs_render_bwd_stored", C.byref(g.c_struct()), C.byref(self.c_cam), C.byref(self.c_opts),
                C.byref(self.c_proj()), C.byref(self.c_bins()), _ptr(self.final_T), _ptr(self.n_contrib),
                _ptr(state), state.numel() * state.element_size(), _ptr(dimg), C.byref(self.c_grads()),
-               C.c_void_p(stream_handle(stream)))
+               _ptr(self.bwd_ws), self.bwd_ws.numel() * 4, C.c_void_p(stream_handle(stream)))
 
     def forward(self, g: DeviceGaussians, stream=None):
         self.project(g, stream)
