@@ -242,10 +242,12 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
                 const uint64_t cm = __ballot(contrib);
                 if (cm == 0ull) continue;
                 // row sums, spread over the row's lanes 0..8, added into the
-                // tile's LDS accumulator of the row's entry (a row that
-                // walked nothing adds zeros)
+                // tile's LDS accumulator of the row's entry
                 const float2 r = row_sum9(mx, my, mx * e.dx, mx * e.dy, my * e.dy, v5, v6, v7, v8, b0, b1, b2);
-                if (l16 <= 8) atomicAdd(s_acc + (__umul24((uint32_t)kk, 9u) + (uint32_t)l16), l16 == 8 ? r.y : r.x);
+                // LDS float atomics cost about one cycle per active lane:
+                // rows without a contributing pixel add nothing
+                if (l16 <= 8 && ((cm >> (lane & 48)) & 0xFFFFull) != 0ull)
+                    atomicAdd(s_acc + (__umul24((uint32_t)kk, 9u) + (uint32_t)l16), l16 == 8 ? r.y : r.x);
             }
         }
         __syncthreads();
