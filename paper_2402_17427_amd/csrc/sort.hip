@@ -12,12 +12,15 @@
 //   k_hist        one read of every key builds the histograms of all
 //                 passes at once (LDS atomics, then one global atomic per
 //                 non-empty bin and workgroup)
-//   k_hist_scan   exclusive scan of each pass's 256 bins
+//   k_hist_scan   exclusive scan of each pass's 256 bins (one workgroup
+//                 per pass)
 //   k_onesweep    per pass: each workgroup takes the next partition of
 //                 4096 keys from an atomic counter, ranks its keys stably
 //                 with wave64 ballots (match-by-digit), publishes its digit
 //                 counts and resolves its global offsets by decoupled
-//                 look-back over the earlier partitions, sorts the
+//                 look-back over the earlier partitions (a window of
+//                 eight per step, so the walk is not one dependent load
+//                 per partition), sorts the
 //                 partition locally in LDS and writes it out digit run by
 //                 digit run (coalesced).
 // The pair count stays on the device; grids are sized for the capacity
@@ -39,6 +42,7 @@ constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1u;
 constexpr int kMaxGrid = 2048;
+constexpr int kLook = 8;                        // look-back window (partitions per step)
 
 struct SortWs {
     int64_t capacity;    // pairs the buffers hold; the device count is clamped to it
@@ -94,23 +98,25 @@ __global__ __launch_bounds__(256) void k_hist(const uint64_t* __restrict__ keys,
         if (h[j]) atomicAdd(&w.hist[j], h[j]);
 }
 
-__global__ __launch_bounds__(kRadix) void k_hist_scan(SortWs w, int passes) {
-    __shared__ uint32_t s[kRadix];
-    const int t = threadIdx.x;
-    for (int p = 0; p < passes; ++p) {
-        const uint32_t v = w.hist[p * kRadix + t];
-        s[t] = v;
-        __syncthreads();
-        // Hillis-Steele inclusive scan over 256 entries
-        for (int d = 1; d < kRadix; d <<= 1) {
-            const uint32_t y = t >= d ? s[t - d] : 0u;
-            __syncthreads();
-            s[t] += y;
-            __syncthreads();
-        }
-        w.hist[p * kRadix + t] = s[t] - v;
-        __syncthreads();
+// One workgroup per pass: exclusive scan of the pass's 256 digit counts.
+__global__ __launch_bounds__(kRadix) void k_hist_scan(SortWs w) {
+    __shared__ uint32_t s_w[kRadix / kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
+    uint32_t* h = w.hist + blockIdx.x * kRadix;
+    const uint32_t v = h[t];
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
     }
+    if (lane == kWave - 1) s_w[wv] = x;
+    __syncthreads();
+    uint32_t base = 0;
+#pragma unroll
+    for (int q = 0; q < kRadix / kWave; ++q)
+        if (q < wv) base += s_w[q];
+    h[t] = base + x - v;
 }
 
 __device__ __forceinline__ uint64_t ballot64(bool b) { return __ballot(b); }
@@ -195,18 +201,32 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
                 s_dbase[t] = goff[t];
             } else {
                 store_relaxed(&look[part * kRadix + t], kFlagAgg | total);
+                // look back over a window of kLook earlier partitions per
+                // step (independent loads), nearest first: add published
+                // counts until an inclusive prefix; stop at a partition
+                // that has published nothing yet and read again from it
                 uint32_t prefix = 0;
                 int64_t j = part - 1;
                 while (j >= 0) {
-                    const uint32_t v = load_relaxed(&look[j * kRadix + t]);
-                    const uint32_t flag = v & ~kValMask;
-                    if (flag == 0u) {
-                        __builtin_amdgcn_s_sleep(1);
-                        continue;
+                    uint32_t v[kLook];
+#pragma unroll
+                    for (int q = 0; q < kLook; ++q)
+                        v[q] = j - q >= 0 ? load_relaxed(&look[(j - q) * kRadix + t]) : kFlagInc;
+                    int q = 0;
+                    bool stalled = false;
+#pragma unroll
+                    for (; q < kLook; ++q) {
+                        const uint32_t flag = v[q] & ~kValMask;
+                        if (flag == 0u) {
+                            stalled = true;
+                            break;
+                        }
+                        prefix += v[q] & kValMask;
+                        if (flag == kFlagInc) break;
                     }
-                    prefix += v & kValMask;
-                    if (flag == kFlagInc) break;
-                    --j;
+                    if (!stalled && q < kLook) break;   // reached an inclusive prefix
+                    j -= q;
+                    if (stalled) __builtin_amdgcn_s_sleep(1);
                 }
                 store_relaxed(&look[part * kRadix + t], kFlagInc | (prefix + total));
                 s_dbase[t] = goff[t] + prefix;
@@ -291,7 +311,7 @@ void launch_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint3
     int64_t hb = (capacity + 256 * 16 - 1) / (256 * 16);
     if (hb > kMaxGrid) hb = kMaxGrid;
     hipLaunchKernelGGL(k_hist, dim3((unsigned)hb), dim3(256), 0, st, src, count, passes, w);
-    hipLaunchKernelGGL(k_hist_scan, dim3(1), dim3(kRadix), 0, st, w, passes);
+    hipLaunchKernelGGL(k_hist_scan, dim3((unsigned)passes), dim3(kRadix), 0, st, w);
     int64_t grid = parts < kMaxGrid ? parts : kMaxGrid;
     bool in_alt = start_in_alt;
     for (int p = 0; p < passes; ++p) {
