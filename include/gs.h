@@ -368,13 +368,18 @@ gs_status gs_render_stats(const gs_proj *proj, const gs_bins *bins, const gs_cam
 
 /* Stage timing (observability).  gs_profile_enable(1) starts a window in
  * which every stage the library enqueues (project, scan_emit, sort,
- * tile_ranges, render_fwd, grad_zero, render_bwd, project_bwd, ...) is
- * bracketed by HIP events on its stream; gs_profile_enable(0) ends it and
- * discards what was recorded.  gs_profile_report() waits for the recorded
+ * tile_ranges, render_fwd, pair_zero, render_bwd, pair_gather,
+ * project_bwd, ...) is bracketed by HIP events on its stream;
+ * gs_profile_enable(0) ends it and discards what was recorded.
+ * gs_profile_select(stages) restricts the bracketing to the stages named
+ * in a comma-separated list (NULL or "" = all); each event pair adds a
+ * few microseconds between kernels, so a timing of the whole step brackets
+ * only the stage it needs.  gs_profile_report() waits for the recorded
  * events and writes a JSON object {"stage": [total_ms, launches], ...} of
  * the window so far into buf (host, len bytes), then starts counting
  * afresh.  Process-wide; calls from several threads are serialised. */
 gs_status gs_profile_enable(int on);
+gs_status gs_profile_select(const char *stages);
 gs_status gs_profile_report(char *buf, size_t len);
 
 #ifdef __cplusplus

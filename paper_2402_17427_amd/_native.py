@@ -88,6 +88,7 @@ _SIGS = {
                              P],
     "gs_render_stats": [C.POINTER(gs_proj), C.POINTER(gs_bins), C.POINTER(gs_camera), C.POINTER(gs_opts), P, P],
     "gs_profile_enable": [C.c_int],
+    "gs_profile_select": [C.c_char_p],
     "gs_profile_report": [C.c_char_p, C.c_size_t],
 }
 _RESTYPES = {"gs_last_error": C.c_char_p, "gs_abi_version": C.c_int}
@@ -155,6 +156,11 @@ def make_opts(tile_w=16, tile_h=16) -> gs_opts:
 
 def profile_enable(on: bool) -> None:
     call("gs_profile_enable", 1 if on else 0)
+
+
+def profile_select(stages=None) -> None:
+    """Bracket only the named stages (None: all)."""
+    call("gs_profile_select", ",".join(stages).encode() if stages else None)
 
 
 def profile_report() -> dict:

@@ -25,6 +25,12 @@ struct Pending {
 struct Profiler {
     std::mutex mu;
     bool on = false;
+    std::string only;   // ",a,b," : bracket only these stages; empty: all
+
+    bool wanted(const char* name) const {
+        if (only.empty()) return true;
+        return only.find("," + std::string(name) + ",") != std::string::npos;
+    }
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
 
@@ -50,7 +56,7 @@ Profiler& prof() {
 ProfScope::ProfScope(const char* name, hipStream_t st) : name_(name), st_(st), a_(nullptr) {
     Profiler& p = prof();
     std::lock_guard<std::mutex> lk(p.mu);
-    if (!p.on) return;
+    if (!p.on || !p.wanted(name)) return;
     a_ = p.get();
     if (a_ && hipEventRecord(static_cast<hipEvent_t>(a_), st) != hipSuccess) a_ = nullptr;
 }
@@ -80,6 +86,19 @@ gs_status gs_profile_enable(int on) {
     }
     p.pending.clear();
     p.on = on != 0;
+    return GS_OK;
+}
+
+gs_status gs_profile_select(const char* stages) {
+    Profiler& p = prof();
+    std::lock_guard<std::mutex> lk(p.mu);
+    p.only.clear();
+    if (stages && *stages) {
+        p.only = ",";
+        for (const char* c = stages; *c; ++c)
+            if (*c != ' ') p.only += *c;
+        p.only += ",";
+    }
     return GS_OK;
 }
 
