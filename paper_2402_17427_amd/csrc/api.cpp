@@ -229,24 +229,21 @@ gs_status gs_bin_sort(const gs_proj* proj, int64_t n, const gs_camera* cam, cons
     uint32_t* alt_v = reinterpret_cast<uint32_t*>(p);
     p += align256((size_t)cap * 4);
     void* sort_ws = p;
-    const int kb = 32 + tile_bits(n_tiles);
-    const bool odd = sort_passes(kb) % 2 == 1;
+    const int tb = tile_bits(n_tiles);
+    const bool to_alt = bin_sort_emit_to_alt(tb);
     {
         ProfScope ps("scan_emit", st);
         Gauss G0;
         std::memset(&G0, 0, sizeof G0);
         G0.n = n;
         launch_emit_pairs(n, proj->tiles_touched, reinterpret_cast<const ushort4*>(proj->rect), proj->depth,
-                          single_job(G0, nullptr), single_view(C, tw, th), cap, odd ? alt_k : out->keys,
-                          odd ? alt_v : out->vals, out->first, out->pair_count, out->status, scan_ws, st);
+                          single_job(G0, nullptr), single_view(C, tw, th), cap, to_alt ? alt_k : out->keys,
+                          to_alt ? alt_v : out->vals, out->first, out->pair_count, out->status, scan_ws, st);
     }
     {
         ProfScope ps("sort", st);
-        launch_sort_pairs(out->keys, out->vals, alt_k, alt_v, out->pair_count, cap, kb, odd, sort_ws, st);
-    }
-    {
-        ProfScope ps("tile_ranges", st);
-        launch_tile_ranges(out->keys, out->pair_count, cap, n_tiles, out->ranges, st);
+        launch_bin_sort(out->keys, out->vals, alt_k, alt_v, out->pair_count, cap, tb, out->ranges, n_tiles, sort_ws,
+                        st);
     }
     return check_hip("gs_bin_sort");
 }

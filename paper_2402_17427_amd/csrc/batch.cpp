@@ -162,12 +162,10 @@ struct gs_batch {
         return t;
     }
 
-    int key_bits() const { return 32 + tile_bits(n_tiles); }
-
     void enqueue_project_bin(hipStream_t st) {
         launch_project(jt(), vt(), K, nslots, tw, th, rec, depth, rect, tt, st);
-        const bool odd = sort_passes(key_bits()) % 2 == 1;
-        launch_emit_pairs(nslots, tt, rect, depth, jt(), vt(), capacity, odd ? alt_k : keys, odd ? alt_v : vals,
+        const bool to_alt = bin_sort_emit_to_alt(tile_bits(n_tiles));
+        launch_emit_pairs(nslots, tt, rect, depth, jt(), vt(), capacity, to_alt ? alt_k : keys, to_alt ? alt_v : vals,
                           first, pair_count, status, scan_ws, st);
     }
 
@@ -175,9 +173,8 @@ struct gs_batch {
     // L1 loss gradient, blend backward, projection backward.
     void enqueue_step(hipStream_t st) {
         enqueue_project_bin(st);
-        const int kb = key_bits();
-        launch_sort_pairs(keys, vals, alt_k, alt_v, pair_count, capacity, kb, sort_passes(kb) % 2 == 1, sort_ws, st);
-        launch_tile_ranges(keys, pair_count, capacity, n_tiles, ranges, st);
+        launch_bin_sort(keys, vals, alt_k, alt_v, pair_count, capacity, tile_bits(n_tiles), ranges, n_tiles, sort_ws,
+                        st);
         RenderArgs r;
         std::memset(&r, 0, sizeof r);
         r.rec = rec;

@@ -46,6 +46,16 @@ int sort_passes(int key_bits);
 void launch_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals,
                        const uint32_t* count, int64_t capacity, int key_bits, bool start_in_alt, void* ws,
                        hipStream_t st);
+// Binning sort of emitted (tile << 32 | depth bits, index) pairs: a stable
+// radix sort on the tile bits, per-tile ranges, then each tile's run sorted
+// stably by depth inside one workgroup -- the order of a stable sort on the
+// whole key.  The emission must go to (alt_keys, alt_vals) when
+// bin_sort_emit_to_alt(tile_bits), else to (keys, vals); the sorted pairs
+// end in (keys, vals) and `ranges` [n_tiles][2] is written.  `ws` holds
+// sort_workspace_bytes(capacity, 32 + tile_bits) bytes.
+bool bin_sort_emit_to_alt(int tile_bits);
+void launch_bin_sort(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals, const uint32_t* count,
+                     int64_t capacity, int tile_bits, uint32_t* ranges, int64_t n_tiles, void* ws, hipStream_t st);
 
 // ---- blend (render_fwd.hip / render_bwd.hip)
 // What both blend passes read: records, sorted values, per-tile ranges of

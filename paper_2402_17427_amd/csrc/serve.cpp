@@ -274,13 +274,12 @@ struct gs_server {
             slot = 0;
         }
         const int64_t cap = p.pairs_cap;
-        const int kb = 32 + tile_bits(std::max<uint32_t>(tile, 1));
-        const bool odd = sort_passes(kb) % 2 == 1;
+        const int tb = tile_bits(std::max<uint32_t>(tile, 1));
+        const bool to_alt = bin_sort_emit_to_alt(tb);
         launch_project(jt, vt, scene.K, slot, tw, th, p.rec, p.depth, p.rect, p.tt, st);
-        launch_emit_pairs(slot, p.tt, p.rect, p.depth, jt, vt, cap, odd ? p.alt_k : p.keys, odd ? p.alt_v : p.vals,
-                          nullptr, p.pair_count, p.status, p.scan_ws, st);
-        launch_sort_pairs(p.keys, p.vals, p.alt_k, p.alt_v, p.pair_count, cap, kb, odd, p.sort_ws, st);
-        launch_tile_ranges(p.keys, p.pair_count, cap, tile, p.ranges, st);
+        launch_emit_pairs(slot, p.tt, p.rect, p.depth, jt, vt, cap, to_alt ? p.alt_k : p.keys,
+                          to_alt ? p.alt_v : p.vals, nullptr, p.pair_count, p.status, p.scan_ws, st);
+        launch_bin_sort(p.keys, p.vals, p.alt_k, p.alt_v, p.pair_count, cap, tb, p.ranges, tile, p.sort_ws, st);
         RenderArgs r;
         std::memset(&r, 0, sizeof r);
         r.rec = p.rec;

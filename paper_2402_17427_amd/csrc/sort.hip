@@ -83,26 +83,27 @@ __global__ __launch_bounds__(256) void k_sort_clear(SortWs w, const uint32_t* __
         for (int64_t j = tid; j < parts * kRadix; j += stride) w.look[(int64_t)p * w.max_parts * kRadix + j] = 0u;
 }
 
+// Digit histograms of passes p0 .. p1-1 in one read of the keys.
 __global__ __launch_bounds__(256) void k_hist(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ count,
-                                              int passes, SortWs w) {
+                                              int p0, int p1, SortWs w) {
     __shared__ uint32_t h[kMaxPasses * kRadix];
-    for (int j = threadIdx.x; j < passes * kRadix; j += 256) h[j] = 0u;
+    for (int j = threadIdx.x; j < kMaxPasses * kRadix; j += 256) h[j] = 0u;
     __syncthreads();
     const int64_t P = clamp_count(count, w.capacity);
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256) {
         const uint64_t k = keys[i];
-        for (int p = 0; p < passes; ++p) atomicAdd(&h[p * kRadix + (uint32_t)((k >> (8 * p)) & 0xFF)], 1u);
+        for (int p = p0; p < p1; ++p) atomicAdd(&h[p * kRadix + (uint32_t)((k >> (8 * p)) & 0xFF)], 1u);
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < passes * kRadix; j += 256)
+    for (int j = p0 * kRadix + threadIdx.x; j < p1 * kRadix; j += 256)
         if (h[j]) atomicAdd(&w.hist[j], h[j]);
 }
 
 // One workgroup per pass: exclusive scan of the pass's 256 digit counts.
-__global__ __launch_bounds__(kRadix) void k_hist_scan(SortWs w) {
+__global__ __launch_bounds__(kRadix) void k_hist_scan(SortWs w, int p0) {
     __shared__ uint32_t s_w[kRadix / kWave];
     const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
-    uint32_t* h = w.hist + blockIdx.x * kRadix;
+    uint32_t* h = w.hist + (p0 + (int)blockIdx.x) * kRadix;
     const uint32_t v = h[t];
     uint32_t x = v;
 #pragma unroll
@@ -281,6 +282,149 @@ __global__ __launch_bounds__(256) void k_copy_pairs(const uint64_t* __restrict__
     }
 }
 
+// ---- per-tile depth sort -------------------------------------------------
+// After the stable sort on the tile bits, each tile's run is in emission
+// order; sorting the run stably by the low 32 key bits (the depth) gives
+// exactly the order of the stable sort on the whole key.
+
+constexpr int kSegThreads = 256;
+constexpr int kSegCap = 2048;   // longest run sorted in LDS
+
+// Runs of 2 .. kSegCap pairs: bitonic sort in LDS of (depth << 32 | position
+// in the run), distinct keys, so the result is the stable order; then the
+// values are gathered by position.
+__global__ __launch_bounds__(kSegThreads) void k_seg_sort_lds(const uint64_t* __restrict__ kin,
+                                                              const uint32_t* __restrict__ vin,
+                                                              uint64_t* __restrict__ kout,
+                                                              uint32_t* __restrict__ vout,
+                                                              const uint2* __restrict__ ranges) {
+    __shared__ uint64_t s[kSegCap];
+    const uint2 r = ranges[blockIdx.x];
+    const uint32_t n = r.y - r.x;
+    if (n == 0u || n > (uint32_t)kSegCap) return;
+    const int tid = threadIdx.x;
+    const uint64_t tile_hi = kin[r.x] & 0xFFFFFFFF00000000ull;
+    if (n == 1u) {
+        if (tid == 0) {
+            kout[r.x] = kin[r.x];
+            vout[r.x] = vin[r.x];
+        }
+        return;
+    }
+    uint32_t m = 2;
+    while (m < n) m <<= 1;
+    for (uint32_t i = tid; i < m; i += kSegThreads)
+        s[i] = i < n ? ((kin[r.x + i] & 0xFFFFFFFFull) << 32) | i : ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= m; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = tid; i < (m >> 1); i += kSegThreads) {
+                const uint32_t lo = ((i & ~(j - 1)) << 1) | (i & (j - 1)), hi = lo + j;
+                const uint64_t a = s[lo], b = s[hi];
+                const bool up = (lo & k) == 0u;
+                if ((a > b) == up) {
+                    s[lo] = b;
+                    s[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = tid; i < n; i += kSegThreads) {
+        const uint64_t c = s[i];
+        kout[r.x + i] = tile_hi | (c >> 32);
+        vout[r.x + i] = vin[r.x + (uint32_t)c];
+    }
+}
+
+// Runs longer than kSegCap: one workgroup sorts the run stably by its
+// 32 depth bits with four 8-bit LSD passes over global memory, 256 pairs
+// at a time in order (ballot match ranks within a wave, per-wave digit
+// counts order the waves), ping-ponging between the two buffers; the
+// fourth pass ends in the input buffers, copied out at the end.
+__global__ __launch_bounds__(kSegThreads) void k_seg_sort_long(uint64_t* __restrict__ ka, uint32_t* __restrict__ va,
+                                                               uint64_t* __restrict__ kb, uint32_t* __restrict__ vb,
+                                                               const uint2* __restrict__ ranges) {
+    __shared__ uint32_t s_start[kRadix];   // digit start in the run
+    __shared__ uint32_t s_run[kRadix];     // pairs of each digit placed so far
+    __shared__ uint32_t s_wc[kSegThreads / kWave][kRadix];
+    __shared__ uint32_t s_w[kRadix / kWave];
+    const uint2 r = ranges[blockIdx.x];
+    const uint32_t n = r.y - r.x;
+    if (n <= (uint32_t)kSegCap) return;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int pass = 0; pass < 4; ++pass) {
+        const uint64_t* ki = (pass & 1) ? kb : ka;
+        const uint32_t* vi = (pass & 1) ? vb : va;
+        uint64_t* ko = (pass & 1) ? ka : kb;
+        uint32_t* vo = (pass & 1) ? va : vb;
+        const int shift = 8 * pass;
+        // digit counts of the run and their exclusive scan
+        s_start[tid] = 0u;
+        s_run[tid] = 0u;
+        for (int q = 0; q < kSegThreads / kWave; ++q) s_wc[q][tid] = 0u;
+        __syncthreads();
+        for (uint32_t i = tid; i < n; i += kSegThreads)
+            atomicAdd(&s_start[(uint32_t)(ki[r.x + i] >> shift) & 0xFFu], 1u);
+        __syncthreads();
+        {
+            const uint32_t v = s_start[tid];
+            uint32_t x = v;
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t y = __shfl_up(x, d, kWave);
+                if (lane >= d) x += y;
+            }
+            if (lane == kWave - 1) s_w[wv] = x;
+            __syncthreads();
+            uint32_t base = 0;
+            for (int q = 0; q < kRadix / kWave; ++q)
+                if (q < wv) base += s_w[q];
+            s_start[tid] = base + x - v;
+        }
+        __syncthreads();
+        for (uint32_t c0 = 0; c0 < n; c0 += kSegThreads) {
+            const uint32_t i = c0 + (uint32_t)tid;
+            const bool ok = i < n;
+            const uint64_t key = ok ? ki[r.x + i] : 0ull;
+            const uint32_t val = ok ? vi[r.x + i] : 0u;
+            const uint32_t d = (uint32_t)(key >> shift) & 0xFFu;
+            uint64_t mt = __ballot(ok);
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t vote = __ballot(bit);
+                mt &= bit ? vote : ~vote;
+            }
+            const uint32_t below = (uint32_t)__popcll(mt & lt_mask);
+            if (ok && below == 0u) s_wc[wv][d] = (uint32_t)__popcll(mt);
+            __syncthreads();
+            if (ok) {
+                uint32_t pos = s_start[d] + s_run[d] + below;
+                for (int q = 0; q < kSegThreads / kWave; ++q)
+                    if (q < wv) pos += s_wc[q][d];
+                ko[r.x + pos] = key;
+                vo[r.x + pos] = val;
+            }
+            __syncthreads();
+            uint32_t add = 0;
+            for (int q = 0; q < kSegThreads / kWave; ++q) {
+                add += s_wc[q][tid];
+                s_wc[q][tid] = 0u;
+            }
+            s_run[tid] += add;
+            __syncthreads();
+        }
+        // the next pass reads what this one wrote (same workgroup)
+        __threadfence_block();
+        __syncthreads();
+    }
+    // four passes: the run is back in (ka, va); the result goes to (kb, vb)
+    for (uint32_t i = tid; i < n; i += kSegThreads) {
+        kb[r.x + i] = ka[r.x + i];
+        vb[r.x + i] = va[r.x + i];
+    }
+}
+
 }  // namespace
 
 int sort_passes(int key_bits) { return (key_bits + 7) / 8; }
@@ -292,29 +436,28 @@ size_t sort_workspace_bytes(int64_t capacity, int key_bits) {
            align256((size_t)passes * (size_t)(parts > 0 ? parts : 1) * kRadix * 4);
 }
 
-void launch_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals, const uint32_t* count,
-                       int64_t capacity, int key_bits, bool start_in_alt, void* ws, hipStream_t st) {
-    const int passes = sort_passes(key_bits);
-    if (passes == 0 || capacity == 0) {
-        if (start_in_alt && capacity > 0)
-            hipLaunchKernelGGL(k_copy_pairs, dim3(1024), dim3(256), 0, st, alt_keys, alt_vals, keys, vals, count,
-                               capacity);
-        return;
-    }
-    SortWs w = carve(ws, capacity, passes);
+namespace {
+
+// Passes p0 .. p1-1 (digits 8 p .. 8 p + 7) of the stable LSD sort, reading
+// the alternate buffers first when `start_in_alt`.  Returns whether the
+// result sits in the alternate buffers.
+bool radix_passes(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals, const uint32_t* count,
+                  int64_t capacity, int p0, int p1, bool start_in_alt, void* ws, hipStream_t st) {
+    if (p1 <= p0 || capacity == 0) return start_in_alt;
+    SortWs w = carve(ws, capacity, p1);
     const int64_t parts = (capacity + kPart - 1) / kPart;
     int64_t clear_blocks = (parts * kRadix + 255) / 256;
     if (clear_blocks > 1024) clear_blocks = 1024;
     if (clear_blocks < 1) clear_blocks = 1;
-    hipLaunchKernelGGL(k_sort_clear, dim3((unsigned)clear_blocks), dim3(256), 0, st, w, count, passes);
+    hipLaunchKernelGGL(k_sort_clear, dim3((unsigned)clear_blocks), dim3(256), 0, st, w, count, p1);
     const uint64_t* src = start_in_alt ? alt_keys : keys;
     int64_t hb = (capacity + 256 * 16 - 1) / (256 * 16);
     if (hb > kMaxGrid) hb = kMaxGrid;
-    hipLaunchKernelGGL(k_hist, dim3((unsigned)hb), dim3(256), 0, st, src, count, passes, w);
-    hipLaunchKernelGGL(k_hist_scan, dim3((unsigned)passes), dim3(kRadix), 0, st, w);
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)hb), dim3(256), 0, st, src, count, p0, p1, w);
+    hipLaunchKernelGGL(k_hist_scan, dim3((unsigned)(p1 - p0)), dim3(kRadix), 0, st, w, p0);
     int64_t grid = parts < kMaxGrid ? parts : kMaxGrid;
     bool in_alt = start_in_alt;
-    for (int p = 0; p < passes; ++p) {
+    for (int p = p0; p < p1; ++p) {
         const uint64_t* ki = in_alt ? alt_keys : keys;
         const uint32_t* vi = in_alt ? alt_vals : vals;
         uint64_t* ko = in_alt ? keys : alt_keys;
@@ -322,9 +465,39 @@ void launch_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint3
         hipLaunchKernelGGL(k_onesweep, dim3((unsigned)grid), dim3(kSortThreads), 0, st, ki, vi, ko, vo, count, p, w);
         in_alt = !in_alt;
     }
+    return in_alt;
+}
+
+}  // namespace
+
+void launch_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals, const uint32_t* count,
+                       int64_t capacity, int key_bits, bool start_in_alt, void* ws, hipStream_t st) {
+    if (capacity == 0) return;
+    const bool in_alt = radix_passes(keys, vals, alt_keys, alt_vals, count, capacity, 0, sort_passes(key_bits),
+                                     start_in_alt, ws, st);
     if (in_alt)  // result sits in the alternate buffers
         hipLaunchKernelGGL(k_copy_pairs, dim3(1024), dim3(256), 0, st, alt_keys, alt_vals, keys, vals, count,
-                               capacity);
+                           capacity);
+}
+
+int bin_tile_passes(int tile_bits) { return (tile_bits + 7) / 8; }
+
+bool bin_sort_emit_to_alt(int tile_bits) { return bin_tile_passes(tile_bits) % 2 == 0; }
+
+void launch_bin_sort(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals, const uint32_t* count,
+                     int64_t capacity, int tile_bits, uint32_t* ranges, int64_t n_tiles, void* ws, hipStream_t st) {
+    // tile bits: passes 4 .. 4 + ceil(tile_bits / 8) - 1, ending in the
+    // alternate buffers (the emission went where bin_sort_emit_to_alt says)
+    const bool in_alt = radix_passes(keys, vals, alt_keys, alt_vals, count, capacity, 4, 4 + bin_tile_passes(tile_bits),
+                                     bin_sort_emit_to_alt(tile_bits), ws, st);
+    (void)in_alt;   // always true
+    launch_tile_ranges(alt_keys, count, capacity, n_tiles, ranges, st);
+    if (capacity == 0 || n_tiles == 0) return;
+    const uint2* rg = reinterpret_cast<const uint2*>(ranges);
+    hipLaunchKernelGGL(k_seg_sort_lds, dim3((unsigned)n_tiles), dim3(kSegThreads), 0, st, alt_keys, alt_vals, keys,
+                       vals, rg);
+    hipLaunchKernelGGL(k_seg_sort_long, dim3((unsigned)n_tiles), dim3(kSegThreads), 0, st, alt_keys, alt_vals, keys,
+                       vals, rg);
 }
 
 }  // namespace gs

@@ -61,6 +61,10 @@ def _scene(name):
         return scenes.small_city(n=20_000, seed=11, width=200, height=150)
     if name == "city_white":
         return scenes.small_city(n=8_000, seed=12, width=97, height=61, bg=(1.0, 1.0, 1.0))
+    if name == "city_dense":
+        # the whole city in a 40x30 image: thousands of Gaussians per tile,
+        # so tile runs are longer than the in-LDS per-tile sort handles
+        return scenes.small_city(n=20_000, seed=13, width=40, height=30)
     raise KeyError(name)
 
 
@@ -95,7 +99,7 @@ def test_projection_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name,tile", [("config1", (16, 16)), ("city_ragged", (16, 16)), ("city_ragged", (8, 8)),
-                                       ("city_ragged", (32, 8))])
+                                       ("city_ragged", (32, 8)), ("city_dense", (16, 16)), ("city_dense", (8, 8))])
 def test_bins_match_oracle_bit_exact(name, tile):
     _case(f"bins {name} tile={tile}")
     g, cam = _scene(name)
@@ -111,11 +115,13 @@ def test_bins_match_oracle_bit_exact(name, tile):
     np.testing.assert_array_equal(keys, b["keys"])
     np.testing.assert_array_equal(vals, b["vals"])
     np.testing.assert_array_equal(ranges, b["ranges"])
+    runs = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+    print(f"[case] longest tile run {runs.max()}", flush=True)
 
 
 # --------------------------------------------------------------- forward --
 
-@pytest.mark.parametrize("name", ["config1", "city_ragged", "city_white"])
+@pytest.mark.parametrize("name", ["config1", "city_ragged", "city_white", "city_dense"])
 def test_forward_image_matches_oracle(name):
     _case(f"forward {name}")
     g, cam = _scene(name)
