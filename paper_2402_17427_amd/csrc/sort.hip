@@ -288,49 +288,115 @@ __global__ __launch_bounds__(256) void k_copy_pairs(const uint64_t* __restrict__
 // exactly the order of the stable sort on the whole key.
 
 constexpr int kSegThreads = 256;
-constexpr int kSegCap = 2048;   // longest run sorted in LDS
+constexpr int kSegCap = 1024;   // longest run sorted in LDS
 
-// Runs of 2 .. kSegCap pairs: bitonic sort in LDS of (depth << 32 | position
-// in the run), distinct keys, so the result is the stable order; then the
-// values are gathered by position.
-__global__ __launch_bounds__(kSegThreads) void k_seg_sort_lds(const uint64_t* __restrict__ kin,
-                                                              const uint32_t* __restrict__ vin,
-                                                              uint64_t* __restrict__ kout,
-                                                              uint32_t* __restrict__ vout,
-                                                              const uint2* __restrict__ ranges) {
+// Runs of 1 .. kSegCap pairs, one wave each, sorted in LDS by a stable LSD
+// radix sort on the 32 depth bits: up to four 8-bit passes, skipping the
+// bytes on which the whole run agrees (a stable pass over a constant digit
+// leaves the order as it is).  Entries are (depth << 32 | position in the
+// run), ranked in order 64 at a time with ballot matches and running digit
+// counts; the values are gathered by position at the end.  One wave per
+// run: no workgroup barriers, and the loops stop at the run's length.
+__global__ __launch_bounds__(kWave) void k_seg_sort_lds(const uint64_t* __restrict__ kin,
+                                                        const uint32_t* __restrict__ vin,
+                                                        uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                        const uint2* __restrict__ ranges) {
+    constexpr int IPL = kSegCap / kWave;   // entries per lane
+    constexpr int DPL = kRadix / kWave;    // digits per lane in the offset scan
     __shared__ uint64_t s[kSegCap];
+    __shared__ uint32_t s_cnt[kRadix];     // digit counts, then digit offsets
     const uint2 r = ranges[blockIdx.x];
     const uint32_t n = r.y - r.x;
     if (n == 0u || n > (uint32_t)kSegCap) return;
-    const int tid = threadIdx.x;
-    const uint64_t tile_hi = kin[r.x] & 0xFFFFFFFF00000000ull;
+    const int lane = threadIdx.x;
     if (n == 1u) {
-        if (tid == 0) {
+        if (lane == 0) {
             kout[r.x] = kin[r.x];
             vout[r.x] = vin[r.x];
         }
         return;
     }
-    uint32_t m = 2;
-    while (m < n) m <<= 1;
-    for (uint32_t i = tid; i < m; i += kSegThreads)
-        s[i] = i < n ? ((kin[r.x + i] & 0xFFFFFFFFull) << 32) | i : ~0ull;
-    __syncthreads();
-    for (uint32_t k = 2; k <= m; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = tid; i < (m >> 1); i += kSegThreads) {
-                const uint32_t lo = ((i & ~(j - 1)) << 1) | (i & (j - 1)), hi = lo + j;
-                const uint64_t a = s[lo], b = s[hi];
-                const bool up = (lo & k) == 0u;
-                if ((a > b) == up) {
-                    s[lo] = b;
-                    s[hi] = a;
-                }
-            }
-            __syncthreads();
-        }
+    const uint64_t tile_hi = kin[r.x] & 0xFFFFFFFF00000000ull;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t z0 = (uint32_t)kin[r.x];
+    const int nq = (int)((n + kWave - 1) / kWave);
+    uint32_t vary = 0;
+    for (uint32_t i = lane; i < n; i += kWave) {
+        const uint32_t z = (uint32_t)kin[r.x + i];
+        s[i] = ((uint64_t)z << 32) | i;
+        vary |= z ^ z0;
     }
-    for (uint32_t i = tid; i < n; i += kSegThreads) {
+    // OR over the wave
+    for (int d = 1; d < kWave; d <<= 1) vary |= (uint32_t)__shfl_xor((int)vary, d, kWave);
+    __builtin_amdgcn_wave_barrier();
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 32 + 8 * pass;
+        if (((vary >> (8 * pass)) & 0xFFu) == 0u) continue;
+        uint64_t it[IPL];
+        uint32_t rk[IPL];
+#pragma unroll
+        for (int q = 0; q < IPL; ++q) {
+            const uint32_t idx = (uint32_t)(q * kWave + lane);
+            it[q] = (q < nq && idx < n) ? s[idx] : 0ull;
+        }
+#pragma unroll
+        for (int e = 0; e < DPL; ++e) s_cnt[e * kWave + lane] = 0u;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < IPL; ++q) {
+            if (q < nq) {
+                const uint32_t idx = (uint32_t)(q * kWave + lane);
+                const bool ok = idx < n;
+                const uint32_t d = (uint32_t)(it[q] >> shift) & 0xFFu;
+                uint64_t mt = __ballot(ok);
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const bool bit = (d >> b) & 1u;
+                    const uint64_t vote = __ballot(bit);
+                    mt &= bit ? vote : ~vote;
+                }
+                const uint32_t below = (uint32_t)__popcll(mt & lt_mask);
+                const uint32_t old = ok ? s_cnt[d] : 0u;
+                rk[q] = old + below;
+                __builtin_amdgcn_wave_barrier();
+                if (ok && below == 0u) s_cnt[d] = old + (uint32_t)__popcll(mt);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        // digit offsets: lane l owns digits l*DPL .. l*DPL + DPL - 1
+        {
+            uint32_t c[DPL], sum = 0;
+#pragma unroll
+            for (int e = 0; e < DPL; ++e) {
+                c[e] = s_cnt[lane * DPL + e];
+                sum += c[e];
+            }
+            uint32_t x = sum;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t y = __shfl_up(x, d, kWave);
+                if (lane >= d) x += y;
+            }
+            uint32_t run = x - sum;
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int e = 0; e < DPL; ++e) {
+                s_cnt[lane * DPL + e] = run;
+                run += c[e];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < IPL; ++q) {
+            const uint32_t idx = (uint32_t)(q * kWave + lane);
+            if (q < nq && idx < n) {
+                const uint32_t d = (uint32_t)(it[q] >> shift) & 0xFFu;
+                s[s_cnt[d] + rk[q]] = it[q];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    for (uint32_t i = lane; i < n; i += kWave) {
         const uint64_t c = s[i];
         kout[r.x + i] = tile_hi | (c >> 32);
         vout[r.x + i] = vin[r.x + (uint32_t)c];
@@ -494,8 +560,8 @@ void launch_bin_sort(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_
     launch_tile_ranges(alt_keys, count, capacity, n_tiles, ranges, st);
     if (capacity == 0 || n_tiles == 0) return;
     const uint2* rg = reinterpret_cast<const uint2*>(ranges);
-    hipLaunchKernelGGL(k_seg_sort_lds, dim3((unsigned)n_tiles), dim3(kSegThreads), 0, st, alt_keys, alt_vals, keys,
-                       vals, rg);
+    hipLaunchKernelGGL(k_seg_sort_lds, dim3((unsigned)n_tiles), dim3(kWave), 0, st, alt_keys, alt_vals, keys, vals,
+                       rg);
     hipLaunchKernelGGL(k_seg_sort_long, dim3((unsigned)n_tiles), dim3(kSegThreads), 0, st, alt_keys, alt_vals, keys,
                        vals, rg);
 }
