@@ -65,7 +65,37 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-grid", type=int, default=10, help="merged scene: grid x grid cells of 200k Gaussians")
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, run one elementwise kernel that reads and writes MIB MiB "
+                         "(float32): the reference that scales the HBM byte counters of a profiling run")
     return ap.parse_args()
+
+
+def traffic_record(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the kernel's sources have changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_cell_1M_1080p.md")
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    for ln in lines:
+        if not ln.startswith("traffic-record: "):
+            continue
+        rec = json.loads(ln[len("traffic-record: "):])
+        if rec.get("kernel") != kernel:
+            continue
+        h = hashlib.sha256()
+        try:
+            for src in rec["sources"]:
+                with open(os.path.join(ROOT, src), "rb") as fh:
+                    h.update(fh.read())
+        except OSError:
+            return None
+        if h.hexdigest() == rec["sources_sha256"]:
+            return int(rec["bytes_per_launch"])
+    return None
 
 
 def cpu_baseline(g, cam, stride):
@@ -339,6 +369,15 @@ def main():
     npix = cam.width * cam.height
     value = npix / (ms * 1e-3) / 1e6
 
+    if args.copy_calib > 0:
+        # one elementwise kernel that reads MIB MiB and writes MIB MiB
+        src = torch.ones(args.copy_calib * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
     stats = frame.stats()
     dom_ms = dprof[dom][0] / dprof[dom][1]
     if dom == "render_bwd":
@@ -348,11 +387,15 @@ def main():
     else:
         work = None
     roof = None
+    # measured HBM bytes per launch (counter summary), only for the workload
+    # and kernel sources it was taken on
+    default_cell = (args.n == 1_000_000 and args.width == 1920 and args.height == 1080 and tuple(args.tile) == (16, 16))
+    traffic = traffic_record(dom) if default_cell else None
     if work is not None:
         achieved = work / (dom_ms * 1e-3) / 1e12     # T lane-ops/s
         peak = VALU_PEAK_GOPS / 1e3
         roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "Tlane-op/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "Tlane-op/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "work_lane_ops": int(work), "avg_ms": round(dom_ms, 4)}
 
     out = {

@@ -155,9 +155,19 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, Staged
         }
     }
     if (STATS) {
-        atomicAdd(&a.stats[0], n_eval);
-        atomicAdd(&a.stats[1], n_supp);
-        atomicAdd(&a.stats[2], n_blend);
+        // one atomic per counter and wave (same-address atomics from every
+        // lane serialise)
+        uint32_t e32 = (uint32_t)n_eval, s32 = (uint32_t)n_supp, b32 = (uint32_t)n_blend;
+        for (int d = 1; d < kWave; d <<= 1) {
+            e32 += (uint32_t)__shfl_xor((int)e32, d, kWave);
+            s32 += (uint32_t)__shfl_xor((int)s32, d, kWave);
+            b32 += (uint32_t)__shfl_xor((int)b32, d, kWave);
+        }
+        if ((threadIdx.x & (kWave - 1)) == 0) {
+            atomicAdd(&a.stats[0], (unsigned long long)e32);
+            atomicAdd(&a.stats[1], (unsigned long long)s32);
+            atomicAdd(&a.stats[2], (unsigned long long)b32);
+        }
     } else if (inside) {
         image[off] = __builtin_fmaf(T, V.cam.bg[0], c0);
         image[npix + off] = __builtin_fmaf(T, V.cam.bg[1], c1);
