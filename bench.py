@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=32, help="oracle pixel sample: every n-th row and column")
+    ap.add_argument("--cpu-stride", type=int, default=22, help="oracle pixel sample: every n-th row and column")
     ap.add_argument("--tile", type=int, nargs=2, default=(16, 16))
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--width", type=int, default=1920)
