@@ -201,12 +201,6 @@ __global__ __launch_bounds__(kProjThreads) void k_project(JobTab jobs, ViewTab v
     }
     const float o = G.opacity[i];
     fin = fin && isfinite(o);
-    float coef[3 * K];
-#pragma unroll
-    for (int j = 0; j < 3 * K; ++j) {
-        coef[j] = G.sh[(int64_t)j * ld + i];
-        fin = fin && isfinite(coef[j]);
-    }
 
     Rec out;
     out.u = 0.0; out.v = 0.0;
@@ -237,11 +231,20 @@ __global__ __launch_bounds__(kProjThreads) void k_project(JobTab jobs, ViewTab v
             const double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             float Y[16];
             sh_basis((float)(d[0] / dn), (float)(d[1] / dn), (float)(d[2] / dn), Y);
+            // the SH coefficients are read only here, for Gaussians that
+            // survive the geometry, and consumed as they arrive (a
+            // non-finite coefficient culls the Gaussian like any other
+            // non-finite input)
             float col[3];
+            bool fin_sh = true;
             for (int ch = 0; ch < 3; ++ch) {
                 float acc = 0.f;
 #pragma unroll
-                for (int j = 0; j < K; ++j) acc += coef[ch * K + j] * Y[j];
+                for (int j = 0; j < K; ++j) {
+                    const float cf = G.sh[(int64_t)(ch * K + j) * ld + i];
+                    fin_sh = fin_sh && isfinite(cf);
+                    acc += cf * Y[j];
+                }
                 col[ch] = fmaxf(acc + 0.5f, 0.0f);
             }
             out.r = col[0]; out.g = col[1]; out.b = col[2];
@@ -255,7 +258,13 @@ __global__ __launch_bounds__(kProjThreads) void k_project(JobTab jobs, ViewTab v
             y0 = fmax(y0, 0.0);
             x1 = fmin(x1, (double)(cam.W - 1));
             y1 = fmin(y1, (double)(cam.H - 1));
-            if (x0 <= x1 && y0 <= y1) {
+            if (!fin_sh) {   // culled: the record as for a non-finite input
+                out.u = out.v = 0.0;
+                out.A = out.B = out.C = 0.f;
+                out.r = out.g = out.b = 0.f;
+                out.thr = 0.f;
+                z = 0.f;
+            } else if (x0 <= x1 && y0 <= y1) {
                 const int tx0 = (int)x0 / tw, tx1 = (int)x1 / tw + 1;
                 const int ty0 = (int)y0 / th, ty1 = (int)y1 / th + 1;
                 rc = make_ushort4((unsigned short)tx0, (unsigned short)ty0, (unsigned short)tx1, (unsigned short)ty1);
