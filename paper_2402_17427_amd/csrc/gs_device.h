@@ -163,35 +163,26 @@ __device__ __forceinline__ Eval eval_pair(const Staged& s, float x, float y) {
 // Can the staged Gaussian reach alpha >= 1/255 at some point of the
 // rectangle [x0, x1] x [y0, y1] (image coordinates; the rectangle spanned by
 // a block's pixel centres)?  The base-2 exponent q(d) = ca dx^2 + cb dx dy +
-// cc dy^2 is a concave quadratic of the offset d; its maximum over the
-// rectangle is at the centre when the centre lies inside, else on an edge,
-// where it is the clamped vertex of a 1D parabola.  The answer is
+// cc dy^2 is a concave quadratic of the offset d with its maximum 0 at the
+// centre.  Along the segment from any point of the rectangle towards the
+// centre q does not decrease, so the maximum over the rectangle lies where
+// the rectangle faces the centre: on the x-face at X = clamp(0, ax, bx) or
+// the y-face at Y = clamp(0, ay, by) (offsets; when the centre's x lies
+// within the rectangle that "face" is an inner line, which can only lower
+// the bound, and when the centre lies inside both give q = 0).  On each, q
+// is a 1D parabola maximised at its clamped vertex.  The answer is
 // conservative: the comparison with thr carries a margin far above the FP32
 // error of q, and the continuous rectangle contains every pixel centre.
 __device__ __forceinline__ bool box_overlaps(const Staged& s, float x0, float x1, float y0, float y1) {
     const float u = s.geo.x + s.geo.y, v = s.geo.z + s.geo.w;
     const float ax = x0 - u, bx = x1 - u, ay = y0 - v, by = y1 - v;
-    if (ax <= 0.f && bx >= 0.f && ay <= 0.f && by >= 0.f) return true;
     const float ca = s.coef.x, cb = s.coef.y, cc = s.coef.z;
     const float kx = -0.5f * cb * __builtin_amdgcn_rcpf(cc);   // vertex of q along x = X: y* = kx X
     const float ky = -0.5f * cb * __builtin_amdgcn_rcpf(ca);   // vertex of q along y = Y: x* = ky Y
-    float m = -3.0e38f;
-#define GS_EDGE_X(X)                                               \
-    {                                                             \
-        const float y = fminf(fmaxf(kx * (X), ay), by);           \
-        m = fmaxf(m, ca * (X) * (X) + cb * (X) * y + cc * y * y); \
-    }
-#define GS_EDGE_Y(Y)                                               \
-    {                                                             \
-        const float x = fminf(fmaxf(ky * (Y), ax), bx);           \
-        m = fmaxf(m, ca * x * x + cb * x * (Y) + cc * (Y) * (Y)); \
-    }
-    GS_EDGE_X(ax)
-    GS_EDGE_X(bx)
-    GS_EDGE_Y(ay)
-    GS_EDGE_Y(by)
-#undef GS_EDGE_X
-#undef GS_EDGE_Y
+    const float X = fminf(fmaxf(0.0f, ax), bx), Y = fminf(fmaxf(0.0f, ay), by);
+    const float yx = fminf(fmaxf(kx * X, ay), by);
+    const float xy = fminf(fmaxf(ky * Y, ax), bx);
+    const float m = fmaxf(ca * X * X + cb * X * yx + cc * yx * yx, ca * xy * xy + cb * xy * Y + cc * Y * Y);
     return m >= s.col.w - (1e-3f + 1e-4f * fabsf(m));
 }
 
