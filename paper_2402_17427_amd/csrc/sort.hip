@@ -8,7 +8,8 @@
 //
 // Structure (8-bit digits, one kernel per digit pass):
 //   k_sort_clear  zero the digit histograms, partition counters and
-//                 look-back words for the pair count on the device
+//                 look-back words of the passes to run, for the pair count
+//                 on the device
 //   k_hist        one read of every key builds the histograms of all
 //                 passes at once (LDS atomics, then one global atomic per
 //                 non-empty bin and workgroup)
@@ -73,13 +74,15 @@ __device__ __forceinline__ int64_t clamp_count(const uint32_t* count, int64_t ca
     return c < capacity ? c : capacity;
 }
 
-__global__ __launch_bounds__(256) void k_sort_clear(SortWs w, const uint32_t* __restrict__ count, int passes) {
+// Zero the histograms, partition counters and look-back words of passes
+// p0 .. p1-1 for the pair count on the device.
+__global__ __launch_bounds__(256) void k_sort_clear(SortWs w, const uint32_t* __restrict__ count, int p0, int p1) {
     const int64_t P = clamp_count(count, w.capacity);
     const int64_t parts = ((int64_t)P + kPart - 1) / kPart;
     const int64_t tid = (int64_t)blockIdx.x * 256 + threadIdx.x, stride = (int64_t)gridDim.x * 256;
-    for (int64_t j = tid; j < (int64_t)passes * kRadix; j += stride) w.hist[j] = 0u;
-    for (int64_t j = tid; j < passes; j += stride) w.counter[j] = 0u;
-    for (int p = 0; p < passes; ++p)
+    for (int64_t j = p0 * kRadix + tid; j < (int64_t)p1 * kRadix; j += stride) w.hist[j] = 0u;
+    for (int64_t j = p0 + tid; j < p1; j += stride) w.counter[j] = 0u;
+    for (int p = p0; p < p1; ++p)
         for (int64_t j = tid; j < parts * kRadix; j += stride) w.look[(int64_t)p * w.max_parts * kRadix + j] = 0u;
 }
 
@@ -512,10 +515,10 @@ bool radix_passes(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* 
     if (p1 <= p0 || capacity == 0) return start_in_alt;
     SortWs w = carve(ws, capacity, p1);
     const int64_t parts = (capacity + kPart - 1) / kPart;
-    int64_t clear_blocks = (parts * kRadix + 255) / 256;
+    int64_t clear_blocks = (parts * kRadix * (p1 - p0) + 255) / 256;
     if (clear_blocks > 1024) clear_blocks = 1024;
     if (clear_blocks < 1) clear_blocks = 1;
-    hipLaunchKernelGGL(k_sort_clear, dim3((unsigned)clear_blocks), dim3(256), 0, st, w, count, p1);
+    hipLaunchKernelGGL(k_sort_clear, dim3((unsigned)clear_blocks), dim3(256), 0, st, w, count, p0, p1);
     const uint64_t* src = start_in_alt ? alt_keys : keys;
     int64_t hb = (capacity + 256 * 16 - 1) / (256 * 16);
     if (hb > kMaxGrid) hb = kMaxGrid;
