@@ -68,3 +68,45 @@ def test_host_validation_rejects_bad_descriptors_without_a_device():
     bins.pair_capacity = 1 << 31
     assert lib.gs_render_fwd(C.byref(proj), C.byref(bins), C.byref(cam), None, None, None, None,
                              None) == N.GS_ERR_INVALID
+
+
+def test_backward_workspace_query_and_validation_without_a_device():
+    """gs_render_bwd_workspace sizes the per-pair gradient slots (36 bytes
+    per pair of capacity); gs_render_bwd rejects a missing, short or
+    misaligned workspace and a NULL bins.first before any launch (the
+    device pointers below are never dereferenced)."""
+    lib = N.lib()
+    fake = 1 << 20   # 256-byte aligned stand-in for device buffers
+    bins = N.gs_bins()
+    bins.keys, bins.vals, bins.first = fake, fake, fake
+    bins.ranges, bins.pair_count, bins.status = fake, fake, fake
+    bins.pair_capacity = 1000
+    nbytes = C.c_size_t(0)
+    assert lib.gs_render_bwd_workspace(C.byref(bins), C.byref(nbytes)) == N.GS_OK
+    assert nbytes.value == 36 * 1000
+    assert lib.gs_render_bwd_workspace(None, C.byref(nbytes)) == N.GS_ERR_INVALID
+
+    g = N.gs_gaussians()
+    g.n, g.ld, g.sh_degree = 10, 10, 0
+    g.mean = g.scale = g.quat = g.opacity = g.sh = fake
+    cam = N.gs_camera()
+    cam.width, cam.height, cam.fx, cam.fy, cam.near_z = 64, 64, 100.0, 100.0, 0.2
+    cam.R[0] = cam.R[4] = cam.R[8] = 1.0
+    proj = N.gs_proj()
+    proj.rec, proj.depth, proj.rect, proj.tiles_touched = fake, fake, fake, fake
+    out = N.gs_grads()
+    out.ld = 10
+    out.mean = out.scale = out.quat = out.opacity = out.sh = out.grad2d = fake
+
+    def bwd(ws, ws_bytes):
+        return lib.gs_render_bwd(C.byref(g), C.byref(cam), None, C.byref(proj), C.byref(bins), fake, fake, fake,
+                                 C.byref(out), ws, ws_bytes, None)
+
+    assert bwd(None, 0) == N.GS_ERR_INVALID
+    assert b"workspace" in lib.gs_last_error()
+    assert bwd(fake, 36 * 1000 - 4) == N.GS_ERR_INVALID
+    assert bwd(fake + 4, 36 * 1000) == N.GS_ERR_INVALID
+    assert b"aligned" in lib.gs_last_error()
+    bins.first = None
+    assert bwd(fake, 36 * 1000) == N.GS_ERR_INVALID
+    assert b"first" in lib.gs_last_error()

@@ -297,3 +297,27 @@ def test_full_size_cell_sampled_pixels_match_oracle():
     assert live.sum() > 50
     for k in ("mean", "opacity", "sh"):
         grad_close(k, gr[k].cpu().numpy()[..., live], rb[k][..., live])
+
+
+def test_profile_select_brackets_only_the_named_stages():
+    _case("profile select")
+    g, cam = _scene("city_ragged")
+    dg = raster.DeviceGaussians.from_host(g)
+    f = raster.Frame(g.n, g.sh_degree, cam)
+    f.ensure_capacity(dg)
+    try:
+        N.profile_select(["render_fwd"])
+        N.profile_enable(True)
+        f.forward(dg)
+        torch.cuda.synchronize()
+        rep = N.profile_report()
+        assert set(rep) == {"render_fwd"}, rep
+        assert rep["render_fwd"][1] == 1 and rep["render_fwd"][0] > 0.0
+        N.profile_select(None)
+        f.forward(dg)
+        torch.cuda.synchronize()
+        rep = N.profile_report()
+        assert {"project", "scan_emit", "sort", "render_fwd"} <= set(rep), rep
+    finally:
+        N.profile_enable(False)
+        N.profile_select(None)
