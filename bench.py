@@ -6,8 +6,8 @@ arXiv 2402.17427, section 4.1 cells; section 3 renderer): 1,000,000
 Gaussians with SH degree 3 on a 200 m x 200 m synthetic city heightfield,
 one aerial view at 150 m altitude pitched -45 deg, 1920x1080, 16x16 tiles.
 A step is one pass of the whole hot path: projection (EWA + SH), key
-emission, onesweep radix sort, tile ranges, forward blend, backward blend
-and the projection backward, with dL/dImage precomputed and every input
+emission, sort (onesweep radix on the tile bits, per-tile depth sort), tile
+ranges, forward blend, backward blend and the projection backward, with dL/dImage precomputed and every input
 resident in HBM before timing.
 
 Prints one JSON line: metric value in Mpix/s (W*H per fwd+bwd step),

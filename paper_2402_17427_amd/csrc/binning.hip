@@ -14,6 +14,7 @@ namespace {
 
 constexpr int kScanThreads = 256;
 constexpr int kScanTopThreads = 1024;
+constexpr int kScanTopItems = 4;
 
 // Block-wide exclusive scan of one uint32 per thread (wave64 prefix via
 // shuffles, then a scan of the wave totals).  Returns the exclusive prefix;
@@ -56,13 +57,24 @@ __global__ __launch_bounds__(kScanThreads) void k_block_sums(const uint32_t* __r
 __global__ __launch_bounds__(kScanTopThreads) void k_scan_top(uint64_t* __restrict__ block_sums, int64_t nb,
                                                               int64_t capacity, uint32_t* __restrict__ pair_count,
                                                               int32_t* __restrict__ status) {
+    // kScanTopItems consecutive sums per thread, so that one block-wide scan
+    // covers up to kScanTopThreads * kScanTopItems of them
     uint64_t carry = 0;
-    for (int64_t base = 0; base < nb; base += kScanTopThreads) {
-        const int64_t i = base + threadIdx.x;
-        const uint64_t v = i < nb ? block_sums[i] : 0u;
+    for (int64_t base = 0; base < nb; base += (int64_t)kScanTopThreads * kScanTopItems) {
+        const int64_t i0 = base + (int64_t)threadIdx.x * kScanTopItems;
+        uint64_t v[kScanTopItems], sum = 0;
+#pragma unroll
+        for (int e = 0; e < kScanTopItems; ++e) {
+            v[e] = i0 + e < nb ? block_sums[i0 + e] : 0u;
+            sum += v[e];
+        }
         uint64_t tot;
-        const uint64_t ex = block_exclusive_scan<kScanTopThreads>(v, &tot);
-        if (i < nb) block_sums[i] = carry + ex;
+        uint64_t run = carry + block_exclusive_scan<kScanTopThreads>(sum, &tot);
+#pragma unroll
+        for (int e = 0; e < kScanTopItems; ++e) {
+            if (i0 + e < nb) block_sums[i0 + e] = run;
+            run += v[e];
+        }
         carry += tot;
     }
     if (threadIdx.x == 0) {
@@ -142,8 +154,8 @@ void launch_emit_pairs(int64_t n, const uint32_t* tt, const ushort4* rect, const
 }
 
 void launch_tile_ranges(const uint64_t* keys, const uint32_t* pair_count, int64_t capacity, int64_t n_tiles,
-                        uint32_t* ranges, hipStream_t st) {
-    launch_fill_u32(ranges, 0u, (size_t)n_tiles * 2, st);
+                        uint32_t* ranges, hipStream_t st, bool zeroed) {
+    if (!zeroed) launch_fill_u32(ranges, 0u, (size_t)n_tiles * 2, st);
     if (capacity == 0) return;
     const int64_t blocks = (capacity + 255) / 256;
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)blocks), dim3(256), 0, st, keys, pair_count, capacity, n_tiles,

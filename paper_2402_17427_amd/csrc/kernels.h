@@ -31,8 +31,9 @@ size_t scan_workspace_bytes(int64_t n);
 void launch_emit_pairs(int64_t n, const uint32_t* tiles_touched, const ushort4* rect, const float* depth,
                        const JobTab& jobs, const ViewTab& views, int64_t capacity, uint64_t* keys, uint32_t* vals,
                        uint32_t* first, uint32_t* pair_count, int32_t* status, void* scan_ws, hipStream_t st);
+// Per-tile [start, end) of sorted keys; `zeroed`: ranges already hold zeros.
 void launch_tile_ranges(const uint64_t* keys, const uint32_t* pair_count, int64_t capacity, int64_t n_tiles,
-                        uint32_t* ranges, hipStream_t st);
+                        uint32_t* ranges, hipStream_t st, bool zeroed = false);
 void launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t st);
 
 // ---- radix sort (sort.hip)

@@ -75,11 +75,14 @@ __device__ __forceinline__ int64_t clamp_count(const uint32_t* count, int64_t ca
 }
 
 // Zero the histograms, partition counters and look-back words of passes
-// p0 .. p1-1 for the pair count on the device.
-__global__ __launch_bounds__(256) void k_sort_clear(SortWs w, const uint32_t* __restrict__ count, int p0, int p1) {
+// p0 .. p1-1 for the pair count on the device, and zero_count words of
+// `zero` (saves the caller a launch).
+__global__ __launch_bounds__(256) void k_sort_clear(SortWs w, const uint32_t* __restrict__ count, int p0, int p1,
+                                                    uint32_t* __restrict__ zero, int64_t zero_count) {
     const int64_t P = clamp_count(count, w.capacity);
     const int64_t parts = ((int64_t)P + kPart - 1) / kPart;
     const int64_t tid = (int64_t)blockIdx.x * 256 + threadIdx.x, stride = (int64_t)gridDim.x * 256;
+    for (int64_t j = tid; j < zero_count; j += stride) zero[j] = 0u;   // a caller's buffer (tile ranges)
     for (int64_t j = p0 * kRadix + tid; j < (int64_t)p1 * kRadix; j += stride) w.hist[j] = 0u;
     for (int64_t j = p0 + tid; j < p1; j += stride) w.counter[j] = 0u;
     for (int p = p0; p < p1; ++p)
@@ -145,8 +148,18 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
     const uint32_t* goff = w.hist + pass * kRadix;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-    for (;;) {
-        if (tid == 0) s_part = (int64_t)atomicAdd(&w.counter[pass], 1u);
+    // When the grid covers every partition, workgroup b takes partition b
+    // (workgroups are dispatched in index order, so the partitions a
+    // look-back waits for are already running or done); otherwise they are
+    // handed out in order by an atomic counter.
+    const bool one_each = (int64_t)gridDim.x >= nparts;
+    for (int round = 0;; ++round) {
+        if (one_each) {
+            if (round > 0) break;
+            s_part = (int64_t)blockIdx.x;
+        } else if (tid == 0) {
+            s_part = (int64_t)atomicAdd(&w.counter[pass], 1u);
+        }
         __syncthreads();
         const int64_t part = s_part;
         if (part >= nparts) break;
@@ -510,15 +523,19 @@ namespace {
 // Passes p0 .. p1-1 (digits 8 p .. 8 p + 7) of the stable LSD sort, reading
 // the alternate buffers first when `start_in_alt`.  Returns whether the
 // result sits in the alternate buffers.
-bool radix_passes(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals, const uint32_t* count,
-                  int64_t capacity, int p0, int p1, bool start_in_alt, void* ws, hipStream_t st) {
-    if (p1 <= p0 || capacity == 0) return start_in_alt;
+// `zero` (zero_count u32 words, may be NULL) is cleared by the first kernel
+// when any pass runs; the return value then has bit 1 set.
+int radix_passes(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals, const uint32_t* count,
+                 int64_t capacity, int p0, int p1, bool start_in_alt, void* ws, hipStream_t st,
+                 uint32_t* zero = nullptr, int64_t zero_count = 0) {
+    if (p1 <= p0 || capacity == 0) return start_in_alt ? 1 : 0;
     SortWs w = carve(ws, capacity, p1);
     const int64_t parts = (capacity + kPart - 1) / kPart;
     int64_t clear_blocks = (parts * kRadix * (p1 - p0) + 255) / 256;
     if (clear_blocks > 1024) clear_blocks = 1024;
     if (clear_blocks < 1) clear_blocks = 1;
-    hipLaunchKernelGGL(k_sort_clear, dim3((unsigned)clear_blocks), dim3(256), 0, st, w, count, p0, p1);
+    hipLaunchKernelGGL(k_sort_clear, dim3((unsigned)clear_blocks), dim3(256), 0, st, w, count, p0, p1, zero,
+                       zero ? zero_count : (int64_t)0);
     const uint64_t* src = start_in_alt ? alt_keys : keys;
     int64_t hb = (capacity + 256 * 16 - 1) / (256 * 16);
     if (hb > kMaxGrid) hb = kMaxGrid;
@@ -534,7 +551,7 @@ bool radix_passes(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* 
         hipLaunchKernelGGL(k_onesweep, dim3((unsigned)grid), dim3(kSortThreads), 0, st, ki, vi, ko, vo, count, p, w);
         in_alt = !in_alt;
     }
-    return in_alt;
+    return (in_alt ? 1 : 0) | 2;
 }
 
 }  // namespace
@@ -542,8 +559,8 @@ bool radix_passes(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* 
 void launch_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals, const uint32_t* count,
                        int64_t capacity, int key_bits, bool start_in_alt, void* ws, hipStream_t st) {
     if (capacity == 0) return;
-    const bool in_alt = radix_passes(keys, vals, alt_keys, alt_vals, count, capacity, 0, sort_passes(key_bits),
-                                     start_in_alt, ws, st);
+    const bool in_alt = (radix_passes(keys, vals, alt_keys, alt_vals, count, capacity, 0, sort_passes(key_bits),
+                                      start_in_alt, ws, st) & 1) != 0;
     if (in_alt)  // result sits in the alternate buffers
         hipLaunchKernelGGL(k_copy_pairs, dim3(1024), dim3(256), 0, st, alt_keys, alt_vals, keys, vals, count,
                            capacity);
@@ -557,10 +574,10 @@ void launch_bin_sort(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_
                      int64_t capacity, int tile_bits, uint32_t* ranges, int64_t n_tiles, void* ws, hipStream_t st) {
     // tile bits: passes 4 .. 4 + ceil(tile_bits / 8) - 1, ending in the
     // alternate buffers (the emission went where bin_sort_emit_to_alt says)
-    const bool in_alt = radix_passes(keys, vals, alt_keys, alt_vals, count, capacity, 4, 4 + bin_tile_passes(tile_bits),
-                                     bin_sort_emit_to_alt(tile_bits), ws, st);
-    (void)in_alt;   // always true
-    launch_tile_ranges(alt_keys, count, capacity, n_tiles, ranges, st);
+    // (the first pass's clear also zeroes the tile ranges)
+    const int r = radix_passes(keys, vals, alt_keys, alt_vals, count, capacity, 4, 4 + bin_tile_passes(tile_bits),
+                               bin_sort_emit_to_alt(tile_bits), ws, st, ranges, n_tiles * 2);
+    launch_tile_ranges(alt_keys, count, capacity, n_tiles, ranges, st, (r & 2) != 0);
     if (capacity == 0 || n_tiles == 0) return;
     const uint2* rg = reinterpret_cast<const uint2*>(ranges);
     hipLaunchKernelGGL(k_seg_sort_lds, dim3((unsigned)n_tiles), dim3(kWave), 0, st, alt_keys, alt_vals, keys, vals,
