@@ -321,3 +321,48 @@ def test_profile_select_brackets_only_the_named_stages():
     finally:
         N.profile_enable(False)
         N.profile_select(None)
+
+
+def _degenerate_scene():
+    """A reduced city (SH degree 3) with seven visible Gaussians made
+    degenerate: non-finite mean, scale and SH coefficient, a zero quaternion
+    and an opacity below 1/255 (all culled by the projection), a zero scale
+    (only the 2D dilation remains) and a very large scale (many tiles)."""
+    g, cam = scenes.small_city(n=3000, seed=21, width=96, height=64)
+    vis = np.nonzero(oracle.project(g, cam)["valid"])[0]
+    i = vis[[0, 5, 10, 15, 20, 25, 30]]
+    g.mean[0, i[0]] = np.nan
+    g.scale[1, i[1]] = np.inf
+    g.quat[:, i[2]] = 0.0
+    g.sh[5, i[3]] = np.nan
+    g.opacity[i[4]] = 1e-3
+    g.scale[:, i[5]] = 0.0
+    g.scale[:, i[6]] = 4.0
+    return g, cam, i
+
+
+def test_degenerate_gaussians_match_the_oracle():
+    _case("degenerate inputs")
+    g, cam, idx = _degenerate_scene()
+    culled = idx[:5]
+    ref = oracle.project(g, cam)
+    assert not ref["valid"][culled].any() and ref["valid"][idx[5:]].all()
+    dg = raster.DeviceGaussians.from_host(g)
+    f = raster.Frame(g.n, g.sh_degree, cam)
+    P = f.ensure_capacity(dg)
+    b = oracle.bin(g, cam)
+    assert not b["amb"].any()
+    assert P == b["keys"].size
+    np.testing.assert_array_equal(f.keys.cpu().numpy().view(np.uint64)[:P], b["keys"])
+    np.testing.assert_array_equal(f.vals.cpu().numpy().view(np.uint32)[:P], b["vals"])
+    tt = f.tiles_touched.cpu().numpy().view(np.uint32)[: g.n]
+    assert (tt[culled] == 0).all() and tt[idx[6]] > 4
+    f.render_fwd()
+    torch.cuda.synchronize()
+    r = oracle.render(g, cam)
+    image_close("degenerate", f.image.cpu().numpy(), r["image"], r["flags"])
+    out, rb, keep = _backward_case(g, cam)
+    for k in ("mean", "scale", "quat", "opacity", "sh"):
+        assert np.isfinite(out[k]).all(), k
+        assert (out[k][..., culled] == 0).all(), k
+        grad_close(k, out[k][..., keep], rb[k][..., keep])
