@@ -122,38 +122,37 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, Staged
             uint64_t mm = row == 0 ? m0 : (row == 1 ? m1 : (row == 2 ? m2 : m3));
             if (((lv >> (16 * row)) & 0xFFFFull) == 0ull) mm = 0ull;   // this row's pixels have all stopped
             while (__ballot(mm != 0ull) != 0ull) {
-                bool stopped_now = false;
-                if (mm != 0ull) {
-                    const int kk = c0k + (int)__builtin_ctzll(mm);
-                    mm &= mm - 1;
-                    const Staged g = staged_at(s, kk);
-                    // branch-free per pixel: a stopped pixel, or an entry
-                    // below the alpha threshold, changes nothing
-                    const Eval e = eval_pair(g, fx, fy);
-                    if (MODE == kStore && !done)
-                        a.state[(int64_t)(b0 + (uint32_t)kk) * NT + tid] =
-                            make_float2(e.capped && e.alpha > 0.0f ? -e.alpha : e.alpha, T);
-                    const bool supp = !done && e.alpha > 0.0f;
-                    const float Tn = T * (1.0f - e.alpha);
-                    const bool stop = supp && Tn < kTMin;
-                    const bool blend = supp && !stop;
-                    if (STATS) {
-                        n_eval += done ? 0u : 1u;
-                        n_supp += supp ? 1u : 0u;
-                        n_blend += blend ? 1u : 0u;
-                    }
-                    const float w = blend ? e.alpha * T : 0.0f;
-                    c0 = __builtin_fmaf(g.col.x, w, c0);
-                    c1 = __builtin_fmaf(g.col.y, w, c1);
-                    c2 = __builtin_fmaf(g.col.z, w, c2);
-                    T = blend ? Tn : T;
-                    last = blend ? b0 - rg.x + (uint32_t)kk + 1u : last;
-                    done = done || stop;
-                    stopped_now = stop;
+                // branch-free: a row with nothing left evaluates entry
+                // c0k and, like a stopped pixel or an entry below the
+                // alpha threshold, changes nothing
+                const bool has = mm != 0ull;
+                const int kk = c0k + (has ? (int)__builtin_ctzll(mm) : 0);
+                mm &= mm - 1;
+                const bool act = has && !done;
+                const Staged g = staged_at(s, kk);
+                const Eval e = eval_pair(g, fx, fy);
+                if (MODE == kStore && act)
+                    a.state[(int64_t)(b0 + (uint32_t)kk) * NT + tid] =
+                        make_float2(e.capped && e.alpha > 0.0f ? -e.alpha : e.alpha, T);
+                const bool supp = act && e.alpha > 0.0f;
+                const float Tn = T * (1.0f - e.alpha);
+                const bool stop = supp && Tn < kTMin;
+                const bool blend = supp && !stop;
+                if (STATS) {
+                    n_eval += act ? 1u : 0u;
+                    n_supp += supp ? 1u : 0u;
+                    n_blend += blend ? 1u : 0u;
                 }
-                // a row whose pixels have all stopped leaves its walk (checked
-                // only when some pixel of the wave stopped just now)
-                if (__ballot(stopped_now) != 0ull) {
+                const float w = blend ? e.alpha * T : 0.0f;
+                c0 = __builtin_fmaf(g.col.x, w, c0);
+                c1 = __builtin_fmaf(g.col.y, w, c1);
+                c2 = __builtin_fmaf(g.col.z, w, c2);
+                T = blend ? Tn : T;
+                last = blend ? b0 - rg.x + (uint32_t)kk + 1u : last;
+                done = done || stop;
+                // a row whose pixels have all stopped leaves its walk
+                // (checked only when some pixel of the wave stopped now)
+                if (__ballot(stop) != 0ull) {
                     const uint64_t lv2 = __ballot(!done);
                     if (((lv2 >> (16 * row)) & 0xFFFFull) == 0ull) mm = 0ull;
                 }
