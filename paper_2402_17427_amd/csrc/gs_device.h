@@ -173,12 +173,20 @@ __device__ __forceinline__ Eval eval_pair(const Staged& s, float x, float y) {
 // is a 1D parabola maximised at its clamped vertex.  The answer is
 // conservative: the comparison with thr carries a margin far above the FP32
 // error of q, and the continuous rectangle contains every pixel centre.
-__device__ __forceinline__ bool box_overlaps(const Staged& s, float x0, float x1, float y0, float y1) {
-    const float u = s.geo.x + s.geo.y, v = s.geo.z + s.geo.w;
+// What the test below needs of a staged Gaussian beyond its coefficients:
+// the centre (u, v) and the slopes of the vertex lines of q, y* = kx X along
+// x = X and x* = ky Y along y = Y.  Computed once per staged entry.
+__device__ __forceinline__ float4 stage_cull(const Staged& s) {
+    return make_float4(s.geo.x + s.geo.y, s.geo.z + s.geo.w, -0.5f * s.coef.y * __builtin_amdgcn_rcpf(s.coef.z),
+                       -0.5f * s.coef.y * __builtin_amdgcn_rcpf(s.coef.x));
+}
+
+__device__ __forceinline__ bool box_overlaps(const Staged& s, const float4& cu, float x0, float x1, float y0,
+                                             float y1) {
+    const float u = cu.x, v = cu.y;
     const float ax = x0 - u, bx = x1 - u, ay = y0 - v, by = y1 - v;
     const float ca = s.coef.x, cb = s.coef.y, cc = s.coef.z;
-    const float kx = -0.5f * cb * __builtin_amdgcn_rcpf(cc);   // vertex of q along x = X: y* = kx X
-    const float ky = -0.5f * cb * __builtin_amdgcn_rcpf(ca);   // vertex of q along y = Y: x* = ky Y
+    const float kx = cu.z, ky = cu.w;
     const float X = fminf(fmaxf(0.0f, ax), bx), Y = fminf(fmaxf(0.0f, ay), by);
     const float yx = fminf(fmaxf(kx * X, ay), by);
     const float xy = fminf(fmaxf(ky * Y, ax), bx);

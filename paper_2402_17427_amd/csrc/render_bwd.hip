@@ -183,11 +183,12 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
             const int k = c0k + lane;
             bool o0 = false, o1 = false, o2 = false, o3 = false;
             if (k < nb) {
-                const Staged gk = s[k];
-                o0 = box_overlaps(gk, bx0, bx0 + 3.0f, by0, by0 + 3.0f);
-                o1 = box_overlaps(gk, bx0 + 4.0f, bx0 + 7.0f, by0, by0 + 3.0f);
-                o2 = box_overlaps(gk, bx0, bx0 + 3.0f, by0 + 4.0f, by0 + 7.0f);
-                o3 = box_overlaps(gk, bx0 + 4.0f, bx0 + 7.0f, by0 + 4.0f, by0 + 7.0f);
+                const Staged gk = staged_at(s, k);
+                const float4 ck = stage_cull(gk);
+                o0 = box_overlaps(gk, ck, bx0, bx0 + 3.0f, by0, by0 + 3.0f);
+                o1 = box_overlaps(gk, ck, bx0 + 4.0f, bx0 + 7.0f, by0, by0 + 3.0f);
+                o2 = box_overlaps(gk, ck, bx0, bx0 + 3.0f, by0 + 4.0f, by0 + 7.0f);
+                o3 = box_overlaps(gk, ck, bx0 + 4.0f, bx0 + 7.0f, by0 + 4.0f, by0 + 7.0f);
             }
             const uint64_t m0 = __ballot(o0), m1 = __ballot(o1), m2 = __ballot(o2), m3 = __ballot(o3);
             uint64_t mm = row == 0 ? m0 : (row == 1 ? m1 : (row == 2 ? m2 : m3));

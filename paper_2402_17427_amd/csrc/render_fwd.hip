@@ -53,7 +53,7 @@ struct FwdArgs {
 };
 
 template <int TW, int TH, int MODE>
-__device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, Staged* s) {
+__device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, Staged* s, float4* sc) {
     constexpr int NT = TW * TH;
     constexpr bool STATS = MODE == kStats;
     constexpr int WX = TW / 8;
@@ -99,7 +99,11 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, Staged
     for (uint32_t b0 = rg.x; b0 < rg.y; b0 += NT) {
         if (__syncthreads_count(done) == NT) break;
         const uint32_t j = b0 + tid;
-        if (j < rg.y) s[tid] = stage_rec(a.rec[a.vals[j]]);
+        if (j < rg.y) {
+            const Staged st = stage_rec(a.rec[a.vals[j]]);
+            s[tid] = st;
+            sc[tid] = stage_cull(st);
+        }
         __syncthreads();
         const int nb = (int)min((uint32_t)NT, rg.y - b0);
         // 64 staged Gaussians at a time: each lane tests one against the
@@ -112,11 +116,12 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, Staged
             const int k = c0k + lane;
             bool o0 = false, o1 = false, o2 = false, o3 = false;
             if (k < nb) {
-                const Staged gk = s[k];
-                o0 = box_overlaps(gk, bx0, bx0 + 3.0f, by0, by0 + 3.0f);
-                o1 = box_overlaps(gk, bx0 + 4.0f, bx0 + 7.0f, by0, by0 + 3.0f);
-                o2 = box_overlaps(gk, bx0, bx0 + 3.0f, by0 + 4.0f, by0 + 7.0f);
-                o3 = box_overlaps(gk, bx0 + 4.0f, bx0 + 7.0f, by0 + 4.0f, by0 + 7.0f);
+                const Staged gk = staged_at(s, k);
+                const float4 ck = sc[k];
+                o0 = box_overlaps(gk, ck, bx0, bx0 + 3.0f, by0, by0 + 3.0f);
+                o1 = box_overlaps(gk, ck, bx0 + 4.0f, bx0 + 7.0f, by0, by0 + 3.0f);
+                o2 = box_overlaps(gk, ck, bx0, bx0 + 3.0f, by0 + 4.0f, by0 + 7.0f);
+                o3 = box_overlaps(gk, ck, bx0 + 4.0f, bx0 + 7.0f, by0 + 4.0f, by0 + 7.0f);
             }
             const uint64_t m0 = __ballot(o0), m1 = __ballot(o1), m2 = __ballot(o2), m3 = __ballot(o3);
             uint64_t mm = row == 0 ? m0 : (row == 1 ? m1 : (row == 2 ? m2 : m3));
@@ -185,12 +190,14 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, Staged
 template <int TW, int TH, int MODE>
 __global__ __launch_bounds__(TW * TH) void k_render_fwd(FwdArgs a) {
     __shared__ Staged s[TW * TH];
-    fwd_tile<TW, TH, MODE>(a, blockIdx.x, s);
+    __shared__ float4 sc[TW * TH];
+    fwd_tile<TW, TH, MODE>(a, blockIdx.x, s, sc);
 }
 
 template <int TW, int TH>
 __global__ __launch_bounds__(TW * TH) void k_render_fwd_persistent(FwdArgs a) {
     __shared__ Staged s[TW * TH];
+    __shared__ float4 sc[TW * TH];
     __shared__ uint32_t s_next;
     for (;;) {
         __syncthreads();
@@ -198,7 +205,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd_persistent(FwdArgs a) {
         __syncthreads();
         const uint32_t q = s_next;
         if (q >= a.n_tiles) break;
-        fwd_tile<TW, TH, kPlain>(a, a.order ? a.order[q] : q, s);
+        fwd_tile<TW, TH, kPlain>(a, a.order ? a.order[q] : q, s, sc);
     }
 }
 
