@@ -63,4 +63,4 @@ def image_pair(seed, width, height, channels=3, n_blocks=None):
         x = int(rng.integers(0, W))
         r[:, y:y + h, x:x + w] += rng.uniform(-0.3, 0.3, (C, 1, 1))
     r = np.maximum(r, 0.0)
-    return r.astype(np.float32), t.astype(np.float32)
+    return np.ascontiguousarray(r, np.float32), np.ascontiguousarray(t, np.float32)

@@ -241,6 +241,35 @@ gs_status gs_sort_workspace(int64_t capacity, int32_t key_bits, size_t *bytes);
 gs_status gs_sort_pairs(uint64_t *keys, uint32_t *vals, const uint32_t *count, int64_t capacity,
                         int32_t key_bits, void *ws, size_t ws_bytes, gs_stream stream);
 
+/* ---- Training loss ---------------------------------------------------------
+ * Eq. 1 (section 4.2): the loss of a rendered image I^r against its ground
+ * truth I is (1 - lambda) L1(I^r, I) + lambda D-SSIM(I^r, I); Eq. 3
+ * (section 4.3), with decoupled appearance modelling, takes the L1 term on
+ * the appearance-adjusted image I^a instead and keeps D-SSIM on I^r.  D-SSIM
+ * follows 3DGS (section 5.1): 1 - SSIM, SSIM averaged over every pixel and
+ * channel with an 11 x 11 Gaussian window of sigma 1.5, C1 = 0.01^2,
+ * C2 = 0.03^2 (dynamic range 1) and window sums that count the outside of
+ * the image as zero; L1 = mean |I^a - I|, its gradient sign(I^a - I) / n
+ * with sign(0) = 0; n = channels * width * height.  The prior-art weight
+ * is lambda = 0.2.
+ *
+ * image (I^r), target (I): device [channels][height][width] FP32.
+ * image_l1 (I^a): device, same shape, or NULL for Eq. 1 (then I^a = I^r).
+ * loss: device float[3], overwritten with (total loss, L1, mean SSIM).
+ * d_image: device, same shape, overwritten with dLoss/dI^r -- both terms
+ *   for Eq. 1, the D-SSIM term only for Eq. 3.
+ * d_image_l1: device, same shape, overwritten with dLoss/dI^a; required
+ *   when image_l1 is set, ignored (may be NULL) otherwise.
+ * ws: device scratch of gs_loss_workspace() bytes, 8-byte aligned.
+ * The outputs must not overlap the inputs.  Rejected with GS_ERR_INVALID:
+ * NULL buffers, channels < 1, width or height < 1, non-finite lambda, a
+ * workspace that is too small or misaligned.  Deterministic: the same
+ * inputs give bit-identical outputs. */
+gs_status gs_loss_workspace(int32_t channels, int32_t width, int32_t height, size_t *bytes);
+gs_status gs_loss(const float *image, const float *image_l1, const float *target, int32_t channels,
+                  int32_t width, int32_t height, float lambda, float *loss, float *d_image,
+                  float *d_image_l1, void *ws, size_t ws_bytes, gs_stream stream);
+
 /* ---- Batched cells (training) --------------------------------------------
  * Section 4.1: a scene is split into cells optimised independently.  A
  * gs_batch runs one training step (render, L1 image loss, backward) of
@@ -369,7 +398,7 @@ gs_status gs_render_stats(const gs_proj *proj, const gs_bins *bins, const gs_cam
 /* Stage timing (observability).  gs_profile_enable(1) starts a window in
  * which every stage the library enqueues (project, scan_emit, sort,
  * tile_ranges, render_fwd, pair_zero, render_bwd, pair_gather,
- * project_bwd, ...) is bracketed by HIP events on its stream;
+ * project_bwd, loss, ...) is bracketed by HIP events on its stream;
  * gs_profile_enable(0) ends it and discards what was recorded.
  * gs_profile_select(stages) restricts the bracketing to the stages named
  * in a comma-separated list (NULL or "" = all); each event pair adds a

@@ -87,6 +87,8 @@ _SIGS = {
                              C.POINTER(gs_bins), P, P, P, C.c_size_t, P, C.POINTER(gs_grads), P, C.c_size_t,
                              P],
     "gs_render_stats": [C.POINTER(gs_proj), C.POINTER(gs_bins), C.POINTER(gs_camera), C.POINTER(gs_opts), P, P],
+    "gs_loss_workspace": [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
+    "gs_loss": [P, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, P, P, C.c_size_t, P],
     "gs_profile_enable": [C.c_int],
     "gs_profile_select": [C.c_char_p],
     "gs_profile_report": [C.c_char_p, C.c_size_t],

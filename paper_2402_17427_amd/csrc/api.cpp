@@ -387,6 +387,37 @@ gs_status gs_render_bwd_stored(const gs_gaussians* g, const gs_camera* cam, cons
                            ws_bytes, stream);
 }
 
+gs_status gs_loss_workspace(int32_t channels, int32_t width, int32_t height, size_t* bytes) {
+    if (!bytes) return fail(GS_ERR_INVALID, "bytes is NULL");
+    if (channels < 1 || width < 1 || height < 1)
+        return fail(GS_ERR_INVALID, "image shape %dx%dx%d", channels, height, width);
+    if ((height + 31) / 32 > 65535 || channels > 65535 ||
+        (int64_t)channels * ((width + 31) / 32) * ((height + 31) / 32) > INT32_MAX)
+        return fail(GS_ERR_INVALID, "image too large");
+    *bytes = loss_workspace_bytes(channels, width, height);
+    return GS_OK;
+}
+
+gs_status gs_loss(const float* image, const float* image_l1, const float* target, int32_t channels, int32_t width,
+                  int32_t height, float lambda, float* loss, float* d_image, float* d_image_l1, void* ws,
+                  size_t ws_bytes, gs_stream stream) {
+    size_t need = 0;
+    gs_status s;
+    if ((s = gs_loss_workspace(channels, width, height, &need))) return s;
+    if (!image || !target || !loss || !d_image) return fail(GS_ERR_INVALID, "buffer is NULL");
+    if (image_l1 && !d_image_l1) return fail(GS_ERR_INVALID, "image_l1 given without d_image_l1");
+    if (!std::isfinite(lambda)) return fail(GS_ERR_INVALID, "lambda not finite");
+    if (!ws || ws_bytes < need) return fail(GS_ERR_INVALID, "workspace too small: %zu < %zu", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(ws) % 8) return fail(GS_ERR_INVALID, "workspace not 8-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    {
+        ProfScope ps("loss", st);
+        launch_loss(image, image_l1, target, channels, width, height, lambda, loss, d_image,
+                    image_l1 ? d_image_l1 : nullptr, ws, st);
+    }
+    return check_hip("gs_loss");
+}
+
 gs_status gs_sort_workspace(int64_t capacity, int32_t key_bits, size_t* bytes) {
     if (!bytes || capacity < 0 || capacity > kMaxPairs || key_bits < 0 || key_bits > 64)
         return fail(GS_ERR_INVALID, "bad arguments");

@@ -110,3 +110,38 @@ def test_backward_workspace_query_and_validation_without_a_device():
     bins.first = None
     assert bwd(fake, 36 * 1000) == N.GS_ERR_INVALID
     assert b"first" in lib.gs_last_error()
+
+
+def test_loss_workspace_query_and_validation_without_a_device():
+    """gs_loss_workspace sizes one (float, float) partial per 32 x 32 tile
+    of every channel; gs_loss rejects bad shapes, NULL buffers, a missing
+    d_image_l1 for the Eq. 3 form, a non-finite lambda and a short or
+    misaligned workspace before any launch."""
+    lib = N.lib()
+    nbytes = C.c_size_t(0)
+    assert lib.gs_loss_workspace(3, 1920, 1080, C.byref(nbytes)) == N.GS_OK
+    assert nbytes.value == 8 * 3 * 60 * 34
+    assert lib.gs_loss_workspace(3, 33, 1, C.byref(nbytes)) == N.GS_OK
+    assert nbytes.value == 8 * 3 * 2
+    for bad in ((0, 8, 8), (3, 0, 8), (3, 8, -1)):
+        assert lib.gs_loss_workspace(*bad, C.byref(nbytes)) == N.GS_ERR_INVALID
+    assert lib.gs_loss_workspace(3, 8, 8, None) == N.GS_ERR_INVALID
+    fake = 1 << 20
+    need = 8 * 3
+
+    def loss(img=fake, img_l1=None, tgt=fake, c=3, w=8, h=8, lam=0.2, out=fake, d=fake, d1=None, ws=fake,
+             ws_bytes=need):
+        return lib.gs_loss(img, img_l1, tgt, c, w, h, C.c_float(lam), out, d, d1, ws, ws_bytes, None)
+
+    assert loss(img=None) == N.GS_ERR_INVALID
+    assert loss(tgt=None) == N.GS_ERR_INVALID
+    assert loss(out=None) == N.GS_ERR_INVALID
+    assert loss(d=None) == N.GS_ERR_INVALID
+    assert loss(c=0) == N.GS_ERR_INVALID
+    assert loss(img_l1=fake) == N.GS_ERR_INVALID
+    assert b"d_image_l1" in lib.gs_last_error()
+    assert loss(lam=float("nan")) == N.GS_ERR_INVALID
+    assert loss(ws_bytes=need - 1) == N.GS_ERR_INVALID
+    assert b"workspace" in lib.gs_last_error()
+    assert loss(ws=fake + 4) == N.GS_ERR_INVALID
+    assert b"aligned" in lib.gs_last_error()
