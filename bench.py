@@ -12,7 +12,10 @@ resident in HBM before timing.
 
 Prints one JSON line: metric value in Mpix/s (W*H per fwd+bwd step),
 the roofline of the dominant kernel and the FP64 oracle timed on the host
-on a bounded pixel sample.  Every HIP event pair between two kernels adds a
+on a bounded pixel sample.  A `loss` object measures, apart from the step,
+the training loss that follows the forward blend in every optimisation
+step (Eq. 1: L1 + D-SSIM, value and dLoss/dImage at 1920x1080x3) with its
+own roofline and oracle timing.  Every HIP event pair between two kernels adds a
 few microseconds to the step, so the per-stage breakdown comes from a first
 loop with every stage bracketed, and the timed loop (the value) brackets
 only the dominant stage, whose average duration over the timed steps gives
@@ -47,6 +50,14 @@ VALU_PEAK_GOPS = N_CU * LANES_PER_CU_CLK * CLOCK_GHZ        # 39,321.6 G lane-op
 FWD_OPS_SUPPORT = 18
 FWD_OPS_BLEND = 6
 BWD_OPS_BLEND = 48
+# Training loss (Eq. 1: L1 + D-SSIM), per pixel and channel, counted at the
+# output pixel with separable 11-tap window sums (no halo recompute):
+#   products x^2, y^2, xy 3 + five forward window sums 5 x 22 = 110
+#   + SSIM (moments 6, a1 a2 b1 b2 7, reciprocal 1 + 4, S 2, sum 1) 21
+#   + partials w.r.t. the window sums of x 12 + three backward window
+#   sums 3 x 22 = 66 + combination 4 + L1 (difference, |.|, sum, sign) 5 = 221
+LOSS_OPS_PIXEL = 221
+LOSS_BYTES_PIXEL = 12      # read I^r and I, write dLoss/dI^r (FP32)
 
 
 def parse():
@@ -61,6 +72,7 @@ def parse():
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--no-forms", action="store_true", help="skip the batched-cells and serving measurements")
+    ap.add_argument("--no-loss", action="store_true", help="skip the training-loss measurement")
     ap.add_argument("--serve-rates", type=float, nargs="+", default=(100.0, 400.0))
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-grid", type=int, default=10, help="merged scene: grid x grid cells of 200k Gaussians")
@@ -71,11 +83,11 @@ def parse():
     return ap.parse_args()
 
 
-def traffic_record(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
+def traffic_record(kernel, summary="hbm_traffic_cell_1M_1080p.md"):
+    """HBM bytes per launch of `kernel` from a committed counter summary,
     or None when the kernel's sources have changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_cell_1M_1080p.md")
+    path = os.path.join(ROOT, "profiles", summary)
     try:
         lines = open(path).read().splitlines()
     except OSError:
@@ -117,6 +129,59 @@ def cpu_baseline(g, cam, stride):
             "kind": "oracle",
             "sample": f"fwd+bwd of {px.size} pixels (every {stride}th row and column of the {cam.width}x"
                       f"{cam.height} view, 1M Gaussians) in {dt:.1f} s, per-view projection and sort included"}
+
+
+def bench_loss(args, torch, N):
+    """Eq. 1 training loss ((1 - 0.2) L1 + 0.2 D-SSIM) of a 1920x1080 RGB
+    render against its ground truth, value and image gradient (gs_loss),
+    inputs resident in HBM; the oracle timed on the same frame."""
+    from gen import images
+    from paper_2402_17427_amd import loss as gl
+    W, H = args.width, args.height
+    r, t = images.image_pair(5, W, H)
+    rd, td = torch.as_tensor(r).cuda(), torch.as_tensor(t).cuda()
+    L = gl.ImageLoss(3, H, W)
+    for _ in range(10):
+        L(rd, td)
+    torch.cuda.synchronize()
+    steps = max(50, 10 * args.steps)
+    N.profile_select(["loss"])
+    N.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        L(rd, td)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    prof = N.profile_report()
+    N.profile_enable(False)
+    N.profile_select(None)
+    k_ms = prof["loss"][0] / prof["loss"][1]
+    units = 3 * W * H
+    work = units * LOSS_OPS_PIXEL
+    achieved = work / (k_ms * 1e-3) / 1e12
+    peak = VALU_PEAK_GOPS / 1e3
+    full = W == 1920 and H == 1080
+    out = {"workload": f"Eq. 1 loss, lambda 0.2, {W}x{H}x3 render vs target (synthetic city-like pair), "
+                       "value + dLoss/dImage",
+           "value": round(W * H / (ms * 1e-3) / 1e6, 1), "unit": "Mpix/s", "ms_per_call": round(ms, 4),
+           "loss": [round(float(v), 6) for v in L.loss.cpu().tolist()],
+           "roofline": {"bound": "alu", "kernel": "loss", "achieved": round(achieved, 3), "peak": round(peak, 3),
+                        "unit": "Tlane-op/s", "frac": round(achieved / peak, 4),
+                        "traffic": traffic_record("loss", "hbm_traffic_loss_1080p.md") if full else None,
+                        "algorithmic_bytes": units * LOSS_BYTES_PIXEL, "work_lane_ops": int(work),
+                        "avg_ms": round(k_ms, 4)}}
+    if not args.no_cpu_baseline:
+        import oracle.loss as orc
+        rows = H
+        t0 = time.perf_counter()
+        orc.loss(r[:, :rows], t[:, :rows])
+        orc.loss_grad(r[:, :rows], t[:, :rows])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(W * rows / dt / 1e6, 6), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+                               "sample": f"loss value + gradient of the whole {W}x{rows}x3 frame in "
+                                         f"{dt:.1f} s (NumPy FP64, one thread)"}
+    return out
 
 
 def bench_batched(args, torch, scenes, raster):
@@ -420,6 +485,9 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(g, cam, args.cpu_stride)
+    if not args.no_loss:
+        print("[bench] training loss", file=sys.stderr, flush=True)
+        out["loss"] = bench_loss(args, torch, N)
     if not args.no_forms:
         del frame, dg
         torch.cuda.empty_cache()

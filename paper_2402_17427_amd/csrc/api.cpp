@@ -412,8 +412,12 @@ gs_status gs_loss(const float* image, const float* image_l1, const float* target
     hipStream_t st = static_cast<hipStream_t>(stream);
     {
         ProfScope ps("loss", st);
-        launch_loss(image, image_l1, target, channels, width, height, lambda, loss, d_image,
+        launch_loss(image, image_l1, target, channels, width, height, lambda, d_image,
                     image_l1 ? d_image_l1 : nullptr, ws, st);
+    }
+    {
+        ProfScope ps("loss_finish", st);
+        launch_loss_finish(channels, width, height, lambda, ws, loss, st);
     }
     return check_hip("gs_loss");
 }

@@ -113,11 +113,14 @@ void launch_l1(const ViewTab& views, int n_views, int64_t max_pix, const float* 
 // ---- training loss (loss.hip)
 // Eq. 1 / Eq. 3 loss of one [channels][height][width] image against its
 // target: d_image gets the gradient (of both terms when image_l1 is NULL,
-// else of the D-SSIM term, the L1 term's going to d_image_l1); loss[3] =
-// (total, L1, mean SSIM).  ws holds loss_workspace_bytes().
+// else of the D-SSIM term, the L1 term's going to d_image_l1) and ws
+// (loss_workspace_bytes()) the per-tile partial sums, which
+// launch_loss_finish reduces into loss[3] = (total, L1, mean SSIM).
 size_t loss_workspace_bytes(int channels, int width, int height);
 void launch_loss(const float* image, const float* image_l1, const float* target, int channels, int width, int height,
-                 float lambda, float* loss, float* d_image, float* d_image_l1, void* ws, hipStream_t st);
+                 float lambda, float* d_image, float* d_image_l1, void* ws, hipStream_t st);
+void launch_loss_finish(int channels, int width, int height, float lambda, const void* ws, float* loss,
+                        hipStream_t st);
 // Sort keys putting the tiles with the longest lists first.
 void launch_tile_len_keys(const uint32_t* ranges, uint32_t n_tiles, uint64_t* keys, uint32_t* vals, hipStream_t st);
 

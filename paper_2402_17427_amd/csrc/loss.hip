@@ -373,7 +373,7 @@ size_t loss_workspace_bytes(int channels, int width, int height) {
 }
 
 void launch_loss(const float* image, const float* image_l1, const float* target, int channels, int width, int height,
-                 float lambda, float* loss, float* d_image, float* d_image_l1, void* ws, hipStream_t st) {
+                 float lambda, float* d_image, float* d_image_l1, void* ws, hipStream_t st) {
     static const Win win = make_window();
     const double n = (double)channels * width * height;
     LossArgs a;
@@ -392,6 +392,11 @@ void launch_loss(const float* image, const float* image_l1, const float* target,
     a.tiles_y = (height + kT - 1) / kT;
     const dim3 grid(a.tiles_x, a.tiles_y, channels);
     hipLaunchKernelGGL(k_loss, grid, dim3(kThreads), 0, st, a);
+}
+
+void launch_loss_finish(int channels, int width, int height, float lambda, const void* ws, float* loss,
+                        hipStream_t st) {
+    const double n = (double)channels * width * height;
     hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(kFinThreads), 0, st, static_cast<const float2*>(ws),
                        loss_blocks(channels, width, height), n, (double)lambda, loss);
 }
