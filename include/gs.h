@@ -270,6 +270,67 @@ gs_status gs_loss(const float *image, const float *image_l1, const float *target
                   int32_t width, int32_t height, float lambda, float *loss, float *d_image,
                   float *d_image_l1, void *ws, size_t ws_bytes, gs_stream stream);
 
+/* ---- Optimiser step ---------------------------------------------------------
+ * Section 3: the Gaussians' properties are optimised by gradient descent on
+ * the loss, interleaved with adaptive densification that is triggered by
+ * each point's cumulative gradient; section 5.1 leaves the optimiser to
+ * 3DGS, whose choices are these: Adam with bias correction over the raw
+ * properties, one learning rate per group, every Gaussian updated every
+ * step; the renderer's gradients (w.r.t. the activated scale and opacity)
+ * reach the raw values through scale = exp(log_scale) and opacity =
+ * 1 / (1 + exp(-logit)); for every Gaussian visible in the step's view
+ * (tiles_touched > 0) the norm of its image-space centre gradient
+ * |(dL/du, dL/dv)| (pixels) is added to grad_accum and visible_count is
+ * incremented.  The densify/prune policy that reads them is the caller's.
+ *
+ * Raw properties (device, stride ld >= n, updated in place).  mean, quat and
+ * sh are also the planes the rasterizer reads (gs_gaussians may point at
+ * them); log_scale and logit_opacity are kept apart and their activated
+ * values written to scale_out [3][ld] and opacity_out [ld], which must hold
+ * exp / sigmoid of the raw values on entry (each step keeps them so). */
+typedef struct {
+    int64_t n, ld;
+    int32_t sh_degree;
+    float *mean;          /* [3][ld]  */
+    float *log_scale;     /* [3][ld]  */
+    float *quat;          /* [4][ld]  */
+    float *logit_opacity; /* [ld]     */
+    float *sh;            /* [3K][ld] */
+} gs_params;
+
+/* Optimiser state (device, stride ld of the gs_params).  m and v hold
+ * 11 + 3K planes in the order mean 3, log_scale 3, quat 4, logit_opacity 1,
+ * sh 3K; zero them before the first step.  grad_accum and visible_count
+ * ([ld] each) may be NULL when tiles_touched is NULL. */
+typedef struct {
+    float *m, *v;
+    float *grad_accum, *visible_count;
+} gs_adam_state;
+
+/* Hyper-parameters of one step (host struct).  step is the 1-based step
+ * number t of the bias correction 1 - beta^t.  SH plane c*K + j takes
+ * lr_sh_dc for j = 0 and lr_sh_rest otherwise.  3DGS uses beta1 0.9,
+ * beta2 0.999, eps 1e-15, lr_scale 5e-3, lr_quat 1e-3, lr_opacity 5e-2,
+ * lr_sh_dc 2.5e-3, lr_sh_rest 1.25e-4 and a position rate decayed from
+ * 1.6e-4 to 1.6e-6 times the scene extent (the caller's schedule). */
+typedef struct {
+    float lr_mean, lr_scale, lr_quat, lr_opacity, lr_sh_dc, lr_sh_rest;
+    float beta1, beta2, eps;
+    int32_t step;
+} gs_adam_config;
+
+/* One Adam step of the Gaussians in p with the gradients of gs_render_bwd
+ * (grads: stride grads->ld, grad2d [9][n]).  tiles_touched: device [n]
+ * from the step's gs_project, or NULL to leave the statistics alone.
+ * status: device flag of the step's gs_bin_sort (nothing changes when it is
+ * non-zero: a step whose pairs overflowed has no valid gradient), or NULL.
+ * Rejected with GS_ERR_INVALID: NULL buffers, n < 0, ld < n, grads->ld < n,
+ * SH degree > 3, non-finite or out-of-range hyper-parameters (beta outside
+ * [0, 1), eps < 0, step < 1).  Deterministic. */
+gs_status gs_adam_step(const gs_params *p, float *scale_out, float *opacity_out, const gs_adam_state *st,
+                       const gs_grads *grads, const uint32_t *tiles_touched, const int32_t *status,
+                       const gs_adam_config *cfg, gs_stream stream);
+
 /* ---- Batched cells (training) --------------------------------------------
  * Section 4.1: a scene is split into cells optimised independently.  A
  * gs_batch runs one training step (render, L1 image loss, backward) of
@@ -398,7 +459,7 @@ gs_status gs_render_stats(const gs_proj *proj, const gs_bins *bins, const gs_cam
 /* Stage timing (observability).  gs_profile_enable(1) starts a window in
  * which every stage the library enqueues (project, scan_emit, sort,
  * tile_ranges, render_fwd, pair_zero, render_bwd, pair_gather,
- * project_bwd, loss, loss_finish, ...) is bracketed by HIP events on its stream;
+ * project_bwd, loss, loss_finish, adam, ...) is bracketed by HIP events on its stream;
  * gs_profile_enable(0) ends it and discards what was recorded.
  * gs_profile_select(stages) restricts the bracketing to the stages named
  * in a comma-separated list (NULL or "" = all); each event pair adds a

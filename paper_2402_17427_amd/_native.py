@@ -64,6 +64,21 @@ class gs_grads(C.Structure):
                 ("grad2d", P)]
 
 
+class gs_params(C.Structure):
+    _fields_ = [("n", C.c_int64), ("ld", C.c_int64), ("sh_degree", C.c_int32), ("mean", P), ("log_scale", P),
+                ("quat", P), ("logit_opacity", P), ("sh", P)]
+
+
+class gs_adam_state(C.Structure):
+    _fields_ = [("m", P), ("v", P), ("grad_accum", P), ("visible_count", P)]
+
+
+class gs_adam_config(C.Structure):
+    _fields_ = [("lr_mean", C.c_float), ("lr_scale", C.c_float), ("lr_quat", C.c_float), ("lr_opacity", C.c_float),
+                ("lr_sh_dc", C.c_float), ("lr_sh_rest", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("step", C.c_int32)]
+
+
 _lib = None
 
 # name -> (argtypes); every function returns gs_status (int) unless listed
@@ -89,6 +104,8 @@ _SIGS = {
     "gs_render_stats": [C.POINTER(gs_proj), C.POINTER(gs_bins), C.POINTER(gs_camera), C.POINTER(gs_opts), P, P],
     "gs_loss_workspace": [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
     "gs_loss": [P, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, P, P, C.c_size_t, P],
+    "gs_adam_step": [C.POINTER(gs_params), P, P, C.POINTER(gs_adam_state), C.POINTER(gs_grads), P, P,
+                     C.POINTER(gs_adam_config), P],
     "gs_profile_enable": [C.c_int],
     "gs_profile_select": [C.c_char_p],
     "gs_profile_report": [C.c_char_p, C.c_size_t],

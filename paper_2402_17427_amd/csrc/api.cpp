@@ -422,6 +422,70 @@ gs_status gs_loss(const float* image, const float* image_l1, const float* target
     return check_hip("gs_loss");
 }
 
+gs_status gs_adam_step(const gs_params* p, float* scale_out, float* opacity_out, const gs_adam_state* st,
+                       const gs_grads* grads, const uint32_t* tiles_touched, const int32_t* status,
+                       const gs_adam_config* cfg, gs_stream stream) {
+    if (!p || !st || !grads || !cfg) return fail(GS_ERR_INVALID, "NULL argument");
+    if (p->n < 0 || p->ld < p->n) return fail(GS_ERR_INVALID, "bad sizes n=%lld ld=%lld", (long long)p->n,
+                                              (long long)p->ld);
+    if (p->sh_degree < 0 || p->sh_degree > 3) return fail(GS_ERR_INVALID, "sh_degree %d", p->sh_degree);
+    if (grads->ld < p->n) return fail(GS_ERR_INVALID, "gradient ld < n");
+    if (p->n > 0) {
+        if (!p->mean || !p->log_scale || !p->quat || !p->logit_opacity || !p->sh || !scale_out || !opacity_out)
+            return fail(GS_ERR_INVALID, "parameter buffer is NULL");
+        if (!st->m || !st->v) return fail(GS_ERR_INVALID, "moment buffer is NULL");
+        if (!grads->mean || !grads->scale || !grads->quat || !grads->opacity || !grads->sh)
+            return fail(GS_ERR_INVALID, "gradient buffer is NULL");
+        if (tiles_touched && (!grads->grad2d || !st->grad_accum || !st->visible_count))
+            return fail(GS_ERR_INVALID, "statistics buffer is NULL");
+    }
+    const float lrs[6] = {cfg->lr_mean, cfg->lr_scale, cfg->lr_quat, cfg->lr_opacity, cfg->lr_sh_dc, cfg->lr_sh_rest};
+    for (float lr : lrs)
+        if (!std::isfinite(lr)) return fail(GS_ERR_INVALID, "learning rate not finite");
+    if (!(cfg->beta1 >= 0.f && cfg->beta1 < 1.f) || !(cfg->beta2 >= 0.f && cfg->beta2 < 1.f) ||
+        !(cfg->eps >= 0.f) || !std::isfinite(cfg->eps) || cfg->step < 1)
+        return fail(GS_ERR_INVALID, "bad Adam hyper-parameters");
+    AdamArgs a;
+    a.mean = p->mean;
+    a.log_scale = p->log_scale;
+    a.quat = p->quat;
+    a.logit = p->logit_opacity;
+    a.sh = p->sh;
+    a.scale_out = scale_out;
+    a.opacity_out = opacity_out;
+    a.g_mean = grads->mean;
+    a.g_scale = grads->scale;
+    a.g_quat = grads->quat;
+    a.g_opacity = grads->opacity;
+    a.g_sh = grads->sh;
+    a.g2d = grads->grad2d;
+    a.m = st->m;
+    a.v = st->v;
+    a.accum = st->grad_accum;
+    a.count = st->visible_count;
+    a.tiles = tiles_touched;
+    a.status = status;
+    a.n = p->n;
+    a.ld = p->ld;
+    a.gld = grads->ld;
+    a.K = (p->sh_degree + 1) * (p->sh_degree + 1);
+    const double b1 = cfg->beta1, b2 = cfg->beta2;
+    const double bc1 = 1.0 - std::pow(b1, (double)cfg->step), bc2 = 1.0 - std::pow(b2, (double)cfg->step);
+    for (int k = 0; k < 6; ++k) a.step_size[k] = (float)((double)lrs[k] / bc1);
+    a.beta1 = cfg->beta1;
+    a.beta2 = cfg->beta2;
+    a.one_m_beta1 = (float)(1.0 - b1);
+    a.one_m_beta2 = (float)(1.0 - b2);
+    a.inv_sqrt_bc2 = (float)(1.0 / std::sqrt(bc2));
+    a.eps = cfg->eps;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    {
+        ProfScope ps("adam", s);
+        launch_adam(a, s);
+    }
+    return check_hip("gs_adam_step");
+}
+
 gs_status gs_sort_workspace(int64_t capacity, int32_t key_bits, size_t* bytes) {
     if (!bytes || capacity < 0 || capacity > kMaxPairs || key_bits < 0 || key_bits > 64)
         return fail(GS_ERR_INVALID, "bad arguments");

@@ -121,6 +121,24 @@ void launch_loss(const float* image, const float* image_l1, const float* target,
                  float lambda, float* d_image, float* d_image_l1, void* ws, hipStream_t st);
 void launch_loss_finish(int channels, int width, int height, float lambda, const void* ws, float* loss,
                         hipStream_t st);
+// ---- optimiser step (optim.hip)
+// Adam over every raw plane of n Gaussians (stride ld; gradients with
+// stride gld, grad2d [9][n]) plus the densification statistics; nothing
+// changes when *status != 0.  step_size[g] = lr_g / (1 - beta1^t) for the
+// groups mean, scale, quat, opacity, SH DC, SH rest.
+struct AdamArgs {
+    float *mean, *log_scale, *quat, *logit, *sh;
+    float *scale_out, *opacity_out;
+    const float *g_mean, *g_scale, *g_quat, *g_opacity, *g_sh, *g2d;
+    float *m, *v, *accum, *count;
+    const uint32_t* tiles;
+    const int32_t* status;
+    int64_t n, ld, gld;
+    int K;
+    float step_size[6];
+    float beta1, beta2, one_m_beta1, one_m_beta2, inv_sqrt_bc2, eps;
+};
+void launch_adam(const AdamArgs& a, hipStream_t st);
 // Sort keys putting the tiles with the longest lists first.
 void launch_tile_len_keys(const uint32_t* ranges, uint32_t n_tiles, uint64_t* keys, uint32_t* vals, hipStream_t st);
 

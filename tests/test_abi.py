@@ -145,3 +145,51 @@ def test_loss_workspace_query_and_validation_without_a_device():
     assert b"workspace" in lib.gs_last_error()
     assert loss(ws=fake + 4) == N.GS_ERR_INVALID
     assert b"aligned" in lib.gs_last_error()
+
+
+def test_adam_step_validation_without_a_device():
+    """gs_adam_step rejects NULL descriptors and buffers, ld < n, a bad SH
+    degree and out-of-range hyper-parameters before any launch (the device
+    pointers below are never dereferenced)."""
+    lib = N.lib()
+    fake = 1 << 20
+    p = N.gs_params()
+    p.n, p.ld, p.sh_degree = 10, 10, 3
+    p.mean = p.log_scale = p.quat = p.logit_opacity = p.sh = fake
+    st = N.gs_adam_state()
+    st.m = st.v = st.grad_accum = st.visible_count = fake
+    gr = N.gs_grads()
+    gr.ld = 10
+    gr.mean = gr.scale = gr.quat = gr.opacity = gr.sh = gr.grad2d = fake
+
+    def cfg(**kw):
+        c = N.gs_adam_config()
+        c.lr_mean = c.lr_scale = c.lr_quat = c.lr_opacity = c.lr_sh_dc = c.lr_sh_rest = 1e-3
+        c.beta1, c.beta2, c.eps, c.step = 0.9, 0.999, 1e-15, 1
+        for k, v in kw.items():
+            setattr(c, k, v)
+        return c
+
+    def step(c, pp=p, s=st, g=gr, so=fake, oo=fake, tiles=fake):
+        return lib.gs_adam_step(C.byref(pp) if pp is not None else None, so, oo,
+                                C.byref(s) if s is not None else None, C.byref(g) if g is not None else None,
+                                tiles, None, C.byref(c) if c is not None else None, None)
+
+    assert step(None) == N.GS_ERR_INVALID
+    assert step(cfg(), pp=None) == N.GS_ERR_INVALID
+    assert step(cfg(), s=None) == N.GS_ERR_INVALID
+    assert step(cfg(), g=None) == N.GS_ERR_INVALID
+    assert step(cfg(), so=None) == N.GS_ERR_INVALID
+    for bad in (dict(beta1=1.0), dict(beta2=-0.1), dict(eps=-1.0), dict(step=0), dict(lr_quat=float("inf"))):
+        assert step(cfg(**bad)) == N.GS_ERR_INVALID, bad
+    p.ld = 5
+    assert step(cfg()) == N.GS_ERR_INVALID
+    p.ld, p.sh_degree = 10, 4
+    assert step(cfg()) == N.GS_ERR_INVALID
+    p.sh_degree = 3
+    gr.ld = 9
+    assert step(cfg()) == N.GS_ERR_INVALID
+    gr.ld = 10
+    st.grad_accum = None
+    assert step(cfg()) == N.GS_ERR_INVALID
+    assert b"statistics" in lib.gs_last_error()
