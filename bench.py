@@ -15,7 +15,9 @@ the roofline of the dominant kernel and the FP64 oracle timed on the host
 on a bounded pixel sample.  A `loss` object measures, apart from the step,
 the training loss that follows the forward blend in every optimisation
 step (Eq. 1: L1 + D-SSIM, value and dLoss/dImage at 1920x1080x3) with its
-own roofline and oracle timing.  Every HIP event pair between two kernels adds a
+own roofline and oracle timing, and a `train_step` object times a complete
+optimisation step of the cell (render, loss, backward, Adam step with the
+densification statistics), with the optimiser kernel's HBM roofline.  Every HIP event pair between two kernels adds a
 few microseconds to the step, so the per-stage breakdown comes from a first
 loop with every stage bracketed, and the timed loop (the value) brackets
 only the dominant stage, whose average duration over the timed steps gives
@@ -60,6 +62,15 @@ LOSS_OPS_PIXEL = 221
 LOSS_BYTES_PIXEL = 12      # read I^r and I, write dLoss/dI^r (FP32)
 
 
+def adam_bytes(n, planes, visible):
+    """Algorithmic HBM bytes of one optimiser step: per Gaussian and plane
+    read the raw value, gradient and both moments and write the value and
+    both moments (28 B); write the activated scale (3 planes) and opacity
+    (4 B each); read the visibility (4 B); per visible Gaussian read its
+    centre gradient (8 B) and read and write its two statistics (16 B)."""
+    return n * (planes * 28 + 4 * 4 + 4) + visible * 24
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,7 +83,7 @@ def parse():
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--no-forms", action="store_true", help="skip the batched-cells and serving measurements")
-    ap.add_argument("--no-loss", action="store_true", help="skip the training-loss measurement")
+    ap.add_argument("--no-loss", action="store_true", help="skip the training-loss and training-step measurements")
     ap.add_argument("--serve-rates", type=float, nargs="+", default=(100.0, 400.0))
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-grid", type=int, default=10, help="merged scene: grid x grid cells of 200k Gaussians")
@@ -181,6 +192,85 @@ def bench_loss(args, torch, N):
         out["cpu_baseline"] = {"value": round(W * rows / dt / 1e6, 6), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
                                "sample": f"loss value + gradient of the whole {W}x{rows}x3 frame in "
                                          f"{dt:.1f} s (NumPy FP64, one thread)"}
+    return out
+
+
+def bench_train(args, torch, N, frame, dg, cam):
+    """One complete optimisation step of the cell (section 3: Eq. 1 loss,
+    gradient descent): project, bin/sort, forward, L1 + D-SSIM against a
+    target, backward, and the Adam step with the densification statistics,
+    every input resident.  The Gaussians move with every step."""
+    import numpy as np
+    from gen import images
+    from paper_2402_17427_amd import loss as gl
+    from paper_2402_17427_amd import optim
+    _, tgt = images.image_pair(9, cam.width, cam.height)
+    target = torch.as_tensor(tgt).cuda()
+    L = gl.ImageLoss(3, cam.height, cam.width)
+    opt = optim.Adam.from_activated(dg)
+
+    def tstep():
+        frame.project(dg)
+        frame.bin_sort()
+        frame.render_fwd()
+        _, dimg, _ = L(frame.image, target)
+        frame.render_bwd(dg, dimg)
+        opt.step(frame)
+
+    for _ in range(3):
+        tstep()
+    torch.cuda.synchronize()
+    frame.check_status()
+    N.profile_select(None)
+    N.profile_enable(True)
+    for _ in range(args.steps):
+        tstep()
+    torch.cuda.synchronize()
+    prof = N.profile_report()
+    N.profile_enable(False)
+    stages = {k: round(v[0] / v[1], 4) for k, v in prof.items()}
+    N.profile_select(["adam"])
+    N.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tstep()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    aprof = N.profile_report()
+    N.profile_enable(False)
+    N.profile_select(None)
+    frame.check_status()
+    loss = [round(float(v), 6) for v in L.loss.cpu().tolist()]
+    visible = int((frame.tiles_touched[:dg.n] > 0).sum().item())
+    planes = 11 + 3 * (dg.sh_degree + 1) ** 2
+    nbytes = adam_bytes(dg.n, planes, visible)
+    a_ms = aprof["adam"][0] / aprof["adam"][1]
+    achieved = nbytes / (a_ms * 1e-3) / 1e9
+    full = (args.n == 1_000_000 and args.width == 1920 and args.height == 1080 and tuple(args.tile) == (16, 16))
+    out = {"workload": f"one training step of the cell ({dg.n} Gaussians SH{dg.sh_degree}, {cam.width}x{cam.height}): "
+                       "render, Eq. 1 loss (lambda 0.2) against a synthetic target, backward, Adam (3DGS rates) "
+                       "with densification statistics",
+           "value": round(cam.width * cam.height / (ms * 1e-3) / 1e6, 1), "unit": "Mpix/s",
+           "ms_per_step": round(ms, 4), "loss_after": loss, "steps_taken": opt.t, "stage_ms": stages,
+           "adam_roofline": {"bound": "hbm", "kernel": "adam", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                             "traffic": traffic_record("adam", "hbm_traffic_adam_cell_1M.md") if full else None,
+                             "algorithmic_bytes": int(nbytes), "visible": visible, "avg_ms": round(a_ms, 4)}}
+    if not args.no_cpu_baseline:
+        import oracle.adam as orc
+        n = dg.n
+        rng = np.random.default_rng(3)
+        raw = rng.normal(0, 1, (planes, n))
+        g = rng.normal(0, 1e-4, (planes, n))
+        m = np.zeros((planes, n))
+        v = np.zeros((planes, n))
+        t0 = time.perf_counter()
+        orc.adam_step(raw, m, v, g, orc.DEFAULTS, dg.sh_degree, 1)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(n / dt / 1e6, 3), "unit": "MGaussian/s", "cores": 1, "kind": "oracle",
+                               "sample": f"one optimiser step of {n} Gaussians x {planes} planes in {dt:.1f} s "
+                                         "(NumPy FP64, one thread)"}
     return out
 
 
@@ -488,6 +578,8 @@ def main():
     if not args.no_loss:
         print("[bench] training loss", file=sys.stderr, flush=True)
         out["loss"] = bench_loss(args, torch, N)
+        print("[bench] training step", file=sys.stderr, flush=True)
+        out["train_step"] = bench_train(args, torch, N, frame, dg, cam)
     if not args.no_forms:
         del frame, dg
         torch.cuda.empty_cache()
