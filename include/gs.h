@@ -345,7 +345,10 @@ gs_status gs_adam_step(const gs_params *p, float *scale_out, float *opacity_out,
  * targets[n_cells] are device [3][H][W] target images; outputs: images
  * (device, stacked: cell c's [3][H][W] image starts at the sum of 3 W H of
  * the cells before it), grads[n_cells] (device planes per cell, overwritten
- * each step) and loss (device, n_cells floats: mean |I - I*| of each cell).
+ * each step) and loss (device, n_cells floats: mean |I - I*| of each cell,
+ * or its Eq. 1 loss when cfg->loss_lambda > 0).  With cfg->optim the step
+ * ends with the optimiser step of every cell (section 3: a complete
+ * training step of every cell in one graph replay).
  * Every pointer must stay valid until gs_batch_destroy (the graph holds
  * them).  The pair capacity is sized at creation from the cells' current
  * parameters with the configured headroom; a later step that needs more
@@ -354,13 +357,32 @@ gs_status gs_adam_step(const gs_params *p, float *scale_out, float *opacity_out,
  * the batch's workspace (freed by gs_batch_destroy).
  * gs_batch_step: enqueue one step on `stream` (graph replay), no sync. */
 typedef struct gs_batch gs_batch;
+/* Optimiser of a batch (see gs_adam_step): params[c] are cell c's raw
+ * properties, and cells[c] must read params[c].mean / quat / sh, with
+ * cells[c].scale and cells[c].opacity writable (the step rewrites them
+ * from the raw log-scale and logit); states[c] its moments and statistics
+ * (statistics always kept).  The first gs_batch_step takes step number
+ * hyper.step (>= 1), every later one the next; the position rate decays
+ * log-linearly from hyper.lr_mean to lr_mean_final over lr_mean_steps
+ * steps when both are > 0 (3DGS), else stays constant.  The autotune runs
+ * at creation do not step the optimiser. */
+typedef struct {
+    const gs_params *params;
+    const gs_adam_state *states;
+    gs_adam_config hyper;
+    float lr_mean_final;
+    int32_t lr_mean_steps;
+} gs_batch_optim;
+
 typedef struct {
     int32_t tile_w, tile_h;     /* tile shape (0 = 16x16) */
     int32_t persistent;         /* 1 = persistent blend grids with a longest-first tile queue */
     int32_t use_graph;          /* 1 = capture the step as a hipGraph */
     int32_t autotune;           /* 1 = time the candidate shapes/forms at creation, keep the fastest */
     double capacity_headroom;   /* pair capacity = headroom x pairs needed at creation (<= 1: 1.25) */
-} gs_batch_config;              /* NULL = {16, 16, 1, 1, 0, 1.25} */
+    float loss_lambda;          /* Eq. 1 D-SSIM weight (gs_loss); 0 = the L1 loss alone */
+    const gs_batch_optim *optim; /* NULL = no optimiser step in the batch step */
+} gs_batch_config;              /* NULL = {16, 16, 1, 1, 0, 1.25, 0, NULL} */
 typedef struct {
     int32_t tile_w, tile_h, persistent, use_graph, grid_fwd, grid_bwd;
     uint32_t n_tiles;

@@ -1,11 +1,14 @@
 """Batched training step over several partition cells (gs_batch_* C ABI).
 
 VastGaussian (arXiv 2402.17427), section 4.1: the scene's cells are
-optimised independently.  `BatchStep` runs one training step (render, L1
-loss, backward) of several cells of uneven sizes at once, each stage one
-launch over all cells, captured as a hipGraph and replayed per `step()`.
-Outputs live in torch tensors owned by this object (the graph writes into
-them): `image(c)`, `grads[c]`, `loss`.
+optimised independently.  `BatchStep` runs one training step (render, loss,
+backward, and optionally the optimiser step) of several cells of uneven
+sizes at once, each stage one launch over all cells, captured as a hipGraph
+and replayed per `step()`.  The loss is L1, or Eq. 1 (L1 + D-SSIM) with
+`loss_lambda` > 0; with `optimizers` (one optim.Adam per cell, built on the
+same DeviceGaussians) every replay ends with each cell's Adam step and
+densification statistics.  Outputs live in torch tensors owned by this
+object (the graph writes into them): `image(c)`, `grads[c]`, `loss`.
 """
 from __future__ import annotations
 
@@ -17,9 +20,15 @@ from . import _native as N
 from .raster import SH_DIM, DeviceGaussians, _ptr, stream_handle
 
 
+class gs_batch_optim(C.Structure):
+    _fields_ = [("params", C.POINTER(N.gs_params)), ("states", C.POINTER(N.gs_adam_state)),
+                ("hyper", N.gs_adam_config), ("lr_mean_final", C.c_float), ("lr_mean_steps", C.c_int32)]
+
+
 class gs_batch_config(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("persistent", C.c_int32), ("use_graph", C.c_int32),
-                ("autotune", C.c_int32), ("capacity_headroom", C.c_double)]
+                ("autotune", C.c_int32), ("capacity_headroom", C.c_double), ("loss_lambda", C.c_float),
+                ("optim", C.POINTER(gs_batch_optim))]
 
 
 class gs_batch_stats(C.Structure):
@@ -40,7 +49,9 @@ N.register("gs_batch_destroy", [C.c_void_p], None)
 
 class BatchStep:
     def __init__(self, cells: list[DeviceGaussians], cams, targets: list[torch.Tensor], tile=(16, 16),
-                 persistent=True, use_graph=True, autotune=False, headroom=1.25, stream=None):
+                 persistent=True, use_graph=True, autotune=False, headroom=1.25, stream=None,
+                 loss_lambda: float = 0.0, optimizers=None, lr_mean_final: float = 0.0, lr_mean_steps: int = 0,
+                 **hyper):
         n = len(cells)
         assert n == len(cams) == len(targets) and n > 0
         dev = cells[0].mean.device
@@ -73,12 +84,25 @@ class BatchStep:
         c_cams = (N.gs_camera * n)(*[N.make_camera(c) for c in cams])
         c_tg = (C.c_void_p * n)(*[t.data_ptr() for t in self.targets])
         cfg = gs_batch_config(int(tile[0]), int(tile[1]), int(bool(persistent)), int(bool(use_graph)),
-                              int(bool(autotune)), float(headroom))
+                              int(bool(autotune)), float(headroom), float(loss_lambda), None)
+        keep_opt = None
+        if optimizers is not None:
+            from . import optim
+            assert len(optimizers) == n
+            for o, g in zip(optimizers, cells):
+                assert o.dg is g, "each optimizer must hold its cell's DeviceGaussians"
+                assert o.grad_accum is not None, "the batch keeps the densification statistics"
+            c_par = (N.gs_params * n)(*[o.c_params() for o in optimizers])
+            c_st = (N.gs_adam_state * n)(*[o.c_state() for o in optimizers])
+            first = optimizers[0].t + 1
+            opt = gs_batch_optim(c_par, c_st, optim.config(first, **hyper), float(lr_mean_final), int(lr_mean_steps))
+            cfg.optim = C.pointer(opt)
+            keep_opt = (c_par, c_st, opt)
         h = C.c_void_p(0)
         N.call("gs_batch_create", c_cells, c_cams, c_tg, n, _ptr(self.images), c_grads, _ptr(self.loss),
                C.byref(cfg), C.c_void_p(stream_handle(stream)), C.byref(h))
         self._h = h
-        self._keep = (c_cells, c_cams, c_tg, c_grads)
+        self._keep = (c_cells, c_cams, c_tg, c_grads, keep_opt)
 
     def step(self, stream=None):
         N.call("gs_batch_step", self._h, C.c_void_p(stream_handle(stream)))

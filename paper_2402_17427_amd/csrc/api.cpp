@@ -446,6 +446,7 @@ gs_status gs_adam_step(const gs_params* p, float* scale_out, float* opacity_out,
         !(cfg->eps >= 0.f) || !std::isfinite(cfg->eps) || cfg->step < 1)
         return fail(GS_ERR_INVALID, "bad Adam hyper-parameters");
     AdamArgs a;
+    a.dev = nullptr;
     a.mean = p->mean;
     a.log_scale = p->log_scale;
     a.quat = p->quat;
@@ -468,6 +469,7 @@ gs_status gs_adam_step(const gs_params* p, float* scale_out, float* opacity_out,
     a.n = p->n;
     a.ld = p->ld;
     a.gld = grads->ld;
+    a.g2d_ld = p->n;
     a.K = (p->sh_degree + 1) * (p->sh_degree + 1);
     const double b1 = cfg->beta1, b2 = cfg->beta2;
     const double bc1 = 1.0 - std::pow(b1, (double)cfg->step), bc2 = 1.0 - std::pow(b2, (double)cfg->step);

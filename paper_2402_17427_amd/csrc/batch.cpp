@@ -43,6 +43,31 @@ gs_status dmalloc(T** p, size_t count) {
     return GS_OK;
 }
 
+// The optimiser of a batch must update the planes the cells are rendered
+// from, with the moments and statistics of each cell.
+gs_status check_batch_optim(const gs_batch_optim* o, const gs_gaussians* cells, const gs_grads* grads, int n) {
+    if (!o->params || !o->states) return fail(GS_ERR_INVALID, "optim params or states is NULL");
+    const gs_adam_config& y = o->hyper;
+    const float lrs[6] = {y.lr_mean, y.lr_scale, y.lr_quat, y.lr_opacity, y.lr_sh_dc, y.lr_sh_rest};
+    for (float lr : lrs)
+        if (!std::isfinite(lr)) return fail(GS_ERR_INVALID, "learning rate not finite");
+    if (!(y.beta1 >= 0.f && y.beta1 < 1.f) || !(y.beta2 >= 0.f && y.beta2 < 1.f) || !(y.eps >= 0.f) ||
+        !std::isfinite(y.eps) || y.step < 1 || !std::isfinite(o->lr_mean_final))
+        return fail(GS_ERR_INVALID, "bad Adam hyper-parameters");
+    for (int c = 0; c < n; ++c) {
+        const gs_params& P = o->params[c];
+        const gs_adam_state& S = o->states[c];
+        if (P.n != cells[c].n || P.ld != cells[c].ld || P.sh_degree != cells[c].sh_degree)
+            return fail(GS_ERR_INVALID, "optim params of cell %d do not match the cell", c);
+        if (P.n > 0 && (P.mean != cells[c].mean || P.quat != cells[c].quat || P.sh != cells[c].sh))
+            return fail(GS_ERR_INVALID, "cell %d must be rendered from its optimised planes", c);
+        if (P.n > 0 && (!P.log_scale || !P.logit_opacity || !S.m || !S.v || !S.grad_accum || !S.visible_count))
+            return fail(GS_ERR_INVALID, "optimiser buffers of cell %d", c);
+        if (grads[c].ld < P.n) return fail(GS_ERR_INVALID, "gradient ld of cell %d", c);
+    }
+    return GS_OK;
+}
+
 }  // namespace
 
 }  // namespace gs
@@ -103,6 +128,14 @@ struct gs_batch {
     // caller outputs
     float* images = nullptr;
     float* loss = nullptr;
+    // Eq. 1 loss (lambda > 0) per view, and the optimiser step of every cell
+    float lambda = 0.f;
+    std::vector<const float*> h_targets;
+    void* loss_ws = nullptr;
+    std::vector<size_t> loss_ws_off;
+    AdamSched* sched = nullptr;   // device schedule advanced inside the step
+    std::vector<AdamArgs> adam;   // one launch per cell (empty: no optimiser)
+    bool optim_on = false;        // off during sizing and autotune
 
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -114,7 +147,7 @@ struct gs_batch {
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         void* ptrs[] = {d_views, d_jobs, d_targets, rec, depth, rect, tt, g2d, first, scan_ws, keys, alt_k, vals,
                         alt_v, pair_grad, sort_ws, ranges, pair_count, status, queue, tiles_dev, tkeys, tkeys_alt, tvals, tvals_alt,
-                        tsort_ws, final_T, n_contrib, dimg};
+                        tsort_ws, final_T, n_contrib, dimg, loss_ws, sched};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
     }
@@ -193,12 +226,26 @@ struct gs_batch {
             r.persistent_grid = grid_fwd;
         }
         launch_render_fwd(r, images, final_T, n_contrib, nullptr, nullptr, st);
-        launch_l1(vt(), n, max_pix, d_targets, images, dimg, loss, status, st);
+        if (lambda > 0.f) {
+            for (int c = 0; c < n; ++c) {
+                const View& v = h_views[c];
+                void* ws = static_cast<char*>(loss_ws) + loss_ws_off[c];
+                launch_loss(images + v.img_base, nullptr, h_targets[c], 3, cams[c].W, cams[c].H, lambda,
+                            dimg + v.img_base, nullptr, ws, st);
+                launch_loss_finish(3, cams[c].W, cams[c].H, lambda, ws, loss + c, st, 1);
+            }
+        } else {
+            launch_l1(vt(), n, max_pix, d_targets, images, dimg, loss, status, st);
+        }
         launch_pair_zero(pair_grad, pair_count, capacity, st);
         if (persistent) r.persistent_grid = grid_bwd;
         launch_render_bwd(r, final_T, n_contrib, dimg, rect, first, pair_grad, capacity, nullptr, st);
         launch_pair_gather(nslots, first, tt, pair_grad, capacity, status, g2d, st);
         launch_project_bwd(jt(), vt(), K, nslots, tt, g2d, status, st);
+        if (optim_on && !adam.empty()) {
+            launch_adam_prepare(sched, st);
+            for (const AdamArgs& a : adam) launch_adam(a, st);
+        }
     }
 
     // Pairs the current tile shape needs (one projection + emission, synchronous).
@@ -318,6 +365,10 @@ gs_status gs_batch_create(const gs_gaussians* cells, const gs_camera* cams, cons
     b->persistent = cfg ? (cfg->persistent != 0) : 1;
     b->use_graph = cfg ? (cfg->use_graph != 0) : 1;
     b->headroom = cfg && cfg->capacity_headroom > 1.0 ? cfg->capacity_headroom : 1.25;
+    b->lambda = cfg ? cfg->loss_lambda : 0.f;
+    if (!s && (!std::isfinite(b->lambda) || b->lambda < 0.f)) s = fail(GS_ERR_INVALID, "loss_lambda must be >= 0");
+    const gs_batch_optim* opt = cfg ? cfg->optim : nullptr;
+    if (!s && opt) s = check_batch_optim(opt, cells, grads, n_cells);
     if (!s && !render_tile_supported(tw0, th0)) s = fail(GS_ERR_UNSUPPORTED, "tile %dx%d not supported", tw0, th0);
     if (s) {
         delete b;
@@ -379,6 +430,68 @@ gs_status gs_batch_create(const gs_gaussians* cells, const gs_camera* cams, cons
             (s = dmalloc(&b->n_contrib, pix)) || (s = dmalloc(&b->dimg, img)))
             ;
     }
+    if (!s) {
+        b->h_targets.assign(targets, targets + n_cells);
+        size_t off = 0;
+        for (int c = 0; c < n_cells; ++c) {
+            b->loss_ws_off.push_back(off);
+            off += (loss_workspace_bytes(3, b->cams[c].W, b->cams[c].H) + 255) / 256 * 256;
+        }
+        if (b->lambda > 0.f) s = dmalloc(reinterpret_cast<char**>(&b->loss_ws), off);
+    }
+    if (!s && opt) {
+        AdamSched h;
+        std::memset(&h, 0, sizeof h);
+        h.step = opt->hyper.step - 1;
+        const gs_adam_config& y = opt->hyper;
+        const float lrs[6] = {y.lr_mean, y.lr_scale, y.lr_quat, y.lr_opacity, y.lr_sh_dc, y.lr_sh_rest};
+        for (int k = 0; k < 6; ++k) h.lr[k] = lrs[k];
+        h.beta1 = y.beta1;
+        h.beta2 = y.beta2;
+        h.lr_mean_final = opt->lr_mean_final;
+        h.lr_mean_steps = opt->lr_mean_steps;
+        if ((s = dmalloc(&b->sched, 1)) == GS_OK &&
+            (hipMemcpyAsync(b->sched, &h, sizeof h, hipMemcpyHostToDevice, st) != hipSuccess ||
+             hipStreamSynchronize(st) != hipSuccess))
+            s = check_hip("gs_batch: optimiser schedule upload");
+        for (int c = 0; c < n_cells && !s; ++c) {
+            const gs_params& P = opt->params[c];
+            const gs_adam_state& S = opt->states[c];
+            AdamArgs a;
+            std::memset(&a, 0, sizeof a);
+            a.dev = &b->sched->dev;
+            a.mean = P.mean;
+            a.log_scale = P.log_scale;
+            a.quat = P.quat;
+            a.logit = P.logit_opacity;
+            a.sh = P.sh;
+            a.scale_out = const_cast<float*>(cells[c].scale);
+            a.opacity_out = const_cast<float*>(cells[c].opacity);
+            a.g_mean = grads[c].mean;
+            a.g_scale = grads[c].scale;
+            a.g_quat = grads[c].quat;
+            a.g_opacity = grads[c].opacity;
+            a.g_sh = grads[c].sh;
+            a.g2d = b->g2d + b->out0[c];
+            a.g2d_ld = b->nslots;
+            a.m = S.m;
+            a.v = S.v;
+            a.accum = S.grad_accum;
+            a.count = S.visible_count;
+            a.tiles = b->tt + b->out0[c];
+            a.status = b->status;
+            a.n = P.n;
+            a.ld = P.ld;
+            a.gld = grads[c].ld;
+            a.K = b->K;
+            a.beta1 = y.beta1;
+            a.beta2 = y.beta2;
+            a.one_m_beta1 = (float)(1.0 - (double)y.beta1);
+            a.one_m_beta2 = (float)(1.0 - (double)y.beta2);
+            a.eps = y.eps;
+            if (P.n > 0) b->adam.push_back(a);
+        }
+    }
     if (!s && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
         s = check_hip("gs_batch: stream");
     if (!s) {
@@ -428,6 +541,7 @@ gs_status gs_batch_create(const gs_gaussians* cells, const gs_camera* cams, cons
     } else if (!s) {
         s = b->set_tiles(tw0, th0, st);
     }
+    b->optim_on = true;
     if (!s) s = b->capture(st);
     if (s) {
         delete b;

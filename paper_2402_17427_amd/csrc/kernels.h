@@ -119,26 +119,44 @@ void launch_l1(const ViewTab& views, int n_views, int64_t max_pix, const float* 
 size_t loss_workspace_bytes(int channels, int width, int height);
 void launch_loss(const float* image, const float* image_l1, const float* target, int channels, int width, int height,
                  float lambda, float* d_image, float* d_image_l1, void* ws, hipStream_t st);
+// n_out = 3: loss[0..2] = (total, L1, mean SSIM); n_out = 1: the total only.
 void launch_loss_finish(int channels, int width, int height, float lambda, const void* ws, float* loss,
-                        hipStream_t st);
+                        hipStream_t st, int n_out = 3);
 // ---- optimiser step (optim.hip)
 // Adam over every raw plane of n Gaussians (stride ld; gradients with
 // stride gld, grad2d [9][n]) plus the densification statistics; nothing
 // changes when *status != 0.  step_size[g] = lr_g / (1 - beta1^t) for the
 // groups mean, scale, quat, opacity, SH DC, SH rest.
+struct AdamDev {
+    float step_size[6];
+    float inv_sqrt_bc2;
+};
+// Device-resident schedule of a sequence of steps (the batched step): the
+// prepare kernel advances `step` and writes `dev`, which AdamArgs::dev
+// points at.
+struct AdamSched {
+    int step;                 // steps taken so far
+    float lr[6];
+    float beta1, beta2;
+    float lr_mean_final;      // <= 0: constant position rate
+    int lr_mean_steps;
+    AdamDev dev;
+};
 struct AdamArgs {
+    const AdamDev* dev;  // when set, step_size and inv_sqrt_bc2 are read from it
     float *mean, *log_scale, *quat, *logit, *sh;
     float *scale_out, *opacity_out;
     const float *g_mean, *g_scale, *g_quat, *g_opacity, *g_sh, *g2d;
     float *m, *v, *accum, *count;
     const uint32_t* tiles;
     const int32_t* status;
-    int64_t n, ld, gld;
+    int64_t n, ld, gld, g2d_ld;  // g2d rows: [9][g2d_ld]
     int K;
     float step_size[6];
     float beta1, beta2, one_m_beta1, one_m_beta2, inv_sqrt_bc2, eps;
 };
 void launch_adam(const AdamArgs& a, hipStream_t st);
+void launch_adam_prepare(AdamSched* s, hipStream_t st);
 // Sort keys putting the tiles with the longest lists first.
 void launch_tile_len_keys(const uint32_t* ranges, uint32_t n_tiles, uint64_t* keys, uint32_t* vals, hipStream_t st);
 

@@ -324,7 +324,8 @@ constexpr int kFinThreads = 1024;
 
 // loss[0] = (1 - lambda) L1 + lambda (1 - SSIM), loss[1] = L1, loss[2] = SSIM
 __global__ __launch_bounds__(kFinThreads) void k_loss_finish(const float2* __restrict__ partial, int64_t count,
-                                                             double n, double lam, float* __restrict__ loss) {
+                                                             double n, double lam, float* __restrict__ loss,
+                                                             int n_out) {
     __shared__ double red[2][kFinThreads];
     double s = 0.0, l = 0.0;
     for (int64_t i = threadIdx.x; i < count; i += kFinThreads) {
@@ -345,8 +346,10 @@ __global__ __launch_bounds__(kFinThreads) void k_loss_finish(const float2* __res
     if (threadIdx.x == 0) {
         const double ssim = red[0][0] / n, l1 = red[1][0] / n;
         loss[0] = (float)((1.0 - lam) * l1 + lam * (1.0 - ssim));
-        loss[1] = (float)l1;
-        loss[2] = (float)ssim;
+        if (n_out == 3) {
+            loss[1] = (float)l1;
+            loss[2] = (float)ssim;
+        }
     }
 }
 
@@ -395,10 +398,10 @@ void launch_loss(const float* image, const float* image_l1, const float* target,
 }
 
 void launch_loss_finish(int channels, int width, int height, float lambda, const void* ws, float* loss,
-                        hipStream_t st) {
+                        hipStream_t st, int n_out) {
     const double n = (double)channels * width * height;
     hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(kFinThreads), 0, st, static_cast<const float2*>(ws),
-                       loss_blocks(channels, width, height), n, (double)lambda, loss);
+                       loss_blocks(channels, width, height), n, (double)lambda, loss, n_out);
 }
 
 }  // namespace gs

@@ -36,6 +36,12 @@ __device__ __forceinline__ float sigmoidf(float x) { return 1.f / (1.f + expf(-x
 
 __global__ __launch_bounds__(kThreads) void k_adam(AdamArgs a) {
     if (a.status && *a.status != 0) return;
+    if (a.dev) {
+        // step-dependent scalars prepared on the device (graph replays)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) a.step_size[k] = a.dev->step_size[k];
+        a.inv_sqrt_bc2 = a.dev->inv_sqrt_bc2;
+    }
     const int p = blockIdx.y;
     const int np = 11 + 3 * a.K;
     const int64_t i0 = (int64_t)blockIdx.x * (kThreads * kPer) + threadIdx.x;
@@ -46,7 +52,7 @@ __global__ __launch_bounds__(kThreads) void k_adam(AdamArgs a) {
         for (int k = 0; k < kPer; ++k) {
             const int64_t i = i0 + (int64_t)k * kThreads;
             if (i < a.n && a.tiles[i] > 0u) {
-                const float gu = a.g2d[i], gv = a.g2d[a.n + i];
+                const float gu = a.g2d[i], gv = a.g2d[a.g2d_ld + i];
                 a.accum[i] += sqrtf(gu * gu + gv * gv);
                 a.count[i] += 1.f;
             }
@@ -121,7 +127,28 @@ __global__ __launch_bounds__(kThreads) void k_adam(AdamArgs a) {
     }
 }
 
+// One thread: advance the step count and derive this step's scalars
+// (bias corrections in FP64; the position rate decays log-linearly from
+// lr_mean to lr_mean_final over lr_mean_steps steps when those are set).
+__global__ void k_adam_prepare(AdamSched* s) {
+    const int t = ++s->step;
+    const double b1 = s->beta1, b2 = s->beta2;
+    const double bc1 = 1.0 - pow(b1, (double)t), bc2 = 1.0 - pow(b2, (double)t);
+    double lr0 = s->lr[0];
+    if (s->lr_mean_final > 0.f && s->lr_mean_steps > 0) {
+        const double f = fmin(1.0, (double)t / (double)s->lr_mean_steps);
+        lr0 = exp(log((double)s->lr[0]) * (1.0 - f) + log((double)s->lr_mean_final) * f);
+    }
+    s->dev.step_size[0] = (float)(lr0 / bc1);
+    for (int k = 1; k < 6; ++k) s->dev.step_size[k] = (float)((double)s->lr[k] / bc1);
+    s->dev.inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
+}
+
 }  // namespace
+
+void launch_adam_prepare(AdamSched* s, hipStream_t st) {
+    hipLaunchKernelGGL(k_adam_prepare, dim3(1), dim3(1), 0, st, s);
+}
 
 void launch_adam(const AdamArgs& a, hipStream_t st) {
     if (a.n <= 0) return;

@@ -10,6 +10,10 @@ Tolerances (written out here once, used by every GPU test):
                and ||g - g_ref|| / ||g_ref|| <= 1e-3, over the Gaussians that
                touch no flagged pixel.
   integers     keys, values, ranges, tile rectangles: bit-exact.
+  optimiser    one step from the same FP32 state (adam_close): first moment
+               within 6e-7 of the magnitudes of its two terms, second moment
+               6e-7 relative, raw values 1.2e-7 relative plus the update's
+               error, activated scale and opacity through exp and sigmoid.
 """
 from __future__ import annotations
 
@@ -57,3 +61,29 @@ def image_close(name, img, ref, flags, atol=IMAGE_ATOL, max_flagged_frac=0.01):
     frac = float((~ok).mean())
     assert frac <= max_flagged_frac, f"{name}: {frac:.4f} of pixels flagged"
     return worst, int((~ok).sum())
+
+
+def adam_close(pre_raw, pre_m, pre_v, grad_act, got, hyper, deg, step):
+    """One Adam step of the FP64 oracle from the FP32 state (planes
+    [11 + 3K][n]) against the kernel's result `got` (dict raw, m, v, scale,
+    opacity; same planes, scale [3][n], opacity [n])."""
+    from oracle import adam as A
+    raw, g, m0, v0 = (np.asarray(a, np.float64) for a in (pre_raw, grad_act, pre_m, pre_v))
+    cfg = {k: float(np.float32(v)) for k, v in hyper.items()}
+    r1, m1, v1 = A.adam_step(raw, m0, v0, g, cfg, deg, step)
+    graw = A.raw_gradient(raw, g)
+    b1 = cfg["beta1"]
+    tol_m = 6e-7 * (b1 * np.abs(m0) + (1 - b1) * np.abs(graw)) + 1e-37
+    err = np.abs(got["m"] - m1)
+    assert np.all(err <= tol_m), ("m", np.max(err / tol_m))
+    assert np.all(np.abs(got["v"] - v1) <= 6e-7 * v1 + 1e-37), "v"
+    lr = A.lr_of_planes(cfg, deg)[:, None]
+    ss = lr / (1 - cfg["beta1"] ** step)
+    den = np.sqrt(v1 / (1 - cfg["beta2"] ** step)) + cfg["eps"]
+    tol_r = 1.2e-7 * np.abs(r1) + ss * (tol_m + 1e-6 * np.abs(m1)) / den + 1e-30
+    err = np.abs(got["raw"] - r1)
+    assert np.all(err <= tol_r), ("raw", np.unravel_index(np.argmax(err / tol_r), err.shape), np.max(err / tol_r))
+    act = A.activated(r1)
+    assert np.all(np.abs(got["scale"] - act["scale"]) <= act["scale"] * (3e-7 + 1.0001 * tol_r[3:6]) + 1e-38), "scale"
+    o = act["opacity"]
+    assert np.all(np.abs(got["opacity"] - o) <= 3e-7 * o + o * (1 - o) * tol_r[10] + 1e-38), "opacity"

@@ -109,3 +109,75 @@ def test_batch_autotune_picks_a_timed_candidate_and_stays_exact():
     ref = oracle.render(g, cam)
     image_close("autotuned cell 0", b.image(0).cpu().numpy(), ref["image"], ref["flags"])
     b.close()
+
+
+def _raw_planes(opt):
+    dg = opt.dg
+    return np.concatenate([dg.mean.cpu().numpy(), opt.log_scale.cpu().numpy(), dg.quat.cpu().numpy(),
+                           opt.logit_opacity.cpu().numpy()[None], dg.sh.cpu().numpy()], axis=0)
+
+
+def test_batch_training_step_with_eq1_loss_and_optimiser():
+    """A complete training step of every cell in one graph replay: Eq. 1
+    loss (lambda 0.2), backward, Adam with the densification statistics.
+    Per cell and step: the image and loss equal the plain path's
+    (single-view calls, gs_loss) bit for bit, the gradients are within
+    tolerance of the plain path's, and the optimiser's result is the FP64
+    oracle's Adam step from the pre-step state with the batch's own
+    gradients and the step number the device schedule reached (1, then 2)."""
+    from paper_2402_17427_amd import loss as gl
+    from paper_2402_17427_amd import optim
+    from gpu_util import adam_close
+    _case("batch training step")
+    cells = _cells()
+    hyper = dict(optim.DEFAULTS, lr_mean=1e-3)
+    dgs = [raster.DeviceGaussians.from_host(g) for g, _, _ in cells]
+    opts = [optim.Adam.from_activated(dg) for dg in dgs]
+    tg = [torch.as_tensor(t).cuda() for _, _, t in cells]
+    b = BatchStep(dgs, [c for _, c, _ in cells], tg, loss_lambda=0.2, optimizers=opts, **hyper)
+    assert b.info()["use_graph"]
+    # plain path on separate copies
+    pdgs = [raster.DeviceGaussians.from_host(g) for g, _, _ in cells]
+    popts = [optim.Adam.from_activated(dg) for dg in pdgs]
+    frames = []
+    for dg, (_, cam, _) in zip(pdgs, cells):
+        f = raster.Frame(dg.n, dg.sh_degree, cam)
+        f.ensure_capacity(dg)
+        frames.append(f)
+    losses = [gl.ImageLoss(3, c.height, c.width) for _, c, _ in cells]
+    deg = cells[0][0].sh_degree
+    for step in (1, 2):
+        pre = [(_raw_planes(o), o.m.cpu().numpy(), o.v.cpu().numpy()) for o in opts]
+        b.step()
+        torch.cuda.synchronize()
+        assert b.status()[0] == 0
+        for c, (f, dg, o, L) in enumerate(zip(frames, pdgs, popts, losses)):
+            f.project(dg)
+            f.bin_sort()
+            f.render_fwd()
+            lv, dimg, _ = L(f.image, tg[c], 0.2)
+            f.render_bwd(dg, dimg)
+            img_p = f.image.cpu().numpy()
+            gr_p = f.grads()
+            o.step(f, **hyper)
+            torch.cuda.synchronize()
+            if step == 1:
+                # same parameters before the first step: same image and loss
+                np.testing.assert_array_equal(b.image(c).cpu().numpy(), img_p, err_msg=f"cell {c}")
+                assert float(b.loss[c]) == float(lv[0]), (c, float(b.loss[c]), float(lv[0]))
+                got = b.cell_grads(c)
+                for k in PARAMS:
+                    grad_close(f"cell {c} {k}", got[k].cpu().numpy(), gr_p[k].cpu().numpy())
+                np.testing.assert_array_equal(opts[c].visible_count.cpu().numpy()[:dg.n],
+                                              o.visible_count.cpu().numpy()[:dg.n])
+            # the batch's optimiser against the oracle from its own state
+            n = dgs[c].n
+            gb = b.cell_grads(c)
+            ga = np.concatenate([gb["mean"].cpu().numpy(), gb["scale"].cpu().numpy(), gb["quat"].cpu().numpy(),
+                                 gb["opacity"].cpu().numpy()[None], gb["sh"].cpu().numpy()], axis=0)
+            raw0, m0, v0 = pre[c]
+            got = dict(raw=_raw_planes(opts[c])[:, :n], m=opts[c].m.cpu().numpy()[:, :n],
+                       v=opts[c].v.cpu().numpy()[:, :n], scale=dgs[c].scale.cpu().numpy()[:, :n],
+                       opacity=dgs[c].opacity.cpu().numpy()[:n])
+            adam_close(raw0[:, :n], m0[:, :n], v0[:, :n], ga[:, :n], got, hyper, deg, step)
+    b.close()
