@@ -326,8 +326,31 @@ def bench_batched(args, torch, scenes, raster):
     torch.cuda.synchronize()
     ms_plain = (time.perf_counter() - t0) / args.batch_steps * 1e3
     npix = sum(c.width * c.height for c in cams)
+    # the complete training step: Eq. 1 loss and the optimiser in the graph
+    from paper_2402_17427_amd import optim
+    opts = [optim.Adam.from_activated(dg) for dg in dgs]
+    bt = BatchStep(dgs, cams, tgts, tile=info["tile"], persistent=info["persistent"], loss_lambda=0.2,
+                   optimizers=opts, lr_mean_final=1.6e-6, lr_mean_steps=30000)
+    for _ in range(3):
+        bt.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        bt.step()
+    torch.cuda.synchronize()
+    ms_train = (time.perf_counter() - t0) / args.batch_steps * 1e3
+    st_train, _ = bt.status()
+    train_loss = [round(float(x), 5) for x in bt.loss.cpu().tolist()]
+    bt.close()
+    del opts
+    training = {"workload": "the same 8 cells and views, complete training step in one graph replay: render, "
+                            "Eq. 1 loss (lambda 0.2) per view, backward, Adam (3DGS rates) with densification "
+                            "statistics per cell",
+                "ms_per_step": round(ms_train, 3), "mpix_per_s": round(npix / (ms_train * 1e-3) / 1e6, 1),
+                "status": st_train, "loss_per_cell": train_loss}
     return {"workload": "8 cells (0.3M-2.5M Gaussians, 9.9M total, SH3), one 1600x1066 view each, "
                         "training step = render + L1 + backward",
+            "training": training,
             "ms_per_step": round(ms_batch, 3), "mpix_per_s": round(npix / (ms_batch * 1e-3) / 1e6, 1),
             "plain_ms_per_step": round(ms_plain, 3),
             "plain_mpix_per_s": round(npix / (ms_plain * 1e-3) / 1e6, 1),
