@@ -324,3 +324,35 @@ def pixel_sample(width, height, stride=32, offset=None):
     ys = np.arange(o, height, stride)
     py, px = np.meshgrid(ys, xs, indexing="ij")
     return px.ravel().astype(np.int32), py.ravel().astype(np.int32)
+
+
+# ---------------------------------------------------------- partitioning ---
+
+def aerial_survey(n_views, seed, extent_m=1000.0, width=1152, height=864, altitude=(120.0, 180.0)):
+    """A drone survey over a square site centred at the origin: camera
+    positions on a jittered lawnmower grid at `altitude`, each view pitched
+    -30..-90 deg with a random heading (the oblique captures of aerial
+    datasets)."""
+    rng = np.random.default_rng(seed)
+    side = max(1, int(math.ceil(math.sqrt(n_views))))
+    cams = []
+    for k in range(n_views):
+        i, j = divmod(k, side)
+        if i % 2:
+            j = side - 1 - j
+        x = (i + 0.5) / side * extent_m - extent_m / 2 + rng.normal(0.0, 0.1 * extent_m / side)
+        z = (j + 0.5) / side * extent_m - extent_m / 2 + rng.normal(0.0, 0.1 * extent_m / side)
+        alt = rng.uniform(*altitude)
+        pitch = math.radians(rng.uniform(-90.0, -30.0))
+        yaw = rng.uniform(0.0, 2.0 * math.pi)
+        if pitch < math.radians(-89.0):
+            pitch = math.radians(-89.0)
+        cams.append(camera_from_pose((x, alt, z), yaw, pitch, width, height))
+    return cams
+
+
+def sfm_points(n, seed, extent_m=1000.0):
+    """A sparse point cloud of the city over the same site: [n][3] float32
+    world positions on the ground and the building tops."""
+    g = city_gaussians(n, seed, size_m=extent_m, sh_degree=0)
+    return np.ascontiguousarray(g.mean.T, np.float32)

@@ -331,6 +331,63 @@ gs_status gs_adam_step(const gs_params *p, float *scale_out, float *opacity_out,
                        const gs_grads *grads, const uint32_t *tiles_touched, const int32_t *status,
                        const gs_adam_config *cfg, gs_stream stream);
 
+/* ---- Progressive data partitioning ----------------------------------------
+ * Section 4.1: the scene is split into cells by the camera positions on the
+ * ground plane (world y up; ground coordinates x, z): m sections along x
+ * with equal view counts, each split into n segments along z with equal
+ * view counts (group sizes differ by at most one, the first groups larger;
+ * boundaries midway between neighbouring camera positions; the outermost
+ * ones at the bounding rectangle of all camera positions and points).  Each
+ * region's rectangle is expanded by `expand` (0.2) of its side lengths about
+ * its centre; views and points whose ground position lies in the (closed)
+ * expanded rectangle join the cell.  Every other camera joins it when its
+ * airspace-aware visibility of the cell exceeds `visibility_threshold`
+ * (0.25): the fraction of its image covered by the projection of the cell's
+ * box -- the axis-aligned box of the cell's points from the ground (y = 0)
+ * up to the highest point -- with the part behind the near plane clipped
+ * off.  Then the points covered by any view of the cell (in front of its
+ * near plane, projecting inside its image; occlusion ignored) join it
+ * (gs_select_points).  Section 4.3: after optimisation a cell keeps the
+ * Gaussians inside its original rectangle (gs_merge_keep). */
+typedef struct {
+    int32_t m, n;               /* grid: m sections along x, n segments along z */
+    float expand;               /* boundary expansion ratio (0.2) */
+    float visibility_threshold; /* T_h (0.25) */
+} gs_partition_config;
+
+/* Host call (host buffers, FP64 geometry).  points: [n_points][3] world
+ * positions (the SfM point cloud).  Outputs, cell c = i * n + j for section
+ * i and segment j: bounds [m n][4] and expanded [m n][4] rectangles (x0, x1,
+ * z0, z1; the original ones tile the scene, half-open above except at the
+ * outermost edges); boxes [m n][6] airspace boxes (x0, y0, z0, x1, y1, z1;
+ * all zero when the cell has no point); visibility [m n][n_views] (0 for
+ * views selected by position); view_member [m n][n_views]: 0 = not in the
+ * cell, 1 = by position, 2 = by visibility.  GS_ERR_INVALID for NULL
+ * buffers, n_views < 1, a bad grid, non-finite points or cameras. */
+gs_status gs_partition_views(const gs_camera *cams, int32_t n_views, const float *points, int64_t n_points,
+                             const gs_partition_config *cfg, double *bounds, double *expanded, double *boxes,
+                             double *visibility, uint8_t *view_member);
+
+/* Point selection on the device.  points: device [3][ld] positions (SoA,
+ * like gs_gaussians.mean); cams[n_views], expanded [n_cells][4] and
+ * view_member [n_cells][n_views] are the host values of gs_partition_views.
+ * point_member: device [n_cells][n_points], overwritten: 1 = in the
+ * expanded rectangle, 2 = covered by a view of the cell, 0 = neither.
+ * tests: device uint64 counter of the projections performed (work counter,
+ * added to), or NULL.  ws: device scratch of gs_select_points_workspace()
+ * bytes; the call uploads the camera and cell tables into it and
+ * synchronises `stream` once before launching. */
+gs_status gs_select_points_workspace(int32_t n_views, int32_t n_cells, size_t *bytes);
+gs_status gs_select_points(const float *points, int64_t n_points, int64_t ld, const gs_camera *cams,
+                           int32_t n_views, const double *expanded, int32_t n_cells, const uint8_t *view_member,
+                           uint8_t *point_member, uint64_t *tests, void *ws, size_t ws_bytes, gs_stream stream);
+
+/* Section 4.3 merge mask: keep[i] = 1 when Gaussian i's (x, z) (mean, device
+ * [3][ld]) lies in rect = (x0, x1, z0, z1) (host), half-open above unless
+ * closed_x / closed_z (the outermost cells); keep: device [n]. */
+gs_status gs_merge_keep(const float *mean, int64_t n, int64_t ld, const double *rect, int32_t closed_x,
+                        int32_t closed_z, uint8_t *keep, gs_stream stream);
+
 /* ---- Batched cells (training) --------------------------------------------
  * Section 4.1: a scene is split into cells optimised independently.  A
  * gs_batch runs one training step (render, L1 image loss, backward) of

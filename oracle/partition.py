@@ -26,8 +26,9 @@ Readings where the paper is silent: the sections' counts follow
 numpy.array_split (the first |V| mod m sections take one view more),
 boundaries lie midway between the neighbouring camera positions, the
 outermost boundaries are the bounding rectangle of all camera positions and
-points; the expansion keeps the rectangle's centre; rectangles are
-half-open [lo, hi) except at the outermost upper edges, which are closed;
+points; the expansion keeps the rectangle's centre; the expanded
+rectangles (which overlap) are closed, the original ones (which tile the
+scene) half-open [lo, hi) except at the outermost upper edges;
 the cell's box is formed by the points selected by position (step 2);
 the box's part behind the near plane is clipped off before projecting;
 "covered by the views" is the union of the views' frusta, occlusion
@@ -219,8 +220,6 @@ def partition(cams, points, m, n, ratio=EXPAND, threshold=VISIBILITY):
     pts = np.asarray(points, np.float64).reshape(-1, 3)
     centres = np.array([camera_centre(c) for c in cams])
     bounds = region_division(centres, pts, m, n)
-    X1 = max(centres[:, 0].max(), pts[:, 0].max() if len(pts) else -np.inf)
-    Z1 = max(centres[:, 2].max(), pts[:, 2].max() if len(pts) else -np.inf)
     ncell, nv = m * n, len(cams)
     exp = np.array([expand(b, ratio) for b in bounds])
     vm = np.zeros((ncell, nv), np.uint8)
@@ -228,9 +227,8 @@ def partition(cams, points, m, n, ratio=EXPAND, threshold=VISIBILITY):
     vis = np.zeros((ncell, nv))
     boxes = []
     for j in range(ncell):
-        hi = (bounds[j][1] == X1, bounds[j][3] == Z1)
-        vm[j, inside(centres[:, 0], centres[:, 2], exp[j], hi)] = 1
-        sel = inside(pts[:, 0], pts[:, 2], exp[j], hi)
+        vm[j, inside(centres[:, 0], centres[:, 2], exp[j], (True, True))] = 1
+        sel = inside(pts[:, 0], pts[:, 2], exp[j], (True, True))
         pm[j, sel] = 1
         box = cell_box(pts[sel])
         boxes.append(box)

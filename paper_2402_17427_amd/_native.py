@@ -79,6 +79,10 @@ class gs_adam_config(C.Structure):
                 ("eps", C.c_float), ("step", C.c_int32)]
 
 
+class gs_partition_config(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("expand", C.c_float), ("visibility_threshold", C.c_float)]
+
+
 _lib = None
 
 # name -> (argtypes); every function returns gs_status (int) unless listed
@@ -106,6 +110,10 @@ _SIGS = {
     "gs_loss": [P, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, P, P, C.c_size_t, P],
     "gs_adam_step": [C.POINTER(gs_params), P, P, C.POINTER(gs_adam_state), C.POINTER(gs_grads), P, P,
                      C.POINTER(gs_adam_config), P],
+    "gs_partition_views": [P, C.c_int32, P, C.c_int64, C.POINTER(gs_partition_config), P, P, P, P, P],
+    "gs_select_points_workspace": [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
+    "gs_select_points": [P, C.c_int64, C.c_int64, P, C.c_int32, P, C.c_int32, P, P, P, P, C.c_size_t, P],
+    "gs_merge_keep": [P, C.c_int64, C.c_int64, P, C.c_int32, C.c_int32, P, P],
     "gs_profile_enable": [C.c_int],
     "gs_profile_select": [C.c_char_p],
     "gs_profile_report": [C.c_char_p, C.c_size_t],

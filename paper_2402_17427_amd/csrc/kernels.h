@@ -157,6 +157,28 @@ struct AdamArgs {
 };
 void launch_adam(const AdamArgs& a, hipStream_t st);
 void launch_adam_prepare(AdamSched* s, hipStream_t st);
+// ---- partitioning (partition.hip)
+// Camera table rows: R[9], t[3], fx, fy, cx, cy, W, H, near, pad.
+constexpr int kCamDoubles = 20;
+// member[c][i] = 1 when point i's ground position (x, z) lies in cell c's
+// closed expanded rectangle cells[c] = (x0, x1, z0, z1), else 2 when one of
+// the cell's views (views[offsets[c] .. offsets[c + 1])) covers it, else 0.
+// tests (optional) accumulates the projections performed.
+struct SelectArgs {
+    const float* points;  // [3][ld]
+    int64_t n, ld;
+    const double* cells;  // [n_cells][4]
+    const double* cams;   // [n_views][kCamDoubles]
+    const int* offsets;   // [n_cells + 1]
+    const int* views;
+    int n_cells;
+    uint8_t* member;      // [n_cells][n]
+    uint64_t* tests;
+};
+void launch_select_points(const SelectArgs& a, hipStream_t st);
+// keep[i] = Gaussian i's (x, z) in [x0, x1) x [z0, z1) (closed above where asked)
+void launch_merge_keep(const float* mean, int64_t n, int64_t ld, const double rect[4], int closed_x, int closed_z,
+                       uint8_t* keep, hipStream_t st);
 // Sort keys putting the tiles with the longest lists first.
 void launch_tile_len_keys(const uint32_t* ranges, uint32_t n_tiles, uint64_t* keys, uint32_t* vals, hipStream_t st);
 

@@ -140,11 +140,11 @@ def test_partition_invariants():
     assert (vm.sum(axis=0) > 0).all()          # every view lands in some cell
     for j in range(4):
         e = out["expanded"][j]
-        ins = P.inside(c[:, 0], c[:, 2], e)
+        ins = P.inside(c[:, 0], c[:, 2], e, (True, True))
         assert np.all((vm[j] == 1) <= ins)
         assert np.all(out["visibility"][j][vm[j] == 2] > P.VISIBILITY)
         assert np.all(out["visibility"][j][vm[j] == 0] <= P.VISIBILITY)
-        assert np.all((pm[j] == 1) == P.inside(pts[:, 0], pts[:, 2], e))
+        assert np.all((pm[j] == 1) == P.inside(pts[:, 0], pts[:, 2], e, (True, True)))
         cov = np.zeros(len(pts), bool)
         for i in np.nonzero(vm[j])[0]:
             cov |= P.covered(cams[i], pts)
