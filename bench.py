@@ -17,7 +17,9 @@ the training loss that follows the forward blend in every optimisation
 step (Eq. 1: L1 + D-SSIM, value and dLoss/dImage at 1920x1080x3) with its
 own roofline and oracle timing, and a `train_step` object times a complete
 optimisation step of the cell (render, loss, backward, Adam step with the
-densification statistics), with the optimiser kernel's HBM roofline.  Every HIP event pair between two kernels adds a
+densification statistics), with the optimiser kernel's HBM roofline; a
+`partition` object times the progressive data partitioning of a synthetic
+drone survey (host view selection, device point selection).  Every HIP event pair between two kernels adds a
 few microseconds to the step, so the per-stage breakdown comes from a first
 loop with every stage bracketed, and the timed loop (the value) brackets
 only the dominant stage, whose average duration over the timed steps gives
@@ -60,6 +62,12 @@ BWD_OPS_BLEND = 48
 #   sums 3 x 22 = 66 + combination 4 + L1 (difference, |.|, sum, sign) 5 = 221
 LOSS_OPS_PIXEL = 221
 LOSS_BYTES_PIXEL = 12      # read I^r and I, write dLoss/dI^r (FP32)
+
+
+# Coverage test of one (point, view) pair in the point selection (FP64
+# lane-ops): camera-space position 3 x (mul + 2 fma + add) 12, depth test 1,
+# u and v numerators 2 x 2, image bounds W z, H z 2, four comparisons 4 = 23
+SELECT_OPS_TEST = 23
 
 
 def adam_bytes(n, planes, visible):
@@ -272,6 +280,72 @@ def bench_train(args, torch, N, frame, dg, cam):
                                "sample": f"one optimiser step of {n} Gaussians x {planes} planes in {dt:.1f} s "
                                          "(NumPy FP64, one thread)"}
     return out
+
+
+def bench_partition(args, torch, N):
+    """Progressive data partitioning of a synthetic drone survey (1000 views
+    at 1152x864 over 1 km^2, 2M SfM points, 2 x 4 cells): the host step
+    (region division, expansion, airspace-aware visibility) and the device
+    point selection (position + coverage), with the selection kernel's
+    FP64 ALU roofline from its work counter."""
+    import numpy as np
+    from gen import scenes
+    from paper_2402_17427_amd import partition as gp
+    cams = scenes.aerial_survey(1000, 7)
+    pts = scenes.sfm_points(2_000_000, 8)
+    t0 = time.perf_counter()
+    host = gp.partition_views(cams, pts, 2, 4)
+    host_ms = (time.perf_counter() - t0) * 1e3
+    sel = gp.PointSelector(len(cams), 8, len(pts))
+    dev = torch.as_tensor(np.ascontiguousarray(pts.T)).cuda()
+    tests = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = sel(dev, cams, host["expanded"], host["view_member"], tests=tests)
+    torch.cuda.synchronize()
+    n_tests = int(tests.item())
+    reps = 5
+    N.profile_select(["select_points"])
+    N.profile_enable(True)
+    for _ in range(reps):
+        sel(dev, cams, host["expanded"], host["view_member"], out=out)
+    torch.cuda.synchronize()
+    prof = N.profile_report()
+    N.profile_enable(False)
+    N.profile_select(None)
+    k_ms = prof["select_points"][0] / prof["select_points"][1]
+    work = n_tests * SELECT_OPS_TEST
+    achieved = work / (k_ms * 1e-3) / 1e12
+    peak = VALU_PEAK_GOPS / 1e3
+    mem = out.cpu().numpy()
+    res = {"workload": "drone survey: 1000 views 1152x864 over 1 km^2 at 120-180 m, pitch -30..-90 deg, "
+                       "2M SfM points on the city, 2 x 4 cells, expansion 0.2, visibility threshold 0.25",
+           "host_ms": round(host_ms, 2), "select_ms": round(k_ms, 4),
+           "views_per_cell": [int((host["view_member"][j] > 0).sum()) for j in range(8)],
+           "views_by_visibility": [int((host["view_member"][j] == 2).sum()) for j in range(8)],
+           "points_per_cell": [int((mem[j] > 0).sum()) for j in range(8)],
+           "points_by_coverage": [int((mem[j] == 2).sum()) for j in range(8)],
+           "roofline": {"bound": "alu", "kernel": "select_points (Morton keys, order sort, selection)",
+                        "achieved": round(achieved, 3),
+                        "peak": round(peak, 3), "unit": "Tlane-op/s (FP64)", "frac": round(achieved / peak, 4),
+                        "traffic": None, "coverage_tests": n_tests, "work_lane_ops": int(work),
+                        "avg_ms": round(k_ms, 4)}}
+    if not args.no_cpu_baseline:
+        import oracle.partition as orc
+        idx = np.random.default_rng(9).choice(len(pts), 500_000, replace=False)
+        sub = pts[idx].astype(np.float64)
+        t0 = time.perf_counter()
+        for j in range(8):
+            ins = orc.inside(sub[:, 0], sub[:, 2], host["expanded"][j], (True, True))
+            cov = np.zeros(len(sub), bool)
+            for i in np.nonzero(host["view_member"][j])[0]:
+                cov |= orc.covered(cams[i], sub)
+            del ins, cov
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": round(len(sub) / dt / 1e6, 6), "unit": "Mpoint/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"point selection of {len(sub)} of the 2M points over the 8 cells in {dt:.1f} s "
+                                         f"(NumPy FP64, every view of each cell); GPU: "
+                                         f"{len(pts) / (k_ms * 1e-3) / 1e6:.1f} Mpoint/s"}
+    return res
 
 
 def bench_batched(args, torch, scenes, raster):
@@ -603,6 +677,9 @@ def main():
         out["loss"] = bench_loss(args, torch, N)
         print("[bench] training step", file=sys.stderr, flush=True)
         out["train_step"] = bench_train(args, torch, N, frame, dg, cam)
+    if not args.no_forms:
+        print("[bench] partitioning", file=sys.stderr, flush=True)
+        out["partition"] = bench_partition(args, torch, N)
     if not args.no_forms:
         del frame, dg
         torch.cuda.empty_cache()

@@ -375,9 +375,11 @@ gs_status gs_partition_views(const gs_camera *cams, int32_t n_views, const float
  * expanded rectangle, 2 = covered by a view of the cell, 0 = neither.
  * tests: device uint64 counter of the projections performed (work counter,
  * added to), or NULL.  ws: device scratch of gs_select_points_workspace()
- * bytes; the call uploads the camera and cell tables into it and
- * synchronises `stream` once before launching. */
-gs_status gs_select_points_workspace(int32_t n_views, int32_t n_cells, size_t *bytes);
+ * bytes (n_points < 2^32); the call uploads the camera and cell tables into
+ * it and synchronises `stream` once before launching.  The points are
+ * visited in the Morton order of their ground position (sorted in ws), so
+ * that neighbouring points, covered by the same views, share a wave. */
+gs_status gs_select_points_workspace(int32_t n_views, int32_t n_cells, int64_t n_points, size_t *bytes);
 gs_status gs_select_points(const float *points, int64_t n_points, int64_t ld, const gs_camera *cams,
                            int32_t n_views, const double *expanded, int32_t n_cells, const uint8_t *view_member,
                            uint8_t *point_member, uint64_t *tests, void *ws, size_t ws_bytes, gs_stream stream);

@@ -111,7 +111,7 @@ _SIGS = {
     "gs_adam_step": [C.POINTER(gs_params), P, P, C.POINTER(gs_adam_state), C.POINTER(gs_grads), P, P,
                      C.POINTER(gs_adam_config), P],
     "gs_partition_views": [P, C.c_int32, P, C.c_int64, C.POINTER(gs_partition_config), P, P, P, P, P],
-    "gs_select_points_workspace": [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
+    "gs_select_points_workspace": [C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_size_t)],
     "gs_select_points": [P, C.c_int64, C.c_int64, P, C.c_int32, P, C.c_int32, P, P, P, P, C.c_size_t, P],
     "gs_merge_keep": [P, C.c_int64, C.c_int64, P, C.c_int32, C.c_int32, P, P],
     "gs_profile_enable": [C.c_int],

@@ -174,8 +174,13 @@ struct SelectArgs {
     int n_cells;
     uint8_t* member;      // [n_cells][n]
     uint64_t* tests;
+    const uint32_t* order;  // visiting order of the points (set by the launcher)
 };
-void launch_select_points(const SelectArgs& a, hipStream_t st);
+// Scratch of the visiting-order sort for n points.
+size_t select_sort_bytes(int64_t n);
+// Points are visited in the Morton order of their ground position over
+// box = (x0, x1, z0, z1) (sorted in sort_ws, select_sort_bytes(n) bytes).
+void launch_select_points(const SelectArgs& a, const double box[4], void* sort_ws, hipStream_t st);
 // keep[i] = Gaussian i's (x, z) in [x0, x1) x [z0, z1) (closed above where asked)
 void launch_merge_keep(const float* mean, int64_t n, int64_t ld, const double rect[4], int closed_x, int closed_z,
                        uint8_t* keep, hipStream_t st);

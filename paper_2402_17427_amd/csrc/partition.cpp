@@ -292,10 +292,17 @@ gs_status gs_partition_views(const gs_camera* cams, int32_t n_views, const float
     return GS_OK;
 }
 
-gs_status gs_select_points_workspace(int32_t n_views, int32_t n_cells, size_t* bytes) {
-    if (!bytes || n_views < 1 || n_cells < 1 || n_cells > 65535) return fail(GS_ERR_INVALID, "bad arguments");
-    *bytes = align256((size_t)n_views * kCamDoubles * 8) + align256((size_t)n_cells * 4 * 8) +
-             align256((size_t)(n_cells + 1) * 4) + align256((size_t)n_cells * n_views * 4);
+namespace {
+size_t table_bytes(int32_t n_views, int32_t n_cells) {
+    return align256((size_t)n_views * kCamDoubles * 8) + align256((size_t)n_cells * 4 * 8) +
+           align256((size_t)(n_cells + 1) * 4) + align256((size_t)n_cells * n_views * 4);
+}
+}  // namespace
+
+gs_status gs_select_points_workspace(int32_t n_views, int32_t n_cells, int64_t n_points, size_t* bytes) {
+    if (!bytes || n_views < 1 || n_cells < 1 || n_cells > 65535 || n_points < 0 || n_points > 0xFFFFFFFFll)
+        return fail(GS_ERR_INVALID, "bad arguments");
+    *bytes = table_bytes(n_views, n_cells) + select_sort_bytes(n_points);
     return GS_OK;
 }
 
@@ -304,14 +311,15 @@ gs_status gs_select_points(const float* points, int64_t n_points, int64_t ld, co
                            uint8_t* point_member, uint64_t* tests, void* ws, size_t ws_bytes, gs_stream stream) {
     size_t need = 0;
     gs_status s;
-    if ((s = gs_select_points_workspace(n_views, n_cells, &need))) return s;
+    if ((s = gs_select_points_workspace(n_views, n_cells, n_points, &need))) return s;
+    const size_t tbytes = table_bytes(n_views, n_cells);
     if (!cams || !expanded || !view_member) return fail(GS_ERR_INVALID, "NULL host table");
     if (n_points < 0 || ld < n_points) return fail(GS_ERR_INVALID, "bad sizes");
     if (n_points > 0 && (!points || !point_member)) return fail(GS_ERR_INVALID, "NULL device buffer");
     if (!ws || ws_bytes < need) return fail(GS_ERR_INVALID, "workspace too small: %zu < %zu", ws_bytes, need);
     if (reinterpret_cast<uintptr_t>(ws) % 8) return fail(GS_ERR_INVALID, "workspace not 8-byte aligned");
     // host tables, laid out as in the workspace
-    std::vector<char> host(need, 0);
+    std::vector<char> host(tbytes, 0);
     double* tc = reinterpret_cast<double*>(host.data());
     for (int i = 0; i < n_views; ++i) {
         Cam tmp;
@@ -350,7 +358,7 @@ gs_status gs_select_points(const float* points, int64_t n_points, int64_t ld, co
     }
     offsets[n_cells] = nv;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (hipMemcpyAsync(ws, host.data(), need, hipMemcpyHostToDevice, st) != hipSuccess ||
+    if (hipMemcpyAsync(ws, host.data(), tbytes, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return check_hip("gs_select_points: table upload");
     SelectArgs a;
@@ -365,9 +373,18 @@ gs_status gs_select_points(const float* points, int64_t n_points, int64_t ld, co
     a.n_cells = n_cells;
     a.member = point_member;
     a.tests = tests;
+    a.order = nullptr;
+    // Morton box: the union of the expanded rectangles
+    double box[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+    for (int c = 0; c < n_cells; ++c) {
+        box[0] = std::min(box[0], expanded[4 * c]);
+        box[1] = std::max(box[1], expanded[4 * c + 1]);
+        box[2] = std::min(box[2], expanded[4 * c + 2]);
+        box[3] = std::max(box[3], expanded[4 * c + 3]);
+    }
     {
         ProfScope ps("select_points", st);
-        launch_select_points(a, st);
+        launch_select_points(a, box, w + tbytes, st);
     }
     return check_hip("gs_select_points");
 }

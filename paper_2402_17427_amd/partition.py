@@ -45,9 +45,10 @@ def partition_views(cams, points_host, m: int, n: int, expand: float = EXPAND,
 class PointSelector:
     """Device buffers of the point selection for fixed view and cell counts."""
 
-    def __init__(self, n_views: int, n_cells: int, device="cuda"):
+    def __init__(self, n_views: int, n_cells: int, n_points: int, device="cuda"):
         b = C.c_size_t()
-        N.call("gs_select_points_workspace", n_views, n_cells, C.byref(b))
+        N.call("gs_select_points_workspace", n_views, n_cells, n_points, C.byref(b))
+        self.n_points = n_points
         self.ws = torch.empty((int(b.value) + 7) // 8, dtype=torch.float64, device=device)
         self.ws_bytes = int(b.value)
         self.n_views, self.n_cells = n_views, n_cells
@@ -57,6 +58,7 @@ class PointSelector:
         1 position / 2 coverage)."""
         assert points_dev.dtype == torch.float32 and points_dev.dim() == 2 and points_dev.shape[0] == 3
         npts = points_dev.shape[1]
+        assert npts <= self.n_points, "workspace sized for fewer points"
         ld = points_dev.stride(0)
         c_cams = (N.gs_camera * len(cams))(*[N.make_camera(c) for c in cams])
         ex = np.ascontiguousarray(expanded, np.float64)

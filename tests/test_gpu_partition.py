@@ -60,7 +60,7 @@ def test_select_points_matches_the_oracle(seed, V, Pn, m, n):
     cams = scenes.aerial_survey(V, seed, extent_m=600.0, width=320, height=240)
     pts = scenes.sfm_points(Pn, seed + 1, extent_m=600.0)
     host = gp.partition_views(cams, pts, m, n)
-    sel = gp.PointSelector(V, m * n)
+    sel = gp.PointSelector(V, m * n, Pn)
     dev = torch.as_tensor(np.ascontiguousarray(pts.T)).cuda()
     tests = torch.zeros(1, dtype=torch.int64, device="cuda")
     got = sel(dev, cams, host["expanded"], host["view_member"], tests=tests)
@@ -82,7 +82,7 @@ def test_full_survey_sampled_points():
     cams = scenes.aerial_survey(1000, 7)
     pts = scenes.sfm_points(2_000_000, 8)
     host = gp.partition_views(cams, pts, 2, 4)
-    sel = gp.PointSelector(len(cams), 8)
+    sel = gp.PointSelector(len(cams), 8, len(pts))
     dev = torch.as_tensor(np.ascontiguousarray(pts.T)).cuda()
     got = sel(dev, cams, host["expanded"], host["view_member"])
     torch.cuda.synchronize()

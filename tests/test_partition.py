@@ -72,5 +72,6 @@ def test_host_partition_rejects_bad_arguments():
     assert lib.gs_partition_views(*a) == N.GS_ERR_INVALID
     assert lib.gs_partition_views(*args(cfg)) == N.GS_OK
     nb = C.c_size_t()
-    assert lib.gs_select_points_workspace(0, 4, C.byref(nb)) == N.GS_ERR_INVALID
-    assert lib.gs_select_points_workspace(10, 4, C.byref(nb)) == N.GS_OK and nb.value > 0
+    assert lib.gs_select_points_workspace(0, 4, 100, C.byref(nb)) == N.GS_ERR_INVALID
+    assert lib.gs_select_points_workspace(10, 4, -1, C.byref(nb)) == N.GS_ERR_INVALID
+    assert lib.gs_select_points_workspace(10, 4, 100, C.byref(nb)) == N.GS_OK and nb.value > 0
