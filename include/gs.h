@@ -390,6 +390,40 @@ gs_status gs_select_points(const float *points, int64_t n_points, int64_t ld, co
 gs_status gs_merge_keep(const float *mean, int64_t n, int64_t ld, const double *rect, int32_t closed_x,
                         int32_t closed_z, uint8_t *keep, gs_stream stream);
 
+/* ---- Decoupled appearance modelling ----------------------------------------
+ * Section 4.2 and supplement S1.1: the rendered image I^r (device [3][H][W])
+ * is downsampled 32 times (ceil(H/32) x ceil(W/32) block means, border
+ * blocks over the pixels they hold), an appearance embedding of length m
+ * (64) is concatenated to every pixel, and a CNN maps the (3 + m)-channel
+ * map to the transformation map M ([3][H][W]); the adjusted image is
+ * I^a = I^r * M (pixel-wise), whose L1 loss Eq. 3 takes (gs_loss with
+ * image_l1 = I^a).  The CNN: conv0 3x3 (3 + m -> 256); four blocks of pixel
+ * shuffle by 2 (out[c][2y+i][2x+j] = in[4c+2i+j][y][x]), 3x3 convolution
+ * halving the block input's channels (64 -> 128, 32 -> 64, 16 -> 32,
+ * 8 -> 16) and ReLU; bilinear interpolation to H x W (half-pixel centres);
+ * 3x3 convolution 16 -> 16, ReLU; 3x3 convolution 16 -> 3.  Every
+ * convolution has a bias, zero padding 1, stride 1.
+ * params: device FP32, the seven layers in that order, each its weights
+ * [Cout][Cin][3][3] then its bias [Cout] (gs_appearance_param_count
+ * floats).  ws: device scratch of gs_appearance_workspace() bytes, 256-byte
+ * aligned; the forward keeps its activations there and the backward of the
+ * same image, embedding and parameters must be given the same ws.
+ * Forward: image_adj = I^a (device [3][H][W]); transform, if not NULL,
+ * receives M.  Backward, for the gradient d_image_adj = dL/dI^a: d_image
+ * (device [3][H][W]) is ADDED dL/dI^r through both the product and the
+ * downsampling (so it can hold the D-SSIM term already); d_embedding [m]
+ * and d_params (packed like params) are overwritten.  Deterministic.
+ * GS_ERR_INVALID for NULL buffers, W or H < 1, m outside [0, 4096], a
+ * workspace that is too small or misaligned. */
+gs_status gs_appearance_param_count(int32_t embed_dim, int64_t *count);
+gs_status gs_appearance_workspace(int32_t width, int32_t height, int32_t embed_dim, size_t *bytes);
+gs_status gs_appearance_fwd(const float *image, int32_t width, int32_t height, const float *embedding,
+                            int32_t embed_dim, const float *params, float *image_adj, float *transform, void *ws,
+                            size_t ws_bytes, gs_stream stream);
+gs_status gs_appearance_bwd(const float *image, int32_t width, int32_t height, const float *embedding,
+                            int32_t embed_dim, const float *params, const float *d_image_adj, float *d_image,
+                            float *d_embedding, float *d_params, void *ws, size_t ws_bytes, gs_stream stream);
+
 /* ---- Batched cells (training) --------------------------------------------
  * Section 4.1: a scene is split into cells optimised independently.  A
  * gs_batch runs one training step (render, L1 image loss, backward) of

@@ -121,15 +121,17 @@ def _bilinear_weights(n_in, n_out):
 
 
 def bilinear(x, H, W):
+    """Ay x Ax^T per channel (rows, then columns)."""
     Ay = _bilinear_weights(x.shape[1], H)
     Ax = _bilinear_weights(x.shape[2], W)
-    return np.einsum("yh,chw,xw->cyx", Ay, x, Ax)
+    return np.stack([Ay @ x[c] @ Ax.T for c in range(x.shape[0])])
 
 
 def bilinear_adjoint(g, h, w):
+    """Ay^T g Ax per channel."""
     Ay = _bilinear_weights(h, g.shape[1])
     Ax = _bilinear_weights(w, g.shape[2])
-    return np.einsum("yh,cyx,xw->chw", Ay, g, Ax)
+    return np.stack([Ay.T @ g[c] @ Ax for c in range(g.shape[0])])
 
 
 def forward(img, embed, params):

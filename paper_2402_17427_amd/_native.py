@@ -114,6 +114,10 @@ _SIGS = {
     "gs_select_points_workspace": [C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_size_t)],
     "gs_select_points": [P, C.c_int64, C.c_int64, P, C.c_int32, P, C.c_int32, P, P, P, P, C.c_size_t, P],
     "gs_merge_keep": [P, C.c_int64, C.c_int64, P, C.c_int32, C.c_int32, P, P],
+    "gs_appearance_param_count": [C.c_int32, C.POINTER(C.c_int64)],
+    "gs_appearance_workspace": [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
+    "gs_appearance_fwd": [P, C.c_int32, C.c_int32, P, C.c_int32, P, P, P, P, C.c_size_t, P],
+    "gs_appearance_bwd": [P, C.c_int32, C.c_int32, P, C.c_int32, P, P, P, P, P, P, C.c_size_t, P],
     "gs_profile_enable": [C.c_int],
     "gs_profile_select": [C.c_char_p],
     "gs_profile_report": [C.c_char_p, C.c_size_t],

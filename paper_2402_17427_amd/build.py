@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libgsmi.so")
 ARCH = os.environ.get("GSMI_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "profile.cpp", "project.hip", "binning.hip", "sort.hip", "render_fwd.hip", "render_bwd.hip",
-           "batch_kernels.hip", "loss.hip", "optim.hip", "partition.hip", "partition.cpp", "batch.cpp", "serve.cpp"]
+           "batch_kernels.hip", "loss.hip", "optim.hip", "partition.hip", "partition.cpp", "appearance.hip", "appearance.cpp", "batch.cpp", "serve.cpp"]
 EXTRA_SOURCES = []
 
 

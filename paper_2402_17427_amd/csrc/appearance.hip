@@ -1,0 +1,410 @@
+// Kernels of the decoupled appearance model (gs_appearance_*).
+//
+// VastGaussian (arXiv 2402.17427), section 4.2 and supplement S1.1: the
+// rendered image is downsampled 32 times, an appearance embedding is
+// concatenated to every pixel, and a CNN (3x3 convolution to 256 channels;
+// four blocks of pixel shuffle, 3x3 convolution halving the channels, ReLU;
+// bilinear interpolation to the image size; 3x3 convolution, ReLU, 3x3
+// convolution to 3 channels) produces the transformation map M; the
+// adjusted image is I^r * M.
+//
+// Every layer works on planar FP32 maps [C][H][W].  The convolutions are
+// direct: a workgroup computes a 16 x 16 pixel tile for a group of output
+// channels, staging the input tile with its one-pixel halo in LDS a few
+// input channels at a time; the weights are the same for the whole
+// workgroup and come through scalar loads.  The same kernel runs the
+// transposed convolution of the backward (weights read flipped and
+// transposed) with the ReLU mask of the layer applied to its input as it
+// is staged.  Weight gradients are per-workgroup partial sums over pixel
+// tiles (a sliding 3 x 3 window in registers), reduced in a fixed order by
+// a second kernel, so every result is deterministic.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace gs {
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int kCI = 8;             // input channels staged per round
+constexpr int kTile = 16;          // output tile edge of the convolution
+constexpr int kHalo = kTile + 2;   // staged tile edge
+constexpr int kWR = 8, kWC = 32;   // pixel tile of the weight gradient
+
+__global__ __launch_bounds__(kT) void k_down_concat(const float* __restrict__ img, int H, int W, int h, int w,
+                                                    const float* __restrict__ embed, int m, float* __restrict__ D) {
+    __shared__ float red[kT / kWave][2];
+    const int by = blockIdx.x / w, bx = blockIdx.x - by * w;
+    const int64_t HW = (int64_t)H * W, hw = (int64_t)h * w;
+    const int ny = min(32, H - 32 * by), nx = min(32, W - 32 * bx);
+    for (int c = 0; c < 3; ++c) {
+        float s = 0.f;
+        for (int k = threadIdx.x; k < 1024; k += kT) {
+            const int yy = k >> 5, xx = k & 31;
+            if (yy < ny && xx < nx) s += img[c * HW + (int64_t)(32 * by + yy) * W + 32 * bx + xx];
+        }
+        for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+        if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave][0] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float t = 0.f;
+            for (int k = 0; k < kT / kWave; ++k) t += red[k][0];
+            D[c * hw + blockIdx.x] = t / (float)(ny * nx);
+        }
+        __syncthreads();
+    }
+    for (int k = threadIdx.x; k < m; k += kT) D[(3 + k) * hw + blockIdx.x] = embed[k];
+}
+
+// d_img[c][y][x] += g[c][y/32][x/32] / (pixels of that block)
+__global__ __launch_bounds__(kT) void k_down_adjoint(const float* __restrict__ g, int H, int W, int h, int w,
+                                                     float* __restrict__ d_img) {
+    const int64_t HW = (int64_t)H * W;
+    const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (q >= 3 * HW) return;
+    const int c = (int)(q / HW);
+    const int64_t p = q - c * HW;
+    const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+    const int by = y >> 5, bx = x >> 5;
+    const int ny = min(32, H - 32 * by), nx = min(32, W - 32 * bx);
+    d_img[q] += g[(int64_t)c * h * w + (int64_t)by * w + bx] / (float)(ny * nx);
+}
+
+template <int CO>
+__global__ __launch_bounds__(kT) void k_conv(ConvArgs a) {
+    __shared__ float s_in[kCI * kHalo * kHalo];
+    const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
+    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    const int og = blockIdx.z * CO;
+    const int64_t HW = (int64_t)a.H * a.W;
+    const int px = x0 + tx, py = y0 + ty;
+    float acc[CO];
+#pragma unroll
+    for (int k = 0; k < CO; ++k) acc[k] = (a.b && og + k < a.Cout) ? a.b[og + k] : 0.f;
+    for (int c0 = 0; c0 < a.Cin; c0 += kCI) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < kCI * kHalo * kHalo; k += kT) {
+            const int c = k / (kHalo * kHalo), r = (k / kHalo) % kHalo, q = k % kHalo;
+            const int gy = y0 - 1 + r, gx = x0 - 1 + q;
+            float v = 0.f;
+            if (c0 + c < a.Cin && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
+                const int64_t idx = (int64_t)(c0 + c) * HW + (int64_t)gy * a.W + gx;
+                v = a.in[idx];
+                if (a.mask && !(a.mask[idx] > 0.f)) v = 0.f;
+            }
+            s_in[k] = v;
+        }
+        __syncthreads();
+        const int cn = min(kCI, a.Cin - c0);
+        for (int c = 0; c < cn; ++c) {
+            float v[9];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) v[t] = s_in[(c * kHalo + ty + t / 3) * kHalo + tx + t % 3];
+            const int ci = c0 + c;
+#pragma unroll
+            for (int k = 0; k < CO; ++k) {
+                const int o = og + k;
+                if (o >= a.Cout) break;
+                // forward: w[o][ci][tap]; transposed: w[ci][o][8 - tap] of the
+                // forward layer (its output channel ci, input channel o)
+                const float* wr = a.transposed ? a.w + ((int64_t)ci * a.CinF + o) * 9
+                                               : a.w + ((int64_t)o * a.Cin + ci) * 9;
+                float s = acc[k];
+#pragma unroll
+                for (int t = 0; t < 9; ++t) s = fmaf(a.transposed ? wr[8 - t] : wr[t], v[t], s);
+                acc[k] = s;
+            }
+        }
+    }
+    if (px < a.W && py < a.H) {
+#pragma unroll
+        for (int k = 0; k < CO; ++k) {
+            const int o = og + k;
+            if (o >= a.Cout) break;
+            a.out[(int64_t)o * HW + (int64_t)py * a.W + px] = a.relu ? fmaxf(acc[k], 0.f) : acc[k];
+        }
+    }
+}
+
+// Per-workgroup partial sums of dW[o][i][tap] and db[o] over its pixel
+// tiles (8 x 32, grid-stride); thread (o, i) of a 16 x 16 channel block.
+__global__ __launch_bounds__(kT) void k_wgrad(WgradArgs a) {
+    __shared__ float s_g[16 * kWR * kWC];
+    __shared__ float s_in[16 * (kWR + 2) * (kWC + 2)];
+    const int ol = threadIdx.x / 16, il = threadIdx.x % 16;
+    const int n_ig = (a.Cin + 15) / 16;
+    const int o0 = (blockIdx.y / n_ig) * 16, i0 = (blockIdx.y % n_ig) * 16;
+    const int64_t HW = (int64_t)a.H * a.W;
+    const int tiles_x = (a.W + kWC - 1) / kWC, tiles_y = (a.H + kWR - 1) / kWR;
+    const int n_tiles = tiles_x * tiles_y;
+    float acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = 0.f;
+    float bacc = 0.f;
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int y0 = (tile / tiles_x) * kWR, x0 = (tile % tiles_x) * kWC;
+        __syncthreads();
+        for (int k = threadIdx.x; k < 16 * kWR * kWC; k += kT) {
+            const int o = k / (kWR * kWC), r = (k / kWC) % kWR, q = k % kWC;
+            const int gy = y0 + r, gx = x0 + q;
+            float v = 0.f;
+            if (o0 + o < a.Cout && gy < a.H && gx < a.W) {
+                const int64_t idx = (int64_t)(o0 + o) * HW + (int64_t)gy * a.W + gx;
+                v = a.g[idx];
+                if (a.mask && !(a.mask[idx] > 0.f)) v = 0.f;
+            }
+            s_g[k] = v;
+        }
+        for (int k = threadIdx.x; k < 16 * (kWR + 2) * (kWC + 2); k += kT) {
+            const int i = k / ((kWR + 2) * (kWC + 2)), r = (k / (kWC + 2)) % (kWR + 2), q = k % (kWC + 2);
+            const int gy = y0 - 1 + r, gx = x0 - 1 + q;
+            float v = 0.f;
+            if (i0 + i < a.Cin && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+                v = a.in[(int64_t)(i0 + i) * HW + (int64_t)gy * a.W + gx];
+            s_in[k] = v;
+        }
+        __syncthreads();
+        const float* gi = s_g + ol * kWR * kWC;
+        const float* xi = s_in + il * (kWR + 2) * (kWC + 2);
+        for (int r = 0; r < kWR; ++r) {
+            float w0[3], w1[3];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                w0[t] = xi[(r + t) * (kWC + 2) + 0];
+                w1[t] = xi[(r + t) * (kWC + 2) + 1];
+            }
+            for (int q = 0; q < kWC; ++q) {
+                float w2[3];
+#pragma unroll
+                for (int t = 0; t < 3; ++t) w2[t] = xi[(r + t) * (kWC + 2) + q + 2];
+                const float gv = gi[r * kWC + q];
+                bacc += gv;
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    acc[3 * t + 0] = fmaf(gv, w0[t], acc[3 * t + 0]);
+                    acc[3 * t + 1] = fmaf(gv, w1[t], acc[3 * t + 1]);
+                    acc[3 * t + 2] = fmaf(gv, w2[t], acc[3 * t + 2]);
+                    w0[t] = w1[t];
+                    w1[t] = w2[t];
+                }
+            }
+        }
+    }
+    const int o = o0 + ol, i = i0 + il;
+    float* part = a.partial + (int64_t)blockIdx.x * a.J;
+    if (o < a.Cout && i < a.Cin) {
+#pragma unroll
+        for (int t = 0; t < 9; ++t) part[((int64_t)o * a.Cin + i) * 9 + t] = acc[t];
+    }
+    if (o < a.Cout && i0 == 0 && il == 0) part[(int64_t)a.Cout * a.Cin * 9 + o] = bacc;
+}
+
+// out[j] = sum over the parts (in order) of partial[part][j]
+__global__ __launch_bounds__(1024) void k_reduce_parts(const float* __restrict__ partial, int parts, int64_t J,
+                                                       float* __restrict__ out) {
+    __shared__ float red[16][64];
+    const int jj = threadIdx.x % 64, pp = threadIdx.x / 64;
+    const int64_t j = (int64_t)blockIdx.x * 64 + jj;
+    float s = 0.f;
+    if (j < J)
+        for (int p = pp; p < parts; p += 16) s += partial[(int64_t)p * J + j];
+    red[pp][jj] = s;
+    __syncthreads();
+    if (pp == 0 && j < J) {
+        float t = 0.f;
+        for (int k = 0; k < 16; ++k) t += red[k][jj];
+        out[j] = t;
+    }
+}
+
+// pixel shuffle by 2: out[c][2y+i][2x+j] = in[4c+2i+j][y][x] (inverse: the
+// same map read the other way)
+__global__ __launch_bounds__(kT) void k_shuffle(const float* __restrict__ in, int C, int h, int w,
+                                                float* __restrict__ out, int inverse) {
+    const int64_t n = (int64_t)4 * C * h * w;
+    const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (q >= n) return;
+    // q indexes the shuffled map [C][2h][2w]
+    const int W2 = 2 * w, H2 = 2 * h;
+    const int c = (int)(q / ((int64_t)H2 * W2));
+    const int64_t r = q - (int64_t)c * H2 * W2;
+    const int Y = (int)(r / W2), X = (int)(r - (int64_t)Y * W2);
+    const int64_t src = ((int64_t)(4 * c + 2 * (Y & 1) + (X & 1)) * h + (Y >> 1)) * w + (X >> 1);
+    if (inverse) out[src] = in[q];
+    else out[q] = in[src];
+}
+
+// per-axis interpolation tables (half-pixel centres), FP64 coordinates
+__global__ void k_bilin_table(int n_in, int n_out, int* __restrict__ i0, int* __restrict__ i1, float* __restrict__ f) {
+    const int d = blockIdx.x * kT + threadIdx.x;
+    if (d >= n_out) return;
+    double s = ((double)d + 0.5) * (double)n_in / (double)n_out - 0.5;
+    if (s < 0.0) s = 0.0;
+    int a = (int)floor(s);
+    if (a > n_in - 1) a = n_in - 1;
+    i0[d] = a;
+    i1[d] = min(a + 1, n_in - 1);
+    f[d] = (float)(s - (double)a);
+}
+
+__global__ __launch_bounds__(kT) void k_bilinear(const float* __restrict__ in, int C, int h, int w, int H, int W,
+                                                 const int* __restrict__ y0, const int* __restrict__ y1,
+                                                 const float* __restrict__ fy, const int* __restrict__ x0,
+                                                 const int* __restrict__ x1, const float* __restrict__ fx,
+                                                 float* __restrict__ out) {
+    const int64_t HW = (int64_t)H * W;
+    const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (q >= C * HW) return;
+    const int c = (int)(q / HW);
+    const int64_t p = q - c * HW;
+    const int Y = (int)(p / W), X = (int)(p - (int64_t)Y * W);
+    const float* b = in + (int64_t)c * h * w;
+    const float a = fy[Y], e = fx[X];
+    const float top = (1.f - e) * b[(int64_t)y0[Y] * w + x0[X]] + e * b[(int64_t)y0[Y] * w + x1[X]];
+    const float bot = (1.f - e) * b[(int64_t)y1[Y] * w + x0[X]] + e * b[(int64_t)y1[Y] * w + x1[X]];
+    out[q] = (1.f - a) * top + a * bot;
+}
+
+// weight of output index d on input index i along one axis
+__device__ __forceinline__ float axis_weight(int d, int i, const int* i0, const int* i1, const float* f) {
+    float wgt = 0.f;
+    if (i0[d] == i) wgt += 1.f - f[d];
+    if (i1[d] == i) wgt += f[d];
+    return wgt;
+}
+
+// adjoint of k_bilinear: each input pixel gathers from the outputs that
+// read it (a window of output indices around its image)
+__global__ __launch_bounds__(kT) void k_bilinear_adj(const float* __restrict__ g, int C, int H, int W, int h, int w,
+                                                     const int* __restrict__ y0, const int* __restrict__ y1,
+                                                     const float* __restrict__ fy, const int* __restrict__ x0,
+                                                     const int* __restrict__ x1, const float* __restrict__ fx,
+                                                     float* __restrict__ out) {
+    const int64_t hw = (int64_t)h * w;
+    const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (q >= C * hw) return;
+    const int c = (int)(q / hw);
+    const int64_t p = q - c * hw;
+    const int yi = (int)(p / w), xi = (int)(p - (int64_t)yi * w);
+    // outputs d read input i only if |d + 0.5 - (i + 0.5) n_out / n_in| < n_out / n_in + 1
+    const float sy = (float)H / (float)h, sx = (float)W / (float)w;
+    const int ya = max(0, (int)floorf((yi - 1.f) * sy) - 1), yb = min(H - 1, (int)ceilf((yi + 2.f) * sy) + 1);
+    const int xa = max(0, (int)floorf((xi - 1.f) * sx) - 1), xb = min(W - 1, (int)ceilf((xi + 2.f) * sx) + 1);
+    const float* gc = g + (int64_t)c * H * W;
+    float s = 0.f;
+    for (int Y = ya; Y <= yb; ++Y) {
+        const float wy = axis_weight(Y, yi, y0, y1, fy);
+        if (wy == 0.f) continue;
+        float r = 0.f;
+        for (int X = xa; X <= xb; ++X) {
+            const float wx = axis_weight(X, xi, x0, x1, fx);
+            if (wx != 0.f) r = fmaf(wx, gc[(int64_t)Y * W + X], r);
+        }
+        s = fmaf(wy, r, s);
+    }
+    out[q] = s;
+}
+
+__global__ __launch_bounds__(kT) void k_mul(const float* __restrict__ a, const float* __restrict__ b, int64_t n,
+                                            float* __restrict__ out) {
+    const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (q < n) out[q] = a[q] * b[q];
+}
+
+// dM = dIa * Ir; dIr += dIa * M
+__global__ __launch_bounds__(kT) void k_mul_bwd(const float* __restrict__ d_adj, const float* __restrict__ img,
+                                                const float* __restrict__ M, int64_t n, float* __restrict__ dM,
+                                                float* __restrict__ d_img) {
+    const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (q >= n) return;
+    const float g = d_adj[q];
+    dM[q] = g * img[q];
+    d_img[q] += g * M[q];
+}
+
+// d_embed[k] = sum over the pixels of channel 3 + k of dD
+__global__ __launch_bounds__(kT) void k_embed_grad(const float* __restrict__ dD, int64_t hw, float* __restrict__ d_embed) {
+    __shared__ float red[kT / kWave];
+    const float* src = dD + (int64_t)(3 + blockIdx.x) * hw;
+    float s = 0.f;
+    for (int64_t p = threadIdx.x; p < hw; p += kT) s += src[p];
+    for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int k = 0; k < kT / kWave; ++k) t += red[k];
+        d_embed[blockIdx.x] = t;
+    }
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + kT - 1) / kT); }
+
+}  // namespace
+
+void launch_down_concat(const float* img, int H, int W, int h, int w, const float* embed, int m, float* D,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_down_concat, dim3(h * w), dim3(kT), 0, st, img, H, W, h, w, embed, m, D);
+}
+
+void launch_down_adjoint(const float* g, int H, int W, int h, int w, float* d_img, hipStream_t st) {
+    hipLaunchKernelGGL(k_down_adjoint, dim3(blocks_for(3 * (int64_t)H * W)), dim3(kT), 0, st, g, H, W, h, w, d_img);
+}
+
+void launch_conv(const ConvArgs& a, hipStream_t st) {
+    const dim3 grid_base((a.W + kTile - 1) / kTile, (a.H + kTile - 1) / kTile);
+    if (a.Cout <= 4) {
+        hipLaunchKernelGGL(k_conv<4>, dim3(grid_base.x, grid_base.y, (a.Cout + 3) / 4), dim3(kT), 0, st, a);
+    } else {
+        hipLaunchKernelGGL(k_conv<16>, dim3(grid_base.x, grid_base.y, (a.Cout + 15) / 16), dim3(kT), 0, st, a);
+    }
+}
+
+int wgrad_parts(int H, int W) {
+    const int tiles = ((W + kWC - 1) / kWC) * ((H + kWR - 1) / kWR);
+    return tiles < 1024 ? tiles : 1024;
+}
+
+void launch_wgrad(const WgradArgs& a, float* dw, hipStream_t st) {
+    const int parts = wgrad_parts(a.H, a.W);
+    const int groups = ((a.Cout + 15) / 16) * ((a.Cin + 15) / 16);
+    hipLaunchKernelGGL(k_wgrad, dim3(parts, groups), dim3(kT), 0, st, a);
+    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((a.J + 63) / 64)), dim3(1024), 0, st, a.partial, parts, a.J, dw);
+}
+
+void launch_shuffle(const float* in, int C, int h, int w, float* out, bool inverse, hipStream_t st) {
+    hipLaunchKernelGGL(k_shuffle, dim3(blocks_for((int64_t)4 * C * h * w)), dim3(kT), 0, st, in, C, h, w, out,
+                       inverse ? 1 : 0);
+}
+
+void launch_bilin_table(int n_in, int n_out, int* i0, int* i1, float* f, hipStream_t st) {
+    hipLaunchKernelGGL(k_bilin_table, dim3(blocks_for(n_out)), dim3(kT), 0, st, n_in, n_out, i0, i1, f);
+}
+
+void launch_bilinear(const float* in, int C, int h, int w, int H, int W, const BilinTab& t, float* out,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_bilinear, dim3(blocks_for((int64_t)C * H * W)), dim3(kT), 0, st, in, C, h, w, H, W, t.y0,
+                       t.y1, t.fy, t.x0, t.x1, t.fx, out);
+}
+
+void launch_bilinear_adj(const float* g, int C, int H, int W, int h, int w, const BilinTab& t, float* out,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_bilinear_adj, dim3(blocks_for((int64_t)C * h * w)), dim3(kT), 0, st, g, C, H, W, h, w, t.y0,
+                       t.y1, t.fy, t.x0, t.x1, t.fx, out);
+}
+
+void launch_mul(const float* a, const float* b, int64_t n, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_mul, dim3(blocks_for(n)), dim3(kT), 0, st, a, b, n, out);
+}
+
+void launch_mul_bwd(const float* d_adj, const float* img, const float* M, int64_t n, float* dM, float* d_img,
+                    hipStream_t st) {
+    hipLaunchKernelGGL(k_mul_bwd, dim3(blocks_for(n)), dim3(kT), 0, st, d_adj, img, M, n, dM, d_img);
+}
+
+void launch_embed_grad(const float* dD, int64_t hw, int m, float* d_embed, hipStream_t st) {
+    hipLaunchKernelGGL(k_embed_grad, dim3(m), dim3(kT), 0, st, dD, hw, d_embed);
+}
+
+}  // namespace gs

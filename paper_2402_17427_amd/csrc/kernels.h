@@ -184,6 +184,53 @@ void launch_select_points(const SelectArgs& a, const double box[4], void* sort_w
 // keep[i] = Gaussian i's (x, z) in [x0, x1) x [z0, z1) (closed above where asked)
 void launch_merge_keep(const float* mean, int64_t n, int64_t ld, const double rect[4], int closed_x, int closed_z,
                        uint8_t* keep, hipStream_t st);
+// ---- appearance model (appearance.hip)
+// 3x3 convolution, zero padding 1, planar [C][H][W] maps.  Forward:
+// out[o] = b[o] + sum_i w[o][i] * in[i]; transposed (the backward w.r.t. the
+// input): out[i] = sum_o flip(w[o][i]) * in[o] with Cin = the forward
+// layer's Cout, Cout = its Cin (CinF).  mask: the input is used only where
+// mask > 0 (a ReLU's output); relu: max(0, .) on the output.
+struct ConvArgs {
+    const float* in;
+    const float* mask;
+    const float* w;
+    const float* b;
+    float* out;
+    int Cin, Cout, H, W;
+    int transposed, relu, CinF;
+};
+void launch_conv(const ConvArgs& a, hipStream_t st);
+// Weight and bias gradients of a forward convolution with input `in`
+// [Cin][H][W] and output gradient g [Cout][H][W] (masked like ConvArgs):
+// dw = [Cout][Cin][9] then [Cout] (J = Cout Cin 9 + Cout floats); partial
+// holds wgrad_parts(H, W) x J floats.
+struct WgradArgs {
+    const float* in;
+    const float* g;
+    const float* mask;
+    float* partial;
+    int Cin, Cout, H, W;
+    int64_t J;
+};
+int wgrad_parts(int H, int W);
+void launch_wgrad(const WgradArgs& a, float* dw, hipStream_t st);
+void launch_down_concat(const float* img, int H, int W, int h, int w, const float* embed, int m, float* D,
+                        hipStream_t st);
+void launch_down_adjoint(const float* g, int H, int W, int h, int w, float* d_img, hipStream_t st);
+void launch_shuffle(const float* in, int C, int h, int w, float* out, bool inverse, hipStream_t st);
+struct BilinTab {
+    const int *y0, *y1, *x0, *x1;
+    const float *fy, *fx;
+};
+void launch_bilin_table(int n_in, int n_out, int* i0, int* i1, float* f, hipStream_t st);
+void launch_bilinear(const float* in, int C, int h, int w, int H, int W, const BilinTab& t, float* out,
+                     hipStream_t st);
+void launch_bilinear_adj(const float* g, int C, int H, int W, int h, int w, const BilinTab& t, float* out,
+                         hipStream_t st);
+void launch_mul(const float* a, const float* b, int64_t n, float* out, hipStream_t st);
+void launch_mul_bwd(const float* d_adj, const float* img, const float* M, int64_t n, float* dM, float* d_img,
+                    hipStream_t st);
+void launch_embed_grad(const float* dD, int64_t hw, int m, float* d_embed, hipStream_t st);
 // Sort keys putting the tiles with the longest lists first.
 void launch_tile_len_keys(const uint32_t* ranges, uint32_t n_tiles, uint64_t* keys, uint32_t* vals, hipStream_t st);
 

@@ -1,0 +1,161 @@
+"""GPU parity of the decoupled appearance model (gs_appearance_fwd/bwd:
+x32 downsample, embedding concat, the supplement's CNN, I^a = I^r * M;
+VastGaussian, arXiv 2402.17427, section 4.2 and S1.1) against the FP64
+oracle.
+
+Every test calls the HIP kernels through the C ABI.  Tolerances: the map M
+and I^a within 1e-4 of max |M| elementwise (seven FP32 convolution layers
+of up to 603 terms each, about 1e-6 relative rounding per layer).  Every
+gradient (image, embedding, each layer's weights and biases) is a chain of
+FP32 sums; the forward-error bound of a sum is proportional to the sum of
+its terms' magnitudes, not to its value, and the gradients here cancel
+heavily (weight gradients are sums over up to 2M pixels of signed upstream
+gradients).  So each element must lie within 1e-4 of its magnitude bound,
+the same chain evaluated on absolute values (|weights|, |activations|,
+|incoming gradient|, the forward's ReLU masks): 1e-4 is about 1700 units of
+FP32 rounding, for some 15 reduction stages whose errors grow like the
+square root of their lengths.  The gradient norms must also agree within
+1e-3 relative.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gen import images
+from oracle import appearance as A
+from paper_2402_17427_amd import appearance as ap
+
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    print(f"\n[case] {name}", flush=True)
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed)
+    layers = [(rng.normal(0, 0.06, (co, ci, 3, 3)).astype(np.float32), rng.normal(0, 0.02, co).astype(np.float32))
+              for co, ci in A.layer_shapes()]
+    w6, b6 = layers[6]
+    layers[6] = (w6, (b6 + 1.0).astype(np.float32))     # M near 1, as an adjusted image would be
+    return layers
+
+
+def _run(H, W, seed, l1_gradient=True):
+    img, tgt = images.image_pair(seed, W, H)
+    rng = np.random.default_rng(seed + 50)
+    emb = rng.normal(0, 1, A.EMBED).astype(np.float32)
+    layers = _params(seed + 1)
+    flat = ap.pack(layers)
+    if l1_gradient:
+        params64 = [(w.astype(np.float64), b.astype(np.float64)) for w, b in layers]
+        _, Ia, _ = A.forward(img.astype(np.float64), emb.astype(np.float64), params64)
+        d_adj = (0.8 * np.sign(Ia - tgt) / (3 * H * W)).astype(np.float32)
+    else:
+        d_adj = (rng.uniform(-1, 1, (3, H, W)) / (3 * H * W)).astype(np.float32)
+    d_prev = (rng.uniform(-1, 1, (3, H, W)) / (3 * H * W)).astype(np.float32)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    model = ap.AppearanceModel(H, W, dev(flat))
+    ti, te = dev(img), dev(emb)
+    Ia = model.forward(ti, te).cpu().numpy()
+    M = model.transform.cpu().numpy()
+    d_img = dev(d_prev)
+    d_emb, d_par = model.backward(ti, te, dev(d_adj), d_img)
+    torch.cuda.synchronize()
+    got = dict(M=M, Ia=Ia, d_img=d_img.cpu().numpy() - d_prev, d_emb=d_emb.cpu().numpy(),
+               d_par=d_par.cpu().numpy())
+    params64 = [(w.astype(np.float64), b.astype(np.float64)) for w, b in layers]
+    rM, rIa, cache = A.forward(img.astype(np.float64), emb.astype(np.float64), params64)
+    r_img, r_emb, r_grads = A.backward(img.astype(np.float64), emb.astype(np.float64), params64, cache, rM,
+                                       d_adj.astype(np.float64))
+    mag = _magnitudes(img.astype(np.float64), emb.astype(np.float64), params64, cache, rM, d_adj.astype(np.float64))
+    return got, dict(M=rM, Ia=rIa, d_img=r_img, d_emb=r_emb, grads=r_grads, mag=mag)
+
+
+def _magnitudes(img, emb, params, cache, M, d_adj):
+    """Sum of the absolute values of the terms behind every gradient
+    element: the oracle's backward chain on absolute values, with the
+    forward's ReLU masks."""
+    a = np.abs
+    H, W = cache["H"], cache["W"]
+    d_img = a(d_adj) * a(M)
+    g = a(d_adj) * a(img)
+    mags = [None] * 7
+    g, dw, db = A.conv3x3_backward(a(cache["f1"]), a(params[6][0]), g)
+    mags[6] = (dw, db)
+    g = g * (cache["f1"] > 0)
+    g, dw, db = A.conv3x3_backward(a(cache["u"]), a(params[5][0]), g)
+    mags[5] = (dw, db)
+    g = A.bilinear_adjoint(g, cache["x4"].shape[1], cache["x4"].shape[2])
+    for k in range(4, 0, -1):
+        g = g * (cache[f"x{k}"] > 0)
+        g, dw, db = A.conv3x3_backward(a(cache[f"s{k}"]), a(params[k][0]), g)
+        mags[k] = (dw, db)
+        g = A.pixel_shuffle_adjoint(g)
+    g, dw, db = A.conv3x3_backward(a(cache["D"]), a(params[0][0]), g)
+    mags[0] = (dw, db)
+    return d_img + A.downsample_adjoint(g[:3], H, W), g[3:].sum(axis=(1, 2)), mags
+
+
+def _grad_ok(name, got, ref, mag):
+    got = np.asarray(got, np.float64)
+    err = np.abs(got - ref)
+    lim = 1e-4 * mag + 1e-30
+    worst = float(np.max(err / lim)) if err.size else 0.0
+    nrm = np.linalg.norm(ref)
+    rel = np.linalg.norm(got - ref) / nrm if nrm > 0 else 0.0
+    print(f"{name}: max err/bound {worst:.3f}, norm rel {rel:.2e}", flush=True)
+    assert worst <= 1.0 and rel <= 1e-3, (name, worst, rel)
+
+
+def _check(got, ref):
+    scale = np.abs(ref["M"]).max()
+    err = np.abs(got["M"] - ref["M"]).max()
+    print(f"M max err {err:.3e} (scale {scale:.3e})", flush=True)
+    assert err <= 1e-4 * scale
+    assert np.abs(got["Ia"] - ref["Ia"]).max() <= 1e-4 * np.abs(ref["Ia"]).max()
+    m_img, m_emb, m_par = ref["mag"]
+    _grad_ok("d_image", got["d_img"], ref["d_img"], m_img)
+    _grad_ok("d_embedding", got["d_emb"], ref["d_emb"], m_emb)
+    layers = ap.unpack(got["d_par"])
+    for k, ((gw, gb), (rw, rb), (mw, mb)) in enumerate(zip(layers, ref["grads"], m_par)):
+        _grad_ok(f"layer {k} weights", gw, rw, mw)
+        _grad_ok(f"layer {k} bias", gb, rb, mb)
+
+
+@pytest.mark.parametrize("H,W,seed,l1", [(70, 100, 1, False), (64, 64, 2, True), (33, 95, 3, False),
+                                         (1, 1, 4, False), (97, 31, 5, True)])
+def test_appearance_matches_the_oracle(H, W, seed, l1):
+    _case(f"appearance {H}x{W} ({'L1' if l1 else 'random'} gradient)")
+    got, ref = _run(H, W, seed, l1)
+    _check(got, ref)
+
+
+def test_appearance_full_hd():
+    """1920 x 1080, the size the benchmark times: every output and gradient
+    against the oracle on the whole image."""
+    _case("appearance 1920x1080")
+    got, ref = _run(1080, 1920, 6)
+    _check(got, ref)
+
+
+def test_appearance_is_deterministic():
+    _case("appearance determinism")
+    H, W = 120, 200
+    img, _ = images.image_pair(7, W, H)
+    layers = _params(8)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    model = ap.AppearanceModel(H, W, dev(ap.pack(layers)))
+    ti, te = dev(img), dev(np.ones(A.EMBED, np.float32))
+    g = dev(np.full((3, H, W), 1e-5, np.float32))
+    outs = []
+    for _ in range(2):
+        Ia = model.forward(ti, te).clone()
+        d = torch.zeros_like(ti)
+        de, dp = model.backward(ti, te, g, d)
+        outs.append((Ia, d.clone(), de.clone(), dp.clone()))
+    torch.cuda.synchronize()
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
