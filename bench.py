@@ -19,7 +19,9 @@ own roofline and oracle timing, and a `train_step` object times a complete
 optimisation step of the cell (render, loss, backward, Adam step with the
 densification statistics), with the optimiser kernel's HBM roofline; a
 `partition` object times the progressive data partitioning of a synthetic
-drone survey (host view selection, device point selection).  Every HIP event pair between two kernels adds a
+drone survey (host view selection, device point selection); an
+`appearance` object times the decoupled appearance model (forward and
+backward at 1080p).  Every HIP event pair between two kernels adds a
 few microseconds to the step, so the per-stage breakdown comes from a first
 loop with every stage bracketed, and the timed loop (the value) brackets
 only the dominant stage, whose average duration over the timed steps gives
@@ -279,6 +281,76 @@ def bench_train(args, torch, N, frame, dg, cam):
         out["cpu_baseline"] = {"value": round(n / dt / 1e6, 3), "unit": "MGaussian/s", "cores": 1, "kind": "oracle",
                                "sample": f"one optimiser step of {n} Gaussians x {planes} planes in {dt:.1f} s "
                                          "(NumPy FP64, one thread)"}
+    return out
+
+
+def appearance_fmas(H, W, embed=64):
+    """Multiply-adds of the appearance CNN's convolutions at H x W (forward;
+    the backward does twice as many: input and weight gradients)."""
+    h, w = -(-H // 32), -(-W // 32)
+    layers = [(256, 3 + embed, h * w), (128, 64, 4 * h * w), (64, 32, 16 * h * w), (32, 16, 64 * h * w),
+              (16, 8, 256 * h * w), (16, 16, H * W), (3, 16, H * W)]
+    return sum(co * ci * 9 * px for co, ci, px in layers)
+
+
+def bench_appearance(args, torch, N):
+    """Decoupled appearance model (section 4.2, supplement S1.1) on a
+    1920x1080 render: forward (downsample, embedding, CNN, multiply) and
+    backward (input, embedding and parameter gradients), inputs resident."""
+    import numpy as np
+    from gen import images
+    from paper_2402_17427_amd import appearance as ap
+    W, H = args.width, args.height
+    r, t = images.image_pair(5, W, H)
+    rng = np.random.default_rng(3)
+    layers = [(rng.normal(0, 0.06, (co, ci, 3, 3)), rng.normal(0, 0.02, co)) for co, ci in ap.layer_shapes()]
+    layers[6] = (layers[6][0], layers[6][1] + 1.0)
+    flat = torch.as_tensor(ap.pack(layers)).cuda()
+    model = ap.AppearanceModel(H, W, flat)
+    img = torch.as_tensor(r).cuda()
+    emb = torch.as_tensor(rng.normal(0, 1, 64).astype(np.float32)).cuda()
+    g = torch.as_tensor((0.8 * np.sign(rng.uniform(-1, 1, (3, H, W))) / (3 * H * W)).astype(np.float32)).cuda()
+    d_img = torch.zeros_like(img)
+    for _ in range(3):
+        model.forward(img, emb)
+        model.backward(img, emb, g, d_img)
+    torch.cuda.synchronize()
+    steps = max(10, args.steps)
+    N.profile_select(["appearance_fwd", "appearance_bwd"])
+    N.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        model.forward(img, emb)
+        model.backward(img, emb, g, d_img)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    prof = N.profile_report()
+    N.profile_enable(False)
+    N.profile_select(None)
+    f_ms = prof["appearance_fwd"][0] / prof["appearance_fwd"][1]
+    b_ms = prof["appearance_bwd"][0] / prof["appearance_bwd"][1]
+    fma = appearance_fmas(H, W)
+    achieved = 3 * fma / ((f_ms + b_ms) * 1e-3) / 1e12
+    peak = VALU_PEAK_GOPS / 1e3
+    out = {"workload": f"appearance model on a {W}x{H} render: x32 downsample, 64-d embedding, supplement CNN "
+                       f"(255,539 parameters), I^a = I^r * M; forward and backward",
+           "value": round(W * H / (ms * 1e-3) / 1e6, 1), "unit": "Mpix/s", "ms_per_call": round(ms, 4),
+           "fwd_ms": round(f_ms, 4), "bwd_ms": round(b_ms, 4),
+           "roofline": {"bound": "alu", "kernel": "appearance fwd+bwd (all layers)", "achieved": round(achieved, 3),
+                        "peak": round(peak, 3), "unit": "Tlane-op/s", "frac": round(achieved / peak, 4),
+                        "traffic": None, "work_lane_ops": int(3 * fma), "avg_ms": round(f_ms + b_ms, 4)}}
+    if not args.no_cpu_baseline:
+        import oracle.appearance as orc
+        hs, ws = H // 4, W // 4
+        params64 = [(wt.astype(np.float64), b.astype(np.float64)) for wt, b in layers]
+        im = r[:, :hs * 4:4, :ws * 4:4].astype(np.float64)
+        t0 = time.perf_counter()
+        M, _, cache = orc.forward(im, np.ones(64), params64)
+        orc.backward(im, np.ones(64), params64, cache, M, np.ones((3, hs, ws)))
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(hs * ws / dt / 1e6, 6), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+                               "sample": f"forward + backward at {ws}x{hs} (1/16 of the pixels) in {dt:.1f} s "
+                                         "(NumPy FP64)"}
     return out
 
 
@@ -677,6 +749,8 @@ def main():
         out["loss"] = bench_loss(args, torch, N)
         print("[bench] training step", file=sys.stderr, flush=True)
         out["train_step"] = bench_train(args, torch, N, frame, dg, cam)
+        print("[bench] appearance model", file=sys.stderr, flush=True)
+        out["appearance"] = bench_appearance(args, torch, N)
     if not args.no_forms:
         print("[bench] partitioning", file=sys.stderr, flush=True)
         out["partition"] = bench_partition(args, torch, N)

@@ -37,7 +37,7 @@ struct Plan {
     int64_t poff[kLayers];   // parameter offsets (weights, then bias)
     int64_t n_params;
     // workspace offsets (bytes)
-    size_t D, x[5], s[5], u, f1, M, gA, gB, part, ty0, ty1, tfy, tx0, tx1, tfx, bytes;
+    size_t D, x[5], s[5], u, f1, M, gA, gB, part, tmp, ty0, ty1, tfy, tx0, tx1, tfx, rylo, ryhi, rxlo, rxhi, bytes;
 };
 
 void make_plan(int W, int H, int m, Plan* p) {
@@ -84,12 +84,17 @@ void make_plan(int W, int H, int m, Plan* p) {
     p->gA = take(gmax);
     p->gB = take(gmax);
     p->part = take(pmax);
+    p->tmp = take(16 * (int64_t)H * (p->w * 16));   // x pass of the interpolation adjoint
     p->ty0 = take(H);
     p->ty1 = take(H);
     p->tfy = take(H);
     p->tx0 = take(W);
     p->tx1 = take(W);
     p->tfx = take(W);
+    p->rylo = take(p->h * 16);
+    p->ryhi = take(p->h * 16);
+    p->rxlo = take(p->w * 16);
+    p->rxhi = take(p->w * 16);
     p->bytes = off;
 }
 
@@ -112,6 +117,10 @@ BilinTab tables(const Plan& p, void* ws) {
     t.x0 = at<int>(ws, p.tx0);
     t.x1 = at<int>(ws, p.tx1);
     t.fx = at<float>(ws, p.tfx);
+    t.ylo = at<int>(ws, p.rylo);
+    t.yhi = at<int>(ws, p.ryhi);
+    t.xlo = at<int>(ws, p.rxlo);
+    t.xhi = at<int>(ws, p.rxhi);
     return t;
 }
 
@@ -262,7 +271,7 @@ gs_status gs_appearance_bwd(const float* image, int32_t width, int32_t height, c
     launch_conv(conv_args(gB, f1, params + p.poff[5], nullptr, gA, 16, 16, H, W, true, false, 16), st);
     // interpolation
     const int h4 = h * 16, w4 = w * 16;
-    launch_bilinear_adj(gA, 16, H, W, h4, w4, tables(p, ws), gB, st);
+    launch_bilinear_adj(gA, 16, H, W, h4, w4, tables(p, ws), at<float>(ws, p.tmp), gB, st);
     // upsampling blocks, last to first
     int hk = h4, wk = w4, C = 16;   // C: the block's output channels
     for (int k = 4; k >= 1; --k) {

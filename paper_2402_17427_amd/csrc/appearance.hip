@@ -9,10 +9,10 @@
 // adjusted image is I^r * M.
 //
 // Every layer works on planar FP32 maps [C][H][W].  The convolutions are
-// direct: a workgroup computes a 16 x 16 pixel tile for a group of output
-// channels, staging the input tile with its one-pixel halo in LDS a few
-// input channels at a time; the weights are the same for the whole
-// workgroup and come through scalar loads.  The same kernel runs the
+// direct: a workgroup computes a 16 x 32 pixel tile (two rows per thread)
+// for a group of output channels, staging the input tile with its
+// one-pixel halo and the chunk's weights (as [ci][tap][co], read by every
+// lane at once) in LDS a few input channels at a time.  The same kernel runs the
 // transposed convolution of the backward (weights read flipped and
 // transposed) with the ReLU mask of the layer applied to its input as it
 // is staged.  Weight gradients are per-workgroup partial sums over pixel
@@ -28,8 +28,10 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kCI = 8;             // input channels staged per round
-constexpr int kTile = 16;          // output tile edge of the convolution
-constexpr int kHalo = kTile + 2;   // staged tile edge
+constexpr int kTile = 16;          // output tile width of the convolution
+constexpr int kTileR = 32;         // its height (two rows per thread)
+constexpr int kHalo = kTile + 2;   // staged tile width
+constexpr int kInR = kTileR + 2;   // staged tile height
 constexpr int kWR = 8, kWC = 32;   // pixel tile of the weight gradient
 
 __global__ __launch_bounds__(kT) void k_down_concat(const float* __restrict__ img, int H, int W, int h, int w,
@@ -73,19 +75,27 @@ __global__ __launch_bounds__(kT) void k_down_adjoint(const float* __restrict__ g
 
 template <int CO>
 __global__ __launch_bounds__(kT) void k_conv(ConvArgs a) {
-    __shared__ float s_in[kCI * kHalo * kHalo];
-    const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
-    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    // input tile (16 wide, 32 tall, one-pixel halo) and the chunk's weights
+    // as [ci][tap][co], read by every lane at the same address
+    __shared__ float s_in[kCI * kInR * kHalo];
+    __shared__ float4 s_w[kCI * 9 * (CO / 4)];
+    const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;   // ty 0..15, rows 2 ty, 2 ty + 1
+    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTileR;
     const int og = blockIdx.z * CO;
     const int64_t HW = (int64_t)a.H * a.W;
-    const int px = x0 + tx, py = y0 + ty;
-    float acc[CO];
+    const int px = x0 + tx, py = y0 + 2 * ty;
+    float acc0[CO], acc1[CO];
 #pragma unroll
-    for (int k = 0; k < CO; ++k) acc[k] = (a.b && og + k < a.Cout) ? a.b[og + k] : 0.f;
+    for (int k = 0; k < CO; ++k) {
+        const float b = (a.b && og + k < a.Cout) ? a.b[og + k] : 0.f;
+        acc0[k] = b;
+        acc1[k] = b;
+    }
+    float* s_wf = reinterpret_cast<float*>(s_w);
     for (int c0 = 0; c0 < a.Cin; c0 += kCI) {
         __syncthreads();
-        for (int k = threadIdx.x; k < kCI * kHalo * kHalo; k += kT) {
-            const int c = k / (kHalo * kHalo), r = (k / kHalo) % kHalo, q = k % kHalo;
+        for (int k = threadIdx.x; k < kCI * kInR * kHalo; k += kT) {
+            const int c = k / (kInR * kHalo), r = (k / kHalo) % kInR, q = k % kHalo;
             const int gy = y0 - 1 + r, gx = x0 - 1 + q;
             float v = 0.f;
             if (c0 + c < a.Cin && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
@@ -95,34 +105,51 @@ __global__ __launch_bounds__(kT) void k_conv(ConvArgs a) {
             }
             s_in[k] = v;
         }
+        for (int k = threadIdx.x; k < kCI * 9 * CO; k += kT) {
+            const int c = k / (9 * CO), t = (k / CO) % 9, co = k % CO;
+            const int ci = c0 + c, o = og + co;
+            float v = 0.f;
+            if (ci < a.Cin && o < a.Cout) {
+                // forward: w[o][ci][t]; transposed: w[ci][o][8 - t] of the
+                // forward layer (its output channel ci, input channel o)
+                v = a.transposed ? a.w[((int64_t)ci * a.CinF + o) * 9 + (8 - t)] : a.w[((int64_t)o * a.Cin + ci) * 9 + t];
+            }
+            s_wf[k] = v;
+        }
         __syncthreads();
         const int cn = min(kCI, a.Cin - c0);
         for (int c = 0; c < cn; ++c) {
-            float v[9];
+            float v[12];   // rows 2 ty .. 2 ty + 3 of the staged tile, columns tx .. tx + 2
 #pragma unroll
-            for (int t = 0; t < 9; ++t) v[t] = s_in[(c * kHalo + ty + t / 3) * kHalo + tx + t % 3];
-            const int ci = c0 + c;
+            for (int t = 0; t < 12; ++t) v[t] = s_in[(c * kInR + 2 * ty + t / 3) * kHalo + tx + t % 3];
 #pragma unroll
-            for (int k = 0; k < CO; ++k) {
-                const int o = og + k;
-                if (o >= a.Cout) break;
-                // forward: w[o][ci][tap]; transposed: w[ci][o][8 - tap] of the
-                // forward layer (its output channel ci, input channel o)
-                const float* wr = a.transposed ? a.w + ((int64_t)ci * a.CinF + o) * 9
-                                               : a.w + ((int64_t)o * a.Cin + ci) * 9;
-                float s = acc[k];
+            for (int t = 0; t < 9; ++t) {
+                const float u0 = v[t], u1 = v[t + 3];
 #pragma unroll
-                for (int t = 0; t < 9; ++t) s = fmaf(a.transposed ? wr[8 - t] : wr[t], v[t], s);
-                acc[k] = s;
+                for (int q = 0; q < CO / 4; ++q) {
+                    const float4 w4 = s_w[(c * 9 + t) * (CO / 4) + q];
+                    acc0[4 * q + 0] = fmaf(w4.x, u0, acc0[4 * q + 0]);
+                    acc0[4 * q + 1] = fmaf(w4.y, u0, acc0[4 * q + 1]);
+                    acc0[4 * q + 2] = fmaf(w4.z, u0, acc0[4 * q + 2]);
+                    acc0[4 * q + 3] = fmaf(w4.w, u0, acc0[4 * q + 3]);
+                    acc1[4 * q + 0] = fmaf(w4.x, u1, acc1[4 * q + 0]);
+                    acc1[4 * q + 1] = fmaf(w4.y, u1, acc1[4 * q + 1]);
+                    acc1[4 * q + 2] = fmaf(w4.z, u1, acc1[4 * q + 2]);
+                    acc1[4 * q + 3] = fmaf(w4.w, u1, acc1[4 * q + 3]);
+                }
             }
         }
     }
-    if (px < a.W && py < a.H) {
+    if (px < a.W) {
 #pragma unroll
         for (int k = 0; k < CO; ++k) {
             const int o = og + k;
-            if (o >= a.Cout) break;
-            a.out[(int64_t)o * HW + (int64_t)py * a.W + px] = a.relu ? fmaxf(acc[k], 0.f) : acc[k];
+            if (o < a.Cout) {
+                if (py < a.H)
+                    a.out[(int64_t)o * HW + (int64_t)py * a.W + px] = a.relu ? fmaxf(acc0[k], 0.f) : acc0[k];
+                if (py + 1 < a.H)
+                    a.out[(int64_t)o * HW + (int64_t)(py + 1) * a.W + px] = a.relu ? fmaxf(acc1[k], 0.f) : acc1[k];
+            }
         }
     }
 }
@@ -266,44 +293,62 @@ __global__ __launch_bounds__(kT) void k_bilinear(const float* __restrict__ in, i
     out[q] = (1.f - a) * top + a * bot;
 }
 
-// weight of output index d on input index i along one axis
-__device__ __forceinline__ float axis_weight(int d, int i, const int* i0, const int* i1, const float* f) {
-    float wgt = 0.f;
-    if (i0[d] == i) wgt += 1.f - f[d];
-    if (i1[d] == i) wgt += f[d];
-    return wgt;
+// Outputs d reading input i along one axis are those with i0[d] <= i <=
+// i1[d] (i1 is i0 or i0 + 1, both nondecreasing in d): a contiguous range,
+// found by a short scan from its estimate.
+__device__ __forceinline__ void axis_range(int i, int n_in, int n_out, const int* i0, const int* i1, int* lo, int* hi) {
+    const float sc = (float)n_out / (float)n_in;
+    int d = (int)floorf(((float)i - 0.5f) * sc - 0.5f) - 2;
+    d = max(0, min(d, n_out));
+    while (d > 0 && i1[d - 1] >= i) --d;
+    while (d < n_out && i1[d] < i) ++d;
+    int e = d;
+    while (e < n_out && i0[e] <= i) ++e;
+    *lo = d;
+    *hi = e;
 }
 
-// adjoint of k_bilinear: each input pixel gathers from the outputs that
-// read it (a window of output indices around its image)
-__global__ __launch_bounds__(kT) void k_bilinear_adj(const float* __restrict__ g, int C, int H, int W, int h, int w,
-                                                     const int* __restrict__ y0, const int* __restrict__ y1,
-                                                     const float* __restrict__ fy, const int* __restrict__ x0,
-                                                     const int* __restrict__ x1, const float* __restrict__ fx,
-                                                     float* __restrict__ out) {
-    const int64_t hw = (int64_t)h * w;
+// per input index, the [lo, hi) range of outputs that read it
+__global__ void k_bilin_ranges(int n_in, int n_out, const int* __restrict__ i0, const int* __restrict__ i1,
+                               int* __restrict__ lo, int* __restrict__ hi) {
+    const int i = blockIdx.x * kT + threadIdx.x;
+    if (i >= n_in) return;
+    int a, b;
+    axis_range(i, n_in, n_out, i0, i1, &a, &b);
+    lo[i] = a;
+    hi[i] = b;
+}
+
+// adjoint of k_bilinear along one axis: out[c][r][i] = sum over the
+// outputs d that read input i of their weight times g[c][r][d], for rows r
+// (the x pass: stride 1 within a row) or columns (the y pass: stride = row
+// length); the two passes together give the 2D adjoint
+__global__ __launch_bounds__(kT) void k_bilinear_adj_axis(const float* __restrict__ g, int64_t lines, int n_out,
+                                                          int n_in, int64_t line_stride_g, int64_t line_stride_o,
+                                                          int64_t elem_stride, const int* __restrict__ i0,
+                                                          const int* __restrict__ i1, const float* __restrict__ f,
+                                                          const int* __restrict__ rlo, const int* __restrict__ rhi,
+                                                          float* __restrict__ out) {
     const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (q >= C * hw) return;
-    const int c = (int)(q / hw);
-    const int64_t p = q - c * hw;
-    const int yi = (int)(p / w), xi = (int)(p - (int64_t)yi * w);
-    // outputs d read input i only if |d + 0.5 - (i + 0.5) n_out / n_in| < n_out / n_in + 1
-    const float sy = (float)H / (float)h, sx = (float)W / (float)w;
-    const int ya = max(0, (int)floorf((yi - 1.f) * sy) - 1), yb = min(H - 1, (int)ceilf((yi + 2.f) * sy) + 1);
-    const int xa = max(0, (int)floorf((xi - 1.f) * sx) - 1), xb = min(W - 1, (int)ceilf((xi + 2.f) * sx) + 1);
-    const float* gc = g + (int64_t)c * H * W;
-    float s = 0.f;
-    for (int Y = ya; Y <= yb; ++Y) {
-        const float wy = axis_weight(Y, yi, y0, y1, fy);
-        if (wy == 0.f) continue;
-        float r = 0.f;
-        for (int X = xa; X <= xb; ++X) {
-            const float wx = axis_weight(X, xi, x0, x1, fx);
-            if (wx != 0.f) r = fmaf(wx, gc[(int64_t)Y * W + X], r);
-        }
-        s = fmaf(wy, r, s);
+    if (q >= lines * n_in) return;
+    // consecutive threads take consecutive lines (coalesced for the y pass)
+    // or consecutive inputs of a line (the x pass): elem_stride decides
+    int64_t line, i;
+    if (elem_stride == 1) {
+        line = q / n_in;
+        i = q - line * n_in;
+    } else {
+        i = q / lines;
+        line = q - i * lines;
     }
-    out[q] = s;
+    const int lo = rlo[i], hi = rhi[i];
+    const float* gl = g + line * line_stride_g;
+    float s = 0.f;
+    for (int d = lo; d < hi; ++d) {
+        const float wgt = (i0[d] == i ? 1.f - f[d] : 0.f) + (i1[d] == i ? f[d] : 0.f);
+        s = fmaf(wgt, gl[(int64_t)d * elem_stride], s);
+    }
+    out[line * line_stride_o + i * elem_stride] = s;
 }
 
 __global__ __launch_bounds__(kT) void k_mul(const float* __restrict__ a, const float* __restrict__ b, int64_t n,
@@ -353,7 +398,7 @@ void launch_down_adjoint(const float* g, int H, int W, int h, int w, float* d_im
 }
 
 void launch_conv(const ConvArgs& a, hipStream_t st) {
-    const dim3 grid_base((a.W + kTile - 1) / kTile, (a.H + kTile - 1) / kTile);
+    const dim3 grid_base((a.W + kTile - 1) / kTile, (a.H + kTileR - 1) / kTileR);
     if (a.Cout <= 4) {
         hipLaunchKernelGGL(k_conv<4>, dim3(grid_base.x, grid_base.y, (a.Cout + 3) / 4), dim3(kT), 0, st, a);
     } else {
@@ -388,10 +433,19 @@ void launch_bilinear(const float* in, int C, int h, int w, int H, int W, const B
                        t.y1, t.fy, t.x0, t.x1, t.fx, out);
 }
 
-void launch_bilinear_adj(const float* g, int C, int H, int W, int h, int w, const BilinTab& t, float* out,
-                         hipStream_t st) {
-    hipLaunchKernelGGL(k_bilinear_adj, dim3(blocks_for((int64_t)C * h * w)), dim3(kT), 0, st, g, C, H, W, h, w, t.y0,
-                       t.y1, t.fy, t.x0, t.x1, t.fx, out);
+void launch_bilinear_adj(const float* g, int C, int H, int W, int h, int w, const BilinTab& t, float* tmp,
+                         float* out, hipStream_t st) {
+    // x pass: [C][H][W] -> tmp [C][H][w]; lines = C H rows
+    const int64_t rows = (int64_t)C * H;
+    hipLaunchKernelGGL(k_bilin_ranges, dim3(blocks_for(w)), dim3(kT), 0, st, w, W, t.x0, t.x1, t.xlo, t.xhi);
+    hipLaunchKernelGGL(k_bilin_ranges, dim3(blocks_for(h)), dim3(kT), 0, st, h, H, t.y0, t.y1, t.ylo, t.yhi);
+    hipLaunchKernelGGL(k_bilinear_adj_axis, dim3(blocks_for(rows * w)), dim3(kT), 0, st, g, rows, W, w, (int64_t)W,
+                       (int64_t)w, (int64_t)1, t.x0, t.x1, t.fx, t.xlo, t.xhi, tmp);
+    // y pass: tmp [C][H][w] -> out [C][h][w]; per channel, lines = w columns
+    for (int c = 0; c < C; ++c)
+        hipLaunchKernelGGL(k_bilinear_adj_axis, dim3(blocks_for((int64_t)w * h)), dim3(kT), 0, st,
+                           tmp + (int64_t)c * H * w, (int64_t)w, H, h, (int64_t)1, (int64_t)1, (int64_t)w, t.y0, t.y1,
+                           t.fy, t.ylo, t.yhi, out + (int64_t)c * h * w);
 }
 
 void launch_mul(const float* a, const float* b, int64_t n, float* out, hipStream_t st) {

@@ -221,12 +221,14 @@ void launch_shuffle(const float* in, int C, int h, int w, float* out, bool inver
 struct BilinTab {
     const int *y0, *y1, *x0, *x1;
     const float *fy, *fx;
+    int *ylo, *yhi, *xlo, *xhi;   // adjoint ranges per input index (written by launch_bilinear_adj)
 };
 void launch_bilin_table(int n_in, int n_out, int* i0, int* i1, float* f, hipStream_t st);
 void launch_bilinear(const float* in, int C, int h, int w, int H, int W, const BilinTab& t, float* out,
                      hipStream_t st);
-void launch_bilinear_adj(const float* g, int C, int H, int W, int h, int w, const BilinTab& t, float* out,
-                         hipStream_t st);
+// tmp: C H w floats of scratch
+void launch_bilinear_adj(const float* g, int C, int H, int W, int h, int w, const BilinTab& t, float* tmp,
+                         float* out, hipStream_t st);
 void launch_mul(const float* a, const float* b, int64_t n, float* out, hipStream_t st);
 void launch_mul_bwd(const float* d_adj, const float* img, const float* M, int64_t n, float* dM, float* d_img,
                     hipStream_t st);
