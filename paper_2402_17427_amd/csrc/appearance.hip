@@ -9,8 +9,8 @@
 // adjusted image is I^r * M.
 //
 // Every layer works on planar FP32 maps [C][H][W].  The convolutions are
-// direct: a workgroup computes a 16 x 32 pixel tile (two rows per thread)
-// for a group of output channels, staging the input tile with its
+// direct: a workgroup computes a 16-wide pixel tile of one to four rows
+// per thread for a group of 4 or 16 output channels (chosen per layer), staging the input tile with its
 // one-pixel halo and the chunk's weights (as [ci][tap][co], read by every
 // lane at once) in LDS a few input channels at a time.  The same kernel runs the
 // transposed convolution of the backward (weights read flipped and
@@ -29,9 +29,7 @@ namespace {
 constexpr int kT = 256;
 constexpr int kCI = 8;             // input channels staged per round
 constexpr int kTile = 16;          // output tile width of the convolution
-constexpr int kTileR = 32;         // its height (two rows per thread)
 constexpr int kHalo = kTile + 2;   // staged tile width
-constexpr int kInR = kTileR + 2;   // staged tile height
 constexpr int kWR = 8, kWC = 32;   // pixel tile of the weight gradient
 
 __global__ __launch_bounds__(kT) void k_down_concat(const float* __restrict__ img, int H, int W, int h, int w,
@@ -73,29 +71,31 @@ __global__ __launch_bounds__(kT) void k_down_adjoint(const float* __restrict__ g
     d_img[q] += g[(int64_t)c * h * w + (int64_t)by * w + bx] / (float)(ny * nx);
 }
 
-template <int CO>
+template <int CO, int R>
 __global__ __launch_bounds__(kT) void k_conv(ConvArgs a) {
-    // input tile (16 wide, 32 tall, one-pixel halo) and the chunk's weights
-    // as [ci][tap][co], read by every lane at the same address
-    __shared__ float s_in[kCI * kInR * kHalo];
+    // input tile (16 wide, 16 R tall, one-pixel halo) and the chunk's
+    // weights as [ci][tap][co], read by every lane at the same address
+    constexpr int TR = kTile * R;       // output rows of the tile
+    constexpr int IR = TR + 2;          // staged rows
+    __shared__ float s_in[kCI * IR * kHalo];
     __shared__ float4 s_w[kCI * 9 * (CO / 4)];
-    const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;   // ty 0..15, rows 2 ty, 2 ty + 1
-    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTileR;
+    const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;   // rows R ty .. R ty + R - 1
+    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * TR;
     const int og = blockIdx.z * CO;
     const int64_t HW = (int64_t)a.H * a.W;
-    const int px = x0 + tx, py = y0 + 2 * ty;
-    float acc0[CO], acc1[CO];
+    const int px = x0 + tx, py = y0 + R * ty;
+    float acc[R][CO];
 #pragma unroll
     for (int k = 0; k < CO; ++k) {
         const float b = (a.b && og + k < a.Cout) ? a.b[og + k] : 0.f;
-        acc0[k] = b;
-        acc1[k] = b;
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r][k] = b;
     }
     float* s_wf = reinterpret_cast<float*>(s_w);
     for (int c0 = 0; c0 < a.Cin; c0 += kCI) {
         __syncthreads();
-        for (int k = threadIdx.x; k < kCI * kInR * kHalo; k += kT) {
-            const int c = k / (kInR * kHalo), r = (k / kHalo) % kInR, q = k % kHalo;
+        for (int k = threadIdx.x; k < kCI * IR * kHalo; k += kT) {
+            const int c = k / (IR * kHalo), r = (k / kHalo) % IR, q = k % kHalo;
             const int gy = y0 - 1 + r, gx = x0 - 1 + q;
             float v = 0.f;
             if (c0 + c < a.Cin && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
@@ -119,23 +119,22 @@ __global__ __launch_bounds__(kT) void k_conv(ConvArgs a) {
         __syncthreads();
         const int cn = min(kCI, a.Cin - c0);
         for (int c = 0; c < cn; ++c) {
-            float v[12];   // rows 2 ty .. 2 ty + 3 of the staged tile, columns tx .. tx + 2
+            float v[(R + 2) * 3];   // rows R ty .. R ty + R + 1 of the staged tile, columns tx .. tx + 2
 #pragma unroll
-            for (int t = 0; t < 12; ++t) v[t] = s_in[(c * kInR + 2 * ty + t / 3) * kHalo + tx + t % 3];
+            for (int t = 0; t < (R + 2) * 3; ++t) v[t] = s_in[(c * IR + R * ty + t / 3) * kHalo + tx + t % 3];
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
-                const float u0 = v[t], u1 = v[t + 3];
 #pragma unroll
                 for (int q = 0; q < CO / 4; ++q) {
                     const float4 w4 = s_w[(c * 9 + t) * (CO / 4) + q];
-                    acc0[4 * q + 0] = fmaf(w4.x, u0, acc0[4 * q + 0]);
-                    acc0[4 * q + 1] = fmaf(w4.y, u0, acc0[4 * q + 1]);
-                    acc0[4 * q + 2] = fmaf(w4.z, u0, acc0[4 * q + 2]);
-                    acc0[4 * q + 3] = fmaf(w4.w, u0, acc0[4 * q + 3]);
-                    acc1[4 * q + 0] = fmaf(w4.x, u1, acc1[4 * q + 0]);
-                    acc1[4 * q + 1] = fmaf(w4.y, u1, acc1[4 * q + 1]);
-                    acc1[4 * q + 2] = fmaf(w4.z, u1, acc1[4 * q + 2]);
-                    acc1[4 * q + 3] = fmaf(w4.w, u1, acc1[4 * q + 3]);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const float u = v[t + 3 * r];
+                        acc[r][4 * q + 0] = fmaf(w4.x, u, acc[r][4 * q + 0]);
+                        acc[r][4 * q + 1] = fmaf(w4.y, u, acc[r][4 * q + 1]);
+                        acc[r][4 * q + 2] = fmaf(w4.z, u, acc[r][4 * q + 2]);
+                        acc[r][4 * q + 3] = fmaf(w4.w, u, acc[r][4 * q + 3]);
+                    }
                 }
             }
         }
@@ -145,10 +144,11 @@ __global__ __launch_bounds__(kT) void k_conv(ConvArgs a) {
         for (int k = 0; k < CO; ++k) {
             const int o = og + k;
             if (o < a.Cout) {
-                if (py < a.H)
-                    a.out[(int64_t)o * HW + (int64_t)py * a.W + px] = a.relu ? fmaxf(acc0[k], 0.f) : acc0[k];
-                if (py + 1 < a.H)
-                    a.out[(int64_t)o * HW + (int64_t)(py + 1) * a.W + px] = a.relu ? fmaxf(acc1[k], 0.f) : acc1[k];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (py + r < a.H)
+                        a.out[(int64_t)o * HW + (int64_t)(py + r) * a.W + px] =
+                            a.relu ? fmaxf(acc[r][k], 0.f) : acc[r][k];
             }
         }
     }
@@ -398,12 +398,29 @@ void launch_down_adjoint(const float* g, int H, int W, int h, int w, float* d_im
 }
 
 void launch_conv(const ConvArgs& a, hipStream_t st) {
-    const dim3 grid_base((a.W + kTile - 1) / kTile, (a.H + kTileR - 1) / kTileR);
-    if (a.Cout <= 4) {
-        hipLaunchKernelGGL(k_conv<4>, dim3(grid_base.x, grid_base.y, (a.Cout + 3) / 4), dim3(kT), 0, st, a);
-    } else {
-        hipLaunchKernelGGL(k_conv<16>, dim3(grid_base.x, grid_base.y, (a.Cout + 15) / 16), dim3(kT), 0, st, a);
+    // The shape with the most reuse (output channels x rows per thread: each
+    // staged weight feeds that many multiply-adds) that still gives every CU
+    // four workgroups; the small maps with many channels take narrow
+    // channel groups and one row per thread.
+    struct Shape {
+        int co, r;
+    };
+    const Shape shapes[] = {{16, 4}, {16, 2}, {4, 2}, {4, 1}};
+    Shape pick = shapes[3];
+    for (const Shape& sh : shapes) {
+        const int64_t blocks = (int64_t)((a.W + kTile - 1) / kTile) * ((a.H + kTile * sh.r - 1) / (kTile * sh.r)) *
+                               ((a.Cout + sh.co - 1) / sh.co);
+        if (blocks >= 1024) {
+            pick = sh;
+            break;
+        }
     }
+    const unsigned gx = (a.W + kTile - 1) / kTile, gy = (a.H + kTile * pick.r - 1) / (kTile * pick.r);
+    const unsigned gz = (a.Cout + pick.co - 1) / pick.co;
+    if (pick.co == 16 && pick.r == 4) hipLaunchKernelGGL((k_conv<16, 4>), dim3(gx, gy, gz), dim3(kT), 0, st, a);
+    else if (pick.co == 16) hipLaunchKernelGGL((k_conv<16, 2>), dim3(gx, gy, gz), dim3(kT), 0, st, a);
+    else if (pick.r == 2) hipLaunchKernelGGL((k_conv<4, 2>), dim3(gx, gy, gz), dim3(kT), 0, st, a);
+    else hipLaunchKernelGGL((k_conv<4, 1>), dim3(gx, gy, gz), dim3(kT), 0, st, a);
 }
 
 int wgrad_parts(int H, int W) {
