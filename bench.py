@@ -93,7 +93,9 @@ def parse():
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--no-forms", action="store_true", help="skip the batched-cells and serving measurements")
-    ap.add_argument("--no-loss", action="store_true", help="skip the training-loss and training-step measurements")
+    ap.add_argument("--no-loss", action="store_true",
+                    help="skip the measurements around the rasterizer (loss, training step, appearance model, "
+                         "partitioning)")
     ap.add_argument("--serve-rates", type=float, nargs="+", default=(100.0, 400.0))
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-grid", type=int, default=10, help="merged scene: grid x grid cells of 200k Gaussians")
@@ -751,7 +753,6 @@ def main():
         out["train_step"] = bench_train(args, torch, N, frame, dg, cam)
         print("[bench] appearance model", file=sys.stderr, flush=True)
         out["appearance"] = bench_appearance(args, torch, N)
-    if not args.no_forms:
         print("[bench] partitioning", file=sys.stderr, flush=True)
         out["partition"] = bench_partition(args, torch, N)
     if not args.no_forms:
