@@ -154,6 +154,82 @@ __global__ __launch_bounds__(kT) void k_conv(ConvArgs a) {
     }
 }
 
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+// The same convolution as an implicit GEMM on the matrix cores:
+// out[o][p] = sum_k W[o][k] X[k][p] with k = (input channel, tap), sixteen
+// output channels by sixteen pixels per v_mfma_f32_16x16x4f32 (FP32 in, FP32
+// accumulate).  A workgroup computes a 16 x 16 pixel tile for 16 output
+// channels; wave w owns tile rows 4w .. 4w + 3, one accumulator each.  Per
+// chunk of 8 input channels the input tile (with its halo) and the
+// [o][ci][tap] weights are staged in LDS; each k-step gives every lane one
+// weight (A: row o = lane % 16, k = lane / 16) and, per row, one input
+// sample (B: k = lane / 16, pixel = lane % 16).
+__global__ __launch_bounds__(kT) void k_conv_mfma(ConvArgs a) {
+    constexpr int KC = kCI * 9;   // k values per chunk (72)
+    __shared__ float s_in[kCI * kHalo * kHalo];
+    __shared__ float s_w[16 * KC];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    const int og = blockIdx.z * 16;
+    const int64_t HW = (int64_t)a.H * a.W;
+    const int li = lane % 16, lk = lane / 16;
+    mfma_f4 acc[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) acc[g] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+    for (int c0 = 0; c0 < a.Cin; c0 += kCI) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < kCI * kHalo * kHalo; k += kT) {
+            const int c = k / (kHalo * kHalo), r = (k / kHalo) % kHalo, q = k % kHalo;
+            const int gy = y0 - 1 + r, gx = x0 - 1 + q;
+            float v = 0.f;
+            if (c0 + c < a.Cin && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
+                const int64_t idx = (int64_t)(c0 + c) * HW + (int64_t)gy * a.W + gx;
+                v = a.in[idx];
+                if (a.mask && !(a.mask[idx] > 0.f)) v = 0.f;
+            }
+            s_in[k] = v;
+        }
+        for (int k = threadIdx.x; k < 16 * KC; k += kT) {
+            const int o = k / KC, kk = k % KC, c = kk / 9, t = kk % 9;
+            const int ci = c0 + c, oo = og + o;
+            float v = 0.f;
+            if (ci < a.Cin && oo < a.Cout)
+                v = a.transposed ? a.w[((int64_t)ci * a.CinF + oo) * 9 + (8 - t)] : a.w[((int64_t)oo * a.Cin + ci) * 9 + t];
+            s_w[k] = v;
+        }
+        __syncthreads();
+        const int steps = (min(kCI, a.Cin - c0) * 9 + 3) / 4;
+        for (int s = 0; s < steps; ++s) {
+            const int k = 4 * s + lk;                  // this lane's k (< KC)
+            const int c = k / 9, t = k - 9 * (k / 9);
+            const int dy = t / 3, dx = t - 3 * (t / 3);
+            const float av = s_w[li * KC + k];
+            const float* src = s_in + c * kHalo * kHalo + (4 * wave + dy) * kHalo + li + dx;
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, src[g * kHalo], acc[g], 0, 0, 0);
+        }
+    }
+    // D[o = 4 (lane / 16) + r][pixel = lane % 16] of row 4 wave + g
+    const int px = x0 + li;
+    if (px < a.W) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int py = y0 + 4 * wave + g;
+            if (py >= a.H) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o = og + 4 * lk + r;
+                if (o < a.Cout) {
+                    float v = acc[g][r] + (a.b ? a.b[o] : 0.f);
+                    a.out[(int64_t)o * HW + (int64_t)py * a.W + px] = a.relu ? fmaxf(v, 0.f) : v;
+                }
+            }
+        }
+    }
+}
+
 // Per-workgroup partial sums of dW[o][i][tap] and db[o] over its pixel
 // tiles (8 x 32, grid-stride); thread (o, i) of a 16 x 16 channel block.
 __global__ __launch_bounds__(kT) void k_wgrad(WgradArgs a) {
@@ -398,29 +474,19 @@ void launch_down_adjoint(const float* g, int H, int W, int h, int w, float* d_im
 }
 
 void launch_conv(const ConvArgs& a, hipStream_t st) {
-    // The shape with the most reuse (output channels x rows per thread: each
-    // staged weight feeds that many multiply-adds) that still gives every CU
-    // four workgroups; the small maps with many channels take narrow
-    // channel groups and one row per thread.
-    struct Shape {
-        int co, r;
-    };
-    const Shape shapes[] = {{16, 4}, {16, 2}, {4, 2}, {4, 1}};
-    Shape pick = shapes[3];
-    for (const Shape& sh : shapes) {
-        const int64_t blocks = (int64_t)((a.W + kTile - 1) / kTile) * ((a.H + kTile * sh.r - 1) / (kTile * sh.r)) *
-                               ((a.Cout + sh.co - 1) / sh.co);
-        if (blocks >= 1024) {
-            pick = sh;
-            break;
-        }
+    if (a.Cout > 4) {
+        // a dense contraction over 9 Cin: the matrix cores
+        const dim3 grid((a.W + kTile - 1) / kTile, (a.H + kTile - 1) / kTile, (a.Cout + 15) / 16);
+        hipLaunchKernelGGL(k_conv_mfma, grid, dim3(kT), 0, st, a);
+        return;
     }
-    const unsigned gx = (a.W + kTile - 1) / kTile, gy = (a.H + kTile * pick.r - 1) / (kTile * pick.r);
-    const unsigned gz = (a.Cout + pick.co - 1) / pick.co;
-    if (pick.co == 16 && pick.r == 4) hipLaunchKernelGGL((k_conv<16, 4>), dim3(gx, gy, gz), dim3(kT), 0, st, a);
-    else if (pick.co == 16) hipLaunchKernelGGL((k_conv<16, 2>), dim3(gx, gy, gz), dim3(kT), 0, st, a);
-    else if (pick.r == 2) hipLaunchKernelGGL((k_conv<4, 2>), dim3(gx, gy, gz), dim3(kT), 0, st, a);
-    else hipLaunchKernelGGL((k_conv<4, 1>), dim3(gx, gy, gz), dim3(kT), 0, st, a);
+    // three or four output channels (the map M): most of a 16-row matrix
+    // tile would be padding, so the VALU kernel, with the shape that still
+    // gives every CU four workgroups
+    const int r = ((int64_t)((a.W + kTile - 1) / kTile) * ((a.H + 2 * kTile - 1) / (2 * kTile)) >= 1024) ? 2 : 1;
+    const unsigned gx = (a.W + kTile - 1) / kTile, gy = (a.H + kTile * r - 1) / (kTile * r);
+    if (r == 2) hipLaunchKernelGGL((k_conv<4, 2>), dim3(gx, gy, 1), dim3(kT), 0, st, a);
+    else hipLaunchKernelGGL((k_conv<4, 1>), dim3(gx, gy, 1), dim3(kT), 0, st, a);
 }
 
 int wgrad_parts(int H, int W) {
