@@ -163,18 +163,24 @@ __global__ __launch_bounds__(kThreads, 3) void k_loss(LossArgs a) {
     const float* __restrict__ gx = a.x + plane;
     const float* __restrict__ gy = a.y + plane;
 
-    // ---- input with a 10-pixel halo, zero outside the image
-    for (int i = tid; i < kAY * kALoad; i += kThreads) {
-        const int r = i / kALoad, c = i - r * kALoad;
-        const int py = y0 - 2 * kR + r, px = x0 - 2 * kR + c;
-        float vx = 0.f, vy = 0.f;
-        if (py >= 0 && py < H && px >= 0 && px < W) {
-            const int64_t q = (int64_t)py * W + px;
-            vx = gx[q];
-            vy = gy[q];
+    // ---- input with a 10-pixel halo, zero outside the image: a wave per
+    // row (lanes 0..53 load), four rows per pass
+    {
+        const int c = tid % kWave, px = x0 - 2 * kR + c;
+        const bool col_ok = c < kALoad && px >= 0 && px < W;
+        for (int r = tid / kWave; r < kAY; r += kThreads / kWave) {
+            const int py = y0 - 2 * kR + r;
+            float vx = 0.f, vy = 0.f;
+            if (col_ok && py >= 0 && py < H) {
+                const int64_t q = (int64_t)py * W + px;
+                vx = gx[q];
+                vy = gy[q];
+            }
+            if (c < kALoad) {
+                sx[r * kAX + c] = vx;
+                sy[r * kAX + c] = vy;
+            }
         }
-        sx[r * kAX + c] = vx;
-        sy[r * kAX + c] = vy;
     }
     __syncthreads();
 
