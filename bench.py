@@ -149,10 +149,105 @@ def cpu_baseline(g, cam, stride):
     oracle.render(g, cam, px, py)
     oracle.backward(g, cam, dimg, px, py)
     dt = time.perf_counter() - t0
-    return {"value": round(px.size / dt / 1e6, 6), "unit": "Mpix/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"fwd+bwd of {px.size} pixels (every {stride}th row and column of the {cam.width}x"
-                      f"{cam.height} view, 1M Gaussians) in {dt:.1f} s, per-view projection and sort included"}
+    threads = oracle.num_threads()
+    out = {"value": round(px.size / dt / 1e6, 6), "unit": "Mpix/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"fwd+bwd of {px.size} pixels (every {stride}th row and column of the {cam.width}x"
+                     f"{cam.height} view, 1M Gaussians) in {dt:.1f} s, per-view projection and sort included",
+           "cpu_model": cpu_model()}
+    # the same oracle on one thread, over a sample with about 1/threads of the pixels
+    s1 = max(stride, int(round(stride * threads ** 0.5)))
+    px1, py1 = scenes.pixel_sample(cam.width, cam.height, stride=s1)
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.render(g, cam, px1, py1)
+        oracle.backward(g, cam, dimg, px1, py1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    out["single_thread"] = {"value": round(px1.size / dt1 / 1e6, 6), "unit": "Mpix/s", "cores": 1,
+                            "sample": f"fwd+bwd of {px1.size} pixels (every {s1}th row and column) in {dt1:.1f} s"}
+    return out
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def environment(torch):
+    """Device, software versions and the GPU clocks at the time of the run."""
+    import subprocess
+    env = {"device": torch.cuda.get_device_name(0), "hip": torch.version.hip, "torch": torch.__version__}
+    try:
+        env["rocm"] = open("/opt/rocm/.info/version").read().strip()
+    except OSError:
+        env["rocm"] = None
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=20)
+        env["clocks"] = [ln.strip() for ln in r.stdout.splitlines() if "sclk" in ln or "mclk" in ln][:4]
+    except (OSError, subprocess.SubprocessError):
+        env["clocks"] = None
+    try:
+        r = subprocess.run(["rocm-smi", "--showdriverversion"], capture_output=True, text=True, timeout=20)
+        env["driver"] = next((ln.split(":", 1)[1].strip() for ln in r.stdout.splitlines()
+                              if "version" in ln.lower() and ":" in ln), None)
+    except (OSError, subprocess.SubprocessError):
+        env["driver"] = None
+    return env
+
+
+def plain_graph(torch, frame, step, steps, npix):
+    """The same plain step captured once as a graph and replayed: time per
+    replay, and every replay's image (bit-exact) and gradients against an
+    eager step's."""
+    import numpy as np
+    step()
+    torch.cuda.synchronize()
+    ref_img = frame.image.clone()
+    ref_g = {k: v.clone() for k, v in frame.grads().items()}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for _ in range(3):
+        frame.image.zero_()
+        for v in frame.grads().values():
+            v.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        if not torch.equal(frame.image, ref_img):
+            raise RuntimeError("graph replay of the plain step: image differs from the eager step")
+        for k, v in frame.grads().items():
+            r = ref_g[k]
+            rel = float(torch.linalg.vector_norm((v - r).double()) / max(float(torch.linalg.vector_norm(r.double())), 1e-30))
+            worst = max(worst, rel)
+        step()                       # eager work between replays
+        torch.cuda.synchronize()
+    if worst > 1e-5:
+        raise RuntimeError(f"graph replay of the plain step: gradients differ from the eager step ({worst:.2e})")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    del g
+    return {"ms_per_step": round(ms, 4), "mpix_per_s": round(npix / (ms * 1e-3) / 1e6, 1),
+            "replays_checked": 3, "grad_rel_diff": float(f"{worst:.2e}")}
 
 
 def bench_loss(args, torch, N):
@@ -698,6 +793,18 @@ def main():
     npix = cam.width * cam.height
     value = npix / (ms * 1e-3) / 1e6
 
+    # distribution of whole-step times (an event pair around every step)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in evs:
+        a.record()
+        step()
+        b.record()
+    torch.cuda.synchronize()
+    st = np.array([a.elapsed_time(b) for a, b in evs])
+    step_dist = {"p10": round(float(np.percentile(st, 10)), 4), "median": round(float(np.median(st)), 4),
+                 "p90": round(float(np.percentile(st, 90)), 4)}
+    graph = plain_graph(torch, frame, step, args.steps, npix)
+
     if args.copy_calib > 0:
         # one elementwise kernel that reads MIB MiB and writes MIB MiB
         src = torch.ones(args.copy_calib * (1 << 18), dtype=torch.float32, device="cuda")
@@ -745,6 +852,9 @@ def main():
                    "gaussians": g.n, "width": cam.width, "height": cam.height, "pairs": P,
                    "blend_counts": stats, "stage_ms": stages},
         "roofline": roof,
+        "step_ms": step_dist,
+        "graph": graph,
+        "environment": environment(torch),
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)

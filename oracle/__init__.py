@@ -65,6 +65,7 @@ def lib():
         L.orc_sh_basis.argtypes = [P, P]
         L.orc_sh_basis_grad.argtypes = [P, P]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -236,3 +237,8 @@ def sh_basis_grad(d):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count of the oracle's later OpenMP regions."""
+    lib().orc_set_num_threads(int(n))
