@@ -81,6 +81,27 @@ void make_plan(int W, int H, int m, Plan* p) {
     p->f1 = take(16 * HW);
     p->M = take(3 * HW);
     pmax = std::max<int64_t>(pmax, (int64_t)wgrad_parts(H, W) * std::max(layer_params(p->L[5]), layer_params(p->L[6])));
+    // split convolutions: [splits][Cout][area] partial sums, forward and
+    // transposed (backward) shapes of every layer
+    auto split_need = [](int cin, int cout, int hh, int ww) {
+        const int sp = conv_splits(cin, cout, hh, ww);
+        return sp > 1 ? (int64_t)sp * cout * hh * ww : (int64_t)0;
+    };
+    {
+        int c = 256, hk = p->h, wk = p->w;
+        pmax = std::max(pmax, split_need(3 + m, 256, hk, wk));
+        pmax = std::max(pmax, split_need(256, 3 + m, hk, wk));
+        for (int k = 1; k <= 4; ++k) {
+            hk *= 2;
+            wk *= 2;
+            pmax = std::max(pmax, split_need(c / 4, c / 2, hk, wk));
+            pmax = std::max(pmax, split_need(c / 2, c / 4, hk, wk));
+            c /= 2;
+        }
+        pmax = std::max(pmax, split_need(16, 16, H, W));
+        pmax = std::max(pmax, split_need(3, 16, H, W));
+        pmax = std::max(pmax, split_need(16, 3, H, W));
+    }
     p->gA = take(gmax);
     p->gB = take(gmax);
     p->part = take(pmax);
@@ -139,6 +160,7 @@ ConvArgs conv_args(const float* in, const float* mask, const float* w, const flo
     a.transposed = transposed ? 1 : 0;
     a.relu = relu ? 1 : 0;
     a.CinF = cinf;
+    a.part = nullptr;
     return a;
 }
 
@@ -203,13 +225,17 @@ gs_status gs_appearance_fwd(const float* image, int32_t width, int32_t height, c
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int H = height, W = width, h = p.h, w = p.w;
     ProfScope ps("appearance_fwd", st);
+    float* part = at<float>(ws, p.part);
+    auto conv = [&](ConvArgs a) {
+        a.part = part;
+        launch_conv(a, st);
+    };
     float* D = at<float>(ws, p.D);
     launch_down_concat(image, H, W, h, w, embedding, embed_dim, D, st);
     const Layer* L = p.L;
     float* x = at<float>(ws, p.x[0]);
-    launch_conv(conv_args(D, nullptr, params + p.poff[0], params + p.poff[0] + (int64_t)L[0].cout * L[0].cin * 9, x,
-                          L[0].cin, L[0].cout, h, w, false, false, 0),
-                st);
+    conv(conv_args(D, nullptr, params + p.poff[0], params + p.poff[0] + (int64_t)L[0].cout * L[0].cin * 9, x,
+                          L[0].cin, L[0].cout, h, w, false, false, 0));
     int hk = h, wk = w, C = 256;
     for (int k = 1; k <= 4; ++k) {
         float* sk = at<float>(ws, p.s[k]);
@@ -217,9 +243,8 @@ gs_status gs_appearance_fwd(const float* image, int32_t width, int32_t height, c
         hk *= 2;
         wk *= 2;
         float* xk = at<float>(ws, p.x[k]);
-        launch_conv(conv_args(sk, nullptr, params + p.poff[k], params + p.poff[k] + (int64_t)L[k].cout * L[k].cin * 9,
-                              xk, C / 4, C / 2, hk, wk, false, true, 0),
-                    st);
+        conv(conv_args(sk, nullptr, params + p.poff[k], params + p.poff[k] + (int64_t)L[k].cout * L[k].cin * 9,
+                              xk, C / 4, C / 2, hk, wk, false, true, 0));
         x = xk;
         C /= 2;
     }
@@ -229,13 +254,11 @@ gs_status gs_appearance_fwd(const float* image, int32_t width, int32_t height, c
     float* u = at<float>(ws, p.u);
     launch_bilinear(x, 16, hk, wk, H, W, t, u, st);
     float* f1 = at<float>(ws, p.f1);
-    launch_conv(conv_args(u, nullptr, params + p.poff[5], params + p.poff[5] + (int64_t)L[5].cout * L[5].cin * 9, f1,
-                          16, 16, H, W, false, true, 0),
-                st);
+    conv(conv_args(u, nullptr, params + p.poff[5], params + p.poff[5] + (int64_t)L[5].cout * L[5].cin * 9, f1,
+                          16, 16, H, W, false, true, 0));
     float* M = at<float>(ws, p.M);
-    launch_conv(conv_args(f1, nullptr, params + p.poff[6], params + p.poff[6] + (int64_t)L[6].cout * L[6].cin * 9, M,
-                          16, 3, H, W, false, false, 0),
-                st);
+    conv(conv_args(f1, nullptr, params + p.poff[6], params + p.poff[6] + (int64_t)L[6].cout * L[6].cin * 9, M,
+                          16, 3, H, W, false, false, 0));
     const int64_t n = 3 * (int64_t)H * W;
     launch_mul(image, M, n, image_adj, st);
     if (transform && hipMemcpyAsync(transform, M, n * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
@@ -256,6 +279,14 @@ gs_status gs_appearance_bwd(const float* image, int32_t width, int32_t height, c
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int H = height, W = width, h = p.h, w = p.w;
     ProfScope ps("appearance_bwd", st);
+    // the split convolutions' partial sums share the weight-gradient
+    // partials' buffer: each weight gradient is reduced before the next
+    // convolution starts on the stream
+    float* part = at<float>(ws, p.part);
+    auto conv = [&](ConvArgs a) {
+        a.part = part;
+        launch_conv(a, st);
+    };
     const Layer* L = p.L;
     float* gA = at<float>(ws, p.gA);
     float* gB = at<float>(ws, p.gB);
@@ -266,9 +297,9 @@ gs_status gs_appearance_bwd(const float* image, int32_t width, int32_t height, c
     launch_mul_bwd(d_image_adj, image, M, n, gA, d_image, st);
     // final convolutions
     wgrad(p, ws, f1, gA, nullptr, L[6], H, W, d_params + p.poff[6], st);
-    launch_conv(conv_args(gA, nullptr, params + p.poff[6], nullptr, gB, 3, 16, H, W, true, false, 16), st);
+    conv(conv_args(gA, nullptr, params + p.poff[6], nullptr, gB, 3, 16, H, W, true, false, 16));
     wgrad(p, ws, u, gB, f1, L[5], H, W, d_params + p.poff[5], st);
-    launch_conv(conv_args(gB, f1, params + p.poff[5], nullptr, gA, 16, 16, H, W, true, false, 16), st);
+    conv(conv_args(gB, f1, params + p.poff[5], nullptr, gA, 16, 16, H, W, true, false, 16));
     // interpolation
     const int h4 = h * 16, w4 = w * 16;
     launch_bilinear_adj(gA, 16, H, W, h4, w4, tables(p, ws), at<float>(ws, p.tmp), gB, st);
@@ -278,7 +309,7 @@ gs_status gs_appearance_bwd(const float* image, int32_t width, int32_t height, c
         const float* sk = at<float>(ws, p.s[k]);
         const float* xk = at<float>(ws, p.x[k]);
         wgrad(p, ws, sk, gB, xk, L[k], hk, wk, d_params + p.poff[k], st);
-        launch_conv(conv_args(gB, xk, params + p.poff[k], nullptr, gA, C, C / 2, hk, wk, true, false, C / 2), st);
+        conv(conv_args(gB, xk, params + p.poff[k], nullptr, gA, C, C / 2, hk, wk, true, false, C / 2));
         launch_shuffle(gA, C / 2, hk / 2, wk / 2, gB, true, st);
         hk /= 2;
         wk /= 2;
@@ -287,9 +318,8 @@ gs_status gs_appearance_bwd(const float* image, int32_t width, int32_t height, c
     // first convolution
     const float* D = at<float>(ws, p.D);
     wgrad(p, ws, D, gB, nullptr, L[0], h, w, d_params + p.poff[0], st);
-    launch_conv(conv_args(gB, nullptr, params + p.poff[0], nullptr, gA, 256, 3 + embed_dim, h, w, true, false,
-                          3 + embed_dim),
-                st);
+    conv(conv_args(gB, nullptr, params + p.poff[0], nullptr, gA, 256, 3 + embed_dim, h, w, true, false,
+                          3 + embed_dim));
     if (embed_dim > 0) launch_embed_grad(gA, (int64_t)h * w, embed_dim, d_embedding, st);
     launch_down_adjoint(gA, H, W, h, w, d_image, st);
     return check_hip("gs_appearance_bwd");

@@ -20,6 +20,8 @@
 // a second kernel, so every result is deterministic.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace gs {
@@ -165,25 +167,30 @@ typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 // [o][ci][tap] weights are staged in LDS; each k-step gives every lane one
 // weight (A: row o = lane % 16, k = lane / 16) and, per row, one input
 // sample (B: k = lane / 16, pixel = lane % 16).
-__global__ __launch_bounds__(kT) void k_conv_mfma(ConvArgs a) {
+__global__ __launch_bounds__(kT) void k_conv_mfma(ConvArgs a, int splits, int cps) {
     constexpr int KC = kCI * 9;   // k values per chunk (72)
     __shared__ float s_in[kCI * kHalo * kHalo];
     __shared__ float s_w[16 * KC];
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
-    const int og = blockIdx.z * 16;
+    // blockIdx.z = split * (output-channel groups) + group; split s sums
+    // input channels [s cps kCI, (s + 1) cps kCI)
+    const int n_og = (a.Cout + 15) / 16;
+    const int split = (int)blockIdx.z / n_og;
+    const int og = ((int)blockIdx.z - split * n_og) * 16;
+    const int cbeg = split * cps * kCI, cend = min(a.Cin, cbeg + cps * kCI);
     const int64_t HW = (int64_t)a.H * a.W;
     const int li = lane % 16, lk = lane / 16;
     mfma_f4 acc[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) acc[g] = mfma_f4{0.f, 0.f, 0.f, 0.f};
-    for (int c0 = 0; c0 < a.Cin; c0 += kCI) {
+    for (int c0 = cbeg; c0 < cend; c0 += kCI) {
         __syncthreads();
         for (int k = threadIdx.x; k < kCI * kHalo * kHalo; k += kT) {
             const int c = k / (kHalo * kHalo), r = (k / kHalo) % kHalo, q = k % kHalo;
             const int gy = y0 - 1 + r, gx = x0 - 1 + q;
             float v = 0.f;
-            if (c0 + c < a.Cin && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
+            if (c0 + c < cend && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
                 const int64_t idx = (int64_t)(c0 + c) * HW + (int64_t)gy * a.W + gx;
                 v = a.in[idx];
                 if (a.mask && !(a.mask[idx] > 0.f)) v = 0.f;
@@ -194,12 +201,12 @@ __global__ __launch_bounds__(kT) void k_conv_mfma(ConvArgs a) {
             const int o = k / KC, kk = k % KC, c = kk / 9, t = kk % 9;
             const int ci = c0 + c, oo = og + o;
             float v = 0.f;
-            if (ci < a.Cin && oo < a.Cout)
+            if (ci < cend && oo < a.Cout)
                 v = a.transposed ? a.w[((int64_t)ci * a.CinF + oo) * 9 + (8 - t)] : a.w[((int64_t)oo * a.Cin + ci) * 9 + t];
             s_w[k] = v;
         }
         __syncthreads();
-        const int steps = (min(kCI, a.Cin - c0) * 9 + 3) / 4;
+        const int steps = (min(kCI, cend - c0) * 9 + 3) / 4;
         for (int s = 0; s < steps; ++s) {
             const int k = 4 * s + lk;                  // this lane's k (< KC)
             const int c = k / 9, t = k - 9 * (k / 9);
@@ -222,22 +229,48 @@ __global__ __launch_bounds__(kT) void k_conv_mfma(ConvArgs a) {
             for (int r = 0; r < 4; ++r) {
                 const int o = og + 4 * lk + r;
                 if (o < a.Cout) {
-                    float v = acc[g][r] + (a.b ? a.b[o] : 0.f);
-                    a.out[(int64_t)o * HW + (int64_t)py * a.W + px] = a.relu ? fmaxf(v, 0.f) : v;
+                    const int64_t pix = (int64_t)py * a.W + px;
+                    if (splits > 1) {
+                        a.part[((int64_t)split * a.Cout + o) * HW + pix] = acc[g][r];
+                    } else {
+                        float v = acc[g][r] + (a.b ? a.b[o] : 0.f);
+                        a.out[(int64_t)o * HW + pix] = a.relu ? fmaxf(v, 0.f) : v;
+                    }
                 }
             }
         }
     }
 }
 
+// out[o][p] = (bias[o] + sum over the splits, in order, of part[s][o][p]),
+// ReLU if asked: the end of a split convolution
+__global__ __launch_bounds__(kT) void k_conv_reduce(const float* __restrict__ part, int splits, int Cout, int64_t HW,
+                                                    const float* __restrict__ b, int relu, float* __restrict__ out) {
+    const int o = blockIdx.y;
+    const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (p >= HW) return;
+    float s = 0.f;
+    for (int k = 0; k < splits; ++k) s += part[((int64_t)k * Cout + o) * HW + p];
+    if (b) s += b[o];
+    out[(int64_t)o * HW + p] = relu ? fmaxf(s, 0.f) : s;
+}
+
 // Per-workgroup partial sums of dW[o][i][tap] and db[o] over its pixel
-// tiles (8 x 32, grid-stride); thread (o, i) of a 16 x 16 channel block.
+// tiles (8 x 32, grid-stride).  OG = 16: thread (o, i) of a 16 x 16
+// channel block.  OG = 4 (layers with at most four output channels):
+// thread (column quarter, o, i) of a 4 x 16 block, each quarter of the
+// tile's columns summed by its own threads and the four added in order at
+// the end.
+template <int OG>
 __global__ __launch_bounds__(kT) void k_wgrad(WgradArgs a) {
-    __shared__ float s_g[16 * kWR * kWC];
+    constexpr int CS = 16 / OG;          // column splits of the pixel tile
+    constexpr int QW = kWC / CS;         // columns per split
+    __shared__ float s_g[OG * kWR * kWC];
     __shared__ float s_in[16 * (kWR + 2) * (kWC + 2)];
-    const int ol = threadIdx.x / 16, il = threadIdx.x % 16;
+    const int cs = threadIdx.x / (OG * 16);
+    const int ol = (threadIdx.x / 16) % OG, il = threadIdx.x % 16;
     const int n_ig = (a.Cin + 15) / 16;
-    const int o0 = (blockIdx.y / n_ig) * 16, i0 = (blockIdx.y % n_ig) * 16;
+    const int o0 = (blockIdx.y / n_ig) * OG, i0 = (blockIdx.y % n_ig) * 16;
     const int64_t HW = (int64_t)a.H * a.W;
     const int tiles_x = (a.W + kWC - 1) / kWC, tiles_y = (a.H + kWR - 1) / kWR;
     const int n_tiles = tiles_x * tiles_y;
@@ -248,7 +281,7 @@ __global__ __launch_bounds__(kT) void k_wgrad(WgradArgs a) {
     for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int y0 = (tile / tiles_x) * kWR, x0 = (tile % tiles_x) * kWC;
         __syncthreads();
-        for (int k = threadIdx.x; k < 16 * kWR * kWC; k += kT) {
+        for (int k = threadIdx.x; k < OG * kWR * kWC; k += kT) {
             const int o = k / (kWR * kWC), r = (k / kWC) % kWR, q = k % kWC;
             const int gy = y0 + r, gx = x0 + q;
             float v = 0.f;
@@ -270,14 +303,15 @@ __global__ __launch_bounds__(kT) void k_wgrad(WgradArgs a) {
         __syncthreads();
         const float* gi = s_g + ol * kWR * kWC;
         const float* xi = s_in + il * (kWR + 2) * (kWC + 2);
+        const int q0 = cs * QW;
         for (int r = 0; r < kWR; ++r) {
             float w0[3], w1[3];
 #pragma unroll
             for (int t = 0; t < 3; ++t) {
-                w0[t] = xi[(r + t) * (kWC + 2) + 0];
-                w1[t] = xi[(r + t) * (kWC + 2) + 1];
+                w0[t] = xi[(r + t) * (kWC + 2) + q0];
+                w1[t] = xi[(r + t) * (kWC + 2) + q0 + 1];
             }
-            for (int q = 0; q < kWC; ++q) {
+            for (int q = q0; q < q0 + QW; ++q) {
                 float w2[3];
 #pragma unroll
                 for (int t = 0; t < 3; ++t) w2[t] = xi[(r + t) * (kWC + 2) + q + 2];
@@ -292,6 +326,24 @@ __global__ __launch_bounds__(kT) void k_wgrad(WgradArgs a) {
                     w1[t] = w2[t];
                 }
             }
+        }
+    }
+    if (CS > 1) {
+        // add the column splits in order (thread (0, o, i) keeps the sum)
+        float* red = s_in;
+        __syncthreads();
+        const int slot = (threadIdx.x % (OG * 16)) * 10;
+        if (cs > 0) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) red[((cs - 1) * OG * 16) * 10 + slot + t] = acc[t];
+            red[((cs - 1) * OG * 16) * 10 + slot + 9] = bacc;
+        }
+        __syncthreads();
+        if (cs > 0) return;
+        for (int k = 0; k < CS - 1; ++k) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) acc[t] += red[(k * OG * 16) * 10 + slot + t];
+            bacc += red[(k * OG * 16) * 10 + slot + 9];
         }
     }
     const int o = o0 + ol, i = i0 + il;
@@ -351,22 +403,45 @@ __global__ void k_bilin_table(int n_in, int n_out, int* __restrict__ i0, int* __
     f[d] = (float)(s - (double)a);
 }
 
+constexpr int kRows = 8;   // rows per workgroup of the interpolation kernels
+
+// kRows output rows (channel c, row Y) per workgroup, one column per
+// thread: the column's taps are read once, the rows' loads are independent
 __global__ __launch_bounds__(kT) void k_bilinear(const float* __restrict__ in, int C, int h, int w, int H, int W,
                                                  const int* __restrict__ y0, const int* __restrict__ y1,
                                                  const float* __restrict__ fy, const int* __restrict__ x0,
                                                  const int* __restrict__ x1, const float* __restrict__ fx,
                                                  float* __restrict__ out) {
-    const int64_t HW = (int64_t)H * W;
-    const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (q >= C * HW) return;
-    const int c = (int)(q / HW);
-    const int64_t p = q - c * HW;
-    const int Y = (int)(p / W), X = (int)(p - (int64_t)Y * W);
-    const float* b = in + (int64_t)c * h * w;
-    const float a = fy[Y], e = fx[X];
-    const float top = (1.f - e) * b[(int64_t)y0[Y] * w + x0[X]] + e * b[(int64_t)y0[Y] * w + x1[X]];
-    const float bot = (1.f - e) * b[(int64_t)y1[Y] * w + x0[X]] + e * b[(int64_t)y1[Y] * w + x1[X]];
-    out[q] = (1.f - a) * top + a * bot;
+    const int X = (int)blockIdx.x * kT + (int)threadIdx.x;
+    if (X >= W) return;
+    const int ex0 = x0[X], ex1 = x1[X];
+    const float e = fx[X];
+    const int rows = C * H;
+    for (int r0 = (int)blockIdx.y * kRows; r0 < rows; r0 += (int)gridDim.y * kRows) {
+        // all loads of the kRows rows first (rows past the end repeat the
+        // last one and are not stored), then the blends
+        float v[kRows][4], a[kRows];
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+            const int row = min(r0 + k, rows - 1);
+            const int c = row / H, Y = row - c * H;
+            const float* b = in + (int64_t)c * h * w;
+            const float* p0 = b + (int64_t)y0[Y] * w;
+            const float* p1 = b + (int64_t)y1[Y] * w;
+            a[k] = fy[Y];
+            v[k][0] = p0[ex0];
+            v[k][1] = p0[ex1];
+            v[k][2] = p1[ex0];
+            v[k][3] = p1[ex1];
+        }
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+            if (r0 + k >= rows) break;
+            const float top = (1.f - e) * v[k][0] + e * v[k][1];
+            const float bot = (1.f - e) * v[k][2] + e * v[k][3];
+            out[(int64_t)(r0 + k) * W + X] = (1.f - a[k]) * top + a[k] * bot;
+        }
+    }
 }
 
 // Outputs d reading input i along one axis are those with i0[d] <= i <=
@@ -395,36 +470,111 @@ __global__ void k_bilin_ranges(int n_in, int n_out, const int* __restrict__ i0, 
     hi[i] = b;
 }
 
-// adjoint of k_bilinear along one axis: out[c][r][i] = sum over the
-// outputs d that read input i of their weight times g[c][r][d], for rows r
-// (the x pass: stride 1 within a row) or columns (the y pass: stride = row
-// length); the two passes together give the 2D adjoint
-__global__ __launch_bounds__(kT) void k_bilinear_adj_axis(const float* __restrict__ g, int64_t lines, int n_out,
-                                                          int n_in, int64_t line_stride_g, int64_t line_stride_o,
-                                                          int64_t elem_stride, const int* __restrict__ i0,
-                                                          const int* __restrict__ i1, const float* __restrict__ f,
-                                                          const int* __restrict__ rlo, const int* __restrict__ rhi,
-                                                          float* __restrict__ out) {
-    const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (q >= lines * n_in) return;
-    // consecutive threads take consecutive lines (coalesced for the y pass)
-    // or consecutive inputs of a line (the x pass): elem_stride decides
-    int64_t line, i;
-    if (elem_stride == 1) {
-        line = q / n_in;
-        i = q - line * n_in;
-    } else {
-        i = q / lines;
-        line = q - i * lines;
-    }
+// Adjoint of k_bilinear along x: tmp[c][Y][i] = sum over the outputs X
+// that read input column i of their weight times g[c][Y][X] (one row per
+// grid row, one input column per thread)
+__device__ __forceinline__ float adj_weight(int d, int i, const int* i0, const int* i1, const float* f) {
+    return (i0[d] == i ? 1.f - f[d] : 0.f) + (i1[d] == i ? f[d] : 0.f);
+}
+
+__global__ __launch_bounds__(kT) void k_bilin_adj_x(const float* __restrict__ g, int rows, int W, int w,
+                                                    const int* __restrict__ i0, const int* __restrict__ i1,
+                                                    const float* __restrict__ f, const int* __restrict__ rlo,
+                                                    const int* __restrict__ rhi, float* __restrict__ out) {
+    const int i = (int)blockIdx.x * kT + (int)threadIdx.x;
+    if (i >= w) return;
     const int lo = rlo[i], hi = rhi[i];
-    const float* gl = g + line * line_stride_g;
-    float s = 0.f;
-    for (int d = lo; d < hi; ++d) {
-        const float wgt = (i0[d] == i ? 1.f - f[d] : 0.f) + (i1[d] == i ? f[d] : 0.f);
-        s = fmaf(wgt, gl[(int64_t)d * elem_stride], s);
+    // upsampling by at most 2 (the only use): at most four outputs read an
+    // input; their taps are loaded once, padded with weight-0 taps (which
+    // leave the sum unchanged); longer ranges take the plain loop
+    constexpr int K = 4;
+    const bool fits = hi - lo <= K;
+    int dk[K];
+    float wk[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const bool on = lo + k < hi;
+        dk[k] = on ? lo + k : 0;
+        wk[k] = on ? adj_weight(lo + k, i, i0, i1, f) : 0.f;
     }
-    out[line * line_stride_o + i * elem_stride] = s;
+    for (int r0 = (int)blockIdx.y * kRows; r0 < rows; r0 += (int)gridDim.y * kRows) {
+        if (fits) {
+            float v[kRows][K];
+#pragma unroll
+            for (int k = 0; k < kRows; ++k) {
+                const float* gl = g + (int64_t)min(r0 + k, rows - 1) * W;
+#pragma unroll
+                for (int t = 0; t < K; ++t) v[k][t] = gl[dk[t]];
+            }
+#pragma unroll
+            for (int k = 0; k < kRows; ++k) {
+                if (r0 + k >= rows) break;
+                float s = 0.f;
+#pragma unroll
+                for (int t = 0; t < K; ++t) s = fmaf(wk[t], v[k][t], s);
+                out[(int64_t)(r0 + k) * w + i] = s;
+            }
+        } else {
+            for (int k = 0; k < kRows && r0 + k < rows; ++k) {
+                const float* gl = g + (int64_t)(r0 + k) * W;
+                float s = 0.f;
+                for (int d = lo; d < hi; ++d) s = fmaf(adj_weight(d, i, i0, i1, f), gl[d], s);
+                out[(int64_t)(r0 + k) * w + i] = s;
+            }
+        }
+    }
+}
+
+// ... and along y: out[c][i][x] = sum over the output rows Y that read
+// input row i of their weight times tmp[c][Y][x] (one (c, i) per grid row,
+// one column per thread)
+__global__ __launch_bounds__(kT) void k_bilin_adj_y(const float* __restrict__ tmp, int C, int H, int h, int w,
+                                                    const int* __restrict__ i0, const int* __restrict__ i1,
+                                                    const float* __restrict__ f, const int* __restrict__ rlo,
+                                                    const int* __restrict__ rhi, float* __restrict__ out) {
+    const int x = (int)blockIdx.x * kT + (int)threadIdx.x;
+    if (x >= w) return;
+    const int rows = C * h;
+    constexpr int K = 4;   // as in the x pass: at most four taps when upsampling by at most 2
+    for (int r0 = (int)blockIdx.y * kRows; r0 < rows; r0 += (int)gridDim.y * kRows) {
+        float v[kRows][K], wt[kRows][K];
+        bool fits = true;
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+            const int row = min(r0 + k, rows - 1);
+            const int c = row / h, i = row - c * h;
+            const int lo = rlo[i], hi = rhi[i];
+            fits = fits && hi - lo <= K;
+            const float* tc = tmp + (int64_t)c * H * w + x;
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+                const bool on = lo + t < hi;
+                const int d = on ? lo + t : 0;
+                wt[k][t] = on ? adj_weight(d, i, i0, i1, f) : 0.f;
+                v[k][t] = tc[(int64_t)d * w];
+            }
+        }
+        if (fits) {
+#pragma unroll
+            for (int k = 0; k < kRows; ++k) {
+                if (r0 + k >= rows) break;
+                float s = 0.f;
+#pragma unroll
+                for (int t = 0; t < K; ++t) s = fmaf(wt[k][t], v[k][t], s);
+                out[(int64_t)(r0 + k) * w + x] = s;
+            }
+        } else {
+            for (int k = 0; k < kRows && r0 + k < rows; ++k) {
+                const int row = r0 + k;
+                const int c = row / h, i = row - c * h;
+                const int lo = rlo[i], hi = rhi[i];
+                const float* tc = tmp + (int64_t)c * H * w + x;
+                float s = 0.f;
+                for (int d = lo; d < hi; ++d) s = fmaf(adj_weight(d, i, i0, i1, f), tc[(int64_t)d * w], s);
+                out[(int64_t)row * w + x] = s;
+            }
+        }
+    }
 }
 
 __global__ __launch_bounds__(kT) void k_mul(const float* __restrict__ a, const float* __restrict__ b, int64_t n,
@@ -473,11 +623,32 @@ void launch_down_adjoint(const float* g, int H, int W, int h, int w, float* d_im
     hipLaunchKernelGGL(k_down_adjoint, dim3(blocks_for(3 * (int64_t)H * W)), dim3(kT), 0, st, g, H, W, h, w, d_img);
 }
 
+int conv_splits(int Cin, int Cout, int H, int W) {
+    if (Cout <= 4) return 1;   // the VALU kernel
+    // the low-resolution layers give too few workgroups to fill 256 CUs:
+    // split their input channels until the grid has about 2048
+    const int64_t wgs = (int64_t)((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * ((Cout + 15) / 16);
+    const int chunks = (Cin + kCI - 1) / kCI;
+    if (wgs >= 1024 || chunks < 2) return 1;
+    const int want = (int)std::min<int64_t>(chunks, (2048 + wgs - 1) / wgs);
+    const int cps = (chunks + want - 1) / want;
+    return (chunks + cps - 1) / cps;
+}
+
 void launch_conv(const ConvArgs& a, hipStream_t st) {
     if (a.Cout > 4) {
         // a dense contraction over 9 Cin: the matrix cores
-        const dim3 grid((a.W + kTile - 1) / kTile, (a.H + kTile - 1) / kTile, (a.Cout + 15) / 16);
-        hipLaunchKernelGGL(k_conv_mfma, grid, dim3(kT), 0, st, a);
+        const int splits = a.part ? conv_splits(a.Cin, a.Cout, a.H, a.W) : 1;
+        const int chunks = (a.Cin + kCI - 1) / kCI;
+        const int cps = (chunks + splits - 1) / splits;
+        const int n_og = (a.Cout + 15) / 16;
+        const dim3 grid((a.W + kTile - 1) / kTile, (a.H + kTile - 1) / kTile, n_og * splits);
+        hipLaunchKernelGGL(k_conv_mfma, grid, dim3(kT), 0, st, a, splits, cps);
+        if (splits > 1) {
+            const int64_t HW = (int64_t)a.H * a.W;
+            hipLaunchKernelGGL(k_conv_reduce, dim3(blocks_for(HW), a.Cout), dim3(kT), 0, st, a.part, splits, a.Cout,
+                               HW, a.b, a.relu, a.out);
+        }
         return;
     }
     // three or four output channels (the map M): most of a 16-row matrix
@@ -496,8 +667,12 @@ int wgrad_parts(int H, int W) {
 
 void launch_wgrad(const WgradArgs& a, float* dw, hipStream_t st) {
     const int parts = wgrad_parts(a.H, a.W);
-    const int groups = ((a.Cout + 15) / 16) * ((a.Cin + 15) / 16);
-    hipLaunchKernelGGL(k_wgrad, dim3(parts, groups), dim3(kT), 0, st, a);
+    if (a.Cout <= 4) {
+        hipLaunchKernelGGL(k_wgrad<4>, dim3(parts, (a.Cin + 15) / 16), dim3(kT), 0, st, a);
+    } else {
+        const int groups = ((a.Cout + 15) / 16) * ((a.Cin + 15) / 16);
+        hipLaunchKernelGGL(k_wgrad<16>, dim3(parts, groups), dim3(kT), 0, st, a);
+    }
     hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((a.J + 63) / 64)), dim3(1024), 0, st, a.partial, parts, a.J, dw);
 }
 
@@ -510,10 +685,13 @@ void launch_bilin_table(int n_in, int n_out, int* i0, int* i1, float* f, hipStre
     hipLaunchKernelGGL(k_bilin_table, dim3(blocks_for(n_out)), dim3(kT), 0, st, n_in, n_out, i0, i1, f);
 }
 
+// workgroup rows for kRows rows each (the kernels stride over the rest)
+unsigned grid_rows(int64_t rows) { return (unsigned)std::min<int64_t>((rows + kRows - 1) / kRows, 65535); }
+
 void launch_bilinear(const float* in, int C, int h, int w, int H, int W, const BilinTab& t, float* out,
                      hipStream_t st) {
-    hipLaunchKernelGGL(k_bilinear, dim3(blocks_for((int64_t)C * H * W)), dim3(kT), 0, st, in, C, h, w, H, W, t.y0,
-                       t.y1, t.fy, t.x0, t.x1, t.fx, out);
+    hipLaunchKernelGGL(k_bilinear, dim3(blocks_for(W), grid_rows((int64_t)C * H)), dim3(kT), 0, st, in, C, h, w, H,
+                       W, t.y0, t.y1, t.fy, t.x0, t.x1, t.fx, out);
 }
 
 void launch_bilinear_adj(const float* g, int C, int H, int W, int h, int w, const BilinTab& t, float* tmp,
@@ -522,13 +700,11 @@ void launch_bilinear_adj(const float* g, int C, int H, int W, int h, int w, cons
     const int64_t rows = (int64_t)C * H;
     hipLaunchKernelGGL(k_bilin_ranges, dim3(blocks_for(w)), dim3(kT), 0, st, w, W, t.x0, t.x1, t.xlo, t.xhi);
     hipLaunchKernelGGL(k_bilin_ranges, dim3(blocks_for(h)), dim3(kT), 0, st, h, H, t.y0, t.y1, t.ylo, t.yhi);
-    hipLaunchKernelGGL(k_bilinear_adj_axis, dim3(blocks_for(rows * w)), dim3(kT), 0, st, g, rows, W, w, (int64_t)W,
-                       (int64_t)w, (int64_t)1, t.x0, t.x1, t.fx, t.xlo, t.xhi, tmp);
-    // y pass: tmp [C][H][w] -> out [C][h][w]; per channel, lines = w columns
-    for (int c = 0; c < C; ++c)
-        hipLaunchKernelGGL(k_bilinear_adj_axis, dim3(blocks_for((int64_t)w * h)), dim3(kT), 0, st,
-                           tmp + (int64_t)c * H * w, (int64_t)w, H, h, (int64_t)1, (int64_t)1, (int64_t)w, t.y0, t.y1,
-                           t.fy, t.ylo, t.yhi, out + (int64_t)c * h * w);
+    hipLaunchKernelGGL(k_bilin_adj_x, dim3(blocks_for(w), grid_rows(rows)), dim3(kT), 0, st, g, (int)rows, W, w,
+                       t.x0, t.x1, t.fx, t.xlo, t.xhi, tmp);
+    // y pass: tmp [C][H][w] -> out [C][h][w]
+    hipLaunchKernelGGL(k_bilin_adj_y, dim3(blocks_for(w), grid_rows((int64_t)C * h)), dim3(kT), 0, st, tmp, C, H, h,
+                       w, t.y0, t.y1, t.fy, t.ylo, t.yhi, out);
 }
 
 void launch_mul(const float* a, const float* b, int64_t n, float* out, hipStream_t st) {

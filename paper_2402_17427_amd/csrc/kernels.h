@@ -198,8 +198,14 @@ struct ConvArgs {
     float* out;
     int Cin, Cout, H, W;
     int transposed, relu, CinF;
+    // split of the input-channel reduction over conv_splits() workgroup
+    // groups: raw partial sums [splits][Cout][H][W] (no bias, no ReLU),
+    // added in a fixed order by a second kernel; NULL = never split
+    float* part;
 };
 void launch_conv(const ConvArgs& a, hipStream_t st);
+// input-channel splits launch_conv uses for this shape (1 = none)
+int conv_splits(int Cin, int Cout, int H, int W);
 // Weight and bias gradients of a forward convolution with input `in`
 // [Cin][H][W] and output gradient g [Cout][H][W] (masked like ConvArgs):
 // dw = [Cout][Cin][9] then [Cout] (J = Cout Cin 9 + Cout floats); partial
