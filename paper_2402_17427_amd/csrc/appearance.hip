@@ -34,6 +34,33 @@ constexpr int kTile = 16;          // output tile width of the convolution
 constexpr int kHalo = kTile + 2;   // staged tile width
 constexpr int kWR = 8, kWC = 32;   // pixel tile of the weight gradient
 
+// Stages N floats into LDS: element k (k = tid, tid + kT, ...) is
+// src[q] with (ok, q) = at(k), zero when !ok, and zero where MASK and
+// mask[q] <= 0 (the ReLU mask of a backward pass).  Every load of the
+// thread is issued before the first LDS write (an out-of-range element
+// loads src[0] and is replaced by zero), so the loads overlap instead of
+// each waiting for the previous one.
+template <int N, bool MASK, typename At>
+__device__ __forceinline__ void stage(float* dst, const float* __restrict__ src, const float* __restrict__ mask, At at) {
+    constexpr int J = (N + kT - 1) / kT;
+    float v[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int k = (int)threadIdx.x + j * kT;
+        int64_t q = 0;
+        const bool ok = k < N && at(k, &q);
+        const int64_t qq = ok ? q : 0;
+        float x = src[qq];
+        if (MASK) x = mask[qq] > 0.f ? x : 0.f;
+        v[j] = ok ? x : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int k = (int)threadIdx.x + j * kT;
+        if (k < N) dst[k] = v[j];
+    }
+}
+
 __global__ __launch_bounds__(kT) void k_down_concat(const float* __restrict__ img, int H, int W, int h, int w,
                                                     const float* __restrict__ embed, int m, float* __restrict__ D) {
     __shared__ float red[kT / kWave][2];
@@ -73,7 +100,7 @@ __global__ __launch_bounds__(kT) void k_down_adjoint(const float* __restrict__ g
     d_img[q] += g[(int64_t)c * h * w + (int64_t)by * w + bx] / (float)(ny * nx);
 }
 
-template <int CO, int R>
+template <int CO, int R, bool MASK>
 __global__ __launch_bounds__(kT) void k_conv(ConvArgs a) {
     // input tile (16 wide, 16 R tall, one-pixel halo) and the chunk's
     // weights as [ci][tap][co], read by every lane at the same address
@@ -96,28 +123,20 @@ __global__ __launch_bounds__(kT) void k_conv(ConvArgs a) {
     float* s_wf = reinterpret_cast<float*>(s_w);
     for (int c0 = 0; c0 < a.Cin; c0 += kCI) {
         __syncthreads();
-        for (int k = threadIdx.x; k < kCI * IR * kHalo; k += kT) {
-            const int c = k / (IR * kHalo), r = (k / kHalo) % IR, q = k % kHalo;
-            const int gy = y0 - 1 + r, gx = x0 - 1 + q;
-            float v = 0.f;
-            if (c0 + c < a.Cin && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
-                const int64_t idx = (int64_t)(c0 + c) * HW + (int64_t)gy * a.W + gx;
-                v = a.in[idx];
-                if (a.mask && !(a.mask[idx] > 0.f)) v = 0.f;
-            }
-            s_in[k] = v;
-        }
-        for (int k = threadIdx.x; k < kCI * 9 * CO; k += kT) {
+        stage<kCI * IR * kHalo, MASK>(s_in, a.in, a.mask, [&](int k, int64_t* q) {
+            const int c = k / (IR * kHalo), r = (k / kHalo) % IR, x = k % kHalo;
+            const int gy = y0 - 1 + r, gx = x0 - 1 + x;
+            *q = (int64_t)(c0 + c) * HW + (int64_t)gy * a.W + gx;
+            return c0 + c < a.Cin && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W;
+        });
+        stage<kCI * 9 * CO, false>(s_wf, a.w, nullptr, [&](int k, int64_t* q) {
             const int c = k / (9 * CO), t = (k / CO) % 9, co = k % CO;
             const int ci = c0 + c, o = og + co;
-            float v = 0.f;
-            if (ci < a.Cin && o < a.Cout) {
-                // forward: w[o][ci][t]; transposed: w[ci][o][8 - t] of the
-                // forward layer (its output channel ci, input channel o)
-                v = a.transposed ? a.w[((int64_t)ci * a.CinF + o) * 9 + (8 - t)] : a.w[((int64_t)o * a.Cin + ci) * 9 + t];
-            }
-            s_wf[k] = v;
-        }
+            // forward: w[o][ci][t]; transposed: w[ci][o][8 - t] of the
+            // forward layer (its output channel ci, input channel o)
+            *q = a.transposed ? ((int64_t)ci * a.CinF + o) * 9 + (8 - t) : ((int64_t)o * a.Cin + ci) * 9 + t;
+            return ci < a.Cin && o < a.Cout;
+        });
         __syncthreads();
         const int cn = min(kCI, a.Cin - c0);
         for (int c = 0; c < cn; ++c) {
@@ -167,6 +186,7 @@ typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 // [o][ci][tap] weights are staged in LDS; each k-step gives every lane one
 // weight (A: row o = lane % 16, k = lane / 16) and, per row, one input
 // sample (B: k = lane / 16, pixel = lane % 16).
+template <bool MASK>
 __global__ __launch_bounds__(kT) void k_conv_mfma(ConvArgs a, int splits, int cps) {
     constexpr int KC = kCI * 9;   // k values per chunk (72)
     __shared__ float s_in[kCI * kHalo * kHalo];
@@ -186,25 +206,18 @@ __global__ __launch_bounds__(kT) void k_conv_mfma(ConvArgs a, int splits, int cp
     for (int g = 0; g < 4; ++g) acc[g] = mfma_f4{0.f, 0.f, 0.f, 0.f};
     for (int c0 = cbeg; c0 < cend; c0 += kCI) {
         __syncthreads();
-        for (int k = threadIdx.x; k < kCI * kHalo * kHalo; k += kT) {
-            const int c = k / (kHalo * kHalo), r = (k / kHalo) % kHalo, q = k % kHalo;
-            const int gy = y0 - 1 + r, gx = x0 - 1 + q;
-            float v = 0.f;
-            if (c0 + c < cend && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
-                const int64_t idx = (int64_t)(c0 + c) * HW + (int64_t)gy * a.W + gx;
-                v = a.in[idx];
-                if (a.mask && !(a.mask[idx] > 0.f)) v = 0.f;
-            }
-            s_in[k] = v;
-        }
-        for (int k = threadIdx.x; k < 16 * KC; k += kT) {
+        stage<kCI * kHalo * kHalo, MASK>(s_in, a.in, a.mask, [&](int k, int64_t* q) {
+            const int c = k / (kHalo * kHalo), r = (k / kHalo) % kHalo, x = k % kHalo;
+            const int gy = y0 - 1 + r, gx = x0 - 1 + x;
+            *q = (int64_t)(c0 + c) * HW + (int64_t)gy * a.W + gx;
+            return c0 + c < cend && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W;
+        });
+        stage<16 * KC, false>(s_w, a.w, nullptr, [&](int k, int64_t* q) {
             const int o = k / KC, kk = k % KC, c = kk / 9, t = kk % 9;
             const int ci = c0 + c, oo = og + o;
-            float v = 0.f;
-            if (ci < cend && oo < a.Cout)
-                v = a.transposed ? a.w[((int64_t)ci * a.CinF + oo) * 9 + (8 - t)] : a.w[((int64_t)oo * a.Cin + ci) * 9 + t];
-            s_w[k] = v;
-        }
+            *q = a.transposed ? ((int64_t)ci * a.CinF + oo) * 9 + (8 - t) : ((int64_t)oo * a.Cin + ci) * 9 + t;
+            return ci < cend && oo < a.Cout;
+        });
         __syncthreads();
         const int steps = (min(kCI, cend - c0) * 9 + 3) / 4;
         for (int s = 0; s < steps; ++s) {
@@ -219,6 +232,13 @@ __global__ __launch_bounds__(kT) void k_conv_mfma(ConvArgs a, int splits, int cp
         }
     }
     // D[o = 4 (lane / 16) + r][pixel = lane % 16] of row 4 wave + g
+    float bias[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int o = og + 4 * lk + r;
+        const float bv = a.b ? a.b[o < a.Cout ? o : 0] : 0.f;
+        bias[r] = (splits == 1 && o < a.Cout) ? bv : 0.f;
+    }
     const int px = x0 + li;
     if (px < a.W) {
 #pragma unroll
@@ -233,7 +253,7 @@ __global__ __launch_bounds__(kT) void k_conv_mfma(ConvArgs a, int splits, int cp
                     if (splits > 1) {
                         a.part[((int64_t)split * a.Cout + o) * HW + pix] = acc[g][r];
                     } else {
-                        float v = acc[g][r] + (a.b ? a.b[o] : 0.f);
+                        const float v = acc[g][r] + bias[r];
                         a.out[(int64_t)o * HW + pix] = a.relu ? fmaxf(v, 0.f) : v;
                     }
                 }
@@ -261,7 +281,7 @@ __global__ __launch_bounds__(kT) void k_conv_reduce(const float* __restrict__ pa
 // thread (column quarter, o, i) of a 4 x 16 block, each quarter of the
 // tile's columns summed by its own threads and the four added in order at
 // the end.
-template <int OG>
+template <int OG, bool MASK>
 __global__ __launch_bounds__(kT) void k_wgrad(WgradArgs a) {
     constexpr int CS = 16 / OG;          // column splits of the pixel tile
     constexpr int QW = kWC / CS;         // columns per split
@@ -281,25 +301,18 @@ __global__ __launch_bounds__(kT) void k_wgrad(WgradArgs a) {
     for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int y0 = (tile / tiles_x) * kWR, x0 = (tile % tiles_x) * kWC;
         __syncthreads();
-        for (int k = threadIdx.x; k < OG * kWR * kWC; k += kT) {
-            const int o = k / (kWR * kWC), r = (k / kWC) % kWR, q = k % kWC;
-            const int gy = y0 + r, gx = x0 + q;
-            float v = 0.f;
-            if (o0 + o < a.Cout && gy < a.H && gx < a.W) {
-                const int64_t idx = (int64_t)(o0 + o) * HW + (int64_t)gy * a.W + gx;
-                v = a.g[idx];
-                if (a.mask && !(a.mask[idx] > 0.f)) v = 0.f;
-            }
-            s_g[k] = v;
-        }
-        for (int k = threadIdx.x; k < 16 * (kWR + 2) * (kWC + 2); k += kT) {
-            const int i = k / ((kWR + 2) * (kWC + 2)), r = (k / (kWC + 2)) % (kWR + 2), q = k % (kWC + 2);
-            const int gy = y0 - 1 + r, gx = x0 - 1 + q;
-            float v = 0.f;
-            if (i0 + i < a.Cin && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
-                v = a.in[(int64_t)(i0 + i) * HW + (int64_t)gy * a.W + gx];
-            s_in[k] = v;
-        }
+        stage<OG * kWR * kWC, MASK>(s_g, a.g, a.mask, [&](int k, int64_t* q) {
+            const int o = k / (kWR * kWC), r = (k / kWC) % kWR, x = k % kWC;
+            const int gy = y0 + r, gx = x0 + x;
+            *q = (int64_t)(o0 + o) * HW + (int64_t)gy * a.W + gx;
+            return o0 + o < a.Cout && gy < a.H && gx < a.W;
+        });
+        stage<16 * (kWR + 2) * (kWC + 2), false>(s_in, a.in, nullptr, [&](int k, int64_t* q) {
+            const int i = k / ((kWR + 2) * (kWC + 2)), r = (k / (kWC + 2)) % (kWR + 2), x = k % (kWC + 2);
+            const int gy = y0 - 1 + r, gx = x0 - 1 + x;
+            *q = (int64_t)(i0 + i) * HW + (int64_t)gy * a.W + gx;
+            return i0 + i < a.Cin && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W;
+        });
         __syncthreads();
         const float* gi = s_g + ol * kWR * kWC;
         const float* xi = s_in + il * (kWR + 2) * (kWC + 2);
@@ -643,7 +656,8 @@ void launch_conv(const ConvArgs& a, hipStream_t st) {
         const int cps = (chunks + splits - 1) / splits;
         const int n_og = (a.Cout + 15) / 16;
         const dim3 grid((a.W + kTile - 1) / kTile, (a.H + kTile - 1) / kTile, n_og * splits);
-        hipLaunchKernelGGL(k_conv_mfma, grid, dim3(kT), 0, st, a, splits, cps);
+        if (a.mask) hipLaunchKernelGGL(k_conv_mfma<true>, grid, dim3(kT), 0, st, a, splits, cps);
+        else hipLaunchKernelGGL(k_conv_mfma<false>, grid, dim3(kT), 0, st, a, splits, cps);
         if (splits > 1) {
             const int64_t HW = (int64_t)a.H * a.W;
             hipLaunchKernelGGL(k_conv_reduce, dim3(blocks_for(HW), a.Cout), dim3(kT), 0, st, a.part, splits, a.Cout,
@@ -656,8 +670,13 @@ void launch_conv(const ConvArgs& a, hipStream_t st) {
     // gives every CU four workgroups
     const int r = ((int64_t)((a.W + kTile - 1) / kTile) * ((a.H + 2 * kTile - 1) / (2 * kTile)) >= 1024) ? 2 : 1;
     const unsigned gx = (a.W + kTile - 1) / kTile, gy = (a.H + kTile * r - 1) / (kTile * r);
-    if (r == 2) hipLaunchKernelGGL((k_conv<4, 2>), dim3(gx, gy, 1), dim3(kT), 0, st, a);
-    else hipLaunchKernelGGL((k_conv<4, 1>), dim3(gx, gy, 1), dim3(kT), 0, st, a);
+    if (a.mask) {
+        if (r == 2) hipLaunchKernelGGL((k_conv<4, 2, true>), dim3(gx, gy, 1), dim3(kT), 0, st, a);
+        else hipLaunchKernelGGL((k_conv<4, 1, true>), dim3(gx, gy, 1), dim3(kT), 0, st, a);
+    } else {
+        if (r == 2) hipLaunchKernelGGL((k_conv<4, 2, false>), dim3(gx, gy, 1), dim3(kT), 0, st, a);
+        else hipLaunchKernelGGL((k_conv<4, 1, false>), dim3(gx, gy, 1), dim3(kT), 0, st, a);
+    }
 }
 
 int wgrad_parts(int H, int W) {
@@ -667,11 +686,15 @@ int wgrad_parts(int H, int W) {
 
 void launch_wgrad(const WgradArgs& a, float* dw, hipStream_t st) {
     const int parts = wgrad_parts(a.H, a.W);
+    const bool m = a.mask != nullptr;
     if (a.Cout <= 4) {
-        hipLaunchKernelGGL(k_wgrad<4>, dim3(parts, (a.Cin + 15) / 16), dim3(kT), 0, st, a);
+        const dim3 grid(parts, (a.Cin + 15) / 16);
+        if (m) hipLaunchKernelGGL((k_wgrad<4, true>), grid, dim3(kT), 0, st, a);
+        else hipLaunchKernelGGL((k_wgrad<4, false>), grid, dim3(kT), 0, st, a);
     } else {
-        const int groups = ((a.Cout + 15) / 16) * ((a.Cin + 15) / 16);
-        hipLaunchKernelGGL(k_wgrad<16>, dim3(parts, groups), dim3(kT), 0, st, a);
+        const dim3 grid(parts, ((a.Cout + 15) / 16) * ((a.Cin + 15) / 16));
+        if (m) hipLaunchKernelGGL((k_wgrad<16, true>), grid, dim3(kT), 0, st, a);
+        else hipLaunchKernelGGL((k_wgrad<16, false>), grid, dim3(kT), 0, st, a);
     }
     hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((a.J + 63) / 64)), dim3(1024), 0, st, a.partial, parts, a.J, dw);
 }
