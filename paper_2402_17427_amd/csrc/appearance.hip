@@ -212,23 +212,32 @@ __global__ __launch_bounds__(kT) void k_conv_mfma(ConvArgs a, int splits, int cp
             *q = (int64_t)(c0 + c) * HW + (int64_t)gy * a.W + gx;
             return c0 + c < cend && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W;
         });
-        stage<16 * KC, false>(s_w, a.w, nullptr, [&](int k, int64_t* q) {
-            const int o = k / KC, kk = k % KC, c = kk / 9, t = kk % 9;
+        // weights as [k][o] with k = 8 tap + channel
+        stage<16 * KC, false>(s_w, a.w, nullptr, [&](int e, int64_t* q) {
+            const int k = e >> 4, o = e & 15, t = k >> 3, c = k & 7;
             const int ci = c0 + c, oo = og + o;
             *q = a.transposed ? ((int64_t)ci * a.CinF + oo) * 9 + (8 - t) : ((int64_t)oo * a.Cin + ci) * 9 + t;
             return ci < cend && oo < a.Cout;
         });
         __syncthreads();
-        const int steps = (min(kCI, cend - c0) * 9 + 3) / 4;
-        for (int s = 0; s < steps; ++s) {
-            const int k = 4 * s + lk;                  // this lane's k (< KC)
-            const int c = k / 9, t = k - 9 * (k / 9);
-            const int dy = t / 3, dx = t - 3 * (t / 3);
-            const float av = s_w[li * KC + k];
-            const float* src = s_in + c * kHalo * kHalo + (4 * wave + dy) * kHalo + li + dx;
+        // k-step s = 2 tap + h takes k = 4 s + lane / 16: channels 4 h ..
+        // 4 h + 3 of one tap, so every operand offset is a constant from
+        // the lane's base; the upper channel half is skipped when the chunk
+        // has at most four channels
+        const bool upper = cend - c0 > 4;
+        const float* aw = s_w + lane;
+        const float* bb = s_in + lk * kHalo * kHalo + 4 * wave * kHalo + li;
 #pragma unroll
-            for (int g = 0; g < 4; ++g)
-                acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, src[g * kHalo], acc[g], 0, 0, 0);
+        for (int t = 0; t < 9; ++t) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h == 1 && !upper) continue;
+                const float av = aw[64 * (2 * t + h)];
+                const float* src = bb + h * 4 * kHalo * kHalo + (t / 3) * kHalo + t % 3;
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                    acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, src[g * kHalo], acc[g], 0, 0, 0);
+            }
         }
     }
     // D[o = 4 (lane / 16) + r][pixel = lane % 16] of row 4 wave + g
