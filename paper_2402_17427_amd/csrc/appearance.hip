@@ -34,6 +34,21 @@ constexpr int kTile = 16;          // output tile width of the convolution
 constexpr int kHalo = kTile + 2;   // staged tile width
 constexpr int kWR = 8, kWC = 32;   // pixel tile of the weight gradient
 
+constexpr int kXcds = 8;   // XCDs of an MI355X; workgroups are dealt to them round-robin
+
+// Tile (x, y) of a workgroup of a 2D tile grid, in an XCD-aware order: the
+// workgroups dealt to one XCD take a contiguous band of tiles (in row
+// order), so horizontally adjacent tiles, which share halo columns and the
+// cache lines of their output rows, go through the same L2.
+__device__ __forceinline__ void xcd_tile(int* tx, int* ty) {
+    const int nx = (int)gridDim.x, n = nx * (int)gridDim.y;
+    const int b = (int)blockIdx.y * nx + (int)blockIdx.x;
+    const int per = n / kXcds;
+    const int t = b < per * kXcds ? (b % kXcds) * per + b / kXcds : b;
+    *ty = t / nx;
+    *tx = t - *ty * nx;
+}
+
 // Stages N floats into LDS: element k (k = tid, tid + kT, ...) is
 // src[q] with (ok, q) = at(k), zero when !ok, and zero where MASK and
 // mask[q] <= 0 (the ReLU mask of a backward pass).  Every load of the
@@ -109,7 +124,9 @@ __global__ __launch_bounds__(kT) void k_conv(ConvArgs a) {
     __shared__ float s_in[kCI * IR * kHalo];
     __shared__ float4 s_w[kCI * 9 * (CO / 4)];
     const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;   // rows R ty .. R ty + R - 1
-    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * TR;
+    int bx, by;
+    xcd_tile(&bx, &by);
+    const int x0 = bx * kTile, y0 = by * TR;
     const int og = blockIdx.z * CO;
     const int64_t HW = (int64_t)a.H * a.W;
     const int px = x0 + tx, py = y0 + R * ty;
@@ -192,7 +209,9 @@ __global__ __launch_bounds__(kT) void k_conv_mfma(ConvArgs a, int splits, int cp
     __shared__ float s_in[kCI * kHalo * kHalo];
     __shared__ float s_w[16 * KC];
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    int bx, by;
+    xcd_tile(&bx, &by);
+    const int x0 = bx * kTile, y0 = by * kTile;
     // blockIdx.z = split * (output-channel groups) + group; split s sums
     // input channels [s cps kCI, (s + 1) cps kCI)
     const int n_og = (a.Cout + 15) / 16;
