@@ -326,7 +326,16 @@ __global__ __launch_bounds__(kT) void k_wgrad(WgradArgs a) {
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t] = 0.f;
     float bacc = 0.f;
-    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    // the workgroups dealt to one XCD (blockIdx.x % kXcds) walk a
+    // contiguous band of tiles, so neighbouring tiles' halos share an L2
+    int t_beg = (int)blockIdx.x, t_end = n_tiles, t_step = (int)gridDim.x;
+    if (gridDim.x % kXcds == 0) {
+        const int xcd = (int)blockIdx.x % kXcds;
+        t_beg = (int)((int64_t)n_tiles * xcd / kXcds) + (int)blockIdx.x / kXcds;
+        t_end = (int)((int64_t)n_tiles * (xcd + 1) / kXcds);
+        t_step = (int)gridDim.x / kXcds;
+    }
+    for (int tile = t_beg; tile < t_end; tile += t_step) {
         const int y0 = (tile / tiles_x) * kWR, x0 = (tile % tiles_x) * kWC;
         __syncthreads();
         stage<OG * kWR * kWC, MASK>(s_g, a.g, a.mask, [&](int k, int64_t* q) {
@@ -453,12 +462,14 @@ __global__ __launch_bounds__(kT) void k_bilinear(const float* __restrict__ in, i
                                                  const float* __restrict__ fy, const int* __restrict__ x0,
                                                  const int* __restrict__ x1, const float* __restrict__ fx,
                                                  float* __restrict__ out) {
-    const int X = (int)blockIdx.x * kT + (int)threadIdx.x;
+    int bx, by;
+    xcd_tile(&bx, &by);
+    const int X = bx * kT + (int)threadIdx.x;
     if (X >= W) return;
     const int ex0 = x0[X], ex1 = x1[X];
     const float e = fx[X];
     const int rows = C * H;
-    for (int r0 = (int)blockIdx.y * kRows; r0 < rows; r0 += (int)gridDim.y * kRows) {
+    for (int r0 = by * kRows; r0 < rows; r0 += (int)gridDim.y * kRows) {
         // all loads of the kRows rows first (rows past the end repeat the
         // last one and are not stored), then the blends
         float v[kRows][4], a[kRows];
@@ -522,7 +533,9 @@ __global__ __launch_bounds__(kT) void k_bilin_adj_x(const float* __restrict__ g,
                                                     const int* __restrict__ i0, const int* __restrict__ i1,
                                                     const float* __restrict__ f, const int* __restrict__ rlo,
                                                     const int* __restrict__ rhi, float* __restrict__ out) {
-    const int i = (int)blockIdx.x * kT + (int)threadIdx.x;
+    int bx, by;
+    xcd_tile(&bx, &by);
+    const int i = bx * kT + (int)threadIdx.x;
     if (i >= w) return;
     const int lo = rlo[i], hi = rhi[i];
     // upsampling by at most 2 (the only use): at most four outputs read an
@@ -538,7 +551,7 @@ __global__ __launch_bounds__(kT) void k_bilin_adj_x(const float* __restrict__ g,
         dk[k] = on ? lo + k : 0;
         wk[k] = on ? adj_weight(lo + k, i, i0, i1, f) : 0.f;
     }
-    for (int r0 = (int)blockIdx.y * kRows; r0 < rows; r0 += (int)gridDim.y * kRows) {
+    for (int r0 = by * kRows; r0 < rows; r0 += (int)gridDim.y * kRows) {
         if (fits) {
             float v[kRows][K];
 #pragma unroll
@@ -573,11 +586,13 @@ __global__ __launch_bounds__(kT) void k_bilin_adj_y(const float* __restrict__ tm
                                                     const int* __restrict__ i0, const int* __restrict__ i1,
                                                     const float* __restrict__ f, const int* __restrict__ rlo,
                                                     const int* __restrict__ rhi, float* __restrict__ out) {
-    const int x = (int)blockIdx.x * kT + (int)threadIdx.x;
+    int bx, by;
+    xcd_tile(&bx, &by);
+    const int x = bx * kT + (int)threadIdx.x;
     if (x >= w) return;
     const int rows = C * h;
     constexpr int K = 4;   // as in the x pass: at most four taps when upsampling by at most 2
-    for (int r0 = (int)blockIdx.y * kRows; r0 < rows; r0 += (int)gridDim.y * kRows) {
+    for (int r0 = by * kRows; r0 < rows; r0 += (int)gridDim.y * kRows) {
         float v[kRows][K], wt[kRows][K];
         bool fits = true;
 #pragma unroll
