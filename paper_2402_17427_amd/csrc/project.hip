@@ -299,7 +299,12 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(JobTab jobs, ViewT
     float* __restrict__ gopac = J.gopac;
     float* __restrict__ gsh = J.gsh;
     const bool live = tt[slot] != 0 && *status == 0;
-    if (!live) {
+    // Culled Gaussians get zero gradients.  A wave with live lanes runs
+    // the whole computation on every lane and each lane stores every plane
+    // once (zero where culled): storing the culled lanes' zeros in a branch
+    // of their own wrote each output line in two partial pieces, which
+    // reached HBM as about 1.6x the gradient bytes.
+    if (__ballot(live) == 0ull) {
         for (int r = 0; r < 3; ++r) { gmean[r * gld + i] = 0.f; gscale[r * gld + i] = 0.f; }
         for (int r = 0; r < 4; ++r) gquat[r * gld + i] = 0.f;
         gopac[i] = 0.f;
@@ -311,10 +316,10 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(JobTab jobs, ViewT
     for (int r = 0; r < 4; ++r) q[r] = G.quat[r * ld + i];
     const double du = g2d[slot], dv = g2d[n + slot];
     const double dA = g2d[2 * n + slot], dB = g2d[3 * n + slot], dC = g2d[4 * n + slot];
-    gopac[i] = g2d[5 * n + slot];
+    gopac[i] = live ? g2d[5 * n + slot] : 0.f;
     const float drgb[3] = {g2d[6 * n + slot], g2d[7 * n + slot], g2d[8 * n + slot]};
 
-    Geo g;
+    Geo g = {};
     geometry(cam, mu, s, q, g);   // live implies it succeeded in the forward
 
     // ---- colour: rgb_c = max(0, sum_j k_cj Y_j(dir) + 0.5)
@@ -340,7 +345,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(JobTab jobs, ViewT
         const float gch = raw > 0.0f ? drgb[ch] : 0.0f;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            gsh[(int64_t)(ch * K + j) * gld + i] = gch * Y[j];
+            gsh[(int64_t)(ch * K + j) * gld + i] = live ? gch * Y[j] : 0.f;
             wsum[j] += gch * kc[j];
         }
     }
@@ -397,7 +402,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(JobTab jobs, ViewT
     gt[2] -= (fx * tx * du + fy * ty * dv) * itz2;
     // t = W mu + t_v
     for (int k = 0; k < 3; ++k) gmu[k] += cam.R[k] * gt[0] + cam.R[3 + k] * gt[1] + cam.R[6 + k] * gt[2];
-    for (int k = 0; k < 3; ++k) gmean[k * gld + i] = (float)gmu[k];
+    for (int k = 0; k < 3; ++k) gmean[k * gld + i] = live ? (float)gmu[k] : 0.f;
 
     // ---- Sigma = M M^T: dM = 2 dS M;  M = Rq diag(s)
     double dM[9];
@@ -406,7 +411,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(JobTab jobs, ViewT
             dM[3 * r + k] = 2.0 * (dS[3 * r] * g.M[k] + dS[3 * r + 1] * g.M[3 + k] + dS[3 * r + 2] * g.M[6 + k]);
     double dR[9];
     for (int k = 0; k < 3; ++k) {
-        gscale[k * gld + i] = (float)(dM[k] * g.Rq[k] + dM[3 + k] * g.Rq[3 + k] + dM[6 + k] * g.Rq[6 + k]);
+        gscale[k * gld + i] = live ? (float)(dM[k] * g.Rq[k] + dM[3 + k] * g.Rq[3 + k] + dM[6 + k] * g.Rq[6 + k]) : 0.f;
         for (int r = 0; r < 3; ++r) dR[3 * r + k] = dM[3 * r + k] * s[k];
     }
     // ---- Rq(qh) with qh = q/|q|
@@ -418,10 +423,10 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(JobTab jobs, ViewT
     double gy = 2.0 * (x * (dR[1] + dR[3]) + w * (dR[2] - dR[6]) + z * (dR[5] + dR[7]) - 2.0 * y * (dR[0] + dR[8]));
     double gz = 2.0 * (w * (dR[3] - dR[1]) + x * (dR[2] + dR[6]) + y * (dR[5] + dR[7]) - 2.0 * z * (dR[0] + dR[4]));
     const double dot = w * gw + x * gx + y * gy + z * gz;
-    gquat[0 * gld + i] = (float)((gw - w * dot) * inv);
-    gquat[1 * gld + i] = (float)((gx - x * dot) * inv);
-    gquat[2 * gld + i] = (float)((gy - y * dot) * inv);
-    gquat[3 * gld + i] = (float)((gz - z * dot) * inv);
+    gquat[0 * gld + i] = live ? (float)((gw - w * dot) * inv) : 0.f;
+    gquat[1 * gld + i] = live ? (float)((gx - x * dot) * inv) : 0.f;
+    gquat[2 * gld + i] = live ? (float)((gy - y * dot) * inv) : 0.f;
+    gquat[3 * gld + i] = live ? (float)((gz - z * dot) * inv) : 0.f;
 }
 
 }  // namespace
