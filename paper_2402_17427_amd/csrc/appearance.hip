@@ -8,16 +8,18 @@
 // convolution to 3 channels) produces the transformation map M; the
 // adjusted image is I^r * M.
 //
-// Every layer works on planar FP32 maps [C][H][W].  The convolutions are
-// direct: a workgroup computes a 16-wide pixel tile of one to four rows
-// per thread for a group of 4 or 16 output channels (chosen per layer), staging the input tile with its
-// one-pixel halo and the chunk's weights (as [ci][tap][co], read by every
-// lane at once) in LDS a few input channels at a time.  The same kernel runs the
-// transposed convolution of the backward (weights read flipped and
-// transposed) with the ReLU mask of the layer applied to its input as it
-// is staged.  Weight gradients are per-workgroup partial sums over pixel
-// tiles (a sliding 3 x 3 window in registers), reduced in a fixed order by
-// a second kernel, so every result is deterministic.
+// Every layer works on planar FP32 maps [C][H][W].  Convolutions with more
+// than four output channels are implicit GEMMs on the matrix cores
+// (k_conv_mfma); the 3-channel map M uses a direct VALU kernel (k_conv).
+// Both stage a pixel tile with its one-pixel halo and the weights of a few
+// input channels at a time in LDS; the same kernels run the transposed
+// convolutions of the backward (weights read flipped and transposed) with
+// the layer's ReLU mask applied to the input as it is staged.  The
+// low-resolution layers split their input channels over several workgroups
+// whose partial sums a second kernel adds in a fixed order.  Weight
+// gradients are per-workgroup partial sums over pixel tiles (a sliding
+// 3 x 3 window in registers), reduced in a fixed order by a second kernel,
+// so every result is deterministic.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -194,15 +196,17 @@ __global__ __launch_bounds__(kT) void k_conv(ConvArgs a) {
 
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 
-// The same convolution as an implicit GEMM on the matrix cores:
-// out[o][p] = sum_k W[o][k] X[k][p] with k = (input channel, tap), sixteen
-// output channels by sixteen pixels per v_mfma_f32_16x16x4f32 (FP32 in, FP32
-// accumulate).  A workgroup computes a 16 x 16 pixel tile for 16 output
-// channels; wave w owns tile rows 4w .. 4w + 3, one accumulator each.  Per
-// chunk of 8 input channels the input tile (with its halo) and the
-// [o][ci][tap] weights are staged in LDS; each k-step gives every lane one
-// weight (A: row o = lane % 16, k = lane / 16) and, per row, one input
-// sample (B: k = lane / 16, pixel = lane % 16).
+// The convolution as an implicit GEMM on the matrix cores:
+// out[o][p] = sum_k W[o][k] X[k][p] with k = 8 tap + input channel (within
+// a chunk of 8 channels), sixteen output channels by sixteen pixels per
+// v_mfma_f32_16x16x4f32 (FP32 in, FP32 accumulate).  A workgroup computes a
+// 16 x 16 pixel tile for 16 output channels; wave w owns tile rows
+// 4w .. 4w + 3, one accumulator each.  Per chunk the input tile (with its
+// halo) and the [k][o] weights are staged in LDS; each k-step gives every
+// lane one weight (A: row o = lane % 16, k = lane / 16) and, per row, one
+// input sample (B: k = lane / 16, pixel = lane % 16).  Split launches
+// (splits > 1) sum input channels [s cps 8, (s + 1) cps 8) and write raw
+// partial sums for k_conv_reduce.
 template <bool MASK>
 __global__ __launch_bounds__(kT) void k_conv_mfma(ConvArgs a, int splits, int cps) {
     constexpr int KC = kCI * 9;   // k values per chunk (72)
