@@ -500,6 +500,69 @@ __global__ __launch_bounds__(kT) void k_bilinear(const float* __restrict__ in, i
     }
 }
 
+// Row kernels of the interpolation for images up to kRowW = 2048 wide (the
+// source rows then hold at most 1024 values): a workgroup handles a
+// contiguous run of rows, staging each row's sources in LDS with coalesced
+// loads (every load of the thread issued before its LDS writes), and each
+// thread keeps the taps of its output columns in registers for all rows.
+constexpr int kRowW = 2048;
+constexpr int kRowCols = kRowW / kT;   // output columns per thread (forward)
+constexpr int kRowSrc = kRowW / 2 / kT;   // source values per thread and row (forward)
+
+__global__ __launch_bounds__(kT) void k_bilinear_rows(const float* __restrict__ in, int C, int h, int w, int H,
+                                                      int W, const int* __restrict__ y0, const int* __restrict__ y1,
+                                                      const float* __restrict__ fy, const int* __restrict__ x0,
+                                                      const int* __restrict__ x1, const float* __restrict__ fx,
+                                                      float* __restrict__ out) {
+    extern __shared__ float s_src[];   // the two source rows, 2 w floats
+    const int tid = (int)threadIdx.x;
+    int ex0[kRowCols], ex1[kRowCols];
+    float e[kRowCols];
+#pragma unroll
+    for (int m = 0; m < kRowCols; ++m) {
+        const int X = tid + m * kT;
+        const bool ok = X < W;
+        ex0[m] = ok ? x0[X] : 0;
+        ex1[m] = ok ? x1[X] : 0;
+        e[m] = ok ? fx[X] : 0.f;
+    }
+    const int rows = C * H;
+    const int chunk = (rows + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int r_end = min(rows, ((int)blockIdx.x + 1) * chunk);
+    for (int row = (int)blockIdx.x * chunk; row < r_end; ++row) {
+        const int c = row / H, Y = row - c * H;
+        const float* p0 = in + ((int64_t)c * h + y0[Y]) * w;
+        const float* p1 = in + ((int64_t)c * h + y1[Y]) * w;
+        const float a = fy[Y];
+        float v0[kRowSrc], v1[kRowSrc];
+#pragma unroll
+        for (int j = 0; j < kRowSrc; ++j) {
+            const int k = tid + j * kT;
+            v0[j] = p0[k < w ? k : 0];
+            v1[j] = p1[k < w ? k : 0];
+        }
+        __syncthreads();   // the previous row's blends are done with s_src
+#pragma unroll
+        for (int j = 0; j < kRowSrc; ++j) {
+            const int k = tid + j * kT;
+            if (k < w) {
+                s_src[k] = v0[j];
+                s_src[w + k] = v1[j];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kRowCols; ++m) {
+            const int X = tid + m * kT;
+            if (X < W) {
+                const float top = (1.f - e[m]) * s_src[ex0[m]] + e[m] * s_src[ex1[m]];
+                const float bot = (1.f - e[m]) * s_src[w + ex0[m]] + e[m] * s_src[w + ex1[m]];
+                out[(int64_t)row * W + X] = (1.f - a) * top + a * bot;
+            }
+        }
+    }
+}
+
 // Outputs d reading input i along one axis are those with i0[d] <= i <=
 // i1[d] (i1 is i0 or i0 + 1, both nondecreasing in d): a contiguous range,
 // found by a short scan from its estimate.
@@ -543,9 +606,10 @@ __global__ __launch_bounds__(kT) void k_bilin_adj_x(const float* __restrict__ g,
     if (i >= w) return;
     const int lo = rlo[i], hi = rhi[i];
     // upsampling by at most 2 (the only use): at most four outputs read an
-    // input; their taps are loaded once, padded with weight-0 taps (which
-    // leave the sum unchanged); longer ranges take the plain loop
-    constexpr int K = 4;
+    // input, five at the clamped last one; their taps are loaded once,
+    // padded to six with weight-0 taps (which leave the sum unchanged);
+    // longer ranges take the plain loop
+    constexpr int K = 6;
     const bool fits = hi - lo <= K;
     int dk[K];
     float wk[K];
@@ -583,6 +647,66 @@ __global__ __launch_bounds__(kT) void k_bilin_adj_x(const float* __restrict__ g,
     }
 }
 
+// The x pass of the adjoint as a row kernel: the row of g (W <= kRowW) is
+// staged in LDS; thread columns i = tid + m kT (i < w <= kRowW / 2) keep
+// their taps in registers (at most four when upsampling by at most 2, five
+// at the clamped last input; padded to six with weight-0 taps; a longer
+// range falls back to the plain loop over the staged row).
+__global__ __launch_bounds__(kT) void k_bilin_adj_x_rows(const float* __restrict__ g, int rows, int W, int w,
+                                                         const int* __restrict__ i0, const int* __restrict__ i1,
+                                                         const float* __restrict__ f, const int* __restrict__ rlo,
+                                                         const int* __restrict__ rhi, float* __restrict__ out) {
+    extern __shared__ float s_row[];   // W floats
+    constexpr int M = kRowW / 2 / kT, K = 6, J = kRowW / kT;
+    const int tid = (int)threadIdx.x;
+    int dk[M][K], lo[M], hi[M];
+    float wk[M][K];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int i = tid + m * kT;
+        lo[m] = i < w ? rlo[i] : 0;
+        hi[m] = i < w ? rhi[i] : 0;
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            const bool on = lo[m] + t < hi[m];
+            dk[m][t] = on ? lo[m] + t : 0;
+            wk[m][t] = on ? adj_weight(lo[m] + t, i, i0, i1, f) : 0.f;
+        }
+    }
+    const int chunk = (rows + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int r_end = min(rows, ((int)blockIdx.x + 1) * chunk);
+    for (int row = (int)blockIdx.x * chunk; row < r_end; ++row) {
+        const float* gl = g + (int64_t)row * W;
+        float v[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int k = tid + j * kT;
+            v[j] = gl[k < W ? k : 0];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int k = tid + j * kT;
+            if (k < W) s_row[k] = v[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int i = tid + m * kT;
+            if (i < w) {
+                float s = 0.f;
+                if (hi[m] - lo[m] <= K) {
+#pragma unroll
+                    for (int t = 0; t < K; ++t) s = fmaf(wk[m][t], s_row[dk[m][t]], s);
+                } else {
+                    for (int d = lo[m]; d < hi[m]; ++d) s = fmaf(adj_weight(d, i, i0, i1, f), s_row[d], s);
+                }
+                out[(int64_t)row * w + i] = s;
+            }
+        }
+    }
+}
+
 // ... and along y: out[c][i][x] = sum over the output rows Y that read
 // input row i of their weight times tmp[c][Y][x] (one (c, i) per grid row,
 // one column per thread)
@@ -595,7 +719,7 @@ __global__ __launch_bounds__(kT) void k_bilin_adj_y(const float* __restrict__ tm
     const int x = bx * kT + (int)threadIdx.x;
     if (x >= w) return;
     const int rows = C * h;
-    constexpr int K = 4;   // as in the x pass: at most four taps when upsampling by at most 2
+    constexpr int K = 6;   // as in the x pass: at most five taps when upsampling by at most 2
     for (int r0 = by * kRows; r0 < rows; r0 += (int)gridDim.y * kRows) {
         float v[kRows][K], wt[kRows][K];
         bool fits = true;
@@ -758,8 +882,17 @@ void launch_bilin_table(int n_in, int n_out, int* i0, int* i1, float* f, hipStre
 // workgroup rows for kRows rows each (the kernels stride over the rest)
 unsigned grid_rows(int64_t rows) { return (unsigned)std::min<int64_t>((rows + kRows - 1) / kRows, 65535); }
 
+// workgroups of the row kernels: about eight per CU, each a run of rows
+unsigned row_groups(int64_t rows) { return (unsigned)std::min<int64_t>(rows, 2048); }
+
 void launch_bilinear(const float* in, int C, int h, int w, int H, int W, const BilinTab& t, float* out,
                      hipStream_t st) {
+    if (W <= kRowW) {
+        const int64_t rows = (int64_t)C * H;
+        hipLaunchKernelGGL(k_bilinear_rows, dim3(row_groups(rows)), dim3(kT), 2 * w * sizeof(float), st, in, C, h, w,
+                           H, W, t.y0, t.y1, t.fy, t.x0, t.x1, t.fx, out);
+        return;
+    }
     hipLaunchKernelGGL(k_bilinear, dim3(blocks_for(W), grid_rows((int64_t)C * H)), dim3(kT), 0, st, in, C, h, w, H,
                        W, t.y0, t.y1, t.fy, t.x0, t.x1, t.fx, out);
 }
@@ -770,8 +903,12 @@ void launch_bilinear_adj(const float* g, int C, int H, int W, int h, int w, cons
     const int64_t rows = (int64_t)C * H;
     hipLaunchKernelGGL(k_bilin_ranges, dim3(blocks_for(w)), dim3(kT), 0, st, w, W, t.x0, t.x1, t.xlo, t.xhi);
     hipLaunchKernelGGL(k_bilin_ranges, dim3(blocks_for(h)), dim3(kT), 0, st, h, H, t.y0, t.y1, t.ylo, t.yhi);
-    hipLaunchKernelGGL(k_bilin_adj_x, dim3(blocks_for(w), grid_rows(rows)), dim3(kT), 0, st, g, (int)rows, W, w,
-                       t.x0, t.x1, t.fx, t.xlo, t.xhi, tmp);
+    if (W <= kRowW)
+        hipLaunchKernelGGL(k_bilin_adj_x_rows, dim3(row_groups(rows)), dim3(kT), W * sizeof(float), st, g, (int)rows,
+                           W, w, t.x0, t.x1, t.fx, t.xlo, t.xhi, tmp);
+    else
+        hipLaunchKernelGGL(k_bilin_adj_x, dim3(blocks_for(w), grid_rows(rows)), dim3(kT), 0, st, g, (int)rows, W, w,
+                           t.x0, t.x1, t.fx, t.xlo, t.xhi, tmp);
     // y pass: tmp [C][H][w] -> out [C][h][w]
     hipLaunchKernelGGL(k_bilin_adj_y, dim3(blocks_for(w), grid_rows((int64_t)C * h)), dim3(kT), 0, st, tmp, C, H, h,
                        w, t.y0, t.y1, t.fy, t.ylo, t.yhi, out);
