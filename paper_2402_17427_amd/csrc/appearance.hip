@@ -528,19 +528,24 @@ __global__ __launch_bounds__(kT) void k_bilinear_rows(const float* __restrict__ 
     }
     const int rows = C * H;
     const int chunk = (rows + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int r_end = min(rows, ((int)blockIdx.x + 1) * chunk);
-    for (int row = (int)blockIdx.x * chunk; row < r_end; ++row) {
+    const int r_beg = (int)blockIdx.x * chunk, r_end = min(rows, r_beg + chunk);
+    // a row's source values are loaded while the previous row is blended
+    float v0[kRowSrc], v1[kRowSrc], an = 0.f;
+    auto load = [&](int row) {
         const int c = row / H, Y = row - c * H;
         const float* p0 = in + ((int64_t)c * h + y0[Y]) * w;
         const float* p1 = in + ((int64_t)c * h + y1[Y]) * w;
-        const float a = fy[Y];
-        float v0[kRowSrc], v1[kRowSrc];
+        an = fy[Y];
 #pragma unroll
         for (int j = 0; j < kRowSrc; ++j) {
             const int k = tid + j * kT;
             v0[j] = p0[k < w ? k : 0];
             v1[j] = p1[k < w ? k : 0];
         }
+    };
+    if (r_beg < r_end) load(r_beg);
+    for (int row = r_beg; row < r_end; ++row) {
+        const float a = an;
         __syncthreads();   // the previous row's blends are done with s_src
 #pragma unroll
         for (int j = 0; j < kRowSrc; ++j) {
@@ -551,6 +556,7 @@ __global__ __launch_bounds__(kT) void k_bilinear_rows(const float* __restrict__ 
             }
         }
         __syncthreads();
+        if (row + 1 < r_end) load(row + 1);
 #pragma unroll
         for (int m = 0; m < kRowCols; ++m) {
             const int X = tid + m * kT;
@@ -674,15 +680,19 @@ __global__ __launch_bounds__(kT) void k_bilin_adj_x_rows(const float* __restrict
         }
     }
     const int chunk = (rows + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int r_end = min(rows, ((int)blockIdx.x + 1) * chunk);
-    for (int row = (int)blockIdx.x * chunk; row < r_end; ++row) {
+    const int r_beg = (int)blockIdx.x * chunk, r_end = min(rows, r_beg + chunk);
+    // a row is loaded while the previous row's sums are formed
+    float v[J];
+    auto load = [&](int row) {
         const float* gl = g + (int64_t)row * W;
-        float v[J];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             const int k = tid + j * kT;
             v[j] = gl[k < W ? k : 0];
         }
+    };
+    if (r_beg < r_end) load(r_beg);
+    for (int row = r_beg; row < r_end; ++row) {
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < J; ++j) {
@@ -690,6 +700,7 @@ __global__ __launch_bounds__(kT) void k_bilin_adj_x_rows(const float* __restrict
             if (k < W) s_row[k] = v[j];
         }
         __syncthreads();
+        if (row + 1 < r_end) load(row + 1);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int i = tid + m * kT;
