@@ -125,8 +125,11 @@ def _check(got, ref):
         _grad_ok(f"layer {k} bias", gb, rb, mb)
 
 
+# 2048 wide: the widest image of the row interpolation kernels; 2100 wide:
+# the general interpolation kernels
 @pytest.mark.parametrize("H,W,seed,l1", [(70, 100, 1, False), (64, 64, 2, True), (33, 95, 3, False),
-                                         (1, 1, 4, False), (97, 31, 5, True)])
+                                         (1, 1, 4, False), (97, 31, 5, True), (20, 2048, 9, True),
+                                         (40, 2100, 10, True)])
 def test_appearance_matches_the_oracle(H, W, seed, l1):
     _case(f"appearance {H}x{W} ({'L1' if l1 else 'random'} gradient)")
     got, ref = _run(H, W, seed, l1)
