@@ -28,6 +28,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "../../include/gs.h"
@@ -243,9 +244,12 @@ gs_status gs_partition_views(const gs_camera* cams, int32_t n_views, const float
             b[3] = ze[j + 1];
         }
     }
-    // 2-3. expansion, position-based selection, airspace box, visibility
+    // 2-3. expansion, position-based selection, airspace box, visibility:
+    // cells are independent (each writes only its own rows), so they run on
+    // host threads; the per-cell computation, and so the result, is the
+    // same for any thread count
     const double r = cfg->expand;
-    for (int c = 0; c < ncell; ++c) {
+    auto one_cell = [&](int c) {
         const double* b = bounds + 4 * c;
         double* e = expanded + 4 * c;
         const double hx = 0.5 * r * (b[1] - b[0]), hz = 0.5 * r * (b[3] - b[2]);
@@ -275,7 +279,7 @@ gs_status gs_partition_views(const gs_camera* cams, int32_t n_views, const float
         double* bx = boxes + 6 * c;
         if (!any) {
             std::memset(bx, 0, 6 * sizeof(double));
-            continue;
+            return;
         }
         bx[0] = lo[0];
         bx[1] = 0.0;
@@ -288,6 +292,18 @@ gs_status gs_partition_views(const gs_camera* cams, int32_t n_views, const float
             vis[i] = box_visibility(pc[i], lo, hi);
             if (vis[i] > cfg->visibility_threshold) vm[i] = 2;
         }
+    };
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int workers = (int)std::min<unsigned>(hw, (unsigned)ncell);
+    if (workers <= 1) {
+        for (int c = 0; c < ncell; ++c) one_cell(c);
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < workers; ++t)
+            pool.emplace_back([&, t] {
+                for (int c = t; c < ncell; c += workers) one_cell(c);
+            });
+        for (std::thread& th : pool) th.join();
     }
     return GS_OK;
 }
