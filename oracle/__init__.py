@@ -15,6 +15,7 @@ readings listed at the top of `gs_oracle.c`.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -43,31 +44,58 @@ def build(force: bool = True) -> str:
 _lib = None
 
 
+def build_planted(macro: str, out_dir: str) -> str:
+    """Compile a copy of the oracle with one planted mistake switched on
+    (`-D<macro>`) into `out_dir`; tests load it with `planted_library` to show
+    that their pins catch the mistake."""
+    path = os.path.join(out_dir, f"liboracle_{macro.lower()}.so")
+    subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+                           f"-D{macro}", "-o", path, _SRC, "-lm"])
+    return path
+
+
+@contextlib.contextmanager
+def planted_library(path):
+    """Route the oracle calls made inside the block through the library at
+    `path` (a planted build), then back to the regular one."""
+    global _lib
+    prev = _lib
+    _lib = _load(path)
+    try:
+        yield
+    finally:
+        _lib = prev
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        L = C.CDLL(_LIB)
-        P = C.c_void_p
-        i64 = C.c_int64
-        L.orc_project.argtypes = [i64, i64, C.c_int] + [P] * 6 + [P] * 8
-        L.orc_project.restype = C.c_int
-        L.orc_render.argtypes = [i64, i64, C.c_int] + [P] * 6 + [i64, P, P, P] + [P] * 5
-        L.orc_render.restype = C.c_int
-        L.orc_backward.argtypes = [i64, i64, C.c_int] + [P] * 6 + [P, i64, P, P, P] + [P] * 8
-        L.orc_backward.restype = C.c_int
-        L.orc_bin.argtypes = [i64, i64, C.c_int] + [P] * 6 + [C.c_int, C.c_int, C.c_double, P, P, i64,
-                                                               P, P, P, P, P]
-        L.orc_bin.restype = C.c_int64
-        L.orc_render_tiled.argtypes = [i64, i64, C.c_int] + [P] * 6 + [C.c_int, C.c_int, P, P, P, P]
-        L.orc_render_tiled.restype = C.c_int
-        L.orc_sh_basis.argtypes = [P, P]
-        L.orc_sh_basis_grad.argtypes = [P, P]
-        L.orc_num_threads.restype = C.c_int
-        L.orc_set_num_threads.argtypes = [C.c_int]
-        _lib = L
+        _lib = _load(_LIB)
     return _lib
+
+
+def _load(path):
+    L = C.CDLL(path)
+    P = C.c_void_p
+    i64 = C.c_int64
+    L.orc_project.argtypes = [i64, i64, C.c_int] + [P] * 6 + [P] * 8
+    L.orc_project.restype = C.c_int
+    L.orc_render.argtypes = [i64, i64, C.c_int] + [P] * 6 + [i64, P, P, P] + [P] * 5
+    L.orc_render.restype = C.c_int
+    L.orc_backward.argtypes = [i64, i64, C.c_int] + [P] * 6 + [P, i64, P, P, P] + [P] * 8
+    L.orc_backward.restype = C.c_int
+    L.orc_bin.argtypes = [i64, i64, C.c_int] + [P] * 6 + [C.c_int, C.c_int, C.c_double, P, P, i64,
+                                                           P, P, P, P, P]
+    L.orc_bin.restype = C.c_int64
+    L.orc_render_tiled.argtypes = [i64, i64, C.c_int] + [P] * 6 + [C.c_int, C.c_int, P, P, P, P]
+    L.orc_render_tiled.restype = C.c_int
+    L.orc_sh_basis.argtypes = [P, P]
+    L.orc_sh_basis_grad.argtypes = [P, P]
+    L.orc_num_threads.restype = C.c_int
+    L.orc_set_num_threads.argtypes = [C.c_int]
+    return L
 
 
 def _p(a):

@@ -454,3 +454,109 @@ def test_gradient_restricted_to_pixel_sample_equals_masked_full_gradient():
     part = oracle.backward(g, cam, w * (m != 0), px=px, py=py)
     for k in ("mean", "scale", "quat", "opacity", "sh"):
         np.testing.assert_allclose(part[k], full[k], rtol=1e-12, atol=1e-15)
+
+
+# -------------------------------------------------- alpha capped at 0.99 --
+
+def _capped_scene(seed, W=40, H=32):
+    """Seven Gaussians, three of them with opacity 0.995-0.9999 and wide
+    enough that the pixel centres nearest their centres take alpha = 0.99
+    (capped) while a wide ring around them does not."""
+    rng = np.random.default_rng(seed)
+    cam = scenes.look_at((0.2, 0.1, -5.0), (0, 0, 0), W, H, hfov_deg=50, bg=(0.2, 0.4, 0.3))
+    n, deg = 7, 1
+    K = (deg + 1) ** 2
+    mean = np.stack([rng.uniform(-0.7, 0.7, n), rng.uniform(-0.5, 0.5, n), rng.uniform(-0.6, 0.6, n)])
+    scale = np.exp(rng.normal(-1.7, 0.3, (3, n)))
+    opac = rng.uniform(0.3, 0.8, n)
+    opac[:3] = [0.995, 0.999, 0.9999]
+    scale[:, :3] = rng.uniform(0.7, 1.1, (3, 3))
+    quat = rng.normal(size=(4, n))
+    sh = rng.normal(0, 0.3, (3 * K, n))
+    sh[0::K] = rng.uniform(-0.5, 1.5, (3, n))
+    g = scenes.Gaussians(mean, scale, quat, opac, sh, deg)
+    w = rng.normal(size=(3, H, W))
+    return g, cam, w
+
+
+def _capped_contributions(g, cam, i):
+    """Pixels where Gaussian i is blended with alpha capped at 0.99, and
+    pixels where it is blended below the cap (recomputed here from the
+    oracle's own blend order, in plain NumPy)."""
+    pr = oracle.project(g, cam)
+    r = oracle.render(g, cam)
+    W, H = cam.width, cam.height
+    ys, xs = np.mgrid[0:H, 0:W]
+    u, v = pr["uv"][i]
+    A, B, C = pr["conic"][i]
+    dx, dy = xs + 0.5 - u, ys + 0.5 - v
+    a = g.opacity[i] * np.exp(-0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy)
+    order = np.argsort(pr["depth"], kind="stable")
+    rank = np.empty_like(order)
+    rank[order] = np.arange(order.size)
+    # blended at a pixel iff it lies at or before the pixel's last blended Gaussian
+    last = r["last_id"]
+    reached = (last >= 0) & (rank[np.maximum(last, 0)] >= rank[i])
+    return reached & (a > 0.99), reached & (a >= 1 / 255) & (a <= 0.99)
+
+
+def _fd_mismatches(g, cam, w, names=("mean", "scale", "quat", "opacity")):
+    """Central differences (h = 1e-6 relative) of L = sum(w * I) against
+    the oracle's analytic gradient, skipping components whose +-h renders
+    change a blend decision or come near one (flags, including the 0.99
+    cap window).  Returns (mismatches, checked)."""
+    w = w * (oracle.render(g, cam)["flags"] == 0)     # no weight on ambiguous pixels
+    an = oracle.backward(g, cam, w)
+    live = np.abs(w).sum(0) > 0
+
+    def sig(r):
+        return r["nblend"][live], r["last_id"][live], r["flags"][live]
+
+    bad, checked = [], 0
+    for name in names:
+        arr = getattr(g, name)
+        flat = arr.reshape(-1)
+        gan = an[name].reshape(-1)
+        for j in range(flat.size):
+            x0 = flat[j]
+            h = 1e-6 * max(1.0, abs(x0))
+            flat[j] = x0 + h
+            rp = oracle.render(g, cam)
+            flat[j] = x0 - h
+            rm = oracle.render(g, cam)
+            flat[j] = x0
+            sp, sm = sig(rp), sig(rm)
+            if (sp[2] != 0).any() or (sm[2] != 0).any() or \
+                    not all(np.array_equal(a, b) for a, b in zip(sp, sm)):
+                continue
+            fd = float(((rp["image"] - rm["image"]) * w).sum()) / (2 * h)
+            checked += 1
+            if abs(gan[j] - fd) > 1e-5 * abs(fd) + 1e-7:
+                bad.append((name, j, float(gan[j]), fd))
+    return bad, checked
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_capped_alpha_gradient_matches_central_differences(seed):
+    """Where alpha = min(0.99, o exp(power)) takes the cap, alpha depends on
+    neither o nor the geometry: the opacity, mean, scale and rotation
+    gradients of Gaussians that are capped at their centre pixels and not
+    in the ring around them agree with central differences."""
+    g, cam, w = _capped_scene(seed)
+    for i in range(3):
+        cap, ring = _capped_contributions(g, cam, i)
+        assert cap.sum() >= 1 and ring.sum() >= 100, (i, int(cap.sum()), int(ring.sum()))
+    bad, checked = _fd_mismatches(g, cam, w)
+    assert checked >= 60
+    assert not bad, bad[:5]
+
+
+def test_planted_capped_opacity_gradient_is_caught(tmp_path):
+    """A slip that keeps dL/do = dL/dalpha * G under the cap (planted in the
+    oracle, on the CPU) fails the central-difference pin above."""
+    g, cam, w = _capped_scene(0)
+    path = oracle.build_planted("ORC_PLANT_CAPPED_DOPACITY", str(tmp_path))
+    with oracle.planted_library(path):
+        bad, checked = _fd_mismatches(g, cam, w, names=("opacity",))
+    assert checked >= 3
+    assert {j for name, j, _, _ in bad} >= {0, 1, 2}, bad
