@@ -57,6 +57,17 @@ MFMA_FP32_TFLOPS = 157.3                                    # dense FP32 matrix-
 FWD_OPS_SUPPORT = 18
 FWD_OPS_BLEND = 6
 BWD_OPS_BLEND = 48
+# The frozen work model of the hot path (per evaluation E, the list entries
+# a pixel evaluates before its stop, and per blended pair; slots of the FP32
+# ALUs, a transcendental counted 4):
+#   forward  E * 20 + blended * 5      (dx, dy 2, quadratic form 6, power
+#            test 1, scale and exp 1 + 4, alpha min 2, alpha test 1, T' 2,
+#            stop test 1; blend: alpha T, 3 FMA, T update)
+#   backward E * 20 + blended * 35     (the same recompute; the gradient
+#            terms of a blended pair)
+MODEL_FWD_EVAL, MODEL_FWD_BLEND = 20, 5
+MODEL_BWD_EVAL, MODEL_BWD_BLEND = 20, 35
+REC_BYTES = 48                 # projected record + depth + rect + count, per Gaussian
 # Training loss (Eq. 1: L1 + D-SSIM), per pixel and channel, counted at the
 # output pixel with separable 11-tap window sums (no halo recompute):
 #   products x^2, y^2, xy 3 + five forward window sums 5 x 22 = 110
@@ -82,6 +93,32 @@ def adam_bytes(n, planes, visible):
     return n * (planes * 28 + 4 * 4 + 4) + visible * 24
 
 
+def work_model(stats, pairs, n, K, npix, n_tiles, tile_bits):
+    """Algorithmic bytes and ALU slots of each stage of one fwd+bwd step, and
+    its ideal time max(bytes / HBM peak, slots / ALU peak) in microseconds.
+    Stages: a1 projection, a2 scan and key emission, a3 sort (direct-key
+    onesweep count: one histogram read of the 8-byte keys and 24 bytes per
+    pair per 8-bit digit pass over the 32 depth and the tile bits), a4 tile
+    ranges, a5 forward blend, a6 backward blend, a7 projection backward."""
+    import math
+    E, blended = stats["evaluated"], stats["blended"]
+    inb = 4 * (11 + 3 * K)
+    passes = math.ceil((32 + tile_bits) / 8)
+    st = {
+        "a1_project": {"bytes": n * (inb + REC_BYTES), "slots": 0},
+        "a2_scan_emit": {"bytes": n * 12 + pairs * 12, "slots": 0},
+        "a3_sort": {"bytes": pairs * (8 + 24 * passes), "slots": 0},
+        "a4_ranges": {"bytes": pairs * 8 + n_tiles * 8, "slots": 0},
+        "a5_render_fwd": {"bytes": pairs * 40 + npix * 20, "slots": E * MODEL_FWD_EVAL + blended * MODEL_FWD_BLEND},
+        "a6_render_bwd": {"bytes": pairs * 40 + npix * 20 + pairs * 72,
+                          "slots": E * MODEL_BWD_EVAL + blended * MODEL_BWD_BLEND},
+        "a7_project_bwd": {"bytes": n * (inb * 2 + 36 + REC_BYTES), "slots": 0},
+    }
+    for v in st.values():
+        v["ideal_us"] = round(max(v["bytes"] / (HBM_PEAK_GBS * 1e3), v["slots"] / (VALU_PEAK_GOPS * 1e3)), 3)
+    return st
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,8 +134,11 @@ def parse():
     ap.add_argument("--no-loss", action="store_true",
                     help="skip the measurements around the rasterizer (loss, training step, appearance model, "
                          "partitioning)")
-    ap.add_argument("--serve-rates", type=float, nargs="+", default=(100.0, 400.0))
-    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=(50.0, 100.0, 200.0, 400.0, 1000.0),
+                    help="Poisson arrival rates (req/s); the last lies above the unbatched server's saturation")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per rate")
+    ap.add_argument("--serve-warmup", type=int, default=200, help="warm-up requests per rate (not measured)")
+    ap.add_argument("--no-autograd", action="store_true", help="skip the autograd-form measurement")
     ap.add_argument("--serve-grid", type=int, default=10, help="merged scene: grid x grid cells of 200k Gaussians")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -181,25 +221,31 @@ def cpu_model():
     return None
 
 
-def environment(torch):
-    """Device, software versions and the GPU clocks at the time of the run."""
-    import subprocess
-    env = {"device": torch.cuda.get_device_name(0), "hip": torch.version.hip, "torch": torch.__version__}
+def _read(path):
     try:
-        env["rocm"] = open("/opt/rocm/.info/version").read().strip()
+        with open(path) as fh:
+            return fh.read()
     except OSError:
-        env["rocm"] = None
-    try:
-        r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=20)
-        env["clocks"] = [ln.strip() for ln in r.stdout.splitlines() if "sclk" in ln or "mclk" in ln][:4]
-    except (OSError, subprocess.SubprocessError):
-        env["clocks"] = None
-    try:
-        r = subprocess.run(["rocm-smi", "--showdriverversion"], capture_output=True, text=True, timeout=20)
-        env["driver"] = next((ln.split(":", 1)[1].strip() for ln in r.stdout.splitlines()
-                              if "version" in ln.lower() and ":" in ln), None)
-    except (OSError, subprocess.SubprocessError):
-        env["driver"] = None
+        return None
+
+
+def environment(torch):
+    """Device, software versions and the GPU clocks at the time of the run,
+    read in-process (sysfs and /opt/rocm), no child processes."""
+    import glob
+    env = {"device": torch.cuda.get_device_name(0), "hip": torch.version.hip, "torch": torch.__version__}
+    v = _read("/opt/rocm/.info/version")
+    env["rocm"] = v.strip() if v else None
+    v = _read("/sys/module/amdgpu/version")
+    env["driver"] = v.strip() if v else None
+    clocks = []
+    for dev in sorted(glob.glob("/sys/class/drm/card*/device")):
+        for name in ("pp_dpm_sclk", "pp_dpm_mclk"):
+            txt = _read(os.path.join(dev, name))
+            if txt:
+                cur = [ln.strip() for ln in txt.splitlines() if ln.strip().endswith("*")]
+                clocks.append(f"{os.path.basename(os.path.dirname(dev))} {name[7:]}: " + (cur[0] if cur else "?"))
+    env["clocks"] = clocks or None
     return env
 
 
@@ -606,6 +652,63 @@ def bench_batched(args, torch, scenes, raster):
                                            for c in info["candidates"]]}}
 
 
+def bench_autograd(args, torch, scenes, raster):
+    """The autograd form at 200k Gaussians (SH degree 3) and 800x800: a
+    training-style step (rasterize, L = sum(w * I), backward) through the
+    torch.autograd.Function, for the backward that recomputes the blend
+    state and the one that stores it in the forward; time per step and the
+    device bytes each holds between forward and backward; the same view
+    through the plain calls beside them."""
+    import numpy as np
+    from paper_2402_17427_amd.autograd import RasterSettings, held_bytes, rasterize
+    g, cam = scenes.config3()
+    dg = raster.DeviceGaussians.from_host(g)
+    w = torch.as_tensor(scenes.grad_image(cam, 4, "uniform")).cuda()
+    leaves = [torch.tensor(np.ascontiguousarray(getattr(g, k), np.float32), device="cuda", requires_grad=True)
+              for k in ("mean", "scale", "quat", "opacity", "sh")]
+    steps = max(args.steps, 20)
+    out = {"workload": f"{g.n} Gaussians SH3 on a 100 m city patch, {cam.width}x{cam.height} at 75 m / -45 deg, "
+                       "loss sum(w * I), torch.autograd.Function"}
+    for store in (False, True):
+        st = RasterSettings(cam, store_state=store)
+        for _ in range(3):
+            for leaf in leaves:
+                leaf.grad = None
+            (rasterize(*leaves, st) * w).sum().backward()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for leaf in leaves:
+                leaf.grad = None
+            (rasterize(*leaves, st) * w).sum().backward()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        hb = held_bytes(st, dg)
+        out["stored" if store else "recompute"] = {
+            "ms_per_step": round(ms, 4), "mpix_per_s": round(cam.width * cam.height / (ms * 1e-3) / 1e6, 1),
+            "state_bytes_held": hb["state"], "view_buffer_bytes": hb["frame"]}
+        torch.cuda.empty_cache()
+    f = raster.Frame(g.n, g.sh_degree, cam)
+    f.ensure_capacity(dg)
+
+    def plain():
+        f.project(dg)
+        f.bin_sort()
+        f.render_fwd()
+        f.render_bwd(dg, w)
+
+    for _ in range(3):
+        plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plain()
+    torch.cuda.synchronize()
+    out["plain_calls_ms_per_step"] = round((time.perf_counter() - t0) / steps * 1e3, 4)
+    out["steps"] = steps
+    return out
+
+
 def _percentiles(lat):
     import numpy as np
     a = np.asarray(lat)
@@ -679,9 +782,10 @@ def bench_serving(args, torch, scenes, raster):
         sv.close()
         return res, wall, info
 
-    def run_plain(trace):
+    def run_plain(trace, nw):
         frames = {}
         res = []
+        t_first = None
         t0 = time.perf_counter()
         for ta, cam in trace:
             now = time.perf_counter() - t0
@@ -703,30 +807,34 @@ def bench_serving(args, torch, scenes, raster):
                 f.ensure_capacity(dg)
                 f.render_fwd()
                 torch.cuda.synchronize()
+            if len(res) == nw:
+                t_first = arrive
             res.append(time.perf_counter() - arrive)
-        return res, time.perf_counter() - t0
+        t_end = time.perf_counter()
+        return res, t_end - t0, t_end - (t_first if t_first is not None else t0)
 
     out = {"workload": f"merged scene {n_total} Gaussians ({args.serve_grid}x{args.serve_grid} cells, SH3), "
                        "requests uniform over {640x480, 1280x720, 1920x1080, 3840x2160}, 80-200 m, pitch -90..-30 deg",
            "rates": []}
     for k, rate in enumerate(args.serve_rates):
-        n = args.serve_requests
-        trace = scenes.serve_trace(n + 30, rate, seed=500 + k, extent_m=ext)
-        mpix = sum(c.width * c.height for _, c in trace[30:]) / 1e6
-        row = {"rate_hz": rate, "requests": n}
+        n, nw = args.serve_requests, args.serve_warmup
+        trace = scenes.serve_trace(n + nw, rate, seed=500 + k, extent_m=ext)
+        mpix = sum(c.width * c.height for _, c in trace[nw:]) / 1e6
+        row = {"rate_hz": rate, "requests": n, "warmup": nw}
         for name, kw in (("batched", dict(max_views=8, pipelines=2)), ("unbatched", dict(max_views=1, pipelines=1))):
             res, wall, info = run_server(trace, **kw)
-            lat = [r["latency_ms"] for r in res[30:]]
+            lat = [r["latency_ms"] for r in res[nw:]]
             p50, p99 = _percentiles(lat)
-            span = (max(r["t_done_ns"] for r in res[30:]) - min(r["t_arrive_ns"] for r in res[30:])) * 1e-9
+            span = (max(r["t_done_ns"] for r in res[nw:]) - min(r["t_arrive_ns"] for r in res[nw:])) * 1e-9
             row[name] = {"p50_ms": p50, "p99_ms": p99, "frames_per_s": round(n / span, 1),
                          "mpix_per_s": round(mpix / span, 1), "batches": info["batches"],
                          "max_batch_views": info["max_batch_views"], "requeues": info["requeues"]}
             print(f"[bench] serving {rate} req/s {name}: p50 {p50} ms p99 {p99} ms", file=sys.stderr, flush=True)
-        lat, wall = run_plain(trace)
-        lat = [x * 1e3 for x in lat[30:]]
+        lat, wall, span = run_plain(trace, nw)
+        lat = [x * 1e3 for x in lat[nw:]]
         p50, p99 = _percentiles(lat)
-        row["plain_fifo"] = {"p50_ms": p50, "p99_ms": p99}
+        row["plain_fifo"] = {"p50_ms": p50, "p99_ms": p99, "frames_per_s": round(n / span, 1),
+                             "mpix_per_s": round(mpix / span, 1)}
         print(f"[bench] serving {rate} req/s plain: p50 {p50} ms p99 {p99} ms", file=sys.stderr, flush=True)
         out["rates"].append(row)
     return out
@@ -794,15 +902,16 @@ def main():
     value = npix / (ms * 1e-3) / 1e6
 
     # distribution of whole-step times (an event pair around every step)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(max(args.steps, 50))]
     for a, b in evs:
         a.record()
         step()
         b.record()
     torch.cuda.synchronize()
     st = np.array([a.elapsed_time(b) for a, b in evs])
-    step_dist = {"p10": round(float(np.percentile(st, 10)), 4), "median": round(float(np.median(st)), 4),
-                 "p90": round(float(np.percentile(st, 90)), 4)}
+    step_dist = {"samples": int(st.size), "p10": round(float(np.percentile(st, 10)), 4),
+                 "median": round(float(np.median(st)), 4), "p90": round(float(np.percentile(st, 90)), 4)}
     graph = plain_graph(torch, frame, step, args.steps, npix)
 
     if args.copy_calib > 0:
@@ -816,23 +925,45 @@ def main():
 
     stats = frame.stats()
     dom_ms = dprof[dom][0] / dprof[dom][1]
-    if dom == "render_bwd":
-        work = stats["blended"] * BWD_OPS_BLEND
-    elif dom == "render_fwd":
-        work = stats["support"] * FWD_OPS_SUPPORT + stats["blended"] * FWD_OPS_BLEND
-    else:
-        work = None
-    roof = None
     # measured HBM bytes per launch (counter summary), only for the workload
     # and kernel sources it was taken on
     default_cell = (args.n == 1_000_000 and args.width == 1920 and args.height == 1080 and tuple(args.tile) == (16, 16))
-    traffic = traffic_record(dom) if default_cell else None
-    if work is not None:
-        achieved = work / (dom_ms * 1e-3) / 1e12     # T lane-ops/s
+    K = (g.sh_degree + 1) ** 2
+    tile_bits = max(int(frame.n_tiles - 1).bit_length(), 1)
+    model = work_model(stats, P, g.n, K, npix, frame.n_tiles, tile_bits)
+    roof = None
+    if dom in ("render_bwd", "render_fwd"):
+        key = "a6_render_bwd" if dom == "render_bwd" else "a5_render_fwd"
+        work = model[key]["slots"]
+        minimal = (stats["blended"] * BWD_OPS_BLEND if dom == "render_bwd"
+                   else stats["support"] * FWD_OPS_SUPPORT + stats["blended"] * FWD_OPS_BLEND)
+        achieved = work / (dom_ms * 1e-3) / 1e12     # T slots/s
         peak = VALU_PEAK_GOPS / 1e3
         roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "Tlane-op/s", "frac": round(achieved / peak, 4), "traffic": traffic,
-                "work_lane_ops": int(work), "avg_ms": round(dom_ms, 4)}
+                "unit": "Tlane-op/s", "frac": round(achieved / peak, 4),
+                "traffic": traffic_record(dom) if default_cell else None,
+                "work_lane_ops": int(work), "avg_ms": round(dom_ms, 4),
+                "work_model": f"E*{MODEL_BWD_EVAL if dom == 'render_bwd' else MODEL_FWD_EVAL} + blended*"
+                              f"{MODEL_BWD_BLEND if dom == 'render_bwd' else MODEL_FWD_BLEND} slots "
+                              f"(E = {stats['evaluated']} evaluations, {stats['blended']} blended pairs)",
+                "minimal_count": {"work_lane_ops": int(minimal),
+                                  "frac": round(minimal / (dom_ms * 1e-3) / 1e12 / peak, 4)}}
+    # per-stage and whole-step fractions of the same work model: the ideal
+    # time of each stage against its measured (event-bracketed) time, and
+    # the sum of the ideal times against the whole step
+    stage_of = {"a1_project": ["project"], "a2_scan_emit": ["scan_emit"], "a3_sort": ["sort"], "a4_ranges": [],
+                "a5_render_fwd": ["render_fwd"], "a6_render_bwd": ["pair_zero", "render_bwd", "pair_gather"],
+                "a7_project_bwd": ["project_bwd"]}
+    ideal_us = sum(v["ideal_us"] for v in model.values())
+    for k, v in model.items():
+        t = sum(stages.get(x, 0.0) for x in stage_of[k]) * 1e3
+        v["measured_us"] = round(t, 2) if t else None
+        v["frac"] = round(v["ideal_us"] / t, 3) if t else None
+    step_roof = {"ideal_us": round(ideal_us, 1), "measured_us": round(ms * 1e3, 1),
+                 "frac": round(ideal_us / (ms * 1e3), 4),
+                 "rule": "sum over stages of max(algorithmic bytes / 8 TB/s, ALU slots / 39.32 T/s), "
+                         "over the measured step",
+                 "stages": model}
 
     out = {
         "metric": "fwd+bwd Mpix/s at 1M Gaussians 1080p; serve p50/p99 ms vs plain path",
@@ -852,6 +983,7 @@ def main():
                    "gaussians": g.n, "width": cam.width, "height": cam.height, "pairs": P,
                    "blend_counts": stats, "stage_ms": stages},
         "roofline": roof,
+        "step_roofline": step_roof,
         "step_ms": step_dist,
         "graph": graph,
         "environment": environment(torch),
@@ -868,6 +1000,10 @@ def main():
         out["appearance"] = bench_appearance(args, torch, N)
         print("[bench] partitioning", file=sys.stderr, flush=True)
         out["partition"] = bench_partition(args, torch, N)
+    if not args.no_autograd:
+        print("[bench] autograd form", file=sys.stderr, flush=True)
+        out["autograd"] = bench_autograd(args, torch, scenes, raster)
+        torch.cuda.empty_cache()
     if not args.no_forms:
         del frame, dg
         torch.cuda.empty_cache()
@@ -875,6 +1011,15 @@ def main():
         torch.cuda.empty_cache()
         serving = bench_serving(args, torch, scenes, raster)
         out["serving"] = serving
+        wins = [r["rate_hz"] for r in serving["rates"]
+                if r["batched"]["p99_ms"] < r["unbatched"]["p99_ms"] and r["batched"]["p50_ms"] <= r["unbatched"]["p50_ms"]]
+        serving["batching_beats_one_view_batches_at_hz"] = wins
+        serving["summary_p50_p99_ms"] = [
+            {"rate_hz": r["rate_hz"], "batched": [r["batched"]["p50_ms"], r["batched"]["p99_ms"]],
+             "unbatched": [r["unbatched"]["p50_ms"], r["unbatched"]["p99_ms"]],
+             "plain_fifo": [r["plain_fifo"]["p50_ms"], r["plain_fifo"]["p99_ms"]],
+             "frames_per_s": [r["batched"]["frames_per_s"], r["unbatched"]["frames_per_s"],
+                              r["plain_fifo"]["frames_per_s"]]} for r in serving["rates"]]
         r0 = serving["rates"][0]
         out["serve_p50_p99_ms"] = {"rate_hz": r0["rate_hz"], "batched": [r0["batched"]["p50_ms"], r0["batched"]["p99_ms"]],
                                    "plain_fifo": [r0["plain_fifo"]["p50_ms"], r0["plain_fifo"]["p99_ms"]]}

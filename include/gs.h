@@ -242,9 +242,9 @@ gs_status gs_sort_pairs(uint64_t *keys, uint32_t *vals, const uint32_t *count, i
                         int32_t key_bits, void *ws, size_t ws_bytes, gs_stream stream);
 
 /* ---- Training loss ---------------------------------------------------------
- * Eq. 1 (section 4.2): the loss of a rendered image I^r against its ground
+ * Eq. 1 (section 3): the loss of a rendered image I^r against its ground
  * truth I is (1 - lambda) L1(I^r, I) + lambda D-SSIM(I^r, I); Eq. 3
- * (section 4.3), with decoupled appearance modelling, takes the L1 term on
+ * (section 4.2), with decoupled appearance modelling, takes the L1 term on
  * the appearance-adjusted image I^a instead and keeps D-SSIM on I^r.  D-SSIM
  * follows 3DGS (section 5.1): 1 - SSIM, SSIM averaged over every pixel and
  * channel with an 11 x 11 Gaussian window of sigma 1.5, C1 = 0.01^2,

@@ -4,9 +4,9 @@ Only `tests/`, `__graft_entry__.smoke()` and the benchmark's `cpu_baseline`
 leg may import this module; the GPU loss kernel shares nothing with it.
 
 What it computes (VastGaussian, arXiv 2402.17427): the per-image loss of
-Eq. 1 (section 4.2), a (1 - lambda) weighted L1 term plus a lambda weighted
+Eq. 1 (section 3), a (1 - lambda) weighted L1 term plus a lambda weighted
 D-SSIM term between the rendered image and its ground truth, and its
-Eq. 3 form (section 4.3), where the L1 term is taken on the
+Eq. 3 form (section 4.2), where the L1 term is taken on the
 appearance-adjusted image I^a while D-SSIM stays on the rendered image I^r.
 The paper takes D-SSIM from 3DGS and fixes no constants; the readings used
 here (the 3DGS ones) are:

@@ -1,9 +1,9 @@
 // The training loss of one image and its gradient, fused in one pass.
 //
 // VastGaussian (arXiv 2402.17427) optimises each cell's Gaussians against
-// its training images with the loss of Eq. 1 (section 4.2):
+// its training images with the loss of Eq. 1 (section 3):
 // (1 - lambda) L1(I^r, I) + lambda D-SSIM(I^r, I), and, with decoupled
-// appearance modelling, Eq. 3 (section 4.3): the L1 term on the adjusted
+// appearance modelling, Eq. 3 (section 4.2): the L1 term on the adjusted
 // image I^a and the D-SSIM term on the rendered I^r.  D-SSIM comes from
 // 3DGS: 1 - SSIM, SSIM averaged over every pixel and channel, with an
 // 11 x 11 Gaussian window (sigma 1.5), C1 = 0.01^2, C2 = 0.03^2, and window

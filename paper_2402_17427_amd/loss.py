@@ -1,8 +1,8 @@
 """Torch-facing wrapper of the fused training loss (gs_loss in gs.h).
 
-Eq. 1 of VastGaussian (arXiv 2402.17427, section 4.2): (1 - lambda) L1 +
+Eq. 1 of VastGaussian (arXiv 2402.17427, section 3): (1 - lambda) L1 +
 lambda D-SSIM between a rendered image and its ground truth, or Eq. 3
-(section 4.3) with the L1 term on the appearance-adjusted image.  The
+(section 4.2) with the L1 term on the appearance-adjusted image.  The
 value and the image gradients come from the HIP kernels behind libgsmi.so;
 this module only sizes buffers and passes pointers and the stream.
 """

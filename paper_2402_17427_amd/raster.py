@@ -152,11 +152,25 @@ class Frame:
         b.pair_capacity = self.capacity
         return b
 
-    def c_grads(self) -> N.gs_grads:
+    def c_grads(self, out: dict | None = None) -> N.gs_grads:
+        """Gradient planes: the frame's own, or the caller's `out` (mean,
+        scale, quat, opacity, sh: contiguous float32 [P][n] / [n])."""
         g = N.gs_grads()
-        g.ld = max(self.n, 1)
-        g.mean, g.scale, g.quat = _ptr(self.g_mean), _ptr(self.g_scale), _ptr(self.g_quat)
-        g.opacity, g.sh, g.grad2d = _ptr(self.g_opacity), _ptr(self.g_sh), _ptr(self.grad2d)
+        if out is None:
+            g.ld = max(self.n, 1)
+            g.mean, g.scale, g.quat = _ptr(self.g_mean), _ptr(self.g_scale), _ptr(self.g_quat)
+            g.opacity, g.sh = _ptr(self.g_opacity), _ptr(self.g_sh)
+        else:
+            K = SH_DIM[self.sh_degree]
+            for k, rows in (("mean", 3), ("scale", 3), ("quat", 4), ("sh", 3 * K)):
+                t = out[k]
+                assert t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == (rows, self.n), k
+            o = out["opacity"]
+            assert o.dtype == torch.float32 and o.is_contiguous() and tuple(o.shape) == (self.n,)
+            g.ld = max(self.n, 1)
+            g.mean, g.scale, g.quat = _ptr(out["mean"]), _ptr(out["scale"]), _ptr(out["quat"])
+            g.opacity, g.sh = _ptr(o), _ptr(out["sh"])
+        g.grad2d = _ptr(self.grad2d)
         return g
 
     # -- stages -------------------------------------------------------------
@@ -174,12 +188,12 @@ class Frame:
                C.byref(self.c_opts), _ptr(self.image), _ptr(self.final_T), _ptr(self.n_contrib),
                C.c_void_p(stream_handle(stream)))
 
-    def render_bwd(self, g: DeviceGaussians, dimg: torch.Tensor, stream=None):
+    def render_bwd(self, g: DeviceGaussians, dimg: torch.Tensor, stream=None, out: dict | None = None):
         assert self.has_grads, "frame was created without gradient buffers"
         assert dimg.shape == (3, self.H, self.W) and dimg.dtype == torch.float32 and dimg.is_contiguous()
         N.call("gs_render_bwd", C.byref(g.c_struct()), C.byref(self.c_cam), C.byref(self.c_opts),
                C.byref(self.c_proj()), C.byref(self.c_bins()), _ptr(self.final_T), _ptr(self.n_contrib),
-               _ptr(dimg), C.byref(self.c_grads()), _ptr(self.bwd_ws), self.bwd_ws.numel() * 4,
+               _ptr(dimg), C.byref(self.c_grads(out)), _ptr(self.bwd_ws), self.bwd_ws.numel() * 4,
                C.c_void_p(stream_handle(stream)))
 
     def stats(self, stream=None) -> dict:
@@ -201,11 +215,12 @@ class Frame:
                C.byref(self.c_opts), _ptr(self.image), _ptr(self.final_T), _ptr(self.n_contrib), _ptr(state),
                state.numel() * state.element_size(), C.c_void_p(stream_handle(stream)))
 
-    def render_bwd_stored(self, g: DeviceGaussians, dimg: torch.Tensor, state: torch.Tensor, stream=None):
+    def render_bwd_stored(self, g: DeviceGaussians, dimg: torch.Tensor, state: torch.Tensor, stream=None,
+                          out: dict | None = None):
         assert dimg.shape == (3, self.H, self.W) and dimg.dtype == torch.float32 and dimg.is_contiguous()
         N.call("gs_render_bwd_stored", C.byref(g.c_struct()), C.byref(self.c_cam), C.byref(self.c_opts),
                C.byref(self.c_proj()), C.byref(self.c_bins()), _ptr(self.final_T), _ptr(self.n_contrib),
-               _ptr(state), state.numel() * state.element_size(), _ptr(dimg), C.byref(self.c_grads()),
+               _ptr(state), state.numel() * state.element_size(), _ptr(dimg), C.byref(self.c_grads(out)),
                _ptr(self.bwd_ws), self.bwd_ws.numel() * 4, C.c_void_p(stream_handle(stream)))
 
     def forward(self, g: DeviceGaussians, stream=None):

@@ -11,7 +11,8 @@ torch = pytest.importorskip("torch")
 
 import oracle
 from gen import scenes
-from paper_2402_17427_amd.autograd import RasterSettings, rasterize
+from paper_2402_17427_amd import raster
+from paper_2402_17427_amd.autograd import RasterSettings, held_bytes, rasterize
 
 from gpu_util import grad_close, image_close
 import fd_util as F
@@ -69,24 +70,23 @@ def test_autograd_gradient_matches_central_differences_on_c3_subset():
 def test_recompute_and_stored_state_backward_agree_and_report_cost():
     """C3 (200k Gaussians, 800x800): the backward that recomputes the blend
     state and the one that reads it back from the forward give the same
-    gradients; their time and the state's memory are reported."""
+    gradients; the stored variant holds its (alpha, T) state between
+    forward and backward (8 bytes per evaluated entry and pixel of each
+    tile's list), the recomputing one holds none.  Time and memory are
+    printed (the benchmark reports them)."""
     _case("recompute vs stored")
     g, cam = scenes.config3()
     w = torch.as_tensor(scenes.grad_image(cam, 4, "uniform")).cuda()
+    dg = raster.DeviceGaussians.from_host(g)
     res = {}
     for store in (False, True):
         st = RasterSettings(cam, store_state=store)
         leaves = _leaves(g)
         (rasterize(*leaves, st) * w).sum().backward()
         grads = {k: leaf.grad.cpu().numpy() for k, leaf in zip(PARAMS, leaves)}
-        torch.cuda.synchronize()
-        m0 = torch.cuda.memory_allocated()
-        img = rasterize(*leaves, st)
-        torch.cuda.synchronize()
-        held = torch.cuda.memory_allocated() - m0
-        loss = (img * w).sum()
-        loss.backward()
-        del img, loss
+        held = held_bytes(st, dg)
+        for leaf in leaves:
+            leaf.grad = None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(5):
@@ -95,9 +95,49 @@ def test_recompute_and_stored_state_backward_agree_and_report_cost():
         res[store] = (grads, (time.perf_counter() - t0) / 5, held)
     for k in PARAMS:
         grad_close(f"stored vs recompute {k}", res[True][0][k], res[False][0][k])
+    f = raster.Frame(dg.n, dg.sh_degree, cam)
+    f.ensure_capacity(dg)
+    assert res[False][2]["state"] == 0
+    assert res[True][2]["state"] >= f.state_bytes() > 0
     print(f"[recompute-vs-stored] autograd fwd+bwd per view: recompute {res[False][1] * 1e3:.2f} ms, "
-          f"stored {res[True][1] * 1e3:.2f} ms; device memory held by the forward: recompute "
-          f"{res[False][2] / 2**20:.1f} MiB, stored {res[True][2] / 2**20:.1f} MiB")
+          f"stored {res[True][1] * 1e3:.2f} ms; state held between forward and backward: recompute 0 MiB, "
+          f"stored {res[True][2]['state'] / 2**20:.1f} MiB (view buffers {res[False][2]['frame'] / 2**20:.1f} MiB)")
+
+
+def test_autograd_steady_state_makes_no_host_sync_and_keeps_views_apart():
+    """After the first step on a view shape, a forward + backward makes no
+    synchronising call (PyTorch's sync debug mode raises on one), and two
+    views rendered before either backward keep separate buffers."""
+    _case("autograd steady state")
+    g, cam = scenes.small_city(n=20_000, seed=11, width=200, height=150)
+    leaves = _leaves(g)
+    st = RasterSettings(cam)
+    w = torch.as_tensor(scenes.grad_image(cam, 3, "normal")).cuda()
+    (rasterize(*leaves, st) * w).sum().backward()
+    ref = {k: leaf.grad.clone() for k, leaf in zip(PARAMS, leaves)}
+    torch.cuda.synchronize()
+    for leaf in leaves:
+        leaf.grad = None
+    torch.cuda.set_sync_debug_mode("error")
+    try:
+        for _ in range(3):
+            for leaf in leaves:
+                leaf.grad = None
+            (rasterize(*leaves, st) * w).sum().backward()
+    finally:
+        torch.cuda.set_sync_debug_mode("default")
+    for k, leaf in zip(PARAMS, leaves):
+        grad_close(f"steady {k}", leaf.grad.cpu().numpy(), ref[k].cpu().numpy())
+    # two forwards before the backwards: the second may not overwrite the first
+    for leaf in leaves:
+        leaf.grad = None
+    a = rasterize(*leaves, st)
+    b = rasterize(*leaves, st)
+    assert a.data_ptr() != b.data_ptr()
+    (a * w).sum().backward()
+    (b * 0).sum().backward()
+    for k, leaf in zip(PARAMS, leaves):
+        grad_close(f"two views {k}", leaf.grad.cpu().numpy(), ref[k].cpu().numpy())
 
 
 def test_adam_steps_reduce_l1_on_config1():

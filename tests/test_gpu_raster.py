@@ -29,7 +29,10 @@ def _case(name):
 
 @pytest.mark.parametrize("count,key_bits,seed", [(0, 40, 0), (1, 40, 1), (4095, 45, 2), (4096, 45, 3),
                                                  (4097, 38, 4), (100_003, 45, 5), (250_000, 64, 6),
-                                                 (70_000, 8, 7), (33_333, 13, 8)])
+                                                 (70_000, 8, 7), (33_333, 13, 8),
+                                                 # more partitions than the onesweep grid holds: the
+                                                 # partitions are handed out by the atomic counter
+                                                 (9_000_000, 64, 9), (9_500_001, 45, 10)])
 def test_sort_pairs_equals_stable_argsort(count, key_bits, seed):
     _case(f"sort count={count} bits={key_bits}")
     rng = np.random.default_rng(seed)
@@ -65,7 +68,43 @@ def _scene(name):
         # the whole city in a 40x30 image: thousands of Gaussians per tile,
         # so tile runs are longer than the in-LDS per-tile sort handles
         return scenes.small_city(n=20_000, seed=13, width=40, height=30)
+    if name == "city_capped":
+        return _capped_city()
     raise KeyError(name)
+
+
+# thousands of Gaussians cover each pixel of the 40x30 image, so each pixel
+# takes far more blend decisions and more of them lie near a threshold
+FLAGGED_FRAC = {"city_dense": 1e-2}
+
+
+def _capped_city():
+    """The ragged city with 40 visible Gaussians made nearly opaque
+    (opacity 0.995-0.9999) and wide (scale x 12-20): alpha takes the 0.99 cap
+    at the pixels nearest their centres and not in the ring around them."""
+    g, cam = scenes.small_city(n=20_000, seed=11, width=200, height=150)
+    pr = oracle.project(g, cam)
+    rng = np.random.default_rng(31)
+    vis = np.nonzero(pr["valid"])[0]
+    i = rng.choice(vis, 40, replace=False)
+    g.opacity[i] = rng.uniform(0.995, 0.9999, i.size).astype(np.float32)
+    g.scale[:, i] *= rng.uniform(12.0, 20.0, (1, i.size)).astype(np.float32)
+    return g, cam
+
+
+def _capped_pixels(g, cam):
+    """Pixels where some Gaussian's unclamped alpha exceeds 0.99 (plain NumPy
+    from the oracle's FP64 projection)."""
+    pr = oracle.project(g, cam)
+    hi = np.nonzero((pr["valid"] != 0) & (g.opacity > 0.99))[0]
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    count = 0
+    for i in hi:
+        u, v = pr["uv"][i]
+        A, B, C = pr["conic"][i]
+        dx, dy = xs + 0.5 - u, ys + 0.5 - v
+        count += int((g.opacity[i] * np.exp(-0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy) > 0.99).sum())
+    return count
 
 
 @pytest.mark.parametrize("name", ["config1", "city_ragged"])
@@ -121,7 +160,7 @@ def test_bins_match_oracle_bit_exact(name, tile):
 
 # --------------------------------------------------------------- forward --
 
-@pytest.mark.parametrize("name", ["config1", "city_ragged", "city_white", "city_dense"])
+@pytest.mark.parametrize("name", ["config1", "city_ragged", "city_white", "city_dense", "city_capped"])
 def test_forward_image_matches_oracle(name):
     _case(f"forward {name}")
     g, cam = _scene(name)
@@ -131,7 +170,8 @@ def test_forward_image_matches_oracle(name):
     ref = oracle.render(g, cam)
     img = f.image.cpu().numpy()
     fT = f.final_T.cpu().numpy()
-    worst, nflag = image_close(name, img, ref["image"], ref["flags"])
+    worst, nflag, _ = image_close(name, img, ref["image"], ref["flags"],
+                                  max_flagged_frac=FLAGGED_FRAC.get(name, 1e-3))
     ok = ref["flags"] == 0
     assert np.abs(fT - ref["final_T"])[ok].max() <= 1e-4
     # n_contrib points at the oracle's last blended Gaussian
@@ -184,13 +224,13 @@ def test_forward_compositing_invariants_on_gpu():
 
 # -------------------------------------------------------------- backward --
 
-def _backward_case(g, cam, dimg_seed=5):
+def _backward_case(g, cam, dimg_seed=5, tile=(16, 16)):
     """Gradient of L = sum w . I with seeded w ~ N(0, 1), except w = 0 at the
     pixels the oracle flags as ambiguous (there FP32 and FP64 may take a
     different discontinuous decision; with w = 0 the pixel contributes
     nothing to either gradient)."""
     dg = raster.DeviceGaussians.from_host(g)
-    f = raster.render(dg, cam)
+    f = raster.render(dg, cam, tile=tile)
     flags = oracle.render(g, cam)["flags"]
     dimg = scenes.grad_image(cam, dimg_seed, "normal")
     dimg[:, flags != 0] = 0.0
@@ -202,11 +242,17 @@ def _backward_case(g, cam, dimg_seed=5):
     return out, rb, np.ones(g.n, bool)
 
 
-@pytest.mark.parametrize("name", ["config1", "city_ragged"])
-def test_backward_matches_oracle_gradient(name):
-    _case(f"backward {name}")
+TILES = [(16, 16), (8, 8), (16, 8), (32, 8), (32, 16), (32, 32)]
+
+
+@pytest.mark.parametrize("name,tile", [("config1", (16, 16)), ("city_ragged", (16, 16))] +
+                         [("city_capped", t) for t in TILES])
+def test_backward_matches_oracle_gradient(name, tile):
+    _case(f"backward {name} tile={tile}")
     g, cam = _scene(name)
-    out, rb, keep = _backward_case(g, cam)
+    if name == "city_capped":
+        assert _capped_pixels(g, cam) >= 40
+    out, rb, keep = _backward_case(g, cam, tile=tile)
     g2 = out["grad2d"]
     names = ["du", "dv", "dA", "dB", "dC", "dopacity", "dr", "dg", "db"]
     for c in range(9):
@@ -281,12 +327,11 @@ def test_full_size_cell_sampled_pixels_match_oracle():
     g, cam = scenes.config2()
     dg = raster.DeviceGaussians.from_host(g)
     f = raster.render(dg, cam)
-    px, py = scenes.pixel_sample(cam.width, cam.height, stride=120)
+    px, py = scenes.pixel_sample(cam.width, cam.height, stride=60)
     ref = oracle.render(g, cam, px, py)
     img = f.image.cpu().numpy()[:, py, px]
     ok = ref["flags"] == 0
-    assert ok.mean() > 0.9
-    assert np.abs(img.T - ref["image"])[ok].max() <= 1e-4
+    image_close("1M 1080p sampled", img, ref["image"].T, ref["flags"])
     # gradient of L = sum over the sampled pixels of w . I
     rng = np.random.default_rng(9)
     dimg = np.zeros((3, cam.height, cam.width), np.float32)
@@ -294,8 +339,12 @@ def test_full_size_cell_sampled_pixels_match_oracle():
     gr = raster.render_backward(f, dg, torch.as_tensor(dimg).cuda())
     rb = oracle.backward(g, cam, dimg, px[ok], py[ok])
     live = np.abs(rb["g2d"]).sum(1) > 0
-    assert live.sum() > 50
-    for k in ("mean", "opacity", "sh"):
+    assert live.sum() > 200
+    g2 = gr["grad2d"].cpu().numpy()
+    names = ["du", "dv", "dA", "dB", "dC", "dopacity", "dr", "dg", "db"]
+    for c in range(9):
+        grad_close(names[c], g2[c][live], rb["g2d"][live, c])
+    for k in ("mean", "scale", "quat", "opacity", "sh"):
         grad_close(k, gr[k].cpu().numpy()[..., live], rb[k][..., live])
 
 
