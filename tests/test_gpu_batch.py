@@ -203,7 +203,7 @@ def test_batch_above_the_onesweep_grid_matches_plain_path():
     torch.cuda.synchronize()
     st, pairs = b.status()
     print(f"[case] {pairs} pairs", flush=True)
-    assert st == 0 and pairs > 2048 * 4096
+    assert st == 0 and pairs[0] > 2048 * 4096
     loss = b.loss.cpu().numpy()
     for c, (img, l1, gr) in enumerate(ref):
         np.testing.assert_array_equal(b.image(c).cpu().numpy(), img, err_msg=f"cell {c}")

@@ -327,7 +327,7 @@ def test_full_size_cell_sampled_pixels_match_oracle():
     g, cam = scenes.config2()
     dg = raster.DeviceGaussians.from_host(g)
     f = raster.render(dg, cam)
-    px, py = scenes.pixel_sample(cam.width, cam.height, stride=60)
+    px, py = scenes.pixel_sample(cam.width, cam.height, stride=30)
     ref = oracle.render(g, cam, px, py)
     img = f.image.cpu().numpy()[:, py, px]
     ok = ref["flags"] == 0
