@@ -35,8 +35,11 @@ def sources():
     return out
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
+def build(verbose: bool = False, defines=(), out: str | None = None) -> str:
+    """Compile the library; `defines` are extra -D options (tuning
+    constants), `out` another output path (default libgsmi.so here)."""
+    lib = out or LIB
+    tmp = lib + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-ffp-contract=off", "-munsafe-fp-atomics",
            # atomics are issued from one lane where it matters; the
@@ -45,14 +48,14 @@ def build(verbose: bool = False) -> str:
            "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
-           "-I", os.path.join(HERE, "..", "include"), "-o", tmp] + sources() + ["-lpthread"]
+           "-I", os.path.join(HERE, "..", "include"), "-o", tmp] + [f"-D{d}" for d in defines] + sources() + ["-lpthread"]
     if verbose:
         print(" ".join(cmd))
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed ({r.returncode}):\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -1,0 +1,163 @@
+// What the blend kernels share: the cell layout of a tile, the exact cull
+// of a staged Gaussian against the cells, and the bit transpose that turns
+// per-Gaussian cell masks into per-cell walk masks.
+//
+// Layout: a tile of TW x TH pixels is cut into cells of CW x CH pixels, one
+// cell per lane, numbered row-major over the tile; a wave owns 64
+// consecutive cells (whole cell rows).  Every lane walks, in list order, only
+// the staged Gaussians whose support (alpha >= 1/255, section 3's skip rule)
+// reaches a pixel centre of its cell, so the lanes of a wave walk different
+// Gaussians in the same instructions.
+#pragma once
+
+#include "gs_device.h"
+
+namespace gs {
+
+template <int TW_, int TH_, int CW_, int CH_>
+struct Cells {
+    static constexpr int TW = TW_, TH = TH_, CW = CW_, CH = CH_;
+    static constexpr int NT = TW * TH;            // pixels of the tile
+    static constexpr int CPR = TW / CW;           // cells per row
+    static constexpr int NCELL = CPR * (TH / CH);
+    static constexpr int WAVES = NCELL / kWave;   // waves of a workgroup
+    static constexpr int NP = CW * CH;            // pixels per lane
+    static constexpr int ROWS_W = kWave / CPR;    // cell rows per wave
+    static constexpr int PXROWS_W = ROWS_W * CH;  // pixel rows per wave
+    static constexpr int CW_SHIFT = CW == 2 ? 1 : 0;
+    static_assert(NCELL % kWave == 0 && kWave % CPR == 0, "cell layout");
+    static_assert(CW <= 2 && CH <= 2 && CPR <= 16, "cell layout");
+};
+
+// The cell layout used for each supported tile shape: 2x2 cells, except
+// 8x8 tiles (1x1, 64 lanes) and 16x8 tiles (2x1, 64 lanes).
+template <int TW, int TH> struct CellsFor { using L = Cells<TW, TH, 2, 2>; };
+template <> struct CellsFor<8, 8> { using L = Cells<8, 8, 1, 1>; };
+template <> struct CellsFor<16, 8> { using L = Cells<16, 8, 2, 1>; };
+
+// 64-bit mask of the cells of one wave that a staged Gaussian can reach:
+// bit c is set when some pixel centre of cell c (c = row * CPR + column
+// within the wave's cells) may have alpha >= 1/255.  For each pixel row
+// of the wave the support is the chord of the ellipse
+//   ca dx^2 + cb dx dy + cc dy^2 >= thr
+// (base-2 exponent of the Gaussian, thr = -log2(255 o); ca, cc < 0) at the
+// row's centre height: with dy fixed the exponent is a concave quadratic in
+// dx, whose roots bound the chord.  The threshold is lowered by a margin
+// (2e-3 + 2e-4 |thr| in base-2 units, far above the FP32 error of the
+// exponent the blend evaluates) and the chord widened by 1e-3 px, so every
+// pixel the blend can find at or above 1/255 is covered; covering a few
+// more only costs evaluations that the blend then skips.  x0: the tile's
+// first pixel column, y0: the wave's first pixel row (image coordinates).
+template <class L>
+__device__ __forceinline__ uint64_t cell_mask(const Staged& g, int x0, int y0) {
+    const float ca = g.coef.x, cb = g.coef.y, cc = g.coef.z;
+    const float thm = g.col.w - (2e-3f + 2e-4f * fabsf(g.col.w));
+    const float ia = 0.5f * __builtin_amdgcn_rcpf(ca);        // 1 / (2 ca) < 0
+    const float ca4 = -4.0f * ca;
+    // pixel column p (tile-local) has offset dx = p - xs from the centre;
+    // the chord's ends are widened by 1e-3 px
+    const float xs = ((g.geo.x - (float)x0) + g.geo.y) - 0.5f;
+    const float xs_lo = xs - 1e-3f, xs_hi = xs + 1e-3f;
+    uint32_t lo = 0u, hi = 0u;
+#pragma unroll
+    for (int j = 0; j < L::PXROWS_W; ++j) {
+        const float dy = (((float)(y0 + j) + 0.5f) - g.geo.z) - g.geo.w;
+        const float b = cb * dy;
+        const float c = __builtin_fmaf(cc * dy, dy, -thm);
+        const float D = __builtin_fmaf(ca4, c, b * b);          // b^2 - 4 ca c
+        const float s = __builtin_amdgcn_sqrtf(fmaxf(D, 0.0f));   // ~1 ulp, covered by the margins
+        const float plo = __builtin_fmaf(s - b, ia, xs_lo);
+        const float phi = __builtin_fmaf(-s - b, ia, xs_hi);
+        // covered pixel columns, clamped to the tile before the conversion
+        const int c0 = (int)__builtin_ceilf(fminf(fmaxf(plo, -1.0f), (float)L::TW));
+        const int c1 = (int)__builtin_floorf(fminf(fmaxf(phi, -1.0f), (float)L::TW));
+        const bool ok = (D >= 0.0f) & (c0 <= c1) & (c1 >= 0) & (c0 < L::TW);
+        const int a0 = max(c0, 0) >> L::CW_SHIFT, a1 = min(c1, L::TW - 1) >> L::CW_SHIFT;
+        const uint32_t bits = ok ? ((2u << a1) - (1u << a0)) : 0u;
+        const int sh = (j / L::CH) * L::CPR;                    // the row's cells within the 64 bits
+        if (sh < 32) lo |= bits << sh;
+        else hi |= bits << (sh - 32);
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Lane exchanges used by the transpose (lane ^ s).
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v, int s) {
+    switch (s) {
+    case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
+    case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
+    case 4: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);              // xor 4 in 32 lanes
+    case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, true);  // row_ror:8
+    case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);             // xor 16 in 32 lanes
+    default: return (uint32_t)__shfl_xor((int)v, 32, kWave);
+    }
+}
+
+// Transpose of a 64 x 64 bit matrix held one row per lane: on entry lane k
+// holds row k (bit c = element (k, c)), on return lane c holds column c (bit
+// k = element (k, c)).  Recursive block swap: at each size s the lanes k and
+// k ^ s exchange the off-diagonal s x s blocks.  Must be called by all 64
+// lanes of the wave.
+__device__ __forceinline__ uint64_t transpose64(uint64_t x, int lane) {
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    {   // s = 32: the lower lanes take the partner's low word as their high word
+        const bool up = (lane & 32) != 0;
+        const uint32_t r = xor_lane(up ? lo : hi, 32);
+        if (up) lo = r;
+        else hi = r;
+    }
+#define GS_TSTAGE(S, M0)                                                       \
+    {                                                                          \
+        const bool up = (lane & (S)) != 0;                                     \
+        const uint32_t keep = up ? ~(uint32_t)(M0) : (uint32_t)(M0);           \
+        const uint32_t rl = xor_lane(lo & ~keep, (S)), rh = xor_lane(hi & ~keep, (S)); \
+        lo = (lo & keep) | (up ? (rl >> (S)) : (rl << (S)));                   \
+        hi = (hi & keep) | (up ? (rh >> (S)) : (rh << (S)));                   \
+    }
+    GS_TSTAGE(16, 0x0000FFFFu)
+    GS_TSTAGE(8, 0x00FF00FFu)
+    GS_TSTAGE(4, 0x0F0F0F0Fu)
+    GS_TSTAGE(2, 0x33333333u)
+    GS_TSTAGE(1, 0x55555555u)
+#undef GS_TSTAGE
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// The staged record `k` (k < 1024) of an LDS array; the bound lets the byte
+// offset 48 k use the full-rate 24-bit multiply.
+__device__ __forceinline__ const Staged& staged_at(const Staged* s, int k) {
+    static_assert(sizeof(Staged) == 48, "staged record layout");
+    return *reinterpret_cast<const Staged*>(reinterpret_cast<const char*>(s) + ((unsigned)k & 0x3FFu) * 48u);
+}
+
+// Stage list entries b0 + j (j < nb <= PER * nthreads) of a tile into
+// LDS: each thread issues all of its value loads, then all of its record
+// loads, before the first wait, so a batch costs two memory latencies.
+template <int PER>
+__device__ __forceinline__ void stage_batch(Staged* s, const Rec* __restrict__ rec, const uint32_t* __restrict__ vals,
+                                            uint32_t b0, int nb, int tid, int nthreads, uint32_t* gid_out = nullptr) {
+    uint32_t v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = tid + q * nthreads;
+        v[q] = j < nb ? vals[b0 + (uint32_t)j] : 0u;
+    }
+    Rec r[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+        if (tid + q * nthreads < nb) r[q] = rec[v[q]];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = tid + q * nthreads;
+        if (j < nb) {
+            s[j] = stage_rec(r[q]);
+            if (gid_out) gid_out[j] = v[q];
+        }
+    }
+}
+
+// Index of the lowest / highest set bit of a non-zero 64-bit mask.
+__device__ __forceinline__ int low_bit(uint64_t m) { return (int)__builtin_ctzll(m); }
+__device__ __forceinline__ int high_bit(uint64_t m) { return 63 - (int)__builtin_clzll(m); }
+
+}  // namespace gs

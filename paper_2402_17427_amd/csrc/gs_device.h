@@ -123,8 +123,8 @@ __device__ __forceinline__ View view_at(const ViewTab& t, int v) { return t.dev 
 // Gaussian only, so the result does not depend on the tile size or origin,
 // and its error is a few ulp of the offset itself.  The conic is pre-scaled
 // so that exp2(ca dx^2 + cb dx dy + cc dy^2) = exp(power).  Forward and
-// backward stage the same values through stage_rec(), so both take
-// identical decisions.
+// backward stage the same values through stage_rec() and evaluate the
+// exponent with the same expression, so both take identical decisions.
 struct Staged {
     float4 geo;   // hi_u, lo_u, hi_v, lo_v
     float4 coef;  // ca, cb, cc, o
@@ -140,91 +140,11 @@ __device__ __forceinline__ Staged stage_rec(const Rec& r) {
     return s;
 }
 
-// Evaluate one staged Gaussian at pixel centre (x, y) (image coordinates).
-// Returns alpha (0 when the pair is skipped) and G = exp(power).
-struct Eval {
-    float dx, dy, G, alpha;
-    bool capped;
-};
-
-__device__ __forceinline__ Eval eval_pair(const Staged& s, float x, float y) {
-    Eval e;
-    e.dx = (x - s.geo.x) - s.geo.y;
-    e.dy = (y - s.geo.z) - s.geo.w;
-    const float p = __builtin_fmaf(s.coef.x, e.dx * e.dx, __builtin_fmaf(s.coef.z, e.dy * e.dy, s.coef.y * (e.dx * e.dy)));
-    e.G = __builtin_amdgcn_exp2f(p);
-    const float araw = s.coef.w * e.G;
-    e.capped = araw > kAlphaMax;
-    const float a = e.capped ? kAlphaMax : araw;
-    e.alpha = (p > 0.0f || a < kAlphaMin) ? 0.0f : a;
-    return e;
-}
-
-// Can the staged Gaussian reach alpha >= 1/255 at some point of the
-// rectangle [x0, x1] x [y0, y1] (image coordinates; the rectangle spanned by
-// a block's pixel centres)?  The base-2 exponent q(d) = ca dx^2 + cb dx dy +
-// cc dy^2 is a concave quadratic of the offset d with its maximum 0 at the
-// centre.  Along the segment from any point of the rectangle towards the
-// centre q does not decrease, so the maximum over the rectangle lies where
-// the rectangle faces the centre: on the x-face at X = clamp(0, ax, bx) or
-// the y-face at Y = clamp(0, ay, by) (offsets; when the centre's x lies
-// within the rectangle that "face" is an inner line, which can only lower
-// the bound, and when the centre lies inside both give q = 0).  On each, q
-// is a 1D parabola maximised at its clamped vertex.  The answer is
-// conservative: the comparison with thr carries a margin far above the FP32
-// error of q, and the continuous rectangle contains every pixel centre.
-// What the test below needs of a staged Gaussian beyond its coefficients:
-// the centre (u, v) and the slopes of the vertex lines of q, y* = kx X along
-// x = X and x* = ky Y along y = Y.  Computed once per staged entry.
-__device__ __forceinline__ float4 stage_cull(const Staged& s) {
-    return make_float4(s.geo.x + s.geo.y, s.geo.z + s.geo.w, -0.5f * s.coef.y * __builtin_amdgcn_rcpf(s.coef.z),
-                       -0.5f * s.coef.y * __builtin_amdgcn_rcpf(s.coef.x));
-}
-
-__device__ __forceinline__ bool box_overlaps(const Staged& s, const float4& cu, float x0, float x1, float y0,
-                                             float y1) {
-    const float u = cu.x, v = cu.y;
-    const float ax = x0 - u, bx = x1 - u, ay = y0 - v, by = y1 - v;
-    const float ca = s.coef.x, cb = s.coef.y, cc = s.coef.z;
-    const float kx = cu.z, ky = cu.w;
-    const float X = fminf(fmaxf(0.0f, ax), bx), Y = fminf(fmaxf(0.0f, ay), by);
-    const float yx = fminf(fmaxf(kx * X, ay), by);
-    const float xy = fminf(fmaxf(ky * Y, ax), bx);
-    const float m = fmaxf(ca * X * X + cb * X * yx + cc * yx * yx, ca * xy * xy + cb * xy * Y + cc * Y * Y);
-    return m >= s.col.w - (1e-3f + 1e-4f * fabsf(m));
-}
-
-// The staged record `k` of an LDS array, addressed with a 24-bit multiply
-// (full rate) instead of a 32-bit one.
-__device__ __forceinline__ const Staged& staged_at(const Staged* s, int k) {
-    return *reinterpret_cast<const Staged*>(reinterpret_cast<const char*>(s) + __umul24((unsigned)k, (unsigned)sizeof(Staged)));
-}
-
-// Sum of v over each 16-lane row of the wave (DPP), left in every lane of
-// the row.
-__device__ __forceinline__ float row_sum(float v) {
-    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true));  // quad_perm [1,0,3,2]
-    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, true));  // quad_perm [2,3,0,1]
-    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x141, 0xF, 0xF, true)); // row_half_mirror
-    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x140, 0xF, 0xF, true)); // row_mirror
-    return v;
-}
-
 __device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void store_relaxed(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Sum of v over the 64 lanes of the wave, complete in lane 63 only: DPP
-// sums within each 16-lane row, then the two GFX9 row broadcasts carry the
-// row sums upwards.  Must be called with all 64 lanes active.
-__device__ __forceinline__ float wave_sum_to_lane63(float v) {
-    v = row_sum(v);
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));  // row_bcast:15 into rows 1, 3
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xC, 0xF, false));  // row_bcast:31 into rows 2, 3
-    return v;
 }
 
 }  // namespace gs

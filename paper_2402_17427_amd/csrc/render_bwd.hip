@@ -17,22 +17,31 @@
 // skip decisions), recovers T_i = T_{i+1} / (1 - alpha_i) from the stored
 // final transmittance, and accumulates S_i as it goes.
 //
-// Walk: as in the forward, each wave covers an 8x8 block and walks only the
-// staged entries whose support box meets its block (ballot mask, scanned
-// from the back) and that lie before its pixels' last contributor.
-// Reduction: per walked entry, a wave first checks (ballot) whether any of
-// its 64 pixels contributed; only then are the nine gradient terms summed
-// over each 16-lane row with a transposing DPP butterfly that leaves the
-// nine sums in lanes 0..8 of the row, which add them with one LDS atomic
-// instruction into a per-tile accumulator.  After the batch each entry's
-// sums are written, without global atomics, to its (Gaussian, tile) pair
-// slot in emission order; a gather then adds each Gaussian's slots, so the
-// per-Gaussian sum over tiles has a fixed order.
+// Walk: one lane per cell of CW x CH pixels (blend_cells.h); each lane
+// walks, from the back, only the list entries whose support reaches its
+// cell and that lie before its pixels' last contributor.  The list is
+// taken in chunks of at most 64 entries from the back.  Accumulation: for
+// every (cell, entry) it walks, a lane adds its pixels' nine gradient
+// terms in registers and writes the sums once, with plain stores, to a slot
+// of its own in LDS; the slots of one entry are contiguous (entry-major,
+// then wave, then cell order), so after the chunk one thread per entry adds
+// its slots in a fixed order and writes the nine sums, without global
+// atomics, to the entry's (Gaussian, tile) pair slot in emission order; a
+// gather then adds each Gaussian's pair slots, so the per-Gaussian sum has
+// a fixed order.  A chunk ends early when its entries' slots would exceed
+// the LDS capacity (Gaussians that reach many cells).
+#include "blend_cells.h"
 #include "kernels.h"
 
 namespace gs {
 
 namespace {
+
+constexpr int kChunk = 64;      // candidate entries per chunk (one walk word)
+#ifndef GS_ITEM_CAP
+#define GS_ITEM_CAP 512
+#endif
+constexpr int kItemCap = GS_ITEM_CAP;   // (cell, entry) slots per chunk (>= 64 x waves of any layout)
 
 struct BwdArgs {
     const Rec* rec;
@@ -54,61 +63,23 @@ struct BwdArgs {
     uint32_t n_tiles;
 };
 
-// One DPP exchange inside each 16-lane row: quad_perm [1,0,3,2] (partner
-// lane ^ 1), quad_perm [2,3,0,1] (lane ^ 2), row_ror:4 and row_ror:8 (lane
-// - 4 and lane - 8 within the row).
-template <int CTRL>
-__device__ __forceinline__ float xch(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
-}
-constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kRor4 = 0x124, kRor8 = 0x128;
-
-// Sums nine values over each 16-lane row with a transposing butterfly: in
-// each of the first three exchanges a lane keeps one value of every pair and
-// sends its partner the other, so the values per lane halve as the span of
-// the sums doubles (27 VALU operations instead of 36 for nine plain
-// butterflies, and the sums end up spread over the lanes).  On return lane
-// l (0..15) of a row holds the row sum of v[l & 7] in .x and of v8 in .y.
-// b0, b1, b2 are bits 0, 1, 2 of the lane index.
-__device__ __forceinline__ float2 row_sum9(float v0, float v1, float v2, float v3, float v4, float v5, float v6,
-                                           float v7, float v8, bool b0, bool b1, bool b2) {
-    // lane ^ 1: keep v[2j + b0]
-    const float r0 = (b0 ? v1 : v0) + xch<kXor1>(b0 ? v0 : v1);
-    const float r1 = (b0 ? v3 : v2) + xch<kXor1>(b0 ? v2 : v3);
-    const float r2 = (b0 ? v5 : v4) + xch<kXor1>(b0 ? v4 : v5);
-    const float r3 = (b0 ? v7 : v6) + xch<kXor1>(b0 ? v6 : v7);
-    const float r4 = v8 + xch<kXor1>(v8);
-    // lane ^ 2: keep v[4k + 2 b1 + b0]
-    const float s0 = (b1 ? r1 : r0) + xch<kXor2>(b1 ? r0 : r1);
-    const float s1 = (b1 ? r3 : r2) + xch<kXor2>(b1 ? r2 : r3);
-    const float s2 = r4 + xch<kXor2>(r4);
-    // lane - 4 (opposite bit 2, same low bits): keep v[4 b2 + 2 b1 + b0]
-    const float t0 = (b2 ? s1 : s0) + xch<kRor4>(b2 ? s0 : s1);
-    const float t1 = s2 + xch<kRor4>(s2);
-    // lane - 8: the other two quads of the row
-    return make_float2(t0 + xch<kRor8>(t0), t1 + xch<kRor8>(t1));
-}
-
-template <int NT>
+template <class L>
 struct BwdShared {
-    static constexpr int B = NT < 256 ? NT : 256;   // staged Gaussians per batch
-    Staged s[B];
-    uint32_t gid[B];
-    float acc[B * 9];
+    Staged s[kChunk];
+    uint32_t gid[kChunk];
+    uint64_t mask[L::WAVES][kChunk];   // per wave: the cells that walk each entry
+    uint32_t base[L::WAVES][kChunk];   // items per (wave, entry), then their first slot
+    uint32_t total[kChunk];            // items per entry
+    float item[9][kItemCap];           // the nine sums of each (cell, entry)
     uint32_t max_last;
+    int kmin;                          // the chunk: candidates kmin .. ncand - 1
 };
 
 // STORED = true reads each entry's (alpha, T) from the state the storing
 // forward wrote (alpha negated when capped) instead of recomputing them.
-template <int TW, int TH, bool STORED>
-__device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdShared<TW * TH>& sh) {
-    constexpr int NT = TW * TH;
-    constexpr int B = BwdShared<NT>::B;
-    constexpr int WX = TW / 8;
-    Staged* s = sh.s;
-    uint32_t* s_gid = sh.gid;
-    float* s_acc = sh.acc;
-
+template <class L, bool STORED>
+__device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdShared<L>& sh) {
+    constexpr int NP = L::NP;
     if (*a.status != 0) return;
 
     const View V = view_at(a.views, find_view(a.views, tile));
@@ -116,165 +87,219 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
     const int local = (int)(tile - V.tile_base);
     const int tx = local % V.ntx, ty = local / V.ntx;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    // wave = 8x8 block; its 16-lane row r = the 4x4 quadrant (r & 1, r >> 1)
-    const int row = lane >> 4, l16 = lane & 15;
-    const int bx = (wv % WX) * 8, by = (wv / WX) * 8;
-    const int lx = bx + (row & 1) * 4 + (l16 & 3), ly = by + (row >> 1) * 4 + (l16 >> 2);
-    const int px = tx * TW + lx, py = ty * TH + ly;
-    const bool inside = px < W && py < H;
+    const int cx = tid % L::CPR, cy = tid / L::CPR;
+    const int x0 = tx * L::TW, y0 = ty * L::TH;
+    const int wy0 = y0 + wv * L::PXROWS_W;
     const int64_t npix = (int64_t)W * H;
-    const int64_t off = (int64_t)py * W + px;
     const float* final_T = a.final_T + V.pix_base;
     const uint32_t* n_contrib = a.n_contrib + V.pix_base;
     const float* dimg = a.dimg + V.img_base;
-    const Rec* __restrict__ rec = a.rec;
-    const uint32_t* __restrict__ vals = a.vals;
-    const float2* __restrict__ state = a.state;
     const float bg0 = V.cam.bg[0], bg1 = V.cam.bg[1], bg2 = V.cam.bg[2];
-
     const uint2 rg = a.ranges[tile];
-    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-    const float bx0 = (float)(tx * TW + bx) + 0.5f, by0 = (float)(ty * TH + by) + 0.5f;
 
-    uint32_t my_last = 0;
-    float T = 1.0f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-    if (inside) {
-        my_last = n_contrib[off];
-        T = final_T[off];
-        g0 = dimg[off];
-        g1 = dimg[npix + off];
-        g2 = dimg[2 * npix + off];
+    const int px0 = x0 + cx * L::CW, py0 = y0 + cy * L::CH;
+    float fxp[L::CW], fyp[L::CH];
+#pragma unroll
+    for (int i = 0; i < L::CW; ++i) fxp[i] = (float)(px0 + i) + 0.5f;
+#pragma unroll
+    for (int j = 0; j < L::CH; ++j) fyp[j] = (float)(py0 + j) + 0.5f;
+
+    uint32_t my_last[NP];
+    float T[NP], g0[NP], g1[NP], g2[NP], gbg[NP], ga[NP];
+    uint32_t cell_last = 0;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int x = px0 + p % L::CW, y = py0 + p / L::CW;
+        my_last[p] = 0u;
+        T[p] = 1.0f;
+        g0[p] = g1[p] = g2[p] = 0.0f;
+        if (x < W && y < H) {
+            const int64_t off = (int64_t)y * W + x;
+            my_last[p] = n_contrib[off];
+            T[p] = final_T[off];
+            g0[p] = dimg[off];
+            g1[p] = dimg[npix + off];
+            g2[p] = dimg[2 * npix + off];
+        }
+        // g . (T_final bg): the background's share of every suffix colour
+        gbg[p] = g0[p] * (T[p] * bg0) + g1[p] * (T[p] * bg1) + g2[p] * (T[p] * bg2);
+        ga[p] = 0.0f;   // g . sum of rgb_j w_j over the blended j behind the current entry
+        cell_last = max(cell_last, my_last[p]);
     }
-    // g . (T_final bg): the background's share of every suffix colour
-    const float gbg = g0 * (T * bg0) + g1 * (T * bg1) + g2 * (T * bg2);
-    float ga = 0.f;   // g . sum of rgb_j w_j over the blended j behind the current entry
 
     __syncthreads();   // the previous tile of a persistent workgroup is done with the shared state
     if (tid == 0) sh.max_last = 0u;
     __syncthreads();
-    if (my_last) atomicMax(&sh.max_last, my_last);
+    if (cell_last) atomicMax(&sh.max_last, cell_last);
     __syncthreads();
     // never walk past the tile's list, whatever n_contrib holds
-    const uint32_t max_last = min(sh.max_last, rg.y - rg.x);
+    int hi = (int)min(sh.max_last, rg.y - rg.x);
 
-    const bool b0 = (lane & 1) != 0, b1 = (lane & 2) != 0, b2 = (lane & 4) != 0;
-    // a row never needs entries at or beyond its pixels' last contributor
-    uint32_t row_last = my_last;
-    for (int d = 1; d < 16; d <<= 1) row_last = max(row_last, (uint32_t)__shfl_xor((int)row_last, d, kWave));
-
-    for (int64_t hi = (int64_t)max_last; hi > 0; hi -= B) {
-        const int64_t lo = hi - B > 0 ? hi - B : 0;
-        const int nb = (int)(hi - lo);
+    while (hi > 0) {
+        const int lo0 = hi > kChunk ? hi - kChunk : 0;
+        const int ncand = hi - lo0;
+        __syncthreads();   // the previous chunk's slots and staged entries are no longer read
+        stage_batch<1>(sh.s, a.rec, a.vals, rg.x + (uint32_t)lo0, ncand, tid, L::NCELL, sh.gid);
         __syncthreads();
-        if (tid < nb) {
-            const uint32_t gid = vals[rg.x + lo + tid];
-            s_gid[tid] = gid;
-            s[tid] = stage_rec(rec[gid]);
+
+        // entry-major cell masks of this wave, transposed into the lane's
+        // walk word, cut at the cell's last contributor, and back
+        const uint64_t m = lane < ncand ? cell_mask<L>(sh.s[lane], x0, wy0) : 0ull;
+        uint64_t walk = transpose64(m, lane);
+        {
+            const int lim = (int)cell_last - lo0;   // entries lo0 + k with k < lim
+            walk = lim <= 0 ? 0ull : (lim >= kWave ? walk : (walk & ((1ull << lim) - 1ull)));
         }
-        for (int q = tid; q < B * 9; q += NT) s_acc[q] = 0.f;
+        const uint64_t mw = transpose64(walk, lane);
+        sh.mask[wv][lane] = mw;
+        sh.base[wv][lane] = (uint32_t)__popcll(mw);
         __syncthreads();
 
-        // 64 staged entries at a time, back to front: each lane tests one
-        // against the four quadrants of the wave's block; every row then
-        // walks, back to front, the entries whose support meets its quadrant
-        // and that lie before its pixels' last contributor (the four rows
-        // of a wave walk different Gaussians in step).
-        for (int c0k = ((nb - 1) / kWave) * kWave; c0k >= 0; c0k -= kWave) {
-            const int k = c0k + lane;
-            bool o0 = false, o1 = false, o2 = false, o3 = false;
-            if (k < nb) {
-                const Staged gk = staged_at(s, k);
-                const float4 ck = stage_cull(gk);
-                o0 = box_overlaps(gk, ck, bx0, bx0 + 3.0f, by0, by0 + 3.0f);
-                o1 = box_overlaps(gk, ck, bx0 + 4.0f, bx0 + 7.0f, by0, by0 + 3.0f);
-                o2 = box_overlaps(gk, ck, bx0, bx0 + 3.0f, by0 + 4.0f, by0 + 7.0f);
-                o3 = box_overlaps(gk, ck, bx0 + 4.0f, bx0 + 7.0f, by0 + 4.0f, by0 + 7.0f);
+        // one thread per candidate: its items, the chunk (the candidates from
+        // the top whose items fit), and the first slot of each (wave, entry)
+        if (wv == 0) {
+            uint32_t tot = 0;
+#pragma unroll
+            for (int w = 0; w < L::WAVES; ++w) tot += sh.base[w][lane];
+            // inclusive suffix sum over the candidates above (k >= lane)
+            uint32_t suf = tot;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t y = (uint32_t)__shfl_down((int)suf, d, kWave);
+                if (lane + d < kWave) suf += y;
             }
-            const uint64_t m0 = __ballot(o0), m1 = __ballot(o1), m2 = __ballot(o2), m3 = __ballot(o3);
-            uint64_t mm = row == 0 ? m0 : (row == 1 ? m1 : (row == 2 ? m2 : m3));
-            const int lim = (int)row_last - (int)(lo + c0k);
-            mm = lim <= 0 ? 0ull : (lim >= kWave ? mm : (mm & ((1ull << lim) - 1ull)));
-            while (__ballot(mm != 0ull) != 0ull) {
-                const bool has = mm != 0ull;
-                int kk = 0;
-                if (has) {
-                    const int j = 63 - (int)__builtin_clzll(mm);
-                    mm &= ~(1ull << j);
-                    kk = c0k + j;
+            const bool in = lane < ncand && suf <= (uint32_t)kItemCap;
+            const uint64_t inm = __ballot(in);
+            if (lane == 0) sh.kmin = inm ? low_bit(inm) : ncand;
+            uint32_t b = suf - tot;   // slots of the entries above
+#pragma unroll
+            for (int w = 0; w < L::WAVES; ++w) {
+                const uint32_t c = sh.base[w][lane];
+                sh.base[w][lane] = b;
+                b += c;
+            }
+            sh.total[lane] = tot;
+        }
+        __syncthreads();
+        const int kmin = sh.kmin;
+
+        // walk: entries kmin .. ncand - 1 of the lane's word, from the back
+        uint64_t wk = kmin >= kWave ? 0ull : (walk & ~((1ull << kmin) - 1ull));
+        const uint64_t below = (1ull << lane) - 1ull;
+        if (__ballot(wk != 0ull) != 0ull) do {
+            const bool has = wk != 0ull;
+            const int kk = has ? high_bit(wk) : kmin;
+            wk &= ~(1ull << kk);
+            const Staged g = staged_at(sh.s, kk);
+            const uint32_t pos = (uint32_t)(lo0 + kk);
+            float dxs[L::CW], dys[L::CH], qa[L::CW], qb[L::CW], qc[L::CH];
+#pragma unroll
+            for (int i = 0; i < L::CW; ++i) {
+                dxs[i] = (fxp[i] - g.geo.x) - g.geo.y;
+                qa[i] = (g.coef.x * dxs[i]) * dxs[i];
+                qb[i] = g.coef.y * dxs[i];
+            }
+#pragma unroll
+            for (int j = 0; j < L::CH; ++j) {
+                dys[j] = (fyp[j] - g.geo.z) - g.geo.w;
+                qc[j] = (g.coef.z * dys[j]) * dys[j];
+            }
+            // the cell's sums: dpow dx, dpow dy, dpow dx^2, dpow dx dy,
+            // dpow dy^2, dL/do, dL/drgb
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f, s6 = 0.f, s7 = 0.f, s8 = 0.f;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int i = p % L::CW, j = p / L::CW;
+                float alpha, G, Ts;
+                bool capped;
+                if (STORED) {
+                    const int pix = (py0 + j - y0) * L::TW + (px0 + i - x0);
+                    const bool rd = has && pos < my_last[p];
+                    const float2 st = rd ? a.state[(int64_t)(rg.x + pos) * L::NT + pix] : make_float2(0.f, 0.f);
+                    alpha = fabsf(st.x);
+                    capped = st.x < 0.0f;
+                    G = alpha * __builtin_amdgcn_rcpf(g.coef.w);
+                    Ts = st.y;
+                } else {
+                    const float pw = __builtin_fmaf(qb[i], dys[j], qa[i] + qc[j]);
+                    G = __builtin_amdgcn_exp2f(pw);
+                    const float araw = g.coef.w * G;
+                    capped = araw > kAlphaMax;
+                    const float al0 = capped ? kAlphaMax : araw;
+                    alpha = (pw > 0.0f || al0 < kAlphaMin) ? 0.0f : al0;
+                    Ts = 0.0f;
                 }
-                const Staged g = staged_at(s, kk);
-                const uint32_t pos = (uint32_t)(lo + kk);
-                const bool live = has && pos < my_last;
                 // Branch-free: a pair that does not contribute gets alpha 0,
                 // which leaves T and the suffix colour unchanged and makes
                 // every gradient term 0.
-                Eval e;
-                float Ts = T;
-                if (STORED) {
-                    const float2 st = live ? state[(int64_t)(rg.x + pos) * NT + tid] : make_float2(0.f, 0.f);
-                    e.alpha = fabsf(st.x);
-                    e.capped = st.x < 0.0f;
-                    e.dx = (fx - g.geo.x) - g.geo.y;
-                    e.dy = (fy - g.geo.z) - g.geo.w;
-                    e.G = e.alpha * __builtin_amdgcn_rcpf(g.coef.w);
-                    Ts = st.y;
-                } else {
-                    e = eval_pair(g, fx, fy);
-                }
-                const bool contrib = live && e.alpha > 0.0f;
-                const float a = contrib ? e.alpha : 0.0f;
-                const float iom = __builtin_amdgcn_rcpf(1.0f - a);
-                const float Ti = STORED ? (contrib ? Ts : T) : T * iom;
-                const float w = a * Ti;
-                const float grgb = g0 * g.col.x + g1 * g.col.y + g2 * g.col.z;
+                const bool contrib = has && pos < my_last[p] && alpha > 0.0f;
+                const float al = contrib ? alpha : 0.0f;
+                const float iom = __builtin_amdgcn_rcpf(1.0f - al);
+                const float Ti = STORED ? (contrib ? Ts : T[p]) : T[p] * iom;
+                const float w = al * Ti;
+                const float grgb = g0[p] * g.col.x + g1[p] * g.col.y + g2[p] * g.col.z;
                 // dL/dalpha = g . (rgb T_i - S_i / (1 - alpha)), S_i = suffix colour + T_final bg;
                 // no gradient through a capped alpha
-                const float da0 = grgb * Ti - (ga + gbg) * iom;
-                const float da = (contrib && !e.capped) ? da0 : 0.0f;
-                ga = __builtin_fmaf(grgb, w, ga);
-                T = Ti;
-                // per-lane terms; a lane without a contribution holds zeros
-                const float v6 = g0 * w, v7 = g1 * w, v8 = g2 * w;
-                const float v5 = (contrib && !e.capped) ? da0 * e.G : 0.0f;
+                const float da0 = grgb * Ti - (ga[p] + gbg[p]) * iom;
+                const float da = (contrib && !capped) ? da0 : 0.0f;
+                ga[p] = __builtin_fmaf(grgb, w, ga[p]);
+                T[p] = Ti;
+                s6 = __builtin_fmaf(g0[p], w, s6);
+                s7 = __builtin_fmaf(g1[p], w, s7);
+                s8 = __builtin_fmaf(g2[p], w, s8);
+                s5 = __builtin_fmaf(da, G, s5);
                 // moments of dL/dpower over the pixel offsets; the centre and
                 // conic gradients are linear in them (formed at the flush)
-                const float dpow = da * a;
-                const float mx = dpow * e.dx, my = dpow * e.dy;
-                const uint64_t cm = __ballot(contrib);
-                if (cm == 0ull) continue;
-                // row sums, spread over the row's lanes 0..8, added into the
-                // tile's LDS accumulator of the row's entry
-                const float2 r = row_sum9(mx, my, mx * e.dx, mx * e.dy, my * e.dy, v5, v6, v7, v8, b0, b1, b2);
-                // LDS float atomics cost about one cycle per active lane:
-                // rows without a contributing pixel add nothing
-                if (l16 <= 8 && ((cm >> (lane & 48)) & 0xFFFFull) != 0ull)
-                    atomicAdd(s_acc + (__umul24((uint32_t)kk, 9u) + (uint32_t)l16), l16 == 8 ? r.y : r.x);
+                const float dpow = da * al;
+                const float mx = dpow * dxs[i], my = dpow * dys[j];
+                s0 += mx;
+                s1 += my;
+                s2 = __builtin_fmaf(mx, dxs[i], s2);
+                s3 = __builtin_fmaf(mx, dys[j], s3);
+                s4 = __builtin_fmaf(my, dys[j], s4);
             }
-        }
+            if (has) {
+                const uint32_t slot = sh.base[wv][kk] + (uint32_t)__popcll(sh.mask[wv][kk] & below);
+                sh.item[0][slot] = s0;
+                sh.item[1][slot] = s1;
+                sh.item[2][slot] = s2;
+                sh.item[3][slot] = s3;
+                sh.item[4][slot] = s4;
+                sh.item[5][slot] = s5;
+                sh.item[6][slot] = s6;
+                sh.item[7][slot] = s7;
+                sh.item[8][slot] = s8;
+            }
+        } while (__ballot(wk != 0ull) != 0ull);
         __syncthreads();
-        // the accumulator holds, per entry, the sums of dpow dx, dpow dy,
-        // dpow dx^2, dpow dx dy, dpow dy^2, dL/do, dL/drgb; with
+
+        // the accumulated sums of dpow dx, dpow dy, dpow dx^2, dpow dx dy,
+        // dpow dy^2, dL/do, dL/drgb give, with
         // power = -(A dx^2 + C dy^2)/2 - B dx dy and dx = x - u:
         // du = sum dpow (A dx + B dy), dv = sum dpow (B dx + C dy),
         // dA = -sum dpow dx^2 / 2, dB = -sum dpow dx dy, dC = -sum dpow dy^2 / 2,
         // where A = -2 ca / log2e, B = -cb / log2e, C = -2 cc / log2e.
-        // Each entry's nine sums go, without atomics, to the entry's own
-        // pair slot: one thread per entry.
-        if (tid < nb) {
-            const float* acc = s_acc + tid * 9;
+        // One thread per entry adds the entry's slots in order and writes
+        // its pair slot (no atomics).
+        if (tid >= kmin && tid < ncand) {
+            const uint32_t b = sh.base[0][tid], n = sh.total[tid];
             float m[9];
-            bool any = false;
-            for (int c = 0; c < 9; ++c) {
-                m[c] = acc[c];
-                any |= m[c] != 0.0f;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) m[c] = 0.0f;
+            for (uint32_t e = b; e < b + n; ++e) {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) m[c] += sh.item[c][e];
             }
+            bool any = false;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) any |= m[c] != 0.0f;
             if (any) {
-                const uint32_t gid = s_gid[tid];
+                const uint32_t gid = sh.gid[tid];
                 const ushort4 r = a.rect[gid];
                 const int64_t p = (int64_t)a.first[gid] + (int64_t)(ty - (int)r.y) * ((int)r.z - (int)r.x) +
                                   (tx - (int)r.x);
                 if (p >= 0 && p < a.cap) {
-                    const float4 cf = s[tid].coef;
+                    const float4 cf = sh.s[tid].coef;
                     const float A = -2.0f * cf.x * (1.0f / kLog2e), Bc = -cf.y * (1.0f / kLog2e),
                                 C = -2.0f * cf.z * (1.0f / kLog2e);
                     a.pg8[2 * p] = make_float4(A * m[0] + Bc * m[1], Bc * m[0] + C * m[1], -0.5f * m[2], -m[3]);
@@ -283,18 +308,19 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
                 }
             }
         }
+        hi = lo0 + kmin;
     }
 }
 
-template <int TW, int TH, bool STORED>
-__global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
-    __shared__ BwdShared<TW * TH> sh;
-    bwd_tile<TW, TH, STORED>(a, blockIdx.x, sh);
+template <class L, bool STORED>
+__global__ __launch_bounds__(L::NCELL) void k_render_bwd(BwdArgs a) {
+    __shared__ BwdShared<L> sh;
+    bwd_tile<L, STORED>(a, blockIdx.x, sh);
 }
 
-template <int TW, int TH>
-__global__ __launch_bounds__(TW * TH) void k_render_bwd_persistent(BwdArgs a) {
-    __shared__ BwdShared<TW * TH> sh;
+template <class L>
+__global__ __launch_bounds__(L::NCELL) void k_render_bwd_persistent(BwdArgs a) {
+    __shared__ BwdShared<L> sh;
     __shared__ uint32_t s_next;
     for (;;) {
         __syncthreads();
@@ -302,7 +328,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd_persistent(BwdArgs a) {
         __syncthreads();
         const uint32_t q = s_next;
         if (q >= a.n_tiles) break;
-        bwd_tile<TW, TH, false>(a, a.order ? a.order[q] : q, sh);
+        bwd_tile<L, false>(a, a.order ? a.order[q] : q, sh);
     }
 }
 
@@ -351,13 +377,20 @@ __global__ __launch_bounds__(256) void k_pair_gather(int64_t nslots, const uint3
 
 template <int TW, int TH>
 void launch_t(const BwdArgs& a, int persistent_grid, hipStream_t st) {
-    const dim3 block(TW * TH);
+    using L = typename CellsFor<TW, TH>::L;
+    const dim3 block(L::NCELL);
     if (a.state)
-        hipLaunchKernelGGL((k_render_bwd<TW, TH, true>), dim3(a.n_tiles), block, 0, st, a);
+        hipLaunchKernelGGL((k_render_bwd<L, true>), dim3(a.n_tiles), block, 0, st, a);
     else if (persistent_grid > 0)
-        hipLaunchKernelGGL((k_render_bwd_persistent<TW, TH>), dim3(persistent_grid), block, 0, st, a);
+        hipLaunchKernelGGL((k_render_bwd_persistent<L>), dim3(persistent_grid), block, 0, st, a);
     else
-        hipLaunchKernelGGL((k_render_bwd<TW, TH, false>), dim3(a.n_tiles), block, 0, st, a);
+        hipLaunchKernelGGL((k_render_bwd<L, false>), dim3(a.n_tiles), block, 0, st, a);
+}
+
+template <int TW, int TH>
+hipError_t occupancy_t(int* per) {
+    using L = typename CellsFor<TW, TH>::L;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_render_bwd_persistent<L>, L::NCELL, 0);
 }
 
 }  // namespace
@@ -422,15 +455,12 @@ int render_persistent_grid_bwd(int tw, int th) {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     hipError_t e = hipErrorInvalidValue;
-#define GS_OCC(x, y) \
-    if (tw == x && th == y) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_render_bwd_persistent<x, y>, x * y, 0)
-    GS_OCC(16, 16);
-    GS_OCC(8, 8);
-    GS_OCC(16, 8);
-    GS_OCC(32, 8);
-    GS_OCC(32, 16);
-    GS_OCC(32, 32);
-#undef GS_OCC
+    if (tw == 16 && th == 16) e = occupancy_t<16, 16>(&per);
+    else if (tw == 8 && th == 8) e = occupancy_t<8, 8>(&per);
+    else if (tw == 16 && th == 8) e = occupancy_t<16, 8>(&per);
+    else if (tw == 32 && th == 8) e = occupancy_t<32, 8>(&per);
+    else if (tw == 32 && th == 16) e = occupancy_t<32, 16>(&per);
+    else if (tw == 32 && th == 32) e = occupancy_t<32, 32>(&per);
     if (e != hipSuccess || per < 1) per = 1;
     return cus * per;
 }

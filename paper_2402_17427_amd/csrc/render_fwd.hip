@@ -9,17 +9,16 @@
 // Output pixel = C + T bg.
 //
 // Launch: one workgroup per tile (or a persistent grid pulling tiles from
-// a queue, longest list first), one lane per pixel.  Every wave covers an
-// 8x8 block of the tile and each of its four 16-lane rows a 4x4 quadrant.
-// Batches of records are staged in LDS; for each 64 of them every lane
-// tests one against the four quadrants (an exact ellipse-rectangle test),
-// and each row then walks, in list order, only the Gaussians whose support
-// meets its quadrant; the rows of a wave walk different Gaussians in the
-// same instructions.  Skipping the others never changes a result: such a
-// Gaussian has alpha < 1/255 at every pixel of the quadrant.  A wave leaves
-// the tile once all its pixels have stopped, the workgroup once all waves
-// have.  Tiles of several views are numbered consecutively; a tile finds
-// its view (camera, image planes) in the view table.
+// a queue), one lane per cell of CW x CH pixels (blend_cells.h).  Batches
+// of 256 list entries are staged in LDS.  For each 64 of them every lane
+// computes one entry's cell mask from the exact chords of its support, a
+// bit transpose gives each lane the entries that reach its cell, and each
+// lane then walks its own entries of the whole batch in list order, with
+// its pixels' state in registers.  Skipping the other entries never
+// changes a result: they have alpha < 1/255 at every pixel of the cell.
+// Tiles of several views are numbered consecutively; a tile finds its view
+// (camera, image planes) in the view table.
+#include "blend_cells.h"
 #include "kernels.h"
 
 namespace gs {
@@ -28,13 +27,17 @@ namespace {
 
 // MODE kPlain is the forward.  kStats is the instrumented variant behind
 // gs_render_stats: the same walk, counting per pixel the list entries it
-// evaluates (after the wave culling), the entries with alpha >= 1/255
-// before its stop, and the blended ones, summed into stats[0..2]; it
-// writes no image.  kStore is the forward that also keeps the blend state:
-// for every entry a pixel evaluates, state[(list position) * NT + lane in
-// tile] = (alpha, T before it), alpha negated when capped at 0.99 and 0 when
-// skipped; the stored-state backward reads it instead of recomputing.
+// evaluates, the entries with alpha >= 1/255 before its stop, and the
+// blended ones, summed into stats[0..2]; it writes no image.  kStore is the
+// forward that also keeps the blend state: for every entry a pixel
+// evaluates, state[(list position) * NT + pixel in tile] = (alpha, T before
+// it), alpha negated when capped at 0.99 and 0 when skipped; the
+// stored-state backward reads it instead of recomputing.
 constexpr int kPlain = 0, kStats = 1, kStore = 2;
+#ifndef GS_FWD_BATCH
+#define GS_FWD_BATCH 256
+#endif
+constexpr int kBatch = GS_FWD_BATCH;   // staged entries per batch (one walk word per 64)
 
 struct FwdArgs {
     const Rec* rec;
@@ -52,95 +55,139 @@ struct FwdArgs {
     uint32_t n_tiles;
 };
 
-template <int TW, int TH, int MODE>
-__device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, Staged* s, float4* sc) {
-    constexpr int NT = TW * TH;
+struct FwdShared {
+    Staged s[kBatch];
+};
+
+template <class L, int MODE>
+__device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdShared& sh) {
+    constexpr int NP = L::NP;
     constexpr bool STATS = MODE == kStats;
-    constexpr int WX = TW / 8;
 
     const View V = view_at(a.views, find_view(a.views, tile));
     const int W = V.cam.W, H = V.cam.H;
     const int local = (int)(tile - V.tile_base);
     const int tx = local % V.ntx, ty = local / V.ntx;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    // wave = 8x8 block; its 16-lane row r = the 4x4 quadrant (r & 1, r >> 1)
-    const int row = lane >> 4, l16 = lane & 15;
-    const int bx = (wv % WX) * 8, by = (wv / WX) * 8;
-    const int lx = bx + (row & 1) * 4 + (l16 & 3), ly = by + (row >> 1) * 4 + (l16 >> 2);
-    const int px = tx * TW + lx, py = ty * TH + ly;
-    const bool inside = px < W && py < H;
+    const int cx = tid % L::CPR, cy = tid / L::CPR;
+    const int x0 = tx * L::TW, y0 = ty * L::TH;
+    const int wy0 = y0 + wv * L::PXROWS_W;           // the wave's first pixel row
     const int64_t npix = (int64_t)W * H;
-    const int64_t off = (int64_t)py * W + px;
     float* image = V.out_image ? V.out_image : a.image + V.img_base;
     float* final_T = a.final_T + V.pix_base;
     uint32_t* n_contrib = a.n_contrib + V.pix_base;
 
+    // the lane's pixels: (px0 + i % CW, py0 + i / CW)
+    const int px0 = x0 + cx * L::CW, py0 = y0 + cy * L::CH;
+    bool inside[NP];
+    float fxp[L::CW], fyp[L::CH];
+#pragma unroll
+    for (int i = 0; i < L::CW; ++i) fxp[i] = (float)(px0 + i) + 0.5f;
+#pragma unroll
+    for (int j = 0; j < L::CH; ++j) fyp[j] = (float)(py0 + j) + 0.5f;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) inside[p] = (px0 + p % L::CW) < W && (py0 + p / L::CW) < H;
+
     if (*a.status != 0) {
-        if (!STATS && inside) {
+        if (!STATS) {
             const float nan = __builtin_nanf("");
-            image[off] = nan;
-            image[npix + off] = nan;
-            image[2 * npix + off] = nan;
-            final_T[off] = nan;
-            n_contrib[off] = 0u;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                if (!inside[p]) continue;
+                const int64_t off = (int64_t)(py0 + p / L::CW) * W + px0 + p % L::CW;
+                image[off] = nan;
+                image[npix + off] = nan;
+                image[2 * npix + off] = nan;
+                final_T[off] = nan;
+                n_contrib[off] = 0u;
+            }
         }
         return;
     }
 
     const uint2 rg = a.ranges[tile];
-    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-    const float bx0 = (float)(tx * TW + bx) + 0.5f, by0 = (float)(ty * TH + by) + 0.5f;
-
-    float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-    uint32_t last = 0;
-    bool done = !inside;
+    // T > 0: the pixel is blending; a pixel that has stopped (or lies
+    // outside the image) keeps its transmittance negated
+    float T[NP], c0[NP], c1[NP], c2[NP];
+    uint32_t last[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        T[p] = inside[p] ? 1.0f : -1.0f;
+        c0[p] = c1[p] = c2[p] = 0.0f;
+        last[p] = 0u;
+    }
     unsigned long long n_eval = 0, n_supp = 0, n_blend = 0;
 
-    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += NT) {
-        if (__syncthreads_count(done) == NT) break;
-        const uint32_t j = b0 + tid;
-        if (j < rg.y) {
-            const Staged st = stage_rec(a.rec[a.vals[j]]);
-            s[tid] = st;
-            sc[tid] = stage_cull(st);
-        }
+    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kBatch) {
+        bool all_done = true;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) all_done = all_done && !(T[p] > 0.0f);
+        if (__syncthreads_count(all_done) == L::NCELL) break;
+        const int nb = (int)min((uint32_t)kBatch, rg.y - b0);
+        stage_batch<(kBatch + L::NCELL - 1) / L::NCELL>(sh.s, a.rec, a.vals, b0, nb, tid, L::NCELL);
         __syncthreads();
-        const int nb = (int)min((uint32_t)NT, rg.y - b0);
-        // 64 staged Gaussians at a time: each lane tests one against the
-        // four quadrants of the wave's block; every row then walks, in list
-        // order, the Gaussians whose support meets its own quadrant (the
-        // four rows of a wave walk different Gaussians in step).
-        for (int c0k = 0; c0k < nb; c0k += kWave) {
-            const uint64_t lv = __ballot(!done);
-            if (lv == 0ull) break;
-            const int k = c0k + lane;
-            bool o0 = false, o1 = false, o2 = false, o3 = false;
-            if (k < nb) {
-                const Staged gk = staged_at(s, k);
-                const float4 ck = sc[k];
-                o0 = box_overlaps(gk, ck, bx0, bx0 + 3.0f, by0, by0 + 3.0f);
-                o1 = box_overlaps(gk, ck, bx0 + 4.0f, bx0 + 7.0f, by0, by0 + 3.0f);
-                o2 = box_overlaps(gk, ck, bx0, bx0 + 3.0f, by0 + 4.0f, by0 + 7.0f);
-                o3 = box_overlaps(gk, ck, bx0 + 4.0f, bx0 + 7.0f, by0 + 4.0f, by0 + 7.0f);
+
+        // the lane's walk words: entries 64 q .. 64 q + 63 of the batch that
+        // reach its cell, kept in order with the empty words dropped
+        uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+        int q0 = 0, q1 = 0, q2 = 0, q3 = 0, nw = 0;
+#pragma unroll
+        for (int q = 0; q < kBatch / kWave; ++q) {
+            if (q * kWave >= nb) break;
+            const int k = q * kWave + lane;
+            const uint64_t m = k < nb ? cell_mask<L>(sh.s[k], x0, wy0) : 0ull;
+            uint64_t t = transpose64(m, lane);
+            if (all_done) t = 0ull;
+            if (t != 0ull) {
+                if (nw == 0) { w0 = t; q0 = q * kWave; }
+                else if (nw == 1) { w1 = t; q1 = q * kWave; }
+                else if (nw == 2) { w2 = t; q2 = q * kWave; }
+                else { w3 = t; q3 = q * kWave; }
+                ++nw;
             }
-            const uint64_t m0 = __ballot(o0), m1 = __ballot(o1), m2 = __ballot(o2), m3 = __ballot(o3);
-            uint64_t mm = row == 0 ? m0 : (row == 1 ? m1 : (row == 2 ? m2 : m3));
-            if (((lv >> (16 * row)) & 0xFFFFull) == 0ull) mm = 0ull;   // this row's pixels have all stopped
-            while (__ballot(mm != 0ull) != 0ull) {
-                // branch-free: a row with nothing left evaluates entry
-                // c0k and, like a stopped pixel or an entry below the
-                // alpha threshold, changes nothing
-                const bool has = mm != 0ull;
-                const int kk = c0k + (has ? (int)__builtin_ctzll(mm) : 0);
-                mm &= mm - 1;
-                const bool act = has && !done;
-                const Staged g = staged_at(s, kk);
-                const Eval e = eval_pair(g, fx, fy);
-                if (MODE == kStore && act)
-                    a.state[(int64_t)(b0 + (uint32_t)kk) * NT + tid] =
-                        make_float2(e.capped && e.alpha > 0.0f ? -e.alpha : e.alpha, T);
-                const bool supp = act && e.alpha > 0.0f;
-                const float Tn = T * (1.0f - e.alpha);
+        }
+
+        const uint32_t pos0 = b0 - rg.x;   // list position of the batch's first entry
+        // Branch-free walk: a lane with nothing left evaluates entry 0 and,
+        // like a stopped pixel or an entry below the alpha threshold,
+        // changes nothing.
+        if (__ballot(w0 != 0ull) != 0ull) do {
+            const bool has = w0 != 0ull;
+            const int kk = has ? q0 + low_bit(w0) : 0;
+            w0 &= w0 - 1ull;
+            const Staged g = staged_at(sh.s, kk);
+            // offsets of the lane's pixel columns and rows, then each pixel's
+            // base-2 exponent (a function of the pixel and the Gaussian only)
+            float dys[L::CH], qa[L::CW], qb[L::CW], qc[L::CH];
+#pragma unroll
+            for (int i = 0; i < L::CW; ++i) {
+                const float dx = (fxp[i] - g.geo.x) - g.geo.y;
+                qa[i] = (g.coef.x * dx) * dx;
+                qb[i] = g.coef.y * dx;
+            }
+#pragma unroll
+            for (int j = 0; j < L::CH; ++j) {
+                dys[j] = (fyp[j] - g.geo.z) - g.geo.w;
+                qc[j] = (g.coef.z * dys[j]) * dys[j];
+            }
+            const uint32_t lastv = pos0 + (uint32_t)kk + 1u;
+            bool all = true;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int i = p % L::CW, j = p / L::CW;
+                const float pw = __builtin_fmaf(qb[i], dys[j], qa[i] + qc[j]);
+                const float G = __builtin_amdgcn_exp2f(pw);
+                const float araw = g.coef.w * G;
+                const float al0 = fminf(araw, kAlphaMax);
+                const float alpha = (pw > 0.0f || al0 < kAlphaMin) ? 0.0f : al0;
+                const bool act = has && T[p] > 0.0f;
+                if (MODE == kStore && act) {
+                    const int pix = (py0 + j - y0) * L::TW + (px0 + i - x0);
+                    a.state[(int64_t)(b0 + (uint32_t)kk) * L::NT + pix] =
+                        make_float2(araw > kAlphaMax && alpha > 0.0f ? -alpha : alpha, T[p]);
+                }
+                const bool supp = act && alpha > 0.0f;
+                const float Tn = T[p] * (1.0f - alpha);
                 const bool stop = supp && Tn < kTMin;
                 const bool blend = supp && !stop;
                 if (STATS) {
@@ -148,21 +195,25 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, Staged
                     n_supp += supp ? 1u : 0u;
                     n_blend += blend ? 1u : 0u;
                 }
-                const float w = blend ? e.alpha * T : 0.0f;
-                c0 = __builtin_fmaf(g.col.x, w, c0);
-                c1 = __builtin_fmaf(g.col.y, w, c1);
-                c2 = __builtin_fmaf(g.col.z, w, c2);
-                T = blend ? Tn : T;
-                last = blend ? b0 - rg.x + (uint32_t)kk + 1u : last;
-                done = done || stop;
-                // a row whose pixels have all stopped leaves its walk
-                // (checked only when some pixel of the wave stopped now)
-                if (__ballot(stop) != 0ull) {
-                    const uint64_t lv2 = __ballot(!done);
-                    if (((lv2 >> (16 * row)) & 0xFFFFull) == 0ull) mm = 0ull;
-                }
+                const float w = blend ? alpha * T[p] : 0.0f;
+                c0[p] = __builtin_fmaf(g.col.x, w, c0[p]);
+                c1[p] = __builtin_fmaf(g.col.y, w, c1[p]);
+                c2[p] = __builtin_fmaf(g.col.z, w, c2[p]);
+                T[p] = blend ? Tn : (stop ? -T[p] : T[p]);
+                last[p] = blend ? lastv : last[p];
+                all = all && !(T[p] > 0.0f);
             }
-        }
+            // a lane whose pixels have all stopped leaves its walk; a lane
+            // at the end of a word moves to its next one
+            const bool adv = !all && w0 == 0ull && nw > 1;
+            w0 = all ? 0ull : (adv ? w1 : w0);
+            q0 = adv ? q1 : q0;
+            w1 = adv ? w2 : w1;
+            q1 = adv ? q2 : q1;
+            w2 = adv ? w3 : w2;
+            q2 = adv ? q3 : q2;
+            nw = all ? 0 : nw - (adv ? 1 : 0);
+        } while (__ballot(w0 != 0ull) != 0ull);
     }
     if (STATS) {
         // one atomic per counter and wave (same-address atomics from every
@@ -173,31 +224,35 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, Staged
             s32 += (uint32_t)__shfl_xor((int)s32, d, kWave);
             b32 += (uint32_t)__shfl_xor((int)b32, d, kWave);
         }
-        if ((threadIdx.x & (kWave - 1)) == 0) {
+        if (lane == 0) {
             atomicAdd(&a.stats[0], (unsigned long long)e32);
             atomicAdd(&a.stats[1], (unsigned long long)s32);
             atomicAdd(&a.stats[2], (unsigned long long)b32);
         }
-    } else if (inside) {
-        image[off] = __builtin_fmaf(T, V.cam.bg[0], c0);
-        image[npix + off] = __builtin_fmaf(T, V.cam.bg[1], c1);
-        image[2 * npix + off] = __builtin_fmaf(T, V.cam.bg[2], c2);
-        final_T[off] = T;
-        n_contrib[off] = last;
+    } else {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (!inside[p]) continue;
+            const int64_t off = (int64_t)(py0 + p / L::CW) * W + px0 + p % L::CW;
+            const float Tf = fabsf(T[p]);
+            image[off] = __builtin_fmaf(Tf, V.cam.bg[0], c0[p]);
+            image[npix + off] = __builtin_fmaf(Tf, V.cam.bg[1], c1[p]);
+            image[2 * npix + off] = __builtin_fmaf(Tf, V.cam.bg[2], c2[p]);
+            final_T[off] = fabsf(T[p]);
+            n_contrib[off] = last[p];
+        }
     }
 }
 
-template <int TW, int TH, int MODE>
-__global__ __launch_bounds__(TW * TH) void k_render_fwd(FwdArgs a) {
-    __shared__ Staged s[TW * TH];
-    __shared__ float4 sc[TW * TH];
-    fwd_tile<TW, TH, MODE>(a, blockIdx.x, s, sc);
+template <class L, int MODE>
+__global__ __launch_bounds__(L::NCELL) void k_render_fwd(FwdArgs a) {
+    __shared__ FwdShared sh;
+    fwd_tile<L, MODE>(a, blockIdx.x, sh);
 }
 
-template <int TW, int TH>
-__global__ __launch_bounds__(TW * TH) void k_render_fwd_persistent(FwdArgs a) {
-    __shared__ Staged s[TW * TH];
-    __shared__ float4 sc[TW * TH];
+template <class L>
+__global__ __launch_bounds__(L::NCELL) void k_render_fwd_persistent(FwdArgs a) {
+    __shared__ FwdShared sh;
     __shared__ uint32_t s_next;
     for (;;) {
         __syncthreads();
@@ -205,21 +260,28 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd_persistent(FwdArgs a) {
         __syncthreads();
         const uint32_t q = s_next;
         if (q >= a.n_tiles) break;
-        fwd_tile<TW, TH, kPlain>(a, a.order ? a.order[q] : q, s, sc);
+        fwd_tile<L, kPlain>(a, a.order ? a.order[q] : q, sh);
     }
 }
 
 template <int TW, int TH>
 void launch_t(const FwdArgs& a, int persistent_grid, hipStream_t st) {
-    const dim3 block(TW * TH);
+    using L = typename CellsFor<TW, TH>::L;
+    const dim3 block(L::NCELL);
     if (a.stats)
-        hipLaunchKernelGGL((k_render_fwd<TW, TH, kStats>), dim3(a.n_tiles), block, 0, st, a);
+        hipLaunchKernelGGL((k_render_fwd<L, kStats>), dim3(a.n_tiles), block, 0, st, a);
     else if (a.state)
-        hipLaunchKernelGGL((k_render_fwd<TW, TH, kStore>), dim3(a.n_tiles), block, 0, st, a);
+        hipLaunchKernelGGL((k_render_fwd<L, kStore>), dim3(a.n_tiles), block, 0, st, a);
     else if (persistent_grid > 0)
-        hipLaunchKernelGGL((k_render_fwd_persistent<TW, TH>), dim3(persistent_grid), block, 0, st, a);
+        hipLaunchKernelGGL((k_render_fwd_persistent<L>), dim3(persistent_grid), block, 0, st, a);
     else
-        hipLaunchKernelGGL((k_render_fwd<TW, TH, kPlain>), dim3(a.n_tiles), block, 0, st, a);
+        hipLaunchKernelGGL((k_render_fwd<L, kPlain>), dim3(a.n_tiles), block, 0, st, a);
+}
+
+template <int TW, int TH>
+hipError_t occupancy_t(int* per) {
+    using L = typename CellsFor<TW, TH>::L;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_render_fwd_persistent<L>, L::NCELL, 0);
 }
 
 }  // namespace
@@ -270,15 +332,12 @@ int render_persistent_grid_fwd(int tw, int th) {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     hipError_t e = hipErrorInvalidValue;
-#define GS_OCC(x, y) \
-    if (tw == x && th == y) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_render_fwd_persistent<x, y>, x * y, 0)
-    GS_OCC(16, 16);
-    GS_OCC(8, 8);
-    GS_OCC(16, 8);
-    GS_OCC(32, 8);
-    GS_OCC(32, 16);
-    GS_OCC(32, 32);
-#undef GS_OCC
+    if (tw == 16 && th == 16) e = occupancy_t<16, 16>(&per);
+    else if (tw == 8 && th == 8) e = occupancy_t<8, 8>(&per);
+    else if (tw == 16 && th == 8) e = occupancy_t<16, 8>(&per);
+    else if (tw == 32 && th == 8) e = occupancy_t<32, 8>(&per);
+    else if (tw == 32 && th == 16) e = occupancy_t<32, 16>(&per);
+    else if (tw == 32 && th == 32) e = occupancy_t<32, 32>(&per);
     if (e != hipSuccess || per < 1) per = 1;
     return cus * per;
 }
