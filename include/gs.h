@@ -270,6 +270,20 @@ gs_status gs_loss(const float *image, const float *image_l1, const float *target
                   int32_t width, int32_t height, float lambda, float *loss, float *d_image,
                   float *d_image_l1, void *ws, size_t ws_bytes, gs_stream stream);
 
+/* gs_loss without a workspace, for callers that cannot allocate device
+ * memory (work recorded under stream capture, tight serving loops).  The
+ * per-tile partial sums go to a fixed device array the library holds (one
+ * per device, 1 MiB, kept until the process ends), so this call allocates
+ * nothing and takes the same arguments as gs_loss minus the workspace.
+ * Limit: channels * ceil(width / 32) * ceil(height / 32) <= 131072 (an RGB
+ * image up to 7680 x 4320); a larger image is rejected with
+ * GS_ERR_CAPACITY before anything is enqueued.  Calls that overlap on one
+ * device share that array and race: serialise them (one stream, or events).
+ * Results are bit-identical to gs_loss's.  Other errors as gs_loss. */
+gs_status gs_loss_noalloc(const float *image, const float *image_l1, const float *target, int32_t channels,
+                          int32_t width, int32_t height, float lambda, float *loss, float *d_image,
+                          float *d_image_l1, gs_stream stream);
+
 /* ---- Optimiser step ---------------------------------------------------------
  * Section 3: the Gaussians' properties are optimised by gradient descent on
  * the loss, interleaved with adaptive densification that is triggered by

@@ -108,6 +108,7 @@ _SIGS = {
     "gs_render_stats": [C.POINTER(gs_proj), C.POINTER(gs_bins), C.POINTER(gs_camera), C.POINTER(gs_opts), P, P],
     "gs_loss_workspace": [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
     "gs_loss": [P, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, P, P, C.c_size_t, P],
+    "gs_loss_noalloc": [P, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, P, P],
     "gs_adam_step": [C.POINTER(gs_params), P, P, C.POINTER(gs_adam_state), C.POINTER(gs_grads), P, P,
                      C.POINTER(gs_adam_config), P],
     "gs_partition_views": [P, C.c_int32, P, C.c_int64, C.POINTER(gs_partition_config), P, P, P, P, P],

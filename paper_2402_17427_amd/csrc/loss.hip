@@ -32,7 +32,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
+#include "api_internal.h"
 #include "kernels.h"
 
 namespace gs {
@@ -411,3 +413,63 @@ void launch_loss_finish(int channels, int width, int height, float lambda, const
 }
 
 }  // namespace gs
+
+// ---- the loss without a caller workspace ---------------------------------
+// For callers that cannot allocate (code under stream capture, serving
+// loops): the per-tile partial sums go to a fixed device array instead of
+// a workspace.  Every call on a device uses that device's copy of the
+// array, so calls that overlap on one device race; each call rewrites
+// every partial it reads, so nothing needs clearing between calls.
+namespace gs {
+namespace {
+
+constexpr size_t kLossScratchBytes = (size_t)1 << 20;   // 131072 (tile, channel) partials: 8K RGB
+static __device__ __align__(256) unsigned char scratch[kLossScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices];
+
+// Device address of the current device's `scratch`, looked up once per
+// device with that device current (each device holds its own copy).
+gs_status scratch_of_current_device(void** out) {
+    int dev = 0;
+    const hipError_t ed = hipGetDevice(&dev);
+    if (ed != hipSuccess) return fail(GS_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(ed));
+    if (dev < 0 || dev >= kMaxDevices) return fail(GS_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(GS_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return GS_OK;
+}
+
+}  // namespace
+}  // namespace gs
+
+extern "C" gs_status gs_loss_noalloc(const float* image, const float* image_l1, const float* target,
+                                     int32_t channels, int32_t width, int32_t height, float lambda, float* loss,
+                                     float* d_image, float* d_image_l1, gs_stream stream) {
+    using namespace gs;
+    size_t need = 0;
+    gs_status s;
+    if ((s = gs_loss_workspace(channels, width, height, &need))) return s;
+    if (!image || !target || !loss || !d_image) return fail(GS_ERR_INVALID, "buffer is NULL");
+    if (image_l1 && !d_image_l1) return fail(GS_ERR_INVALID, "image_l1 given without d_image_l1");
+    if (!std::isfinite(lambda)) return fail(GS_ERR_INVALID, "lambda not finite");
+    if (need > kLossScratchBytes)
+        return fail(GS_ERR_CAPACITY, "a %dx%dx%d image needs %zu bytes of partial sums, more than the %zu this call holds",
+                    channels, height, width, need, kLossScratchBytes);
+    void* ws = nullptr;
+    if ((s = scratch_of_current_device(&ws))) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    launch_loss(image, image_l1, target, channels, width, height, lambda, d_image, image_l1 ? d_image_l1 : nullptr,
+                ws, st);
+    launch_loss_finish(channels, width, height, lambda, ws, loss, st);
+    return check_hip("gs_loss_noalloc");
+}

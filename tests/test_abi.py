@@ -147,6 +147,26 @@ def test_loss_workspace_query_and_validation_without_a_device():
     assert b"aligned" in lib.gs_last_error()
 
 
+def test_loss_noalloc_validation_without_a_device():
+    """gs_loss_noalloc checks its arguments like gs_loss and rejects an
+    image whose partial sums exceed its fixed scratch (GS_ERR_CAPACITY)
+    before any device call."""
+    lib = N.lib()
+    fake = 1 << 20
+
+    def call(img=fake, img_l1=None, tgt=fake, c=3, w=8, h=8, lam=0.2, out=fake, d=fake, d1=None):
+        return lib.gs_loss_noalloc(img, img_l1, tgt, c, w, h, C.c_float(lam), out, d, d1, None)
+
+    assert call(img=None) == N.GS_ERR_INVALID
+    assert call(d=None) == N.GS_ERR_INVALID
+    assert call(c=0) == N.GS_ERR_INVALID
+    assert call(img_l1=fake) == N.GS_ERR_INVALID
+    assert call(lam=float("inf")) == N.GS_ERR_INVALID
+    # 3 x 256 x 256 tiles of 32 x 32: more partials than the scratch holds
+    assert call(w=8192, h=8192) == N.GS_ERR_CAPACITY
+    assert b"partial sums" in lib.gs_last_error()
+
+
 def test_adam_step_validation_without_a_device():
     """gs_adam_step rejects NULL descriptors and buffers, ld < n, a bad SH
     degree and out-of-range hyper-parameters before any launch (the device
