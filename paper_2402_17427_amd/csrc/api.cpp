@@ -236,14 +236,15 @@ gs_status gs_bin_sort(const gs_proj* proj, int64_t n, const gs_camera* cam, cons
         Gauss G0;
         std::memset(&G0, 0, sizeof G0);
         G0.n = n;
+        const ZeroList z = bin_sort_zero_list(sort_ws, cap, tb, out->ranges, n_tiles);
         launch_emit_pairs(n, proj->tiles_touched, reinterpret_cast<const ushort4*>(proj->rect), proj->depth,
                           single_job(G0, nullptr), single_view(C, tw, th), cap, to_alt ? alt_k : out->keys,
-                          to_alt ? alt_v : out->vals, out->first, out->pair_count, out->status, scan_ws, st);
+                          to_alt ? alt_v : out->vals, out->first, out->pair_count, out->status, scan_ws, st, &z);
     }
     {
         ProfScope ps("sort", st);
         launch_bin_sort(out->keys, out->vals, alt_k, alt_v, out->pair_count, cap, tb, out->ranges, n_tiles, sort_ws,
-                        st);
+                        st, true);
     }
     return check_hip("gs_bin_sort");
 }

@@ -198,8 +198,9 @@ struct gs_batch {
     void enqueue_project_bin(hipStream_t st) {
         launch_project(jt(), vt(), K, nslots, tw, th, rec, depth, rect, tt, st);
         const bool to_alt = bin_sort_emit_to_alt(tile_bits(n_tiles));
+        const ZeroList z = bin_sort_zero_list(sort_ws, capacity, tile_bits(n_tiles), ranges, n_tiles);
         launch_emit_pairs(nslots, tt, rect, depth, jt(), vt(), capacity, to_alt ? alt_k : keys, to_alt ? alt_v : vals,
-                          first, pair_count, status, scan_ws, st);
+                          first, pair_count, status, scan_ws, st, &z);
     }
 
     // One training step of every cell: project, bin, sort, ranges, blend,
@@ -207,7 +208,7 @@ struct gs_batch {
     void enqueue_step(hipStream_t st) {
         enqueue_project_bin(st);
         launch_bin_sort(keys, vals, alt_k, alt_v, pair_count, capacity, tile_bits(n_tiles), ranges, n_tiles, sort_ws,
-                        st);
+                        st, true);
         RenderArgs r;
         std::memset(&r, 0, sizeof r);
         r.rec = rec;

@@ -7,6 +7,7 @@
 // (the rectangle from the projection), emitted in row-major order; the sort
 // that follows is stable, so equal keys keep Gaussian-index order.
 #include "kernels.h"
+#include <algorithm>
 
 namespace gs {
 
@@ -44,8 +45,14 @@ __device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t* t
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_block_sums(const uint32_t* __restrict__ tt, int64_t n,
-                                                             uint64_t* __restrict__ block_sums) {
+                                                             uint64_t* __restrict__ block_sums, ZeroList zero) {
     const int64_t i = (int64_t)blockIdx.x * kScanThreads + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kScanThreads;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+        for (int64_t j = i; j < zero.n[r]; j += stride) zero.p[r][j] = 0u;
+    const int64_t nb = (n + kScanThreads - 1) / kScanThreads;
+    if ((int64_t)blockIdx.x >= nb) return;   // a clearing-only workgroup
     const uint64_t v = i < n ? tt[i] : 0u;
     uint64_t tot;
     block_exclusive_scan<kScanThreads>(v, &tot);
@@ -143,10 +150,25 @@ void launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t st) {
 
 void launch_emit_pairs(int64_t n, const uint32_t* tt, const ushort4* rect, const float* depth, const JobTab& jobs,
                        const ViewTab& views, int64_t capacity, uint64_t* keys, uint32_t* vals, uint32_t* first,
-                       uint32_t* pair_count, int32_t* status, void* scan_ws, hipStream_t st) {
+                       uint32_t* pair_count, int32_t* status, void* scan_ws, hipStream_t st, const ZeroList* zero) {
     uint64_t* bs = static_cast<uint64_t*>(scan_ws);
     const int64_t nb = (n + kScanThreads - 1) / kScanThreads;
-    if (nb > 0) hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nb), dim3(kScanThreads), 0, st, tt, n, bs);
+    ZeroList z{};
+    int64_t zn = 0;
+    if (zero) {
+        z = *zero;
+        for (int r = 0; r < 3; ++r) {
+            if (!z.p[r]) z.n[r] = 0;
+            zn += z.n[r];
+        }
+    }
+    // the block-sum pass also clears what the caller listed (grid-stride),
+    // with at least enough workgroups that each thread clears a few words
+    int64_t grid = nb;
+    const int64_t zgrid = std::min<int64_t>((zn + 4 * kScanThreads - 1) / (4 * kScanThreads), 2048);
+    if (zgrid > grid) grid = zgrid;
+    if (grid > 0)
+        hipLaunchKernelGGL(k_block_sums, dim3((unsigned)grid), dim3(kScanThreads), 0, st, tt, n, bs, z);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTopThreads), 0, st, bs, nb, capacity, pair_count, status);
     if (nb > 0)
         hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kScanThreads), 0, st, tt, rect, depth, n, jobs, views,

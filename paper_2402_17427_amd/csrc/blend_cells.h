@@ -81,18 +81,6 @@ __device__ __forceinline__ uint64_t cell_mask(const Staged& g, int x0, int y0) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Lane exchanges used by the transpose (lane ^ s).
-__device__ __forceinline__ uint32_t xor_lane(uint32_t v, int s) {
-    switch (s) {
-    case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
-    case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
-    case 4: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);              // xor 4 in 32 lanes
-    case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, true);  // row_ror:8
-    case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);             // xor 16 in 32 lanes
-    default: return (uint32_t)__shfl_xor((int)v, 32, kWave);
-    }
-}
-
 // Transpose of a 64 x 64 bit matrix held one row per lane: on entry lane k
 // holds row k (bit c = element (k, c)), on return lane c holds column c (bit
 // k = element (k, c)).  Recursive block swap: at each size s the lanes k and

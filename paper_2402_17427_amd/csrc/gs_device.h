@@ -140,6 +140,19 @@ __device__ __forceinline__ Staged stage_rec(const Rec& r) {
     return s;
 }
 
+// The value of lane ^ s (s a power of two below 64), by the cheapest
+// exchange for each distance.  Must be called by all 64 lanes of the wave.
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v, int s) {
+    switch (s) {
+    case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
+    case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
+    case 4: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);              // xor 4 in 32 lanes
+    case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, true);  // row_ror:8
+    case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);             // xor 16 in 32 lanes
+    default: return (uint32_t)__shfl_xor((int)v, 32, kWave);
+    }
+}
+
 __device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -21,6 +21,12 @@ void launch_project_bwd(const JobTab& jobs, const ViewTab& views, int K, int64_t
                         const uint32_t* tiles_touched, const float* g2d, const int32_t* status, hipStream_t st);
 
 // ---- binning (binning.hip)
+// Device words to zero before a binning sort; the emission's first kernel
+// clears them (saving the sort a launch).
+struct ZeroList {
+    uint32_t* p[3];
+    int64_t n[3];
+};
 // Workspace for the tiles_touched scan over n Gaussians.
 size_t scan_workspace_bytes(int64_t n);
 // Exclusive scan of tiles_touched, then one (tile << 32 | depth bits, index)
@@ -30,7 +36,8 @@ size_t scan_workspace_bytes(int64_t n);
 // first emission position.
 void launch_emit_pairs(int64_t n, const uint32_t* tiles_touched, const ushort4* rect, const float* depth,
                        const JobTab& jobs, const ViewTab& views, int64_t capacity, uint64_t* keys, uint32_t* vals,
-                       uint32_t* first, uint32_t* pair_count, int32_t* status, void* scan_ws, hipStream_t st);
+                       uint32_t* first, uint32_t* pair_count, int32_t* status, void* scan_ws, hipStream_t st,
+                       const ZeroList* zero = nullptr);
 // Per-tile [start, end) of sorted keys; `zeroed`: ranges already hold zeros.
 void launch_tile_ranges(const uint64_t* keys, const uint32_t* pair_count, int64_t capacity, int64_t n_tiles,
                         uint32_t* ranges, hipStream_t st, bool zeroed = false);
@@ -55,8 +62,11 @@ void launch_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint3
 // end in (keys, vals) and `ranges` [n_tiles][2] is written.  `ws` holds
 // sort_workspace_bytes(capacity, 32 + tile_bits) bytes.
 bool bin_sort_emit_to_alt(int tile_bits);
+// What the emission must zero for launch_bin_sort(..., zeroed = true).
+ZeroList bin_sort_zero_list(void* ws, int64_t capacity, int tile_bits, uint32_t* ranges, int64_t n_tiles);
 void launch_bin_sort(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals, const uint32_t* count,
-                     int64_t capacity, int tile_bits, uint32_t* ranges, int64_t n_tiles, void* ws, hipStream_t st);
+                     int64_t capacity, int tile_bits, uint32_t* ranges, int64_t n_tiles, void* ws, hipStream_t st,
+                     bool zeroed = false);
 
 // ---- blend (render_fwd.hip / render_bwd.hip)
 // What both blend passes read: records, sorted values, per-tile ranges of

@@ -277,9 +277,11 @@ struct gs_server {
         const int tb = tile_bits(std::max<uint32_t>(tile, 1));
         const bool to_alt = bin_sort_emit_to_alt(tb);
         launch_project(jt, vt, scene.K, slot, tw, th, p.rec, p.depth, p.rect, p.tt, st);
+        const ZeroList z = bin_sort_zero_list(p.sort_ws, cap, tb, p.ranges, tile);
         launch_emit_pairs(slot, p.tt, p.rect, p.depth, jt, vt, cap, to_alt ? p.alt_k : p.keys,
-                          to_alt ? p.alt_v : p.vals, nullptr, p.pair_count, p.status, p.scan_ws, st);
-        launch_bin_sort(p.keys, p.vals, p.alt_k, p.alt_v, p.pair_count, cap, tb, p.ranges, tile, p.sort_ws, st);
+                          to_alt ? p.alt_v : p.vals, nullptr, p.pair_count, p.status, p.scan_ws, st, &z);
+        launch_bin_sort(p.keys, p.vals, p.alt_k, p.alt_v, p.pair_count, cap, tb, p.ranges, tile, p.sort_ws, st,
+                        true);
         RenderArgs r;
         std::memset(&r, 0, sizeof r);
         r.rec = p.rec;

@@ -9,19 +9,19 @@
 // Structure (8-bit digits, one kernel per digit pass):
 //   k_sort_clear  zero the digit histograms, partition counters and
 //                 look-back words of the passes to run, for the pair count
-//                 on the device
+//                 on the device (in the binning sort the key emission's
+//                 first kernel does this instead)
 //   k_hist        one read of every key builds the histograms of all
 //                 passes at once (LDS atomics, then one global atomic per
 //                 non-empty bin and workgroup)
-//   k_hist_scan   exclusive scan of each pass's 256 bins (one workgroup
-//                 per pass)
-//   k_onesweep    per pass: each workgroup takes the next partition of
-//                 4096 keys from an atomic counter, ranks its keys stably
-//                 with wave64 ballots (match-by-digit), publishes its digit
-//                 counts and resolves its global offsets by decoupled
-//                 look-back over the earlier partitions (a window of
-//                 eight per step, so the walk is not one dependent load
-//                 per partition), sorts the
+//   k_onesweep    per pass: every workgroup first scans the pass's 256
+//                 bins into global digit offsets, then takes the next
+//                 partition of 4096 keys from an atomic counter, ranks its
+//                 keys stably with wave64 ballots (match-by-digit),
+//                 publishes its digit counts and resolves its global
+//                 offsets by decoupled look-back over the earlier
+//                 partitions (a window of eight per step, so the walk is
+//                 not one dependent load per partition), sorts the
 //                 partition locally in LDS and writes it out digit run by
 //                 digit run (coalesced).
 // The pair count stays on the device; grids are sized for the capacity
@@ -105,27 +105,6 @@ __global__ __launch_bounds__(256) void k_hist(const uint64_t* __restrict__ keys,
         if (h[j]) atomicAdd(&w.hist[j], h[j]);
 }
 
-// One workgroup per pass: exclusive scan of the pass's 256 digit counts.
-__global__ __launch_bounds__(kRadix) void k_hist_scan(SortWs w, int p0) {
-    __shared__ uint32_t s_w[kRadix / kWave];
-    const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
-    uint32_t* h = w.hist + (p0 + (int)blockIdx.x) * kRadix;
-    const uint32_t v = h[t];
-    uint32_t x = v;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, kWave);
-        if (lane >= d) x += y;
-    }
-    if (lane == kWave - 1) s_w[wv] = x;
-    __syncthreads();
-    uint32_t base = 0;
-#pragma unroll
-    for (int q = 0; q < kRadix / kWave; ++q)
-        if (q < wv) base += s_w[q];
-    h[t] = base + x - v;
-}
-
 __device__ __forceinline__ uint64_t ballot64(bool b) { return __ballot(b); }
 
 __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __restrict__ kin,
@@ -145,7 +124,26 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
     const int64_t P = clamp_count(count, w.capacity);
     const int64_t nparts = (P + kPart - 1) / kPart;
     uint32_t* look = w.look + (int64_t)pass * w.max_parts * kRadix;
-    const uint32_t* goff = w.hist + pass * kRadix;
+    // exclusive scan of this pass's digit counts (thread t owns digit t):
+    // each workgroup forms the global digit offsets itself
+    __shared__ uint32_t s_goff[kRadix];
+    {
+        const uint32_t v = w.hist[pass * kRadix + tid];
+        uint32_t x = v;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, kWave);
+            if (lane >= d) x += y;
+        }
+        if (lane == kWave - 1) s_scan[wv] = x;
+        __syncthreads();
+        uint32_t b = 0;
+#pragma unroll
+        for (int q = 0; q < kSortWaves; ++q)
+            if (q < wv) b += s_scan[q];
+        s_goff[tid] = b + x - v;
+        __syncthreads();
+    }
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     // When the grid covers every partition, workgroup b takes partition b
@@ -215,7 +213,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
             const uint32_t total = run;
             if (part == 0) {
                 store_relaxed(&look[t], kFlagInc | total);
-                s_dbase[t] = goff[t];
+                s_dbase[t] = s_goff[t];
             } else {
                 store_relaxed(&look[part * kRadix + t], kFlagAgg | total);
                 // look back over a window of kLook earlier partitions per
@@ -246,7 +244,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
                     if (stalled) __builtin_amdgcn_s_sleep(1);
                 }
                 store_relaxed(&look[part * kRadix + t], kFlagInc | (prefix + total));
-                s_dbase[t] = goff[t] + prefix;
+                s_dbase[t] = s_goff[t] + prefix;
             }
             // exclusive scan of the partition's digit counts
             uint32_t x = total;
@@ -527,20 +525,21 @@ namespace {
 // when any pass runs; the return value then has bit 1 set.
 int radix_passes(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals, const uint32_t* count,
                  int64_t capacity, int p0, int p1, bool start_in_alt, void* ws, hipStream_t st,
-                 uint32_t* zero = nullptr, int64_t zero_count = 0) {
+                 uint32_t* zero = nullptr, int64_t zero_count = 0, bool cleared = false) {
     if (p1 <= p0 || capacity == 0) return start_in_alt ? 1 : 0;
     SortWs w = carve(ws, capacity, p1);
     const int64_t parts = (capacity + kPart - 1) / kPart;
-    int64_t clear_blocks = (parts * kRadix * (p1 - p0) + 255) / 256;
-    if (clear_blocks > 1024) clear_blocks = 1024;
-    if (clear_blocks < 1) clear_blocks = 1;
-    hipLaunchKernelGGL(k_sort_clear, dim3((unsigned)clear_blocks), dim3(256), 0, st, w, count, p0, p1, zero,
-                       zero ? zero_count : (int64_t)0);
+    if (!cleared) {
+        int64_t clear_blocks = (parts * kRadix * (p1 - p0) + 255) / 256;
+        if (clear_blocks > 1024) clear_blocks = 1024;
+        if (clear_blocks < 1) clear_blocks = 1;
+        hipLaunchKernelGGL(k_sort_clear, dim3((unsigned)clear_blocks), dim3(256), 0, st, w, count, p0, p1, zero,
+                           zero ? zero_count : (int64_t)0);
+    }
     const uint64_t* src = start_in_alt ? alt_keys : keys;
     int64_t hb = (capacity + 256 * 16 - 1) / (256 * 16);
     if (hb > kMaxGrid) hb = kMaxGrid;
     hipLaunchKernelGGL(k_hist, dim3((unsigned)hb), dim3(256), 0, st, src, count, p0, p1, w);
-    hipLaunchKernelGGL(k_hist_scan, dim3((unsigned)(p1 - p0)), dim3(kRadix), 0, st, w, p0);
     int64_t grid = parts < kMaxGrid ? parts : kMaxGrid;
     bool in_alt = start_in_alt;
     for (int p = p0; p < p1; ++p) {
@@ -570,14 +569,41 @@ int bin_tile_passes(int tile_bits) { return (tile_bits + 7) / 8; }
 
 bool bin_sort_emit_to_alt(int tile_bits) { return bin_tile_passes(tile_bits) % 2 == 0; }
 
+ZeroList bin_sort_zero_list(void* ws, int64_t capacity, int tile_bits, uint32_t* ranges, int64_t n_tiles) {
+    const int p0 = 4, p1 = 4 + bin_tile_passes(tile_bits);
+    ZeroList z;
+    for (int r = 0; r < 3; ++r) {
+        z.p[r] = nullptr;
+        z.n[r] = 0;
+    }
+    // the tile ranges; with pairs to sort, also the histograms and
+    // partition counters (the workspace header) and the look-back words of
+    // the tile passes
+    if (ranges && n_tiles > 0) {
+        z.p[2] = ranges;
+        z.n[2] = n_tiles * 2;
+    }
+    if (ws && capacity > 0) {
+        SortWs w = carve(ws, capacity, p1);
+        z.p[0] = w.hist;
+        z.n[0] = (int64_t)((reinterpret_cast<char*>(w.look) - reinterpret_cast<char*>(w.hist)) / 4);
+        z.p[1] = w.look + (int64_t)p0 * w.max_parts * kRadix;
+        z.n[1] = (int64_t)(p1 - p0) * w.max_parts * kRadix;
+    }
+    return z;
+}
+
 void launch_bin_sort(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals, const uint32_t* count,
-                     int64_t capacity, int tile_bits, uint32_t* ranges, int64_t n_tiles, void* ws, hipStream_t st) {
+                     int64_t capacity, int tile_bits, uint32_t* ranges, int64_t n_tiles, void* ws, hipStream_t st,
+                     bool zeroed) {
     // tile bits: passes 4 .. 4 + ceil(tile_bits / 8) - 1, ending in the
-    // alternate buffers (the emission went where bin_sort_emit_to_alt says)
-    // (the first pass's clear also zeroes the tile ranges)
+    // alternate buffers (the emission went where bin_sort_emit_to_alt says);
+    // the workspace words and ranges are zeroed by the emission when
+    // `zeroed`, else by the first pass's clear
     const int r = radix_passes(keys, vals, alt_keys, alt_vals, count, capacity, 4, 4 + bin_tile_passes(tile_bits),
-                               bin_sort_emit_to_alt(tile_bits), ws, st, ranges, n_tiles * 2);
-    launch_tile_ranges(alt_keys, count, capacity, n_tiles, ranges, st, (r & 2) != 0);
+                               bin_sort_emit_to_alt(tile_bits), ws, st, zeroed ? nullptr : ranges, n_tiles * 2,
+                               zeroed);
+    launch_tile_ranges(alt_keys, count, capacity, n_tiles, ranges, st, zeroed || (r & 2) != 0);
     if (capacity == 0 || n_tiles == 0) return;
     const uint2* rg = reinterpret_cast<const uint2*>(ranges);
     hipLaunchKernelGGL(k_seg_sort_lds, dim3((unsigned)n_tiles), dim3(kWave), 0, st, alt_keys, alt_vals, keys, vals,
