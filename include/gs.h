@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 1
+#define GS_ABI_VERSION 2
 
 typedef enum {
     GS_OK = 0,
@@ -140,6 +140,16 @@ typedef struct {
  *                        needs (saturated at 2^32-1), to size a retry
  *   status[1]            0, or GS_ERR_CAPACITY if the pairs needed exceed
  *                        pair_capacity (nothing is sorted then)
+ *   cell_masks           optional (NULL = not kept), gs_render_mask_bytes()
+ *                        bytes, 8-byte aligned: for each sorted pair, one
+ *                        64-bit word per 64-lane wave of a tile's workgroup,
+ *                        bit c set when the pair's Gaussian can reach cell c
+ *                        of that wave (the exact alpha >= 1/255 chords of
+ *                        section 3's skip rule).  gs_render_fwd writes the
+ *                        words of every list entry it stages; gs_render_bwd
+ *                        then reads them instead of recomputing them, so
+ *                        it must get the buffer the forward of these bins
+ *                        filled (or NULL).  gs_bin_sort ignores it.
  * Tiles are numbered row-major: tile_y * ceil(W / tile_w) + tile_x. */
 typedef struct {
     uint64_t *keys;
@@ -149,6 +159,7 @@ typedef struct {
     uint32_t *pair_count;
     int32_t *status;
     int64_t pair_capacity;
+    uint64_t *cell_masks;
 } gs_bins;
 
 /* Gradient output (caller-owned device buffers, same shapes as gs_gaussians
@@ -188,6 +199,11 @@ gs_status gs_render_fwd(const gs_proj *proj, const gs_bins *bins, const gs_camer
                         const gs_opts *opts, float *image, float *final_T, uint32_t *n_contrib,
                         gs_stream stream);
 
+/* Bytes of bins->cell_masks for these bins and tiles: pair_capacity * 8 *
+ * (64-lane waves per tile: 1 for 8x8, 16x8, 16x16 and 32x8 tiles, 2 for
+ * 32x16, 4 for 32x32) (host query). */
+gs_status gs_render_mask_bytes(const gs_bins *bins, const gs_opts *opts, size_t *bytes);
+
 /* Bytes of the device workspace gs_render_bwd needs for these bins:
  * 36 bytes per pair of capacity (host query). */
 gs_status gs_render_bwd_workspace(const gs_bins *bins, size_t *bytes);
@@ -199,12 +215,13 @@ gs_status gs_render_bwd_workspace(const gs_bins *bins, size_t *bytes);
  * bins->first must be set.  Each pixel walks its list back to front from
  * its last contributor, recovering the transmittance by division from
  * final_T; no per-contributor state is stored.  Each tile sums its pixels'
- * terms per Gaussian (FP32 LDS atomics, so the last bits depend on their
- * order) and stores the sums, without global atomics, in `ws` (device
- * scratch of gs_render_bwd_workspace() bytes, 16-byte aligned,
- * caller-owned, contents on return unspecified) at the (Gaussian, tile)
- * pair's emission position; each Gaussian's entries are then added in
- * emission order into out->grad2d, which is overwritten.  The parameter
+ * terms per Gaussian in a fixed order (no atomics, so the gradients are
+ * bitwise repeatable) and stores the sums in `ws` (device scratch of
+ * gs_render_bwd_workspace() bytes, 16-byte aligned, caller-owned, contents
+ * on return unspecified) at the (Gaussian, tile) pair's emission position;
+ * each Gaussian's entries are then added in emission order into
+ * out->grad2d, which is overwritten.  With bins->cell_masks set, the cell
+ * masks the forward kept there are read instead of recomputed.  The parameter
  * gradients are overwritten (zero for culled Gaussians, and for all
  * Gaussians when *bins->status is non-zero). */
 gs_status gs_render_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_opts *opts,

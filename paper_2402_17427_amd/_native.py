@@ -56,7 +56,7 @@ class gs_proj(C.Structure):
 
 class gs_bins(C.Structure):
     _fields_ = [("keys", P), ("vals", P), ("first", P), ("ranges", P), ("pair_count", P), ("status", P),
-                ("pair_capacity", C.c_int64)]
+                ("pair_capacity", C.c_int64), ("cell_masks", P)]
 
 
 class gs_grads(C.Structure):
@@ -100,6 +100,7 @@ _SIGS = {
     "gs_sort_workspace": [C.c_int64, C.c_int32, C.POINTER(C.c_size_t)],
     "gs_sort_pairs": [P, P, P, C.c_int64, C.c_int32, P, C.c_size_t, P],
     "gs_render_state_bytes": [C.POINTER(gs_bins), C.POINTER(gs_opts), C.POINTER(C.c_size_t)],
+    "gs_render_mask_bytes": [C.POINTER(gs_bins), C.POINTER(gs_opts), C.POINTER(C.c_size_t)],
     "gs_render_fwd_stored": [C.POINTER(gs_proj), C.POINTER(gs_bins), C.POINTER(gs_camera), C.POINTER(gs_opts),
                              P, P, P, P, C.c_size_t, P],
     "gs_render_bwd_stored": [C.POINTER(gs_gaussians), C.POINTER(gs_camera), C.POINTER(gs_opts), C.POINTER(gs_proj),

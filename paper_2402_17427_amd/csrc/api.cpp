@@ -147,6 +147,7 @@ RenderArgs single_render(const gs_proj* proj, const gs_bins* bins, const Cam& C,
     r.n_tiles = (uint32_t)(r.views.one.ntx * r.views.one.nty);
     r.tw = tw;
     r.th = th;
+    r.masks = bins->cell_masks;
     return r;
 }
 
@@ -166,6 +167,8 @@ gs_status check_bins(const gs_bins* b) {
     if (!b->ranges || !b->pair_count || !b->status) return fail(GS_ERR_INVALID, "bins buffer is NULL");
     if (b->pair_capacity > 0 && (!b->keys || !b->vals)) return fail(GS_ERR_INVALID, "bins keys/vals NULL");
     if (reinterpret_cast<uintptr_t>(b->ranges) % 8) return fail(GS_ERR_INVALID, "ranges not 8-byte aligned");
+    if (reinterpret_cast<uintptr_t>(b->cell_masks) % 8)
+        return fail(GS_ERR_INVALID, "cell_masks not 8-byte aligned");
     return GS_OK;
 }
 
@@ -271,6 +274,15 @@ gs_status gs_render_state_bytes(const gs_bins* bins, const gs_opts* opts, size_t
     if ((s = tiles_of(opts, &tw, &th)) || (s = check_bins(bins))) return s;
     if (!bytes) return fail(GS_ERR_INVALID, "bytes is NULL");
     *bytes = (size_t)bins->pair_capacity * (size_t)(tw * th) * sizeof(float) * 2;
+    return GS_OK;
+}
+
+gs_status gs_render_mask_bytes(const gs_bins* bins, const gs_opts* opts, size_t* bytes) {
+    int tw, th;
+    gs_status s;
+    if ((s = tiles_of(opts, &tw, &th)) || (s = check_bins(bins))) return s;
+    if (!bytes) return fail(GS_ERR_INVALID, "bytes is NULL");
+    *bytes = (size_t)bins->pair_capacity * (size_t)render_mask_words(tw, th) * sizeof(uint64_t);
     return GS_OK;
 }
 

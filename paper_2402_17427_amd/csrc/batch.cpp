@@ -110,6 +110,8 @@ struct gs_batch {
     uint64_t *keys = nullptr, *alt_k = nullptr;
     uint32_t *vals = nullptr, *alt_v = nullptr;
     void* pair_grad = nullptr;   // per-pair image-space gradients of the backward
+    uint64_t* masks = nullptr;   // per-pair cell masks the forward keeps for the backward
+    int mask_words = 1;          // mask words per pair (most over the candidate tile shapes)
     void* sort_ws = nullptr;
     size_t sort_ws_bytes = 0;
     uint32_t* ranges = nullptr;
@@ -146,8 +148,8 @@ struct gs_batch {
         if (graph) (void)hipGraphDestroy(graph);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         void* ptrs[] = {d_views, d_jobs, d_targets, rec, depth, rect, tt, g2d, first, scan_ws, keys, alt_k, vals,
-                        alt_v, pair_grad, sort_ws, ranges, pair_count, status, queue, tiles_dev, tkeys, tkeys_alt, tvals, tvals_alt,
-                        tsort_ws, final_T, n_contrib, dimg, loss_ws, sched};
+                        alt_v, pair_grad, masks, sort_ws, ranges, pair_count, status, queue, tiles_dev, tkeys, tkeys_alt, tvals,
+                        tvals_alt, tsort_ws, final_T, n_contrib, dimg, loss_ws, sched};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
     }
@@ -219,6 +221,7 @@ struct gs_batch {
         r.n_tiles = n_tiles;
         r.tw = tw;
         r.th = th;
+        r.masks = masks;
         if (persistent) {
             launch_tile_len_keys(ranges, n_tiles, tkeys, tvals, st);
             launch_sort_pairs(tkeys, tvals, tkeys_alt, tvals_alt, tiles_dev, max_tiles, 20, false, tsort_ws, st);
@@ -265,16 +268,18 @@ struct gs_batch {
 
     gs_status alloc_pairs(int64_t cap) {
         if (cap > kMaxPairs) return fail(GS_ERR_CAPACITY, "batch needs %lld pairs (> 2^30-1)", (long long)cap);
-        for (void* p : {(void*)keys, (void*)alt_k, (void*)vals, (void*)alt_v, pair_grad, sort_ws})
+        for (void* p : {(void*)keys, (void*)alt_k, (void*)vals, (void*)alt_v, pair_grad, (void*)masks, sort_ws})
             if (p) (void)hipFree(p);
         keys = alt_k = nullptr;
         vals = alt_v = nullptr;
         pair_grad = sort_ws = nullptr;
+        masks = nullptr;
         gs_status s;
         sort_ws_bytes = sort_workspace_bytes(cap, 64);
         if ((s = dmalloc(&keys, cap)) || (s = dmalloc(&alt_k, cap)) || (s = dmalloc(&vals, cap)) ||
             (s = dmalloc(&alt_v, cap)) || (s = dmalloc(reinterpret_cast<char**>(&sort_ws), sort_ws_bytes)) ||
-            (s = dmalloc(reinterpret_cast<char**>(&pair_grad), pair_grad_bytes(cap))))
+            (s = dmalloc(reinterpret_cast<char**>(&pair_grad), pair_grad_bytes(cap))) ||
+            (s = dmalloc(&masks, cap * mask_words)))
             return s;
         capacity = cap;
         return GS_OK;
@@ -515,6 +520,7 @@ gs_status gs_batch_create(const gs_gaussians* cells, const gs_camera* cams, cons
         uint32_t p = 0;
         if ((s = b->set_tiles(c.tw, c.th, st)) || (s = b->pairs_needed(st, &p))) break;
         need = std::max(need, p);
+        b->mask_words = std::max(b->mask_words, render_mask_words(c.tw, c.th));
     }
     if (!s) s = b->alloc_pairs((int64_t)std::ceil(need * b->headroom) + 4096);
     // autotune: time every candidate (eager launches), keep the fastest

@@ -85,9 +85,15 @@ struct RenderArgs {
     uint32_t* queue;
     const uint32_t* order;
     int persistent_grid;
+    // Optional, render_mask_words(tw, th) words per sorted pair: the
+    // forward stores each pair's cell mask of every wave of its tile, the
+    // backward reads them instead of recomputing (NULL: not kept).
+    uint64_t* masks;
 };
 
 bool render_tile_supported(int tw, int th);
+// Cell-mask words per sorted pair (waves of a tile's workgroup).
+int render_mask_words(int tw, int th);
 // image/final_T/n_contrib are the stacked planes of all views.  stats !=
 // NULL runs the counting variant instead (no image written); state !=
 // NULL also stores the per-entry blend state (pairs * tile pixels).

@@ -19,7 +19,8 @@
 //
 // Walk: one lane per cell of CW x CH pixels (blend_cells.h); each lane
 // walks, from the back, only the list entries whose support reaches its
-// cell and that lie before its pixels' last contributor.  The list is
+// cell and that lie before its pixels' last contributor (the cell masks are
+// the forward's when it kept them, else recomputed the same way).  The list is
 // taken in chunks of at most 64 entries from the back.  Accumulation: for
 // every (cell, entry) it walks, a lane adds its pixels' nine gradient
 // terms in registers and writes the sums once, with plain stores, to a slot
@@ -58,6 +59,7 @@ struct BwdArgs {
     float* pg1;             // per pair: db
     int64_t cap;            // pair capacity
     const float2* state;
+    const uint64_t* masks;  // per sorted pair and wave: the forward's cell masks (NULL = recompute)
     uint32_t* queue;        // persistent launch: next queue position (zeroed before launch)
     const uint32_t* order;  // persistent launch: tiles in processing order (NULL = 0, 1, ...)
     uint32_t n_tiles;
@@ -138,13 +140,17 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
     while (hi > 0) {
         const int lo0 = hi > kChunk ? hi - kChunk : 0;
         const int ncand = hi - lo0;
+        // the forward's mask of candidate `lane` for this wave, loaded
+        // while the entries are staged
+        uint64_t mk = 0ull;
+        if (a.masks && lane < ncand) mk = a.masks[(int64_t)(rg.x + (uint32_t)(lo0 + lane)) * L::WAVES + wv];
         __syncthreads();   // the previous chunk's slots and staged entries are no longer read
         stage_batch<1>(sh.s, a.rec, a.vals, rg.x + (uint32_t)lo0, ncand, tid, L::NCELL, sh.gid);
         __syncthreads();
 
         // entry-major cell masks of this wave, transposed into the lane's
         // walk word, cut at the cell's last contributor, and back
-        const uint64_t m = lane < ncand ? cell_mask<L>(sh.s[lane], x0, wy0) : 0ull;
+        const uint64_t m = lane < ncand ? (a.masks ? mk : cell_mask<L>(sh.s[lane], x0, wy0)) : 0ull;
         uint64_t walk = transpose64(m, lane);
         {
             const int lim = (int)cell_last - lo0;   // entries lo0 + k with k < lim
@@ -435,6 +441,7 @@ void launch_render_bwd(const RenderArgs& r, const float* final_T, const uint32_t
     a.pg1 = reinterpret_cast<float*>(static_cast<char*>(pairs) + (size_t)capacity * 32);
     a.cap = capacity;
     a.state = state;
+    a.masks = r.masks;
     a.queue = r.queue;
     a.order = r.order;
     a.n_tiles = r.n_tiles;

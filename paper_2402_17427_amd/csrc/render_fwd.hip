@@ -16,6 +16,9 @@
 // lane then walks its own entries of the whole batch in list order, with
 // its pixels' state in registers.  Skipping the other entries never
 // changes a result: they have alpha < 1/255 at every pixel of the cell.
+// When the caller keeps them, every computed mask is also stored per
+// sorted pair and wave, so that the backward walks the same entries
+// without recomputing the chords.
 // Tiles of several views are numbered consecutively; a tile finds its view
 // (camera, image planes) in the view table.
 #include "blend_cells.h"
@@ -50,6 +53,7 @@ struct FwdArgs {
     uint32_t* n_contrib;
     unsigned long long* stats;
     float2* state;
+    uint64_t* masks;        // per sorted pair and wave: the cell mask (NULL = not kept)
     uint32_t* queue;        // persistent launch: next queue position (zeroed before launch)
     const uint32_t* order;  // persistent launch: tiles in processing order (NULL = 0, 1, ...)
     uint32_t n_tiles;
@@ -136,6 +140,8 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdSha
             if (q * kWave >= nb) break;
             const int k = q * kWave + lane;
             const uint64_t m = k < nb ? cell_mask<L>(sh.s[k], x0, wy0) : 0ull;
+            // kept for the backward, which walks the same entries
+            if (MODE != kStats && a.masks && k < nb) a.masks[(int64_t)(b0 + (uint32_t)k) * L::WAVES + wv] = m;
             uint64_t t = transpose64(m, lane);
             if (all_done) t = 0ull;
             if (t != 0ull) {
@@ -291,6 +297,16 @@ bool render_tile_supported(int tw, int th) {
            (tw == 32 && th == 16) || (tw == 32 && th == 32);
 }
 
+int render_mask_words(int tw, int th) {
+    if (tw == 16 && th == 16) return CellsFor<16, 16>::L::WAVES;
+    if (tw == 8 && th == 8) return CellsFor<8, 8>::L::WAVES;
+    if (tw == 16 && th == 8) return CellsFor<16, 8>::L::WAVES;
+    if (tw == 32 && th == 8) return CellsFor<32, 8>::L::WAVES;
+    if (tw == 32 && th == 16) return CellsFor<32, 16>::L::WAVES;
+    if (tw == 32 && th == 32) return CellsFor<32, 32>::L::WAVES;
+    return 0;
+}
+
 void launch_render_fwd(const RenderArgs& r, float* image, float* final_T, uint32_t* n_contrib,
                        unsigned long long* stats, float2* state, hipStream_t st) {
     if (r.n_tiles == 0) return;
@@ -305,6 +321,7 @@ void launch_render_fwd(const RenderArgs& r, float* image, float* final_T, uint32
     a.n_contrib = n_contrib;
     a.stats = stats;
     a.state = state;
+    a.masks = stats ? nullptr : r.masks;
     a.queue = r.queue;
     a.order = r.order;
     a.n_tiles = r.n_tiles;

@@ -84,7 +84,7 @@ class Frame:
     `ensure_capacity`/`check_status`, which read the device status)."""
 
     def __init__(self, n: int, sh_degree: int, cam, tile=(16, 16), capacity: int | None = None,
-                 device="cuda", grads: bool = True):
+                 device="cuda", grads: bool = True, keep_masks: bool = True):
         self.n, self.sh_degree, self.device = int(n), int(sh_degree), device
         self.cam = cam
         self.c_cam = N.make_camera(cam)
@@ -116,8 +116,10 @@ class Frame:
         self.g_sh = torch.empty((3 * K, ng), dtype=torch.float32, device=device)
         self.grad2d = torch.empty((9, ng), dtype=torch.float32, device=device)
         self.has_grads = grads
+        # the forward keeps its cell masks for the backward (gradient frames)
+        self.keep_masks = bool(grads and keep_masks)
         self.capacity = 0
-        self.keys = self.vals = self.ws = self.bwd_ws = None
+        self.keys = self.vals = self.ws = self.bwd_ws = self.masks = None
         self.set_capacity(capacity if capacity is not None else max(2 * self.n, 1 << 16))
         del npix
 
@@ -137,6 +139,10 @@ class Frame:
             # float32 storage keeps the 16-byte alignment the ABI asks for
             self.bwd_ws = torch.empty(max((int(nbytes.value) + 15) // 16 * 4, 4), dtype=torch.float32,
                                       device=self.device)
+        if self.keep_masks:
+            self.masks = None
+            N.call("gs_render_mask_bytes", C.byref(self.c_bins()), C.byref(self.c_opts), C.byref(nbytes))
+            self.masks = torch.empty(max(int(nbytes.value) // 8, 1), dtype=torch.int64, device=self.device)
 
     def c_proj(self) -> N.gs_proj:
         p = N.gs_proj()
@@ -150,6 +156,7 @@ class Frame:
         b.first = _ptr(self.first)
         b.pair_count, b.status = _ptr(self.pair_count), _ptr(self.status)
         b.pair_capacity = self.capacity
+        b.cell_masks = _ptr(self.masks) if self.masks is not None else None
         return b
 
     def c_grads(self, out: dict | None = None) -> N.gs_grads:

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_error_strings():
     lib = N.lib()
-    assert lib.gs_abi_version() == 1
+    assert lib.gs_abi_version() == 2
     nbytes = C.c_size_t(0)
     assert lib.gs_bin_sort_workspace(-1, 10, 4, C.byref(nbytes)) == N.GS_ERR_INVALID
     assert b"bad sizes" in lib.gs_last_error()

@@ -261,6 +261,34 @@ def test_backward_matches_oracle_gradient(name, tile):
         grad_close(k, out[k][..., keep], rb[k][..., keep])
 
 
+@pytest.mark.parametrize("name,tile", [("city_dense", t) for t in TILES] + [("city_ragged", (16, 16))])
+def test_backward_with_the_forward_masks_equals_the_recomputing_backward(name, tile):
+    """The backward that reads the cell masks the forward kept walks exactly
+    the entries of the one that recomputes them, so every gradient is
+    bitwise the same; and each is bitwise repeatable (fixed-order sums)."""
+    _case(f"kept masks {name} tile={tile}")
+    g, cam = _scene(name)
+    dg = raster.DeviceGaussians.from_host(g)
+    f = raster.render(dg, cam, tile=tile)
+    assert f.masks is not None
+    dimg = torch.as_tensor(scenes.grad_image(cam, 7, "normal")).cuda()
+
+    def grads():
+        return {k: v.cpu().numpy().copy() for k, v in raster.render_backward(f, dg, dimg).items()}
+
+    kept = grads()
+    again = grads()
+    masks, f.masks = f.masks, None
+    try:
+        recomputed = grads()
+    finally:
+        f.masks = masks
+    for k in kept:
+        np.testing.assert_array_equal(kept[k], again[k], err_msg=f"repeat {k}")
+        np.testing.assert_array_equal(kept[k], recomputed[k], err_msg=f"kept vs recomputed {k}")
+    assert np.abs(kept["grad2d"]).max() > 0
+
+
 def test_capacity_overflow_sets_status_and_poisons_outputs():
     _case("capacity overflow")
     g, cam = _scene("config1")
