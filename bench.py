@@ -134,17 +134,23 @@ def parse():
     ap.add_argument("--no-loss", action="store_true",
                     help="skip the measurements around the rasterizer (loss, training step, appearance model, "
                          "partitioning)")
-    ap.add_argument("--serve-rates", type=float, nargs="+", default=(50.0, 100.0, 200.0, 400.0, 1000.0),
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=(50.0, 100.0, 200.0, 400.0, 1000.0, 2000.0),
                     help="Poisson arrival rates (req/s); the last lies above the unbatched server's saturation")
-    ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per rate")
-    ap.add_argument("--serve-warmup", type=int, default=200, help="warm-up requests per rate (not measured)")
+    ap.add_argument("--serve-requests", type=int, default=500, help="measured requests per rate")
+    ap.add_argument("--serve-warmup", type=int, default=100, help="warm-up requests per rate (not measured)")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="the full serving protocol: 200 warm-up and 2000 measured requests per rate (arrivals run "
+                         "in real time, so this takes about four minutes)")
     ap.add_argument("--no-autograd", action="store_true", help="skip the autograd-form measurement")
     ap.add_argument("--serve-grid", type=int, default=10, help="merged scene: grid x grid cells of 200k Gaussians")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run one elementwise kernel that reads and writes MIB MiB "
                          "(float32): the reference that scales the HBM byte counters of a profiling run")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.serve_full:
+        args.serve_requests, args.serve_warmup = 2000, 200
+    return args
 
 
 def traffic_record(kernel, summary="hbm_traffic_cell_1M_1080p.md"):
@@ -1014,6 +1020,9 @@ def main():
         wins = [r["rate_hz"] for r in serving["rates"]
                 if r["batched"]["p99_ms"] < r["unbatched"]["p99_ms"] and r["batched"]["p50_ms"] <= r["unbatched"]["p50_ms"]]
         serving["batching_beats_one_view_batches_at_hz"] = wins
+        serving["protocol"] = (f"{args.serve_warmup} warm-up + {args.serve_requests} measured requests per rate, "
+                               "Poisson arrivals in real time" + (" (full protocol)" if args.serve_full else
+                                                                  " (short run; --serve-full: 200 + 2000)"))
         serving["summary_p50_p99_ms"] = [
             {"rate_hz": r["rate_hz"], "batched": [r["batched"]["p50_ms"], r["batched"]["p99_ms"]],
              "unbatched": [r["unbatched"]["p50_ms"], r["unbatched"]["p99_ms"]],

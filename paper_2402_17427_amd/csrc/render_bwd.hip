@@ -67,6 +67,9 @@ struct BwdArgs {
 
 template <class L>
 struct BwdShared {
+    // one entry can reach every cell of the workgroup: its slots must fit,
+    // or a chunk could not take even its top candidate
+    static_assert(kItemCap >= L::NCELL, "slot capacity below the cells of a tile");
     Staged s[kChunk];
     uint32_t gid[kChunk];
     uint64_t mask[L::WAVES][kChunk];   // per wave: the cells that walk each entry
