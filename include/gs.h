@@ -461,8 +461,9 @@ gs_status gs_appearance_bwd(const float *image, int32_t width, int32_t height, c
  * several cells of uneven Gaussian counts together: each stage is one
  * launch over all cells, the blends are persistent grids pulling tiles
  * longest list first, and the step is captured once as a hipGraph and
- * replayed by gs_batch_step.  With `autotune` the tile shape and the launch
- * form are chosen at creation by timing each candidate on the batch.
+ * replayed by gs_batch_step.  With `autotune` the tile shape, the launch
+ * form, the blends' LDS batch and slot capacity and the persistent grid
+ * size are chosen at creation by timing each candidate on the batch.
  *
  * gs_batch_create: cells[n_cells] (device SoA planes, one SH degree for all)
  * and cams[n_cells] (host) define the cells and their training views;
@@ -506,7 +507,12 @@ typedef struct {
     double capacity_headroom;   /* pair capacity = headroom x pairs needed at creation (<= 1: 1.25) */
     float loss_lambda;          /* Eq. 1 D-SSIM weight (gs_loss); 0 = the L1 loss alone */
     const gs_batch_optim *optim; /* NULL = no optimiser step in the batch step */
-} gs_batch_config;              /* NULL = {16, 16, 1, 1, 0, 1.25, 0, NULL} */
+    /* Persistent blend grids only (ignored with autotune, which times its
+     * own choices): */
+    int32_t fwd_batch;          /* forward's staged list entries per LDS batch: 0 = 256, or 128 */
+    int32_t item_cap;           /* backward's (cell, entry) slots per chunk: 0 = 512, or 256 */
+    int32_t grid_pct;           /* grid = this % of the workgroups that fit at once: 0 = 100, 1..100 */
+} gs_batch_config;              /* NULL = {16, 16, 1, 1, 0, 1.25, 0, NULL, 0, 0, 0} */
 typedef struct {
     int32_t tile_w, tile_h, persistent, use_graph, grid_fwd, grid_bwd;
     uint32_t n_tiles;
@@ -514,6 +520,8 @@ typedef struct {
     int32_t n_candidates;       /* autotune: candidates timed, in order */
     int32_t cand_tile_w[16], cand_tile_h[16], cand_persistent[16];
     double cand_ms[16];         /* mean step time of each candidate */
+    int32_t fwd_batch, item_cap, grid_pct;   /* the chosen LDS batch, slot capacity and grid share */
+    int32_t cand_fwd_batch[16], cand_item_cap[16], cand_grid_pct[16];
 } gs_batch_stats;
 
 gs_status gs_batch_create(const gs_gaussians *cells, const gs_camera *cams, const float *const *targets,

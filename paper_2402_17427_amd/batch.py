@@ -28,14 +28,18 @@ class gs_batch_optim(C.Structure):
 class gs_batch_config(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("persistent", C.c_int32), ("use_graph", C.c_int32),
                 ("autotune", C.c_int32), ("capacity_headroom", C.c_double), ("loss_lambda", C.c_float),
-                ("optim", C.POINTER(gs_batch_optim))]
+                ("optim", C.POINTER(gs_batch_optim)), ("fwd_batch", C.c_int32), ("item_cap", C.c_int32),
+                ("grid_pct", C.c_int32)]
 
 
 class gs_batch_stats(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("persistent", C.c_int32), ("use_graph", C.c_int32),
                 ("grid_fwd", C.c_int32), ("grid_bwd", C.c_int32), ("n_tiles", C.c_uint32), ("slots", C.c_int64),
                 ("pair_capacity", C.c_int64), ("n_candidates", C.c_int32), ("cand_tile_w", C.c_int32 * 16),
-                ("cand_tile_h", C.c_int32 * 16), ("cand_persistent", C.c_int32 * 16), ("cand_ms", C.c_double * 16)]
+                ("cand_tile_h", C.c_int32 * 16), ("cand_persistent", C.c_int32 * 16), ("cand_ms", C.c_double * 16),
+                ("fwd_batch", C.c_int32), ("item_cap", C.c_int32), ("grid_pct", C.c_int32),
+                ("cand_fwd_batch", C.c_int32 * 16), ("cand_item_cap", C.c_int32 * 16),
+                ("cand_grid_pct", C.c_int32 * 16)]
 
 
 N.register("gs_batch_create", [C.POINTER(N.gs_gaussians), C.POINTER(N.gs_camera), C.POINTER(C.c_void_p), C.c_int32,
@@ -51,7 +55,7 @@ class BatchStep:
     def __init__(self, cells: list[DeviceGaussians], cams, targets: list[torch.Tensor], tile=(16, 16),
                  persistent=True, use_graph=True, autotune=False, headroom=1.25, stream=None,
                  loss_lambda: float = 0.0, optimizers=None, lr_mean_final: float = 0.0, lr_mean_steps: int = 0,
-                 **hyper):
+                 fwd_batch: int = 0, item_cap: int = 0, grid_pct: int = 0, **hyper):
         n = len(cells)
         assert n == len(cams) == len(targets) and n > 0
         dev = cells[0].mean.device
@@ -84,7 +88,8 @@ class BatchStep:
         c_cams = (N.gs_camera * n)(*[N.make_camera(c) for c in cams])
         c_tg = (C.c_void_p * n)(*[t.data_ptr() for t in self.targets])
         cfg = gs_batch_config(int(tile[0]), int(tile[1]), int(bool(persistent)), int(bool(use_graph)),
-                              int(bool(autotune)), float(headroom), float(loss_lambda), None)
+                              int(bool(autotune)), float(headroom), float(loss_lambda), None, int(fwd_batch),
+                              int(item_cap), int(grid_pct))
         keep_opt = None
         if optimizers is not None:
             from . import optim
@@ -120,10 +125,12 @@ class BatchStep:
         s = gs_batch_stats()
         N.call("gs_batch_info", self._h, C.byref(s))
         cands = [dict(tile=(s.cand_tile_w[i], s.cand_tile_h[i]), persistent=bool(s.cand_persistent[i]),
+                      fwd_batch=s.cand_fwd_batch[i], item_cap=s.cand_item_cap[i], grid_pct=s.cand_grid_pct[i],
                       ms=s.cand_ms[i]) for i in range(s.n_candidates)]
         return dict(tile=(s.tile_w, s.tile_h), persistent=bool(s.persistent), use_graph=bool(s.use_graph),
-                    grid_fwd=s.grid_fwd, grid_bwd=s.grid_bwd, n_tiles=s.n_tiles, slots=s.slots,
-                    pair_capacity=s.pair_capacity, candidates=cands)
+                    grid_fwd=s.grid_fwd, grid_bwd=s.grid_bwd, fwd_batch=s.fwd_batch, item_cap=s.item_cap,
+                    grid_pct=s.grid_pct, n_tiles=s.n_tiles, slots=s.slots, pair_capacity=s.pair_capacity,
+                    candidates=cands)
 
     def status(self, stream=None):
         st = C.c_int32(0)

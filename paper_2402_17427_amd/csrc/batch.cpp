@@ -26,11 +26,17 @@ namespace gs {
 
 namespace {
 
+// An autotune candidate: tile shape, launch form and, for persistent grids,
+// the LDS knobs (small = half the default forward batch and backward slot
+// capacity) and the grid's share of the workgroups that fit at once.
 struct Cand {
-    int tw, th, persistent;
+    int tw, th, persistent, small_lds, grid_pct;
 };
 
-const Cand kCands[] = {{16, 16, 1}, {16, 16, 0}, {32, 16, 1}, {32, 16, 0}, {16, 8, 1}, {32, 8, 1}};
+const Cand kCands[] = {{16, 16, 1, 0, 100}, {16, 16, 0, 0, 100}, {32, 16, 1, 0, 100}, {32, 16, 0, 0, 100},
+                       {16, 8, 1, 0, 100},  {32, 8, 1, 0, 100},  {16, 16, 1, 1, 100}, {32, 16, 1, 1, 100},
+                       {16, 16, 1, 0, 75},  {32, 16, 1, 0, 75}};
+static_assert(sizeof(kCands) / sizeof(kCands[0]) <= 16, "gs_batch_stats holds 16 candidates");
 
 template <typename T>
 gs_status dmalloc(T** p, size_t count) {
@@ -87,6 +93,7 @@ struct gs_batch {
     // chosen configuration
     int tw = 16, th = 16, persistent = 1, use_graph = 1;
     int grid_fwd = 0, grid_bwd = 0;
+    int fwd_batch = 0, item_cap = 0, grid_pct = 100;   // persistent grids: LDS knobs (0 = default), grid share
     uint32_t n_tiles = 0;
     int64_t capacity = 0;
     std::vector<double> tune_ms;   // per candidate (autotune), -1 when skipped
@@ -160,6 +167,13 @@ struct gs_batch {
         return t;
     }
 
+    // LDS knobs and grid share of an autotune candidate.
+    void set_knobs(const Cand& c) {
+        fwd_batch = c.small_lds ? render_fwd_batch_small() : 0;
+        item_cap = c.small_lds ? render_item_cap_small() : 0;
+        grid_pct = c.grid_pct;
+    }
+
     // View table for a tile shape (host copy + upload).
     gs_status set_tiles(int w, int h, hipStream_t st) {
         tw = w;
@@ -177,8 +191,8 @@ struct gs_batch {
             hipMemcpyAsync(tiles_dev, &n_tiles, sizeof(uint32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             return check_hip("gs_batch: view table upload");
-        grid_fwd = render_persistent_grid(w, h, false);
-        grid_bwd = render_persistent_grid(w, h, true);
+        grid_fwd = std::max(1, render_persistent_grid(w, h, false, fwd_batch) * grid_pct / 100);
+        grid_bwd = std::max(1, render_persistent_grid(w, h, true, item_cap) * grid_pct / 100);
         return GS_OK;
     }
 
@@ -222,6 +236,8 @@ struct gs_batch {
         r.tw = tw;
         r.th = th;
         r.masks = masks;
+        r.fwd_batch = fwd_batch;
+        r.item_cap = item_cap;
         if (persistent) {
             launch_tile_len_keys(ranges, n_tiles, tkeys, tvals, st);
             launch_sort_pairs(tkeys, tvals, tkeys_alt, tvals_alt, tiles_dev, max_tiles, 20, false, tsort_ws, st);
@@ -372,6 +388,22 @@ gs_status gs_batch_create(const gs_gaussians* cells, const gs_camera* cams, cons
     b->use_graph = cfg ? (cfg->use_graph != 0) : 1;
     b->headroom = cfg && cfg->capacity_headroom > 1.0 ? cfg->capacity_headroom : 1.25;
     b->lambda = cfg ? cfg->loss_lambda : 0.f;
+    if (cfg && cfg->fwd_batch) {
+        if (cfg->fwd_batch == render_fwd_batch_small()) b->fwd_batch = cfg->fwd_batch;
+        else if (cfg->fwd_batch != render_fwd_batch_default())
+            s = fail(GS_ERR_INVALID, "fwd_batch %d: 0, %d or %d", cfg->fwd_batch, render_fwd_batch_default(),
+                     render_fwd_batch_small());
+    }
+    if (cfg && cfg->item_cap) {
+        if (cfg->item_cap == render_item_cap_small()) b->item_cap = cfg->item_cap;
+        else if (cfg->item_cap != render_item_cap_default())
+            s = fail(GS_ERR_INVALID, "item_cap %d: 0, %d or %d", cfg->item_cap, render_item_cap_default(),
+                     render_item_cap_small());
+    }
+    if (cfg && cfg->grid_pct) {
+        if (cfg->grid_pct < 1 || cfg->grid_pct > 100) s = fail(GS_ERR_INVALID, "grid_pct %d not in 1..100", cfg->grid_pct);
+        else b->grid_pct = cfg->grid_pct;
+    }
     if (!s && (!std::isfinite(b->lambda) || b->lambda < 0.f)) s = fail(GS_ERR_INVALID, "loss_lambda must be >= 0");
     const gs_batch_optim* opt = cfg ? cfg->optim : nullptr;
     if (!s && opt) s = check_batch_optim(opt, cells, grads, n_cells);
@@ -513,7 +545,7 @@ gs_status gs_batch_create(const gs_gaussians* cells, const gs_camera* cams, cons
     // capacity: the most pairs any candidate tile shape needs, with headroom
     std::vector<Cand> cands;
     if (autotune) cands.assign(std::begin(kCands), std::end(kCands));
-    else cands.push_back({tw0, th0, b->persistent});
+    else cands.push_back({tw0, th0, b->persistent, 0, b->grid_pct});
     uint32_t need = 0;
     for (const Cand& c : cands) {
         if (s) break;
@@ -532,6 +564,7 @@ gs_status gs_batch_create(const gs_gaussians* cells, const gs_camera* cams, cons
         for (const Cand& c : cands) {
             double ms = -1;
             b->persistent = c.persistent;
+            b->set_knobs(c);
             if ((s = b->set_tiles(c.tw, c.th, st)) || (s = b->time_steps(st, 2, 5, &ms))) break;
             int32_t dst = 0;
             if ((s = b->device_status(st, &dst))) break;
@@ -544,6 +577,7 @@ gs_status gs_batch_create(const gs_gaussians* cells, const gs_camera* cams, cons
         }
         b->use_graph = saved_graph;
         b->persistent = pick.persistent;
+        b->set_knobs(pick);
         if (!s) s = b->set_tiles(pick.tw, pick.th, st);
     } else if (!s) {
         s = b->set_tiles(tw0, th0, st);
@@ -572,6 +606,9 @@ gs_status gs_batch_info(const gs_batch* b, gs_batch_stats* info) {
     info->use_graph = b->use_graph && b->exec != nullptr;
     info->grid_fwd = b->grid_fwd;
     info->grid_bwd = b->grid_bwd;
+    info->fwd_batch = b->fwd_batch ? b->fwd_batch : render_fwd_batch_default();
+    info->item_cap = b->item_cap ? b->item_cap : render_item_cap_default();
+    info->grid_pct = b->grid_pct;
     info->n_tiles = b->n_tiles;
     info->slots = b->nslots;
     info->pair_capacity = b->capacity;
@@ -580,6 +617,9 @@ gs_status gs_batch_info(const gs_batch* b, gs_batch_stats* info) {
         info->cand_tile_w[i] = kCands[i].tw;
         info->cand_tile_h[i] = kCands[i].th;
         info->cand_persistent[i] = kCands[i].persistent;
+        info->cand_fwd_batch[i] = kCands[i].small_lds ? render_fwd_batch_small() : render_fwd_batch_default();
+        info->cand_item_cap[i] = kCands[i].small_lds ? render_item_cap_small() : render_item_cap_default();
+        info->cand_grid_pct[i] = kCands[i].grid_pct;
         info->cand_ms[i] = b->tune_ms[i];
     }
     return GS_OK;

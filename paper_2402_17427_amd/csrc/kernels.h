@@ -89,6 +89,10 @@ struct RenderArgs {
     // forward stores each pair's cell mask of every wave of its tile, the
     // backward reads them instead of recomputing (NULL: not kept).
     uint64_t* masks;
+    // Persistent launches only: the forward's staged entries per batch
+    // (render_fwd_batch_small() or the default) and the backward's slots
+    // per chunk (render_item_cap_small() or the default); 0 = default.
+    int fwd_batch, item_cap;
 };
 
 bool render_tile_supported(int tw, int th);
@@ -117,8 +121,13 @@ void launch_pair_zero(void* pairs, const uint32_t* pair_count, int64_t capacity,
 void launch_pair_gather(int64_t nslots, const uint32_t* first, const uint32_t* tiles_touched, const void* pairs,
                         int64_t capacity, const int32_t* status, float* g2d, hipStream_t st);
 
-// Workgroups of a persistent blend launch that fit on the device at once.
-int render_persistent_grid(int tw, int th, bool backward);
+// Workgroups of a persistent blend launch that fit on the device at once
+// (lds_knob: the fwd_batch or item_cap it will run with, 0 = default).
+int render_persistent_grid(int tw, int th, bool backward, int lds_knob = 0);
+int render_fwd_batch_default();
+int render_fwd_batch_small();
+int render_item_cap_default();
+int render_item_cap_small();
 
 // ---- batched step (batch_kernels.hip)
 // L1 loss of every view against its target ([3][H][W] each; targets is a

@@ -43,6 +43,9 @@ constexpr int kChunk = 64;      // candidate entries per chunk (one walk word)
 #define GS_ITEM_CAP 512
 #endif
 constexpr int kItemCap = GS_ITEM_CAP;   // (cell, entry) slots per chunk (>= 64 x waves of any layout)
+// slot capacities of the persistent launch (a tuning knob of the batched
+// step): kItemCap, or the half of it
+constexpr int kItemCapSmall = kItemCap / 2;
 
 struct BwdArgs {
     const Rec* rec;
@@ -65,25 +68,25 @@ struct BwdArgs {
     uint32_t n_tiles;
 };
 
-template <class L>
+template <class L, int CAP>
 struct BwdShared {
     // one entry can reach every cell of the workgroup: its slots must fit,
     // or a chunk could not take even its top candidate
-    static_assert(kItemCap >= L::NCELL, "slot capacity below the cells of a tile");
+    static_assert(CAP >= L::NCELL, "slot capacity below the cells of a tile");
     Staged s[kChunk];
     uint32_t gid[kChunk];
     uint64_t mask[L::WAVES][kChunk];   // per wave: the cells that walk each entry
     uint32_t base[L::WAVES][kChunk];   // items per (wave, entry), then their first slot
     uint32_t total[kChunk];            // items per entry
-    float item[9][kItemCap];           // the nine sums of each (cell, entry)
+    float item[9][CAP];                // the nine sums of each (cell, entry)
     uint32_t max_last;
     int kmin;                          // the chunk: candidates kmin .. ncand - 1
 };
 
 // STORED = true reads each entry's (alpha, T) from the state the storing
 // forward wrote (alpha negated when capped) instead of recomputing them.
-template <class L, bool STORED>
-__device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdShared<L>& sh) {
+template <class L, bool STORED, int CAP>
+__device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdShared<L, CAP>& sh) {
     constexpr int NP = L::NP;
     if (*a.status != 0) return;
 
@@ -177,7 +180,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
                 const uint32_t y = (uint32_t)__shfl_down((int)suf, d, kWave);
                 if (lane + d < kWave) suf += y;
             }
-            const bool in = lane < ncand && suf <= (uint32_t)kItemCap;
+            const bool in = lane < ncand && suf <= (uint32_t)CAP;
             const uint64_t inm = __ballot(in);
             if (lane == 0) sh.kmin = inm ? low_bit(inm) : ncand;
             uint32_t b = suf - tot;   // slots of the entries above
@@ -323,13 +326,13 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
 
 template <class L, bool STORED>
 __global__ __launch_bounds__(L::NCELL) void k_render_bwd(BwdArgs a) {
-    __shared__ BwdShared<L> sh;
-    bwd_tile<L, STORED>(a, blockIdx.x, sh);
+    __shared__ BwdShared<L, kItemCap> sh;
+    bwd_tile<L, STORED, kItemCap>(a, blockIdx.x, sh);
 }
 
-template <class L>
+template <class L, int CAP>
 __global__ __launch_bounds__(L::NCELL) void k_render_bwd_persistent(BwdArgs a) {
-    __shared__ BwdShared<L> sh;
+    __shared__ BwdShared<L, CAP> sh;
     __shared__ uint32_t s_next;
     for (;;) {
         __syncthreads();
@@ -337,7 +340,7 @@ __global__ __launch_bounds__(L::NCELL) void k_render_bwd_persistent(BwdArgs a) {
         __syncthreads();
         const uint32_t q = s_next;
         if (q >= a.n_tiles) break;
-        bwd_tile<L, false>(a, a.order ? a.order[q] : q, sh);
+        bwd_tile<L, false, CAP>(a, a.order ? a.order[q] : q, sh);
     }
 }
 
@@ -385,21 +388,27 @@ __global__ __launch_bounds__(256) void k_pair_gather(int64_t nslots, const uint3
 }
 
 template <int TW, int TH>
-void launch_t(const BwdArgs& a, int persistent_grid, hipStream_t st) {
+void launch_t(const BwdArgs& a, int persistent_grid, int cap, hipStream_t st) {
     using L = typename CellsFor<TW, TH>::L;
     const dim3 block(L::NCELL);
     if (a.state)
         hipLaunchKernelGGL((k_render_bwd<L, true>), dim3(a.n_tiles), block, 0, st, a);
+    else if (persistent_grid > 0 && cap == kItemCapSmall && kItemCapSmall >= L::NCELL)
+        hipLaunchKernelGGL((k_render_bwd_persistent<L, (kItemCapSmall >= L::NCELL ? kItemCapSmall : kItemCap)>),
+                           dim3(persistent_grid), block, 0, st, a);
     else if (persistent_grid > 0)
-        hipLaunchKernelGGL((k_render_bwd_persistent<L>), dim3(persistent_grid), block, 0, st, a);
+        hipLaunchKernelGGL((k_render_bwd_persistent<L, kItemCap>), dim3(persistent_grid), block, 0, st, a);
     else
         hipLaunchKernelGGL((k_render_bwd<L, false>), dim3(a.n_tiles), block, 0, st, a);
 }
 
 template <int TW, int TH>
-hipError_t occupancy_t(int* per) {
+hipError_t occupancy_t(int* per, int cap) {
     using L = typename CellsFor<TW, TH>::L;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_render_bwd_persistent<L>, L::NCELL, 0);
+    if (cap == kItemCapSmall && kItemCapSmall >= L::NCELL)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            per, k_render_bwd_persistent<L, (kItemCapSmall >= L::NCELL ? kItemCapSmall : kItemCap)>, L::NCELL, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_render_bwd_persistent<L, kItemCap>, L::NCELL, 0);
 }
 
 }  // namespace
@@ -450,7 +459,7 @@ void launch_render_bwd(const RenderArgs& r, const float* final_T, const uint32_t
     a.n_tiles = r.n_tiles;
     const int pg = (r.queue && !state) ? r.persistent_grid : 0;
     if (pg > 0) launch_fill_u32(r.queue, 0u, 1, st);
-#define GS_BWD(x, y) launch_t<x, y>(a, pg, st)
+#define GS_BWD(x, y) launch_t<x, y>(a, pg, r.item_cap, st)
     if (r.tw == 16 && r.th == 16) GS_BWD(16, 16);
     else if (r.tw == 8 && r.th == 8) GS_BWD(8, 8);
     else if (r.tw == 16 && r.th == 8) GS_BWD(16, 8);
@@ -460,17 +469,20 @@ void launch_render_bwd(const RenderArgs& r, const float* final_T, const uint32_t
 #undef GS_BWD
 }
 
-int render_persistent_grid_bwd(int tw, int th) {
+int render_item_cap_default() { return kItemCap; }
+int render_item_cap_small() { return kItemCapSmall; }
+
+int render_persistent_grid_bwd(int tw, int th, int cap) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     hipError_t e = hipErrorInvalidValue;
-    if (tw == 16 && th == 16) e = occupancy_t<16, 16>(&per);
-    else if (tw == 8 && th == 8) e = occupancy_t<8, 8>(&per);
-    else if (tw == 16 && th == 8) e = occupancy_t<16, 8>(&per);
-    else if (tw == 32 && th == 8) e = occupancy_t<32, 8>(&per);
-    else if (tw == 32 && th == 16) e = occupancy_t<32, 16>(&per);
-    else if (tw == 32 && th == 32) e = occupancy_t<32, 32>(&per);
+    if (tw == 16 && th == 16) e = occupancy_t<16, 16>(&per, cap);
+    else if (tw == 8 && th == 8) e = occupancy_t<8, 8>(&per, cap);
+    else if (tw == 16 && th == 8) e = occupancy_t<16, 8>(&per, cap);
+    else if (tw == 32 && th == 8) e = occupancy_t<32, 8>(&per, cap);
+    else if (tw == 32 && th == 16) e = occupancy_t<32, 16>(&per, cap);
+    else if (tw == 32 && th == 32) e = occupancy_t<32, 32>(&per, cap);
     if (e != hipSuccess || per < 1) per = 1;
     return cus * per;
 }

@@ -41,6 +41,10 @@ constexpr int kPlain = 0, kStats = 1, kStore = 2;
 #define GS_FWD_BATCH 256
 #endif
 constexpr int kBatch = GS_FWD_BATCH;   // staged entries per batch (one walk word per 64)
+// LDS batch sizes of the persistent launch (a tuning knob of the batched
+// step): kBatch, or the half of it
+constexpr int kBatchSmall = kBatch / 2;
+static_assert(kBatch % kWave == 0 && kBatch / kWave <= 4 && kBatchSmall % kWave == 0, "walk words");
 
 struct FwdArgs {
     const Rec* rec;
@@ -59,12 +63,14 @@ struct FwdArgs {
     uint32_t n_tiles;
 };
 
+template <int B>
 struct FwdShared {
-    Staged s[kBatch];
+    Staged s[B];
 };
 
-template <class L, int MODE>
-__device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdShared& sh) {
+// B: staged entries per batch (a multiple of 64, at most 256)
+template <class L, int MODE, int B>
+__device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdShared<B>& sh) {
     constexpr int NP = L::NP;
     constexpr bool STATS = MODE == kStats;
 
@@ -122,13 +128,13 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdSha
     }
     unsigned long long n_eval = 0, n_supp = 0, n_blend = 0;
 
-    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kBatch) {
+    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += B) {
         bool all_done = true;
 #pragma unroll
         for (int p = 0; p < NP; ++p) all_done = all_done && !(T[p] > 0.0f);
         if (__syncthreads_count(all_done) == L::NCELL) break;
-        const int nb = (int)min((uint32_t)kBatch, rg.y - b0);
-        stage_batch<(kBatch + L::NCELL - 1) / L::NCELL>(sh.s, a.rec, a.vals, b0, nb, tid, L::NCELL);
+        const int nb = (int)min((uint32_t)B, rg.y - b0);
+        stage_batch<(B + L::NCELL - 1) / L::NCELL>(sh.s, a.rec, a.vals, b0, nb, tid, L::NCELL);
         __syncthreads();
 
         // the lane's walk words: entries 64 q .. 64 q + 63 of the batch that
@@ -136,7 +142,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdSha
         uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
         int q0 = 0, q1 = 0, q2 = 0, q3 = 0, nw = 0;
 #pragma unroll
-        for (int q = 0; q < kBatch / kWave; ++q) {
+        for (int q = 0; q < B / kWave; ++q) {
             if (q * kWave >= nb) break;
             const int k = q * kWave + lane;
             const uint64_t m = k < nb ? cell_mask<L>(sh.s[k], x0, wy0) : 0ull;
@@ -252,13 +258,13 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdSha
 
 template <class L, int MODE>
 __global__ __launch_bounds__(L::NCELL) void k_render_fwd(FwdArgs a) {
-    __shared__ FwdShared sh;
-    fwd_tile<L, MODE>(a, blockIdx.x, sh);
+    __shared__ FwdShared<kBatch> sh;
+    fwd_tile<L, MODE, kBatch>(a, blockIdx.x, sh);
 }
 
-template <class L>
+template <class L, int B>
 __global__ __launch_bounds__(L::NCELL) void k_render_fwd_persistent(FwdArgs a) {
-    __shared__ FwdShared sh;
+    __shared__ FwdShared<B> sh;
     __shared__ uint32_t s_next;
     for (;;) {
         __syncthreads();
@@ -266,28 +272,32 @@ __global__ __launch_bounds__(L::NCELL) void k_render_fwd_persistent(FwdArgs a) {
         __syncthreads();
         const uint32_t q = s_next;
         if (q >= a.n_tiles) break;
-        fwd_tile<L, kPlain>(a, a.order ? a.order[q] : q, sh);
+        fwd_tile<L, kPlain, B>(a, a.order ? a.order[q] : q, sh);
     }
 }
 
 template <int TW, int TH>
-void launch_t(const FwdArgs& a, int persistent_grid, hipStream_t st) {
+void launch_t(const FwdArgs& a, int persistent_grid, int batch, hipStream_t st) {
     using L = typename CellsFor<TW, TH>::L;
     const dim3 block(L::NCELL);
     if (a.stats)
         hipLaunchKernelGGL((k_render_fwd<L, kStats>), dim3(a.n_tiles), block, 0, st, a);
     else if (a.state)
         hipLaunchKernelGGL((k_render_fwd<L, kStore>), dim3(a.n_tiles), block, 0, st, a);
+    else if (persistent_grid > 0 && batch == kBatchSmall)
+        hipLaunchKernelGGL((k_render_fwd_persistent<L, kBatchSmall>), dim3(persistent_grid), block, 0, st, a);
     else if (persistent_grid > 0)
-        hipLaunchKernelGGL((k_render_fwd_persistent<L>), dim3(persistent_grid), block, 0, st, a);
+        hipLaunchKernelGGL((k_render_fwd_persistent<L, kBatch>), dim3(persistent_grid), block, 0, st, a);
     else
         hipLaunchKernelGGL((k_render_fwd<L, kPlain>), dim3(a.n_tiles), block, 0, st, a);
 }
 
 template <int TW, int TH>
-hipError_t occupancy_t(int* per) {
+hipError_t occupancy_t(int* per, int batch) {
     using L = typename CellsFor<TW, TH>::L;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_render_fwd_persistent<L>, L::NCELL, 0);
+    if (batch == kBatchSmall)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_render_fwd_persistent<L, kBatchSmall>, L::NCELL, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_render_fwd_persistent<L, kBatch>, L::NCELL, 0);
 }
 
 }  // namespace
@@ -327,7 +337,7 @@ void launch_render_fwd(const RenderArgs& r, float* image, float* final_T, uint32
     a.n_tiles = r.n_tiles;
     const int pg = (r.queue && !stats && !state) ? r.persistent_grid : 0;
     if (pg > 0) launch_fill_u32(r.queue, 0u, 1, st);
-#define GS_FWD(x, y) launch_t<x, y>(a, pg, st)
+#define GS_FWD(x, y) launch_t<x, y>(a, pg, r.fwd_batch, st)
     if (r.tw == 16 && r.th == 16) GS_FWD(16, 16);
     else if (r.tw == 8 && r.th == 8) GS_FWD(8, 8);
     else if (r.tw == 16 && r.th == 8) GS_FWD(16, 8);
@@ -337,24 +347,27 @@ void launch_render_fwd(const RenderArgs& r, float* image, float* final_T, uint32
 #undef GS_FWD
 }
 
-int render_persistent_grid_bwd(int tw, int th);
-int render_persistent_grid_fwd(int tw, int th);
+int render_persistent_grid_bwd(int tw, int th, int item_cap);
+int render_persistent_grid_fwd(int tw, int th, int batch);
 
-int render_persistent_grid(int tw, int th, bool backward) {
-    return backward ? render_persistent_grid_bwd(tw, th) : render_persistent_grid_fwd(tw, th);
+int render_persistent_grid(int tw, int th, bool backward, int lds_knob) {
+    return backward ? render_persistent_grid_bwd(tw, th, lds_knob) : render_persistent_grid_fwd(tw, th, lds_knob);
 }
 
-int render_persistent_grid_fwd(int tw, int th) {
+int render_fwd_batch_default() { return kBatch; }
+int render_fwd_batch_small() { return kBatchSmall; }
+
+int render_persistent_grid_fwd(int tw, int th, int batch) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     hipError_t e = hipErrorInvalidValue;
-    if (tw == 16 && th == 16) e = occupancy_t<16, 16>(&per);
-    else if (tw == 8 && th == 8) e = occupancy_t<8, 8>(&per);
-    else if (tw == 16 && th == 8) e = occupancy_t<16, 8>(&per);
-    else if (tw == 32 && th == 8) e = occupancy_t<32, 8>(&per);
-    else if (tw == 32 && th == 16) e = occupancy_t<32, 16>(&per);
-    else if (tw == 32 && th == 32) e = occupancy_t<32, 32>(&per);
+    if (tw == 16 && th == 16) e = occupancy_t<16, 16>(&per, batch);
+    else if (tw == 8 && th == 8) e = occupancy_t<8, 8>(&per, batch);
+    else if (tw == 16 && th == 8) e = occupancy_t<16, 8>(&per, batch);
+    else if (tw == 32 && th == 8) e = occupancy_t<32, 8>(&per, batch);
+    else if (tw == 32 && th == 16) e = occupancy_t<32, 16>(&per, batch);
+    else if (tw == 32 && th == 32) e = occupancy_t<32, 32>(&per, batch);
     if (e != hipSuccess || per < 1) per = 1;
     return cus * per;
 }

@@ -99,9 +99,14 @@ def test_batch_autotune_picks_a_timed_candidate_and_stays_exact():
     b = BatchStep(dgs, [c for _, c, _ in cells], [torch.as_tensor(t).cuda() for _, _, t in cells], autotune=True)
     info = b.info()
     timed = [c for c in info["candidates"] if c["ms"] > 0]
-    assert len(timed) == len(info["candidates"]) >= 4
+    assert len(timed) == len(info["candidates"]) == 10
+    # the search covers tile shapes, both launch forms, both LDS sizes and two grid sizes
+    assert {c["fwd_batch"] for c in timed} == {128, 256} and {c["item_cap"] for c in timed} == {256, 512}
+    assert {c["grid_pct"] for c in timed} == {75, 100} and {c["persistent"] for c in timed} == {True, False}
     best = min(timed, key=lambda c: c["ms"])
     assert tuple(best["tile"]) == tuple(info["tile"]) and best["persistent"] == info["persistent"]
+    assert (best["fwd_batch"], best["item_cap"], best["grid_pct"]) == \
+        (info["fwd_batch"], info["item_cap"], info["grid_pct"])
     print("autotune:", info)
     b.step()
     torch.cuda.synchronize()
@@ -109,6 +114,52 @@ def test_batch_autotune_picks_a_timed_candidate_and_stays_exact():
     ref = oracle.render(g, cam)
     image_close("autotuned cell 0", b.image(0).cpu().numpy(), ref["image"], ref["flags"])
     b.close()
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 32)])
+def test_batch_lds_knobs_and_grid_share_leave_every_bit_unchanged(tile):
+    """The forward's LDS batch (128 or 256 entries), the backward's slot
+    capacity (256 or 512) and the persistent grid's share change where the
+    work is cut, not the order of any pixel's or entry's arithmetic: images
+    and gradients are bitwise those of the default configuration, and the
+    images those of the plain path."""
+    _case(f"lds knobs tile={tile}")
+    cells = _cells()
+    dgs = [raster.DeviceGaussians.from_host(g) for g, _, _ in cells]
+    cams, tgts = [c for _, c, _ in cells], [torch.as_tensor(t).cuda() for _, _, t in cells]
+    ref = [_plain(g, cam, tgt, tile)[0] for g, cam, tgt in cells]
+
+    def run(**kw):
+        b = BatchStep(dgs, cams, tgts, tile=tile, **kw)
+        b.step()
+        torch.cuda.synchronize()
+        assert b.status()[0] == 0
+        out = (b.images.cpu().numpy().copy(),
+               [{k: v.cpu().numpy().copy() for k, v in b.cell_grads(c).items()} for c in range(len(cells))],
+               b.info())
+        b.close()
+        return out
+
+    img0, g0, _ = run()
+    img1, g1, info = run(fwd_batch=128, item_cap=256, grid_pct=60)
+    assert (info["fwd_batch"], info["item_cap"], info["grid_pct"]) == (128, 256, 60)
+    np.testing.assert_array_equal(img1, img0)
+    for c in range(len(cells)):
+        for k in PARAMS:
+            np.testing.assert_array_equal(g1[c][k], g0[c][k], err_msg=f"cell {c} {k}")
+    off = 0
+    for c, (h, w) in enumerate([(cam.height, cam.width) for cam in cams]):
+        np.testing.assert_array_equal(img1[off:off + 3 * h * w].reshape(3, h, w), ref[c], err_msg=f"cell {c}")
+        off += 3 * h * w
+
+
+def test_batch_rejects_unsupported_lds_knobs():
+    cells = _cells()[:1]
+    dgs = [raster.DeviceGaussians.from_host(g) for g, _, _ in cells]
+    from paper_2402_17427_amd import _native as N
+    for kw in (dict(fwd_batch=64), dict(item_cap=100), dict(grid_pct=101)):
+        with pytest.raises(N.GsError):
+            BatchStep(dgs, [c for _, c, _ in cells], [torch.as_tensor(t).cuda() for _, _, t in cells], **kw)
 
 
 def _raw_planes(opt):
