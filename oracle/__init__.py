@@ -31,6 +31,23 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 DEFAULT_EPS = (1e-4, 1e-3, 1e-5)
 
 
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
+
+
+def build_sanitized() -> str:
+    """The oracle built with clang under AddressSanitizer and
+    UndefinedBehaviorSanitizer (no OpenMP: one sanitizer runtime, clang's,
+    serves it and the sanitized rasterizer library in one process); loaded
+    instead of the regular build when GS_ORACLE_LIB names it."""
+    clang = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib", "llvm", "bin", "clang")
+    tmp = _LIB_SAN + ".tmp"
+    subprocess.check_call([clang, "-O1", "-g", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-Wall",
+                           "-Wno-unknown-pragmas", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                           "-fno-omit-frame-pointer", "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _LIB_SAN)
+    return _LIB_SAN
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
     if force or not os.path.exists(_LIB):
@@ -70,9 +87,13 @@ def planted_library(path):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        _lib = _load(_LIB)
+        alt = os.environ.get("GS_ORACLE_LIB")
+        if alt:
+            _lib = _load(alt)
+        else:
+            if not os.path.exists(_LIB):
+                build()
+            _lib = _load(_LIB)
     return _lib
 
 

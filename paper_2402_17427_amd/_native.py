@@ -10,7 +10,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgsmi.so")
+# GSMI_LIB names another build of the same library (the sanitized host build)
+LIB_PATH = os.environ.get("GSMI_LIB") or os.path.join(HERE, "libgsmi.so")
 
 GS_OK = 0
 GS_ERR_INVALID = -1
