@@ -654,8 +654,10 @@ def bench_batched(args, torch, scenes, raster):
             "plain_mpix_per_s": round(npix / (ms_plain * 1e-3) / 1e6, 1),
             "speedup_vs_plain": round(ms_plain / ms_batch, 3), "status": st, "pairs": pairs[0],
             "autotune": {"tile": info["tile"], "persistent": info["persistent"], "graph": info["use_graph"],
-                         "candidates_ms": [(c["tile"], c["persistent"], round(c["ms"], 3))
-                                           for c in info["candidates"]]}}
+                         "fwd_batch": info["fwd_batch"], "item_cap": info["item_cap"], "grid_pct": info["grid_pct"],
+                         "candidates": ["tile, persistent, fwd_batch, item_cap, grid_pct, ms"] +
+                                       [(c["tile"], c["persistent"], c["fwd_batch"], c["item_cap"], c["grid_pct"],
+                                         round(c["ms"], 3)) for c in info["candidates"]]}}
 
 
 def bench_autograd(args, torch, scenes, raster):
