@@ -58,6 +58,8 @@ gs_status to_cam(const gs_camera* c, Cam* out) {
     out->H = c->height;
     out->near_z = c->near_z;
     std::memcpy(out->bg, c->bg, sizeof out->bg);
+    out->limx = kFovClampD * (0.5 * (double)out->W) / (double)out->fx;
+    out->limy = kFovClampD * (0.5 * (double)out->H) / (double)out->fy;
     return GS_OK;
 }
 

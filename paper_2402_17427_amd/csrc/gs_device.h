@@ -16,6 +16,7 @@ namespace gs {
 // Image-formation constants.
 constexpr float kDilation = 0.3f;     // px^2 added to the projected covariance
 constexpr float kFovClamp = 1.3f;     // affine-approximation clamp of x/z, y/z
+constexpr double kFovClampD = 1.3;    // the same in FP64 (the projection's geometry)
 constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTMin = 1e-4f;
@@ -42,6 +43,7 @@ struct Cam {
     int W, H;
     float near_z;
     float bg[3];
+    double limx, limy;   // affine-approximation clamp of x/z and y/z: 1.3 (W/2) / fx, 1.3 (H/2) / fy
 };
 
 // Gaussian SoA planes (mirrors gs_gaussians).

@@ -24,7 +24,6 @@ namespace {
 constexpr int kProjThreads = 256;
 // The geometry runs in FP64 with the constants exactly as defined.
 constexpr double kDilationD = 0.3;
-constexpr double kFovClampD = 1.3;
 
 // Real SH basis up to degree 3 (index l*l + l + m), sign pattern of 3DGS
 // scenes.  Constants: 1/(2 sqrt(pi)), sqrt(3/(4 pi)), sqrt(15/pi)/2,
@@ -118,7 +117,8 @@ __device__ __forceinline__ void quat_rot(double w, double x, double y, double z,
 struct Geo {
     double t[3];        // camera-space centre
     double Rq[9];       // rotation of the normalised quaternion
-    double qn;          // quaternion norm
+    double qn, iqn;     // quaternion norm and its reciprocal
+    double itz;         // 1 / tz
     double M[9];        // Rq diag(s)
     double S[9];        // 3D covariance M M^T
     double T[6];        // J W, 2x3
@@ -135,7 +135,8 @@ __device__ __forceinline__ bool geometry(const Cam& cam, const double mu[3], con
     if (!(g.t[2] > (double)cam.near_z)) return false;
     g.qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     if (!(g.qn > 0.0)) return false;
-    const double inv = 1.0 / g.qn;
+    g.iqn = 1.0 / g.qn;
+    const double inv = g.iqn;
     quat_rot(q[0] * inv, q[1] * inv, q[2] * inv, q[3] * inv, g.Rq);
     for (int r = 0; r < 3; ++r)
         for (int k = 0; k < 3; ++k) g.M[3 * r + k] = g.Rq[3 * r + k] * s[k];
@@ -145,16 +146,16 @@ __device__ __forceinline__ bool geometry(const Cam& cam, const double mu[3], con
             g.S[3 * r + k] = v;
             g.S[3 * k + r] = v;
         }
-    const double tz = g.t[2];
-    const double limx = kFovClampD * (0.5 * (double)cam.W) / (double)cam.fx;
-    const double limy = kFovClampD * (0.5 * (double)cam.H) / (double)cam.fy;
-    const double x0 = g.t[0] / tz, y0 = g.t[1] / tz;
+    // one division for the Jacobian (the clamp limits come with the camera)
+    g.itz = 1.0 / g.t[2];
+    const double itz = g.itz, limx = cam.limx, limy = cam.limy;
+    const double x0 = g.t[0] * itz, y0 = g.t[1] * itz;
     g.clx = x0 < -limx || x0 > limx;
     g.cly = y0 < -limy || y0 > limy;
     g.xr = fmin(fmax(x0, -limx), limx);
     g.yr = fmin(fmax(y0, -limy), limy);
-    const double j00 = (double)cam.fx / tz, j02 = -(double)cam.fx * g.xr / tz;
-    const double j11 = (double)cam.fy / tz, j12 = -(double)cam.fy * g.yr / tz;
+    const double j00 = (double)cam.fx * itz, j02 = -(double)cam.fx * g.xr * itz;
+    const double j11 = (double)cam.fy * itz, j12 = -(double)cam.fy * g.yr * itz;
     for (int k = 0; k < 3; ++k) {
         g.T[k] = j00 * (double)cam.R[k] + j02 * (double)cam.R[6 + k];
         g.T[3 + k] = j11 * (double)cam.R[3 + k] + j12 * (double)cam.R[6 + k];
@@ -228,9 +229,9 @@ __global__ __launch_bounds__(kProjThreads) void k_project(JobTab jobs, ViewTab v
             for (int r = 0; r < 3; ++r)
                 cc[r] = -((double)cam.R[r] * cam.t[0] + (double)cam.R[3 + r] * cam.t[1] + (double)cam.R[6 + r] * cam.t[2]);
             double d[3] = {mu[0] - cc[0], mu[1] - cc[1], mu[2] - cc[2]};
-            const double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            const double idn = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             float Y[16];
-            sh_basis((float)(d[0] / dn), (float)(d[1] / dn), (float)(d[2] / dn), Y);
+            sh_basis((float)(d[0] * idn), (float)(d[1] * idn), (float)(d[2] * idn), Y);
             // the SH coefficients are read only here, for Gaussians that
             // survive the geometry, and consumed as they arrive (a
             // non-finite coefficient culls the Gaussian like any other
@@ -251,7 +252,9 @@ __global__ __launch_bounds__(kProjThreads) void k_project(JobTab jobs, ViewTab v
             // support: centres of pixels where alpha can reach 1/255
             const double r2 = 2.0 * log(255.0 * (double)o);
             const double ex = sqrt(r2 * g.a), ey = sqrt(r2 * g.c);
-            out.thr = (float)(-log2(255.0 * (double)o));
+            // the blend uses thr only for its conservative cell masks (whose
+            // margin is far above FP32 error), so FP32 suffices here
+            out.thr = -__builtin_log2f(255.0f * o);
             double x0 = ceil(out.u - ex - 0.5), x1 = floor(out.u + ex - 0.5);
             double y0 = ceil(out.v - ey - 0.5), y1 = floor(out.v + ey - 0.5);
             x0 = fmax(x0, 0.0);
@@ -327,8 +330,8 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(JobTab jobs, ViewT
     for (int r = 0; r < 3; ++r)
         cc[r] = -((double)cam.R[r] * cam.t[0] + (double)cam.R[3 + r] * cam.t[1] + (double)cam.R[6 + r] * cam.t[2]);
     const double dd[3] = {mu[0] - cc[0], mu[1] - cc[1], mu[2] - cc[2]};
-    const double dn = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
-    const float dx = (float)(dd[0] / dn), dy = (float)(dd[1] / dn), dz = (float)(dd[2] / dn);
+    const double dn = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]), idn = 1.0 / dn;
+    const float dx = (float)(dd[0] * idn), dy = (float)(dd[1] * idn), dz = (float)(dd[2] * idn);
     float Y[16];
     sh_basis(dx, dy, dz, Y);
     float wsum[16];
@@ -352,7 +355,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(JobTab jobs, ViewT
     float gdir[3];
     sh_dir_grad(dx, dy, dz, wsum, K, gdir);
     const double proj_d = (double)dx * gdir[0] + (double)dy * gdir[1] + (double)dz * gdir[2];
-    double gmu[3] = {(gdir[0] - dx * proj_d) / dn, (gdir[1] - dy * proj_d) / dn, (gdir[2] - dz * proj_d) / dn};
+    double gmu[3] = {(gdir[0] - dx * proj_d) * idn, (gdir[1] - dy * proj_d) * idn, (gdir[2] - dz * proj_d) * idn};
 
     // ---- conic Q = Sigma2^{-1}: dL/dSigma2 = -Q Gq Q with Gq the gradient
     // w.r.t. Q as a full matrix (the off-diagonal B enters twice).
@@ -387,7 +390,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(JobTab jobs, ViewT
     const double dJ12 = dT[3] * cam.R[6] + dT[4] * cam.R[7] + dT[5] * cam.R[8];
     const double tx = g.t[0], ty = g.t[1], tz = g.t[2];
     const double fx = cam.fx, fy = cam.fy;
-    const double itz = 1.0 / tz, itz2 = itz * itz;
+    const double itz = g.itz, itz2 = itz * itz;
     double gt[3] = {0.0, 0.0, 0.0};
     // J00 = fx/tz, J11 = fy/tz
     gt[2] -= (fx * dJ00 + fy * dJ11) * itz2;
@@ -415,7 +418,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(JobTab jobs, ViewT
         for (int r = 0; r < 3; ++r) dR[3 * r + k] = dM[3 * r + k] * s[k];
     }
     // ---- Rq(qh) with qh = q/|q|
-    const double inv = 1.0 / g.qn;
+    const double inv = g.iqn;
     const double w = q[0] * inv, x = q[1] * inv, y = q[2] * inv, z = q[3] * inv;
     // derivative of each rotation entry w.r.t. (w, x, y, z), contracted with dR
     double gw = 2.0 * (z * (dR[3] - dR[1]) + y * (dR[2] - dR[6]) + x * (dR[7] - dR[5]));
