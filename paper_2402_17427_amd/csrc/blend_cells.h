@@ -42,39 +42,50 @@ template <> struct CellsFor<16, 8> { using L = Cells<16, 8, 2, 1>; };
 //   ca dx^2 + cb dx dy + cc dy^2 >= thr
 // (base-2 exponent of the Gaussian, thr = -log2(255 o); ca, cc < 0) at the
 // row's centre height: with dy fixed the exponent is a concave quadratic in
-// dx, whose roots bound the chord.  The threshold is lowered by a margin
-// (2e-3 + 2e-4 |thr| in base-2 units, far above the FP32 error of the
-// exponent the blend evaluates) and the chord widened by 1e-3 px, so every
-// pixel the blend can find at or above 1/255 is covered; covering a few
-// more only costs evaluations that the blend then skips.  x0: the tile's
-// first pixel column, y0: the wave's first pixel row (image coordinates).
+// dx, whose roots bound the chord.  Its discriminant is quadratic in dy,
+// (cb^2 - 4 ca cc) dy^2 + 4 ca thr, and its centre linear, -cb dy / (2 ca),
+// with coefficients fixed per Gaussian.  The threshold is lowered by a
+// margin (2e-3 + 2e-4 |thr| in base-2 units, far above the FP32 error of
+// the exponent the blend evaluates) and the chord widened by 1e-3 px, so
+// every pixel the blend can find at or above 1/255 is covered; the chords
+// of a cell row's pixel rows are merged into one interval before they are
+// turned into cells (a superset: covering a few more only costs
+// evaluations that the blend then skips).  x0: the tile's first pixel
+// column, y0: the wave's first pixel row (image coordinates).
 template <class L>
 __device__ __forceinline__ uint64_t cell_mask(const Staged& g, int x0, int y0) {
     const float ca = g.coef.x, cb = g.coef.y, cc = g.coef.z;
     const float thm = g.col.w - (2e-3f + 2e-4f * fabsf(g.col.w));
     const float ia = 0.5f * __builtin_amdgcn_rcpf(ca);        // 1 / (2 ca) < 0
-    const float ca4 = -4.0f * ca;
+    const float k2 = __builtin_fmaf(cb, cb, (-4.0f * ca) * cc);  // discriminant = k2 dy^2 + k0
+    const float k0 = (4.0f * ca) * thm;
+    const float m1 = -cb * ia;                                   // chord centre = m1 dy (offset units)
     // pixel column p (tile-local) has offset dx = p - xs from the centre;
     // the chord's ends are widened by 1e-3 px
     const float xs = ((g.geo.x - (float)x0) + g.geo.y) - 0.5f;
     const float xs_lo = xs - 1e-3f, xs_hi = xs + 1e-3f;
     uint32_t lo = 0u, hi = 0u;
 #pragma unroll
-    for (int j = 0; j < L::PXROWS_W; ++j) {
-        const float dy = (((float)(y0 + j) + 0.5f) - g.geo.z) - g.geo.w;
-        const float b = cb * dy;
-        const float c = __builtin_fmaf(cc * dy, dy, -thm);
-        const float D = __builtin_fmaf(ca4, c, b * b);          // b^2 - 4 ca c
-        const float s = __builtin_amdgcn_sqrtf(fmaxf(D, 0.0f));   // ~1 ulp, covered by the margins
-        const float plo = __builtin_fmaf(s - b, ia, xs_lo);
-        const float phi = __builtin_fmaf(-s - b, ia, xs_hi);
+    for (int r = 0; r < L::ROWS_W; ++r) {
+        float cl = __builtin_inff(), ch = -__builtin_inff();   // merged chord of the cell row
+#pragma unroll
+        for (int q = 0; q < L::CH; ++q) {
+            const int j = r * L::CH + q;
+            const float dy = (((float)(y0 + j) + 0.5f) - g.geo.z) - g.geo.w;
+            const float D = __builtin_fmaf(k2, dy * dy, k0);
+            const float s = __builtin_amdgcn_sqrtf(fmaxf(D, 0.0f));   // ~1 ulp, covered by the margins
+            const float plo = __builtin_fmaf(s, ia, __builtin_fmaf(m1, dy, xs_lo));
+            const float phi = __builtin_fmaf(-s, ia, __builtin_fmaf(m1, dy, xs_hi));
+            cl = D >= 0.0f ? fminf(cl, plo) : cl;
+            ch = D >= 0.0f ? fmaxf(ch, phi) : ch;
+        }
         // covered pixel columns, clamped to the tile before the conversion
-        const int c0 = (int)__builtin_ceilf(fminf(fmaxf(plo, -1.0f), (float)L::TW));
-        const int c1 = (int)__builtin_floorf(fminf(fmaxf(phi, -1.0f), (float)L::TW));
-        const bool ok = (D >= 0.0f) & (c0 <= c1) & (c1 >= 0) & (c0 < L::TW);
+        const int c0 = (int)__builtin_ceilf(fminf(fmaxf(cl, -1.0f), (float)L::TW));
+        const int c1 = (int)__builtin_floorf(fminf(fmaxf(ch, -1.0f), (float)L::TW));
+        const bool ok = (c0 <= c1) & (c1 >= 0) & (c0 < L::TW);
         const int a0 = max(c0, 0) >> L::CW_SHIFT, a1 = min(c1, L::TW - 1) >> L::CW_SHIFT;
         const uint32_t bits = ok ? ((2u << a1) - (1u << a0)) : 0u;
-        const int sh = (j / L::CH) * L::CPR;                    // the row's cells within the 64 bits
+        const int sh = r * L::CPR;                               // the row's cells within the 64 bits
         if (sh < 32) lo |= bits << sh;
         else hi |= bits << (sh - 32);
     }

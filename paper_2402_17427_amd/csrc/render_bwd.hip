@@ -113,7 +113,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
     for (int j = 0; j < L::CH; ++j) fyp[j] = (float)(py0 + j) + 0.5f;
 
     uint32_t my_last[NP];
-    float T[NP], g0[NP], g1[NP], g2[NP], gbg[NP], ga[NP];
+    float T[NP], g0[NP], g1[NP], g2[NP], ga[NP];
     uint32_t cell_last = 0;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -129,9 +129,9 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
             g1[p] = dimg[npix + off];
             g2[p] = dimg[2 * npix + off];
         }
-        // g . (T_final bg): the background's share of every suffix colour
-        gbg[p] = g0[p] * (T[p] * bg0) + g1[p] * (T[p] * bg1) + g2[p] * (T[p] * bg2);
-        ga[p] = 0.0f;   // g . sum of rgb_j w_j over the blended j behind the current entry
+        // g . S, S the colour behind the current entry: the background's
+        // share T_final bg, then the blended rgb_j w_j as they are passed
+        ga[p] = g0[p] * (T[p] * bg0) + g1[p] * (T[p] * bg1) + g2[p] * (T[p] * bg2);
         cell_last = max(cell_last, my_last[p]);
     }
 
@@ -216,9 +216,8 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
                 dys[j] = (fyp[j] - g.geo.z) - g.geo.w;
                 qc[j] = (g.coef.z * dys[j]) * dys[j];
             }
-            // the cell's sums: dpow dx, dpow dy, dpow dx^2, dpow dx dy,
-            // dpow dy^2, dL/do, dL/drgb
-            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f, s6 = 0.f, s7 = 0.f, s8 = 0.f;
+            // the cell's sums: dL/do, dL/drgb, and dL/dpower per pixel
+            float s5 = 0.f, s6 = 0.f, s7 = 0.f, s8 = 0.f, dpow[NP];
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const int i = p % L::CW, j = p / L::CW;
@@ -252,7 +251,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
                 const float grgb = g0[p] * g.col.x + g1[p] * g.col.y + g2[p] * g.col.z;
                 // dL/dalpha = g . (rgb T_i - S_i / (1 - alpha)), S_i = suffix colour + T_final bg;
                 // no gradient through a capped alpha
-                const float da0 = grgb * Ti - (ga[p] + gbg[p]) * iom;
+                const float da0 = grgb * Ti - ga[p] * iom;
                 const float da = (contrib && !capped) ? da0 : 0.0f;
                 ga[p] = __builtin_fmaf(grgb, w, ga[p]);
                 T[p] = Ti;
@@ -260,15 +259,43 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
                 s7 = __builtin_fmaf(g1[p], w, s7);
                 s8 = __builtin_fmaf(g2[p], w, s8);
                 s5 = __builtin_fmaf(da, G, s5);
-                // moments of dL/dpower over the pixel offsets; the centre and
-                // conic gradients are linear in them (formed at the flush)
-                const float dpow = da * al;
-                const float mx = dpow * dxs[i], my = dpow * dys[j];
-                s0 += mx;
-                s1 += my;
-                s2 = __builtin_fmaf(mx, dxs[i], s2);
-                s3 = __builtin_fmaf(mx, dys[j], s3);
-                s4 = __builtin_fmaf(my, dys[j], s4);
+                dpow[p] = da * al;
+            }
+            // moments of dL/dpower over the pixel offsets (the centre and
+            // conic gradients are linear in them, formed at the flush):
+            // s0 = sum dpow dx, s1 = sum dpow dy, s2 = sum dpow dx^2,
+            // s3 = sum dpow dx dy, s4 = sum dpow dy^2, from the cell's
+            // column sums (plain and dy-weighted) and row sums
+            float cs[L::CW], csy[L::CW], rs[L::CH];
+#pragma unroll
+            for (int i = 0; i < L::CW; ++i) {
+                cs[i] = dpow[i];
+                csy[i] = dpow[i] * dys[0];
+#pragma unroll
+                for (int j = 1; j < L::CH; ++j) {
+                    cs[i] += dpow[j * L::CW + i];
+                    csy[i] = __builtin_fmaf(dpow[j * L::CW + i], dys[j], csy[i]);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < L::CH; ++j) {
+                rs[j] = dpow[j * L::CW];
+#pragma unroll
+                for (int i = 1; i < L::CW; ++i) rs[j] += dpow[j * L::CW + i];
+            }
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+#pragma unroll
+            for (int i = 0; i < L::CW; ++i) {
+                const float t = dxs[i] * cs[i];
+                s0 += t;
+                s2 = __builtin_fmaf(t, dxs[i], s2);
+                s3 = __builtin_fmaf(dxs[i], csy[i], s3);
+            }
+#pragma unroll
+            for (int j = 0; j < L::CH; ++j) {
+                const float u = dys[j] * rs[j];
+                s1 += u;
+                s4 = __builtin_fmaf(u, dys[j], s4);
             }
             if (has) {
                 const uint32_t slot = sh.base[wv][kk] + (uint32_t)__popcll(sh.mask[wv][kk] & below);
