@@ -205,7 +205,7 @@ gs_status gs_render_fwd(const gs_proj *proj, const gs_bins *bins, const gs_camer
 gs_status gs_render_mask_bytes(const gs_bins *bins, const gs_opts *opts, size_t *bytes);
 
 /* Bytes of the device workspace gs_render_bwd needs for these bins:
- * 36 bytes per pair of capacity (host query). */
+ * at most 40 bytes per pair of capacity plus 516 (host query). */
 gs_status gs_render_bwd_workspace(const gs_bins *bins, size_t *bytes);
 
 /* Section 3 (differentiable rasterizer, Gaussians optimised by gradient

@@ -97,6 +97,13 @@ int tile_bits(int64_t n_tiles) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// The backward's workspace: per-pair gradient slots (36 B per pair), then a
+// tile order of at most one entry per pair and its count.
+size_t bwd_ws_bytes(int64_t cap) {
+    const size_t c = (size_t)(cap > 0 ? cap : 0);
+    return align256(pair_grad_bytes(cap)) + align256((c + 1) * sizeof(uint32_t));
+}
+
 size_t bin_sort_ws_bytes(int64_t n, int64_t cap, int64_t n_tiles) {
     const int kb = 32 + tile_bits(n_tiles);
     return align256(scan_workspace_bytes(n)) + align256((size_t)cap * 8) + align256((size_t)cap * 4) +
@@ -347,21 +354,26 @@ gs_status render_bwd_impl(const gs_gaussians* g, const gs_camera* cam, const gs_
         if (state_bytes < need) return fail(GS_ERR_INVALID, "state buffer too small: %zu < %zu", state_bytes, need);
     }
     if (G.n > 0 && !bins->first) return fail(GS_ERR_INVALID, "bins first is NULL");
-    const size_t need_ws = pair_grad_bytes(bins->pair_capacity);
-    if (need_ws > 0 && (!ws || ws_bytes < need_ws))
-        return fail(GS_ERR_INVALID, "workspace too small: %zu < %zu", ws_bytes, need_ws);
+    const size_t need_ws = bwd_ws_bytes(bins->pair_capacity);
+    if (!ws || ws_bytes < need_ws) return fail(GS_ERR_INVALID, "workspace too small: %zu < %zu", ws_bytes, need_ws);
     if (reinterpret_cast<uintptr_t>(ws) % 16) return fail(GS_ERR_INVALID, "workspace not 16-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t cap = bins->pair_capacity;
+    // workspace: the per-pair gradient slots, then the tiles with pairs in
+    // longest-list-first order (at most one per pair) and their count
+    uint32_t* order = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + align256(pair_grad_bytes(cap)));
+    uint32_t* order_n = order + (cap > 0 ? cap : 0);
+    RenderArgs r = single_render(proj, bins, C, tw, th);
     {
         ProfScope ps("pair_zero", st);
-        launch_pair_zero(ws, bins->pair_count, cap, st);
+        launch_pair_zero(ws, bins->pair_count, cap, st, bins->ranges, r.n_tiles, order, order_n);
     }
+    r.tile_order = order;
+    r.tile_order_count = order_n;
     {
         ProfScope ps(state ? "render_bwd_stored" : "render_bwd", st);
-        launch_render_bwd(single_render(proj, bins, C, tw, th), final_T, n_contrib, dL_dimage,
-                          reinterpret_cast<const ushort4*>(proj->rect), bins->first, ws, cap,
-                          static_cast<const float2*>(state), st);
+        launch_render_bwd(r, final_T, n_contrib, dL_dimage, reinterpret_cast<const ushort4*>(proj->rect),
+                          bins->first, ws, cap, static_cast<const float2*>(state), st);
     }
     {
         ProfScope ps("pair_gather", st);
@@ -381,7 +393,7 @@ gs_status gs_render_bwd_workspace(const gs_bins* bins, size_t* bytes) {
     gs_status s;
     if ((s = check_bins(bins))) return s;
     if (!bytes) return fail(GS_ERR_INVALID, "bytes is NULL");
-    *bytes = pair_grad_bytes(bins->pair_capacity);
+    *bytes = bwd_ws_bytes(bins->pair_capacity);
     return GS_OK;
 }
 

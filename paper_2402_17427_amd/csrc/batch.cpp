@@ -125,10 +125,8 @@ struct gs_batch {
     uint32_t* pair_count = nullptr;
     int32_t* status = nullptr;
     uint32_t* queue = nullptr;
-    uint32_t* tiles_dev = nullptr;   // device copy of n_tiles (count for the tile-order sort)
-    uint64_t *tkeys = nullptr, *tkeys_alt = nullptr;
-    uint32_t *tvals = nullptr, *tvals_alt = nullptr;
-    void* tsort_ws = nullptr;
+    uint32_t* tiles_dev = nullptr;   // device count of the tile order (every tile)
+    uint32_t* tvals = nullptr;   // persistent blends: the tiles, longest list first
     uint32_t max_tiles = 0;
     // per-pixel buffers
     float* final_T = nullptr;
@@ -155,8 +153,8 @@ struct gs_batch {
         if (graph) (void)hipGraphDestroy(graph);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         void* ptrs[] = {d_views, d_jobs, d_targets, rec, depth, rect, tt, g2d, first, scan_ws, keys, alt_k, vals,
-                        alt_v, pair_grad, masks, sort_ws, ranges, pair_count, status, queue, tiles_dev, tkeys, tkeys_alt, tvals,
-                        tvals_alt, tsort_ws, final_T, n_contrib, dimg, loss_ws, sched};
+                        alt_v, pair_grad, masks, sort_ws, ranges, pair_count, status, queue, tiles_dev, tvals,
+                        final_T, n_contrib, dimg, loss_ws, sched};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
     }
@@ -239,8 +237,7 @@ struct gs_batch {
         r.fwd_batch = fwd_batch;
         r.item_cap = item_cap;
         if (persistent) {
-            launch_tile_len_keys(ranges, n_tiles, tkeys, tvals, st);
-            launch_sort_pairs(tkeys, tvals, tkeys_alt, tvals_alt, tiles_dev, max_tiles, 20, false, tsort_ws, st);
+            launch_tile_order(ranges, n_tiles, tvals, tiles_dev, true, st);
             r.queue = queue;
             r.order = tvals;
             r.persistent_grid = grid_fwd;
@@ -454,7 +451,6 @@ gs_status gs_batch_create(const gs_gaussians* cells, const gs_camera* cams, cons
     if (autotune)
         for (const Cand& c : kCands) max_tiles = std::max(max_tiles, b->tiles_for(c.tw, c.th));
     b->max_tiles = max_tiles;
-    size_t tsort = sort_workspace_bytes(max_tiles, 20);
     if (!s) {
         if ((s = dmalloc(&b->d_views, n_cells)) || (s = dmalloc(&b->d_jobs, n_cells)) ||
             (s = dmalloc(&b->d_targets, n_cells)) || (s = dmalloc(&b->rec, slot)) || (s = dmalloc(&b->depth, slot)) ||
@@ -462,9 +458,7 @@ gs_status gs_batch_create(const gs_gaussians* cells, const gs_camera* cams, cons
             (s = dmalloc(reinterpret_cast<char**>(&b->scan_ws), scan_workspace_bytes(slot))) ||
             (s = dmalloc(&b->ranges, (size_t)max_tiles * 2)) || (s = dmalloc(&b->pair_count, 2)) ||
             (s = dmalloc(&b->status, 1)) || (s = dmalloc(&b->queue, 1)) || (s = dmalloc(&b->tiles_dev, 1)) ||
-            (s = dmalloc(&b->tkeys, max_tiles)) || (s = dmalloc(&b->tkeys_alt, max_tiles)) ||
-            (s = dmalloc(&b->tvals, max_tiles)) || (s = dmalloc(&b->tvals_alt, max_tiles)) ||
-            (s = dmalloc(reinterpret_cast<char**>(&b->tsort_ws), tsort)) || (s = dmalloc(&b->final_T, pix)) ||
+            (s = dmalloc(&b->tvals, max_tiles)) || (s = dmalloc(&b->final_T, pix)) ||
             (s = dmalloc(&b->n_contrib, pix)) || (s = dmalloc(&b->dimg, img)))
             ;
     }

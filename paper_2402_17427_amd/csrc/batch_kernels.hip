@@ -1,12 +1,13 @@
-// Small kernels of the batched training step: the L1 image loss and its
-// gradient for every view of the batch, and the longest-list-first tile
-// order the persistent blend launches pull from.
+// Small kernels of the batched training step and of the blends: the L1
+// image loss and its gradient for every view of the batch, and the
+// longest-list-first tile orders the blend launches take their tiles in.
 //
 // VastGaussian (arXiv 2402.17427), section 3: each cell is optimised
 // against its training images with an image loss; the per-pixel L1 term is
 // the part of that loss this step evaluates (mean absolute error over the
 // three colour planes, gradient sign(I - I*) / (3 W H), sign(0) = 0).
 #include "kernels.h"
+#include "tile_order.h"
 
 namespace gs {
 
@@ -43,19 +44,27 @@ __global__ __launch_bounds__(kL1Threads) void k_l1(ViewTab views, const float* c
     }
 }
 
-// keys[t] = (2^20 - 1 - min(list length, 2^20 - 1)), vals[t] = t: a stable
-// ascending sort on 20 key bits gives the tiles longest list first.
-__global__ __launch_bounds__(256) void k_tile_len_keys(const uint2* __restrict__ ranges, uint32_t n_tiles,
-                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= n_tiles) return;
-    const uint2 r = ranges[t];
-    const uint32_t len = min(r.y - r.x, (1u << 20) - 1u);
-    keys[t] = (uint64_t)((1u << 20) - 1u - len);
-    vals[t] = t;
+constexpr int kOrderThreads = 1024;
+
+// One workgroup of 1024 threads orders the tiles (see tile_order_block).
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2* __restrict__ ranges, uint32_t n_tiles,
+                                                             uint32_t* __restrict__ order, uint32_t* __restrict__ count,
+                                                             int include_empty) {
+    __shared__ uint32_t s_h[kOrderThreads / kWave][kTileClasses + 1];
+    tile_order_block<kOrderThreads>(ranges, n_tiles, order, count, include_empty, s_h);
 }
 
 }  // namespace
+
+void launch_tile_order(const uint32_t* ranges, uint32_t n_tiles, uint32_t* order, uint32_t* count, bool include_empty,
+                       hipStream_t st) {
+    if (n_tiles == 0) {
+        launch_fill_u32(count, 0u, 1, st);
+        return;
+    }
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, reinterpret_cast<const uint2*>(ranges),
+                       n_tiles, order, count, include_empty ? 1 : 0);
+}
 
 void launch_l1(const ViewTab& views, int n_views, int64_t max_pix, const float* const* targets, const float* image,
                float* dimg, float* loss, const int32_t* status, hipStream_t st) {
@@ -68,10 +77,5 @@ void launch_l1(const ViewTab& views, int n_views, int64_t max_pix, const float* 
                        dimg, loss, status);
 }
 
-void launch_tile_len_keys(const uint32_t* ranges, uint32_t n_tiles, uint64_t* keys, uint32_t* vals, hipStream_t st) {
-    if (n_tiles == 0) return;
-    hipLaunchKernelGGL(k_tile_len_keys, dim3((n_tiles + 255) / 256), dim3(256), 0, st,
-                       reinterpret_cast<const uint2*>(ranges), n_tiles, keys, vals);
-}
 
 }  // namespace gs

@@ -89,6 +89,11 @@ struct RenderArgs {
     // forward stores each pair's cell mask of every wave of its tile, the
     // backward reads them instead of recomputing (NULL: not kept).
     uint64_t* masks;
+    // One-workgroup-per-tile launches: when set, workgroup b takes tile
+    // tile_order[b] and workgroups b >= *tile_order_count exit (the order
+    // of launch_tile_order, so that the longest lists start first).
+    const uint32_t* tile_order;
+    const uint32_t* tile_order_count;
     // Persistent launches only: the forward's staged entries per batch
     // (render_fwd_batch_small() or the default) and the backward's slots
     // per chunk (render_item_cap_small() or the default); 0 = default.
@@ -114,8 +119,12 @@ void launch_render_bwd(const RenderArgs& r, const float* final_T, const uint32_t
                        const ushort4* rect, const uint32_t* first, void* pairs, int64_t capacity,
                        const float2* state, hipStream_t st);
 size_t pair_grad_bytes(int64_t capacity);
-// Zero the first min(*pair_count, capacity) entries of the pair buffer.
-void launch_pair_zero(void* pairs, const uint32_t* pair_count, int64_t capacity, hipStream_t st);
+// Zero the first min(*pair_count, capacity) entries of the pair buffer;
+// with `order` set, the same launch also writes the tiles with pairs in
+// longest-list-first order (launch_tile_order without the empty tiles).
+void launch_pair_zero(void* pairs, const uint32_t* pair_count, int64_t capacity, hipStream_t st,
+                      const uint32_t* ranges = nullptr, uint32_t n_tiles = 0, uint32_t* order = nullptr,
+                      uint32_t* order_count = nullptr);
 // g2d[9][nslots] = the sum of each slot's pair entries (emission order);
 // zeros for culled slots and when *status != 0.
 void launch_pair_gather(int64_t nslots, const uint32_t* first, const uint32_t* tiles_touched, const void* pairs,
@@ -265,6 +274,9 @@ void launch_mul_bwd(const float* d_adj, const float* img, const float* M, int64_
                     hipStream_t st);
 void launch_embed_grad(const float* dD, int64_t hw, int m, float* d_embed, hipStream_t st);
 // Sort keys putting the tiles with the longest lists first.
-void launch_tile_len_keys(const uint32_t* ranges, uint32_t n_tiles, uint64_t* keys, uint32_t* vals, hipStream_t st);
+// order[0 .. *count) = the tiles with pairs, longest list first by the log2 of
+// its length, then (include_empty) the empty tiles; one small launch.
+void launch_tile_order(const uint32_t* ranges, uint32_t n_tiles, uint32_t* order, uint32_t* count, bool include_empty,
+                       hipStream_t st);
 
 }  // namespace gs

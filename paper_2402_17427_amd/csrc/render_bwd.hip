@@ -33,6 +33,7 @@
 // the LDS capacity (Gaussians that reach many cells).
 #include "blend_cells.h"
 #include "kernels.h"
+#include "tile_order.h"
 
 namespace gs {
 
@@ -66,6 +67,8 @@ struct BwdArgs {
     uint32_t* queue;        // persistent launch: next queue position (zeroed before launch)
     const uint32_t* order;  // persistent launch: tiles in processing order (NULL = 0, 1, ...)
     uint32_t n_tiles;
+    const uint32_t* torder;     // one workgroup per tile: workgroup b takes tile torder[b] (NULL: tile b)
+    const uint32_t* torder_n;   // ... and exits when b >= *torder_n
 };
 
 template <class L, int CAP>
@@ -354,7 +357,12 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
 template <class L, bool STORED>
 __global__ __launch_bounds__(L::NCELL) void k_render_bwd(BwdArgs a) {
     __shared__ BwdShared<L, kItemCap> sh;
-    bwd_tile<L, STORED, kItemCap>(a, blockIdx.x, sh);
+    uint32_t tile = blockIdx.x;
+    if (a.torder) {
+        if (blockIdx.x >= *a.torder_n) return;
+        tile = a.torder[blockIdx.x];
+    }
+    bwd_tile<L, STORED, kItemCap>(a, tile, sh);
 }
 
 template <class L, int CAP>
@@ -371,11 +379,31 @@ __global__ __launch_bounds__(L::NCELL) void k_render_bwd_persistent(BwdArgs a) {
     }
 }
 
-// Clear the pair gradient buffer over the pairs of this frame.
-__global__ __launch_bounds__(256) void k_pair_zero(float4* __restrict__ pg8, float* __restrict__ pg1,
-                                                   const uint32_t* __restrict__ pair_count, int64_t cap) {
+// What k_pair_zero's first workgroup does besides: the tiles with pairs in
+// longest-list-first order for the backward (tile_order_block).
+struct OrderArgs {
+    const uint2* ranges;
+    uint32_t n_tiles;
+    uint32_t* order;   // NULL: no order
+    uint32_t* count;
+};
+
+// Clear the pair gradient buffer over the pairs of this frame; with an
+// order requested, workgroup 0 builds it while the others clear.
+constexpr int kZeroThreads = 1024;
+
+__global__ __launch_bounds__(kZeroThreads) void k_pair_zero(float4* __restrict__ pg8, float* __restrict__ pg1,
+                                                            const uint32_t* __restrict__ pair_count, int64_t cap,
+                                                            OrderArgs o) {
+    const int first = o.order ? 1 : 0;
+    if (o.order && blockIdx.x == 0) {
+        __shared__ uint32_t s_h[kZeroThreads / kWave][kTileClasses + 1];
+        tile_order_block<kZeroThreads>(o.ranges, o.n_tiles, o.order, o.count, 0, s_h);
+        return;
+    }
     const int64_t P = (int64_t)*pair_count < cap ? (int64_t)*pair_count : cap;
-    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < P; p += (int64_t)gridDim.x * 256) {
+    const int64_t nb = (int64_t)gridDim.x - first;
+    for (int64_t p = ((int64_t)blockIdx.x - first) * kZeroThreads + threadIdx.x; p < P; p += nb * kZeroThreads) {
         pg8[2 * p] = make_float4(0.f, 0.f, 0.f, 0.f);
         pg8[2 * p + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
         pg1[p] = 0.f;
@@ -442,13 +470,21 @@ hipError_t occupancy_t(int* per, int cap) {
 
 size_t pair_grad_bytes(int64_t capacity) { return (size_t)(capacity > 0 ? capacity : 0) * 36; }
 
-void launch_pair_zero(void* pairs, const uint32_t* pair_count, int64_t capacity, hipStream_t st) {
-    if (capacity <= 0) return;
-    int64_t blocks = (capacity + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_pair_zero, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<float4*>(pairs),
-                       reinterpret_cast<float*>(static_cast<char*>(pairs) + (size_t)capacity * 32), pair_count,
-                       capacity);
+void launch_pair_zero(void* pairs, const uint32_t* pair_count, int64_t capacity, hipStream_t st,
+                      const uint32_t* ranges, uint32_t n_tiles, uint32_t* order, uint32_t* order_count) {
+    OrderArgs o;
+    o.ranges = reinterpret_cast<const uint2*>(ranges);
+    o.n_tiles = n_tiles;
+    o.order = order;
+    o.count = order_count;
+    if (capacity <= 0 && !order) return;
+    int64_t blocks = (capacity + kZeroThreads - 1) / kZeroThreads;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    if (order) ++blocks;
+    hipLaunchKernelGGL(k_pair_zero, dim3((unsigned)blocks), dim3(kZeroThreads), 0, st, static_cast<float4*>(pairs),
+                       reinterpret_cast<float*>(static_cast<char*>(pairs) + (size_t)(capacity > 0 ? capacity : 0) * 32),
+                       pair_count, capacity, o);
 }
 
 void launch_pair_gather(int64_t nslots, const uint32_t* first, const uint32_t* tiles_touched, const void* pairs,
@@ -484,6 +520,8 @@ void launch_render_bwd(const RenderArgs& r, const float* final_T, const uint32_t
     a.queue = r.queue;
     a.order = r.order;
     a.n_tiles = r.n_tiles;
+    a.torder = r.tile_order;
+    a.torder_n = r.tile_order_count;
     const int pg = (r.queue && !state) ? r.persistent_grid : 0;
     if (pg > 0) launch_fill_u32(r.queue, 0u, 1, st);
 #define GS_BWD(x, y) launch_t<x, y>(a, pg, r.item_cap, st)

@@ -61,6 +61,8 @@ struct FwdArgs {
     uint32_t* queue;        // persistent launch: next queue position (zeroed before launch)
     const uint32_t* order;  // persistent launch: tiles in processing order (NULL = 0, 1, ...)
     uint32_t n_tiles;
+    const uint32_t* torder;     // one workgroup per tile: workgroup b takes tile torder[b] (NULL: tile b)
+    const uint32_t* torder_n;   // ... and exits when b >= *torder_n (the order holds every tile)
 };
 
 template <int B>
@@ -259,7 +261,12 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdSha
 template <class L, int MODE>
 __global__ __launch_bounds__(L::NCELL) void k_render_fwd(FwdArgs a) {
     __shared__ FwdShared<kBatch> sh;
-    fwd_tile<L, MODE, kBatch>(a, blockIdx.x, sh);
+    uint32_t tile = blockIdx.x;
+    if (a.torder) {
+        if (blockIdx.x >= *a.torder_n) return;
+        tile = a.torder[blockIdx.x];
+    }
+    fwd_tile<L, MODE, kBatch>(a, tile, sh);
 }
 
 template <class L, int B>
@@ -335,6 +342,8 @@ void launch_render_fwd(const RenderArgs& r, float* image, float* final_T, uint32
     a.queue = r.queue;
     a.order = r.order;
     a.n_tiles = r.n_tiles;
+    a.torder = r.tile_order;
+    a.torder_n = r.tile_order_count;
     const int pg = (r.queue && !stats && !state) ? r.persistent_grid : 0;
     if (pg > 0) launch_fill_u32(r.queue, 0u, 1, st);
 #define GS_FWD(x, y) launch_t<x, y>(a, pg, r.fwd_batch, st)
