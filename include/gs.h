@@ -150,6 +150,14 @@ typedef struct {
  *                        then reads them instead of recomputing them, so
  *                        it must get the buffer the forward of these bins
  *                        filled (or NULL).  gs_bin_sort ignores it.
+ *   tile_order           optional (NULL = not kept), n_tiles + 1 uint32,
+ *                        4-byte aligned: written by gs_bin_sort, [0] =
+ *                        n_tiles and [1..n_tiles] every tile, those with the
+ *                        longest lists first (by the floor of log2 of the
+ *                        length; order within a class unspecified); both
+ *                        blends then start their workgroups in that order,
+ *                        so that the longest tiles do not finish last.
+ *                        Results do not depend on it.
  * Tiles are numbered row-major: tile_y * ceil(W / tile_w) + tile_x. */
 typedef struct {
     uint64_t *keys;
@@ -160,6 +168,7 @@ typedef struct {
     int32_t *status;
     int64_t pair_capacity;
     uint64_t *cell_masks;
+    uint32_t *tile_order;
 } gs_bins;
 
 /* Gradient output (caller-owned device buffers, same shapes as gs_gaussians

@@ -57,7 +57,7 @@ class gs_proj(C.Structure):
 
 class gs_bins(C.Structure):
     _fields_ = [("keys", P), ("vals", P), ("first", P), ("ranges", P), ("pair_count", P), ("status", P),
-                ("pair_capacity", C.c_int64), ("cell_masks", P)]
+                ("pair_capacity", C.c_int64), ("cell_masks", P), ("tile_order", P)]
 
 
 class gs_grads(C.Structure):

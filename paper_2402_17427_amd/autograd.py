@@ -176,7 +176,7 @@ def held_bytes(settings: RasterSettings, g: DeviceGaussians) -> dict:
         return {"frame": 0, "state": 0}
     s = slots[0]
     f = s.frame
-    tensors = [f.rec, f.depth, f.rect, f.tiles_touched, f.first, f.ranges, f.pair_count, f.status, f.image,
+    tensors = [f.rec, f.depth, f.rect, f.tiles_touched, f.first, f.ranges, f.tile_order, f.pair_count, f.status, f.image,
                f.final_T, f.n_contrib, f.keys, f.vals, f.ws, f.bwd_ws, f.masks, f.grad2d]
     fb = sum(t.numel() * t.element_size() for t in tensors if t is not None)
     sb = s.state.numel() if (settings.store_state and s.state is not None) else 0

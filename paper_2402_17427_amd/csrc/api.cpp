@@ -157,6 +157,10 @@ RenderArgs single_render(const gs_proj* proj, const gs_bins* bins, const Cam& C,
     r.tw = tw;
     r.th = th;
     r.masks = bins->cell_masks;
+    if (bins->tile_order) {   // the blend order gs_bin_sort kept: [0] = count, [1..] = tiles
+        r.tile_order = bins->tile_order + 1;
+        r.tile_order_count = bins->tile_order;
+    }
     return r;
 }
 
@@ -178,6 +182,7 @@ gs_status check_bins(const gs_bins* b) {
     if (reinterpret_cast<uintptr_t>(b->ranges) % 8) return fail(GS_ERR_INVALID, "ranges not 8-byte aligned");
     if (reinterpret_cast<uintptr_t>(b->cell_masks) % 8)
         return fail(GS_ERR_INVALID, "cell_masks not 8-byte aligned");
+    if (reinterpret_cast<uintptr_t>(b->tile_order) % 4) return fail(GS_ERR_INVALID, "tile_order not 4-byte aligned");
     return GS_OK;
 }
 
@@ -256,7 +261,7 @@ gs_status gs_bin_sort(const gs_proj* proj, int64_t n, const gs_camera* cam, cons
     {
         ProfScope ps("sort", st);
         launch_bin_sort(out->keys, out->vals, alt_k, alt_v, out->pair_count, cap, tb, out->ranges, n_tiles, sort_ws,
-                        st, true);
+                        st, true, out->tile_order);
     }
     return check_hip("gs_bin_sort");
 }
@@ -366,10 +371,14 @@ gs_status render_bwd_impl(const gs_gaussians* g, const gs_camera* cam, const gs_
     RenderArgs r = single_render(proj, bins, C, tw, th);
     {
         ProfScope ps("pair_zero", st);
-        launch_pair_zero(ws, bins->pair_count, cap, st, bins->ranges, r.n_tiles, order, order_n);
+        if (bins->tile_order) {   // the order gs_bin_sort kept
+            launch_pair_zero(ws, bins->pair_count, cap, st);
+        } else {                  // else one of the tiles with pairs, built with the zeroing
+            launch_pair_zero(ws, bins->pair_count, cap, st, bins->ranges, r.n_tiles, order, order_n);
+            r.tile_order = order;
+            r.tile_order_count = order_n;
+        }
     }
-    r.tile_order = order;
-    r.tile_order_count = order_n;
     {
         ProfScope ps(state ? "render_bwd_stored" : "render_bwd", st);
         launch_render_bwd(r, final_T, n_contrib, dL_dimage, reinterpret_cast<const ushort4*>(proj->rect),

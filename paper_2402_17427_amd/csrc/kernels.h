@@ -64,9 +64,11 @@ void launch_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint3
 bool bin_sort_emit_to_alt(int tile_bits);
 // What the emission must zero for launch_bin_sort(..., zeroed = true).
 ZeroList bin_sort_zero_list(void* ws, int64_t capacity, int tile_bits, uint32_t* ranges, int64_t n_tiles);
+// `tile_order` (optional, n_tiles + 1 words): [0] = n_tiles, [1..] every
+// tile, the longest lists first (launch_tile_order with the empty tiles).
 void launch_bin_sort(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals, const uint32_t* count,
                      int64_t capacity, int tile_bits, uint32_t* ranges, int64_t n_tiles, void* ws, hipStream_t st,
-                     bool zeroed = false);
+                     bool zeroed = false, uint32_t* tile_order = nullptr);
 
 // ---- blend (render_fwd.hip / render_bwd.hip)
 // What both blend passes read: records, sorted values, per-tile ranges of

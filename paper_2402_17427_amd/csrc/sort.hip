@@ -27,6 +27,7 @@
 // The pair count stays on the device; grids are sized for the capacity
 // and surplus workgroups find no partition and exit.
 #include "kernels.h"
+#include "tile_order.h"
 
 namespace gs {
 
@@ -310,19 +311,37 @@ constexpr int kSegCap = 1024;   // longest run sorted in LDS
 // leaves the order as it is).  Entries are (depth << 32 | position in the
 // run), ranked in order 64 at a time with ballot matches and running digit
 // counts; the values are gathered by position at the end.  One wave per
-// run: no workgroup barriers, and the loops stop at the run's length.
-__global__ __launch_bounds__(kWave) void k_seg_sort_lds(const uint64_t* __restrict__ kin,
-                                                        const uint32_t* __restrict__ vin,
-                                                        uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                        const uint2* __restrict__ ranges) {
+// run, four runs per workgroup: no workgroup barriers, and the loops stop
+// at the run's length.  With `order` set, an extra first workgroup writes
+// the tiles' blend order meanwhile (order[0] = the tile count, order[1..] =
+// every tile, longest list first: tile_order_block).
+constexpr int kSegWaves = 4;
+
+__global__ __launch_bounds__(kSegWaves * kWave) void k_seg_sort_lds(const uint64_t* __restrict__ kin,
+                                                                    const uint32_t* __restrict__ vin,
+                                                                    uint64_t* __restrict__ kout,
+                                                                    uint32_t* __restrict__ vout,
+                                                                    const uint2* __restrict__ ranges,
+                                                                    uint32_t n_tiles, uint32_t* __restrict__ order) {
     constexpr int IPL = kSegCap / kWave;   // entries per lane
     constexpr int DPL = kRadix / kWave;    // digits per lane in the offset scan
-    __shared__ uint64_t s[kSegCap];
-    __shared__ uint32_t s_cnt[kRadix];     // digit counts, then digit offsets
-    const uint2 r = ranges[blockIdx.x];
+    __shared__ uint64_t s_all[kSegWaves][kSegCap];
+    __shared__ uint32_t s_cnt_all[kSegWaves][kRadix];   // per wave: digit counts, then digit offsets
+    const int first = order ? 1 : 0;
+    if (order && blockIdx.x == 0) {
+        __shared__ uint32_t s_h[kSegWaves][kTileClasses + 1];
+        tile_order_block<kSegWaves * kWave>(ranges, n_tiles, order + 1, order, 1, s_h);
+        return;
+    }
+    const int wv = threadIdx.x / kWave;
+    const uint32_t tile = ((uint32_t)blockIdx.x - (uint32_t)first) * kSegWaves + (uint32_t)wv;
+    if (tile >= n_tiles) return;
+    uint64_t* s = s_all[wv];
+    uint32_t* s_cnt = s_cnt_all[wv];
+    const uint2 r = ranges[tile];
     const uint32_t n = r.y - r.x;
     if (n == 0u || n > (uint32_t)kSegCap) return;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
     if (n == 1u) {
         if (lane == 0) {
             kout[r.x] = kin[r.x];
@@ -595,7 +614,7 @@ ZeroList bin_sort_zero_list(void* ws, int64_t capacity, int tile_bits, uint32_t*
 
 void launch_bin_sort(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals, const uint32_t* count,
                      int64_t capacity, int tile_bits, uint32_t* ranges, int64_t n_tiles, void* ws, hipStream_t st,
-                     bool zeroed) {
+                     bool zeroed, uint32_t* tile_order) {
     // tile bits: passes 4 .. 4 + ceil(tile_bits / 8) - 1, ending in the
     // alternate buffers (the emission went where bin_sort_emit_to_alt says);
     // the workspace words and ranges are zeroed by the emission when
@@ -604,10 +623,15 @@ void launch_bin_sort(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_
                                bin_sort_emit_to_alt(tile_bits), ws, st, zeroed ? nullptr : ranges, n_tiles * 2,
                                zeroed);
     launch_tile_ranges(alt_keys, count, capacity, n_tiles, ranges, st, zeroed || (r & 2) != 0);
-    if (capacity == 0 || n_tiles == 0) return;
+    if (n_tiles == 0 || (capacity == 0 && !tile_order)) {
+        if (tile_order) launch_fill_u32(tile_order, 0u, 1, st);
+        return;
+    }
     const uint2* rg = reinterpret_cast<const uint2*>(ranges);
-    hipLaunchKernelGGL(k_seg_sort_lds, dim3((unsigned)n_tiles), dim3(kWave), 0, st, alt_keys, alt_vals, keys, vals,
-                       rg);
+    const unsigned blocks = (unsigned)((n_tiles + kSegWaves - 1) / kSegWaves) + (tile_order ? 1u : 0u);
+    hipLaunchKernelGGL(k_seg_sort_lds, dim3(blocks), dim3(kSegWaves * kWave), 0, st, alt_keys, alt_vals, keys, vals,
+                       rg, (uint32_t)n_tiles, tile_order);
+    if (capacity == 0) return;
     hipLaunchKernelGGL(k_seg_sort_long, dim3((unsigned)n_tiles), dim3(kSegThreads), 0, st, alt_keys, alt_vals, keys,
                        vals, rg);
 }

@@ -84,7 +84,7 @@ class Frame:
     `ensure_capacity`/`check_status`, which read the device status)."""
 
     def __init__(self, n: int, sh_degree: int, cam, tile=(16, 16), capacity: int | None = None,
-                 device="cuda", grads: bool = True, keep_masks: bool = True):
+                 device="cuda", grads: bool = True, keep_masks: bool = True, keep_order: bool = True):
         self.n, self.sh_degree, self.device = int(n), int(sh_degree), device
         self.cam = cam
         self.c_cam = N.make_camera(cam)
@@ -101,6 +101,8 @@ class Frame:
         self.tiles_touched = torch.empty(n1, dtype=torch.int32, device=device)
         self.first = torch.empty(n1, dtype=torch.int32, device=device)
         self.ranges = torch.empty(self.n_tiles * 2, dtype=torch.int32, device=device)
+        # the blend order gs_bin_sort keeps (count, then every tile, longest list first)
+        self.tile_order = torch.empty(self.n_tiles + 1, dtype=torch.int32, device=device) if keep_order else None
         self.pair_count = torch.zeros(2, dtype=torch.int32, device=device)
         self.status = torch.zeros(1, dtype=torch.int32, device=device)
         npix = self.W * self.H
@@ -157,6 +159,7 @@ class Frame:
         b.pair_count, b.status = _ptr(self.pair_count), _ptr(self.status)
         b.pair_capacity = self.capacity
         b.cell_masks = _ptr(self.masks) if self.masks is not None else None
+        b.tile_order = _ptr(self.tile_order) if self.tile_order is not None else None
         return b
 
     def c_grads(self, out: dict | None = None) -> N.gs_grads:

@@ -289,6 +289,38 @@ def test_backward_with_the_forward_masks_equals_the_recomputing_backward(name, t
     assert np.abs(kept["grad2d"]).max() > 0
 
 
+@pytest.mark.parametrize("name,tile", [("city_dense", (16, 16)), ("city_ragged", (16, 16)), ("city_ragged", (32, 8)),
+                                       ("config1", (16, 16))])
+def test_kept_tile_order_is_longest_first_and_changes_no_bit(name, tile):
+    """gs_bin_sort's blend order holds every tile once, by non-increasing
+    floor(log2(list length)) with the empty tiles last; blending in that
+    order (forward and backward) gives bitwise the images and gradients of
+    the frame that keeps no order."""
+    _case(f"tile order {name} tile={tile}")
+    g, cam = _scene(name)
+    dg = raster.DeviceGaussians.from_host(g)
+    dimg = torch.as_tensor(scenes.grad_image(cam, 9, "normal")).cuda()
+    out = []
+    for keep in (True, False):
+        f = raster.Frame(dg.n, dg.sh_degree, cam, tile=tile, keep_order=keep)
+        f.ensure_capacity(dg)
+        f.render_fwd()
+        gr = raster.render_backward(f, dg, dimg)
+        out.append((f.image.cpu().numpy(), {k: v.cpu().numpy() for k, v in gr.items()}, f))
+    (img_a, gr_a, fa), (img_b, gr_b, _) = out
+    np.testing.assert_array_equal(img_a, img_b)
+    for k in gr_a:
+        np.testing.assert_array_equal(gr_a[k], gr_b[k], err_msg=k)
+    order = fa.tile_order.cpu().numpy().astype(np.int64)
+    rg = fa.ranges.cpu().numpy().astype(np.int64).reshape(-1, 2)
+    assert order[0] == fa.n_tiles
+    tiles = order[1:]
+    assert np.array_equal(np.sort(tiles), np.arange(fa.n_tiles))
+    n = rg[tiles, 1] - rg[tiles, 0]
+    cls = np.where(n > 0, np.floor(np.log2(np.maximum(n, 1))), -1)
+    assert np.all(np.diff(cls) <= 0), "classes must not increase along the order"
+
+
 def test_capacity_overflow_sets_status_and_poisons_outputs():
     _case("capacity overflow")
     g, cam = _scene("config1")
