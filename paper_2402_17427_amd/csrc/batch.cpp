@@ -125,8 +125,7 @@ struct gs_batch {
     uint32_t* pair_count = nullptr;
     int32_t* status = nullptr;
     uint32_t* queue = nullptr;
-    uint32_t* tiles_dev = nullptr;   // device count of the tile order (every tile)
-    uint32_t* tvals = nullptr;   // persistent blends: the tiles, longest list first
+    uint32_t* torder = nullptr;   // the blend order the sort keeps: [0] = n_tiles, [1..] every tile
     uint32_t max_tiles = 0;
     // per-pixel buffers
     float* final_T = nullptr;
@@ -153,7 +152,7 @@ struct gs_batch {
         if (graph) (void)hipGraphDestroy(graph);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         void* ptrs[] = {d_views, d_jobs, d_targets, rec, depth, rect, tt, g2d, first, scan_ws, keys, alt_k, vals,
-                        alt_v, pair_grad, masks, sort_ws, ranges, pair_count, status, queue, tiles_dev, tvals,
+                        alt_v, pair_grad, masks, sort_ws, ranges, pair_count, status, queue, torder,
                         final_T, n_contrib, dimg, loss_ws, sched};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
@@ -186,7 +185,6 @@ struct gs_batch {
         }
         n_tiles = base;
         if (hipMemcpyAsync(d_views, h_views.data(), sizeof(View) * n, hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(tiles_dev, &n_tiles, sizeof(uint32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             return check_hip("gs_batch: view table upload");
         grid_fwd = std::max(1, render_persistent_grid(w, h, false, fwd_batch) * grid_pct / 100);
@@ -222,7 +220,7 @@ struct gs_batch {
     void enqueue_step(hipStream_t st) {
         enqueue_project_bin(st);
         launch_bin_sort(keys, vals, alt_k, alt_v, pair_count, capacity, tile_bits(n_tiles), ranges, n_tiles, sort_ws,
-                        st, true);
+                        st, true, torder);
         RenderArgs r;
         std::memset(&r, 0, sizeof r);
         r.rec = rec;
@@ -236,10 +234,13 @@ struct gs_batch {
         r.masks = masks;
         r.fwd_batch = fwd_batch;
         r.item_cap = item_cap;
+        // both launch forms take the tiles longest list first, in the order
+        // the sort kept
+        r.tile_order = torder + 1;
+        r.tile_order_count = torder;
         if (persistent) {
-            launch_tile_order(ranges, n_tiles, tvals, tiles_dev, true, st);
             r.queue = queue;
-            r.order = tvals;
+            r.order = torder + 1;
             r.persistent_grid = grid_fwd;
         }
         launch_render_fwd(r, images, final_T, n_contrib, nullptr, nullptr, st);
@@ -457,8 +458,8 @@ gs_status gs_batch_create(const gs_gaussians* cells, const gs_camera* cams, cons
             (s = dmalloc(&b->rect, slot)) || (s = dmalloc(&b->tt, slot)) || (s = dmalloc(&b->g2d, slot * 9)) || (s = dmalloc(&b->first, slot)) ||
             (s = dmalloc(reinterpret_cast<char**>(&b->scan_ws), scan_workspace_bytes(slot))) ||
             (s = dmalloc(&b->ranges, (size_t)max_tiles * 2)) || (s = dmalloc(&b->pair_count, 2)) ||
-            (s = dmalloc(&b->status, 1)) || (s = dmalloc(&b->queue, 1)) || (s = dmalloc(&b->tiles_dev, 1)) ||
-            (s = dmalloc(&b->tvals, max_tiles)) || (s = dmalloc(&b->final_T, pix)) ||
+            (s = dmalloc(&b->status, 1)) || (s = dmalloc(&b->queue, 1)) || (s = dmalloc(&b->torder, (size_t)max_tiles + 1)) ||
+            (s = dmalloc(&b->final_T, pix)) ||
             (s = dmalloc(&b->n_contrib, pix)) || (s = dmalloc(&b->dimg, img)))
             ;
     }

@@ -83,6 +83,7 @@ struct Pipe {
     uint32_t *vals = nullptr, *alt_v = nullptr;
     void* sort_ws = nullptr;
     uint32_t* ranges = nullptr;
+    uint32_t* torder = nullptr;   // the blend order the sort keeps: [0] = tile count, [1..] the tiles
     uint32_t* pair_count = nullptr;
     int32_t* status = nullptr;
     float* final_T = nullptr;
@@ -281,7 +282,7 @@ struct gs_server {
         launch_emit_pairs(slot, p.tt, p.rect, p.depth, jt, vt, cap, to_alt ? p.alt_k : p.keys,
                           to_alt ? p.alt_v : p.vals, nullptr, p.pair_count, p.status, p.scan_ws, st, &z);
         launch_bin_sort(p.keys, p.vals, p.alt_k, p.alt_v, p.pair_count, cap, tb, p.ranges, tile, p.sort_ws, st,
-                        true);
+                        true, p.torder);
         RenderArgs r;
         std::memset(&r, 0, sizeof r);
         r.rec = p.rec;
@@ -292,6 +293,8 @@ struct gs_server {
         r.n_tiles = tile;
         r.tw = tw;
         r.th = th;
+        r.tile_order = p.torder + 1;   // longest lists first
+        r.tile_order_count = p.torder;
         launch_render_fwd(r, nullptr, p.final_T, p.n_contrib, nullptr, nullptr, st);
         (void)hipMemcpyAsync(p.h_status, p.status, sizeof(int32_t), hipMemcpyDeviceToHost, st);
         (void)hipMemcpyAsync(p.h_status + 1, p.pair_count, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
@@ -361,7 +364,7 @@ struct gs_server {
         for (Pipe& p : pipes) {
             if (p.st) (void)hipStreamSynchronize(p.st);
             void* ptrs[] = {p.rec, p.depth, p.rect, p.tt, p.scan_ws, p.keys, p.alt_k, p.vals, p.alt_v, p.sort_ws,
-                            p.ranges, p.pair_count, p.status, p.final_T, p.n_contrib, p.d_views, p.d_jobs};
+                            p.ranges, p.torder, p.pair_count, p.status, p.final_T, p.n_contrib, p.d_views, p.d_jobs};
             for (void* q : ptrs)
                 if (q) (void)hipFree(q);
             if (p.h_views) (void)hipHostFree(p.h_views);
@@ -441,7 +444,7 @@ gs_status gs_serve_create(const gs_gaussians* scene, const float* cell_aabbs, co
              dalloc(&p.keys, p.pairs_cap) && dalloc(&p.alt_k, p.pairs_cap) && dalloc(&p.vals, p.pairs_cap) &&
              dalloc(&p.alt_v, p.pairs_cap) &&
              dalloc(reinterpret_cast<char**>(&p.sort_ws), sort_workspace_bytes(p.pairs_cap, 64)) &&
-             dalloc(&p.ranges, (size_t)p.tiles_cap * 2) && dalloc(&p.pair_count, 2) && dalloc(&p.status, 1) &&
+             dalloc(&p.ranges, (size_t)p.tiles_cap * 2) && dalloc(&p.torder, (size_t)p.tiles_cap + 1) && dalloc(&p.pair_count, 2) && dalloc(&p.status, 1) &&
              dalloc(&p.final_T, p.pix_cap) && dalloc(&p.n_contrib, p.pix_cap) && dalloc(&p.d_views, p.views_cap) &&
              dalloc(&p.d_jobs, p.jobs_cap) &&
              hipHostMalloc(reinterpret_cast<void**>(&p.h_views), sizeof(View) * p.views_cap, 0) == hipSuccess &&
