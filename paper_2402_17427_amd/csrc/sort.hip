@@ -97,9 +97,23 @@ __global__ __launch_bounds__(256) void k_hist(const uint64_t* __restrict__ keys,
     for (int j = threadIdx.x; j < kMaxPasses * kRadix; j += 256) h[j] = 0u;
     __syncthreads();
     const int64_t P = clamp_count(count, w.capacity);
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256) {
-        const uint64_t k = keys[i];
-        for (int p = p0; p < p1; ++p) atomicAdd(&h[p * kRadix + (uint32_t)((k >> (8 * p)) & 0xFF)], 1u);
+    // eight keys per thread are loaded before any is counted, so that a
+    // thread waits for memory once per eight keys (each load instruction
+    // still reads 256 consecutive keys per workgroup)
+    constexpr int kLoads = 8;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x; i0 < P; i0 += stride * kLoads) {
+        uint64_t k[kLoads];
+#pragma unroll
+        for (int j = 0; j < kLoads; ++j) {
+            const int64_t i = i0 + j * stride;
+            k[j] = i < P ? keys[i] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < kLoads; ++j) {
+            if (i0 + j * stride >= P) break;
+            for (int p = p0; p < p1; ++p) atomicAdd(&h[p * kRadix + (uint32_t)((k[j] >> (8 * p)) & 0xFF)], 1u);
+        }
     }
     __syncthreads();
     for (int j = p0 * kRadix + threadIdx.x; j < p1 * kRadix; j += 256)
