@@ -198,15 +198,18 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
         __syncthreads();
         const int kmin = sh.kmin;
 
-        // walk: entries kmin .. ncand - 1 of the lane's word, from the back
+        // walk: entries kmin .. ncand - 1 of the lane's word, from the back.
+        // The next entry's staged values and slot base are read from LDS
+        // while the current entry is computed (a lane whose word is empty
+        // reads entry kmin, which exists, and writes nothing).
         uint64_t wk = kmin >= kWave ? 0ull : (walk & ~((1ull << kmin) - 1ull));
         const uint64_t below = (1ull << lane) - 1ull;
-        if (__ballot(wk != 0ull) != 0ull) do {
-            const bool has = wk != 0ull;
-            const int kk = has ? high_bit(wk) : kmin;
-            wk &= ~(1ull << kk);
-            const Staged g = staged_at(sh.s, kk);
-            const uint32_t pos = (uint32_t)(lo0 + kk);
+        // one walked entry: its nine sums for the lane's cell, written to
+        // the lane's slot
+        auto entry = [&](const bool has, const int kk, const Staged& g, const uint32_t sbase, const uint64_t smask) {
+            // list position of the entry; past every pixel's last
+            // contributor for a lane with nothing to walk
+            const uint32_t pos = has ? (uint32_t)(lo0 + kk) : 0xFFFFFFFFu;
             float dxs[L::CW], dys[L::CH], qa[L::CW], qb[L::CW], qc[L::CH];
 #pragma unroll
             for (int i = 0; i < L::CW; ++i) {
@@ -225,36 +228,39 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
             for (int p = 0; p < NP; ++p) {
                 const int i = p % L::CW, j = p / L::CW;
                 float alpha, G, Ts;
-                bool capped;
+                bool capped, above;
+                const bool listed = pos < my_last[p];
                 if (STORED) {
                     const int pix = (py0 + j - y0) * L::TW + (px0 + i - x0);
-                    const bool rd = has && pos < my_last[p];
-                    const float2 st = rd ? a.state[(int64_t)(rg.x + pos) * L::NT + pix] : make_float2(0.f, 0.f);
+                    const float2 st = listed ? a.state[(int64_t)(rg.x + pos) * L::NT + pix] : make_float2(0.f, 0.f);
                     alpha = fabsf(st.x);
                     capped = st.x < 0.0f;
+                    above = alpha > 0.0f;
                     G = alpha * __builtin_amdgcn_rcpf(g.coef.w);
                     Ts = st.y;
                 } else {
+                    // the forward's decision: alpha (capped at 0.99) counts
+                    // when the exponent is not positive and alpha >= 1/255
                     const float pw = __builtin_fmaf(qb[i], dys[j], qa[i] + qc[j]);
                     G = __builtin_amdgcn_exp2f(pw);
                     const float araw = g.coef.w * G;
                     capped = araw > kAlphaMax;
-                    const float al0 = capped ? kAlphaMax : araw;
-                    alpha = (pw > 0.0f || al0 < kAlphaMin) ? 0.0f : al0;
+                    alpha = capped ? kAlphaMax : araw;
+                    above = pw <= 0.0f && alpha >= kAlphaMin;
                     Ts = 0.0f;
                 }
                 // Branch-free: a pair that does not contribute gets alpha 0,
                 // which leaves T and the suffix colour unchanged and makes
                 // every gradient term 0.
-                const bool contrib = has && pos < my_last[p] && alpha > 0.0f;
+                const bool contrib = listed && above;
                 const float al = contrib ? alpha : 0.0f;
                 const float iom = __builtin_amdgcn_rcpf(1.0f - al);
                 const float Ti = STORED ? (contrib ? Ts : T[p]) : T[p] * iom;
                 const float w = al * Ti;
-                const float grgb = g0[p] * g.col.x + g1[p] * g.col.y + g2[p] * g.col.z;
+                const float grgb = __builtin_fmaf(g2[p], g.col.z, __builtin_fmaf(g1[p], g.col.y, g0[p] * g.col.x));
                 // dL/dalpha = g . (rgb T_i - S_i / (1 - alpha)), S_i = suffix colour + T_final bg;
                 // no gradient through a capped alpha
-                const float da0 = grgb * Ti - ga[p] * iom;
+                const float da0 = __builtin_fmaf(grgb, Ti, -(ga[p] * iom));
                 const float da = (contrib && !capped) ? da0 : 0.0f;
                 ga[p] = __builtin_fmaf(grgb, w, ga[p]);
                 T[p] = Ti;
@@ -286,22 +292,23 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
 #pragma unroll
                 for (int i = 1; i < L::CW; ++i) rs[j] += dpow[j * L::CW + i];
             }
-            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+            float s0 = dxs[0] * cs[0], s1 = dys[0] * rs[0];
+            float s2 = s0 * dxs[0], s3 = dxs[0] * csy[0], s4 = s1 * dys[0];
 #pragma unroll
-            for (int i = 0; i < L::CW; ++i) {
+            for (int i = 1; i < L::CW; ++i) {
                 const float t = dxs[i] * cs[i];
                 s0 += t;
                 s2 = __builtin_fmaf(t, dxs[i], s2);
                 s3 = __builtin_fmaf(dxs[i], csy[i], s3);
             }
 #pragma unroll
-            for (int j = 0; j < L::CH; ++j) {
+            for (int j = 1; j < L::CH; ++j) {
                 const float u = dys[j] * rs[j];
                 s1 += u;
                 s4 = __builtin_fmaf(u, dys[j], s4);
             }
             if (has) {
-                const uint32_t slot = sh.base[wv][kk] + (uint32_t)__popcll(sh.mask[wv][kk] & below);
+                const uint32_t slot = sbase + (uint32_t)__popcll(smask & below);
                 sh.item[0][slot] = s0;
                 sh.item[1][slot] = s1;
                 sh.item[2][slot] = s2;
@@ -312,7 +319,33 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
                 sh.item[7][slot] = s7;
                 sh.item[8][slot] = s8;
             }
-        } while (__ballot(wk != 0ull) != 0ull);
+        };
+        if (__ballot(wk != 0ull) != 0ull) {
+            // two entries per trip, each reading the next one's values
+            // into the other register set
+            int kk = wk != 0ull ? high_bit(wk) : kmin;
+            Staged g = staged_at(sh.s, kk);
+            uint32_t sbase = sh.base[wv][kk];
+            uint64_t smask = sh.mask[wv][kk];
+            for (;;) {
+                bool has = wk != 0ull;
+                wk &= ~(1ull << kk);
+                const int kn = wk != 0ull ? high_bit(wk) : kmin;
+                const Staged gn = staged_at(sh.s, kn);
+                const uint32_t sbn = sh.base[wv][kn];
+                const uint64_t smn = sh.mask[wv][kn];
+                entry(has, kk, g, sbase, smask);
+                if (__ballot(wk != 0ull) == 0ull) break;
+                has = wk != 0ull;
+                wk &= ~(1ull << kn);
+                kk = wk != 0ull ? high_bit(wk) : kmin;
+                g = staged_at(sh.s, kk);
+                sbase = sh.base[wv][kk];
+                smask = sh.mask[wv][kk];
+                entry(has, kn, gn, sbn, smn);
+                if (__ballot(wk != 0ull) == 0ull) break;
+            }
+        }
         __syncthreads();
 
         // the accumulated sums of dpow dx, dpow dy, dpow dx^2, dpow dx dy,

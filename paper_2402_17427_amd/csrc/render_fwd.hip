@@ -193,15 +193,17 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdSha
                 const float G = __builtin_amdgcn_exp2f(pw);
                 const float araw = g.coef.w * G;
                 const float al0 = fminf(araw, kAlphaMax);
-                const float alpha = (pw > 0.0f || al0 < kAlphaMin) ? 0.0f : al0;
+                // alpha counts when the exponent is not positive and alpha >= 1/255
+                const bool above = !(pw > 0.0f) && !(al0 < kAlphaMin);
                 const bool act = has && T[p] > 0.0f;
                 if (MODE == kStore && act) {
                     const int pix = (py0 + j - y0) * L::TW + (px0 + i - x0);
+                    const float alpha = above ? al0 : 0.0f;
                     a.state[(int64_t)(b0 + (uint32_t)kk) * L::NT + pix] =
-                        make_float2(araw > kAlphaMax && alpha > 0.0f ? -alpha : alpha, T[p]);
+                        make_float2(araw > kAlphaMax && above ? -alpha : alpha, T[p]);
                 }
-                const bool supp = act && alpha > 0.0f;
-                const float Tn = T[p] * (1.0f - alpha);
+                const bool supp = act && above;
+                const float Tn = T[p] * (1.0f - al0);   // used only where supp
                 const bool stop = supp && Tn < kTMin;
                 const bool blend = supp && !stop;
                 if (STATS) {
@@ -209,7 +211,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdSha
                     n_supp += supp ? 1u : 0u;
                     n_blend += blend ? 1u : 0u;
                 }
-                const float w = blend ? alpha * T[p] : 0.0f;
+                const float w = blend ? al0 * T[p] : 0.0f;
                 c0[p] = __builtin_fmaf(g.col.x, w, c0[p]);
                 c1[p] = __builtin_fmaf(g.col.y, w, c1[p]);
                 c2[p] = __builtin_fmaf(g.col.z, w, c2[p]);
