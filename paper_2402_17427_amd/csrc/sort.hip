@@ -13,7 +13,8 @@
 //                 first kernel does this instead)
 //   k_hist        one read of every key builds the histograms of all
 //                 passes at once (LDS atomics, then one global atomic per
-//                 non-empty bin and workgroup)
+//                 non-empty bin and workgroup; few, large workgroups, since
+//                 the global atomics on the same bins serialise)
 //   k_onesweep    per pass: every workgroup first scans the pass's 256
 //                 bins into global digit offsets, then takes the next
 //                 partition of 4096 keys from an atomic counter, ranks its
@@ -45,6 +46,8 @@ constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1u;
 constexpr int kMaxGrid = 2048;
 constexpr int kLook = 8;                        // look-back window (partitions per step)
+constexpr int kHistThreads = 1024;
+constexpr int kHistGrid = 128;                  // at most: fewer flushes of the same bins
 
 struct SortWs {
     int64_t capacity;    // pairs the buffers hold; the device count is clamped to it
@@ -91,18 +94,18 @@ __global__ __launch_bounds__(256) void k_sort_clear(SortWs w, const uint32_t* __
 }
 
 // Digit histograms of passes p0 .. p1-1 in one read of the keys.
-__global__ __launch_bounds__(256) void k_hist(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ count,
-                                              int p0, int p1, SortWs w) {
+__global__ __launch_bounds__(kHistThreads) void k_hist(const uint64_t* __restrict__ keys,
+                                                       const uint32_t* __restrict__ count, int p0, int p1, SortWs w) {
     __shared__ uint32_t h[kMaxPasses * kRadix];
-    for (int j = threadIdx.x; j < kMaxPasses * kRadix; j += 256) h[j] = 0u;
+    for (int j = threadIdx.x; j < kMaxPasses * kRadix; j += kHistThreads) h[j] = 0u;
     __syncthreads();
     const int64_t P = clamp_count(count, w.capacity);
     // eight keys per thread are loaded before any is counted, so that a
     // thread waits for memory once per eight keys (each load instruction
-    // still reads 256 consecutive keys per workgroup)
+    // still reads consecutive keys across the workgroup)
     constexpr int kLoads = 8;
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x; i0 < P; i0 += stride * kLoads) {
+    const int64_t stride = (int64_t)gridDim.x * kHistThreads;
+    for (int64_t i0 = (int64_t)blockIdx.x * kHistThreads + threadIdx.x; i0 < P; i0 += stride * kLoads) {
         uint64_t k[kLoads];
 #pragma unroll
         for (int j = 0; j < kLoads; ++j) {
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(256) void k_hist(const uint64_t* __restrict__ keys,
         }
     }
     __syncthreads();
-    for (int j = p0 * kRadix + threadIdx.x; j < p1 * kRadix; j += 256)
+    for (int j = p0 * kRadix + threadIdx.x; j < p1 * kRadix; j += kHistThreads)
         if (h[j]) atomicAdd(&w.hist[j], h[j]);
 }
 
@@ -570,9 +573,11 @@ int radix_passes(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* a
                            zero ? zero_count : (int64_t)0);
     }
     const uint64_t* src = start_in_alt ? alt_keys : keys;
-    int64_t hb = (capacity + 256 * 16 - 1) / (256 * 16);
-    if (hb > kMaxGrid) hb = kMaxGrid;
-    hipLaunchKernelGGL(k_hist, dim3((unsigned)hb), dim3(256), 0, st, src, count, p0, p1, w);
+    // one round of eight keys per thread where the capacity is small
+    int64_t hb = (capacity + kHistThreads * 8 - 1) / (kHistThreads * 8);
+    if (hb > kHistGrid) hb = kHistGrid;
+    if (hb < 1) hb = 1;
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)hb), dim3(kHistThreads), 0, st, src, count, p0, p1, w);
     int64_t grid = parts < kMaxGrid ? parts : kMaxGrid;
     bool in_alt = start_in_alt;
     for (int p = p0; p < p1; ++p) {
