@@ -134,6 +134,7 @@ struct gs_batch {
     // caller outputs
     float* images = nullptr;
     float* loss = nullptr;
+    double* l1_part = nullptr;    // per view: the L1 loss's partial sums
     // Eq. 1 loss (lambda > 0) per view, and the optimiser step of every cell
     float lambda = 0.f;
     std::vector<const float*> h_targets;
@@ -153,7 +154,7 @@ struct gs_batch {
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         void* ptrs[] = {d_views, d_jobs, d_targets, rec, depth, rect, tt, g2d, first, scan_ws, keys, alt_k, vals,
                         alt_v, pair_grad, masks, sort_ws, ranges, pair_count, status, queue, torder,
-                        final_T, n_contrib, dimg, loss_ws, sched};
+                        final_T, n_contrib, dimg, loss_ws, sched, l1_part};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
     }
@@ -253,7 +254,7 @@ struct gs_batch {
                 launch_loss_finish(3, cams[c].W, cams[c].H, lambda, ws, loss + c, st, 1);
             }
         } else {
-            launch_l1(vt(), n, max_pix, d_targets, images, dimg, loss, status, st);
+            launch_l1(vt(), n, max_pix, d_targets, images, dimg, loss, l1_part, status, st);
         }
         launch_pair_zero(pair_grad, pair_count, capacity, st);
         if (persistent) r.persistent_grid = grid_bwd;
@@ -460,7 +461,8 @@ gs_status gs_batch_create(const gs_gaussians* cells, const gs_camera* cams, cons
             (s = dmalloc(&b->ranges, (size_t)max_tiles * 2)) || (s = dmalloc(&b->pair_count, 2)) ||
             (s = dmalloc(&b->status, 1)) || (s = dmalloc(&b->queue, 1)) || (s = dmalloc(&b->torder, (size_t)max_tiles + 1)) ||
             (s = dmalloc(&b->final_T, pix)) ||
-            (s = dmalloc(&b->n_contrib, pix)) || (s = dmalloc(&b->dimg, img)))
+            (s = dmalloc(&b->n_contrib, pix)) || (s = dmalloc(&b->dimg, img)) ||
+            (s = dmalloc(&b->l1_part, (size_t)n_cells * kL1MaxChunks)))
             ;
     }
     if (!s) {

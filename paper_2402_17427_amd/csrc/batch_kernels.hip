@@ -15,11 +15,14 @@ namespace {
 
 constexpr int kL1Threads = 256;
 
-// One workgroup per (view, chunk of pixels): grid.y = view.
+// One workgroup per (view, chunk of pixels): grid.y = view.  Each
+// workgroup writes its partial sum (FP64) to partials[view][chunk]; the
+// finishing kernel adds them in chunk order, so the loss is the same on
+// every run.
 __global__ __launch_bounds__(kL1Threads) void k_l1(ViewTab views, const float* const* __restrict__ targets,
                                                    const float* __restrict__ image, float* __restrict__ dimg,
-                                                   float* __restrict__ loss, const int32_t* __restrict__ status) {
-    __shared__ float red[kL1Threads / kWave];
+                                                   double* __restrict__ partials, const int32_t* __restrict__ status) {
+    __shared__ double red[kL1Threads / kWave];
     const int v = blockIdx.y;
     const View V = view_at(views, v);
     const int64_t npix = (int64_t)V.cam.W * V.cam.H;
@@ -27,21 +30,32 @@ __global__ __launch_bounds__(kL1Threads) void k_l1(ViewTab views, const float* c
     const float* __restrict__ tgt = targets[v];
     const float inv = 1.0f / (float)total;
     const bool ok = *status == 0;
-    float acc = 0.f;
+    double acc = 0.0;
     for (int64_t q = (int64_t)blockIdx.x * kL1Threads + threadIdx.x; q < total;
          q += (int64_t)gridDim.x * kL1Threads) {
         const float d = image[V.img_base + q] - tgt[q];
-        acc += fabsf(d);
+        acc += (double)fabsf(d);
         dimg[V.img_base + q] = ok ? (d > 0.f ? inv : (d < 0.f ? -inv : 0.f)) : 0.f;
     }
     for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
-        float s = 0.f;
+        double s = 0.0;
         for (int k = 0; k < kL1Threads / kWave; ++k) s += red[k];
-        atomicAdd(&loss[v], s * inv);
+        partials[(int64_t)v * gridDim.x + blockIdx.x] = s;
     }
+}
+
+// One wave per view: loss[v] = (sum of the view's nb partials) / (3 W H).
+__global__ __launch_bounds__(kWave) void k_l1_finish(ViewTab views, const double* __restrict__ partials, int nb,
+                                                     float* __restrict__ loss) {
+    const int v = blockIdx.x, lane = threadIdx.x;
+    const View V = view_at(views, v);
+    double s = 0.0;
+    for (int k = lane; k < nb; k += kWave) s += partials[(int64_t)v * nb + k];
+    for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+    if (lane == 0) loss[v] = (float)(s / (3.0 * (double)V.cam.W * (double)V.cam.H));
 }
 
 constexpr int kOrderThreads = 1024;
@@ -67,14 +81,14 @@ void launch_tile_order(const uint32_t* ranges, uint32_t n_tiles, uint32_t* order
 }
 
 void launch_l1(const ViewTab& views, int n_views, int64_t max_pix, const float* const* targets, const float* image,
-               float* dimg, float* loss, const int32_t* status, hipStream_t st) {
+               float* dimg, float* loss, double* partials, const int32_t* status, hipStream_t st) {
     if (n_views == 0) return;
-    launch_fill_u32(reinterpret_cast<uint32_t*>(loss), 0u, (size_t)n_views, st);
     int64_t bx = (3 * max_pix + kL1Threads * 8 - 1) / (kL1Threads * 8);
-    if (bx > 1024) bx = 1024;
+    if (bx > kL1MaxChunks) bx = kL1MaxChunks;
     if (bx < 1) bx = 1;
     hipLaunchKernelGGL(k_l1, dim3((unsigned)bx, (unsigned)n_views), dim3(kL1Threads), 0, st, views, targets, image,
-                       dimg, loss, status);
+                       dimg, partials, status);
+    hipLaunchKernelGGL(k_l1_finish, dim3((unsigned)n_views), dim3(kWave), 0, st, views, partials, (int)bx, loss);
 }
 
 

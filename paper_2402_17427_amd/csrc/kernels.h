@@ -142,10 +142,13 @@ int render_item_cap_small();
 
 // ---- batched step (batch_kernels.hip)
 // L1 loss of every view against its target ([3][H][W] each; targets is a
-// device array of device pointers): loss[v] = mean |I - I*|, dimg =
-// sign(I - I*) / (3 W H), zero when *status != 0.  loss is zeroed here.
+// device array of device pointers): loss[v] = mean |I - I*| (FP64 partial
+// sums added in a fixed order, the same on every run), dimg =
+// sign(I - I*) / (3 W H), zero when *status != 0.  partials holds
+// kL1MaxChunks doubles per view.
+constexpr int kL1MaxChunks = 1024;
 void launch_l1(const ViewTab& views, int n_views, int64_t max_pix, const float* const* targets, const float* image,
-               float* dimg, float* loss, const int32_t* status, hipStream_t st);
+               float* dimg, float* loss, double* partials, const int32_t* status, hipStream_t st);
 // ---- training loss (loss.hip)
 // Eq. 1 / Eq. 3 loss of one [channels][height][width] image against its
 // target: d_image gets the gradient (of both terms when image_l1 is NULL,

@@ -436,11 +436,14 @@ __global__ __launch_bounds__(kZeroThreads) void k_pair_zero(float4* __restrict__
     }
     const int64_t P = (int64_t)*pair_count < cap ? (int64_t)*pair_count : cap;
     const int64_t nb = (int64_t)gridDim.x - first;
-    for (int64_t p = ((int64_t)blockIdx.x - first) * kZeroThreads + threadIdx.x; p < P; p += nb * kZeroThreads) {
-        pg8[2 * p] = make_float4(0.f, 0.f, 0.f, 0.f);
-        pg8[2 * p + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-        pg1[p] = 0.f;
-    }
+    const int64_t t0 = ((int64_t)blockIdx.x - first) * kZeroThreads + threadIdx.x, step = nb * kZeroThreads;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    // the 32-byte part of every pair as consecutive 16-byte vectors, then
+    // the 4-byte plane four pairs at a time (it starts 16-byte aligned)
+    for (int64_t j = t0; j < 2 * P; j += step) pg8[j] = z4;
+    float4* pg1v = reinterpret_cast<float4*>(pg1);
+    for (int64_t j = t0; j < P / 4; j += step) pg1v[j] = z4;
+    for (int64_t p = (P / 4) * 4 + t0; p < P; p += step) pg1[p] = 0.f;
 }
 
 // Per slot: the sum over its pairs (emission order, so a fixed order) of
