@@ -960,7 +960,7 @@ def main():
     # time of each stage against its measured (event-bracketed) time, and
     # the sum of the ideal times against the whole step
     stage_of = {"a1_project": ["project"], "a2_scan_emit": ["scan_emit"], "a3_sort": ["sort"], "a4_ranges": [],
-                "a5_render_fwd": ["render_fwd"], "a6_render_bwd": ["pair_zero", "render_bwd", "pair_gather"],
+                "a5_render_fwd": ["render_fwd"], "a6_render_bwd": ["tile_order", "render_bwd", "pair_gather"],
                 "a7_project_bwd": ["project_bwd"]}
     ideal_us = sum(v["ideal_us"] for v in model.values())
     for k, v in model.items():

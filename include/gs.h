@@ -621,7 +621,7 @@ gs_status gs_render_stats(const gs_proj *proj, const gs_bins *bins, const gs_cam
 
 /* Stage timing (observability).  gs_profile_enable(1) starts a window in
  * which every stage the library enqueues (project, scan_emit, sort,
- * tile_ranges, render_fwd, pair_zero, render_bwd, pair_gather,
+ * tile_ranges, render_fwd, tile_order, render_bwd, pair_gather,
  * project_bwd, loss, loss_finish, adam, ...) is bracketed by HIP events on its stream;
  * gs_profile_enable(0) ends it and discards what was recorded.
  * gs_profile_select(stages) restricts the bracketing to the stages named

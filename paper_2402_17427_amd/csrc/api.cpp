@@ -369,15 +369,11 @@ gs_status render_bwd_impl(const gs_gaussians* g, const gs_camera* cam, const gs_
     uint32_t* order = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + align256(pair_grad_bytes(cap)));
     uint32_t* order_n = order + (cap > 0 ? cap : 0);
     RenderArgs r = single_render(proj, bins, C, tw, th);
-    {
-        ProfScope ps("pair_zero", st);
-        if (bins->tile_order) {   // the order gs_bin_sort kept
-            launch_pair_zero(ws, bins->pair_count, cap, st);
-        } else {                  // else one of the tiles with pairs, built with the zeroing
-            launch_pair_zero(ws, bins->pair_count, cap, st, bins->ranges, r.n_tiles, order, order_n);
-            r.tile_order = order;
-            r.tile_order_count = order_n;
-        }
+    if (!bins->tile_order) {   // else the order gs_bin_sort kept
+        ProfScope ps("tile_order", st);
+        launch_tile_order(bins->ranges, r.n_tiles, order, order_n, false, st);
+        r.tile_order = order;
+        r.tile_order_count = order_n;
     }
     {
         ProfScope ps(state ? "render_bwd_stored" : "render_bwd", st);

@@ -256,7 +256,6 @@ struct gs_batch {
         } else {
             launch_l1(vt(), n, max_pix, d_targets, images, dimg, loss, l1_part, status, st);
         }
-        launch_pair_zero(pair_grad, pair_count, capacity, st);
         if (persistent) r.persistent_grid = grid_bwd;
         launch_render_bwd(r, final_T, n_contrib, dimg, rect, first, pair_grad, capacity, nullptr, st);
         launch_pair_gather(nslots, first, tt, pair_grad, capacity, status, g2d, st);

@@ -112,21 +112,16 @@ void launch_render_fwd(const RenderArgs& r, float* image, float* final_T, uint32
                        unsigned long long* stats, float2* state, hipStream_t st);
 // Per-pair image-space gradients of the blend.  `pairs` is the pair
 // gradient buffer (pair_grad_bytes(capacity) bytes): the backward writes,
-// for every (Gaussian, tile) pair with a contribution, the nine sums of
-// the tile's pixels at the pair's emission position (first[slot] + the
-// tile's row-major index in the Gaussian's rectangle); launch_pair_zero
-// must have cleared it.  state != NULL reads the stored blend state
-// instead of recomputing it.
+// for every (Gaussian, tile) pair of the frame, the nine sums of the
+// tile's pixels (zero where the Gaussian contributes nothing) at the
+// pair's emission position (first[slot] + the tile's row-major index in
+// the Gaussian's rectangle), so the buffer needs no clearing; when the bin
+// status is set it writes nothing and the gather yields zeros.
+// state != NULL reads the stored blend state instead of recomputing it.
 void launch_render_bwd(const RenderArgs& r, const float* final_T, const uint32_t* n_contrib, const float* dimg,
                        const ushort4* rect, const uint32_t* first, void* pairs, int64_t capacity,
                        const float2* state, hipStream_t st);
 size_t pair_grad_bytes(int64_t capacity);
-// Zero the first min(*pair_count, capacity) entries of the pair buffer;
-// with `order` set, the same launch also writes the tiles with pairs in
-// longest-list-first order (launch_tile_order without the empty tiles).
-void launch_pair_zero(void* pairs, const uint32_t* pair_count, int64_t capacity, hipStream_t st,
-                      const uint32_t* ranges = nullptr, uint32_t n_tiles = 0, uint32_t* order = nullptr,
-                      uint32_t* order_count = nullptr);
 // g2d[9][nslots] = the sum of each slot's pair entries (emission order);
 // zeros for culled slots and when *status != 0.
 void launch_pair_gather(int64_t nslots, const uint32_t* first, const uint32_t* tiles_touched, const void* pairs,

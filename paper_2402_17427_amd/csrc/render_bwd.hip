@@ -145,6 +145,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
     __syncthreads();
     // never walk past the tile's list, whatever n_contrib holds
     int hi = (int)min(sh.max_last, rg.y - rg.x);
+    const int hi0 = hi;
 
     while (hi > 0) {
         const int lo0 = hi > kChunk ? hi - kChunk : 0;
@@ -365,10 +366,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
 #pragma unroll
                 for (int c = 0; c < 9; ++c) m[c] += sh.item[c][e];
             }
-            bool any = false;
-#pragma unroll
-            for (int c = 0; c < 9; ++c) any |= m[c] != 0.0f;
-            if (any) {
+            {   // every entry's pair slot is written, zero sums included
                 const uint32_t gid = sh.gid[tid];
                 const ushort4 r = a.rect[gid];
                 const int64_t p = (int64_t)a.first[gid] + (int64_t)(ty - (int)r.y) * ((int)r.z - (int)r.x) +
@@ -384,6 +382,20 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
             }
         }
         hi = lo0 + kmin;
+    }
+    // Entries behind every pixel's last contributor were never staged:
+    // their pair slots get zeros here, so that every pair of the frame is
+    // written by its tile's workgroup and the gather needs no cleared buffer.
+    const int nlist = (int)(rg.y - rg.x);
+    for (int e = hi0 + tid; e < nlist; e += L::NCELL) {
+        const uint32_t gid = a.vals[rg.x + (uint32_t)e];
+        const ushort4 r = a.rect[gid];
+        const int64_t p = (int64_t)a.first[gid] + (int64_t)(ty - (int)r.y) * ((int)r.z - (int)r.x) + (tx - (int)r.x);
+        if (p >= 0 && p < a.cap) {
+            a.pg8[2 * p] = make_float4(0.f, 0.f, 0.f, 0.f);
+            a.pg8[2 * p + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            a.pg1[p] = 0.f;
+        }
     }
 }
 
@@ -410,40 +422,6 @@ __global__ __launch_bounds__(L::NCELL) void k_render_bwd_persistent(BwdArgs a) {
         if (q >= a.n_tiles) break;
         bwd_tile<L, false, CAP>(a, a.order ? a.order[q] : q, sh);
     }
-}
-
-// What k_pair_zero's first workgroup does besides: the tiles with pairs in
-// longest-list-first order for the backward (tile_order_block).
-struct OrderArgs {
-    const uint2* ranges;
-    uint32_t n_tiles;
-    uint32_t* order;   // NULL: no order
-    uint32_t* count;
-};
-
-// Clear the pair gradient buffer over the pairs of this frame; with an
-// order requested, workgroup 0 builds it while the others clear.
-constexpr int kZeroThreads = 1024;
-
-__global__ __launch_bounds__(kZeroThreads) void k_pair_zero(float4* __restrict__ pg8, float* __restrict__ pg1,
-                                                            const uint32_t* __restrict__ pair_count, int64_t cap,
-                                                            OrderArgs o) {
-    const int first = o.order ? 1 : 0;
-    if (o.order && blockIdx.x == 0) {
-        __shared__ uint32_t s_h[kZeroThreads / kWave][kTileClasses + 1];
-        tile_order_block<kZeroThreads>(o.ranges, o.n_tiles, o.order, o.count, 0, s_h);
-        return;
-    }
-    const int64_t P = (int64_t)*pair_count < cap ? (int64_t)*pair_count : cap;
-    const int64_t nb = (int64_t)gridDim.x - first;
-    const int64_t t0 = ((int64_t)blockIdx.x - first) * kZeroThreads + threadIdx.x, step = nb * kZeroThreads;
-    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    // the 32-byte part of every pair as consecutive 16-byte vectors, then
-    // the 4-byte plane four pairs at a time (it starts 16-byte aligned)
-    for (int64_t j = t0; j < 2 * P; j += step) pg8[j] = z4;
-    float4* pg1v = reinterpret_cast<float4*>(pg1);
-    for (int64_t j = t0; j < P / 4; j += step) pg1v[j] = z4;
-    for (int64_t p = (P / 4) * 4 + t0; p < P; p += step) pg1[p] = 0.f;
 }
 
 // Per slot: the sum over its pairs (emission order, so a fixed order) of
@@ -505,23 +483,6 @@ hipError_t occupancy_t(int* per, int cap) {
 }  // namespace
 
 size_t pair_grad_bytes(int64_t capacity) { return (size_t)(capacity > 0 ? capacity : 0) * 36; }
-
-void launch_pair_zero(void* pairs, const uint32_t* pair_count, int64_t capacity, hipStream_t st,
-                      const uint32_t* ranges, uint32_t n_tiles, uint32_t* order, uint32_t* order_count) {
-    OrderArgs o;
-    o.ranges = reinterpret_cast<const uint2*>(ranges);
-    o.n_tiles = n_tiles;
-    o.order = order;
-    o.count = order_count;
-    if (capacity <= 0 && !order) return;
-    int64_t blocks = (capacity + kZeroThreads - 1) / kZeroThreads;
-    if (blocks > 1024) blocks = 1024;
-    if (blocks < 1) blocks = 1;
-    if (order) ++blocks;
-    hipLaunchKernelGGL(k_pair_zero, dim3((unsigned)blocks), dim3(kZeroThreads), 0, st, static_cast<float4*>(pairs),
-                       reinterpret_cast<float*>(static_cast<char*>(pairs) + (size_t)(capacity > 0 ? capacity : 0) * 32),
-                       pair_count, capacity, o);
-}
 
 void launch_pair_gather(int64_t nslots, const uint32_t* first, const uint32_t* tiles_touched, const void* pairs,
                         int64_t capacity, const int32_t* status, float* g2d, hipStream_t st) {
