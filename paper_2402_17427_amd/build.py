@@ -27,7 +27,7 @@ LIB = os.path.join(HERE, "libgsmi.so")
 LIB_SAN = os.path.join(HERE, "libgsmi_san.so")
 ARCH = os.environ.get("GSMI_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "profile.cpp", "project.hip", "binning.hip", "sort.hip", "render_fwd.hip", "render_bwd.hip",
+SOURCES = ["api.cpp", "profile.cpp", "project.hip", "binning.hip", "sort.hip", "bin_direct.hip", "render_fwd.hip", "render_bwd.hip",
            "batch_kernels.hip", "loss.hip", "optim.hip", "partition.hip", "partition.cpp", "appearance.hip", "appearance.cpp", "batch.cpp", "serve.cpp"]
 EXTRA_SOURCES = []
 

@@ -105,6 +105,7 @@ size_t bwd_ws_bytes(int64_t cap) {
 }
 
 size_t bin_sort_ws_bytes(int64_t n, int64_t cap, int64_t n_tiles) {
+    if (bin_direct_supported(n_tiles)) return bin_direct_ws_bytes(n, cap, n_tiles);
     const int kb = 32 + tile_bits(n_tiles);
     return align256(scan_workspace_bytes(n)) + align256((size_t)cap * 8) + align256((size_t)cap * 4) +
            align256(sort_workspace_bytes(cap, kb));
@@ -238,6 +239,20 @@ gs_status gs_bin_sort(const gs_proj* proj, int64_t n, const gs_camera* cam, cons
     const size_t need = bin_sort_ws_bytes(n, cap, n_tiles);
     if (!ws || ws_bytes < need) return fail(GS_ERR_INVALID, "workspace too small: %zu < %zu", ws_bytes, need);
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (bin_direct_supported(n_tiles)) {   // pairs placed into their tile runs, then each run sorted
+        {
+            ProfScope ps("scan_emit", st);
+            launch_bin_direct_place(n, reinterpret_cast<const ushort4*>(proj->rect), proj->depth,
+                                    (C.W + tw - 1) / tw, n_tiles, cap, out->first, out->ranges, out->pair_count,
+                                    out->status, ws, st);
+        }
+        {
+            ProfScope ps("sort", st);
+            launch_bin_direct_sort(n, n_tiles, cap, out->keys, out->vals, out->ranges, out->status, out->tile_order,
+                                   ws, st);
+        }
+        return check_hip("gs_bin_sort");
+    }
     char* p = static_cast<char*>(ws);
     void* scan_ws = p;
     p += align256(scan_workspace_bytes(n));

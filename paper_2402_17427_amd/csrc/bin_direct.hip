@@ -1,0 +1,684 @@
+// Binning of one view by direct placement: every (Gaussian, tile) pair is
+// written straight into its tile's run, then each run is sorted by depth.
+//
+// VastGaussian (arXiv 2402.17427), section 3: the projected Gaussians are
+// assigned to the screen tiles their support touches, and every tile's list
+// is ordered by depth before the blend.  The tile of each pair is known
+// before any pair exists (the Gaussian's tile rectangle from the
+// projection), so for a view of at most kDirectMaxTiles tiles no radix sort
+// over the tile bits is needed:
+//   k_dcount    per block of consecutive Gaussians: its pairs per tile (an
+//               LDS histogram) -> row b of a count matrix [blocks][tiles],
+//               and its pair total
+//   k_dscan     per strip of 64 tiles: exclusive scan down the matrix's
+//               columns (where each block's share of a tile's run starts
+//               inside the run) and the tile totals; one more workgroup
+//               scans the block totals (each block's first emission position)
+//   k_dscatter  per block: the tile starts (every workgroup scans the tile
+//               totals itself; the first also writes the ranges, pair count
+//               and capacity status), every Gaussian's emission position (`first`,
+//               the exclusive prefix of its tile counts), and each of its
+//               pairs (depth bits << 32 | index) written at the block's
+//               cursor in the tile's run (LDS atomics, so the order inside a
+//               block's share of a run is arbitrary)
+//   k_dsort     one wave per run of at most 1024 pairs: stable LDS radix
+//               passes over the depth bytes that vary in the run; entries
+//               of equal depth are then put in index order (odd-even
+//               transposition, or for long groups a second sort on (depth,
+//               index), index bytes first), so the order never depends on
+//               the scatter's; the sorted keys (tile << 32 | depth bits) and
+//               values are written out; an extra workgroup writes the blend
+//               order (longest list first)
+//   k_dsort_long  one workgroup per longer run: the (depth, index) order by
+//               stable passes over global memory
+// The output -- keys, values, ranges, `first`, pair count, status and tile
+// order -- is exactly that of the emission + stable sort of the whole key
+// (tile, then depth; equal keys in emission, i.e. index, order).
+#include "kernels.h"
+#include "tile_order.h"
+
+namespace gs {
+
+namespace {
+
+constexpr int kDThreads = 1024;
+constexpr int kDWaves = kDThreads / kWave;
+constexpr int kDPer = 4;            // consecutive Gaussians per thread and round
+constexpr int kDMaxBlocks = 256;    // rows of the count matrix (at most one per CU)
+constexpr int64_t kDMinChunk = 2048;  // fewest Gaussians per block
+constexpr int kDRadix = 256;
+constexpr int kDSortWaves = 4;
+constexpr int kDSortCap = 1024;     // longest run sorted in LDS
+constexpr int kDLongThreads = 256;
+constexpr int kDFixPhases = 16;     // odd-even phases for equal depths before a full re-sort
+
+// Exclusive scan over the NT threads of a workgroup; *total = the sum.
+template <int NT>
+__device__ __forceinline__ uint64_t block_scan_ex(uint64_t v, uint64_t* total) {
+    __shared__ uint64_t wsum[NT / kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint64_t x = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) wsum[w] = x;
+    __syncthreads();
+    uint64_t base = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < NT / kWave; ++k) {
+        const uint64_t s = wsum[k];
+        if (k < w) base += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + x - v;
+}
+
+// A Gaussian's tile rectangle cut to the view's grid (a no-op for the
+// rectangles the projection writes for the same tile shape; it keeps the
+// placement inside the runs for any input).
+__device__ __forceinline__ ushort4 grid_rect(ushort4 r, int ntx, int nty) {
+    r.z = (unsigned short)min((int)r.z, ntx);
+    r.w = (unsigned short)min((int)r.w, nty);
+    if (r.x >= r.z || r.y >= r.w) r = make_ushort4(0, 0, 0, 0);
+    return r;
+}
+
+__device__ __forceinline__ uint32_t rect_area(const ushort4 r) {
+    return (uint32_t)(r.z - r.x) * (uint32_t)(r.w - r.y);
+}
+
+// The block's Gaussians [g0, g1).
+__device__ __forceinline__ void block_range(int64_t n, int64_t chunk, int64_t* g0, int64_t* g1) {
+    *g0 = (int64_t)blockIdx.x * chunk;
+    *g1 = *g0 + chunk < n ? *g0 + chunk : n;
+}
+
+__global__ __launch_bounds__(kDThreads) void k_dcount(const ushort4* __restrict__ rect, int64_t n, int64_t chunk,
+                                                      int ntx, int nty, uint32_t n_tiles, uint32_t* __restrict__ M,
+                                                      uint64_t* __restrict__ bsum) {
+    extern __shared__ uint32_t s_hist[];
+    const int tid = threadIdx.x;
+    for (uint32_t t = tid; t < n_tiles; t += kDThreads) s_hist[t] = 0u;
+    __syncthreads();
+    int64_t g0, g1;
+    block_range(n, chunk, &g0, &g1);
+    uint64_t pairs = 0;
+    for (int64_t base = g0; base < g1; base += (int64_t)kDThreads * kDPer) {
+        // kDPer Gaussians per thread, strided by the workgroup (coalesced),
+        // all loaded before any is counted
+        ushort4 r[kDPer];
+#pragma unroll
+        for (int k = 0; k < kDPer; ++k) {
+            const int64_t i = base + k * kDThreads + tid;
+            r[k] = i < g1 ? rect[i] : make_ushort4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < kDPer; ++k) {
+            r[k] = grid_rect(r[k], ntx, nty);
+            pairs += rect_area(r[k]);
+            for (int ty = r[k].y; ty < r[k].w; ++ty)
+                for (int tx = r[k].x; tx < r[k].z; ++tx) atomicAdd(&s_hist[ty * ntx + tx], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t* row = M + (int64_t)blockIdx.x * n_tiles;
+    for (uint32_t t = tid; t < n_tiles; t += kDThreads) row[t] = s_hist[t];
+    uint64_t tot;
+    block_scan_ex<kDThreads>(pairs, &tot);
+    if (tid == 0) bsum[blockIdx.x] = tot;
+}
+
+// The block that comes r-th in a tile's run.  Workgroups are dealt to the
+// eight XCDs in turn (block b runs on XCD b mod 8), so the blocks are taken
+// XCD by XCD: the blocks of one XCD then write one contiguous stretch of
+// every run, and its L2 fills whole cache lines before it writes them back
+// (in plain block order every placed pair would be a partial line of its
+// own, written back to HBM alone).
+__device__ __forceinline__ int xcd_major_block(int r, int nb) {
+    constexpr int X = 8;
+    const int q = nb / X, rem = nb % X;   // XCDs x < rem hold q + 1 blocks, the others q
+    int x, j;
+    if (r < (q + 1) * rem) {
+        x = r / (q + 1);
+        j = r % (q + 1);
+    } else {
+        const int r2 = r - (q + 1) * rem;
+        x = rem + r2 / q;
+        j = r2 % q;
+    }
+    return x + X * j;
+}
+
+// Workgroup c < strips: tiles 64 c .. 64 c + 63 (one per lane), the matrix
+// rows split over the 16 waves (in XCD-major block order); the last
+// workgroup scans the block totals.
+__global__ __launch_bounds__(kDThreads) void k_dscan(uint32_t* __restrict__ M, int nb, uint32_t n_tiles,
+                                                     uint32_t* __restrict__ ttot, uint64_t* __restrict__ bsum) {
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const uint32_t strips = (n_tiles + kWave - 1) / kWave;
+    if (blockIdx.x == strips) {
+        const uint64_t v = tid < nb ? bsum[tid] : 0u;
+        uint64_t tot;
+        const uint64_t ex = block_scan_ex<kDThreads>(v, &tot);
+        if (tid < nb) bsum[tid] = ex;
+        return;
+    }
+    constexpr int kRows = kDMaxBlocks / kDWaves;   // rows per wave
+    __shared__ uint32_t s_part[kDWaves][kWave];
+    __shared__ int s_row[kDMaxBlocks];   // the block of each place in the runs
+    if (tid < nb) s_row[tid] = xcd_major_block(tid, nb);
+    __syncthreads();
+    const uint32_t t = blockIdx.x * kWave + (uint32_t)lane;
+    const int r0 = wv * kRows;
+    uint32_t v[kRows], s = 0;
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int r = r0 + k;
+        v[k] = (r < nb && t < n_tiles) ? M[(int64_t)s_row[r] * n_tiles + t] : 0u;
+        s += v[k];
+    }
+    s_part[wv][lane] = s;
+    __syncthreads();
+    uint32_t run = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kDWaves; ++w) {
+        const uint32_t p = s_part[w][lane];
+        if (w < wv) run += p;
+        tot += p;
+    }
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int r = r0 + k;
+        if (r < nb && t < n_tiles) M[(int64_t)s_row[r] * n_tiles + t] = run;
+        run += v[k];
+    }
+    if (wv == 0 && t < n_tiles) ttot[t] = tot;
+}
+
+constexpr int kDTileRounds = (int)((kDirectMaxTiles + kDThreads - 1) / kDThreads);
+
+// Every workgroup first forms the tile starts itself (the exclusive prefix
+// of the tile totals, tiles 1024 k + tid per thread so that the loads are
+// coalesced, all loaded before the first scan) and, from the grand total,
+// the capacity decision; workgroup 0 also writes the ranges, pair count
+// and status.
+__global__ __launch_bounds__(kDThreads) void k_dscatter(const ushort4* __restrict__ rect,
+                                                        const float* __restrict__ depth, int64_t n, int64_t chunk,
+                                                        int ntx, int nty, uint32_t n_tiles,
+                                                        const uint32_t* __restrict__ M,
+                                                        const uint32_t* __restrict__ ttot, int64_t capacity,
+                                                        const uint64_t* __restrict__ bsum,
+                                                        uint32_t* __restrict__ ranges,
+                                                        uint32_t* __restrict__ pair_count,
+                                                        int32_t* __restrict__ status,
+                                                        uint32_t* __restrict__ first, uint64_t* __restrict__ pairs) {
+    extern __shared__ uint32_t s_cur[];
+    const int tid = threadIdx.x;
+    const int rounds = (int)((n_tiles + kDThreads - 1) / kDThreads);
+    uint32_t c[kDTileRounds];
+#pragma unroll
+    for (int k = 0; k < kDTileRounds; ++k) {
+        const uint32_t t = (uint32_t)(k * kDThreads + tid);
+        c[k] = (k < rounds && t < n_tiles) ? ttot[t] : 0u;
+    }
+    uint64_t total = 0;
+#pragma unroll
+    for (int k = 0; k < kDTileRounds; ++k) {
+        if (k < rounds) {
+            uint64_t tot;
+            const uint64_t ex = total + block_scan_ex<kDThreads>(c[k], &tot);
+            total += tot;
+            const uint32_t t = (uint32_t)(k * kDThreads + tid);
+            if (t < n_tiles) s_cur[t] = (uint32_t)ex;
+        }
+    }
+    const bool over = total > (uint64_t)capacity;
+    if (blockIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kDTileRounds; ++k) {
+            const uint32_t t = (uint32_t)(k * kDThreads + tid);
+            if (k < rounds && t < n_tiles) {
+                // an empty tile's range is (0, 0), as a range pass over sorted keys leaves it
+                const bool none = over || c[k] == 0u;
+                reinterpret_cast<uint2*>(ranges)[t] =
+                    none ? make_uint2(0u, 0u) : make_uint2(s_cur[t], s_cur[t] + c[k]);
+            }
+        }
+        if (tid == 0) {
+            pair_count[0] = over ? 0u : (uint32_t)total;   // pairs the later stages process
+            pair_count[1] = total > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)total;   // pairs needed
+            *status = over ? -4 : 0;
+        }
+    }
+    const bool place = !over;
+    if (place) {
+        const uint32_t* row = M + (int64_t)blockIdx.x * n_tiles;
+        for (uint32_t t = tid; t < n_tiles; t += kDThreads) s_cur[t] += row[t];
+    }
+    __syncthreads();
+    int64_t g0, g1;
+    block_range(n, chunk, &g0, &g1);
+    uint64_t carry = bsum[blockIdx.x];
+    for (int64_t base = g0; base < g1; base += (int64_t)kDThreads * kDPer) {
+        // kDPer consecutive Gaussians per thread, so that one scan gives
+        // every emission position of the round
+        const int64_t i0 = base + (int64_t)tid * kDPer;
+        ushort4 r[kDPer];
+        uint32_t a[kDPer], s = 0;
+#pragma unroll
+        for (int k = 0; k < kDPer; ++k) {
+            r[k] = grid_rect(i0 + k < g1 ? rect[i0 + k] : make_ushort4(0, 0, 0, 0), ntx, nty);
+            a[k] = rect_area(r[k]);
+            s += a[k];
+        }
+        uint64_t tot;
+        uint64_t off = carry + block_scan_ex<kDThreads>(s, &tot);
+        carry += tot;
+#pragma unroll
+        for (int k = 0; k < kDPer; ++k) {
+            const int64_t i = i0 + k;
+            if (i < g1) {
+                if (first) first[i] = (uint32_t)off;
+                off += a[k];
+                if (place && a[k]) {
+                    const uint64_t hi = (uint64_t)__float_as_uint(depth[i]) << 32;
+                    for (int ty = r[k].y; ty < r[k].w; ++ty)
+                        for (int tx = r[k].x; tx < r[k].z; ++tx) {
+                            const uint32_t pos = atomicAdd(&s_cur[ty * ntx + tx], 1u);
+                            pairs[pos] = hi | (uint32_t)i;
+                        }
+                }
+            }
+        }
+    }
+}
+
+// One stable LDS radix pass of a wave's run s[0 .. n) on the 8 bits at
+// `shift`: items ranked 64 at a time in order (match by the digit's bits
+// with ballots, running digit counts), digit offsets from a scan of the
+// counts, then each item stored at its place.
+template <int IPL>
+__device__ __forceinline__ void wave_radix_pass(uint64_t* s, uint32_t* s_cnt, uint32_t n, int nq, int shift,
+                                                int lane, uint64_t lt_mask) {
+    constexpr int DPL = kDRadix / kWave;   // digits per lane in the offset scan
+    uint64_t it[IPL];
+    uint32_t rk[IPL];
+#pragma unroll
+    for (int q = 0; q < IPL; ++q) {
+        const uint32_t idx = (uint32_t)(q * kWave + lane);
+        it[q] = (q < nq && idx < n) ? s[idx] : 0ull;
+    }
+#pragma unroll
+    for (int e = 0; e < DPL; ++e) s_cnt[e * kWave + lane] = 0u;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < IPL; ++q) {
+        if (q < nq) {
+            const uint32_t idx = (uint32_t)(q * kWave + lane);
+            const bool ok = idx < n;
+            const uint32_t d = (uint32_t)(it[q] >> shift) & 0xFFu;
+            uint64_t mt = __ballot(ok);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t vote = __ballot(bit);
+                mt &= bit ? vote : ~vote;
+            }
+            const uint32_t below = (uint32_t)__popcll(mt & lt_mask);
+            const uint32_t old = ok ? s_cnt[d] : 0u;
+            rk[q] = old + below;
+            __builtin_amdgcn_wave_barrier();
+            if (ok && below == 0u) s_cnt[d] = old + (uint32_t)__popcll(mt);
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    {   // digit offsets: lane l owns digits l*DPL .. l*DPL + DPL - 1
+        uint32_t c[DPL], sum = 0;
+#pragma unroll
+        for (int e = 0; e < DPL; ++e) {
+            c[e] = s_cnt[lane * DPL + e];
+            sum += c[e];
+        }
+        uint32_t x = sum;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, kWave);
+            if (lane >= d) x += y;
+        }
+        uint32_t run = x - sum;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int e = 0; e < DPL; ++e) {
+            s_cnt[lane * DPL + e] = run;
+            run += c[e];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < IPL; ++q) {
+        const uint32_t idx = (uint32_t)(q * kWave + lane);
+        if (q < nq && idx < n) {
+            const uint32_t d = (uint32_t)(it[q] >> shift) & 0xFFu;
+            s[s_cnt[d] + rk[q]] = it[q];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) v |= (uint32_t)__shfl_xor((int)v, d, kWave);
+    return v;
+}
+
+// Runs of 1 .. kDSortCap pairs, one wave each, four per workgroup.
+// With `order` set, an extra first workgroup writes the blend order
+// meanwhile (order[0] = the tile count, order[1..] = every tile, longest
+// list first).
+__global__ __launch_bounds__(kDSortWaves * kWave) void k_dsort(const uint64_t* __restrict__ pin,
+                                                               uint64_t* __restrict__ kout,
+                                                               uint32_t* __restrict__ vout,
+                                                               const uint2* __restrict__ ranges, uint32_t n_tiles,
+                                                               const int32_t* __restrict__ status,
+                                                               uint32_t* __restrict__ order) {
+    constexpr int IPL = kDSortCap / kWave;
+    __shared__ uint64_t s_all[kDSortWaves][kDSortCap];
+    __shared__ uint32_t s_cnt_all[kDSortWaves][kDRadix];
+    const int first = order ? 1 : 0;
+    if (order && blockIdx.x == 0) {
+        __shared__ uint32_t s_h[kDSortWaves][kTileClasses + 1];
+        tile_order_block<kDSortWaves * kWave>(ranges, n_tiles, order + 1, order, 1, s_h);
+        return;
+    }
+    if (*status != 0) return;
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    const uint32_t tile = ((uint32_t)blockIdx.x - (uint32_t)first) * kDSortWaves + (uint32_t)wv;
+    if (tile >= n_tiles) return;
+    const uint2 r = ranges[tile];
+    const uint32_t n = r.y - r.x;
+    if (n == 0u || n > (uint32_t)kDSortCap) return;
+    const uint64_t thi = (uint64_t)tile << 32;
+    if (n == 1u) {
+        if (lane == 0) {
+            const uint64_t x = pin[r.x];
+            kout[r.x] = thi | (x >> 32);
+            vout[r.x] = (uint32_t)x;
+        }
+        return;
+    }
+    uint64_t* s = s_all[wv];
+    uint32_t* s_cnt = s_cnt_all[wv];
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int nq = (int)((n + kWave - 1) / kWave);
+    const uint64_t x0 = pin[r.x];
+    uint32_t vz = 0, vg = 0;   // bits in which the depths / indices of the run differ
+    for (uint32_t i = lane; i < n; i += kWave) {
+        const uint64_t x = pin[r.x + i];
+        s[i] = x;
+        vz |= (uint32_t)(x >> 32) ^ (uint32_t)(x0 >> 32);
+        vg |= (uint32_t)x ^ (uint32_t)x0;
+    }
+    vz = wave_or(vz);
+    vg = wave_or(vg);
+    // bytes of the item to pass over (bit p: bits 8p .. 8p + 7), lowest
+    // first; a stable pass over a byte on which the whole run agrees
+    // changes nothing, so only the varying ones are taken.  First the depth
+    // bytes; if two entries then share a depth (their order so far is the
+    // scatter's), the run is reloaded and sorted on (depth, index), index
+    // bytes first.  One pass body in a loop keeps the kernel small.
+    uint32_t zbytes = 0, gbytes = 0;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        if ((vz >> (8 * p)) & 0xFFu) zbytes |= 1u << (4 + p);
+        if ((vg >> (8 * p)) & 0xFFu) gbytes |= 1u << p;
+    }
+    uint32_t todo = zbytes;
+    bool again = true;
+    __builtin_amdgcn_wave_barrier();
+    for (;;) {
+#pragma unroll 1
+        while (todo) {
+            const int p = __builtin_ctz(todo);
+            todo &= todo - 1u;
+            wave_radix_pass<IPL>(s, s_cnt, n, nq, 8 * p, lane, lt_mask);
+        }
+        if (!again) break;
+        again = false;
+        // neighbours of equal depth into index order by odd-even
+        // transposition: comparisons never cross a change of depth, so each
+        // group of equal depths is sorted on its own, and two phases in a
+        // row without a swap leave every neighbour pair in order; a group
+        // too long to settle in kDFixPhases phases sends the run to the
+        // full (depth, index) sort
+        int quiet = 0;
+        for (int ph = 0; ph < kDFixPhases && quiet < 2; ++ph) {
+            bool sw = false;
+            for (uint32_t i = 2u * (uint32_t)lane + (uint32_t)(ph & 1); i + 1 < n; i += 2u * kWave) {
+                const uint64_t a = s[i], b = s[i + 1];
+                if ((a >> 32) == (b >> 32) && (uint32_t)a > (uint32_t)b) {
+                    s[i] = b;
+                    s[i + 1] = a;
+                    sw = true;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            quiet = __ballot(sw) != 0ull ? 0 : quiet + 1;
+        }
+        if (quiet >= 2) break;
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t i = lane; i < n; i += kWave) s[i] = pin[r.x + i];
+        __builtin_amdgcn_wave_barrier();
+        todo = gbytes | zbytes;
+    }
+    for (uint32_t i = lane; i < n; i += kWave) {
+        const uint64_t c = s[i];
+        kout[r.x + i] = thi | (c >> 32);
+        vout[r.x + i] = (uint32_t)c;
+    }
+}
+
+// Runs longer than kDSortCap: one workgroup sorts the run on (depth,
+// index) with stable 8-bit LSD passes over the bytes that vary in it (index
+// bytes first), 256 items at a time in order (ballot match ranks within a
+// wave, per-wave digit counts order the waves), ping-ponging between the
+// placed pairs and the key output; then writes keys and values.
+__global__ __launch_bounds__(kDLongThreads) void k_dsort_long(uint64_t* __restrict__ pa, uint64_t* __restrict__ kout,
+                                                              uint32_t* __restrict__ vout,
+                                                              const uint2* __restrict__ ranges,
+                                                              const int32_t* __restrict__ status) {
+    constexpr int W = kDLongThreads / kWave;
+    __shared__ uint32_t s_start[kDRadix];   // digit start in the run
+    __shared__ uint32_t s_run[kDRadix];     // items of each digit placed so far
+    __shared__ uint32_t s_wc[W][kDRadix];
+    __shared__ uint32_t s_w[kDRadix / kWave];
+    __shared__ uint32_t s_vary[2];
+    if (*status != 0) return;
+    const uint2 r = ranges[blockIdx.x];
+    const uint32_t n = r.y - r.x;
+    if (n <= (uint32_t)kDSortCap) return;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (tid < 2) s_vary[tid] = 0u;
+    __syncthreads();
+    {
+        const uint64_t x0 = pa[r.x];
+        uint32_t vz = 0, vg = 0;
+        for (uint32_t i = tid; i < n; i += kDLongThreads) {
+            const uint64_t x = pa[r.x + i];
+            vz |= (uint32_t)(x >> 32) ^ (uint32_t)(x0 >> 32);
+            vg |= (uint32_t)x ^ (uint32_t)x0;
+        }
+        vz = wave_or(vz);
+        vg = wave_or(vg);
+        if (lane == 0) {
+            atomicOr(&s_vary[0], vg);
+            atomicOr(&s_vary[1], vz);
+        }
+    }
+    __syncthreads();
+    const uint64_t vary = ((uint64_t)s_vary[1] << 32) | s_vary[0];
+    bool in_a = true;
+    for (int pass = 0; pass < 8; ++pass) {
+        const int shift = 8 * pass;
+        if (((vary >> shift) & 0xFFu) == 0u) continue;
+        const uint64_t* ki = in_a ? pa : kout;
+        uint64_t* ko = in_a ? kout : pa;
+        // digit counts of the run and their exclusive scan
+        s_start[tid] = 0u;
+        s_run[tid] = 0u;
+        for (int q = 0; q < W; ++q) s_wc[q][tid] = 0u;
+        __syncthreads();
+        for (uint32_t i = tid; i < n; i += kDLongThreads)
+            atomicAdd(&s_start[(uint32_t)(ki[r.x + i] >> shift) & 0xFFu], 1u);
+        __syncthreads();
+        {
+            const uint32_t v = s_start[tid];
+            uint32_t x = v;
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t y = __shfl_up(x, d, kWave);
+                if (lane >= d) x += y;
+            }
+            if (lane == kWave - 1) s_w[wv] = x;
+            __syncthreads();
+            uint32_t base = 0;
+            for (int q = 0; q < kDRadix / kWave; ++q)
+                if (q < wv) base += s_w[q];
+            s_start[tid] = base + x - v;
+        }
+        __syncthreads();
+        for (uint32_t c0 = 0; c0 < n; c0 += kDLongThreads) {
+            const uint32_t i = c0 + (uint32_t)tid;
+            const bool ok = i < n;
+            const uint64_t key = ok ? ki[r.x + i] : 0ull;
+            const uint32_t d = (uint32_t)(key >> shift) & 0xFFu;
+            uint64_t mt = __ballot(ok);
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t vote = __ballot(bit);
+                mt &= bit ? vote : ~vote;
+            }
+            const uint32_t below = (uint32_t)__popcll(mt & lt_mask);
+            if (ok && below == 0u) s_wc[wv][d] = (uint32_t)__popcll(mt);
+            __syncthreads();
+            if (ok) {
+                uint32_t pos = s_start[d] + s_run[d] + below;
+                for (int q = 0; q < W; ++q)
+                    if (q < wv) pos += s_wc[q][d];
+                ko[r.x + pos] = key;
+            }
+            __syncthreads();
+            uint32_t add = 0;
+            for (int q = 0; q < W; ++q) {
+                add += s_wc[q][tid];
+                s_wc[q][tid] = 0u;
+            }
+            s_run[tid] += add;
+            __syncthreads();
+        }
+        // the next pass reads what this one wrote (same workgroup)
+        __threadfence_block();
+        __syncthreads();
+        in_a = !in_a;
+    }
+    const uint64_t thi = (uint64_t)blockIdx.x << 32;
+    const uint64_t* src = in_a ? pa : kout;
+    for (uint32_t i = tid; i < n; i += kDLongThreads) {
+        const uint64_t c = src[r.x + i];   // each thread reads and writes the same index
+        kout[r.x + i] = thi | (c >> 32);
+        vout[r.x + i] = (uint32_t)c;
+    }
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct DirectWs {
+    uint32_t* M;       // [nb][n_tiles]
+    uint32_t* ttot;    // [n_tiles]
+    uint64_t* bsum;    // [nb]
+    uint64_t* pairs;   // [capacity]: placed (depth << 32 | index)
+};
+
+void direct_shape(int64_t n, int* nb, int64_t* chunk) {
+    int64_t b = (n + kDMinChunk - 1) / kDMinChunk;
+    if (b > kDMaxBlocks) b = kDMaxBlocks;
+    if (b < 1) b = 1;
+    int64_t c = (n + b - 1) / b;
+    c = (c + kDPer - 1) / kDPer * kDPer;
+    if (c < 1) c = 1;
+    *nb = n > 0 ? (int)((n + c - 1) / c) : 0;
+    *chunk = c;
+}
+
+DirectWs carve_direct(void* ws, int64_t n, int64_t capacity, int64_t n_tiles) {
+    int nb;
+    int64_t chunk;
+    direct_shape(n, &nb, &chunk);
+    DirectWs w;
+    char* p = static_cast<char*>(ws);
+    w.M = reinterpret_cast<uint32_t*>(p);
+    p += align256((size_t)(nb > 0 ? nb : 1) * (size_t)n_tiles * 4);
+    w.ttot = reinterpret_cast<uint32_t*>(p);
+    p += align256((size_t)n_tiles * 4);
+    w.bsum = reinterpret_cast<uint64_t*>(p);
+    p += align256((size_t)(nb > 0 ? nb : 1) * 8);
+    w.pairs = reinterpret_cast<uint64_t*>(p);
+    (void)capacity;
+    return w;
+}
+
+}  // namespace
+
+bool bin_direct_supported(int64_t n_tiles) { return n_tiles > 0 && n_tiles <= kDirectMaxTiles; }
+
+size_t bin_direct_ws_bytes(int64_t n, int64_t capacity, int64_t n_tiles) {
+    int nb;
+    int64_t chunk;
+    direct_shape(n, &nb, &chunk);
+    return align256((size_t)(nb > 0 ? nb : 1) * (size_t)n_tiles * 4) + align256((size_t)n_tiles * 4) +
+           align256((size_t)(nb > 0 ? nb : 1) * 8) + align256((size_t)(capacity > 0 ? capacity : 0) * 8);
+}
+
+void launch_bin_direct_place(int64_t n, const ushort4* rect, const float* depth, int ntx, int64_t n_tiles,
+                             int64_t capacity, uint32_t* first, uint32_t* ranges, uint32_t* pair_count,
+                             int32_t* status, void* ws, hipStream_t st) {
+    int nb;
+    int64_t chunk;
+    direct_shape(n, &nb, &chunk);
+    const DirectWs w = carve_direct(ws, n, capacity, n_tiles);
+    const size_t lds = (size_t)n_tiles * 4;
+    const int nty = (int)((n_tiles + ntx - 1) / ntx);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_dcount, dim3((unsigned)nb), dim3(kDThreads), lds, st, rect, n, chunk, ntx, nty,
+                           (uint32_t)n_tiles, w.M, w.bsum);
+    const unsigned strips = (unsigned)((n_tiles + kWave - 1) / kWave);
+    hipLaunchKernelGGL(k_dscan, dim3(strips + 1), dim3(kDThreads), 0, st, w.M, nb, (uint32_t)n_tiles, w.ttot,
+                       w.bsum);
+    // at least one workgroup, which writes ranges, pair count and status
+    hipLaunchKernelGGL(k_dscatter, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kDThreads), lds, st, rect, depth, n,
+                       chunk, ntx, nty, (uint32_t)n_tiles, w.M, w.ttot, capacity, w.bsum, ranges, pair_count, status,
+                       first, w.pairs);
+}
+
+void launch_bin_direct_sort(int64_t n, int64_t n_tiles, int64_t capacity, uint64_t* keys, uint32_t* vals,
+                            const uint32_t* ranges, const int32_t* status, uint32_t* tile_order, void* ws,
+                            hipStream_t st) {
+    const DirectWs w = carve_direct(ws, n, capacity, n_tiles);
+    const uint2* rg = reinterpret_cast<const uint2*>(ranges);
+    if (capacity == 0) {   // nothing to sort (every range is empty); the order is still kept
+        if (tile_order)
+            hipLaunchKernelGGL(k_dsort, dim3(1), dim3(kDSortWaves * kWave), 0, st, w.pairs, keys, vals, rg,
+                               (uint32_t)n_tiles, status, tile_order);
+        return;
+    }
+    const unsigned blocks = (unsigned)((n_tiles + kDSortWaves - 1) / kDSortWaves) + (tile_order ? 1u : 0u);
+    hipLaunchKernelGGL(k_dsort, dim3(blocks), dim3(kDSortWaves * kWave), 0, st, w.pairs, keys, vals, rg,
+                       (uint32_t)n_tiles, status, tile_order);
+    hipLaunchKernelGGL(k_dsort_long, dim3((unsigned)n_tiles), dim3(kDLongThreads), 0, st, w.pairs, keys, vals, rg,
+                       status);
+}
+
+}  // namespace gs

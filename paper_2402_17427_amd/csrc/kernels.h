@@ -70,6 +70,27 @@ void launch_bin_sort(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_
                      int64_t capacity, int tile_bits, uint32_t* ranges, int64_t n_tiles, void* ws, hipStream_t st,
                      bool zeroed = false, uint32_t* tile_order = nullptr);
 
+// ---- direct binning of one view (bin_direct.hip)
+// For one view of at most kDirectMaxTiles tiles the pairs are placed into
+// their tile's run straight from the tile rectangles (per-block tile
+// histograms, their column scan, an LDS-cursor scatter), then each run is
+// sorted on (depth, index): the same keys, values, ranges, `first`, pair
+// count, status and tile order as launch_emit_pairs + launch_bin_sort.
+constexpr int64_t kDirectMaxTiles = 16384;
+bool bin_direct_supported(int64_t n_tiles);
+size_t bin_direct_ws_bytes(int64_t n, int64_t capacity, int64_t n_tiles);
+// Placement: `first`, ranges, pair_count[2], status and the placed pairs
+// in the workspace.
+void launch_bin_direct_place(int64_t n, const ushort4* rect, const float* depth, int ntx, int64_t n_tiles,
+                             int64_t capacity, uint32_t* first, uint32_t* ranges, uint32_t* pair_count,
+                             int32_t* status, void* ws, hipStream_t st);
+// Per-run sort of the placed pairs into (keys, vals), and the tile order
+// (optional, n_tiles + 1 words: [0] = n_tiles, [1..] every tile, the
+// longest lists first).
+void launch_bin_direct_sort(int64_t n, int64_t n_tiles, int64_t capacity, uint64_t* keys, uint32_t* vals,
+                            const uint32_t* ranges, const int32_t* status, uint32_t* tile_order, void* ws,
+                            hipStream_t st);
+
 // ---- blend (render_fwd.hip / render_bwd.hip)
 // What both blend passes read: records, sorted values, per-tile ranges of
 // all views' tiles (global tile ids), status, the view table and the tile

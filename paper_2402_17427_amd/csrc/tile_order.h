@@ -21,10 +21,11 @@ constexpr int kTileClasses = 33;   // 0..31: floor(log2(length)), 32: empty
 __device__ __forceinline__ int tile_length_class(uint32_t n) { return n ? 31 - __builtin_clz(n) : 32; }
 
 // Run by all NT threads of one workgroup; s_h: LDS of NT / 64 rows.
-template <int NT>
-__device__ __forceinline__ void tile_order_block(const uint2* __restrict__ ranges, uint32_t n_tiles,
-                                                 uint32_t* __restrict__ order, uint32_t* __restrict__ count,
-                                                 int include_empty, uint32_t (*s_h)[kTileClasses + 1]) {
+// len(t): the list length of tile t.
+template <int NT, class Len>
+__device__ __forceinline__ void tile_order_block_len(Len len, uint32_t n_tiles, uint32_t* __restrict__ order,
+                                                     uint32_t* __restrict__ count, int include_empty,
+                                                     uint32_t (*s_h)[kTileClasses + 1]) {
     constexpr int kWaves = NT / kWave;
     constexpr int kPer = 8;   // tiles per thread per block of NT x kPer, loaded together
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
@@ -39,7 +40,7 @@ __device__ __forceinline__ void tile_order_block(const uint2* __restrict__ range
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {
                 const uint32_t t = b0 + (uint32_t)(k * NT + tid);
-                cl[k] = t < n_tiles ? tile_length_class(ranges[t].y - ranges[t].x) : kTileClasses;   // kTileClasses: none
+                cl[k] = t < n_tiles ? tile_length_class(len(t)) : kTileClasses;   // kTileClasses: none
             }
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {
@@ -92,6 +93,15 @@ __device__ __forceinline__ void tile_order_block(const uint2* __restrict__ range
         }
         __syncthreads();
     }
+}
+
+// The same, with the lengths taken from per-tile [start, end) ranges.
+template <int NT>
+__device__ __forceinline__ void tile_order_block(const uint2* __restrict__ ranges, uint32_t n_tiles,
+                                                 uint32_t* __restrict__ order, uint32_t* __restrict__ count,
+                                                 int include_empty, uint32_t (*s_h)[kTileClasses + 1]) {
+    tile_order_block_len<NT>([ranges](uint32_t t) { return ranges[t].y - ranges[t].x; }, n_tiles, order, count,
+                             include_empty, s_h);
 }
 
 }  // namespace gs

@@ -158,6 +158,54 @@ def test_bins_match_oracle_bit_exact(name, tile):
     print(f"[case] longest tile run {runs.max()}", flush=True)
 
 
+def _concat(a, b):
+    return scenes.Gaussians(*(np.ascontiguousarray(np.concatenate([x, y], axis=-1)) for x, y in
+                              ((a.mean, b.mean), (a.scale, b.scale), (a.quat, b.quat), (a.opacity, b.opacity),
+                               (a.sh, b.sh))), a.sh_degree)
+
+
+def _tie_scene(name):
+    """Scenes whose tile runs hold Gaussians of exactly equal depth, which
+    the bins must keep in index order: config1's Gaussians all on the plane
+    z = 4.5 in front of its identity camera (every run one depth), and a
+    city with its first Gaussians appended again (every such Gaussian has a
+    twin of the same depth, later in index order)."""
+    if name == "config1_plane":
+        g, cam, _ = scenes.config1()
+        g = g.copy()
+        g.mean[2, :] = np.float32(4.5)
+        return g, cam
+    base, k = ("city_dense", 10_000) if name == "city_dense_twins" else ("city_ragged", 8_000)
+    g, cam = _scene(base)
+    return _concat(g, g.subset(np.arange(k))), cam
+
+
+@pytest.mark.parametrize("name,tile", [("config1_plane", (16, 16)), ("config1_plane", (8, 8)),
+                                       ("city_ragged_twins", (16, 16)), ("city_ragged_twins", (32, 8)),
+                                       ("city_dense_twins", (16, 16))])
+def test_bins_keep_index_order_among_equal_depths(name, tile):
+    _case(f"bins with equal depths {name} tile={tile}")
+    g, cam = _tie_scene(name)
+    dg = raster.DeviceGaussians.from_host(g)
+    f = raster.Frame(g.n, g.sh_degree, cam, tile=tile)
+    P = f.ensure_capacity(dg)
+    b = oracle.bin(g, cam, *tile)
+    assert not b["amb"].any(), "scene has Gaussians on a rounding boundary; pick another seed"
+    assert P == b["keys"].size
+    keys = b["keys"]
+    same = (keys[1:] == keys[:-1]).sum()
+    assert same > P // 20, f"only {same} equal keys"
+    np.testing.assert_array_equal(f.keys.cpu().numpy().view(np.uint64)[:P], keys)
+    np.testing.assert_array_equal(f.vals.cpu().numpy().view(np.uint32)[:P], b["vals"])
+    ranges = f.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    np.testing.assert_array_equal(ranges, b["ranges"])
+    np.testing.assert_array_equal(f.first.cpu().numpy().view(np.uint32)[: g.n],
+                                  np.concatenate([[0], np.cumsum(b["tiles_touched"][:-1], dtype=np.uint64)])
+                                  .astype(np.uint32))
+    runs = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+    print(f"[case] {same} equal keys, longest tile run {runs.max()}", flush=True)
+
+
 # --------------------------------------------------------------- forward --
 
 @pytest.mark.parametrize("name", ["config1", "city_ragged", "city_white", "city_dense", "city_capped"])
