@@ -215,7 +215,8 @@ __global__ __launch_bounds__(kDThreads) void k_dscatter(const ushort4* __restric
                                                         uint32_t* __restrict__ ranges,
                                                         uint32_t* __restrict__ pair_count,
                                                         int32_t* __restrict__ status,
-                                                        uint32_t* __restrict__ first, uint64_t* __restrict__ pairs) {
+                                                        uint32_t* __restrict__ first, uint64_t* __restrict__ pairs,
+                                                        bool vec) {
     extern __shared__ uint32_t s_cur[];
     const int tid = threadIdx.x;
     const int rounds = (int)((n_tiles + kDThreads - 1) / kDThreads);
@@ -266,26 +267,62 @@ __global__ __launch_bounds__(kDThreads) void k_dscatter(const ushort4* __restric
     for (int64_t base = g0; base < g1; base += (int64_t)kDThreads * kDPer) {
         // kDPer consecutive Gaussians per thread, so that one scan gives
         // every emission position of the round
+        // (chunk is a multiple of kDPer = 4, so i0 is, and with the three
+        // arrays 16-byte aligned (`vec`) a thread's four rectangles, depths
+        // and emission positions are 16-byte vectors, unless the block's
+        // range ends inside them)
         const int64_t i0 = base + (int64_t)tid * kDPer;
+        const bool whole = vec && i0 + kDPer <= g1;
         ushort4 r[kDPer];
+        float z[kDPer];
+        if (whole) {
+            const uint4 r01 = *reinterpret_cast<const uint4*>(rect + i0);
+            const uint4 r23 = *reinterpret_cast<const uint4*>(rect + i0 + 2);
+            const uint32_t w[8] = {r01.x, r01.y, r01.z, r01.w, r23.x, r23.y, r23.z, r23.w};
+#pragma unroll
+            for (int k = 0; k < kDPer; ++k)
+                r[k] = make_ushort4((unsigned short)(w[2 * k] & 0xFFFFu), (unsigned short)(w[2 * k] >> 16),
+                                    (unsigned short)(w[2 * k + 1] & 0xFFFFu), (unsigned short)(w[2 * k + 1] >> 16));
+            const float4 z4 = *reinterpret_cast<const float4*>(depth + i0);
+            z[0] = z4.x; z[1] = z4.y; z[2] = z4.z; z[3] = z4.w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < kDPer; ++k) {
+                r[k] = i0 + k < g1 ? rect[i0 + k] : make_ushort4(0, 0, 0, 0);
+                z[k] = i0 + k < g1 ? depth[i0 + k] : 0.0f;
+            }
+        }
         uint32_t a[kDPer], s = 0;
 #pragma unroll
         for (int k = 0; k < kDPer; ++k) {
-            r[k] = grid_rect(i0 + k < g1 ? rect[i0 + k] : make_ushort4(0, 0, 0, 0), ntx, nty);
+            r[k] = grid_rect(r[k], ntx, nty);
             a[k] = rect_area(r[k]);
             s += a[k];
         }
         uint64_t tot;
         uint64_t off = carry + block_scan_ex<kDThreads>(s, &tot);
         carry += tot;
+        if (first) {
+            uint32_t f[kDPer];
+#pragma unroll
+            for (int k = 0; k < kDPer; ++k) {
+                f[k] = (uint32_t)off;
+                off += a[k];
+            }
+            if (whole) {
+                *reinterpret_cast<uint4*>(first + i0) = make_uint4(f[0], f[1], f[2], f[3]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < kDPer; ++k)
+                    if (i0 + k < g1) first[i0 + k] = f[k];
+            }
+        }
 #pragma unroll
         for (int k = 0; k < kDPer; ++k) {
             const int64_t i = i0 + k;
             if (i < g1) {
-                if (first) first[i] = (uint32_t)off;
-                off += a[k];
                 if (place && a[k]) {
-                    const uint64_t hi = (uint64_t)__float_as_uint(depth[i]) << 32;
+                    const uint64_t hi = (uint64_t)__float_as_uint(z[k]) << 32;
                     for (int ty = r[k].y; ty < r[k].w; ++ty)
                         for (int tx = r[k].x; tx < r[k].z; ++tx) {
                             const uint32_t pos = atomicAdd(&s_cur[ty * ntx + tx], 1u);
@@ -657,10 +694,12 @@ void launch_bin_direct_place(int64_t n, const ushort4* rect, const float* depth,
     const unsigned strips = (unsigned)((n_tiles + kWave - 1) / kWave);
     hipLaunchKernelGGL(k_dscan, dim3(strips + 1), dim3(kDThreads), 0, st, w.M, nb, (uint32_t)n_tiles, w.ttot,
                        w.bsum);
+    const bool vec = ((reinterpret_cast<uintptr_t>(rect) | reinterpret_cast<uintptr_t>(depth) |
+                       reinterpret_cast<uintptr_t>(first)) & 15u) == 0;
     // at least one workgroup, which writes ranges, pair count and status
     hipLaunchKernelGGL(k_dscatter, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kDThreads), lds, st, rect, depth, n,
                        chunk, ntx, nty, (uint32_t)n_tiles, w.M, w.ttot, capacity, w.bsum, ranges, pair_count, status,
-                       first, w.pairs);
+                       first, w.pairs, vec);
 }
 
 void launch_bin_direct_sort(int64_t n, int64_t n_tiles, int64_t capacity, uint64_t* keys, uint32_t* vals,
