@@ -191,12 +191,18 @@ gs_status gs_project(const gs_gaussians *g, const gs_camera *cam, const gs_opts 
  * a tile count (host query, no device work). */
 gs_status gs_bin_sort_workspace(int64_t n, int64_t pair_capacity, int64_t n_tiles, size_t *bytes);
 
-/* Section 3 (2D Gaussians binned to tiles and depth-sorted): exclusive scan of
- * tiles_touched, emission of one (tile|depth, index) pair per covered tile
- * (tiles in row-major order within each Gaussian), stable LSD radix sort
- * (onesweep, 8-bit digits) and per-tile ranges.  `ws` is device scratch of
- * gs_bin_sort_workspace() bytes.  No host synchronisation: the pair count
- * stays on the device.  pair_capacity <= 2^30 - 1. */
+/* Section 3 (2D Gaussians binned to tiles and depth-sorted): one
+ * (tile << 32 | depth bits, index) pair per covered tile, ordered by tile,
+ * then depth, then Gaussian index (the order of a stable sort of the keys
+ * emitted Gaussian by Gaussian, tiles row-major within each), with per-tile
+ * ranges and each Gaussian's first emission position (bins.first).  Views
+ * of at most 16384 tiles place every pair straight into its tile's run (per-
+ * block tile histograms, a column scan, a scatter) and sort each run by
+ * depth, equal depths by index; larger ones emit the pairs and radix-sort
+ * them (onesweep, 8-bit digits) on the tile bits, then each run by depth.
+ * `ws` is device scratch of gs_bin_sort_workspace() bytes.  No host
+ * synchronisation: the pair count stays on the device.
+ * pair_capacity <= 2^30 - 1. */
 gs_status gs_bin_sort(const gs_proj *proj, int64_t n, const gs_camera *cam, const gs_opts *opts,
                       gs_bins *out, void *ws, size_t ws_bytes, gs_stream stream);
 
