@@ -27,10 +27,11 @@
 //               transposition, or for long groups a second sort on (depth,
 //               index), index bytes first), so the order never depends on
 //               the scatter's; the sorted keys (tile << 32 | depth bits) and
-//               values are written out; an extra workgroup writes the blend
-//               order (longest list first)
-//   k_dsort_long  the longer runs (listed by k_dsort), one workgroup each:
-//               the (depth, index) order by stable passes over global memory
+//               values are written out.  In the same launch an extra first
+//               workgroup writes the blend order (longest list first), and
+//               up to 64 last workgroups sort the runs of more than 1024
+//               pairs, one at a time each: the (depth, index) order by
+//               stable passes over global memory
 // The output -- keys, values, ranges, `first`, pair count, status and tile
 // order -- is exactly that of the emission + stable sort of the whole key
 // (tile, then depth; equal keys in emission, i.e. index, order).
@@ -50,7 +51,7 @@ constexpr int kDRadix = 256;
 constexpr int kDSortWaves = 4;
 constexpr int kDSortCap = 1024;     // longest run sorted in LDS
 constexpr int kDLongThreads = 256;
-constexpr int kDLongGrid = 64;      // workgroups taking the long runs in turn
+constexpr int kDLongGrid = 64;      // workgroups taking the long runs
 constexpr int kDFixPhases = 16;     // odd-even phases for equal depths before a full re-sort
 
 // Exclusive scan over the NT threads of a workgroup; *total = the sum.
@@ -217,7 +218,7 @@ __global__ __launch_bounds__(kDThreads) void k_dscatter(const ushort4* __restric
                                                         uint32_t* __restrict__ pair_count,
                                                         int32_t* __restrict__ status,
                                                         uint32_t* __restrict__ first, uint64_t* __restrict__ pairs,
-                                                        uint32_t* __restrict__ longs, bool vec) {
+                                                        bool vec) {
     extern __shared__ uint32_t s_cur[];
     const int tid = threadIdx.x;
     const int rounds = (int)((n_tiles + kDThreads - 1) / kDThreads);
@@ -251,7 +252,6 @@ __global__ __launch_bounds__(kDThreads) void k_dscatter(const ushort4* __restric
             }
         }
         if (tid == 0) {
-            longs[0] = 0u;   // the per-run sort lists its long runs here
             pair_count[0] = over ? 0u : (uint32_t)total;   // pairs the later stages process
             pair_count[1] = total > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)total;   // pairs needed
             *status = over ? -4 : 0;
@@ -414,18 +414,138 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
     return v;
 }
 
+// A run longer than kDSortCap, sorted by all kDLongThreads threads of a
+// workgroup on (depth, index) with stable 8-bit LSD passes over the bytes
+// that vary in it (index bytes first), 256 items at a time in order (ballot
+// match ranks within a wave, per-wave digit counts order the waves),
+// ping-ponging between the placed pairs and the key output; then the keys
+// and values are written.  `lds`: LongLds words of shared memory.
+struct LongLds {
+    uint32_t start[kDRadix];   // digit start in the run
+    uint32_t run[kDRadix];     // items of each digit placed so far
+    uint32_t wc[kDLongThreads / kWave][kDRadix];
+    uint32_t w[kDRadix / kWave];
+    uint32_t vary[2];
+    uint32_t list[kDLongThreads];   // long runs found in a round
+    uint32_t nlist;
+};
+
+__device__ __forceinline__ void sort_long_run(uint32_t tile, uint2 r, uint64_t* __restrict__ pa,
+                                              uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                              LongLds& L) {
+    constexpr int W = kDLongThreads / kWave;
+    uint32_t* s_start = L.start;
+    uint32_t* s_run = L.run;
+    uint32_t (*s_wc)[kDRadix] = L.wc;
+    uint32_t* s_w = L.w;
+    uint32_t* s_vary = L.vary;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t n = r.y - r.x;
+    __syncthreads();   // the previous run's last reads of the shared counts are done
+    if (tid < 2) s_vary[tid] = 0u;
+    __syncthreads();
+    {
+        const uint64_t x0 = pa[r.x];
+        uint32_t vz = 0, vg = 0;
+        for (uint32_t i = tid; i < n; i += kDLongThreads) {
+            const uint64_t x = pa[r.x + i];
+            vz |= (uint32_t)(x >> 32) ^ (uint32_t)(x0 >> 32);
+            vg |= (uint32_t)x ^ (uint32_t)x0;
+        }
+        vz = wave_or(vz);
+        vg = wave_or(vg);
+        if (lane == 0) {
+            atomicOr(&s_vary[0], vg);
+            atomicOr(&s_vary[1], vz);
+        }
+    }
+    __syncthreads();
+    const uint64_t vary = ((uint64_t)s_vary[1] << 32) | s_vary[0];
+    bool in_a = true;
+    for (int pass = 0; pass < 8; ++pass) {
+        const int shift = 8 * pass;
+        if (((vary >> shift) & 0xFFu) == 0u) continue;
+        const uint64_t* ki = in_a ? pa : kout;
+        uint64_t* ko = in_a ? kout : pa;
+        // digit counts of the run and their exclusive scan
+        s_start[tid] = 0u;
+        s_run[tid] = 0u;
+        for (int q = 0; q < W; ++q) s_wc[q][tid] = 0u;
+        __syncthreads();
+        for (uint32_t i = tid; i < n; i += kDLongThreads)
+            atomicAdd(&s_start[(uint32_t)(ki[r.x + i] >> shift) & 0xFFu], 1u);
+        __syncthreads();
+        {
+            const uint32_t v = s_start[tid];
+            uint32_t x = v;
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t y = __shfl_up(x, d, kWave);
+                if (lane >= d) x += y;
+            }
+            if (lane == kWave - 1) s_w[wv] = x;
+            __syncthreads();
+            uint32_t base = 0;
+            for (int q = 0; q < kDRadix / kWave; ++q)
+                if (q < wv) base += s_w[q];
+            s_start[tid] = base + x - v;
+        }
+        __syncthreads();
+        for (uint32_t c0 = 0; c0 < n; c0 += kDLongThreads) {
+            const uint32_t i = c0 + (uint32_t)tid;
+            const bool ok = i < n;
+            const uint64_t key = ok ? ki[r.x + i] : 0ull;
+            const uint32_t d = (uint32_t)(key >> shift) & 0xFFu;
+            uint64_t mt = __ballot(ok);
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t vote = __ballot(bit);
+                mt &= bit ? vote : ~vote;
+            }
+            const uint32_t below = (uint32_t)__popcll(mt & lt_mask);
+            if (ok && below == 0u) s_wc[wv][d] = (uint32_t)__popcll(mt);
+            __syncthreads();
+            if (ok) {
+                uint32_t pos = s_start[d] + s_run[d] + below;
+                for (int q = 0; q < W; ++q)
+                    if (q < wv) pos += s_wc[q][d];
+                ko[r.x + pos] = key;
+            }
+            __syncthreads();
+            uint32_t add = 0;
+            for (int q = 0; q < W; ++q) {
+                add += s_wc[q][tid];
+                s_wc[q][tid] = 0u;
+            }
+            s_run[tid] += add;
+            __syncthreads();
+        }
+        // the next pass reads what this one wrote (same workgroup)
+        __threadfence_block();
+        __syncthreads();
+        in_a = !in_a;
+    }
+    const uint64_t thi = (uint64_t)tile << 32;
+    const uint64_t* src = in_a ? pa : kout;
+    for (uint32_t i = tid; i < n; i += kDLongThreads) {
+        const uint64_t c = src[r.x + i];   // each thread reads and writes the same index
+        kout[r.x + i] = thi | (c >> 32);
+        vout[r.x + i] = (uint32_t)c;
+    }
+}
+
 // Runs of 1 .. kDSortCap pairs, one wave each, four per workgroup.
 // With `order` set, an extra first workgroup writes the blend order
 // meanwhile (order[0] = the tile count, order[1..] = every tile, longest
 // list first).
-__global__ __launch_bounds__(kDSortWaves * kWave) void k_dsort(const uint64_t* __restrict__ pin,
+__global__ __launch_bounds__(kDSortWaves * kWave) void k_dsort(uint64_t* __restrict__ pin,
                                                                uint64_t* __restrict__ kout,
                                                                uint32_t* __restrict__ vout,
                                                                const uint2* __restrict__ ranges, uint32_t n_tiles,
                                                                const int32_t* __restrict__ status,
-                                                               uint32_t* __restrict__ order,
-                                                               uint32_t* __restrict__ longs) {
+                                                               uint32_t* __restrict__ order) {
     constexpr int IPL = kDSortCap / kWave;
+    static_assert(kDLongThreads == kDSortWaves * kWave, "a long run takes a whole workgroup");
     __shared__ uint64_t s_all[kDSortWaves][kDSortCap];
     __shared__ uint32_t s_cnt_all[kDSortWaves][kDRadix];
     const int first = order ? 1 : 0;
@@ -435,16 +555,41 @@ __global__ __launch_bounds__(kDSortWaves * kWave) void k_dsort(const uint64_t* _
         return;
     }
     if (*status != 0) return;
+    const uint32_t nshort = (n_tiles + kDSortWaves - 1) / kDSortWaves;
+    const uint32_t blk = (uint32_t)blockIdx.x - (uint32_t)first;
+    if (blk >= nshort) {
+        // long-run workgroup j of nl: the runs above kDSortCap pairs among
+        // tiles j, j + nl, j + 2 nl, ..., one after another, with the
+        // workgroup's LDS as their counts
+        static_assert(sizeof(LongLds) <= sizeof(s_all), "long-run counts fit the run buffers");
+        LongLds& L = *reinterpret_cast<LongLds*>(&s_all[0][0]);
+        const uint32_t j = blk - nshort, nl = (uint32_t)gridDim.x - (uint32_t)first - nshort;
+        for (uint32_t t0 = j; t0 < n_tiles; t0 += nl * kDLongThreads) {
+            const uint32_t t = t0 + nl * threadIdx.x;
+            bool lg = false;
+            if (t < n_tiles) {
+                const uint2 rr = ranges[t];
+                lg = rr.y - rr.x > (uint32_t)kDSortCap;
+            }
+            __syncthreads();   // the previous round's list is no longer read
+            if (threadIdx.x == 0) L.nlist = 0u;
+            __syncthreads();
+            if (lg) L.list[atomicAdd(&L.nlist, 1u)] = t;   // any order: each run is sorted on its own
+            __syncthreads();
+            const uint32_t cnt = L.nlist;
+            for (uint32_t q = 0; q < cnt; ++q) {
+                const uint32_t tile = L.list[q];
+                sort_long_run(tile, ranges[tile], pin, kout, vout, L);
+            }
+        }
+        return;
+    }
     const int wv = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    const uint32_t tile = ((uint32_t)blockIdx.x - (uint32_t)first) * kDSortWaves + (uint32_t)wv;
+    const uint32_t tile = blk * kDSortWaves + (uint32_t)wv;
     if (tile >= n_tiles) return;
     const uint2 r = ranges[tile];
     const uint32_t n = r.y - r.x;
-    if (n > (uint32_t)kDSortCap) {   // listed for k_dsort_long
-        if (lane == 0) longs[1 + atomicAdd(&longs[0], 1u)] = tile;
-        return;
-    }
-    if (n == 0u) return;
+    if (n == 0u || n > (uint32_t)kDSortCap) return;   // longer runs: the long-run workgroups
     const uint64_t thi = (uint64_t)tile << 32;
     if (n == 1u) {
         if (lane == 0) {
@@ -525,124 +670,6 @@ __global__ __launch_bounds__(kDSortWaves * kWave) void k_dsort(const uint64_t* _
     }
 }
 
-// Runs longer than kDSortCap (the tiles k_dsort listed; a small grid takes
-// them in turn): one workgroup sorts a run on (depth, index) with stable
-// 8-bit LSD passes over the bytes that vary in it (index bytes first), 256
-// items at a time in order (ballot match ranks within a wave, per-wave digit
-// counts order the waves), ping-ponging between the placed pairs and the
-// key output; then writes keys and values.
-__global__ __launch_bounds__(kDLongThreads) void k_dsort_long(uint64_t* __restrict__ pa, uint64_t* __restrict__ kout,
-                                                              uint32_t* __restrict__ vout,
-                                                              const uint2* __restrict__ ranges,
-                                                              const int32_t* __restrict__ status,
-                                                              const uint32_t* __restrict__ longs) {
-    constexpr int W = kDLongThreads / kWave;
-    __shared__ uint32_t s_start[kDRadix];   // digit start in the run
-    __shared__ uint32_t s_run[kDRadix];     // items of each digit placed so far
-    __shared__ uint32_t s_wc[W][kDRadix];
-    __shared__ uint32_t s_w[kDRadix / kWave];
-    __shared__ uint32_t s_vary[2];
-    if (*status != 0) return;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint32_t nlong = longs[0];
-    for (uint32_t job = blockIdx.x; job < nlong; job += gridDim.x) {
-        const uint32_t tile = longs[1 + job];
-        const uint2 r = ranges[tile];
-        const uint32_t n = r.y - r.x;
-        __syncthreads();   // the previous run's last reads of the shared counts are done
-        if (tid < 2) s_vary[tid] = 0u;
-        __syncthreads();
-        {
-            const uint64_t x0 = pa[r.x];
-            uint32_t vz = 0, vg = 0;
-            for (uint32_t i = tid; i < n; i += kDLongThreads) {
-                const uint64_t x = pa[r.x + i];
-                vz |= (uint32_t)(x >> 32) ^ (uint32_t)(x0 >> 32);
-                vg |= (uint32_t)x ^ (uint32_t)x0;
-            }
-            vz = wave_or(vz);
-            vg = wave_or(vg);
-            if (lane == 0) {
-                atomicOr(&s_vary[0], vg);
-                atomicOr(&s_vary[1], vz);
-            }
-        }
-        __syncthreads();
-        const uint64_t vary = ((uint64_t)s_vary[1] << 32) | s_vary[0];
-        bool in_a = true;
-        for (int pass = 0; pass < 8; ++pass) {
-            const int shift = 8 * pass;
-            if (((vary >> shift) & 0xFFu) == 0u) continue;
-            const uint64_t* ki = in_a ? pa : kout;
-            uint64_t* ko = in_a ? kout : pa;
-            // digit counts of the run and their exclusive scan
-            s_start[tid] = 0u;
-            s_run[tid] = 0u;
-            for (int q = 0; q < W; ++q) s_wc[q][tid] = 0u;
-            __syncthreads();
-            for (uint32_t i = tid; i < n; i += kDLongThreads)
-                atomicAdd(&s_start[(uint32_t)(ki[r.x + i] >> shift) & 0xFFu], 1u);
-            __syncthreads();
-            {
-                const uint32_t v = s_start[tid];
-                uint32_t x = v;
-                for (int d = 1; d < kWave; d <<= 1) {
-                    const uint32_t y = __shfl_up(x, d, kWave);
-                    if (lane >= d) x += y;
-                }
-                if (lane == kWave - 1) s_w[wv] = x;
-                __syncthreads();
-                uint32_t base = 0;
-                for (int q = 0; q < kDRadix / kWave; ++q)
-                    if (q < wv) base += s_w[q];
-                s_start[tid] = base + x - v;
-            }
-            __syncthreads();
-            for (uint32_t c0 = 0; c0 < n; c0 += kDLongThreads) {
-                const uint32_t i = c0 + (uint32_t)tid;
-                const bool ok = i < n;
-                const uint64_t key = ok ? ki[r.x + i] : 0ull;
-                const uint32_t d = (uint32_t)(key >> shift) & 0xFFu;
-                uint64_t mt = __ballot(ok);
-                for (int b = 0; b < 8; ++b) {
-                    const bool bit = (d >> b) & 1u;
-                    const uint64_t vote = __ballot(bit);
-                    mt &= bit ? vote : ~vote;
-                }
-                const uint32_t below = (uint32_t)__popcll(mt & lt_mask);
-                if (ok && below == 0u) s_wc[wv][d] = (uint32_t)__popcll(mt);
-                __syncthreads();
-                if (ok) {
-                    uint32_t pos = s_start[d] + s_run[d] + below;
-                    for (int q = 0; q < W; ++q)
-                        if (q < wv) pos += s_wc[q][d];
-                    ko[r.x + pos] = key;
-                }
-                __syncthreads();
-                uint32_t add = 0;
-                for (int q = 0; q < W; ++q) {
-                    add += s_wc[q][tid];
-                    s_wc[q][tid] = 0u;
-                }
-                s_run[tid] += add;
-                __syncthreads();
-            }
-            // the next pass reads what this one wrote (same workgroup)
-            __threadfence_block();
-            __syncthreads();
-            in_a = !in_a;
-        }
-        const uint64_t thi = (uint64_t)tile << 32;
-        const uint64_t* src = in_a ? pa : kout;
-        for (uint32_t i = tid; i < n; i += kDLongThreads) {
-            const uint64_t c = src[r.x + i];   // each thread reads and writes the same index
-            kout[r.x + i] = thi | (c >> 32);
-            vout[r.x + i] = (uint32_t)c;
-        }
-    }
-}
-
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct DirectWs {
@@ -650,7 +677,6 @@ struct DirectWs {
     uint32_t* ttot;    // [n_tiles]
     uint64_t* bsum;    // [nb]
     uint64_t* pairs;   // [capacity]: placed (depth << 32 | index)
-    uint32_t* longs;   // [1 + n_tiles]: count, then the tiles whose runs exceed kDSortCap
 };
 
 void direct_shape(int64_t n, int* nb, int64_t* chunk) {
@@ -677,8 +703,7 @@ DirectWs carve_direct(void* ws, int64_t n, int64_t capacity, int64_t n_tiles) {
     w.bsum = reinterpret_cast<uint64_t*>(p);
     p += align256((size_t)(nb > 0 ? nb : 1) * 8);
     w.pairs = reinterpret_cast<uint64_t*>(p);
-    p += align256((size_t)(capacity > 0 ? capacity : 0) * 8);
-    w.longs = reinterpret_cast<uint32_t*>(p);
+    (void)capacity;
     return w;
 }
 
@@ -691,8 +716,7 @@ size_t bin_direct_ws_bytes(int64_t n, int64_t capacity, int64_t n_tiles) {
     int64_t chunk;
     direct_shape(n, &nb, &chunk);
     return align256((size_t)(nb > 0 ? nb : 1) * (size_t)n_tiles * 4) + align256((size_t)n_tiles * 4) +
-           align256((size_t)(nb > 0 ? nb : 1) * 8) + align256((size_t)(capacity > 0 ? capacity : 0) * 8) +
-           align256((size_t)(n_tiles + 1) * 4);
+           align256((size_t)(nb > 0 ? nb : 1) * 8) + align256((size_t)(capacity > 0 ? capacity : 0) * 8);
 }
 
 void launch_bin_direct_place(int64_t n, const ushort4* rect, const float* depth, int ntx, int64_t n_tiles,
@@ -715,7 +739,7 @@ void launch_bin_direct_place(int64_t n, const ushort4* rect, const float* depth,
     // at least one workgroup, which writes ranges, pair count and status
     hipLaunchKernelGGL(k_dscatter, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kDThreads), lds, st, rect, depth, n,
                        chunk, ntx, nty, (uint32_t)n_tiles, w.M, w.ttot, capacity, w.bsum, ranges, pair_count, status,
-                       first, w.pairs, w.longs, vec);
+                       first, w.pairs, vec);
 }
 
 void launch_bin_direct_sort(int64_t n, int64_t n_tiles, int64_t capacity, uint64_t* keys, uint32_t* vals,
@@ -726,18 +750,16 @@ void launch_bin_direct_sort(int64_t n, int64_t n_tiles, int64_t capacity, uint64
     if (capacity == 0) {   // nothing to sort (every range is empty); the order is still kept
         if (tile_order)
             hipLaunchKernelGGL(k_dsort, dim3(1), dim3(kDSortWaves * kWave), 0, st, w.pairs, keys, vals, rg,
-                               (uint32_t)n_tiles, status, tile_order, w.longs);
+                               (uint32_t)n_tiles, status, tile_order);
         return;
     }
     const unsigned blocks = (unsigned)((n_tiles + kDSortWaves - 1) / kDSortWaves) + (tile_order ? 1u : 0u);
-    hipLaunchKernelGGL(k_dsort, dim3(blocks), dim3(kDSortWaves * kWave), 0, st, w.pairs, keys, vals, rg,
-                       (uint32_t)n_tiles, status, tile_order, w.longs);
-    // at most one run in kDSortCap + 1 pairs of capacity is long
+    // long-run workgroups after the others: at most one run in kDSortCap + 1
+    // pairs of capacity is long
     int64_t lg = capacity / (kDSortCap + 1);
     if (lg > kDLongGrid) lg = kDLongGrid;
-    if (lg > 0)
-        hipLaunchKernelGGL(k_dsort_long, dim3((unsigned)lg), dim3(kDLongThreads), 0, st, w.pairs, keys, vals, rg,
-                           status, w.longs);
+    hipLaunchKernelGGL(k_dsort, dim3(blocks + (unsigned)lg), dim3(kDSortWaves * kWave), 0, st, w.pairs, keys, vals,
+                       rg, (uint32_t)n_tiles, status, tile_order);
 }
 
 }  // namespace gs
