@@ -170,38 +170,38 @@ __device__ __forceinline__ bool geometry(const Cam& cam, const double mu[3], con
     return true;
 }
 
+// One slot of the forward projection for its job J and the job's camera.
 template <int K>
-__global__ __launch_bounds__(kProjThreads) void k_project(JobTab jobs, ViewTab views, int tw, int th, int64_t nslots,
-                                                          Rec* __restrict__ rec, float* __restrict__ depth,
-                                                          ushort4* __restrict__ rect, uint32_t* __restrict__ tt) {
-    const int64_t slot = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
-    if (slot >= nslots) return;
-    const Job J = job_at(jobs, find_job(jobs, (int64_t)blockIdx.x * kProjThreads));
+__device__ __forceinline__ void project_slot(const Job& J, const Cam& cam, int64_t slot, int tw, int th,
+                                             Rec* __restrict__ rec, float* __restrict__ depth,
+                                             ushort4* __restrict__ rect, uint32_t* __restrict__ tt) {
     const int64_t k = slot - J.out0;
     if (k >= J.count) {   // alignment padding between jobs
         tt[slot] = 0u;
         rect[slot] = make_ushort4(0, 0, 0, 0);
         return;
     }
-    const Cam cam = view_at(views, J.view).cam;
     const Gauss& G = J.g;
     const int64_t i = J.src0 + k;
     const int64_t ld = G.ld;
     double mu[3], s[3], q[4];
+    // the finiteness tests are combined without short-circuit evaluation:
+    // with && the compiler moves each later plane's load behind the test
+    // of the earlier ones, one memory round trip per test
     bool fin = true;
     for (int r = 0; r < 3; ++r) {
         const float m = G.mean[r * ld + i], sc = G.scale[r * ld + i];
-        fin = fin && isfinite(m) && isfinite(sc);
+        fin = fin & isfinite(m) & isfinite(sc);
         mu[r] = m;
         s[r] = sc;
     }
     for (int r = 0; r < 4; ++r) {
         const float v = G.quat[r * ld + i];
-        fin = fin && isfinite(v);
+        fin = fin & isfinite(v);
         q[r] = v;
     }
     const float o = G.opacity[i];
-    fin = fin && isfinite(o);
+    fin = fin & isfinite(o);
 
     Rec out;
     out.u = 0.0; out.v = 0.0;
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project(JobTab jobs, ViewTab v
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
                     const float cf = G.sh[(int64_t)(ch * K + j) * ld + i];
-                    fin_sh = fin_sh && isfinite(cf);
+                    fin_sh = fin_sh & isfinite(cf);
                     acc += cf * Y[j];
                 }
                 col[ch] = fmaxf(acc + 0.5f, 0.0f);
@@ -281,19 +281,32 @@ __global__ __launch_bounds__(kProjThreads) void k_project(JobTab jobs, ViewTab v
     tt[slot] = count;
 }
 
-// Backward of the projection for one Gaussian.  g2d planes: du, dv, dA, dB,
-// dC, d opacity, dr, dg, db (accumulated by the blend backward).
+// With one job and one view (the plain calls) the job and camera are taken
+// straight from the kernel arguments (scalar loads); with tables, the
+// workgroup's job and view are looked up first.
 template <int K>
-__global__ __launch_bounds__(kProjThreads) void k_project_bwd(JobTab jobs, ViewTab views, int64_t nslots,
-                                                              const uint32_t* __restrict__ tt,
-                                                              const float* __restrict__ g2d,
-                                                              const int32_t* __restrict__ status) {
+__global__ __launch_bounds__(kProjThreads) void k_project(JobTab jobs, ViewTab views, int tw, int th, int64_t nslots,
+                                                          Rec* __restrict__ rec, float* __restrict__ depth,
+                                                          ushort4* __restrict__ rect, uint32_t* __restrict__ tt) {
     const int64_t slot = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
     if (slot >= nslots) return;
-    const Job J = job_at(jobs, find_job(jobs, (int64_t)blockIdx.x * kProjThreads));
+    if (!jobs.dev && !views.dev) {
+        project_slot<K>(jobs.one, views.one.cam, slot, tw, th, rec, depth, rect, tt);
+    } else {
+        const Job J = job_at(jobs, find_job(jobs, (int64_t)blockIdx.x * kProjThreads));
+        project_slot<K>(J, view_at(views, J.view).cam, slot, tw, th, rec, depth, rect, tt);
+    }
+}
+
+// Backward of the projection for one Gaussian.  g2d planes: du, dv, dA, dB,
+// dC, d opacity, dr, dg, db (accumulated by the blend backward).
+// One slot of the projection backward for its job J and the job's camera.
+template <int K>
+__device__ __forceinline__ void project_bwd_slot(const Job& J, const Cam& cam, int64_t slot, int64_t nslots,
+                                                 const uint32_t* __restrict__ tt, const float* __restrict__ g2d,
+                                                 const int32_t* __restrict__ status) {
     const int64_t k = slot - J.out0;
     if (k >= J.count) return;   // alignment padding between jobs
-    const Cam cam = view_at(views, J.view).cam;
     const Gauss& G = J.g;
     const int64_t i = J.src0 + k, ld = G.ld, gld = J.gld, n = nslots;
     float* __restrict__ gmean = J.gmean;
@@ -430,6 +443,21 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(JobTab jobs, ViewT
     gquat[1 * gld + i] = live ? (float)((gx - x * dot) * inv) : 0.f;
     gquat[2 * gld + i] = live ? (float)((gy - y * dot) * inv) : 0.f;
     gquat[3 * gld + i] = live ? (float)((gz - z * dot) * inv) : 0.f;
+}
+
+template <int K>
+__global__ __launch_bounds__(kProjThreads) void k_project_bwd(JobTab jobs, ViewTab views, int64_t nslots,
+                                                              const uint32_t* __restrict__ tt,
+                                                              const float* __restrict__ g2d,
+                                                              const int32_t* __restrict__ status) {
+    const int64_t slot = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
+    if (slot >= nslots) return;
+    if (!jobs.dev && !views.dev) {   // one job and one view: from the kernel arguments
+        project_bwd_slot<K>(jobs.one, views.one.cam, slot, nslots, tt, g2d, status);
+    } else {
+        const Job J = job_at(jobs, find_job(jobs, (int64_t)blockIdx.x * kProjThreads));
+        project_bwd_slot<K>(J, view_at(views, J.view).cam, slot, nslots, tt, g2d, status);
+    }
 }
 
 }  // namespace
