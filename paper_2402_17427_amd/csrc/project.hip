@@ -238,6 +238,9 @@ __device__ __forceinline__ void project_slot(const Job& J, const Cam& cam, int64
             // non-finite input)
             float col[3];
             bool fin_sh = true;
+            // one channel's coefficients in flight at a time (all 48 at once
+            // hold 48 more registers and cost a wave per SIMD)
+#pragma unroll 1
             for (int ch = 0; ch < 3; ++ch) {
                 float acc = 0.f;
 #pragma unroll
