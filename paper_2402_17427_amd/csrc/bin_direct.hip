@@ -29,9 +29,10 @@
 //               the scatter's; the sorted keys (tile << 32 | depth bits) and
 //               values are written out.  In the same launch an extra first
 //               workgroup writes the blend order (longest list first), and
-//               up to 64 last workgroups sort the runs of more than 1024
-//               pairs, one at a time each: the (depth, index) order by
-//               stable passes over global memory
+//               the last workgroups (one per 1025 pairs of capacity, at most
+//               one per tile) sort the runs of more than 1024 pairs: stable
+//               passes over global memory on depth, the same equal-depth
+//               fix, or the full (depth, index) sort
 // The output -- keys, values, ranges, `first`, pair count, status and tile
 // order -- is exactly that of the emission + stable sort of the whole key
 // (tile, then depth; equal keys in emission, i.e. index, order).
@@ -51,7 +52,6 @@ constexpr int kDRadix = 256;
 constexpr int kDSortWaves = 4;
 constexpr int kDSortCap = 1024;     // longest run sorted in LDS
 constexpr int kDLongThreads = 256;
-constexpr int kDLongGrid = 64;      // workgroups taking the long runs
 constexpr int kDFixPhases = 16;     // odd-even phases for equal depths before a full re-sort
 
 // Exclusive scan over the NT threads of a workgroup; *total = the sum.
@@ -415,11 +415,12 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
 }
 
 // A run longer than kDSortCap, sorted by all kDLongThreads threads of a
-// workgroup on (depth, index) with stable 8-bit LSD passes over the bytes
-// that vary in it (index bytes first), 256 items at a time in order (ballot
-// match ranks within a wave, per-wave digit counts order the waves),
-// ping-ponging between the placed pairs and the key output; then the keys
-// and values are written.  `lds`: LongLds words of shared memory.
+// workgroup on (depth, index): stable 8-bit LSD passes over the depth bytes
+// that vary in it, 256 items at a time in order (ballot match ranks within
+// a wave, per-wave digit counts order the waves), ping-ponging between the
+// placed pairs and the key output; then equal depths put in index order as
+// in the short runs (or, for long groups, passes over the index bytes and
+// then the depth bytes again); then the keys and values are written.
 struct LongLds {
     uint32_t start[kDRadix];   // digit start in the run
     uint32_t run[kDRadix];     // items of each digit placed so far
@@ -462,10 +463,15 @@ __device__ __forceinline__ void sort_long_run(uint32_t tile, uint2 r, uint64_t* 
     }
     __syncthreads();
     const uint64_t vary = ((uint64_t)s_vary[1] << 32) | s_vary[0];
+    uint32_t zbytes = 0, gbytes = 0;   // bit p: byte p of the item varies in the run
+    for (int p = 0; p < 4; ++p) {
+        if ((vary >> (32 + 8 * p)) & 0xFFu) zbytes |= 1u << (4 + p);
+        if ((vary >> (8 * p)) & 0xFFu) gbytes |= 1u << p;
+    }
     bool in_a = true;
-    for (int pass = 0; pass < 8; ++pass) {
-        const int shift = 8 * pass;
-        if (((vary >> shift) & 0xFFu) == 0u) continue;
+    // one stable pass over byte p, from (in_a ? pa : kout) to the other
+    auto pass_over = [&](int p) {
+        const int shift = 8 * p;
         const uint64_t* ki = in_a ? pa : kout;
         uint64_t* ko = in_a ? kout : pa;
         // digit counts of the run and their exclusive scan
@@ -524,6 +530,32 @@ __device__ __forceinline__ void sort_long_run(uint32_t tile, uint2 r, uint64_t* 
         __threadfence_block();
         __syncthreads();
         in_a = !in_a;
+    };
+    for (int p = 0; p < 8; ++p)
+        if ((zbytes >> p) & 1u) pass_over(p);
+    // equal depths into index order by odd-even transposition between
+    // equal-depth neighbours (in place); a group too long to settle in
+    // kDFixPhases phases sends the run to the full (depth, index) sort,
+    // which orders it from whatever order it is in
+    {
+        uint64_t* X = (in_a ? pa : kout) + r.x;
+        int quiet = 0;
+        for (int ph = 0; ph < kDFixPhases && quiet < 2; ++ph) {
+            bool sw = false;
+            for (uint32_t i = 2u * (uint32_t)tid + (uint32_t)(ph & 1); i + 1 < n; i += 2u * kDLongThreads) {
+                const uint64_t x = X[i], y = X[i + 1];
+                if ((x >> 32) == (y >> 32) && (uint32_t)x > (uint32_t)y) {
+                    X[i] = y;
+                    X[i + 1] = x;
+                    sw = true;
+                }
+            }
+            __threadfence_block();
+            quiet = __syncthreads_or(sw) ? 0 : quiet + 1;
+        }
+        if (quiet < 2)
+            for (int p = 0; p < 8; ++p)
+                if (((gbytes | zbytes) >> p) & 1u) pass_over(p);
     }
     const uint64_t thi = (uint64_t)tile << 32;
     const uint64_t* src = in_a ? pa : kout;
@@ -754,10 +786,11 @@ void launch_bin_direct_sort(int64_t n, int64_t n_tiles, int64_t capacity, uint64
         return;
     }
     const unsigned blocks = (unsigned)((n_tiles + kDSortWaves - 1) / kDSortWaves) + (tile_order ? 1u : 0u);
-    // long-run workgroups after the others: at most one run in kDSortCap + 1
-    // pairs of capacity is long
+    // long-run workgroups after the others: as many as there can be long
+    // runs (one per kDSortCap + 1 pairs of capacity, at most one per tile),
+    // so that they run side by side
     int64_t lg = capacity / (kDSortCap + 1);
-    if (lg > kDLongGrid) lg = kDLongGrid;
+    if (lg > n_tiles) lg = n_tiles;
     hipLaunchKernelGGL(k_dsort, dim3(blocks + (unsigned)lg), dim3(kDSortWaves * kWave), 0, st, w.pairs, keys, vals,
                        rg, (uint32_t)n_tiles, status, tile_order);
 }
