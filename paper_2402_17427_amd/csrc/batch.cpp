@@ -127,6 +127,15 @@ struct gs_batch {
     uint32_t* queue = nullptr;
     uint32_t* torder = nullptr;   // the blend order the sort keeps: [0] = n_tiles, [1..] every tile
     uint32_t max_tiles = 0;
+    // direct binning (every view of the tile shape at most kDirectMaxTiles
+    // tiles): the plan of the current shape and its device table; the
+    // placed pairs go to alt_k
+    bool direct = false;
+    DPlan dplan;
+    std::vector<DView> h_dviews;
+    DView* d_dviews = nullptr;
+    void* dscratch = nullptr;
+    size_t dscratch_bytes = 0;
     // per-pixel buffers
     float* final_T = nullptr;
     uint32_t* n_contrib = nullptr;
@@ -153,7 +162,8 @@ struct gs_batch {
         if (graph) (void)hipGraphDestroy(graph);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         void* ptrs[] = {d_views, d_jobs, d_targets, rec, depth, rect, tt, g2d, first, scan_ws, keys, alt_k, vals,
-                        alt_v, pair_grad, masks, sort_ws, ranges, pair_count, status, queue, torder,
+                        alt_v, pair_grad, masks, sort_ws, ranges, pair_count, status, queue, torder, d_dviews,
+                        dscratch,
                         final_T, n_contrib, dimg, loss_ws, sched, l1_part};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
@@ -172,6 +182,25 @@ struct gs_batch {
         grid_pct = c.grid_pct;
     }
 
+    // The direct-binning plan of the views for a tile shape (false: some
+    // view has too many tiles, so the emission path bins them).
+    bool plan_direct(int w, int h, std::vector<DView>* dv, DPlan* plan) const {
+        std::vector<int64_t> s0(n), s1(n);
+        std::vector<int> ntx(n), nty(n);
+        std::vector<uint32_t> base(n);
+        uint32_t b = 0;
+        for (int c = 0; c < n; ++c) {
+            s0[c] = h_jobs[c].out0;
+            s1[c] = h_jobs[c].out0 + h_jobs[c].count;
+            ntx[c] = (cams[c].W + w - 1) / w;
+            nty[c] = (cams[c].H + h - 1) / h;
+            base[c] = b;
+            b += (uint32_t)(ntx[c] * nty[c]);
+        }
+        dv->assign(n, DView{});
+        return bin_direct_plan(n, s0.data(), s1.data(), ntx.data(), nty.data(), base.data(), dv->data(), plan);
+    }
+
     // View table for a tile shape (host copy + upload).
     gs_status set_tiles(int w, int h, hipStream_t st) {
         tw = w;
@@ -185,7 +214,10 @@ struct gs_batch {
             base += (uint32_t)(v.ntx * v.nty);
         }
         n_tiles = base;
+        direct = d_dviews && plan_direct(w, h, &h_dviews, &dplan) && bin_direct_scratch_bytes(dplan) <= dscratch_bytes;
         if (hipMemcpyAsync(d_views, h_views.data(), sizeof(View) * n, hipMemcpyHostToDevice, st) != hipSuccess ||
+            (direct && hipMemcpyAsync(d_dviews, h_dviews.data(), sizeof(DView) * n, hipMemcpyHostToDevice, st) !=
+                           hipSuccess) ||
             hipStreamSynchronize(st) != hipSuccess)
             return check_hip("gs_batch: view table upload");
         grid_fwd = std::max(1, render_persistent_grid(w, h, false, fwd_batch) * grid_pct / 100);
@@ -210,6 +242,15 @@ struct gs_batch {
 
     void enqueue_project_bin(hipStream_t st) {
         launch_project(jt(), vt(), K, nslots, tw, th, rec, depth, rect, tt, st);
+        if (direct) {
+            DTab t;
+            std::memset(&t, 0, sizeof t);
+            t.dev = d_dviews;
+            t.n = n;
+            launch_bin_direct_place(dplan, t, rect, depth, capacity, first, ranges, pair_count, status, dscratch,
+                                    alt_k, st);
+            return;
+        }
         const bool to_alt = bin_sort_emit_to_alt(tile_bits(n_tiles));
         const ZeroList z = bin_sort_zero_list(sort_ws, capacity, tile_bits(n_tiles), ranges, n_tiles);
         launch_emit_pairs(nslots, tt, rect, depth, jt(), vt(), capacity, to_alt ? alt_k : keys, to_alt ? alt_v : vals,
@@ -220,8 +261,11 @@ struct gs_batch {
     // L1 loss gradient, blend backward, projection backward.
     void enqueue_step(hipStream_t st) {
         enqueue_project_bin(st);
-        launch_bin_sort(keys, vals, alt_k, alt_v, pair_count, capacity, tile_bits(n_tiles), ranges, n_tiles, sort_ws,
-                        st, true, torder);
+        if (direct)
+            launch_bin_direct_sort(n_tiles, capacity, keys, vals, ranges, status, torder, alt_k, st);
+        else
+            launch_bin_sort(keys, vals, alt_k, alt_v, pair_count, capacity, tile_bits(n_tiles), ranges, n_tiles,
+                            sort_ws, st, true, torder);
         RenderArgs r;
         std::memset(&r, 0, sizeof r);
         r.rec = rec;
@@ -463,6 +507,18 @@ gs_status gs_batch_create(const gs_gaussians* cells, const gs_camera* cams, cons
             (s = dmalloc(&b->n_contrib, pix)) || (s = dmalloc(&b->dimg, img)) ||
             (s = dmalloc(&b->l1_part, (size_t)n_cells * kL1MaxChunks)))
             ;
+    }
+    if (!s) {   // direct-binning scratch for the largest plan over the tile shapes tried
+        std::vector<DView> dv;
+        DPlan plan;
+        size_t need = 0;
+        if (b->plan_direct(tw0, th0, &dv, &plan)) need = bin_direct_scratch_bytes(plan);
+        if (autotune)
+            for (const Cand& c : kCands)
+                if (b->plan_direct(c.tw, c.th, &dv, &plan)) need = std::max(need, bin_direct_scratch_bytes(plan));
+        if (need > 0 && (s = dmalloc(&b->d_dviews, n_cells)) == GS_OK &&
+            (s = dmalloc(reinterpret_cast<char**>(&b->dscratch), need)) == GS_OK)
+            b->dscratch_bytes = need;
     }
     if (!s) {
         b->h_targets.assign(targets, targets + n_cells);

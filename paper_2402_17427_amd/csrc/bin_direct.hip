@@ -36,6 +36,9 @@
 // The output -- keys, values, ranges, `first`, pair count, status and tile
 // order -- is exactly that of the emission + stable sort of the whole key
 // (tile, then depth; equal keys in emission, i.e. index, order).
+#include <algorithm>
+#include <cstring>
+
 #include "kernels.h"
 #include "tile_order.h"
 
@@ -93,21 +96,52 @@ __device__ __forceinline__ uint32_t rect_area(const ushort4 r) {
     return (uint32_t)(r.z - r.x) * (uint32_t)(r.w - r.y);
 }
 
-// The block's Gaussians [g0, g1).
-__device__ __forceinline__ void block_range(int64_t n, int64_t chunk, int64_t* g0, int64_t* g1) {
-    *g0 = (int64_t)blockIdx.x * chunk;
-    *g1 = *g0 + chunk < n ? *g0 + chunk : n;
+// The block's record slots [g0, g1) within its view.
+__device__ __forceinline__ void block_range(const DView& V, int lb, int64_t* g0, int64_t* g1) {
+    const int64_t a = V.s0 + (int64_t)lb * V.chunk;
+    *g0 = a < V.s1 ? a : V.s1;
+    *g1 = a + V.chunk < V.s1 ? a + V.chunk : V.s1;
 }
 
-__global__ __launch_bounds__(kDThreads) void k_dcount(const ushort4* __restrict__ rect, int64_t n, int64_t chunk,
-                                                      int ntx, int nty, uint32_t n_tiles, uint32_t* __restrict__ M,
-                                                      uint64_t* __restrict__ bsum) {
+// The view of block b / of strip c (uniform per workgroup).  With one view
+// (MULTI = false) it is the one in the kernel arguments, read with scalar
+// loads; with several, the device table is searched (views in slot order).
+template <bool MULTI>
+__device__ __forceinline__ DView view_of_block(const DTab& t, int b) {
+    if (!MULTI) return t.one;
+    int lo = 0, hi = t.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t.dev[mid].b0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return t.dev[lo];
+}
+template <bool MULTI>
+__device__ __forceinline__ DView view_of_strip(const DTab& t, int c) {
+    if (!MULTI) return t.one;
+    int lo = 0, hi = t.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t.dev[mid].c0 <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    return t.dev[lo];
+}
+
+template <bool MULTI>
+__global__ __launch_bounds__(kDThreads) void k_dcount(DTab views, const ushort4* __restrict__ rect,
+                                                      uint32_t* __restrict__ M, uint64_t* __restrict__ bsum) {
     extern __shared__ uint32_t s_hist[];
     const int tid = threadIdx.x;
+    const DView V = view_of_block<MULTI>(views, (int)blockIdx.x);
+    const int lb = (int)blockIdx.x - V.b0;
+    const uint32_t n_tiles = V.n_tiles;
+    const int ntx = V.ntx, nty = V.nty;
     for (uint32_t t = tid; t < n_tiles; t += kDThreads) s_hist[t] = 0u;
     __syncthreads();
     int64_t g0, g1;
-    block_range(n, chunk, &g0, &g1);
+    block_range(V, lb, &g0, &g1);
     uint64_t pairs = 0;
     for (int64_t base = g0; base < g1; base += (int64_t)kDThreads * kDPer) {
         // kDPer Gaussians per thread, strided by the workgroup (coalesced),
@@ -127,7 +161,7 @@ __global__ __launch_bounds__(kDThreads) void k_dcount(const ushort4* __restrict_
         }
     }
     __syncthreads();
-    uint32_t* row = M + (int64_t)blockIdx.x * n_tiles;
+    uint32_t* row = M + V.m0 + (int64_t)lb * n_tiles;
     for (uint32_t t = tid; t < n_tiles; t += kDThreads) row[t] = s_hist[t];
     uint64_t tot;
     block_scan_ex<kDThreads>(pairs, &tot);
@@ -139,7 +173,8 @@ __global__ __launch_bounds__(kDThreads) void k_dcount(const ushort4* __restrict_
 // XCD by XCD: the blocks of one XCD then write one contiguous stretch of
 // every run, and its L2 fills whole cache lines before it writes them back
 // (in plain block order every placed pair would be a partial line of its
-// own, written back to HBM alone).
+// own, written back to HBM alone).  r and the result count from the view's
+// first block; which XCD comes first does not matter.
 __device__ __forceinline__ int xcd_major_block(int r, int nb) {
     constexpr int X = 8;
     const int q = nb / X, rem = nb % X;   // XCDs x < rem hold q + 1 blocks, the others q
@@ -155,32 +190,43 @@ __device__ __forceinline__ int xcd_major_block(int r, int nb) {
     return x + X * j;
 }
 
-// Workgroup c < strips: tiles 64 c .. 64 c + 63 (one per lane), the matrix
-// rows split over the 16 waves (in XCD-major block order); the last
-// workgroup scans the block totals.
-__global__ __launch_bounds__(kDThreads) void k_dscan(uint32_t* __restrict__ M, int nb, uint32_t n_tiles,
+// Workgroup c < strips: tiles 64 c' .. 64 c' + 63 of its view (one per
+// lane), the view's matrix rows split over the 16 waves (in XCD-major block
+// order); the last workgroup scans the block totals of all views (each
+// block's first emission position) and stores the grand total after them.
+template <bool MULTI>
+__global__ __launch_bounds__(kDThreads) void k_dscan(DTab views, int strips, int nb_all, uint32_t* __restrict__ M,
                                                      uint32_t* __restrict__ ttot, uint64_t* __restrict__ bsum) {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    const uint32_t strips = (n_tiles + kWave - 1) / kWave;
-    if (blockIdx.x == strips) {
-        const uint64_t v = tid < nb ? bsum[tid] : 0u;
-        uint64_t tot;
-        const uint64_t ex = block_scan_ex<kDThreads>(v, &tot);
-        if (tid < nb) bsum[tid] = ex;
+    if ((int)blockIdx.x == strips) {
+        uint64_t carry = 0;
+        for (int b0 = 0; b0 < nb_all; b0 += kDThreads) {
+            const int b = b0 + tid;
+            const uint64_t v = b < nb_all ? bsum[b] : 0u;
+            uint64_t tot;
+            const uint64_t ex = carry + block_scan_ex<kDThreads>(v, &tot);
+            if (b < nb_all) bsum[b] = ex;
+            carry += tot;
+        }
+        if (tid == 0) bsum[nb_all] = carry;
         return;
     }
+    const DView V = view_of_strip<MULTI>(views, (int)blockIdx.x);
+    const int nb = V.nb;
+    const uint32_t n_tiles = V.n_tiles;
     constexpr int kRows = kDMaxBlocks / kDWaves;   // rows per wave
     __shared__ uint32_t s_part[kDWaves][kWave];
     __shared__ int s_row[kDMaxBlocks];   // the block of each place in the runs
     if (tid < nb) s_row[tid] = xcd_major_block(tid, nb);
     __syncthreads();
-    const uint32_t t = blockIdx.x * kWave + (uint32_t)lane;
+    const uint32_t t = ((uint32_t)blockIdx.x - (uint32_t)V.c0) * kWave + (uint32_t)lane;
+    const uint32_t* Mv = M + V.m0;
     const int r0 = wv * kRows;
     uint32_t v[kRows], s = 0;
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
         const int r = r0 + k;
-        v[k] = (r < nb && t < n_tiles) ? M[(int64_t)s_row[r] * n_tiles + t] : 0u;
+        v[k] = (r < nb && t < n_tiles) ? Mv[(int64_t)s_row[r] * n_tiles + t] : 0u;
         s += v[k];
     }
     s_part[wv][lane] = s;
@@ -195,25 +241,27 @@ __global__ __launch_bounds__(kDThreads) void k_dscan(uint32_t* __restrict__ M, i
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
         const int r = r0 + k;
-        if (r < nb && t < n_tiles) M[(int64_t)s_row[r] * n_tiles + t] = run;
+        if (r < nb && t < n_tiles) M[V.m0 + (int64_t)s_row[r] * n_tiles + t] = run;
         run += v[k];
     }
-    if (wv == 0 && t < n_tiles) ttot[t] = tot;
+    if (wv == 0 && t < n_tiles) ttot[V.tile_base + t] = tot;
 }
 
 constexpr int kDTileRounds = (int)((kDirectMaxTiles + kDThreads - 1) / kDThreads);
 
-// Every workgroup first forms the tile starts itself (the exclusive prefix
-// of the tile totals, tiles 1024 k + tid per thread so that the loads are
-// coalesced, all loaded before the first scan) and, from the grand total,
-// the capacity decision; workgroup 0 also writes the ranges, pair count
-// and status.
-__global__ __launch_bounds__(kDThreads) void k_dscatter(const ushort4* __restrict__ rect,
-                                                        const float* __restrict__ depth, int64_t n, int64_t chunk,
-                                                        int ntx, int nty, uint32_t n_tiles,
+// Every workgroup first forms the starts of its view's tiles itself: the
+// view's first pair (the exclusive block prefix at its first block) plus
+// the exclusive prefix of the view's tile totals (tiles 1024 k + tid per
+// thread, so that the loads are coalesced, all loaded before the first
+// scan); the grand total after the block totals decides the capacity.  The
+// view's first workgroup writes the view's ranges, workgroup 0 the pair
+// count and status.
+template <bool MULTI>
+__global__ __launch_bounds__(kDThreads) void k_dscatter(DTab views, const ushort4* __restrict__ rect,
+                                                        const float* __restrict__ depth,
                                                         const uint32_t* __restrict__ M,
-                                                        const uint32_t* __restrict__ ttot, int64_t capacity,
-                                                        const uint64_t* __restrict__ bsum,
+                                                        const uint32_t* __restrict__ ttot, int nb_all,
+                                                        int64_t capacity, const uint64_t* __restrict__ bsum,
                                                         uint32_t* __restrict__ ranges,
                                                         uint32_t* __restrict__ pair_count,
                                                         int32_t* __restrict__ status,
@@ -221,50 +269,55 @@ __global__ __launch_bounds__(kDThreads) void k_dscatter(const ushort4* __restric
                                                         bool vec) {
     extern __shared__ uint32_t s_cur[];
     const int tid = threadIdx.x;
+    const DView V = view_of_block<MULTI>(views, (int)blockIdx.x);
+    const int lb = (int)blockIdx.x - V.b0;
+    const uint32_t n_tiles = V.n_tiles;
+    const int ntx = V.ntx, nty = V.nty;
+    const uint64_t total = bsum[nb_all];
+    const bool over = total > (uint64_t)capacity;
     const int rounds = (int)((n_tiles + kDThreads - 1) / kDThreads);
     uint32_t c[kDTileRounds];
 #pragma unroll
     for (int k = 0; k < kDTileRounds; ++k) {
         const uint32_t t = (uint32_t)(k * kDThreads + tid);
-        c[k] = (k < rounds && t < n_tiles) ? ttot[t] : 0u;
+        c[k] = (k < rounds && t < n_tiles) ? ttot[V.tile_base + t] : 0u;
     }
-    uint64_t total = 0;
+    uint64_t vrun = bsum[V.b0];   // pairs of the earlier views
 #pragma unroll
     for (int k = 0; k < kDTileRounds; ++k) {
         if (k < rounds) {
             uint64_t tot;
-            const uint64_t ex = total + block_scan_ex<kDThreads>(c[k], &tot);
-            total += tot;
+            const uint64_t ex = vrun + block_scan_ex<kDThreads>(c[k], &tot);
+            vrun += tot;
             const uint32_t t = (uint32_t)(k * kDThreads + tid);
             if (t < n_tiles) s_cur[t] = (uint32_t)ex;
         }
     }
-    const bool over = total > (uint64_t)capacity;
-    if (blockIdx.x == 0) {
+    if (lb == 0) {
 #pragma unroll
         for (int k = 0; k < kDTileRounds; ++k) {
             const uint32_t t = (uint32_t)(k * kDThreads + tid);
             if (k < rounds && t < n_tiles) {
                 // an empty tile's range is (0, 0), as a range pass over sorted keys leaves it
                 const bool none = over || c[k] == 0u;
-                reinterpret_cast<uint2*>(ranges)[t] =
+                reinterpret_cast<uint2*>(ranges)[V.tile_base + t] =
                     none ? make_uint2(0u, 0u) : make_uint2(s_cur[t], s_cur[t] + c[k]);
             }
         }
-        if (tid == 0) {
-            pair_count[0] = over ? 0u : (uint32_t)total;   // pairs the later stages process
-            pair_count[1] = total > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)total;   // pairs needed
-            *status = over ? -4 : 0;
-        }
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        pair_count[0] = over ? 0u : (uint32_t)total;   // pairs the later stages process
+        pair_count[1] = total > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)total;   // pairs needed
+        *status = over ? -4 : 0;
     }
     const bool place = !over;
     if (place) {
-        const uint32_t* row = M + (int64_t)blockIdx.x * n_tiles;
+        const uint32_t* row = M + V.m0 + (int64_t)lb * n_tiles;
         for (uint32_t t = tid; t < n_tiles; t += kDThreads) s_cur[t] += row[t];
     }
     __syncthreads();
     int64_t g0, g1;
-    block_range(n, chunk, &g0, &g1);
+    block_range(V, lb, &g0, &g1);
     uint64_t carry = bsum[blockIdx.x];
     for (int64_t base = g0; base < g1; base += (int64_t)kDThreads * kDPer) {
         // kDPer consecutive Gaussians per thread, so that one scan gives
@@ -704,85 +757,110 @@ __global__ __launch_bounds__(kDSortWaves * kWave) void k_dsort(uint64_t* __restr
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-struct DirectWs {
-    uint32_t* M;       // [nb][n_tiles]
-    uint32_t* ttot;    // [n_tiles]
-    uint64_t* bsum;    // [nb]
-    uint64_t* pairs;   // [capacity]: placed (depth << 32 | index)
+struct Scratch {
+    uint32_t* M;      // count matrix: the views' rows
+    uint32_t* ttot;   // [n_tiles]
+    uint64_t* bsum;   // [nb + 1]: block totals, then their exclusive prefix and the grand total
 };
 
-void direct_shape(int64_t n, int* nb, int64_t* chunk) {
-    int64_t b = (n + kDMinChunk - 1) / kDMinChunk;
-    if (b > kDMaxBlocks) b = kDMaxBlocks;
-    if (b < 1) b = 1;
-    int64_t c = (n + b - 1) / b;
-    c = (c + kDPer - 1) / kDPer * kDPer;
-    if (c < 1) c = 1;
-    *nb = n > 0 ? (int)((n + c - 1) / c) : 0;
-    *chunk = c;
-}
-
-DirectWs carve_direct(void* ws, int64_t n, int64_t capacity, int64_t n_tiles) {
-    int nb;
-    int64_t chunk;
-    direct_shape(n, &nb, &chunk);
-    DirectWs w;
+Scratch carve_scratch(void* ws, const DPlan& plan) {
+    Scratch w;
     char* p = static_cast<char*>(ws);
     w.M = reinterpret_cast<uint32_t*>(p);
-    p += align256((size_t)(nb > 0 ? nb : 1) * (size_t)n_tiles * 4);
+    p += align256((size_t)(plan.m_words > 0 ? plan.m_words : 1) * 4);
     w.ttot = reinterpret_cast<uint32_t*>(p);
-    p += align256((size_t)n_tiles * 4);
+    p += align256((size_t)(plan.n_tiles > 0 ? plan.n_tiles : 1) * 4);
     w.bsum = reinterpret_cast<uint64_t*>(p);
-    p += align256((size_t)(nb > 0 ? nb : 1) * 8);
-    w.pairs = reinterpret_cast<uint64_t*>(p);
-    (void)capacity;
     return w;
+}
+
+// The plan of one view of n Gaussians (slots 0 .. n - 1).
+bool single_plan(int64_t n, int ntx, int64_t n_tiles, DView* v, DPlan* plan) {
+    const int64_t s0 = 0, s1 = n;
+    const int nty = ntx > 0 ? (int)((n_tiles + ntx - 1) / ntx) : 0;
+    const uint32_t base = 0;
+    return bin_direct_plan(1, &s0, &s1, &ntx, &nty, &base, v, plan);
 }
 
 }  // namespace
 
-bool bin_direct_supported(int64_t n_tiles) { return n_tiles > 0 && n_tiles <= kDirectMaxTiles; }
-
-size_t bin_direct_ws_bytes(int64_t n, int64_t capacity, int64_t n_tiles) {
-    int nb;
-    int64_t chunk;
-    direct_shape(n, &nb, &chunk);
-    return align256((size_t)(nb > 0 ? nb : 1) * (size_t)n_tiles * 4) + align256((size_t)n_tiles * 4) +
-           align256((size_t)(nb > 0 ? nb : 1) * 8) + align256((size_t)(capacity > 0 ? capacity : 0) * 8);
+bool bin_direct_plan(int nv, const int64_t* s0, const int64_t* s1, const int* ntx, const int* nty,
+                     const uint32_t* tile_base, DView* out, DPlan* plan) {
+    DPlan p;
+    p.n_views = nv;
+    for (int v = 0; v < nv; ++v) {
+        const int64_t nt = (int64_t)ntx[v] * nty[v];
+        if (nt <= 0 || nt > kDirectMaxTiles) return false;
+        const int64_t slots = s1[v] > s0[v] ? s1[v] - s0[v] : 0;
+        int64_t nb = (slots + kDMinChunk - 1) / kDMinChunk;
+        if (nb > kDMaxBlocks) nb = kDMaxBlocks;
+        if (nb < 1) nb = 1;   // a view without slots still writes its ranges
+        int64_t chunk = (slots + nb - 1) / nb;
+        chunk = (chunk + kDPer - 1) / kDPer * kDPer;
+        if (chunk < kDPer) chunk = kDPer;
+        DView& d = out[v];
+        d.s0 = s0[v];
+        d.s1 = s0[v] + slots;
+        d.chunk = chunk;
+        d.m0 = p.m_words;
+        d.tile_base = tile_base[v];
+        d.n_tiles = (uint32_t)nt;
+        d.ntx = ntx[v];
+        d.nty = nty[v];
+        d.b0 = p.nb;
+        d.nb = (int)nb;
+        d.c0 = p.strips;
+        p.nb += (int)nb;
+        p.strips += (int)((nt + kWave - 1) / kWave);
+        p.m_words += nb * nt;
+        p.n_tiles = std::max(p.n_tiles, tile_base[v] + (uint32_t)nt);
+        p.max_tiles = std::max(p.max_tiles, (uint32_t)nt);
+    }
+    *plan = p;
+    return nv > 0;
 }
 
-void launch_bin_direct_place(int64_t n, const ushort4* rect, const float* depth, int ntx, int64_t n_tiles,
+size_t bin_direct_scratch_bytes(const DPlan& plan) {
+    return align256((size_t)(plan.m_words > 0 ? plan.m_words : 1) * 4) +
+           align256((size_t)(plan.n_tiles > 0 ? plan.n_tiles : 1) * 4) + align256((size_t)(plan.nb + 1) * 8);
+}
+
+void launch_bin_direct_place(const DPlan& plan, const DTab& views, const ushort4* rect, const float* depth,
                              int64_t capacity, uint32_t* first, uint32_t* ranges, uint32_t* pair_count,
-                             int32_t* status, void* ws, hipStream_t st) {
-    int nb;
-    int64_t chunk;
-    direct_shape(n, &nb, &chunk);
-    const DirectWs w = carve_direct(ws, n, capacity, n_tiles);
-    const size_t lds = (size_t)n_tiles * 4;
-    const int nty = (int)((n_tiles + ntx - 1) / ntx);
-    if (nb > 0)
-        hipLaunchKernelGGL(k_dcount, dim3((unsigned)nb), dim3(kDThreads), lds, st, rect, n, chunk, ntx, nty,
-                           (uint32_t)n_tiles, w.M, w.bsum);
-    const unsigned strips = (unsigned)((n_tiles + kWave - 1) / kWave);
-    hipLaunchKernelGGL(k_dscan, dim3(strips + 1), dim3(kDThreads), 0, st, w.M, nb, (uint32_t)n_tiles, w.ttot,
-                       w.bsum);
+                             int32_t* status, void* scratch, uint64_t* pairs, hipStream_t st) {
+    const Scratch w = carve_scratch(scratch, plan);
+    const size_t lds = (size_t)plan.max_tiles * 4;
+    const bool multi = views.dev != nullptr;
+    // views start at multiples of 4 slots, so a thread's four slots are
+    // 16-byte vectors when the arrays are 16-byte aligned
     const bool vec = ((reinterpret_cast<uintptr_t>(rect) | reinterpret_cast<uintptr_t>(depth) |
                        reinterpret_cast<uintptr_t>(first)) & 15u) == 0;
-    // at least one workgroup, which writes ranges, pair count and status
-    hipLaunchKernelGGL(k_dscatter, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kDThreads), lds, st, rect, depth, n,
-                       chunk, ntx, nty, (uint32_t)n_tiles, w.M, w.ttot, capacity, w.bsum, ranges, pair_count, status,
-                       first, w.pairs, vec);
+    if (multi) {
+        hipLaunchKernelGGL(k_dcount<true>, dim3((unsigned)plan.nb), dim3(kDThreads), lds, st, views, rect, w.M,
+                           w.bsum);
+        hipLaunchKernelGGL(k_dscan<true>, dim3((unsigned)plan.strips + 1), dim3(kDThreads), 0, st, views,
+                           plan.strips, plan.nb, w.M, w.ttot, w.bsum);
+        hipLaunchKernelGGL(k_dscatter<true>, dim3((unsigned)plan.nb), dim3(kDThreads), lds, st, views, rect, depth,
+                           w.M, w.ttot, plan.nb, capacity, w.bsum, ranges, pair_count, status, first, pairs, vec);
+    } else {
+        hipLaunchKernelGGL(k_dcount<false>, dim3((unsigned)plan.nb), dim3(kDThreads), lds, st, views, rect, w.M,
+                           w.bsum);
+        hipLaunchKernelGGL(k_dscan<false>, dim3((unsigned)plan.strips + 1), dim3(kDThreads), 0, st, views,
+                           plan.strips, plan.nb, w.M, w.ttot, w.bsum);
+        hipLaunchKernelGGL(k_dscatter<false>, dim3((unsigned)plan.nb), dim3(kDThreads), lds, st, views, rect,
+                           depth, w.M, w.ttot, plan.nb, capacity, w.bsum, ranges, pair_count, status, first, pairs,
+                           vec);
+    }
 }
 
-void launch_bin_direct_sort(int64_t n, int64_t n_tiles, int64_t capacity, uint64_t* keys, uint32_t* vals,
-                            const uint32_t* ranges, const int32_t* status, uint32_t* tile_order, void* ws,
-                            hipStream_t st) {
-    const DirectWs w = carve_direct(ws, n, capacity, n_tiles);
+void launch_bin_direct_sort(uint32_t n_tiles, int64_t capacity, uint64_t* keys, uint32_t* vals,
+                            const uint32_t* ranges, const int32_t* status, uint32_t* tile_order,
+                            uint64_t* pairs, hipStream_t st) {
     const uint2* rg = reinterpret_cast<const uint2*>(ranges);
     if (capacity == 0) {   // nothing to sort (every range is empty); the order is still kept
         if (tile_order)
-            hipLaunchKernelGGL(k_dsort, dim3(1), dim3(kDSortWaves * kWave), 0, st, w.pairs, keys, vals, rg,
-                               (uint32_t)n_tiles, status, tile_order);
+            hipLaunchKernelGGL(k_dsort, dim3(1), dim3(kDSortWaves * kWave), 0, st, pairs, keys, vals, rg, n_tiles,
+                               status, tile_order);
         return;
     }
     const unsigned blocks = (unsigned)((n_tiles + kDSortWaves - 1) / kDSortWaves) + (tile_order ? 1u : 0u);
@@ -790,9 +868,41 @@ void launch_bin_direct_sort(int64_t n, int64_t n_tiles, int64_t capacity, uint64
     // runs (one per kDSortCap + 1 pairs of capacity, at most one per tile),
     // so that they run side by side
     int64_t lg = capacity / (kDSortCap + 1);
-    if (lg > n_tiles) lg = n_tiles;
-    hipLaunchKernelGGL(k_dsort, dim3(blocks + (unsigned)lg), dim3(kDSortWaves * kWave), 0, st, w.pairs, keys, vals,
-                       rg, (uint32_t)n_tiles, status, tile_order);
+    if (lg > (int64_t)n_tiles) lg = n_tiles;
+    hipLaunchKernelGGL(k_dsort, dim3(blocks + (unsigned)lg), dim3(kDSortWaves * kWave), 0, st, pairs, keys, vals,
+                       rg, n_tiles, status, tile_order);
+}
+
+bool bin_direct_supported(int64_t n_tiles) { return n_tiles > 0 && n_tiles <= kDirectMaxTiles; }
+
+size_t bin_direct_ws_bytes(int64_t n, int64_t capacity, int64_t n_tiles) {
+    // the sizes depend on n and the tile count only, not on the grid's shape
+    DView v;
+    DPlan plan;
+    if (!single_plan(n, 1, n_tiles, &v, &plan)) return 0;
+    return bin_direct_scratch_bytes(plan) + align256((size_t)(capacity > 0 ? capacity : 0) * 8);
+}
+
+void launch_bin_direct_place(int64_t n, const ushort4* rect, const float* depth, int ntx, int64_t n_tiles,
+                             int64_t capacity, uint32_t* first, uint32_t* ranges, uint32_t* pair_count,
+                             int32_t* status, void* ws, hipStream_t st) {
+    DTab t;
+    std::memset(&t, 0, sizeof t);
+    DPlan plan;
+    if (!single_plan(n, ntx, n_tiles, &t.one, &plan)) return;
+    t.n = 1;
+    uint64_t* pairs = reinterpret_cast<uint64_t*>(static_cast<char*>(ws) + bin_direct_scratch_bytes(plan));
+    launch_bin_direct_place(plan, t, rect, depth, capacity, first, ranges, pair_count, status, ws, pairs, st);
+}
+
+void launch_bin_direct_sort(int64_t n, int64_t n_tiles, int64_t capacity, uint64_t* keys, uint32_t* vals,
+                            const uint32_t* ranges, const int32_t* status, uint32_t* tile_order, void* ws,
+                            hipStream_t st) {
+    DView v;
+    DPlan plan;
+    if (!single_plan(n, 1, n_tiles, &v, &plan)) return;
+    uint64_t* pairs = reinterpret_cast<uint64_t*>(static_cast<char*>(ws) + bin_direct_scratch_bytes(plan));
+    launch_bin_direct_sort((uint32_t)n_tiles, capacity, keys, vals, ranges, status, tile_order, pairs, st);
 }
 
 }  // namespace gs

@@ -70,23 +70,59 @@ void launch_bin_sort(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_
                      int64_t capacity, int tile_bits, uint32_t* ranges, int64_t n_tiles, void* ws, hipStream_t st,
                      bool zeroed = false, uint32_t* tile_order = nullptr);
 
-// ---- direct binning of one view (bin_direct.hip)
-// For one view of at most kDirectMaxTiles tiles the pairs are placed into
-// their tile's run straight from the tile rectangles (per-block tile
+// ---- direct binning (bin_direct.hip)
+// For views of at most kDirectMaxTiles tiles each, the pairs are placed
+// into their tile's run straight from the tile rectangles (per-block tile
 // histograms, their column scan, an LDS-cursor scatter), then each run is
 // sorted on (depth, index): the same keys, values, ranges, `first`, pair
 // count, status and tile order as launch_emit_pairs + launch_bin_sort.
 constexpr int64_t kDirectMaxTiles = 16384;
-bool bin_direct_supported(int64_t n_tiles);
-size_t bin_direct_ws_bytes(int64_t n, int64_t capacity, int64_t n_tiles);
-// Placement: `first`, ranges, pair_count[2], status and the placed pairs
-// in the workspace.
-void launch_bin_direct_place(int64_t n, const ushort4* rect, const float* depth, int ntx, int64_t n_tiles,
+// One view of a direct binning (bin_direct_plan fills them; several views
+// go to the kernels as a device table, one in the kernel arguments).
+struct DView {
+    int64_t s0, s1;        // the view's record slots [s0, s1), s0 a multiple of 4
+    int64_t chunk;         // slots per block (a multiple of 4)
+    int64_t m0;            // first word of its count-matrix rows (nb rows of n_tiles words)
+    uint32_t tile_base, n_tiles;
+    int ntx, nty;
+    int b0, nb;            // its blocks b0 .. b0 + nb - 1 (global ids, in slot order)
+    int c0;                // its first strip of 64 tiles in the column scan
+};
+struct DTab {
+    const DView* dev;
+    int n;
+    DView one;
+};
+struct DPlan {
+    int n_views = 0, nb = 0, strips = 0;
+    uint32_t n_tiles = 0, max_tiles = 0;
+    int64_t m_words = 0;
+};
+// Views 0 .. nv - 1 (slots [s0[v], s1[v]) in increasing order, tile grid
+// ntx[v] x nty[v] from global tile tile_base[v]); fills out[0 .. nv - 1].
+// False when a view has no tile or more than kDirectMaxTiles of them.
+bool bin_direct_plan(int nv, const int64_t* s0, const int64_t* s1, const int* ntx, const int* nty,
+                     const uint32_t* tile_base, DView* out, DPlan* plan);
+// Device scratch of the placement (count matrix, tile and block totals);
+// the placed pairs (capacity u64) are a buffer of their own.
+size_t bin_direct_scratch_bytes(const DPlan& plan);
+// Placement: `first` (optional, every slot of the views), ranges,
+// pair_count[2], status, and the placed pairs (depth bits << 32 | slot).
+void launch_bin_direct_place(const DPlan& plan, const DTab& views, const ushort4* rect, const float* depth,
                              int64_t capacity, uint32_t* first, uint32_t* ranges, uint32_t* pair_count,
-                             int32_t* status, void* ws, hipStream_t st);
+                             int32_t* status, void* scratch, uint64_t* pairs, hipStream_t st);
 // Per-run sort of the placed pairs into (keys, vals), and the tile order
 // (optional, n_tiles + 1 words: [0] = n_tiles, [1..] every tile, the
 // longest lists first).
+void launch_bin_direct_sort(uint32_t n_tiles, int64_t capacity, uint64_t* keys, uint32_t* vals,
+                            const uint32_t* ranges, const int32_t* status, uint32_t* tile_order,
+                            uint64_t* pairs, hipStream_t st);
+// One view of n Gaussians (the plain calls): workspace = scratch + pairs.
+bool bin_direct_supported(int64_t n_tiles);
+size_t bin_direct_ws_bytes(int64_t n, int64_t capacity, int64_t n_tiles);
+void launch_bin_direct_place(int64_t n, const ushort4* rect, const float* depth, int ntx, int64_t n_tiles,
+                             int64_t capacity, uint32_t* first, uint32_t* ranges, uint32_t* pair_count,
+                             int32_t* status, void* ws, hipStream_t st);
 void launch_bin_direct_sort(int64_t n, int64_t n_tiles, int64_t capacity, uint64_t* keys, uint32_t* vals,
                             const uint32_t* ranges, const int32_t* status, uint32_t* tile_order, void* ws,
                             hipStream_t st);
