@@ -247,15 +247,12 @@ __global__ __launch_bounds__(kDThreads) void k_dscan(DTab views, int strips, int
     if (wv == 0 && t < n_tiles) ttot[V.tile_base + t] = tot;
 }
 
-constexpr int kDTileRounds = (int)((kDirectMaxTiles + kDThreads - 1) / kDThreads);
-
 // Every workgroup first forms the starts of its view's tiles itself: the
 // view's first pair (the exclusive block prefix at its first block) plus
-// the exclusive prefix of the view's tile totals (tiles 1024 k + tid per
-// thread, so that the loads are coalesced, all loaded before the first
-// scan); the grand total after the block totals decides the capacity.  The
-// view's first workgroup writes the view's ranges, workgroup 0 the pair
-// count and status.
+// the exclusive prefix of the view's tile totals, scanned in LDS; the grand
+// total after the block totals decides the capacity.  The view's first
+// workgroup writes the view's ranges, workgroup 0 the pair count and
+// status.
 template <bool MULTI>
 __global__ __launch_bounds__(kDThreads) void k_dscatter(DTab views, const ushort4* __restrict__ rect,
                                                         const float* __restrict__ depth,
@@ -275,34 +272,37 @@ __global__ __launch_bounds__(kDThreads) void k_dscatter(DTab views, const ushort
     const int ntx = V.ntx, nty = V.nty;
     const uint64_t total = bsum[nb_all];
     const bool over = total > (uint64_t)capacity;
-    const int rounds = (int)((n_tiles + kDThreads - 1) / kDThreads);
-    uint32_t c[kDTileRounds];
+    // the view's tile totals into LDS (four loads in flight per thread),
+    // then their exclusive prefix in place, 1024 tiles per workgroup scan
+    for (uint32_t t0 = 0; t0 < n_tiles; t0 += 4 * kDThreads) {
+        uint32_t c4[4];
 #pragma unroll
-    for (int k = 0; k < kDTileRounds; ++k) {
-        const uint32_t t = (uint32_t)(k * kDThreads + tid);
-        c[k] = (k < rounds && t < n_tiles) ? ttot[V.tile_base + t] : 0u;
-    }
-    uint64_t vrun = bsum[V.b0];   // pairs of the earlier views
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t t = t0 + (uint32_t)(k * kDThreads + tid);
+            c4[k] = t < n_tiles ? ttot[V.tile_base + t] : 0u;
+        }
 #pragma unroll
-    for (int k = 0; k < kDTileRounds; ++k) {
-        if (k < rounds) {
-            uint64_t tot;
-            const uint64_t ex = vrun + block_scan_ex<kDThreads>(c[k], &tot);
-            vrun += tot;
-            const uint32_t t = (uint32_t)(k * kDThreads + tid);
-            if (t < n_tiles) s_cur[t] = (uint32_t)ex;
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t t = t0 + (uint32_t)(k * kDThreads + tid);
+            if (t < n_tiles) s_cur[t] = c4[k];
         }
     }
-    if (lb == 0) {
-#pragma unroll
-        for (int k = 0; k < kDTileRounds; ++k) {
-            const uint32_t t = (uint32_t)(k * kDThreads + tid);
-            if (k < rounds && t < n_tiles) {
-                // an empty tile's range is (0, 0), as a range pass over sorted keys leaves it
-                const bool none = over || c[k] == 0u;
+    __syncthreads();
+    uint64_t vrun = bsum[V.b0];   // pairs of the earlier views
+    for (uint32_t t0 = 0; t0 < n_tiles; t0 += kDThreads) {
+        const uint32_t t = t0 + (uint32_t)tid;
+        const uint32_t c = t < n_tiles ? s_cur[t] : 0u;
+        uint64_t tot;
+        // (the scan's barriers order every read of s_cur before the writes)
+        const uint64_t ex = vrun + block_scan_ex<kDThreads>(c, &tot);
+        vrun += tot;
+        if (t < n_tiles) {
+            s_cur[t] = (uint32_t)ex;
+            // the view's first workgroup writes its ranges; an empty tile's
+            // range is (0, 0), as a range pass over sorted keys leaves it
+            if (lb == 0)
                 reinterpret_cast<uint2*>(ranges)[V.tile_base + t] =
-                    none ? make_uint2(0u, 0u) : make_uint2(s_cur[t], s_cur[t] + c[k]);
-            }
+                    (over || c == 0u) ? make_uint2(0u, 0u) : make_uint2((uint32_t)ex, (uint32_t)(ex + c));
         }
     }
     if (blockIdx.x == 0 && tid == 0) {

@@ -76,7 +76,7 @@ void launch_bin_sort(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_
 // histograms, their column scan, an LDS-cursor scatter), then each run is
 // sorted on (depth, index): the same keys, values, ranges, `first`, pair
 // count, status and tile order as launch_emit_pairs + launch_bin_sort.
-constexpr int64_t kDirectMaxTiles = 16384;
+constexpr int64_t kDirectMaxTiles = 32768;
 // One view of a direct binning (bin_direct_plan fills them; several views
 // go to the kernels as a device table, one in the kernel arguments).
 struct DView {

@@ -90,9 +90,13 @@ struct Pipe {
     uint32_t* n_contrib = nullptr;
     View* d_views = nullptr;
     Job* d_jobs = nullptr;
+    DView* d_dviews = nullptr;   // direct binning: the batch's plan
+    void* dscratch = nullptr;
+    size_t dscratch_bytes = 0;
     // pinned host
     View* h_views = nullptr;
     Job* h_jobs = nullptr;
+    DView* h_dviews = nullptr;
     int32_t* h_status = nullptr;   // status, pairs processed, pairs needed
     // batch in flight
     std::vector<uint64_t> tickets;
@@ -275,14 +279,47 @@ struct gs_server {
             slot = 0;
         }
         const int64_t cap = p.pairs_cap;
-        const int tb = tile_bits(std::max<uint32_t>(tile, 1));
-        const bool to_alt = bin_sort_emit_to_alt(tb);
         launch_project(jt, vt, scene.K, slot, tw, th, p.rec, p.depth, p.rect, p.tt, st);
-        const ZeroList z = bin_sort_zero_list(p.sort_ws, cap, tb, p.ranges, tile);
-        launch_emit_pairs(slot, p.tt, p.rect, p.depth, jt, vt, cap, to_alt ? p.alt_k : p.keys,
-                          to_alt ? p.alt_v : p.vals, nullptr, p.pair_count, p.status, p.scan_ws, st, &z);
-        launch_bin_sort(p.keys, p.vals, p.alt_k, p.alt_v, p.pair_count, cap, tb, p.ranges, tile, p.sort_ws, st,
-                        true, p.torder);
+        // direct binning when every view fits it: the views' slot ranges
+        // (their jobs are consecutive) and tile grids
+        bool direct = nv > 0;
+        DPlan plan;
+        if (direct) {
+            std::vector<int64_t> s0(nv), s1(nv);
+            std::vector<int> ntx(nv), nty(nv);
+            std::vector<uint32_t> base(nv);
+            int jv = 0;
+            for (int v = 0; v < nv; ++v) {
+                const int j0 = jv;
+                while (jv < nj && p.h_jobs[jv].view == v) ++jv;
+                s0[v] = j0 < jv ? p.h_jobs[j0].out0 : (jv < nj ? p.h_jobs[jv].out0 : slot);
+                s1[v] = j0 < jv ? p.h_jobs[jv - 1].out0 + p.h_jobs[jv - 1].count : s0[v];
+                ntx[v] = p.h_views[v].ntx;
+                nty[v] = p.h_views[v].nty;
+                base[v] = p.h_views[v].tile_base;
+            }
+            direct = bin_direct_plan(nv, s0.data(), s1.data(), ntx.data(), nty.data(), base.data(), p.h_dviews,
+                                     &plan) &&
+                     bin_direct_scratch_bytes(plan) <= p.dscratch_bytes;
+        }
+        if (direct) {
+            (void)hipMemcpyAsync(p.d_dviews, p.h_dviews, sizeof(DView) * nv, hipMemcpyHostToDevice, st);
+            DTab dt;
+            std::memset(&dt, 0, sizeof dt);
+            dt.dev = p.d_dviews;
+            dt.n = nv;
+            launch_bin_direct_place(plan, dt, p.rect, p.depth, cap, nullptr, p.ranges, p.pair_count, p.status,
+                                    p.dscratch, p.alt_k, st);
+            launch_bin_direct_sort(tile, cap, p.keys, p.vals, p.ranges, p.status, p.torder, p.alt_k, st);
+        } else {
+            const int tb = tile_bits(std::max<uint32_t>(tile, 1));
+            const bool to_alt = bin_sort_emit_to_alt(tb);
+            const ZeroList z = bin_sort_zero_list(p.sort_ws, cap, tb, p.ranges, tile);
+            launch_emit_pairs(slot, p.tt, p.rect, p.depth, jt, vt, cap, to_alt ? p.alt_k : p.keys,
+                              to_alt ? p.alt_v : p.vals, nullptr, p.pair_count, p.status, p.scan_ws, st, &z);
+            launch_bin_sort(p.keys, p.vals, p.alt_k, p.alt_v, p.pair_count, cap, tb, p.ranges, tile, p.sort_ws, st,
+                            true, p.torder);
+        }
         RenderArgs r;
         std::memset(&r, 0, sizeof r);
         r.rec = p.rec;
@@ -364,12 +401,14 @@ struct gs_server {
         for (Pipe& p : pipes) {
             if (p.st) (void)hipStreamSynchronize(p.st);
             void* ptrs[] = {p.rec, p.depth, p.rect, p.tt, p.scan_ws, p.keys, p.alt_k, p.vals, p.alt_v, p.sort_ws,
-                            p.ranges, p.torder, p.pair_count, p.status, p.final_T, p.n_contrib, p.d_views, p.d_jobs};
+                            p.ranges, p.torder, p.pair_count, p.status, p.final_T, p.n_contrib, p.d_views, p.d_jobs,
+                            p.d_dviews, p.dscratch};
             for (void* q : ptrs)
                 if (q) (void)hipFree(q);
             if (p.h_views) (void)hipHostFree(p.h_views);
             if (p.h_jobs) (void)hipHostFree(p.h_jobs);
             if (p.h_status) (void)hipHostFree(p.h_status);
+            if (p.h_dviews) (void)hipHostFree(p.h_dviews);
             if (p.ev) (void)hipEventDestroy(p.ev);
             if (p.st) (void)hipStreamDestroy(p.st);
         }
@@ -450,6 +489,16 @@ gs_status gs_serve_create(const gs_gaussians* scene, const float* cell_aabbs, co
              hipHostMalloc(reinterpret_cast<void**>(&p.h_views), sizeof(View) * p.views_cap, 0) == hipSuccess &&
              hipHostMalloc(reinterpret_cast<void**>(&p.h_jobs), sizeof(Job) * p.jobs_cap, 0) == hipSuccess &&
              hipHostMalloc(reinterpret_cast<void**>(&p.h_status), 4 * sizeof(int32_t), 0) == hipSuccess;
+        // direct binning: at most 256 count-matrix rows per view, each of
+        // the view's tiles, so the matrix holds at most 256 x tiles_cap words
+        if (ok) {
+            p.dscratch_bytes = ((size_t)256 * p.tiles_cap * 4 + 255) / 256 * 256 +
+                               ((size_t)p.tiles_cap * 4 + 255) / 256 * 256 +
+                               ((size_t)(256 * p.views_cap + 1) * 8 + 255) / 256 * 256;
+            ok = dalloc(&p.d_dviews, p.views_cap) &&
+                 dalloc(reinterpret_cast<char**>(&p.dscratch), p.dscratch_bytes) &&
+                 hipHostMalloc(reinterpret_cast<void**>(&p.h_dviews), sizeof(DView) * p.views_cap, 0) == hipSuccess;
+        }
         if (!ok) break;
     }
     if (!ok) {
