@@ -196,7 +196,7 @@ gs_status gs_bin_sort_workspace(int64_t n, int64_t pair_capacity, int64_t n_tile
  * then depth, then Gaussian index (the order of a stable sort of the keys
  * emitted Gaussian by Gaussian, tiles row-major within each), with per-tile
  * ranges and each Gaussian's first emission position (bins.first).  Views
- * of at most 16384 tiles place every pair straight into its tile's run (per-
+ * of at most 32768 tiles place every pair straight into its tile's run (per-
  * block tile histograms, a column scan, a scatter) and sort each run by
  * depth, equal depths by index; larger ones emit the pairs and radix-sort
  * them (onesweep, 8-bit digits) on the tile bits, then each run by depth.

@@ -206,6 +206,28 @@ def test_bins_keep_index_order_among_equal_depths(name, tile):
     print(f"[case] {same} equal keys, longest tile run {runs.max()}", flush=True)
 
 
+def test_bins_of_a_view_above_the_direct_limit_take_the_emission_path():
+    """2048x1100 with 8x8 tiles is 35328 tiles, above what the direct
+    placement takes per view (32768): the pairs are emitted and radix-sorted
+    instead, with the same result."""
+    _case("bins through the emission path (35328 tiles)")
+    g, cam = scenes.small_city(n=20_000, seed=19, width=2048, height=1100)
+    tile = (8, 8)
+    assert ((cam.width + 7) // 8) * ((cam.height + 7) // 8) > 32768
+    dg = raster.DeviceGaussians.from_host(g)
+    f = raster.Frame(g.n, g.sh_degree, cam, tile=tile)
+    P = f.ensure_capacity(dg)
+    b = oracle.bin(g, cam, *tile)
+    assert not b["amb"].any(), "scene has Gaussians on a rounding boundary; pick another seed"
+    assert P == b["keys"].size
+    np.testing.assert_array_equal(f.keys.cpu().numpy().view(np.uint64)[:P], b["keys"])
+    np.testing.assert_array_equal(f.vals.cpu().numpy().view(np.uint32)[:P], b["vals"])
+    np.testing.assert_array_equal(f.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), b["ranges"])
+    np.testing.assert_array_equal(f.first.cpu().numpy().view(np.uint32)[: g.n],
+                                  np.concatenate([[0], np.cumsum(b["tiles_touched"][:-1], dtype=np.uint64)])
+                                  .astype(np.uint32))
+
+
 # --------------------------------------------------------------- forward --
 
 @pytest.mark.parametrize("name", ["config1", "city_ragged", "city_white", "city_dense", "city_capped"])
