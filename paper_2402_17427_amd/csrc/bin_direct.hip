@@ -1,41 +1,45 @@
-// Binning of one view by direct placement: every (Gaussian, tile) pair is
-// written straight into its tile's run, then each run is sorted by depth.
+// Binning by direct placement: every (Gaussian, tile) pair is written
+// straight into its tile's run, then each run is sorted by depth.
 //
 // VastGaussian (arXiv 2402.17427), section 3: the projected Gaussians are
 // assigned to the screen tiles their support touches, and every tile's list
 // is ordered by depth before the blend.  The tile of each pair is known
 // before any pair exists (the Gaussian's tile rectangle from the
-// projection), so for a view of at most kDirectMaxTiles tiles no radix sort
-// over the tile bits is needed:
-//   k_dcount    per block of consecutive Gaussians: its pairs per tile (an
-//               LDS histogram) -> row b of a count matrix [blocks][tiles],
-//               and its pair total
-//   k_dscan     per strip of 64 tiles: exclusive scan down the matrix's
-//               columns (where each block's share of a tile's run starts
-//               inside the run) and the tile totals; one more workgroup
-//               scans the block totals (each block's first emission position)
-//   k_dscatter  per block: the tile starts (every workgroup scans the tile
-//               totals itself; the first also writes the ranges, pair count
-//               and capacity status), every Gaussian's emission position (`first`,
-//               the exclusive prefix of its tile counts), and each of its
-//               pairs (depth bits << 32 | index) written at the block's
-//               cursor in the tile's run (LDS atomics, so the order inside a
-//               block's share of a run is arbitrary)
+// projection), so for views of at most kDirectMaxTiles tiles each no radix
+// sort over the tile bits is needed.  Each view (one for the plain calls,
+// several for the batched cells and the render server) is cut into blocks
+// of consecutive record slots, at most 256 per view:
+//   k_dcount    per block: its pairs per tile of its view (an LDS
+//               histogram) -> one row of the view's count matrix
+//               [blocks][tiles], and its pair total
+//   k_dscan     per strip of 64 tiles of a view: exclusive scan down the
+//               view's matrix columns (where each block's share of a tile's
+//               run starts inside the run) and the tile totals; one more
+//               workgroup scans the block totals of all views (each block's
+//               first emission position) and stores the grand total
+//   k_dscatter  per block: the starts of its view's tiles (every workgroup
+//               scans its view's tile totals itself; the view's first also
+//               writes the view's ranges, workgroup 0 the pair count and
+//               capacity status), every slot's emission position (`first`,
+//               the exclusive prefix of the tile counts), and each pair
+//               (depth bits << 32 | slot) written at the block's cursor in
+//               the tile's run (LDS atomics, so the order inside a block's
+//               share of a run is arbitrary)
 //   k_dsort     one wave per run of at most 1024 pairs: stable LDS radix
 //               passes over the depth bytes that vary in the run; entries
 //               of equal depth are then put in index order (odd-even
 //               transposition, or for long groups a second sort on (depth,
 //               index), index bytes first), so the order never depends on
-//               the scatter's; the sorted keys (tile << 32 | depth bits) and
-//               values are written out.  In the same launch an extra first
-//               workgroup writes the blend order (longest list first), and
-//               the last workgroups (one per 1025 pairs of capacity, at most
-//               one per tile) sort the runs of more than 1024 pairs: stable
-//               passes over global memory on depth, the same equal-depth
-//               fix, or the full (depth, index) sort
+//               the scatter's; the sorted keys (global tile << 32 | depth
+//               bits) and values are written out.  In the same launch an
+//               extra first workgroup writes the blend order (longest list
+//               first), and the last workgroups (one per 1025 pairs of
+//               capacity, at most one per tile) sort the runs of more than
+//               1024 pairs: stable passes over global memory on depth, the
+//               same equal-depth fix, or the full (depth, index) sort
 // The output -- keys, values, ranges, `first`, pair count, status and tile
 // order -- is exactly that of the emission + stable sort of the whole key
-// (tile, then depth; equal keys in emission, i.e. index, order).
+// (global tile, then depth; equal keys in emission, i.e. slot, order).
 #include <algorithm>
 #include <cstring>
 
@@ -49,8 +53,8 @@ namespace {
 constexpr int kDThreads = 1024;
 constexpr int kDWaves = kDThreads / kWave;
 constexpr int kDPer = 4;            // consecutive Gaussians per thread and round
-constexpr int kDMaxBlocks = 256;    // rows of the count matrix (at most one per CU)
-constexpr int64_t kDMinChunk = 2048;  // fewest Gaussians per block
+constexpr int kDMaxBlocks = 256;    // blocks (count-matrix rows) per view: one per CU
+constexpr int64_t kDMinChunk = 2048;  // fewest slots per block
 constexpr int kDRadix = 256;
 constexpr int kDSortWaves = 4;
 constexpr int kDSortCap = 1024;     // longest run sorted in LDS
