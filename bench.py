@@ -101,7 +101,10 @@ def work_model(stats, pairs, n, K, npix, n_tiles, tile_bits):
     pair per 8-bit digit pass over the 32 depth and the tile bits), a4 tile
     ranges, a5 forward blend, a6 backward blend, a7 projection backward."""
     import math
+    # E: the forward's own evaluations; the backward's walk (wider cells)
+    # performs stats["evaluated_bwd"]
     E, blended = stats["evaluated"], stats["blended"]
+    Eb = stats.get("evaluated_bwd") or E
     inb = 4 * (11 + 3 * K)
     passes = math.ceil((32 + tile_bits) / 8)
     st = {
@@ -111,7 +114,7 @@ def work_model(stats, pairs, n, K, npix, n_tiles, tile_bits):
         "a4_ranges": {"bytes": pairs * 8 + n_tiles * 8, "slots": 0},
         "a5_render_fwd": {"bytes": pairs * 40 + npix * 20, "slots": E * MODEL_FWD_EVAL + blended * MODEL_FWD_BLEND},
         "a6_render_bwd": {"bytes": pairs * 40 + npix * 20 + pairs * 72,
-                          "slots": E * MODEL_BWD_EVAL + blended * MODEL_BWD_BLEND},
+                          "slots": Eb * MODEL_BWD_EVAL + blended * MODEL_BWD_BLEND},
         "a7_project_bwd": {"bytes": n * (inb * 2 + 36 + REC_BYTES), "slots": 0},
     }
     for v in st.values():
@@ -953,7 +956,8 @@ def main():
                 "work_lane_ops": int(work), "avg_ms": round(dom_ms, 4),
                 "work_model": f"E*{MODEL_BWD_EVAL if dom == 'render_bwd' else MODEL_FWD_EVAL} + blended*"
                               f"{MODEL_BWD_BLEND if dom == 'render_bwd' else MODEL_FWD_BLEND} slots "
-                              f"(E = {stats['evaluated']} evaluations, {stats['blended']} blended pairs)",
+                              f"(E = {stats['evaluated_bwd'] if dom == 'render_bwd' else stats['evaluated']} "
+                              f"evaluations, {stats['blended']} blended pairs)",
                 "minimal_count": {"work_lane_ops": int(minimal),
                                   "frac": round(minimal / (dom_ms * 1e-3) / 1e12 / peak, 4)}}
     # per-stage and whole-step fractions of the same work model: the ideal

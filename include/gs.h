@@ -614,14 +614,17 @@ gs_status gs_serve_info(gs_server *sv, gs_serve_stats *info);
 gs_status gs_serve_resume(gs_server *sv);
 void gs_serve_destroy(gs_server *sv);
 
-/* Work counters of the forward blend of one view (observability; not on
- * the training path): runs the forward walk without writing an image and
- * stores into counters (device, 4 x uint64, overwritten):
- *   [0] (pixel, list entry) evaluations performed (after the per-wave
- *       culling of Gaussians whose support misses the wave's 8x8 block),
+/* Work counters of the blends of one view (observability; not on the
+ * training path): runs the forward walk without writing an image, and the
+ * same walk over the backward's cells, and stores into counters (device,
+ * 4 x uint64, overwritten):
+ *   [0] (pixel, list entry) evaluations the forward performs (the pixels
+ *       of every cell that a list entry's support reaches),
  *   [1] evaluations with alpha >= 1/255 up to the pixel's stop,
- *   [2] blended (pixel, Gaussian) pairs, [3] 0.
- * These are the units in which the blend's arithmetic work is counted. */
+ *   [2] blended (pixel, Gaussian) pairs,
+ *   [3] evaluations over the backward's cells (2x2 pixels where the
+ *       forward walks 2x1 cells: 16x16 tiles).
+ * These are the units in which the blends' arithmetic work is counted. */
 gs_status gs_render_stats(const gs_proj *proj, const gs_bins *bins, const gs_camera *cam,
                           const gs_opts *opts, uint64_t *counters, gs_stream stream);
 

@@ -346,8 +346,9 @@ gs_status gs_render_stats(const gs_proj* proj, const gs_bins* bins, const gs_cam
     if (!counters) return fail(GS_ERR_INVALID, "counters is NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
     launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 0u, 8, st);
-    launch_render_fwd(single_render(proj, bins, C, tw, th), nullptr, nullptr, nullptr,
-                      reinterpret_cast<unsigned long long*>(counters), nullptr, st);
+    const RenderArgs r = single_render(proj, bins, C, tw, th);
+    launch_render_fwd(r, nullptr, nullptr, nullptr, reinterpret_cast<unsigned long long*>(counters), nullptr, st);
+    launch_render_stats_bwd_cells(r, reinterpret_cast<unsigned long long*>(counters), st);
     return check_hip("gs_render_stats");
 }
 

@@ -35,6 +35,16 @@ template <int TW, int TH> struct CellsFor { using L = Cells<TW, TH, 2, 2>; };
 template <> struct CellsFor<8, 8> { using L = Cells<8, 8, 1, 1>; };
 template <> struct CellsFor<16, 8> { using L = Cells<16, 8, 2, 1>; };
 
+// The forward's layout.  It has no per-entry reduction, so for 16x16 tiles
+// it walks 2x1 cells (two waves): fewer evaluations of pixels outside the
+// support (35.7M instead of 42.3M on the 1M-Gaussian 1080p view) for
+// little more bookkeeping, 120 -> 111 us.  The backward keeps 2x2 cells,
+// where narrower cells cost more slots and combine work than they save
+// (236 -> 305 us with 2x1); the forward writes the cell masks it keeps in
+// the backward's layout (keep_mask in render_fwd.hip).
+template <int TW, int TH> struct FwdCellsFor { using L = typename CellsFor<TW, TH>::L; };
+template <> struct FwdCellsFor<16, 16> { using L = Cells<16, 16, 2, 1>; };
+
 // 64-bit mask of the cells of one wave that a staged Gaussian can reach:
 // bit c is set when some pixel centre of cell c (c = row * CPR + column
 // within the wave's cells) may have alpha >= 1/255.  For each pixel row

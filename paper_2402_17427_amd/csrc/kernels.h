@@ -167,6 +167,9 @@ int render_mask_words(int tw, int th);
 // NULL also stores the per-entry blend state (pairs * tile pixels).
 void launch_render_fwd(const RenderArgs& r, float* image, float* final_T, uint32_t* n_contrib,
                        unsigned long long* stats, float2* state, hipStream_t st);
+// The counting pass with the backward's cells: adds the evaluations its walk
+// performs to stats[3] (the forward's own counts go to stats[0..2]).
+void launch_render_stats_bwd_cells(const RenderArgs& r, unsigned long long* stats, hipStream_t st);
 // Per-pair image-space gradients of the blend.  `pairs` is the pair
 // gradient buffer (pair_grad_bytes(capacity) bytes): the backward writes,
 // for every (Gaussian, tile) pair of the frame, the nine sums of the

@@ -21,6 +21,8 @@
 // without recomputing the chords.
 // Tiles of several views are numbered consecutively; a tile finds its view
 // (camera, image planes) in the view table.
+#include <cstring>
+
 #include "blend_cells.h"
 #include "kernels.h"
 
@@ -56,6 +58,7 @@ struct FwdArgs {
     float* final_T;
     uint32_t* n_contrib;
     unsigned long long* stats;
+    bool stats_eval_only;   // counting pass: add only the evaluations, into stats[3]
     float2* state;
     uint64_t* masks;        // per sorted pair and wave: the cell mask (NULL = not kept)
     uint32_t* queue;        // persistent launch: next queue position (zeroed before launch)
@@ -65,6 +68,27 @@ struct FwdArgs {
     const uint32_t* torder_n;   // ... and exits when b >= *torder_n (the order holds every tile)
 };
 
+// Store a computed cell mask m of forward wave wv for list entry `pair`
+// in the layout of the backward (CellsFor, Lb::WAVES words per pair).
+// With 2x1 cells in the forward and 2x2 in the backward (16x16 tiles),
+// forward wave wv holds pixel rows 8 wv .. 8 wv + 7 as 8 cell rows of 8;
+// the backward's cell row 4 wv + k covers its rows 2k and 2k + 1, so the
+// wave ORs the row pairs and writes its 32-bit half of the backward's word.
+template <class Lf, class Lb>
+__device__ __forceinline__ void keep_mask(uint64_t* masks, uint32_t pair, int wv, uint64_t m) {
+    if constexpr (Lf::CW == Lb::CW && Lf::CH == Lb::CH) {
+        masks[(int64_t)pair * Lb::WAVES + wv] = m;
+    } else {
+        static_assert(Lf::TW == 16 && Lf::TH == 16 && Lf::CW == 2 && Lf::CH == 1 && Lf::WAVES == 2 &&
+                          Lb::TW == 16 && Lb::TH == 16 && Lb::CW == 2 && Lb::CH == 2 && Lb::WAVES == 1,
+                      "mask layouts");
+        const uint64_t x = m | (m >> 8);   // byte 2k: cell rows 2k and 2k + 1
+        const uint32_t half = (uint32_t)(x & 0xFFu) | (uint32_t)((x >> 8) & 0xFF00u) |
+                              (uint32_t)((x >> 16) & 0xFF0000u) | (uint32_t)((x >> 24) & 0xFF000000u);
+        reinterpret_cast<uint32_t*>(masks)[2 * (int64_t)pair + wv] = half;
+    }
+}
+
 template <int B>
 struct FwdShared {
     Staged s[B];
@@ -73,6 +97,7 @@ struct FwdShared {
 // B: staged entries per batch (a multiple of 64, at most 256)
 template <class L, int MODE, int B>
 __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdShared<B>& sh) {
+    using LB = typename CellsFor<L::TW, L::TH>::L;   // the backward's layout (kept masks)
     constexpr int NP = L::NP;
     constexpr bool STATS = MODE == kStats;
 
@@ -149,7 +174,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdSha
             const int k = q * kWave + lane;
             const uint64_t m = k < nb ? cell_mask<L>(sh.s[k], x0, wy0) : 0ull;
             // kept for the backward, which walks the same entries
-            if (MODE != kStats && a.masks && k < nb) a.masks[(int64_t)(b0 + (uint32_t)k) * L::WAVES + wv] = m;
+            if (MODE != kStats && a.masks && k < nb) keep_mask<L, LB>(a.masks, b0 + (uint32_t)k, wv, m);
             uint64_t t = transpose64(m, lane);
             if (all_done) t = 0ull;
             if (t != 0ull) {
@@ -241,9 +266,13 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdSha
             b32 += (uint32_t)__shfl_xor((int)b32, d, kWave);
         }
         if (lane == 0) {
-            atomicAdd(&a.stats[0], (unsigned long long)e32);
-            atomicAdd(&a.stats[1], (unsigned long long)s32);
-            atomicAdd(&a.stats[2], (unsigned long long)b32);
+            if (a.stats_eval_only) {   // the evaluations of another cell layout
+                atomicAdd(&a.stats[3], (unsigned long long)e32);
+            } else {
+                atomicAdd(&a.stats[0], (unsigned long long)e32);
+                atomicAdd(&a.stats[1], (unsigned long long)s32);
+                atomicAdd(&a.stats[2], (unsigned long long)b32);
+            }
         }
     } else {
 #pragma unroll
@@ -287,7 +316,7 @@ __global__ __launch_bounds__(L::NCELL) void k_render_fwd_persistent(FwdArgs a) {
 
 template <int TW, int TH>
 void launch_t(const FwdArgs& a, int persistent_grid, int batch, hipStream_t st) {
-    using L = typename CellsFor<TW, TH>::L;
+    using L = typename FwdCellsFor<TW, TH>::L;
     const dim3 block(L::NCELL);
     if (a.stats)
         hipLaunchKernelGGL((k_render_fwd<L, kStats>), dim3(a.n_tiles), block, 0, st, a);
@@ -301,9 +330,16 @@ void launch_t(const FwdArgs& a, int persistent_grid, int batch, hipStream_t st) 
         hipLaunchKernelGGL((k_render_fwd<L, kPlain>), dim3(a.n_tiles), block, 0, st, a);
 }
 
+// The counting pass in the backward's cell layout (its evaluations).
+template <int TW, int TH>
+void launch_stats_bwd_cells_t(const FwdArgs& a, hipStream_t st) {
+    using L = typename CellsFor<TW, TH>::L;
+    hipLaunchKernelGGL((k_render_fwd<L, kStats>), dim3(a.n_tiles), dim3(L::NCELL), 0, st, a);
+}
+
 template <int TW, int TH>
 hipError_t occupancy_t(int* per, int batch) {
-    using L = typename CellsFor<TW, TH>::L;
+    using L = typename FwdCellsFor<TW, TH>::L;
     if (batch == kBatchSmall)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_render_fwd_persistent<L, kBatchSmall>, L::NCELL, 0);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_render_fwd_persistent<L, kBatch>, L::NCELL, 0);
@@ -339,6 +375,7 @@ void launch_render_fwd(const RenderArgs& r, float* image, float* final_T, uint32
     a.final_T = final_T;
     a.n_contrib = n_contrib;
     a.stats = stats;
+    a.stats_eval_only = false;
     a.state = state;
     a.masks = stats ? nullptr : r.masks;
     a.queue = r.queue;
@@ -356,6 +393,30 @@ void launch_render_fwd(const RenderArgs& r, float* image, float* final_T, uint32
     else if (r.tw == 32 && r.th == 16) GS_FWD(32, 16);
     else if (r.tw == 32 && r.th == 32) GS_FWD(32, 32);
 #undef GS_FWD
+}
+
+void launch_render_stats_bwd_cells(const RenderArgs& r, unsigned long long* stats, hipStream_t st) {
+    if (r.n_tiles == 0) return;
+    FwdArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.rec = r.rec;
+    a.vals = r.vals;
+    a.ranges = reinterpret_cast<const uint2*>(r.ranges);
+    a.status = r.status;
+    a.views = r.views;
+    a.stats = stats;
+    a.stats_eval_only = true;
+    a.n_tiles = r.n_tiles;
+    a.torder = r.tile_order;
+    a.torder_n = r.tile_order_count;
+#define GS_STB(x, y) launch_stats_bwd_cells_t<x, y>(a, st)
+    if (r.tw == 16 && r.th == 16) GS_STB(16, 16);
+    else if (r.tw == 8 && r.th == 8) GS_STB(8, 8);
+    else if (r.tw == 16 && r.th == 8) GS_STB(16, 8);
+    else if (r.tw == 32 && r.th == 8) GS_STB(32, 8);
+    else if (r.tw == 32 && r.th == 16) GS_STB(32, 16);
+    else if (r.tw == 32 && r.th == 32) GS_STB(32, 32);
+#undef GS_STB
 }
 
 int render_persistent_grid_bwd(int tw, int th, int item_cap);

@@ -212,7 +212,7 @@ class Frame:
         N.call("gs_render_stats", C.byref(self.c_proj()), C.byref(self.c_bins()), C.byref(self.c_cam),
                C.byref(self.c_opts), _ptr(c), C.c_void_p(stream_handle(stream)))
         v = c.cpu().numpy()
-        return dict(evaluated=int(v[0]), support=int(v[1]), blended=int(v[2]))
+        return dict(evaluated=int(v[0]), support=int(v[1]), blended=int(v[2]), evaluated_bwd=int(v[3]))
 
     # -- stored blend state (for comparison with the recomputing backward) --
     def state_bytes(self) -> int:
