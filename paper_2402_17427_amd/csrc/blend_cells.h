@@ -35,13 +35,16 @@ template <int TW, int TH> struct CellsFor { using L = Cells<TW, TH, 2, 2>; };
 template <> struct CellsFor<8, 8> { using L = Cells<8, 8, 1, 1>; };
 template <> struct CellsFor<16, 8> { using L = Cells<16, 8, 2, 1>; };
 
-// The forward's layout.  It has no per-entry reduction, so for 16x16 tiles
-// it walks 2x1 cells (two waves): fewer evaluations of pixels outside the
-// support (35.7M instead of 42.3M on the 1M-Gaussian 1080p view) for
-// little more bookkeeping, 120 -> 111 us.  The backward keeps 2x2 cells,
-// where narrower cells cost more slots and combine work than they save
-// (236 -> 305 us with 2x1); the forward writes the cell masks it keeps in
-// the backward's layout (keep_mask in render_fwd.hip).
+// The forward's layout.  It has no per-entry reduction, so on 16x16 tiles
+// it walks 2x1 cells (two waves) where the backward walks 2x2: fewer
+// evaluations of pixels outside the support (35.7M instead of 42.3M on the
+// 1M-Gaussian 1080p view) for little more bookkeeping, 120 -> 112 us.  The
+// backward keeps 2x2 cells, where narrower cells cost more slots and
+// combine work than they save (236 -> 305 us with 2x1); the forward writes
+// the cell masks it keeps in the backward's layout (keep_mask in
+// render_fwd.hip).  On 32-wide tiles (four waves and more with 2x1 cells)
+// the narrower forward measured no faster (batched cells at 32x16: 5.03 ->
+// 5.11 ms), so they keep one layout.
 template <int TW, int TH> struct FwdCellsFor { using L = typename CellsFor<TW, TH>::L; };
 template <> struct FwdCellsFor<16, 16> { using L = Cells<16, 16, 2, 1>; };
 

@@ -70,22 +70,28 @@ struct FwdArgs {
 
 // Store a computed cell mask m of forward wave wv for list entry `pair`
 // in the layout of the backward (CellsFor, Lb::WAVES words per pair).
-// With 2x1 cells in the forward and 2x2 in the backward (16x16 tiles),
-// forward wave wv holds pixel rows 8 wv .. 8 wv + 7 as 8 cell rows of 8;
-// the backward's cell row 4 wv + k covers its rows 2k and 2k + 1, so the
-// wave ORs the row pairs and writes its 32-bit half of the backward's word.
+// With 2x1 cells in the forward and 2x2 in the backward, a forward wave
+// holds 64 / CPR pixel rows as cell rows of CPR bits and a backward wave
+// twice as many pixel rows: backward cell row k of forward wave wv's share
+// covers its cell rows 2k and 2k + 1, so the wave ORs the row pairs and
+// writes them as half (wv mod 2) of the backward word of wave wv / 2.
 template <class Lf, class Lb>
 __device__ __forceinline__ void keep_mask(uint64_t* masks, uint32_t pair, int wv, uint64_t m) {
     if constexpr (Lf::CW == Lb::CW && Lf::CH == Lb::CH) {
         masks[(int64_t)pair * Lb::WAVES + wv] = m;
     } else {
-        static_assert(Lf::TW == 16 && Lf::TH == 16 && Lf::CW == 2 && Lf::CH == 1 && Lf::WAVES == 2 &&
-                          Lb::TW == 16 && Lb::TH == 16 && Lb::CW == 2 && Lb::CH == 2 && Lb::WAVES == 1,
+        static_assert(Lf::TW == Lb::TW && Lf::TH == Lb::TH && Lf::CW == 2 && Lf::CH == 1 && Lb::CW == 2 &&
+                          Lb::CH == 2 && Lf::WAVES == 2 * Lb::WAVES && (Lf::CPR == 8 || Lf::CPR == 16),
                       "mask layouts");
-        const uint64_t x = m | (m >> 8);   // byte 2k: cell rows 2k and 2k + 1
-        const uint32_t half = (uint32_t)(x & 0xFFu) | (uint32_t)((x >> 8) & 0xFF00u) |
-                              (uint32_t)((x >> 16) & 0xFF0000u) | (uint32_t)((x >> 24) & 0xFF000000u);
-        reinterpret_cast<uint32_t*>(masks)[2 * (int64_t)pair + wv] = half;
+        constexpr int C = Lf::CPR;
+        const uint64_t x = m | (m >> C);   // cell row 2k: rows 2k and 2k + 1
+        uint32_t half;
+        if constexpr (C == 8)
+            half = (uint32_t)(x & 0xFFu) | (uint32_t)((x >> 8) & 0xFF00u) | (uint32_t)((x >> 16) & 0xFF0000u) |
+                   (uint32_t)((x >> 24) & 0xFF000000u);
+        else
+            half = (uint32_t)(x & 0xFFFFu) | (uint32_t)((x >> 16) & 0xFFFF0000u);
+        reinterpret_cast<uint32_t*>(masks)[2 * ((int64_t)pair * Lb::WAVES + wv / 2) + (wv & 1)] = half;
     }
 }
 
