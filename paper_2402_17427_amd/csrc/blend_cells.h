@@ -142,6 +142,27 @@ __device__ __forceinline__ const Staged& staged_at(const Staged* s, int k) {
     return *reinterpret_cast<const Staged*>(reinterpret_cast<const char*>(s) + ((unsigned)k & 0x3FFu) * 48u);
 }
 
+// Staged records as three arrays (the forward's batches): entry k's
+// values sit at 16 k in each, so its address is a shift where the 48-byte
+// records of an array of Staged take a multiply (a quarter-rate 32-bit one
+// where the compiler cannot bound k).
+template <int B>
+struct StagedSoA {
+    float4 geo[B], coef[B], col[B];
+    __device__ __forceinline__ void put(int j, const Staged& g) {
+        geo[j] = g.geo;
+        coef[j] = g.coef;
+        col[j] = g.col;
+    }
+    __device__ __forceinline__ Staged get(int k) const {
+        Staged g;
+        g.geo = geo[k];
+        g.coef = coef[k];
+        g.col = col[k];
+        return g;
+    }
+};
+
 // Stage list entries b0 + j (j < nb <= PER * nthreads) of a tile into
 // LDS: each thread issues all of its value loads, then all of its record
 // loads, before the first wait, so a batch costs two memory latencies.
@@ -165,6 +186,28 @@ __device__ __forceinline__ void stage_batch(Staged* s, const Rec* __restrict__ r
             s[j] = stage_rec(r[q]);
             if (gid_out) gid_out[j] = v[q];
         }
+    }
+}
+
+// The same into three arrays.
+template <int PER, int B>
+__device__ __forceinline__ void stage_batch(StagedSoA<B>& s, const Rec* __restrict__ rec,
+                                            const uint32_t* __restrict__ vals, uint32_t b0, int nb, int tid,
+                                            int nthreads) {
+    uint32_t v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = tid + q * nthreads;
+        v[q] = j < nb ? vals[b0 + (uint32_t)j] : 0u;
+    }
+    Rec r[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+        if (tid + q * nthreads < nb) r[q] = rec[v[q]];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = tid + q * nthreads;
+        if (j < nb) s.put(j, stage_rec(r[q]));
     }
 }
 

@@ -97,7 +97,7 @@ __device__ __forceinline__ void keep_mask(uint64_t* masks, uint32_t pair, int wv
 
 template <int B>
 struct FwdShared {
-    Staged s[B];
+    StagedSoA<B> s;
 };
 
 // B: staged entries per batch (a multiple of 64, at most 256)
@@ -178,7 +178,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdSha
         for (int q = 0; q < B / kWave; ++q) {
             if (q * kWave >= nb) break;
             const int k = q * kWave + lane;
-            const uint64_t m = k < nb ? cell_mask<L>(sh.s[k], x0, wy0) : 0ull;
+            const uint64_t m = k < nb ? cell_mask<L>(sh.s.get(k), x0, wy0) : 0ull;
             // kept for the backward, which walks the same entries
             if (MODE != kStats && a.masks && k < nb) keep_mask<L, LB>(a.masks, b0 + (uint32_t)k, wv, m);
             uint64_t t = transpose64(m, lane);
@@ -200,7 +200,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdSha
             const bool has = w0 != 0ull;
             const int kk = has ? q0 + low_bit(w0) : 0;
             w0 &= w0 - 1ull;
-            const Staged g = staged_at(sh.s, kk);
+            const Staged g = sh.s.get(kk);
             // offsets of the lane's pixel columns and rows, then each pixel's
             // base-2 exponent (a function of the pixel and the Gaussian only)
             float dys[L::CH], qa[L::CW], qb[L::CW], qc[L::CH];
