@@ -14,11 +14,12 @@
 //               [blocks][tiles], and its pair total
 //   k_dscan     per strip of 64 tiles of a view: exclusive scan down the
 //               view's matrix columns (where each block's share of a tile's
-//               run starts inside the run) and the tile totals; one more
+//               run starts inside the run), the tile totals, each tile's
+//               prefix within the strip and the strip's sum; one more
 //               workgroup scans the block totals of all views (each block's
 //               first emission position) and stores the grand total
 //   k_dscatter  per block: the starts of its view's tiles (every workgroup
-//               scans its view's tile totals itself; the view's first also
+//               scans its view's strip sums itself; the view's first also
 //               writes the view's ranges, workgroup 0 the pair count and
 //               capacity status), every slot's emission position (`first`,
 //               the exclusive prefix of the tile counts), and each pair
@@ -200,7 +201,8 @@ __device__ __forceinline__ int xcd_major_block(int r, int nb) {
 // block's first emission position) and stores the grand total after them.
 template <bool MULTI>
 __global__ __launch_bounds__(kDThreads) void k_dscan(DTab views, int strips, int nb_all, uint32_t* __restrict__ M,
-                                                     uint32_t* __restrict__ ttot, uint64_t* __restrict__ bsum) {
+                                                     uint32_t* __restrict__ ttot, uint32_t* __restrict__ tex,
+                                                     uint32_t* __restrict__ stot, uint64_t* __restrict__ bsum) {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     if ((int)blockIdx.x == strips) {
         uint64_t carry = 0;
@@ -248,20 +250,38 @@ __global__ __launch_bounds__(kDThreads) void k_dscan(DTab views, int strips, int
         if (r < nb && t < n_tiles) M[V.m0 + (int64_t)s_row[r] * n_tiles + t] = run;
         run += v[k];
     }
-    if (wv == 0 && t < n_tiles) ttot[V.tile_base + t] = tot;
+    if (wv == 0) {
+        // the strip's tile totals: each tile's exclusive prefix within the
+        // strip, and the strip's sum (so that a tile's start is its strip's
+        // start plus this prefix)
+        const uint32_t c = t < n_tiles ? tot : 0u;
+        uint32_t x = c;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)x, d, kWave);
+            if (lane >= d) x += y;
+        }
+        if (t < n_tiles) {
+            ttot[V.tile_base + t] = c;
+            tex[V.tile_base + t] = x - c;
+        }
+        if (lane == kWave - 1) stot[blockIdx.x] = x;
+    }
 }
 
 // Every workgroup first forms the starts of its view's tiles itself: the
-// view's first pair (the exclusive block prefix at its first block) plus
-// the exclusive prefix of the view's tile totals, scanned in LDS; the grand
-// total after the block totals decides the capacity.  The view's first
-// workgroup writes the view's ranges, workgroup 0 the pair count and
-// status.
+// view's first pair (the exclusive block prefix at its first block), plus
+// the exclusive prefix of the view's strip sums (one workgroup scan), plus
+// the tile's prefix within its strip; the grand total after the block
+// totals decides the capacity.  The view's first workgroup writes the
+// view's ranges, workgroup 0 the pair count and status.
 template <bool MULTI>
 __global__ __launch_bounds__(kDThreads) void k_dscatter(DTab views, const ushort4* __restrict__ rect,
                                                         const float* __restrict__ depth,
                                                         const uint32_t* __restrict__ M,
-                                                        const uint32_t* __restrict__ ttot, int nb_all,
+                                                        const uint32_t* __restrict__ ttot,
+                                                        const uint32_t* __restrict__ tex,
+                                                        const uint32_t* __restrict__ stot, int nb_all,
                                                         int64_t capacity, const uint64_t* __restrict__ bsum,
                                                         uint32_t* __restrict__ ranges,
                                                         uint32_t* __restrict__ pair_count,
@@ -276,37 +296,27 @@ __global__ __launch_bounds__(kDThreads) void k_dscatter(DTab views, const ushort
     const int ntx = V.ntx, nty = V.nty;
     const uint64_t total = bsum[nb_all];
     const bool over = total > (uint64_t)capacity;
-    // the view's tile totals into LDS (four loads in flight per thread),
-    // then their exclusive prefix in place, 1024 tiles per workgroup scan
-    for (uint32_t t0 = 0; t0 < n_tiles; t0 += 4 * kDThreads) {
-        uint32_t c4[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t t = t0 + (uint32_t)(k * kDThreads + tid);
-            c4[k] = t < n_tiles ? ttot[V.tile_base + t] : 0u;
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t t = t0 + (uint32_t)(k * kDThreads + tid);
-            if (t < n_tiles) s_cur[t] = c4[k];
-        }
+    // the tile starts: the view's first pair, plus its strips' exclusive
+    // prefix (one workgroup scan over at most 512 strip sums), plus each
+    // tile's prefix within its strip
+    __shared__ uint32_t s_sp[kDirectMaxTiles / kWave];
+    const int nstr = (int)((n_tiles + kWave - 1) / kWave);
+    {
+        const uint32_t v = tid < nstr ? stot[V.c0 + tid] : 0u;
+        uint64_t tot;
+        const uint64_t ex = bsum[V.b0] + block_scan_ex<kDThreads>(v, &tot);   // after the earlier views' pairs
+        if (tid < nstr) s_sp[tid] = (uint32_t)ex;
     }
     __syncthreads();
-    uint64_t vrun = bsum[V.b0];   // pairs of the earlier views
-    for (uint32_t t0 = 0; t0 < n_tiles; t0 += kDThreads) {
-        const uint32_t t = t0 + (uint32_t)tid;
-        const uint32_t c = t < n_tiles ? s_cur[t] : 0u;
-        uint64_t tot;
-        // (the scan's barriers order every read of s_cur before the writes)
-        const uint64_t ex = vrun + block_scan_ex<kDThreads>(c, &tot);
-        vrun += tot;
-        if (t < n_tiles) {
-            s_cur[t] = (uint32_t)ex;
-            // the view's first workgroup writes its ranges; an empty tile's
-            // range is (0, 0), as a range pass over sorted keys leaves it
-            if (lb == 0)
-                reinterpret_cast<uint2*>(ranges)[V.tile_base + t] =
-                    (over || c == 0u) ? make_uint2(0u, 0u) : make_uint2((uint32_t)ex, (uint32_t)(ex + c));
+    for (uint32_t t = tid; t < n_tiles; t += kDThreads) {
+        const uint32_t st = s_sp[t >> 6] + tex[V.tile_base + t];
+        s_cur[t] = st;
+        // the view's first workgroup writes its ranges; an empty tile's
+        // range is (0, 0), as a range pass over sorted keys leaves it
+        if (lb == 0) {
+            const uint32_t c = ttot[V.tile_base + t];
+            reinterpret_cast<uint2*>(ranges)[V.tile_base + t] =
+                (over || c == 0u) ? make_uint2(0u, 0u) : make_uint2(st, st + c);
         }
     }
     if (blockIdx.x == 0 && tid == 0) {
@@ -763,7 +773,9 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Scratch {
     uint32_t* M;      // count matrix: the views' rows
-    uint32_t* ttot;   // [n_tiles]
+    uint32_t* ttot;   // [n_tiles]: pairs per tile
+    uint32_t* tex;    // [n_tiles]: a tile's exclusive prefix within its strip of 64
+    uint32_t* stot;   // [strips]: pairs per strip
     uint64_t* bsum;   // [nb + 1]: block totals, then their exclusive prefix and the grand total
 };
 
@@ -774,6 +786,10 @@ Scratch carve_scratch(void* ws, const DPlan& plan) {
     p += align256((size_t)(plan.m_words > 0 ? plan.m_words : 1) * 4);
     w.ttot = reinterpret_cast<uint32_t*>(p);
     p += align256((size_t)(plan.n_tiles > 0 ? plan.n_tiles : 1) * 4);
+    w.tex = reinterpret_cast<uint32_t*>(p);
+    p += align256((size_t)(plan.n_tiles > 0 ? plan.n_tiles : 1) * 4);
+    w.stot = reinterpret_cast<uint32_t*>(p);
+    p += align256((size_t)(plan.strips > 0 ? plan.strips : 1) * 4);
     w.bsum = reinterpret_cast<uint64_t*>(p);
     return w;
 }
@@ -826,7 +842,8 @@ bool bin_direct_plan(int nv, const int64_t* s0, const int64_t* s1, const int* nt
 
 size_t bin_direct_scratch_bytes(const DPlan& plan) {
     return align256((size_t)(plan.m_words > 0 ? plan.m_words : 1) * 4) +
-           align256((size_t)(plan.n_tiles > 0 ? plan.n_tiles : 1) * 4) + align256((size_t)(plan.nb + 1) * 8);
+           2 * align256((size_t)(plan.n_tiles > 0 ? plan.n_tiles : 1) * 4) +
+           align256((size_t)(plan.strips > 0 ? plan.strips : 1) * 4) + align256((size_t)(plan.nb + 1) * 8);
 }
 
 void launch_bin_direct_place(const DPlan& plan, const DTab& views, const ushort4* rect, const float* depth,
@@ -843,17 +860,18 @@ void launch_bin_direct_place(const DPlan& plan, const DTab& views, const ushort4
         hipLaunchKernelGGL(k_dcount<true>, dim3((unsigned)plan.nb), dim3(kDThreads), lds, st, views, rect, w.M,
                            w.bsum);
         hipLaunchKernelGGL(k_dscan<true>, dim3((unsigned)plan.strips + 1), dim3(kDThreads), 0, st, views,
-                           plan.strips, plan.nb, w.M, w.ttot, w.bsum);
+                           plan.strips, plan.nb, w.M, w.ttot, w.tex, w.stot, w.bsum);
         hipLaunchKernelGGL(k_dscatter<true>, dim3((unsigned)plan.nb), dim3(kDThreads), lds, st, views, rect, depth,
-                           w.M, w.ttot, plan.nb, capacity, w.bsum, ranges, pair_count, status, first, pairs, vec);
+                           w.M, w.ttot, w.tex, w.stot, plan.nb, capacity, w.bsum, ranges, pair_count, status, first,
+                           pairs, vec);
     } else {
         hipLaunchKernelGGL(k_dcount<false>, dim3((unsigned)plan.nb), dim3(kDThreads), lds, st, views, rect, w.M,
                            w.bsum);
         hipLaunchKernelGGL(k_dscan<false>, dim3((unsigned)plan.strips + 1), dim3(kDThreads), 0, st, views,
-                           plan.strips, plan.nb, w.M, w.ttot, w.bsum);
+                           plan.strips, plan.nb, w.M, w.ttot, w.tex, w.stot, w.bsum);
         hipLaunchKernelGGL(k_dscatter<false>, dim3((unsigned)plan.nb), dim3(kDThreads), lds, st, views, rect,
-                           depth, w.M, w.ttot, plan.nb, capacity, w.bsum, ranges, pair_count, status, first, pairs,
-                           vec);
+                           depth, w.M, w.ttot, w.tex, w.stot, plan.nb, capacity, w.bsum, ranges, pair_count, status,
+                           first, pairs, vec);
     }
 }
 
