@@ -147,15 +147,33 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
     int hi = (int)min(sh.max_last, rg.y - rg.x);
     const int hi0 = hi;
 
+    // The chunk's candidate values (thread tid < ncand) and this wave's
+    // cell masks of them (lane < ncand): loaded here for the first chunk and
+    // during the walk of the one before for each later one, so that they
+    // are in flight meanwhile, like each chunk's rectangles and first pairs
+    // (loaded before its walk, read by its combine).  The loads take
+    // clamped indices, not conditions, so the values arrive straight in the
+    // registers that read them, with no copy that would wait for them.
+    // The records of the values are loaded after each walk, before the
+    // combine, whose stores the next chunk's staging then need not wait for.
+    uint32_t vk = 0u;
+    uint64_t mk = 0ull;
+    Rec rk = {};
+    if (hi > 0) {
+        const int lo0 = hi > kChunk ? hi - kChunk : 0;
+        const int last = hi - lo0 - 1;
+        vk = a.vals[rg.x + (uint32_t)(lo0 + min(tid, last))];
+        if (a.masks) mk = a.masks[(int64_t)(rg.x + (uint32_t)(lo0 + min(lane, last))) * L::WAVES + wv];
+        rk = a.rec[vk];
+    }
     while (hi > 0) {
         const int lo0 = hi > kChunk ? hi - kChunk : 0;
         const int ncand = hi - lo0;
-        // the forward's mask of candidate `lane` for this wave, loaded
-        // while the entries are staged
-        uint64_t mk = 0ull;
-        if (a.masks && lane < ncand) mk = a.masks[(int64_t)(rg.x + (uint32_t)(lo0 + lane)) * L::WAVES + wv];
         __syncthreads();   // the previous chunk's slots and staged entries are no longer read
-        stage_batch<1>(sh.s, a.rec, a.vals, rg.x + (uint32_t)lo0, ncand, tid, L::NCELL, sh.gid);
+        if (tid < ncand) {
+            sh.s[tid] = stage_rec(rk);
+            sh.gid[tid] = vk;
+        }
         __syncthreads();
 
         // entry-major cell masks of this wave, transposed into the lane's
@@ -198,6 +216,16 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
         }
         __syncthreads();
         const int kmin = sh.kmin;
+        const uint32_t pgid = sh.gid[min(tid, ncand - 1)];
+        const uint2 prc = reinterpret_cast<const uint2*>(a.rect)[pgid];
+        const uint32_t pfst = a.first[pgid];
+        {   // the next chunk's candidates
+            const int nhi = lo0 + kmin;
+            const int nlo = nhi > kChunk ? nhi - kChunk : 0;
+            const int nlast = max(nhi - nlo - 1, 0);
+            vk = a.vals[rg.x + (uint32_t)(nlo + min(tid, nlast))];
+            if (a.masks) mk = a.masks[(int64_t)(rg.x + (uint32_t)(nlo + min(lane, nlast))) * L::WAVES + wv];
+        }
 
         // walk: entries kmin .. ncand - 1 of the lane's word, from the back.
         // The next entry's staged values and slot base are read from LDS
@@ -347,6 +375,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
                 if (__ballot(wk != 0ull) == 0ull) break;
             }
         }
+        rk = a.rec[vk];
         __syncthreads();
 
         // the accumulated sums of dpow dx, dpow dy, dpow dx^2, dpow dx dy,
@@ -367,10 +396,8 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
                 for (int c = 0; c < 9; ++c) m[c] += sh.item[c][e];
             }
             {   // every entry's pair slot is written, zero sums included
-                const uint32_t gid = sh.gid[tid];
-                const ushort4 r = a.rect[gid];
-                const int64_t p = (int64_t)a.first[gid] + (int64_t)(ty - (int)r.y) * ((int)r.z - (int)r.x) +
-                                  (tx - (int)r.x);
+                const int rx = (int)(prc.x & 0xFFFFu), ry = (int)(prc.x >> 16), rz = (int)(prc.y & 0xFFFFu);
+                const int64_t p = (int64_t)pfst + (int64_t)(ty - ry) * (rz - rx) + (tx - rx);
                 if (p >= 0 && p < a.cap) {
                     const float4 cf = sh.s[tid].coef;
                     const float A = -2.0f * cf.x * (1.0f / kLog2e), Bc = -cf.y * (1.0f / kLog2e),
