@@ -159,6 +159,13 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
     uint32_t vk = 0u;
     uint64_t mk = 0ull;
     Rec rk = {};
+    // Each chunk's pair-slot stores are issued after the next chunk has
+    // taken its staged records and masks: loads and stores share one
+    // counter here, so a wait for those loads behind the stores would
+    // also wait for the stores to complete.  ds < 0: nothing pending.
+    float4 d0 = make_float4(0.f, 0.f, 0.f, 0.f), d1 = d0;
+    float d2 = 0.f;
+    int64_t ds = -1;
     if (hi > 0) {
         const int lo0 = hi > kChunk ? hi - kChunk : 0;
         const int last = hi - lo0 - 1;
@@ -179,6 +186,12 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
         // entry-major cell masks of this wave, transposed into the lane's
         // walk word, cut at the cell's last contributor, and back
         const uint64_t m = lane < ncand ? (a.masks ? mk : cell_mask<L>(sh.s[lane], x0, wy0)) : 0ull;
+        if (ds >= 0) {   // the previous chunk's pair slot
+            a.pg8[2 * ds] = d0;
+            a.pg8[2 * ds + 1] = d1;
+            a.pg1[ds] = d2;
+            ds = -1;
+        }
         uint64_t walk = transpose64(m, lane);
         {
             const int lim = (int)cell_last - lo0;   // entries lo0 + k with k < lim
@@ -402,13 +415,19 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
                     const float4 cf = sh.s[tid].coef;
                     const float A = -2.0f * cf.x * (1.0f / kLog2e), Bc = -cf.y * (1.0f / kLog2e),
                                 C = -2.0f * cf.z * (1.0f / kLog2e);
-                    a.pg8[2 * p] = make_float4(A * m[0] + Bc * m[1], Bc * m[0] + C * m[1], -0.5f * m[2], -m[3]);
-                    a.pg8[2 * p + 1] = make_float4(-0.5f * m[4], m[5], m[6], m[7]);
-                    a.pg1[p] = m[8];
+                    d0 = make_float4(A * m[0] + Bc * m[1], Bc * m[0] + C * m[1], -0.5f * m[2], -m[3]);
+                    d1 = make_float4(-0.5f * m[4], m[5], m[6], m[7]);
+                    d2 = m[8];
+                    ds = p;
                 }
             }
         }
         hi = lo0 + kmin;
+    }
+    if (ds >= 0) {
+        a.pg8[2 * ds] = d0;
+        a.pg8[2 * ds + 1] = d1;
+        a.pg1[ds] = d2;
     }
     // Entries behind every pixel's last contributor were never staged:
     // their pair slots get zeros here, so that every pair of the frame is
