@@ -40,7 +40,13 @@ def test_abi_version_and_error_strings():
     nbytes = C.c_size_t(0)
     assert lib.gs_bin_sort_workspace(-1, 10, 4, C.byref(nbytes)) == N.GS_ERR_INVALID
     assert b"bad sizes" in lib.gs_last_error()
+    # up to 32768 tiles (direct placement): the 8-byte placed pairs of the
+    # capacity and at least one count-matrix row of the tiles
     assert lib.gs_bin_sort_workspace(1000, 4000, 64, C.byref(nbytes)) == N.GS_OK
+    assert nbytes.value >= 4000 * 8 + 64 * 4
+    # above (emission + radix sort): the emitted 8-byte keys and 4-byte
+    # values of the capacity
+    assert lib.gs_bin_sort_workspace(1000, 4000, 40000, C.byref(nbytes)) == N.GS_OK
     assert nbytes.value >= 4000 * 12
 
 
