@@ -252,17 +252,16 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
             // list position of the entry; past every pixel's last
             // contributor for a lane with nothing to walk
             const uint32_t pos = has ? (uint32_t)(lo0 + kk) : 0xFFFFFFFFu;
-            float dxs[L::CW], dys[L::CH], qa[L::CW], qb[L::CW], qc[L::CH];
+            // the forward's exponent: dx (ca dx + cb dy) + cc dy^2, the dy
+            // terms once per pixel row
+            float dxs[L::CW], dys[L::CH], rb[L::CH], rc[L::CH];
 #pragma unroll
-            for (int i = 0; i < L::CW; ++i) {
-                dxs[i] = (fxp[i] - g.geo.x) - g.geo.y;
-                qa[i] = (g.coef.x * dxs[i]) * dxs[i];
-                qb[i] = g.coef.y * dxs[i];
-            }
+            for (int i = 0; i < L::CW; ++i) dxs[i] = (fxp[i] - g.geo.x) - g.geo.y;
 #pragma unroll
             for (int j = 0; j < L::CH; ++j) {
                 dys[j] = (fyp[j] - g.geo.z) - g.geo.w;
-                qc[j] = (g.coef.z * dys[j]) * dys[j];
+                rb[j] = g.coef.y * dys[j];
+                rc[j] = (g.coef.z * dys[j]) * dys[j];
             }
             // the cell's sums: dL/do, dL/drgb, and dL/dpower per pixel
             float s5 = 0.f, s6 = 0.f, s7 = 0.f, s8 = 0.f, dpow[NP];
@@ -283,7 +282,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, uint32_t tile, BwdSha
                 } else {
                     // the forward's decision: alpha (capped at 0.99) counts
                     // when the exponent is not positive and alpha >= 1/255
-                    const float pw = __builtin_fmaf(qb[i], dys[j], qa[i] + qc[j]);
+                    const float pw = __builtin_fmaf(dxs[i], __builtin_fmaf(g.coef.x, dxs[i], rb[j]), rc[j]);
                     G = __builtin_amdgcn_exp2f(pw);
                     const float araw = g.coef.w * G;
                     capped = araw > kAlphaMax;

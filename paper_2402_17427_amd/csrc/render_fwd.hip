@@ -208,23 +208,22 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdSha
             const Staged g = sh.s.get(kk);
             // offsets of the lane's pixel columns and rows, then each pixel's
             // base-2 exponent (a function of the pixel and the Gaussian only)
-            float dys[L::CH], qa[L::CW], qb[L::CW], qc[L::CH];
+            // ca dx^2 + cb dx dy + cc dy^2 = dx (ca dx + cb dy) + cc dy^2,
+            // with the dy terms formed once per pixel row
+            float dxs[L::CW], rb[L::CH], rc[L::CH];
 #pragma unroll
-            for (int i = 0; i < L::CW; ++i) {
-                const float dx = (fxp[i] - g.geo.x) - g.geo.y;
-                qa[i] = (g.coef.x * dx) * dx;
-                qb[i] = g.coef.y * dx;
-            }
+            for (int i = 0; i < L::CW; ++i) dxs[i] = (fxp[i] - g.geo.x) - g.geo.y;
 #pragma unroll
             for (int j = 0; j < L::CH; ++j) {
-                dys[j] = (fyp[j] - g.geo.z) - g.geo.w;
-                qc[j] = (g.coef.z * dys[j]) * dys[j];
+                const float dy = (fyp[j] - g.geo.z) - g.geo.w;
+                rb[j] = g.coef.y * dy;
+                rc[j] = (g.coef.z * dy) * dy;
             }
             const uint32_t lastv = pos0 + (uint32_t)kk + 1u;
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const int i = p % L::CW, j = p / L::CW;
-                const float pw = __builtin_fmaf(qb[i], dys[j], qa[i] + qc[j]);
+                const float pw = __builtin_fmaf(dxs[i], __builtin_fmaf(g.coef.x, dxs[i], rb[j]), rc[j]);
                 const float G = __builtin_amdgcn_exp2f(pw);
                 const float araw = g.coef.w * G;
                 const float al0 = fminf(araw, kAlphaMax);
@@ -240,7 +239,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdSha
                 const bool supp = act && above;
                 const float Tn = T[p] * (1.0f - al0);   // used only where supp
                 const bool stop = supp && Tn < kTMin;
-                const bool blend = supp && !stop;
+                const bool blend = supp != stop;   // stop implies supp (one compare, not two)
                 if (STATS) {
                     n_eval += act ? 1u : 0u;
                     n_supp += supp ? 1u : 0u;
