@@ -237,7 +237,10 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdSha
                         make_float2(araw > kAlphaMax && above ? -alpha : alpha, T[p]);
                 }
                 const bool supp = act && above;
-                const float Tn = T[p] * (1.0f - al0);   // used only where supp
+                // the weight alpha T and the next transmittance T (1 - alpha)
+                // = T - alpha T from it (used only where supp)
+                const float wa = al0 * T[p];
+                const float Tn = T[p] - wa;
                 const bool stop = supp && Tn < kTMin;
                 const bool blend = supp != stop;   // stop implies supp (one compare, not two)
                 if (STATS) {
@@ -245,7 +248,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, uint32_t tile, FwdSha
                     n_supp += supp ? 1u : 0u;
                     n_blend += blend ? 1u : 0u;
                 }
-                const float w = blend ? al0 * T[p] : 0.0f;
+                const float w = blend ? wa : 0.0f;
                 c0[p] = __builtin_fmaf(g.col.x, w, c0[p]);
                 c1[p] = __builtin_fmaf(g.col.y, w, c1[p]);
                 c2[p] = __builtin_fmaf(g.col.z, w, c2[p]);
